@@ -1,0 +1,142 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the
+benchmark.
+
+This module holds problem descriptions (geometry, wavenumber, refractive
+index, discretisation parameters) and random vectors only; it contains none
+of the method's arithmetic.  Both the GPU library and the CPU oracle receive
+the same numbers from here.
+
+Parameter names follow the paper: h interior spacing, (N1, N2) boundary-patch
+intervals, Q Newton–Cotes points, P interpolation nodes per axis, chi_c0 and
+the cut-off radii r_int (physical), r1 / r2 (boundary-patch grid units), the
+polar and varrho rule sizes, cell size H = cell_h * h, q equivalent sources
+per cell face, n_w plane waves per cell.
+"""
+import copy
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+def _base(kappa, h, a, k, s_in, N1, N2, s_a, s_b):
+    return {
+        "dim": 2,
+        "kappa": kappa,
+        "shape": {"a": a, "k": k},
+        "h": h,
+        "band": {"s_in": s_in, "N1": N1, "N2": N2},
+        "pou": {"s_a": s_a, "s_b": s_b},
+        "Q": 5,
+        "P": 8,
+        "chi_c0": 0.1,
+        "r_int": 12 * h,
+        "r1": 12.0,
+        "r2": 8.0,
+        "polar": {"n_in": 16, "grade": 3, "n_out": 32, "n_theta": 48},
+        "band_rule": {"M": 4, "n_in": 24, "n_out": 32},
+        # accelerator (library only; the oracle sums every pair directly)
+        "cell_h": 8,
+        "q": 8,
+        "n_w": 28,
+        "coll_factor": 4,
+    }
+
+
+def config(name):
+    """Named workloads.
+
+    disc_k2pi   unit disc, n = 1.5, kappa = 2 pi, h = 1/32, annulus 0.8 < r < 1
+                with 64 x 16 intervals (about 4k points)
+    star_k32pi  star R = 1 + 0.3 cos 5 theta, n^2 = 1 + 0.8 exp(-4|x|^2),
+                kappa = 32 pi, h = 1/512, band 0.9 < s < 1 with 4096 x 64
+                intervals (about 1.1M points)
+    star_k16pi  the same star at kappa = 16 pi, h = 1/256, band 2048 x 32
+                (about 270k points; 256 incident directions)
+    """
+    if name == "disc_k2pi":
+        c = _base(TWO_PI, 1.0 / 32, 0.0, 0, 0.8, 64, 16, 0.8, 0.95)
+        c["n2"] = {"kind": "const", "value": 2.25}
+        c["incidence"] = [0.0]
+        c["gmres"] = {"tol": 1e-10, "restart": 100}
+    elif name == "star_k32pi":
+        c = _base(32 * math.pi, 1.0 / 512, 0.3, 5, 0.9, 4096, 64, 0.9, 0.975)
+        c["r2"] = 12.0
+        c["n2"] = {"kind": "gauss", "base": 1.0, "amp": 0.8, "decay": 4.0}
+        c["incidence"] = [math.pi / 6]
+        c["gmres"] = {"tol": 1e-8, "restart": 60}
+    elif name == "star_k16pi":
+        c = _base(16 * math.pi, 1.0 / 256, 0.3, 5, 0.9, 2048, 32, 0.9, 0.975)
+        c["n2"] = {"kind": "gauss", "base": 1.0, "amp": 0.8, "decay": 4.0}
+        c["incidence"] = [TWO_PI * r / 256 for r in range(256)]
+        c["gmres"] = {"tol": 1e-8, "restart": 60}
+    else:
+        raise KeyError(name)
+    c["name"] = name
+    return c
+
+
+def scaled(cfg, **over):
+    """Copy of a configuration with some entries replaced (nested dicts are
+    updated, not replaced)."""
+    c = copy.deepcopy(cfg)
+    for k, v in over.items():
+        if isinstance(v, dict) and isinstance(c.get(k), dict):
+            c[k].update(v)
+        else:
+            c[k] = v
+    return c
+
+
+def n2_function(cfg):
+    """n^2 at points x (n, 2); on_boundary flags the nodes on the interface,
+    where the interior limit is returned (every profile here is smooth inside
+    the scatterer, so that limit is the formula itself)."""
+    spec = cfg["n2"]
+    if spec["kind"] == "const":
+        val = float(spec["value"])
+        return lambda x, on_b: np.full(x.shape[0], val)
+    if spec["kind"] == "gauss":
+        b, a, d = float(spec["base"]), float(spec["amp"]), float(spec["decay"])
+        return lambda x, on_b: b + a * np.exp(-d * (x[:, 0] ** 2 + x[:, 1] ** 2))
+    if spec["kind"] == "zero":
+        return lambda x, on_b: np.zeros(x.shape[0])
+    raise KeyError(spec["kind"])
+
+
+def plane_wave(cfg, x, alpha):
+    """Incident field exp(i kappa d . x), d = (cos alpha, sin alpha)."""
+    k = cfg["kappa"]
+    return np.exp(1j * k * (x[:, 0] * math.cos(alpha) + x[:, 1] * math.sin(alpha)))
+
+
+def random_density(keys, seed=1509):
+    """Complex Gaussian (g1 + i g2)/sqrt(2) assigned to nodes by their key
+    (chart, i1, i2), so that both sides see the same value at the same node
+    whatever order they store the nodes in."""
+    keys = np.asarray(keys, dtype=np.int64)
+    order = np.lexsort((keys[:, 2], keys[:, 1], keys[:, 0]))
+    rng = np.random.default_rng(seed)
+    g = (rng.standard_normal(keys.shape[0]) + 1j * rng.standard_normal(keys.shape[0])) / math.sqrt(2)
+    out = np.empty(keys.shape[0], complex)
+    out[order] = g
+    return out
+
+
+def match_keys(keys_a, keys_b):
+    """Permutation p with keys_b[p] == keys_a (raises if the sets differ)."""
+    ka = np.asarray(keys_a, np.int64)
+    kb = np.asarray(keys_b, np.int64)
+    if ka.shape != kb.shape:
+        raise ValueError(f"node counts differ: {ka.shape[0]} vs {kb.shape[0]}")
+    def code(k):
+        return (k[:, 0] << 42) + ((k[:, 1] + (1 << 20)) << 21) + (k[:, 2] + (1 << 20))
+    ca, cb = code(ka), code(kb)
+    ob = np.argsort(cb)
+    pos = np.searchsorted(cb[ob], ca)
+    pos = np.clip(pos, 0, len(ob) - 1)
+    p = ob[pos]
+    if not np.array_equal(cb[p], ca):
+        raise ValueError("node sets differ")
+    return p
