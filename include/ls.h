@@ -1,0 +1,180 @@
+/*
+ * ls.h — C ABI of the MI355X FFT-accelerated Lippmann–Schwinger operator.
+ *
+ * Method: Anand, Pandey, Rathish Kumar, Paul, "An efficient high-order
+ * Nystrom scheme for acoustic scattering by inhomogeneous penetrable media
+ * with discontinuous material interface" (arXiv:1509.05063).
+ *
+ * The library discretises the Lippmann–Schwinger equation (Sec. 1,
+ * eq:-Lippmann)
+ *
+ *     u(x) + kappa^2 int G_kappa(x - y) m(y) u(y) dy = u^i(x),  m = 1 - n^2,
+ *
+ * on two overlapping patches of a star-shaped scatterer (Sec. 2): a Cartesian
+ * interior patch and a boundary band whose transverse parameter t2 = 0 is the
+ * material interface.  ls_apply evaluates v = u + kappa^2 K_h u (the operator
+ * that GMRES applies every iteration, Sec. 2) in four device steps:
+ * projection onto equivalent sources on cell faces (Sec. 3.2,
+ * equiv-conv-loc), FFT convolution with the Green's function on the face
+ * lattices (Sec. 3.2), interpolation back to the Nystrom nodes through cell
+ * Dirichlet fits (Sec. 3.2, eq:-PWE) after subtracting the adjacent cells,
+ * and a sparse near-field correction that carries the singular and interface
+ * quadrature weights (Sec. 3.1, eq:-VolInt-Adj-NonAdj-I).
+ *
+ * Conventions shared by every entry point
+ *   - Complex vectors are interleaved (re, im).  LS_C128: double, LS_C64:
+ *     float.  A block of nrhs vectors is laid out [nrhs][N] (vector-major).
+ *   - Device pointers are HIP device memory owned by the caller; host
+ *     pointers are ordinary memory owned by the caller.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Points are stored in the operator's own order (sorted by cell); the
+ *     caller reads that order with ls_points and works in it.
+ *   - Errors are returned as ls_status; no exception crosses the ABI.  The
+ *     text of the last error of the calling thread is ls_last_error().
+ *     Device faults surface as LS_EDEVICE at the next synchronising call.
+ */
+#ifndef LS_H
+#define LS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LS_OK = 0,
+  LS_EINVAL = 1,      /* invalid argument or unsupported parameter combination */
+  LS_ENOMEM = 2,      /* host or device allocation failed */
+  LS_EDEVICE = 3,     /* HIP runtime error (no device, launch failure, fault) */
+  LS_ENOCONV = 4,     /* solver stopped before the tolerance; iterate written */
+  LS_EBUDGET = 5,     /* request does not fit the memory budget */
+  LS_ENOTREADY = 6    /* serving ticket not finished yet */
+} ls_status;
+
+typedef enum { LS_C128 = 0, LS_C64 = 1 } ls_prec;
+
+/* Scatterer and patches (Sec. 2; the patch layout is a reading, the paper
+ * gives none).  Boundary R(theta) = 1 + shape_a cos(shape_k theta).
+ *   interior patch: lattice x = h (i1, i2), nodes where its partition of
+ *                   unity is positive (s(x) = |x|/R(arg x) < s_b);
+ *   boundary patch: x = s R(theta) (cos, sin), theta = 2 pi t1,
+ *                   s = 1 - (1 - s_in) t2, t1 = i1/N1 (periodic),
+ *                   t2 = i2/N2 (0 <= i2 <= N2), interface at t2 = 0;
+ *   partition of unity: omega_band = step((s - s_a)/(s_b - s_a)),
+ *                   omega_int = 1 - omega_band. */
+typedef struct {
+  int dim;            /* 2 (the only value accepted) */
+  double shape_a;
+  int shape_k;
+  double h;
+  double s_in;
+  int N1, N2;
+  double s_a, s_b;
+} ls_geometry;
+
+/* Quadrature and accelerator parameters (names follow the paper).
+ *   Q            Newton–Cotes points (transverse, boundary patch); N2 % (Q-1) == 0
+ *   P            Lagrange interpolation nodes per axis (even, >= 4)
+ *   chi_c0       cut-off chi == 1 on [0, chi_c0]
+ *   r_int        interior cut-off radius (physical units)
+ *   r1, r2       boundary cut-off radii in grid units of t1 and t2
+ *   polar_*      interior polar rule: graded Gauss rho = a s^grade on
+ *                [0, chi_c0 r] (n_in nodes), Gauss on the rest (n_out),
+ *                trapezoid in theta (n_theta)
+ *   band_*       boundary rule in t1: t1 - t1^x = a s^(M+1) (n_in Gauss
+ *                nodes) plus Gauss on the cut-off transition (n_out)
+ *   cell_h       cell side H = cell_h * h
+ *   q            equivalent-source nodes per cell face
+ *   n_fb         Dirichlet fit order: Fourier–Bessel modes |n| <= n_fb
+ *   coll_factor  collocation points = coll_factor * 4q per source set */
+typedef struct {
+  int Q, P;
+  double chi_c0, r_int, r1, r2;
+  int polar_n_in, polar_grade, polar_n_out, polar_n_theta;
+  int band_M, band_n_in, band_n_out;
+  int cell_h, q, n_fb, coll_factor;
+} ls_params;
+
+/* Refractive index callback: writes n^2 at n points (x, y interleaved);
+ * on_boundary[i] != 0 marks interface nodes, where the interior limit is
+ * expected.  Called on the creating thread during ls_create only. */
+typedef void (*ls_n2_fn)(int64_t n, const double* xy, const int32_t* on_boundary,
+                         double* n2_out, void* ctx);
+
+typedef struct ls_op ls_op;
+
+/* Build the discrete operator for wavenumber kappa on the current HIP device.
+ * Set-up (nodes, weights, near-field quadratures, equivalent-source least
+ * squares, Green's function spectra) runs on the host with OpenMP; the
+ * results are copied to the device once.  The op owns all its memory.
+ * Errors: LS_EINVAL (bad geometry/params, kappa <= 0, cell resonance
+ * kappa H >= pi sqrt(2), cut-off reach beyond two cells), LS_ENOMEM,
+ * LS_EDEVICE. */
+ls_status ls_create(const ls_geometry* geom, ls_n2_fn n2, void* ctx, double kappa,
+                    const ls_params* params, ls_op** out);
+
+/* Release everything the op holds (NULL is accepted). */
+void ls_destroy(ls_op* op);
+
+/* Number of unknowns N. */
+ls_status ls_num_points(const ls_op* op, int64_t* N);
+
+/* Node coordinates xy[2N] (host) in operator order and, if key != NULL,
+ * key[3N] = (patch, i1, i2): patch 0 = interior lattice (i1, i2) = x/h,
+ * patch 1 = boundary patch grid indices. */
+ls_status ls_points(const ls_op* op, double* xy, int32_t* key);
+
+/* Device bytes held by the op (operator data, both precisions). */
+size_t ls_resident_bytes(const ls_op* op);
+
+/* Workspace bytes ls_apply needs for nrhs vectors in precision prec. */
+ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* bytes);
+
+/* v = u + kappa^2 K_h u for nrhs vectors ([nrhs][N] complex, device).
+ * Asynchronous on `stream`; no host synchronisation.  ws (device, >=
+ * ls_workspace_size bytes) is scratch owned by the caller; applies that run
+ * concurrently need distinct workspaces.  u and v must not overlap.
+ * LS_C64 runs every step in single precision (weights rounded from the
+ * double-precision set-up).  Errors: LS_EINVAL, LS_EDEVICE. */
+ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec,
+                   void* ws, size_t ws_bytes, void* stream);
+
+typedef enum { LS_SOLVE_FP64 = 0, LS_SOLVE_FP32_REFINE = 1 } ls_solve_mode;
+
+typedef struct {
+  double tol;           /* stop when ||f - A x|| <= tol ||f|| (per vector) */
+  int max_iter;         /* total inner iterations per vector */
+  int restart;          /* GMRES(m) restart length */
+  ls_solve_mode mode;   /* FP64 GMRES, or FP32 GMRES inside FP64 refinement */
+  double inner_tol;     /* relative tolerance of each inner FP32 solve */
+  int max_outer;        /* refinement steps */
+  int use_x0;           /* nonzero: u_tot holds the initial guess */
+} ls_solve_opts;
+
+typedef struct {
+  int iterations;       /* inner GMRES iterations (max over vectors) */
+  int outer;            /* refinement steps taken */
+  int converged;        /* vectors that met tol */
+  double rel_residual;  /* max over vectors of ||f - A x|| / ||f|| (FP64 apply) */
+  double seconds;       /* wall time of the call */
+  double apply_seconds; /* time spent in operator applies */
+} ls_solve_stats;
+
+/* Solve (I + kappa^2 K_h) u = u_inc for nrhs right-hand sides (device
+ * [nrhs][N] complex double) with matrix-free complex GMRES (Sec. 2): CGS2
+ * Arnoldi in FP64 on the device.  FP32_REFINE runs the inner GMRES with the
+ * single-precision apply and corrects with double-precision residuals.
+ * Synchronous on return.  Scratch memory is allocated by the op on first use
+ * and kept.  LS_ENOCONV still writes the best iterate and the stats. */
+ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs,
+                   const ls_solve_opts* opts, ls_solve_stats* stats, void* stream);
+
+const char* ls_status_str(ls_status s);
+const char* ls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LS_H */

@@ -1,0 +1,257 @@
+"""ctypes binding of the C ABI in include/ls.h and include/ls_host.h.
+
+Argument marshalling only: every step of the apply and the solve runs inside
+libls.so.  Device buffers are torch tensors (complex128 / complex64 on the
+HIP device); torch is used for device memory and streams, nothing else.
+Loading fails loudly when the library has not been built.
+"""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libls.so")
+
+LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOCONV, LS_EBUDGET, LS_ENOTREADY = range(7)
+LS_C128, LS_C64 = 0, 1
+LS_SOLVE_FP64, LS_SOLVE_FP32_REFINE = 0, 1
+
+
+class Geometry(C.Structure):
+    _fields_ = [("dim", C.c_int), ("shape_a", C.c_double), ("shape_k", C.c_int), ("h", C.c_double),
+                ("s_in", C.c_double), ("N1", C.c_int), ("N2", C.c_int), ("s_a", C.c_double),
+                ("s_b", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("Q", C.c_int), ("P", C.c_int), ("chi_c0", C.c_double), ("r_int", C.c_double),
+                ("r1", C.c_double), ("r2", C.c_double), ("polar_n_in", C.c_int), ("polar_grade", C.c_int),
+                ("polar_n_out", C.c_int), ("polar_n_theta", C.c_int), ("band_M", C.c_int),
+                ("band_n_in", C.c_int), ("band_n_out", C.c_int), ("cell_h", C.c_int), ("q", C.c_int),
+                ("n_fb", C.c_int), ("coll_factor", C.c_int)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("mode", C.c_int),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("use_x0", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("converged", C.c_int),
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("apply_seconds", C.c_double)]
+
+
+N2FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                   C.c_void_p)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1509_05063_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        sig = {
+            "ls_create": (C.c_int, [P(Geometry), N2FN, C.c_void_p, C.c_double, P(Params), P(C.c_void_p)]),
+            "ls_destroy": (None, [C.c_void_p]),
+            "ls_num_points": (C.c_int, [C.c_void_p, P(C.c_int64)]),
+            "ls_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+            "ls_resident_bytes": (C.c_size_t, [C.c_void_p]),
+            "ls_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, P(C.c_size_t)]),
+            "ls_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                   C.c_size_t, C.c_void_p]),
+            "ls_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, P(SolveOpts), P(SolveStats),
+                                   C.c_void_p]),
+            "ls_status_str": (C.c_char_p, [C.c_int]),
+            "ls_last_error": (C.c_char_p, []),
+            "ls_host_build": (C.c_int, [P(Geometry), N2FN, C.c_void_p, C.c_double, P(Params), P(C.c_void_p)]),
+            "ls_host_destroy": (None, [C.c_void_p]),
+            "ls_host_num_points": (C.c_int, [C.c_void_p, P(C.c_int64)]),
+            "ls_host_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+            "ls_host_stats": (C.c_int, [C.c_void_p, P(C.c_int64), C.c_int]),
+            "ls_host_near_row": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                           P(C.c_int64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class LSError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        msg = L.ls_last_error().decode()
+        super().__init__(f"{where}: {L.ls_status_str(status).decode()} ({msg})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != LS_OK:
+        raise LSError(status, where)
+
+
+def geometry_from(cfg):
+    b, pou, sh = cfg["band"], cfg["pou"], cfg["shape"]
+    return Geometry(2, float(sh["a"]), int(sh["k"]), float(cfg["h"]), float(b["s_in"]), int(b["N1"]),
+                    int(b["N2"]), float(pou["s_a"]), float(pou["s_b"]))
+
+
+def params_from(cfg):
+    pl, br = cfg["polar"], cfg["band_rule"]
+    return Params(int(cfg["Q"]), int(cfg["P"]), float(cfg["chi_c0"]), float(cfg["r_int"]), float(cfg["r1"]),
+                  float(cfg["r2"]), int(pl["n_in"]), int(pl["grade"]), int(pl["n_out"]), int(pl["n_theta"]),
+                  int(br["M"]), int(br["n_in"]), int(br["n_out"]), int(cfg["cell_h"]), int(cfg["q"]),
+                  int(cfg["n_fb"]), int(cfg["coll_factor"]))
+
+
+def _n2_callback(n2_fn):
+    def cb(n, xy, onb, out, ctx):
+        x = np.ctypeslib.as_array(xy, shape=(n, 2))
+        ob = np.ctypeslib.as_array(onb, shape=(n,)) != 0
+        res = np.ctypeslib.as_array(out, shape=(n,))
+        res[:] = n2_fn(np.array(x), ob)
+    return N2FN(cb)
+
+
+class HostOperator:
+    """Host-only set-up (no device): nodes and near-field rows."""
+
+    def __init__(self, cfg, n2_fn):
+        L = lib()
+        self._cb = _n2_callback(n2_fn)
+        h = C.c_void_p()
+        g, p = geometry_from(cfg), params_from(cfg)
+        _check(L.ls_host_build(C.byref(g), self._cb, None, float(cfg["kappa"]), C.byref(p), C.byref(h)),
+               "ls_host_build")
+        self._h = h
+        n = C.c_int64()
+        _check(L.ls_host_num_points(h, C.byref(n)), "ls_host_num_points")
+        self.N = n.value
+
+    def points(self):
+        xy = np.empty((self.N, 2))
+        key = np.empty((self.N, 3), np.int32)
+        _check(lib().ls_host_points(self._h, xy.ctypes.data, key.ctypes.data), "ls_host_points")
+        return xy, key
+
+    def stats(self):
+        out = (C.c_int64 * 12)()
+        _check(lib().ls_host_stats(self._h, out, 12), "ls_host_stats")
+        names = ["N", "n_band", "ncell", "L", "csr_rows", "csr_nnz", "Pa", "Pb", "U", "F", "S", "Wn"]
+        return dict(zip(names, list(out)))
+
+    def near_row(self, i):
+        cnt = C.c_int64()
+        L = lib()
+        _check(L.ls_host_near_row(self._h, int(i), 0, None, None, C.byref(cnt)), "ls_host_near_row")
+        n = cnt.value
+        cols = np.empty(n, np.int32)
+        vals = np.empty(2 * n)
+        _check(L.ls_host_near_row(self._h, int(i), n, cols.ctypes.data, vals.ctypes.data, C.byref(cnt)),
+               "ls_host_near_row")
+        return cols, vals[0::2] + 1j * vals[1::2]
+
+    def close(self):
+        if self._h:
+            lib().ls_host_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Operator:
+    """Device operator: ls_create / ls_apply / ls_solve."""
+
+    def __init__(self, cfg, n2_fn):
+        L = lib()
+        self.cfg = cfg
+        self._cb = _n2_callback(n2_fn)
+        op = C.c_void_p()
+        g, p = geometry_from(cfg), params_from(cfg)
+        _check(L.ls_create(C.byref(g), self._cb, None, float(cfg["kappa"]), C.byref(p), C.byref(op)), "ls_create")
+        self._op = op
+        n = C.c_int64()
+        _check(L.ls_num_points(op, C.byref(n)), "ls_num_points")
+        self.N = n.value
+        self._ws = {}
+
+    def points(self):
+        xy = np.empty((self.N, 2))
+        key = np.empty((self.N, 3), np.int32)
+        _check(lib().ls_points(self._op, xy.ctypes.data, key.ctypes.data), "ls_points")
+        return xy, key
+
+    def resident_bytes(self):
+        return lib().ls_resident_bytes(self._op)
+
+    def workspace_bytes(self, nrhs, prec):
+        b = C.c_size_t()
+        _check(lib().ls_workspace_size(self._op, nrhs, prec, C.byref(b)), "ls_workspace_size")
+        return b.value
+
+    def workspace(self, nrhs, prec):
+        import torch
+        key = (nrhs, prec)
+        if key not in self._ws:
+            self._ws[key] = torch.empty(self.workspace_bytes(nrhs, prec), dtype=torch.uint8, device="cuda")
+        return self._ws[key]
+
+    def apply(self, u, v, stream=None):
+        """v = u + kappa^2 K_h u; u, v: torch complex128/complex64 [nrhs, N] or [N] on the device."""
+        import torch
+        prec = LS_C128 if u.dtype == torch.complex128 else LS_C64
+        if v.dtype != u.dtype or not u.is_contiguous() or not v.is_contiguous():
+            raise ValueError("u and v must be contiguous and of one dtype")
+        nrhs = 1 if u.dim() == 1 else u.shape[0]
+        if u.numel() != nrhs * self.N or v.numel() != nrhs * self.N:
+            raise ValueError("shape does not match the operator")
+        ws = self.workspace(nrhs, prec)
+        _check(lib().ls_apply(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(), _stream(stream)),
+               "ls_apply")
+        return v
+
+    def solve(self, u_inc, u_tot, tol=1e-10, max_iter=2000, restart=100, mode=LS_SOLVE_FP64, inner_tol=1e-5,
+              max_outer=20, use_x0=False, stream=None, raise_on_noconv=True):
+        nrhs = 1 if u_inc.dim() == 1 else u_inc.shape[0]
+        opts = SolveOpts(float(tol), int(max_iter), int(restart), int(mode), float(inner_tol), int(max_outer),
+                         int(use_x0))
+        st = SolveStats()
+        rc = lib().ls_solve(self._op, _ptr(u_inc), _ptr(u_tot), nrhs, C.byref(opts), C.byref(st), _stream(stream))
+        if rc != LS_OK and (rc != LS_ENOCONV or raise_on_noconv):
+            raise LSError(rc, "ls_solve")
+        return {"iterations": st.iterations, "outer": st.outer, "converged": st.converged,
+                "rel_residual": st.rel_residual, "seconds": st.seconds, "apply_seconds": st.apply_seconds,
+                "status": rc}
+
+    def close(self):
+        if getattr(self, "_op", None):
+            lib().ls_destroy(self._op)
+            self._op = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,700 @@
+// C ABI: operator creation, apply, GMRES solve (host orchestration).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ls.h"
+#include "ls_host.h"
+#include "ls_kernels.hpp"
+#include "ls_setup.hpp"
+
+using lsx::cd;
+
+namespace {
+thread_local std::string g_err;
+ls_status fail(ls_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(LS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Fp32c { float x, y; };
+}  // namespace
+
+struct ls_host_op {
+  lsx::HostOp h;
+};
+
+struct ls_op {
+  int device = 0;
+  int64_t N = 0;
+  std::vector<double> xy;
+  std::vector<int32_t> key;
+  std::vector<void*> allocs;
+  size_t resident = 0;
+  lsx::DevView<double> d64;
+  lsx::DevView<float> d32;
+  double kappa = 0;
+  // solver scratch
+  void* gm = nullptr;
+  size_t gm_bytes = 0;
+};
+
+namespace {
+
+template <typename X>
+ls_status upload(ls_op* op, const X* src, size_t count, void** dst) {
+  *dst = nullptr;
+  if (count == 0) return LS_OK;
+  void* p = nullptr;
+  if (hipMalloc(&p, count * sizeof(X)) != hipSuccess) return fail(LS_ENOMEM, "hipMalloc failed");
+  op->allocs.push_back(p);
+  op->resident += count * sizeof(X);
+  if (hipMemcpy(p, src, count * sizeof(X), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(LS_EDEVICE, "hipMemcpy H2D failed");
+  *dst = p;
+  return LS_OK;
+}
+
+ls_status upload_c(ls_op* op, const std::vector<cd>& v, const void** d64, const void** d32) {
+  void* a = nullptr;
+  ls_status s = upload(op, v.data(), v.size(), &a);
+  if (s) return s;
+  *d64 = a;
+  std::vector<Fp32c> f(v.size());
+  for (size_t i = 0; i < v.size(); ++i) f[i] = {(float)v[i].real(), (float)v[i].imag()};
+  void* b = nullptr;
+  s = upload(op, f.data(), f.size(), &b);
+  if (s) return s;
+  *d32 = b;
+  return LS_OK;
+}
+
+template <typename X>
+ls_status upload_i(ls_op* op, const std::vector<X>& v, const X** dst) {
+  void* a = nullptr;
+  ls_status s = upload(op, v.data(), v.size(), &a);
+  *dst = (const X*)a;
+  return s;
+}
+
+lsx::FftPlan make_plan(int n) {
+  lsx::FftPlan p{};
+  p.n = n;
+  int r = n;
+  p.npass = 0;
+  while (r % 4 == 0) { p.radix[p.npass++] = 4; r /= 4; }
+  while (r % 2 == 0) { p.radix[p.npass++] = 2; r /= 2; }
+  while (r % 3 == 0) { p.radix[p.npass++] = 3; r /= 3; }
+  while (r % 5 == 0) { p.radix[p.npass++] = 5; r /= 5; }
+  return p;
+}
+
+void release(ls_op* op) {
+  for (void* p : op->allocs) (void)hipFree(p);
+  op->allocs.clear();
+  if (op->gm) (void)hipFree(op->gm);
+  op->gm = nullptr;
+}
+
+size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
+  size_t c = prec == LS_C128 ? 16 : 8;
+  const auto& d = op->d64;
+  return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb) + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ls_status_str(ls_status s) {
+  switch (s) {
+    case LS_OK: return "ok";
+    case LS_EINVAL: return "invalid argument";
+    case LS_ENOMEM: return "out of memory";
+    case LS_EDEVICE: return "device error";
+    case LS_ENOCONV: return "not converged";
+    case LS_EBUDGET: return "over memory budget";
+    case LS_ENOTREADY: return "not ready";
+  }
+  return "unknown status";
+}
+
+const char* ls_last_error(void) { return g_err.c_str(); }
+
+ls_status ls_host_build(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, const ls_params* p,
+                        ls_host_op** out) {
+  if (!g || !n2 || !p || !out) return fail(LS_EINVAL, "null argument");
+  *out = nullptr;
+  ls_host_op* h = new (std::nothrow) ls_host_op();
+  if (!h) return fail(LS_ENOMEM, "host allocation");
+  std::string err;
+  ls_status s;
+  try {
+    s = lsx::build_host_op(g, n2, ctx, kappa, p, h->h, err);
+  } catch (const std::bad_alloc&) {
+    s = LS_ENOMEM;
+    err = "host allocation during set-up";
+  }
+  if (s != LS_OK) {
+    delete h;
+    return fail(s, err);
+  }
+  *out = h;
+  return LS_OK;
+}
+
+void ls_host_destroy(ls_host_op* h) { delete h; }
+
+ls_status ls_host_num_points(const ls_host_op* h, int64_t* N) {
+  if (!h || !N) return fail(LS_EINVAL, "null argument");
+  *N = h->h.N;
+  return LS_OK;
+}
+
+ls_status ls_host_points(const ls_host_op* h, double* xy, int32_t* key) {
+  if (!h || !xy) return fail(LS_EINVAL, "null argument");
+  std::memcpy(xy, h->h.xy.data(), h->h.xy.size() * sizeof(double));
+  if (key) std::memcpy(key, h->h.key.data(), h->h.key.size() * sizeof(int32_t));
+  return LS_OK;
+}
+
+ls_status ls_host_stats(const ls_host_op* h, int64_t* out, int nout) {
+  if (!h || !out) return fail(LS_EINVAL, "null argument");
+  const auto& o = h->h;
+  int64_t v[12] = {o.N, o.n_band, o.ncell, o.L, (int64_t)o.rows.size(), (int64_t)o.cols.size(),
+                   o.Pa, o.Pb, o.U, o.F, o.S, o.Wn};
+  for (int i = 0; i < nout && i < 12; ++i) out[i] = v[i];
+  return LS_OK;
+}
+
+ls_status ls_host_near_row(const ls_host_op* h, int64_t i, int64_t cap, int32_t* cols, double* vals,
+                           int64_t* count) {
+  if (!h || !count) return fail(LS_EINVAL, "null argument");
+  const auto& o = h->h;
+  if (i < 0 || i >= o.N) return fail(LS_EINVAL, "row out of range");
+  std::vector<std::pair<int32_t, cd>> ent;
+  if (o.key[3 * i] == 0) {
+    // shared window part: interior sources in the 5x5 cells around i's cell
+    int c = -1, slot = -1;
+    for (int cc = 0; cc < o.ncell && c < 0; ++cc)
+      for (int a = 0; a < o.S; ++a)
+        if (o.slot_map[(size_t)cc * o.S + a] == i) { c = cc; slot = a; break; }
+    const int ch = o.p.cell_h, Wn = o.Wn;
+    const int cx = o.cell_xy[2 * c], cy = o.cell_xy[2 * c + 1];
+    for (int wy = 0; wy < Wn; ++wy)
+      for (int wx = 0; wx < Wn; ++wx) {
+        int nx = cx + wx / ch - 2, ny = cy + wy / ch - 2;
+        if (nx < 0 || ny < 0 || nx >= o.L || ny >= o.L) continue;
+        int cn = o.cell_map[ny * o.L + nx];
+        if (cn < 0) continue;
+        int j = o.slot_map[(size_t)cn * o.S + (wy % ch) * ch + (wx % ch)];
+        if (j < 0) continue;
+        cd w = o.Wsh[(size_t)slot * Wn * Wn + (size_t)wy * Wn + wx] * o.dw[j];
+        if (w != 0.0) ent.emplace_back(j, w);
+      }
+  }
+  auto it = std::lower_bound(o.rows.begin(), o.rows.end(), (int32_t)i);
+  if (it != o.rows.end() && *it == i) {
+    size_t r = it - o.rows.begin();
+    for (int64_t k = o.rowptr[r]; k < o.rowptr[r + 1]; ++k) ent.emplace_back(o.cols[k], o.vals[k]);
+  }
+  *count = (int64_t)ent.size();
+  if (cols && vals) {
+    for (int64_t k = 0; k < (int64_t)ent.size() && k < cap; ++k) {
+      cols[k] = ent[k].first;
+      vals[2 * k] = ent[k].second.real();
+      vals[2 * k + 1] = ent[k].second.imag();
+    }
+  }
+  return LS_OK;
+}
+
+ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, const ls_params* p,
+                    ls_op** out) {
+  if (!out) return fail(LS_EINVAL, "null argument");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(LS_EDEVICE, "no HIP device");
+  ls_host_op* hb = nullptr;
+  ls_status s = ls_host_build(g, n2, ctx, kappa, p, &hb);
+  if (s) return s;
+  lsx::HostOp& h = hb->h;
+  ls_op* op = new (std::nothrow) ls_op();
+  if (!op) { ls_host_destroy(hb); return fail(LS_ENOMEM, "host allocation"); }
+  (void)hipGetDevice(&op->device);
+  op->N = h.N;
+  op->kappa = kappa;
+  op->xy = h.xy;
+  op->key = h.key;
+
+  auto cleanup = [&](ls_status st) {
+    release(op);
+    delete op;
+    ls_host_destroy(hb);
+    return st;
+  };
+  // LDS needed by the FFT kernels
+  int lds_max = 0;
+  (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device);
+  const int tc = std::max(1, std::min(16, (int)(32768 / (2 * (size_t)h.Pa * 16))));
+  size_t need = std::max(2 * (size_t)h.Pb * 16, 2 * (size_t)h.Pa * tc * 16);
+  if (need > 160 * 1024) {
+    ls_host_destroy(hb);
+    delete op;
+    return fail(LS_EINVAL, "FFT line too long for one workgroup's LDS");
+  }
+  if (need > 64 * 1024) {
+    hipError_t e = lsx::set_fft_lds_limits(need);
+    if (e != hipSuccess) return cleanup(fail(LS_EDEVICE, std::string("LDS attribute: ") + hipGetErrorString(e)));
+  }
+  (void)lds_max;
+
+  lsx::DevView<double>& a = op->d64;
+  lsx::DevView<float>& b = op->d32;
+  a.N = b.N = h.N;
+  a.ncell = b.ncell = h.ncell;
+  a.S = b.S = h.S;
+  a.U = b.U = h.U;
+  a.F = b.F = h.F;
+  a.q = b.q = h.q;
+  a.L = b.L = h.L;
+  a.na = b.na = h.na;
+  a.nb = b.nb = h.nb;
+  a.Pa = b.Pa = h.Pa;
+  a.Pb = b.Pb = h.Pb;
+  a.ch = b.ch = h.p.cell_h;
+  a.tc = b.tc = tc;
+  a.kappa = b.kappa = kappa;
+  a.nrows = b.nrows = (int)h.rows.size();
+  a.csr_f64 = true;
+  b.csr_f64 = false;
+  int max_nb = 0;
+  std::vector<int32_t> icells;
+  for (int c = 0; c < h.ncell; ++c) {
+    max_nb = std::max(max_nb, h.cell_nb[c]);
+    if (h.cell_nint[c] > 0) icells.push_back(c);
+  }
+  a.max_nb = b.max_nb = max_nb;
+  a.nicell = b.nicell = (int)icells.size();
+  a.pa = b.pa = make_plan(h.Pa);
+  a.pb = b.pb = make_plan(h.Pb);
+
+#define UP(expr)              \
+  do {                        \
+    ls_status s_ = (expr);    \
+    if (s_) return cleanup(s_); \
+  } while (0)
+  UP(upload_c(op, h.Psh, &a.Psh, &b.Psh));
+  UP(upload_c(op, h.Pbd, &a.Pbd, &b.Pbd));
+  UP(upload_c(op, h.Ish, &a.Ish, &b.Ish));
+  UP(upload_c(op, h.Ibd, &a.Ibd, &b.Ibd));
+  UP(upload_c(op, h.Toff, &a.Toff, &b.Toff));
+  UP(upload_c(op, h.Wsh, &a.Wsh, &b.Wsh));
+  UP(upload_c(op, h.vals, &a.vals, &b.vals));
+  {
+    std::vector<float> f(h.cw.begin(), h.cw.end()), g2(h.dw.begin(), h.dw.end());
+    UP(upload_i(op, h.cw, &a.cw));
+    UP(upload_i(op, f, &b.cw));
+    UP(upload_i(op, h.dw, &a.dw));
+    UP(upload_i(op, g2, &b.dw));
+  }
+  UP(upload_i(op, h.slot_map, &a.slot_map));
+  UP(upload_i(op, h.cell_start, &a.cell_start));
+  UP(upload_i(op, h.cell_nint, &a.cell_nint));
+  UP(upload_i(op, h.cell_nb, &a.cell_nb));
+  UP(upload_i(op, h.cell_boff, &a.cell_boff));
+  UP(upload_i(op, h.cell_xy, &a.cell_xy));
+  UP(upload_i(op, h.cell_map, &a.cell_map));
+  UP(upload_i(op, icells, &a.icells));
+  UP(upload_i(op, h.rows, &a.rows));
+  UP(upload_i(op, h.cols, &a.cols));
+  UP(upload_i(op, h.rowptr, &a.rowptr));
+  b.slot_map = a.slot_map;
+  b.cell_start = a.cell_start;
+  b.cell_nint = a.cell_nint;
+  b.cell_nb = a.cell_nb;
+  b.cell_boff = a.cell_boff;
+  b.cell_xy = a.cell_xy;
+  b.cell_map = a.cell_map;
+  b.icells = a.icells;
+  b.rows = a.rows;
+  b.cols = a.cols;
+  b.rowptr = a.rowptr;
+  // twiddles exp(-2 pi i k / n), computed in double
+  for (int which = 0; which < 2; ++which) {
+    int n = which == 0 ? h.Pa : h.Pb;
+    std::vector<cd> tw(n);
+    for (int k = 0; k < n; ++k) tw[k] = std::polar(1.0, -2.0 * M_PI * (double)k / n);
+    if (which == 0) UP(upload_c(op, tw, &a.twa, &b.twa));
+    else UP(upload_c(op, tw, &a.twb, &b.twb));
+  }
+  // Green's function spectra: forward FFT (double) of the padded lattices
+  {
+    void* kd = nullptr;
+    UP(upload(op, h.kern.data(), h.kern.size(), &kd));
+    // rows a >= na are not all zero here (negative offsets wrap), so transform every row
+    lsx::DevView<double> full = a;
+    full.na = h.Pa;
+    hipError_t e = lsx::launch_fft_kernels_forward(full, kd, 4, 0);
+    if (e != hipSuccess) return cleanup(fail(LS_EDEVICE, std::string("kernel FFT: ") + hipGetErrorString(e)));
+    if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(LS_EDEVICE, "kernel FFT failed"));
+    a.khat = kd;
+    std::vector<cd> kh(h.kern.size());
+    if (hipMemcpy(kh.data(), kd, kh.size() * sizeof(cd), hipMemcpyDeviceToHost) != hipSuccess)
+      return cleanup(fail(LS_EDEVICE, "copy of spectra"));
+    std::vector<Fp32c> kf(kh.size());
+    for (size_t i = 0; i < kh.size(); ++i) kf[i] = {(float)kh[i].real(), (float)kh[i].imag()};
+    void* kf_d = nullptr;
+    UP(upload(op, kf.data(), kf.size(), &kf_d));
+    b.khat = kf_d;
+  }
+#undef UP
+  ls_host_destroy(hb);
+  *out = op;
+  return LS_OK;
+}
+
+void ls_destroy(ls_op* op) {
+  if (!op) return;
+  release(op);
+  delete op;
+}
+
+ls_status ls_num_points(const ls_op* op, int64_t* N) {
+  if (!op || !N) return fail(LS_EINVAL, "null argument");
+  *N = op->N;
+  return LS_OK;
+}
+
+ls_status ls_points(const ls_op* op, double* xy, int32_t* key) {
+  if (!op || !xy) return fail(LS_EINVAL, "null argument");
+  std::memcpy(xy, op->xy.data(), op->xy.size() * sizeof(double));
+  if (key) std::memcpy(key, op->key.data(), op->key.size() * sizeof(int32_t));
+  return LS_OK;
+}
+
+size_t ls_resident_bytes(const ls_op* op) { return op ? op->resident : 0; }
+
+ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* bytes) {
+  if (!op || !bytes || nrhs < 1 || (prec != LS_C128 && prec != LS_C64)) return fail(LS_EINVAL, "bad argument");
+  *bytes = ws_bytes(op, nrhs, prec);
+  return LS_OK;
+}
+
+ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, void* ws, size_t wsb,
+                   void* stream) {
+  if (!op || !u || !v || !ws || nrhs < 1) return fail(LS_EINVAL, "null argument or nrhs < 1");
+  if (prec != LS_C128 && prec != LS_C64) return fail(LS_EINVAL, "unknown precision");
+  if (wsb < ws_bytes(op, nrhs, prec)) return fail(LS_EINVAL, "workspace too small");
+  size_t vb = (size_t)nrhs * op->N * (prec == LS_C128 ? 16 : 8);
+  const char* uc = (const char*)u;
+  const char* vc = (const char*)v;
+  if (uc < vc + vb && vc < uc + vb) return fail(LS_EINVAL, "u and v overlap");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = prec == LS_C128 ? lsx::launch_apply<double>(op->d64, u, v, nrhs, ws, st)
+                                 : lsx::launch_apply<float>(op->d32, u, v, nrhs, ws, st);
+  if (e != hipSuccess) return fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
+  return LS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES (Sec. 2: matrix-free GMRES in complex arithmetic).  All right-hand
+// sides advance together; CGS2 Arnoldi in double precision on the device;
+// the small Hessenberg least-squares problems (Givens rotations) on the host.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Gm {
+  ls_op* op;
+  int nrhs, m;
+  int64_t N;
+  hipStream_t st;
+  char* base;
+  double2 *V, *w, *r, *tmp64, *rout, *e, *hdev, *partial;
+  void *ws, *u32, *v32;
+  double* sdev;
+  size_t wsb;
+  int nparts;
+  double apply_s = 0;
+  int applies = 0;
+};
+
+size_t gm_need(const ls_op* op, int nrhs, int m) {
+  size_t N = op->N;
+  size_t v = 16 * N * nrhs;
+  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 2 + 16 * 256 * (size_t)(m + 2) * nrhs +
+             8 * nrhs + ws_bytes(op, nrhs, LS_C128) + 2 * 8 * N * nrhs + 4096;
+  return b;
+}
+
+ls_status gm_setup(Gm& g) {
+  size_t need = gm_need(g.op, g.nrhs, g.m);
+  if (g.op->gm_bytes < need) {
+    if (g.op->gm) (void)hipFree(g.op->gm);
+    g.op->gm = nullptr;
+    g.op->gm_bytes = 0;
+    if (hipMalloc(&g.op->gm, need) != hipSuccess) return fail(LS_ENOMEM, "solver workspace");
+    g.op->gm_bytes = need;
+  }
+  char* p = (char*)g.op->gm;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) & ~size_t(255);
+    return q;
+  };
+  size_t vb = 16 * (size_t)g.N * g.nrhs;
+  g.V = (double2*)take(vb * (g.m + 1));
+  g.w = (double2*)take(vb);
+  g.r = (double2*)take(vb);
+  g.tmp64 = (double2*)take(vb);
+  g.rout = (double2*)take(vb);
+  g.e = (double2*)take(vb);
+  g.hdev = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs * 2);
+  g.nparts = 256;
+  g.partial = (double2*)take(16 * 256 * (size_t)(g.m + 2) * g.nrhs);
+  g.sdev = (double*)take(8 * g.nrhs);
+  g.wsb = ws_bytes(g.op, g.nrhs, LS_C128);
+  g.ws = take(g.wsb);
+  g.u32 = take(8 * (size_t)g.N * g.nrhs);
+  g.v32 = take(8 * (size_t)g.N * g.nrhs);
+  return LS_OK;
+}
+
+ls_status gm_apply(Gm& g, const double2* x, double2* y, ls_prec prec) {
+  auto t0 = std::chrono::steady_clock::now();
+  int64_t n = g.N * g.nrhs;
+  if (prec == LS_C128) {
+    hipError_t e = lsx::launch_apply<double>(g.op->d64, x, y, g.nrhs, g.ws, g.st);
+    if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
+  } else {
+    HIPCHK(lsx::gm_to_f32(x, g.u32, n, g.st));
+    hipError_t e = lsx::launch_apply<float>(g.op->d32, g.u32, g.v32, g.nrhs, g.ws, g.st);
+    if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
+    HIPCHK(lsx::gm_to_f64(g.v32, y, n, g.st));
+  }
+  HIPCHK(hipStreamSynchronize(g.st));
+  g.apply_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  g.applies++;
+  return LS_OK;
+}
+
+// d[r][j] = <V_j, w>_r for j < nvec (vstride between basis vectors)
+ls_status gm_dots_host(Gm& g, const double2* Vb, const double2* w, int nvec, int64_t vstride,
+                       std::vector<std::complex<double>>& out) {
+  HIPCHK(lsx::gm_dots(Vb, w, g.partial, g.hdev, nvec, g.N, g.nrhs, vstride, g.nparts, g.st));
+  out.resize((size_t)nvec * g.nrhs);
+  HIPCHK(hipMemcpyAsync(out.data(), g.hdev, out.size() * 16, hipMemcpyDeviceToHost, g.st));
+  HIPCHK(hipStreamSynchronize(g.st));
+  return LS_OK;
+}
+
+// Solve A x = f (x holds the initial guess) to relative residual tol; returns
+// the number of iterations and per-rhs estimated relative residuals.
+ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, int max_iter, ls_prec prec,
+                int* iters, std::vector<double>& relres) {
+  const int R = g.nrhs, m = g.m;
+  const int64_t N = g.N;
+  const int64_t vstride = N * R;          // distance between basis vectors (elements)
+  std::vector<std::complex<double>> dd;
+  std::vector<double> fnorm(R);
+  ls_status s = gm_dots_host(g, f, f, 1, 0, dd);
+  if (s) return s;
+  for (int r = 0; r < R; ++r) fnorm[r] = std::sqrt(std::max(0.0, dd[r].real()));
+  relres.assign(R, 1.0);
+  int it = 0;
+  bool first = true;
+  while (true) {
+    // r = f - A x
+    if (x_zero && first) {
+      HIPCHK(hipMemcpyAsync(g.r, f, 16 * (size_t)N * R, hipMemcpyDeviceToDevice, g.st));
+    } else {
+      s = gm_apply(g, x, g.w, prec);
+      if (s) return s;
+      HIPCHK(lsx::gm_sub(f, g.w, g.r, N * R, g.st));
+    }
+    first = false;
+    s = gm_dots_host(g, g.r, g.r, 1, 0, dd);
+    if (s) return s;
+    std::vector<double> beta(R);
+    bool all = true;
+    for (int r = 0; r < R; ++r) {
+      beta[r] = std::sqrt(std::max(0.0, dd[r].real()));
+      relres[r] = fnorm[r] > 0 ? beta[r] / fnorm[r] : 0.0;
+      if (relres[r] > tol) all = false;
+    }
+    if (all || it >= max_iter) break;
+    std::vector<double> inv(R);
+    for (int r = 0; r < R; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+    HIPCHK(hipMemcpyAsync(g.sdev, inv.data(), 8 * R, hipMemcpyHostToDevice, g.st));
+    HIPCHK(lsx::gm_scale_copy(g.r, g.V, g.sdev, N, R, g.st));
+    // Hessenberg per rhs, column-major (m+1) x m, Givens state
+    std::vector<std::complex<double>> Hm((size_t)R * (m + 1) * m, 0.0), cs((size_t)R * m), sn((size_t)R * m),
+        gv((size_t)R * (m + 1), 0.0);
+    for (int r = 0; r < R; ++r) gv[(size_t)r * (m + 1)] = beta[r];
+    std::vector<int> kdone(R, -1);
+    for (int r = 0; r < R; ++r)
+      if (relres[r] <= tol) kdone[r] = 0;
+    int k = 0;
+    for (; k < m && it < max_iter; ++k) {
+      double2* vk = g.V + (size_t)k * vstride;
+      s = gm_apply(g, vk, g.w, prec);
+      if (s) return s;
+      ++it;
+      std::vector<std::complex<double>> h1, h2;
+      for (int pass = 0; pass < 2; ++pass) {
+        s = gm_dots_host(g, g.V, g.w, k + 1, vstride, pass == 0 ? h1 : h2);
+        if (s) return s;
+        HIPCHK(hipMemcpyAsync(g.hdev, (pass == 0 ? h1 : h2).data(), 16 * (size_t)(k + 1) * R,
+                              hipMemcpyHostToDevice, g.st));
+        HIPCHK(lsx::gm_update(g.V, g.w, g.hdev, k + 1, N, R, vstride, g.st));
+      }
+      s = gm_dots_host(g, g.w, g.w, 1, 0, dd);
+      if (s) return s;
+      std::vector<double> invn(R);
+      bool all_done = true;
+      for (int r = 0; r < R; ++r) {
+        double hn = std::sqrt(std::max(0.0, dd[r].real()));
+        invn[r] = hn > 0 ? 1.0 / hn : 0.0;
+        std::complex<double>* col = &Hm[((size_t)r * m + k) * (m + 1)];
+        for (int j = 0; j <= k; ++j) col[j] = h1[(size_t)r * (k + 1) + j] + h2[(size_t)r * (k + 1) + j];
+        col[k + 1] = hn;
+        std::complex<double>* c = &cs[(size_t)r * m];
+        std::complex<double>* sv = &sn[(size_t)r * m];
+        for (int j = 0; j < k; ++j) {
+          std::complex<double> t = c[j] * col[j] + sv[j] * col[j + 1];
+          col[j + 1] = -std::conj(sv[j]) * col[j] + std::conj(c[j]) * col[j + 1];
+          col[j] = t;
+        }
+        double den = std::sqrt(std::norm(col[k]) + std::norm(col[k + 1]));
+        c[k] = den > 0 ? std::conj(col[k]) / den : 1.0;
+        sv[k] = den > 0 ? std::conj(col[k + 1]) / den : 0.0;
+        col[k] = den;
+        col[k + 1] = 0.0;
+        std::complex<double>* gg = &gv[(size_t)r * (m + 1)];
+        gg[k + 1] = -std::conj(sv[k]) * gg[k];
+        gg[k] = c[k] * gg[k];
+        double est = fnorm[r] > 0 ? std::abs(gg[k + 1]) / fnorm[r] : 0.0;
+        if (kdone[r] < 0 && (est <= tol || hn == 0.0)) kdone[r] = k + 1;
+        if (kdone[r] < 0) all_done = false;
+      }
+      HIPCHK(hipMemcpyAsync(g.sdev, invn.data(), 8 * R, hipMemcpyHostToDevice, g.st));
+      HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
+      if (all_done) { ++k; break; }
+    }
+    // x += V y  (each rhs uses its own Krylov dimension)
+    std::vector<std::complex<double>> y((size_t)R * m, 0.0);
+    for (int r = 0; r < R; ++r) {
+      int kk = kdone[r] >= 0 ? kdone[r] : k;
+      const std::complex<double>* Hr = &Hm[(size_t)r * m * (m + 1)];
+      const std::complex<double>* gg = &gv[(size_t)r * (m + 1)];
+      for (int i = kk - 1; i >= 0; --i) {
+        std::complex<double> sacc = gg[i];
+        for (int j = i + 1; j < kk; ++j) sacc -= Hr[(size_t)j * (m + 1) + i] * y[(size_t)r * m + j];
+        y[(size_t)r * m + i] = sacc / Hr[(size_t)i * (m + 1) + i];
+      }
+    }
+    std::vector<std::complex<double>> yk((size_t)R * std::max(k, 1), 0.0);
+    for (int r = 0; r < R; ++r)
+      for (int j = 0; j < k; ++j) yk[(size_t)r * k + j] = y[(size_t)r * m + j];
+    HIPCHK(hipMemcpyAsync(g.hdev, yk.data(), 16 * yk.size(), hipMemcpyHostToDevice, g.st));
+    if (k > 0) HIPCHK(lsx::gm_axpy_combo(x, g.V, g.hdev, k, N, R, vstride, g.st));
+  }
+  *iters = it;
+  return LS_OK;
+}
+
+}  // namespace
+
+ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls_solve_opts* opts,
+                   ls_solve_stats* stats, void* stream) {
+  if (!op || !u_inc || !u_tot || !opts || nrhs < 1) return fail(LS_EINVAL, "null argument");
+  if (opts->restart < 1 || opts->max_iter < 1 || !(opts->tol > 0)) return fail(LS_EINVAL, "bad solver options");
+  auto t0 = std::chrono::steady_clock::now();
+  Gm g{};
+  g.op = op;
+  g.nrhs = nrhs;
+  g.m = opts->restart;
+  g.N = op->N;
+  g.st = (hipStream_t)stream;
+  ls_status s = gm_setup(g);
+  if (s) return s;
+  const double2* f = (const double2*)u_inc;
+  double2* x = (double2*)u_tot;
+  const int64_t n = op->N * nrhs;
+  if (!opts->use_x0) HIPCHK(hipMemsetAsync(x, 0, 16 * (size_t)n, g.st));
+  int iters = 0, outer = 0;
+  std::vector<double> rel;
+  if (opts->mode == LS_SOLVE_FP64) {
+    s = gmres(g, f, x, !opts->use_x0, opts->tol, opts->max_iter, LS_C128, &iters, rel);
+    if (s) return s;
+  } else {
+    // FP64 residual, FP32 inner solves, x += e
+    int total = 0;
+    bool xzero = !opts->use_x0;
+    for (outer = 0;; ++outer) {
+      if (xzero) {
+        HIPCHK(hipMemcpyAsync(g.rout, f, 16 * (size_t)n, hipMemcpyDeviceToDevice, g.st));
+      } else {
+        s = gm_apply(g, x, g.w, LS_C128);
+        if (s) return s;
+        HIPCHK(lsx::gm_sub(f, g.w, g.rout, n, g.st));
+      }
+      std::vector<std::complex<double>> dr, df;
+      s = gm_dots_host(g, g.rout, g.rout, 1, 0, dr);
+      if (s) return s;
+      s = gm_dots_host(g, f, f, 1, 0, df);
+      if (s) return s;
+      bool all = true;
+      for (int k = 0; k < nrhs; ++k)
+        if (std::sqrt(dr[k].real()) > opts->tol * std::sqrt(df[k].real())) all = false;
+      if (all || total >= opts->max_iter || outer >= std::max(1, opts->max_outer)) break;
+      HIPCHK(hipMemsetAsync(g.e, 0, 16 * (size_t)n, g.st));
+      int it = 0;
+      std::vector<double> rr;
+      s = gmres(g, g.rout, g.e, true, opts->inner_tol, opts->max_iter - total, LS_C64, &it, rr);
+      if (s) return s;
+      total += it;
+      HIPCHK(lsx::gm_add(x, g.e, n, g.st));
+      xzero = false;
+    }
+    iters = total;
+  }
+  // true FP64 residual
+  s = gm_apply(g, x, g.w, LS_C128);
+  if (s) return s;
+  HIPCHK(lsx::gm_sub(f, g.w, g.r, n, g.st));
+  std::vector<std::complex<double>> dr, df;
+  s = gm_dots_host(g, g.r, g.r, 1, 0, dr);
+  if (s) return s;
+  s = gm_dots_host(g, f, f, 1, 0, df);
+  if (s) return s;
+  double worst = 0;
+  int conv = 0;
+  for (int k = 0; k < nrhs; ++k) {
+    double rr = df[k].real() > 0 ? std::sqrt(dr[k].real() / df[k].real()) : 0.0;
+    worst = std::max(worst, rr);
+    if (rr <= opts->tol) ++conv;
+  }
+  if (stats) {
+    stats->iterations = iters;
+    stats->outer = outer;
+    stats->converged = conv;
+    stats->rel_residual = worst;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->apply_seconds = g.apply_s;
+  }
+  return conv == nrhs ? LS_OK : fail(LS_ENOCONV, "tolerance not reached");
+}
+
+}  // extern "C"

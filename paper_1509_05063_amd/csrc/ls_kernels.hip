@@ -1,0 +1,737 @@
+// Device kernels of the operator apply (HIP, gfx950).
+//
+// Data layout (all vector-major, [rhs][...]):
+//   u, v        [nrhs][N] complex, operator order (sorted by cell)
+//   sigma       [nrhs][ncell][U] equivalent-source strengths per cell
+//   lattice     [nrhs][2 sets][2 kinds][Pa][Pb] zero-padded face lattices
+//   after the spectral product the field of set s sits in kind 0.
+#include <hip/hip_runtime.h>
+
+#include "ls_kernels.hpp"
+
+namespace lsx {
+
+template <typename T> struct C2;
+template <> struct C2<double> { using t = double2; };
+template <> struct C2<float> { using t = float2; };
+
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename V> __device__ __forceinline__ V cfma(V a, V b, V c) {   // c + a*b
+  c.x = fma(a.x, b.x, c.x);
+  c.x = fma(-a.y, b.y, c.x);
+  c.y = fma(a.x, b.y, c.y);
+  c.y = fma(a.y, b.x, c.y);
+  return c;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { a.x += b.x; a.y += b.y; return a; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename V> __device__ __forceinline__ V cscale(V a, decltype(a.x) s) { a.x *= s; a.y *= s; return a; }
+template <typename V> __device__ __forceinline__ V czero() { V r; r.x = 0; r.y = 0; return r; }
+
+// ---------------------------------------------------------------------------
+// a1: projection onto equivalent sources.  One workgroup per occupied cell
+// and right-hand side; sigma_c = Psh phi_slots + sum_b Pbd_b phi_b with
+// phi = c u (plain quadrature weight times density).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_project(const typename C2<T>::t* __restrict__ u,
+                                                 typename C2<T>::t* __restrict__ sigma,
+                                                 const typename C2<T>::t* __restrict__ Psh,
+                                                 const typename C2<T>::t* __restrict__ Pbd,
+                                                 const T* __restrict__ cw, const int32_t* __restrict__ slot_map,
+                                                 const int32_t* __restrict__ cell_start,
+                                                 const int32_t* __restrict__ cell_nint,
+                                                 const int32_t* __restrict__ cell_nb,
+                                                 const int32_t* __restrict__ cell_boff, int S, int U,
+                                                 int64_t N, int ncell) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  V* phi = reinterpret_cast<V*>(smem_raw);
+  const int c = blockIdx.x;
+  const int r = blockIdx.y;
+  const V* ur = u + (int64_t)r * N;
+  const int nb = cell_nb[c];
+  const int b0 = cell_start[c] + cell_nint[c];
+  for (int a = threadIdx.x; a < S + nb; a += blockDim.x) {
+    int64_t j = a < S ? slot_map[(int64_t)c * S + a] : (int64_t)(b0 + a - S);
+    phi[a] = j >= 0 ? cscale(ur[j], cw[j]) : czero<V>();
+  }
+  __syncthreads();
+  const int64_t boff = cell_boff[c];
+  for (int t = threadIdx.x; t < U; t += blockDim.x) {
+    V acc = czero<V>();
+    const V* prow = Psh + (int64_t)t * S;
+    for (int a = 0; a < S; ++a) acc = cfma(prow[a], phi[a], acc);
+    for (int b = 0; b < nb; ++b) acc = cfma(Pbd[(boff + b) * U + t], phi[S + b], acc);
+    sigma[((int64_t)r * ncell + c) * U + t] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lattice fill: node (a, b) of set s gathers face 0 of the cell whose
+// normal index is a and face 1 of the cell a-1 (at most two cells, no
+// atomics); zero padding elsewhere.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(const typename C2<T>::t* __restrict__ sigma, typename C2<T>::t* __restrict__ lat,
+                       const int32_t* __restrict__ cell_map, int L, int q, int U, int ncell, int na,
+                       int nb, int Pa, int Pb) {
+  using V = typename C2<T>::t;
+  const int64_t plane = (int64_t)Pa * Pb;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= plane) return;
+  const int s = blockIdx.y;       // set
+  const int r = blockIdx.z;       // rhs
+  const int a = (int)(idx / Pb), b = (int)(idx % Pb);
+  V mono = czero<V>(), dip = czero<V>();
+  if (a < na && b < nb) {
+    const int t = b / q, j = b % q;
+    for (int f = 0; f < 2; ++f) {
+      int cn = a - f;            // cell index along the set's normal axis
+      if (cn < 0 || cn >= L) continue;
+      int cx = s == 0 ? cn : t, cy = s == 0 ? t : cn;
+      int c = cell_map[cy * L + cx];
+      if (c < 0) continue;
+      const V* sg = sigma + ((int64_t)r * ncell + c) * U + s * 4 * q;
+      mono = cadd(mono, sg[f * q + j]);
+      dip = cadd(dip, sg[2 * q + f * q + j]);
+    }
+  }
+  V* base = lat + ((int64_t)(r * 2 + s) * 2) * plane;
+  base[idx] = mono;
+  base[plane + idx] = dip;
+}
+
+// ---------------------------------------------------------------------------
+// FFT: Stockham autosort (mixed radix 2/3/4/5), one transform per workgroup
+// held in LDS, twiddles from a table W_n^k = exp(-2 pi i k / n).  Pass with
+// radix R and current sub-length Ns: butterfly j reads x[j + m n/R],
+// multiplies by W^{(j mod Ns) m n/(Ns R)}, applies the R-point DFT and writes
+// y[(j / Ns) Ns R + (j mod Ns) + m Ns].
+// ---------------------------------------------------------------------------
+template <typename V, int DIR>
+__device__ __forceinline__ void dft_small(V* v, int R) {
+  using T = decltype(v[0].x);
+  if (R == 2) {
+    V a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if (R == 4) {
+    V a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    V b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+    // b1 * (-i DIR)
+    V rb1;
+    rb1.x = DIR > 0 ? b1.y : -b1.y;
+    rb1.y = DIR > 0 ? -b1.x : b1.x;
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd(a1, rb1);
+    v[3] = csub(a1, rb1);
+  } else if (R == 3) {
+    const T c1 = (T)-0.5, s1 = (T)(DIR > 0 ? -0.86602540378443864676 : 0.86602540378443864676);
+    V t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    V y0 = cadd(v[0], t1);
+    V m1;
+    m1.x = v[0].x + c1 * t1.x;
+    m1.y = v[0].y + c1 * t1.y;
+    V m2;                         // i s1 t2
+    m2.x = -s1 * t2.y;
+    m2.y = s1 * t2.x;
+    v[0] = y0;
+    v[1] = cadd(m1, m2);
+    v[2] = csub(m1, m2);
+  } else {   // R == 5
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)(DIR > 0 ? -0.95105651629515357212 : 0.95105651629515357212);
+    const T s2 = (T)(DIR > 0 ? -0.58778525229247312917 : 0.58778525229247312917);
+    V a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    V a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    V y0 = cadd(v[0], cadd(a1, a2));
+    V p1, p2;
+    p1.x = v[0].x + c1 * a1.x + c2 * a2.x;
+    p1.y = v[0].y + c1 * a1.y + c2 * a2.y;
+    p2.x = v[0].x + c2 * a1.x + c1 * a2.x;
+    p2.y = v[0].y + c2 * a1.y + c1 * a2.y;
+    V q1, q2;   // i (s1 b1 + s2 b2), i (s2 b1 - s1 b2)
+    q1.x = -(s1 * b1.y + s2 * b2.y);
+    q1.y = s1 * b1.x + s2 * b2.x;
+    q2.x = -(s2 * b1.y - s1 * b2.y);
+    q2.y = s2 * b1.x - s1 * b2.x;
+    v[0] = y0;
+    v[1] = cadd(p1, q1);
+    v[4] = csub(p1, q1);
+    v[2] = cadd(p2, q2);
+    v[3] = csub(p2, q2);
+  }
+}
+
+template <typename V, int DIR>
+__device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, const int8_t* radix,
+                             int npass, int stride, int tid, int nthr, V** result) {
+  // stride: distance between consecutive elements of one transform in LDS
+  // (1 for rows; >1 when several columns are interleaved).  The transforms
+  // handled by this call are at offsets 0..stride-1 (one per lane group).
+  V* src = buf0;
+  V* dst = buf1;
+  int Ns = 1;
+  for (int p = 0; p < npass; ++p) {
+    const int R = radix[p];
+    const int nb = n / R;
+    const int twstep = n / (Ns * R);
+    for (int w = tid; w < nb * stride; w += nthr) {
+      const int j = w / stride, lane = w % stride;
+      V v[5];
+      const int jm = j % Ns;
+      for (int m = 0; m < R; ++m) {
+        V x = src[(j + m * nb) * stride + lane];
+        if (m > 0 && jm > 0) {
+          V t = tw[(jm * m * twstep) % n];
+          if (DIR < 0) t.y = -t.y;
+          x = cmul(x, t);
+        }
+        v[m] = x;
+      }
+      dft_small<V, DIR>(v, R);
+      const int o = (j / Ns) * Ns * R + jm;
+      for (int m = 0; m < R; ++m) dst[(o + m * Ns) * stride + lane] = v[m];
+    }
+    __syncthreads();
+    V* t = src;
+    src = dst;
+    dst = t;
+    Ns *= R;
+  }
+  *result = src;
+}
+
+// transforms along the contiguous axis: one line per workgroup
+template <typename T, int DIR>
+__global__ void __launch_bounds__(256) k_fft_rows(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
+                                                  FftPlan plan, int64_t line_stride, int lines_per_batch,
+                                                  int64_t batch_stride) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  V* b0 = reinterpret_cast<V*>(smem_raw);
+  V* b1 = b0 + plan.n;
+  const int line = blockIdx.x;
+  const int batch = blockIdx.y;
+  V* x = data + batch * batch_stride + (int64_t)line * line_stride;
+  for (int i = threadIdx.x; i < plan.n; i += blockDim.x) b0[i] = x[i];
+  __syncthreads();
+  V* res;
+  stockham_lds<V, DIR>(b0, b1, tw, plan.n, plan.radix, plan.npass, 1, threadIdx.x, blockDim.x, &res);
+  for (int i = threadIdx.x; i < plan.n; i += blockDim.x) x[i] = res[i];
+  (void)lines_per_batch;
+}
+
+// transforms along the strided axis: a workgroup takes TC adjacent columns
+template <typename T, int DIR>
+__global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
+                                                  FftPlan plan, int ncols, int TC, int64_t batch_stride) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  V* b0 = reinterpret_cast<V*>(smem_raw);
+  V* b1 = b0 + plan.n * TC;
+  const int c0 = blockIdx.x * TC;
+  const int batch = blockIdx.y;
+  const int tc = min(TC, ncols - c0);
+  V* x = data + batch * batch_stride + c0;
+  for (int i = threadIdx.x; i < plan.n * TC; i += blockDim.x) {
+    int row = i / TC, col = i % TC;
+    b0[i] = col < tc ? x[(int64_t)row * ncols + col] : czero<V>();
+  }
+  __syncthreads();
+  V* res;
+  stockham_lds<V, DIR>(b0, b1, tw, plan.n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res);
+  for (int i = threadIdx.x; i < plan.n * TC; i += blockDim.x) {
+    int row = i / TC, col = i % TC;
+    if (col < tc) x[(int64_t)row * ncols + col] = res[i];
+  }
+}
+
+// spectral product: set s field = FFT(mono) Khat_m + FFT(dip) Khat_d (into kind 0)
+template <typename T>
+__global__ void k_spectral(typename C2<T>::t* __restrict__ lat, const typename C2<T>::t* __restrict__ khat,
+                           int64_t plane) {
+  using V = typename C2<T>::t;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= plane) return;
+  const int s = blockIdx.y, r = blockIdx.z;
+  V* m = lat + ((int64_t)(r * 2 + s) * 2) * plane;
+  const V* km = khat + (int64_t)(s * 2) * plane;
+  V out = cmul(m[idx], km[idx]);
+  out = cfma(m[plane + idx], km[plane + idx], out);
+  m[idx] = out;
+}
+
+// ---------------------------------------------------------------------------
+// a3 + a5: per cell, face values of the lattice field minus the adjacent
+// cells' equivalent-source fields, Dirichlet fit to the cell's nodes,
+// v = u + kappa^2 far.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restrict__ u,
+                                                typename C2<T>::t* __restrict__ v,
+                                                const typename C2<T>::t* __restrict__ lat,
+                                                const typename C2<T>::t* __restrict__ sigma,
+                                                const typename C2<T>::t* __restrict__ Toff,
+                                                const typename C2<T>::t* __restrict__ Ish,
+                                                const typename C2<T>::t* __restrict__ Ibd,
+                                                const int32_t* __restrict__ cell_xy,
+                                                const int32_t* __restrict__ cell_map,
+                                                const int32_t* __restrict__ slot_map,
+                                                const int32_t* __restrict__ cell_start,
+                                                const int32_t* __restrict__ cell_nint,
+                                                const int32_t* __restrict__ cell_nb,
+                                                const int32_t* __restrict__ cell_boff, int L, int q, int U,
+                                                int F, int S, int ncell, int Pa, int Pb, int64_t N, T k2) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  V* f = reinterpret_cast<V*>(smem_raw);      // F face values
+  V* sg = f + F;                              // 9 * U neighbour strengths
+  int* nbr = reinterpret_cast<int*>(sg + 9 * U);
+  const int c = blockIdx.x, r = blockIdx.y;
+  const int cx = cell_xy[2 * c], cy = cell_xy[2 * c + 1];
+  const int64_t plane = (int64_t)Pa * Pb;
+  if (threadIdx.x < 9) {
+    int ox = threadIdx.x % 3 - 1, oy = threadIdx.x / 3 - 1;
+    int nx = cx + ox, ny = cy + oy;
+    nbr[threadIdx.x] = (nx >= 0 && ny >= 0 && nx < L && ny < L) ? cell_map[ny * L + nx] : -1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 9 * U; i += blockDim.x) {
+    int o = i / U;
+    int cn = nbr[o];
+    sg[i] = cn >= 0 ? sigma[((int64_t)r * ncell + cn) * U + (i % U)] : czero<V>();
+  }
+  for (int t = threadIdx.x; t < F; t += blockDim.x) {
+    int s = t / (2 * q), fj = t % (2 * q), fc = fj / q, j = fj % q;
+    int cn = (s == 0 ? cx : cy) + fc, ct = (s == 0 ? cy : cx);
+    f[t] = lat[((int64_t)(r * 2 + s) * 2) * plane + (int64_t)cn * Pb + ct * q + j];
+  }
+  __syncthreads();
+  // subtract adjacent equivalent-source fields (same set only)
+  for (int t = threadIdx.x; t < F; t += blockDim.x) {
+    int s = t / (2 * q);
+    V acc = f[t];
+    for (int o = 0; o < 9; ++o) {
+      if (nbr[o] < 0) continue;
+      const V* Trow = Toff + ((int64_t)o * F + t) * U + s * 4 * q;
+      const V* sv = sg + o * U + s * 4 * q;
+      for (int k = 0; k < 4 * q; ++k) acc = csub(acc, cmul(Trow[k], sv[k]));
+    }
+    f[t] = acc;
+  }
+  __syncthreads();
+  const V* ur = u + (int64_t)r * N;
+  V* vr = v + (int64_t)r * N;
+  const int nint = cell_nint[c], nb = cell_nb[c];
+  for (int a = threadIdx.x; a < S; a += blockDim.x) {
+    int j = slot_map[(int64_t)c * S + a];
+    if (j < 0) continue;
+    V acc = czero<V>();
+    const V* irow = Ish + (int64_t)a * F;
+    for (int t = 0; t < F; ++t) acc = cfma(irow[t], f[t], acc);
+    V uj = ur[j];
+    vr[j] = cadd(uj, cscale(acc, k2));
+  }
+  const int64_t boff = cell_boff[c];
+  const int b0 = cell_start[c] + nint;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    V acc = czero<V>();
+    const V* irow = Ibd + (boff + b) * F;
+    for (int t = 0; t < F; ++t) acc = cfma(irow[t], f[t], acc);
+    int64_t j = b0 + b;
+    vr[j] = cadd(ur[j], cscale(acc, k2));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a4, interior x interior: out[a][cell] += sum_b W[a][b] psi[b][cell] over
+// the 5x5-cell window (translation invariant weights).  Tiled: a workgroup
+// takes CT cells; W and psi chunks staged in LDS.
+// ---------------------------------------------------------------------------
+template <typename T, int CT, int KC>
+__global__ void __launch_bounds__(256) k_near_shared(const typename C2<T>::t* __restrict__ u,
+                                                     typename C2<T>::t* __restrict__ v,
+                                                     const typename C2<T>::t* __restrict__ W,
+                                                     const T* __restrict__ dw,
+                                                     const int32_t* __restrict__ icells,
+                                                     const int32_t* __restrict__ cell_xy,
+                                                     const int32_t* __restrict__ cell_map,
+                                                     const int32_t* __restrict__ slot_map, int L, int ch,
+                                                     int S, int nicell, int64_t N, T k2) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  V* Ws = reinterpret_cast<V*>(smem_raw);            // S x KC
+  V* Xs = Ws + S * KC;                               // KC x CT
+  int* wc = reinterpret_cast<int*>(Xs + KC * CT);    // 25 x CT window cell ids
+  const int Wn = 5 * ch, K = Wn * Wn;
+  const int r = blockIdx.y;
+  const int cbase = blockIdx.x * CT;
+  const V* ur = u + (int64_t)r * N;
+  for (int i = threadIdx.x; i < 25 * CT; i += blockDim.x) {
+    int cc = i / 25, o = i % 25;
+    int cid = cbase + cc < nicell ? icells[cbase + cc] : -1;
+    int res = -1;
+    if (cid >= 0) {
+      int nx = cell_xy[2 * cid] + o % 5 - 2, ny = cell_xy[2 * cid + 1] + o / 5 - 2;
+      if (nx >= 0 && ny >= 0 && nx < L && ny < L) res = cell_map[ny * L + nx];
+    }
+    wc[cc * 25 + o] = res;
+  }
+  // each thread owns outputs (a, cc) for a = tid % S + k*?  -> S*CT / 256 outputs
+  constexpr int MAXO = 8;
+  const int nout = (S * CT + blockDim.x - 1) / blockDim.x;
+  V acc[MAXO];
+  for (int k = 0; k < MAXO; ++k) acc[k] = czero<V>();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    const int kc = min(KC, K - k0);
+    for (int i = threadIdx.x; i < S * KC; i += blockDim.x) {
+      int a = i / KC, kk = i % KC;
+      Ws[i] = kk < kc ? W[(int64_t)a * K + k0 + kk] : czero<V>();
+    }
+    for (int i = threadIdx.x; i < KC * CT; i += blockDim.x) {
+      int kk = i / CT, cc = i % CT;
+      V val = czero<V>();
+      if (kk < kc) {
+        int b = k0 + kk;
+        int wx = b % Wn, wy = b / Wn;
+        int cn = wc[cc * 25 + (wy / ch) * 5 + (wx / ch)];
+        if (cn >= 0) {
+          int j = slot_map[(int64_t)cn * S + (wy % ch) * ch + (wx % ch)];
+          if (j >= 0) val = cscale(ur[j], dw[j]);
+        }
+      }
+      Xs[i] = val;
+    }
+    __syncthreads();
+    for (int o = 0; o < nout && o < MAXO; ++o) {
+      int id = threadIdx.x + o * blockDim.x;
+      if (id >= S * CT) break;
+      int a = id % S, cc = id / S;
+      V s = acc[o];
+      for (int kk = 0; kk < kc; ++kk) s = cfma(Ws[a * KC + kk], Xs[kk * CT + cc], s);
+      acc[o] = s;
+    }
+    __syncthreads();
+  }
+  V* vr = v + (int64_t)r * N;
+  for (int o = 0; o < nout && o < MAXO; ++o) {
+    int id = threadIdx.x + o * blockDim.x;
+    if (id >= S * CT) break;
+    int a = id % S, cc = id / S;
+    if (cbase + cc >= nicell) continue;
+    int cid = icells[cbase + cc];
+    int j = slot_map[(int64_t)cid * S + a];
+    if (j < 0) continue;
+    V t = vr[j];
+    vr[j] = cadd(t, cscale(acc[o], k2));
+  }
+}
+
+// a4, rows touching the boundary patch: one wavefront per row
+template <typename T, typename VT>
+__global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __restrict__ u,
+                                                  typename C2<T>::t* __restrict__ v,
+                                                  const int64_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ rows,
+                                                  const int32_t* __restrict__ cols, const VT* __restrict__ vals,
+                                                  int nrows, int64_t N, int nrhs, T k2) {
+  using V = typename C2<T>::t;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (row >= nrows) return;
+  const int64_t b = rowptr[row], e = rowptr[row + 1];
+  for (int r = 0; r < nrhs; ++r) {
+    const V* ur = u + (int64_t)r * N;
+    V acc = czero<V>();
+    for (int64_t k = b + lane; k < e; k += 64) {
+      VT w = vals[k];
+      V ww;
+      ww.x = (T)w.x;
+      ww.y = (T)w.y;
+      acc = cfma(ww, ur[cols[k]], acc);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_down(acc.x, off, 64);
+      acc.y += __shfl_down(acc.y, off, 64);
+    }
+    if (lane == 0) {
+      int64_t j = rows[row];
+      V* vr = v + (int64_t)r * N;
+      V t = vr[j];
+      vr[j] = cadd(t, cscale(acc, k2));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES helpers (FP64): dots d[j][r] = <V_j r, w_r>, w -= sum_j h V_j, norms
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_dots(const double2* __restrict__ Vb, const double2* __restrict__ w,
+                                              double2* __restrict__ partial, int nvec, int64_t N, int nrhs,
+                                              int64_t vstride) {
+  // grid.x: blocks over N; grid.y: rhs.  partial[(r * nvec + j) * gridDim.x + blockIdx.x]
+  __shared__ double2 red[256];
+  const int r = blockIdx.y;
+  const double2* wr = w + (int64_t)r * N;
+  for (int j = 0; j < nvec; ++j) {
+    const double2* vj = Vb + j * vstride + (int64_t)r * N;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+      double2 a = vj[i], b = wr[i];
+      acc.x += a.x * b.x + a.y * b.y;    // conj(a) b
+      acc.y += a.x * b.y - a.y * b.x;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        red[threadIdx.x].x += red[threadIdx.x + s].x;
+        red[threadIdx.x].y += red[threadIdx.x + s].y;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[((int64_t)r * nvec + j) * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_reduce_partials(const double2* __restrict__ partial, double2* __restrict__ out, int nparts,
+                                  int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int p = 0; p < nparts; ++p) {
+    s.x += partial[(int64_t)i * nparts + p].x;
+    s.y += partial[(int64_t)i * nparts + p].y;
+  }
+  out[i] = s;
+}
+
+__global__ void k_update(const double2* __restrict__ Vb, double2* __restrict__ w, const double2* __restrict__ h,
+                         int nvec, int64_t N, int nrhs, int64_t vstride) {
+  const int r = blockIdx.y;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double2 acc = w[(int64_t)r * N + i];
+  for (int j = 0; j < nvec; ++j) {
+    double2 hj = h[r * nvec + j];
+    double2 a = Vb[j * vstride + (int64_t)r * N + i];
+    acc.x -= hj.x * a.x - hj.y * a.y;
+    acc.y -= hj.x * a.y + hj.y * a.x;
+  }
+  w[(int64_t)r * N + i] = acc;
+}
+
+__global__ void k_scale_copy(const double2* __restrict__ src, double2* __restrict__ dst, const double* __restrict__ s,
+                             int64_t N) {
+  const int r = blockIdx.y;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double f = s[r];
+  double2 a = src[(int64_t)r * N + i];
+  dst[(int64_t)r * N + i] = make_double2(a.x * f, a.y * f);
+}
+
+__global__ void k_axpy_combo(double2* __restrict__ x, const double2* __restrict__ Vb, const double2* __restrict__ y,
+                             int nvec, int64_t N, int64_t vstride) {
+  // x_r += sum_j y[r][j] V_j r
+  const int r = blockIdx.y;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double2 acc = x[(int64_t)r * N + i];
+  for (int j = 0; j < nvec; ++j) {
+    double2 c = y[r * nvec + j];
+    double2 a = Vb[j * vstride + (int64_t)r * N + i];
+    acc.x += c.x * a.x - c.y * a.y;
+    acc.y += c.x * a.y + c.y * a.x;
+  }
+  x[(int64_t)r * N + i] = acc;
+}
+
+__global__ void k_sub(const double2* __restrict__ a, const double2* __restrict__ b, double2* __restrict__ out,
+                      int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = make_double2(a[i].x - b[i].x, a[i].y - b[i].y);
+}
+
+__global__ void k_add(double2* __restrict__ x, const double2* __restrict__ e, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] = make_double2(x[i].x + e[i].x, x[i].y + e[i].y);
+}
+
+__global__ void k_to_f32(const double2* __restrict__ a, float2* __restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+__global__ void k_to_f64(const float2* __restrict__ a, double2* __restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  b[i] = make_double2((double)a[i].x, (double)a[i].y);
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs, void* ws_, hipStream_t st) {
+  using V = typename C2<T>::t;
+  const V* u = static_cast<const V*>(u_);
+  V* v = static_cast<V*>(v_);
+  V* sigma = static_cast<V*>(ws_);
+  V* lat = sigma + (size_t)nrhs * d.ncell * d.U;
+  const int64_t plane = (int64_t)d.Pa * d.Pb;
+  const T k2 = (T)(d.kappa * d.kappa);
+  // a0 + a1
+  {
+    size_t sh = (size_t)(d.S + d.max_nb) * sizeof(V);
+    hipLaunchKernelGGL(k_project<T>, dim3(d.ncell, nrhs), dim3(128), sh, st, u, sigma, (const V*)d.Psh,
+                       (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
+                       d.S, d.U, d.N, d.ncell);
+  }
+  // lattice fill
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, sigma, lat,
+                     d.cell_map, d.L, d.q, d.U, d.ncell, d.na, d.nb, d.Pa, d.Pb);
+  // a2: forward transforms of all 4 arrays per rhs
+  const int nbatch = nrhs * 4;
+  {
+    size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
+    // rows a >= na are zero padding: their transforms stay zero
+    hipLaunchKernelGGL((k_fft_rows<T, 1>), dim3(d.na, nbatch), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
+                       (int64_t)d.Pb, d.na, plane);
+    int TC = d.tc;
+    size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
+    hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, lat,
+                       (const V*)d.twa, d.pa, d.Pb, TC, plane);
+  }
+  hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, lat,
+                     (const V*)d.khat, plane);
+  {
+    // inverse transforms of kind 0 of each set: batch stride 2 planes
+    int TC = d.tc;
+    size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
+    hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
+                       (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane);
+    size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
+    hipLaunchKernelGGL((k_fft_rows<T, -1>), dim3(d.na, nrhs * 2), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
+                       (int64_t)d.Pb, d.na, 2 * plane);
+  }
+  // a3 + a5
+  {
+    size_t sh = (size_t)(d.F + 9 * d.U) * sizeof(V) + 16 * sizeof(int);
+    hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(128), sh, st, u, v, (const V*)lat, (const V*)sigma,
+                       (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.cell_map, d.slot_map,
+                       d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L, d.q, d.U, d.F, d.S, d.ncell,
+                       d.Pa, d.Pb, d.N, k2);
+  }
+  // a4 shared
+  {
+    constexpr int CT = 16, KC = 32;
+    size_t sh = (size_t)(d.S * KC + KC * CT) * sizeof(V) + 25 * CT * sizeof(int);
+    hipLaunchKernelGGL((k_near_shared<T, CT, KC>), dim3((d.nicell + CT - 1) / CT, nrhs), dim3(256), sh, st, u, v,
+                       (const V*)d.Wsh, d.dw, d.icells, d.cell_xy, d.cell_map, d.slot_map, d.L, d.ch, d.S,
+                       d.nicell, d.N, k2);
+  }
+  // a4 csr
+  if (d.nrows > 0) {
+    if (d.csr_f64)
+      hipLaunchKernelGGL((k_near_csr<T, double2>), dim3((d.nrows + 3) / 4), dim3(256), 0, st, u, v, d.rowptr,
+                         d.rows, d.cols, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
+    else
+      hipLaunchKernelGGL((k_near_csr<T, float2>), dim3((d.nrows + 3) / 4), dim3(256), 0, st, u, v, d.rowptr,
+                         d.rows, d.cols, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_apply<double>(const DevView<double>&, const void*, void*, int, void*, hipStream_t);
+template hipError_t launch_apply<float>(const DevView<float>&, const void*, void*, int, void*, hipStream_t);
+
+hipError_t set_fft_lds_limits(size_t bytes) {
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f) {
+    hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (r != hipSuccess) e = r;
+  };
+  set((const void*)k_fft_rows<double, 1>);
+  set((const void*)k_fft_rows<double, -1>);
+  set((const void*)k_fft_cols<double, 1>);
+  set((const void*)k_fft_cols<double, -1>);
+  set((const void*)k_fft_rows<float, 1>);
+  set((const void*)k_fft_rows<float, -1>);
+  set((const void*)k_fft_cols<float, 1>);
+  set((const void*)k_fft_cols<float, -1>);
+  return e;
+}
+
+hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st) {
+  using V = double2;
+  const int64_t plane = (int64_t)d.Pa * d.Pb;
+  size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
+  hipLaunchKernelGGL((k_fft_rows<double, 1>), dim3(d.Pa, nbatch), dim3(256), sh, st, (V*)data, (const V*)d.twb,
+                     d.pb, (int64_t)d.Pb, d.Pa, plane);
+  int TC = d.tc;
+  size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
+  hipLaunchKernelGGL((k_fft_cols<double, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, (V*)data,
+                     (const V*)d.twa, d.pa, d.Pb, TC, plane);
+  return hipGetLastError();
+}
+
+// GMRES launchers
+hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int nvec, int64_t N, int nrhs,
+                   int64_t vstride, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(k_dots, dim3(nparts, nrhs), dim3(256), 0, st, (const double2*)Vb, (const double2*)w,
+                     (double2*)partial, nvec, N, nrhs, vstride);
+  int count = nvec * nrhs;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((count + 63) / 64), dim3(64), 0, st, (const double2*)partial,
+                     (double2*)out, nparts, count);
+  return hipGetLastError();
+}
+hipError_t gm_update(const void* Vb, void* w, const void* h, int nvec, int64_t N, int nrhs, int64_t vstride,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_update, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, (const double2*)Vb,
+                     (double2*)w, (const double2*)h, nvec, N, nrhs, vstride);
+  return hipGetLastError();
+}
+hipError_t gm_scale_copy(const void* src, void* dst, const double* s, int64_t N, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, (const double2*)src,
+                     (double2*)dst, s, N);
+  return hipGetLastError();
+}
+hipError_t gm_axpy_combo(void* x, const void* Vb, const void* y, int nvec, int64_t N, int nrhs, int64_t vstride,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_combo, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, (double2*)x,
+                     (const double2*)Vb, (const double2*)y, nvec, N, vstride);
+  return hipGetLastError();
+}
+hipError_t gm_sub(const void* a, const void* b, void* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double2*)a,
+                     (const double2*)b, (double2*)out, n);
+  return hipGetLastError();
+}
+hipError_t gm_add(void* x, const void* e, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (double2*)x, (const double2*)e, n);
+  return hipGetLastError();
+}
+hipError_t gm_to_f32(const void* a, void* b, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double2*)a, (float2*)b, n);
+  return hipGetLastError();
+}
+hipError_t gm_to_f64(const void* a, void* b, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const float2*)a, (double2*)b, n);
+  return hipGetLastError();
+}
+
+}  // namespace lsx

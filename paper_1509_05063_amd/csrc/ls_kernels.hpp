@@ -1,0 +1,51 @@
+// Device-side views and launchers (internal header).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lsx {
+
+struct FftPlan {
+  int n;
+  int npass;
+  int8_t radix[28];
+};
+
+// Everything one apply needs, for one precision T (double or float).
+template <typename T>
+struct DevView {
+  int64_t N = 0;
+  int ncell = 0, nicell = 0, S = 0, U = 0, F = 0, q = 0, L = 0, na = 0, nb = 0, Pa = 0, Pb = 0, ch = 0;
+  int max_nb = 0, tc = 1, nrows = 0;
+  bool csr_f64 = true;
+  double kappa = 0;
+  const void *Psh = nullptr, *Pbd = nullptr, *Ish = nullptr, *Ibd = nullptr, *Toff = nullptr, *Wsh = nullptr;
+  const void *khat = nullptr, *twa = nullptr, *twb = nullptr, *vals = nullptr;
+  const T *cw = nullptr, *dw = nullptr;
+  const int32_t *slot_map = nullptr, *cell_start = nullptr, *cell_nint = nullptr, *cell_nb = nullptr;
+  const int32_t *cell_boff = nullptr, *cell_xy = nullptr, *cell_map = nullptr, *icells = nullptr;
+  const int32_t *rows = nullptr, *cols = nullptr;
+  const int64_t* rowptr = nullptr;
+  FftPlan pa{}, pb{};
+};
+
+template <typename T>
+hipError_t launch_apply(const DevView<T>& d, const void* u, void* v, int nrhs, void* ws, hipStream_t st);
+hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st);
+hipError_t set_fft_lds_limits(size_t bytes);
+
+// GMRES building blocks (double complex)
+hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int nvec, int64_t N, int nrhs,
+                   int64_t vstride, int nparts, hipStream_t st);
+hipError_t gm_update(const void* Vb, void* w, const void* h, int nvec, int64_t N, int nrhs, int64_t vstride,
+                     hipStream_t st);
+hipError_t gm_scale_copy(const void* src, void* dst, const double* s, int64_t N, int nrhs, hipStream_t st);
+hipError_t gm_axpy_combo(void* x, const void* Vb, const void* y, int nvec, int64_t N, int nrhs, int64_t vstride,
+                         hipStream_t st);
+hipError_t gm_sub(const void* a, const void* b, void* out, int64_t n, hipStream_t st);
+hipError_t gm_add(void* x, const void* e, int64_t n, hipStream_t st);
+hipError_t gm_to_f32(const void* a, void* b, int64_t n, hipStream_t st);
+hipError_t gm_to_f64(const void* a, void* b, int64_t n, hipStream_t st);
+
+}  // namespace lsx

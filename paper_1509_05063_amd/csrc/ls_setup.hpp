@@ -1,0 +1,81 @@
+// Host-side set-up of the 2-D operator (internal header).
+//
+// Everything here is double precision and runs once per operator in
+// ls_create; the device side only sees the flat arrays of HostOp.
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ls.h"
+
+namespace lsx {
+
+using cd = std::complex<double>;
+
+struct HostOp {
+  ls_geometry g{};
+  ls_params p{};
+  double kappa = 0;
+
+  // ---- Nystrom nodes in operator order (sorted by cell) -----------------
+  int64_t N = 0;
+  std::vector<double> xy;       // 2N
+  std::vector<int32_t> key;     // 3N: (patch, i1, i2)
+  std::vector<double> cw;       // plain quadrature weight c_j = w |J| omega m
+  std::vector<double> dw;       // interior nodes: m omega (density of the
+                                // interior singular rule); boundary nodes: 0
+
+  // ---- cells (side H = cell_h h, aligned with the interior lattice) ------
+  double H = 0;
+  int S = 0;                    // cell_h^2 interior slots per cell
+  int L = 0;                    // cells per axis
+  int64_t c_lo = 0;             // cell(x) = floor(x / H) - c_lo
+  int ncell = 0;                // occupied cells
+  std::vector<int32_t> cell_xy;     // 2 per occupied cell
+  std::vector<int32_t> cell_map;    // L*L -> occupied index or -1
+  std::vector<int32_t> cell_start;  // first op index of the cell
+  std::vector<int32_t> cell_nint;   // interior nodes (first in the cell)
+  std::vector<int32_t> cell_nb;     // boundary-patch nodes (after them)
+  std::vector<int32_t> cell_boff;   // ordinal of the cell's first boundary node
+  std::vector<int32_t> slot_map;    // ncell*S -> op index or -1
+  int64_t n_band = 0;
+
+  // ---- accelerator --------------------------------------------------------
+  int q = 0, U = 0, F = 0, nfb = 0;
+  std::vector<cd> Psh;          // [U][S]  projection of interior slots
+  std::vector<cd> Pbd;          // [n_band][U] projection column per boundary node
+  std::vector<cd> Ish;          // [S][F]  face values -> interior slots
+  std::vector<cd> Ibd;          // [n_band][F] face values -> boundary node
+  std::vector<cd> Toff;         // [9][F][U] adjacent equivalent-source fields
+  int na = 0, nb = 0, Pa = 0, Pb = 0;
+  std::vector<cd> kern;         // [2 sets][2 kinds][Pa*Pb] kernel / (Pa Pb)
+
+  // ---- near field ----------------------------------------------------------
+  int Wn = 0;                   // window side in lattice nodes (5 cell_h)
+  std::vector<cd> Wsh;          // [S][Wn*Wn]
+  std::vector<int64_t> rowptr;  // CSR over `rows`
+  std::vector<int32_t> rows, cols;
+  std::vector<cd> vals;
+};
+
+// Returns LS_OK or an error code with a message in err.
+ls_status build_host_op(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa,
+                        const ls_params* p, HostOp& op, std::string& err);
+
+// ---- numerical helpers shared by the set-up (ls_math.cpp) ----------------
+cd green2d(double kappa, double r);                    // (i/4) H0(kappa r)
+cd green2d_dipole(double kappa, const double d[2], int axis);   // d/dy_axis G(|x-y|), d = x - y
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
+std::vector<double> newton_cotes(int Q);               // closed rule on 0..Q-1
+double smooth_step(double z);
+double chi(double s, double c0);
+void lagrange(double pos, int64_t base, int P, double* w);
+int64_t centered_base(double pos, int P);
+// Minimum-norm least-squares pseudo-inverse of a complex m x n matrix (row
+// major), singular values below rcond * sigma_max dropped.  Result n x m.
+std::vector<cd> pinv(const std::vector<cd>& A, int m, int n, double rcond);
+int next_smooth(int n);                                 // >= n, of the form 2^a 3^b 5^c
+
+}  // namespace lsx

@@ -10,7 +10,7 @@ Parameter names follow the paper: h interior spacing, (N1, N2) boundary-patch
 intervals, Q Newton–Cotes points, P interpolation nodes per axis, chi_c0 and
 the cut-off radii r_int (physical), r1 / r2 (boundary-patch grid units), the
 polar and varrho rule sizes, cell size H = cell_h * h, q equivalent sources
-per cell face, n_w plane waves per cell.
+per cell face, n_fb Fourier–Bessel modes of the cell Dirichlet fit.
 """
 import copy
 import math
@@ -38,8 +38,8 @@ def _base(kappa, h, a, k, s_in, N1, N2, s_a, s_b):
         "band_rule": {"M": 4, "n_in": 24, "n_out": 32},
         # accelerator (library only; the oracle sums every pair directly)
         "cell_h": 8,
-        "q": 8,
-        "n_w": 28,
+        "q": 12,
+        "n_fb": 20,
         "coll_factor": 4,
     }
 

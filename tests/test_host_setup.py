@@ -1,0 +1,82 @@
+"""The library's host set-up (C++, independent code) against the oracle, on
+the CPU: same nodes, same weights, and near-field rows that complete the
+oracle's rows once the plain far sum of non-adjacent cells is added."""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle.op2d import Setup2D
+from paper_1509_05063_amd.inputs import config, match_keys, n2_function, scaled
+
+binding = pytest.importorskip("paper_1509_05063_amd.binding")
+
+
+@pytest.fixture(scope="module")
+def disc():
+    cfg = config("disc_k2pi")
+    n2 = n2_function(cfg)
+    host = binding.HostOperator(cfg, n2)
+    orc = Setup2D(cfg, n2)
+    return cfg, host, orc
+
+
+def test_library_exports_every_symbol():
+    import re
+    L = binding.lib()
+    names = set()
+    for h in ("include/ls.h", "include/ls_host.h"):
+        txt = open(h).read()
+        names |= set(re.findall(r"\b(ls_[a-z0-9_]+)\s*\(", txt))
+    names -= {"ls_n2_fn"}
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_same_nodes(disc):
+    cfg, host, orc = disc
+    xy, key = host.points()
+    p = match_keys(orc.pts["key"], key)       # oracle order -> library index
+    assert np.abs(xy[p] - orc.pts["x"]).max() < 1e-14
+
+
+def _cells(cfg, key, xy):
+    ch, h = cfg["cell_h"], cfg["h"]
+    H = ch * h
+    c = np.where(key[:, :1] == 0, np.floor_divide(key[:, 1:], ch), np.floor(xy / H).astype(np.int64))
+    return c
+
+
+@pytest.mark.parametrize("which", ["interior", "band", "interior_in_band"])
+def test_near_rows_complete_oracle_rows(disc, which):
+    cfg, host, orc = disc
+    xy, key = host.points()
+    p = match_keys(orc.pts["key"], key)       # p[i_oracle] = library index
+    inv = np.empty_like(p)
+    inv[p] = np.arange(p.size)                # library index -> oracle index
+    cells = _cells(cfg, key, xy)
+    s = np.hypot(xy[:, 0], xy[:, 1])
+    if which == "interior":
+        cand = np.where((key[:, 0] == 0) & (s < 0.5))[0]
+    elif which == "band":
+        cand = np.where(key[:, 0] == 1)[0]
+    else:
+        cand = np.where((key[:, 0] == 0) & (s > 0.82))[0]
+    rng = np.random.default_rng(7)
+    for i in rng.choice(cand, 4, replace=False):
+        cols, vals = host.near_row(i)
+        lib_row = np.zeros(host.N, complex)
+        np.add.at(lib_row, cols, vals)
+        orow = orc.K_row(inv[i])[p]            # oracle row in library order... as function of library col
+        # oracle row indexed by oracle col; reorder to library col
+        orow = np.zeros(host.N, complex)
+        orow[p] = orc.K_row(inv[i])
+        adj = np.all(np.abs(cells - cells[i]) <= 1, axis=1)
+        d = np.hypot(*(xy - xy[i]).T)
+        c = np.zeros(host.N)
+        c[p] = orc.pts["c"]
+        far = np.where(adj | (d == 0), 0.0, 0.25j * special.hankel1(0, cfg["kappa"] * np.where(d > 0, d, 1)) * c)
+        scale = np.abs(orow).max()
+        err = np.abs(lib_row + far - orow).max() / scale
+        assert err < 1e-11, (which, i, err)
