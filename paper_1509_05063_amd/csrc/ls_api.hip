@@ -66,11 +66,16 @@ ls_status upload(ls_op* op, const X* src, size_t count, void** dst) {
   return LS_OK;
 }
 
+// upload a complex double array and/or its single-precision rounding
 ls_status upload_c(ls_op* op, const std::vector<cd>& v, const void** d64, const void** d32) {
-  void* a = nullptr;
-  ls_status s = upload(op, v.data(), v.size(), &a);
-  if (s) return s;
-  *d64 = a;
+  if (d64) {
+    void* a = nullptr;
+    ls_status s = upload(op, v.data(), v.size(), &a);
+    if (s) return s;
+    *d64 = a;
+  }
+  if (!d32) return LS_OK;
+  ls_status s;
   std::vector<Fp32c> f(v.size());
   for (size_t i = 0; i < v.size(); ++i) f[i] = {(float)v[i].real(), (float)v[i].imag()};
   void* b = nullptr;
@@ -295,8 +300,10 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     ls_status s_ = (expr);    \
     if (s_) return cleanup(s_); \
   } while (0)
-  UP(upload_c(op, h.Psh, &a.Psh, &b.Psh));
-  UP(upload_c(op, h.Pbd, &a.Pbd, &b.Pbd));
+  UP(upload_c(op, h.Psh, &a.Psh, nullptr));
+  UP(upload_c(op, h.Pbd, &a.Pbd, nullptr));
+  UP(upload_c(op, h.Psh32, nullptr, &b.Psh));
+  UP(upload_c(op, h.Pbd32, nullptr, &b.Pbd));
   UP(upload_c(op, h.Ish, &a.Ish, &b.Ish));
   UP(upload_c(op, h.Ibd, &a.Ibd, &b.Ibd));
   UP(upload_c(op, h.Toff, &a.Toff, &b.Toff));

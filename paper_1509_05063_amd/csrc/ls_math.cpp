@@ -2,6 +2,7 @@
 // cut-offs, Lagrange weights and a complex pseudo-inverse.
 #include <algorithm>
 #include <cmath>
+#include <numeric>
 
 #include "ls_setup.hpp"
 
@@ -114,62 +115,149 @@ void lagrange(double pos, int64_t base, int P, double* w) {
   }
 }
 
-// One-sided (Hestenes) Jacobi SVD of a complex m x n matrix (m >= n), then
-// V diag(1/sigma) U^H with small singular values dropped.
+// One-sided (Hestenes) Jacobi SVD of a complex m x n matrix (m >= n) in
+// extended precision (the matrices are small and their smallest singular
+// directions matter), after scaling the columns to unit norm; then
+// V diag(1/sigma) U^H with singular values below rcond * sigma_max dropped.
 std::vector<cd> pinv(const std::vector<cd>& Ain, int m, int n, double rcond) {
-  std::vector<cd> A(Ain);          // columns are orthogonalised in place
-  std::vector<cd> V(n * n, 0.0);
-  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  using ld = long double;
+  using cl = std::complex<ld>;
+  std::vector<cl> A((size_t)m * n);
+  std::vector<ld> dsc(n);
+  for (int j = 0; j < n; ++j) {
+    ld nn = 0;
+    for (int r = 0; r < m; ++r) nn += std::norm(cl(Ain[(size_t)r * n + j]));
+    dsc[j] = nn > 0 ? 1.0L / std::sqrt(nn) : 1.0L;
+    for (int r = 0; r < m; ++r) A[(size_t)r * n + j] = cl(Ain[(size_t)r * n + j]) * dsc[j];
+  }
+  std::vector<cl> V((size_t)n * n, cl(0));
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1;
   auto col_dot = [&](int a, int b) {  // a^H b
-    cd s = 0;
-    for (int r = 0; r < m; ++r) s += std::conj(A[r * n + a]) * A[r * n + b];
+    cl s = 0;
+    for (int r = 0; r < m; ++r) s += std::conj(A[(size_t)r * n + a]) * A[(size_t)r * n + b];
     return s;
   };
-  for (int sweep = 0; sweep < 80; ++sweep) {
-    double off = 0;
+  const ld tol = 1e-19L;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    ld off = 0;
     for (int p = 0; p < n - 1; ++p)
       for (int qq = p + 1; qq < n; ++qq) {
-        double al = std::real(col_dot(p, p));
-        double be = std::real(col_dot(qq, qq));
-        cd ga = col_dot(p, qq);
-        double ag = std::abs(ga);
-        if (ag == 0.0 || al == 0.0 || be == 0.0) continue;
+        ld al = std::real(col_dot(p, p));
+        ld be = std::real(col_dot(qq, qq));
+        cl ga = col_dot(p, qq);
+        ld ag = std::abs(ga);
+        if (ag == 0 || al == 0 || be == 0) continue;
         off = std::max(off, ag / std::sqrt(al * be));
-        if (ag <= 1e-16 * std::sqrt(al * be)) continue;
-        cd ph = ga / ag;
-        double zeta = (be - al) / (2.0 * ag);
-        double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-        double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        if (ag <= tol * std::sqrt(al * be)) continue;
+        cl ph = ga / ag;
+        ld zeta = (be - al) / (2 * ag);
+        ld t = (zeta >= 0 ? 1 : -1) / (std::fabs(zeta) + std::sqrt(1 + zeta * zeta));
+        ld c = 1 / std::sqrt(1 + t * t), s = c * t;
         // [a_p, a_q] <- [a_p, a_q] [[c, s e^{i phi}], [-s e^{-i phi}, c]]
         for (int r = 0; r < m; ++r) {
-          cd ap = A[r * n + p], aq = A[r * n + qq];
-          A[r * n + p] = c * ap - s * std::conj(ph) * aq;
-          A[r * n + qq] = s * ph * ap + c * aq;
+          cl ap = A[(size_t)r * n + p], aq = A[(size_t)r * n + qq];
+          A[(size_t)r * n + p] = c * ap - s * std::conj(ph) * aq;
+          A[(size_t)r * n + qq] = s * ph * ap + c * aq;
         }
         for (int r = 0; r < n; ++r) {
-          cd vp = V[r * n + p], vq = V[r * n + qq];
-          V[r * n + p] = c * vp - s * std::conj(ph) * vq;
-          V[r * n + qq] = s * ph * vp + c * vq;
+          cl vp = V[(size_t)r * n + p], vq = V[(size_t)r * n + qq];
+          V[(size_t)r * n + p] = c * vp - s * std::conj(ph) * vq;
+          V[(size_t)r * n + qq] = s * ph * vp + c * vq;
         }
       }
-    if (off < 1e-15) break;
+    if (off < tol) break;
   }
-  std::vector<double> sig(n);
-  double smax = 0;
+  std::vector<ld> sig(n);
+  ld smax = 0;
   for (int i = 0; i < n; ++i) {
     sig[i] = std::sqrt(std::real(col_dot(i, i)));
     smax = std::max(smax, sig[i]);
   }
-  std::vector<cd> out(n * m, 0.0);
+  std::vector<cl> acc((size_t)n * m, cl(0));
   for (int i = 0; i < n; ++i) {
     if (sig[i] <= rcond * smax) continue;
-    double inv2 = 1.0 / (sig[i] * sig[i]);   // u_i = a_i / sigma_i
+    ld inv2 = 1 / (sig[i] * sig[i]);   // u_i = a_i / sigma_i
     for (int j = 0; j < n; ++j) {
-      cd vj = V[j * n + i] * inv2;
-      for (int k = 0; k < m; ++k) out[j * m + k] += vj * std::conj(A[k * n + i]);
+      cl vj = V[(size_t)j * n + i] * inv2;
+      for (int k = 0; k < m; ++k) acc[(size_t)j * m + k] += vj * std::conj(A[(size_t)k * n + i]);
     }
   }
+  std::vector<cd> out((size_t)n * m);
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < m; ++k) out[(size_t)j * m + k] = cd(acc[(size_t)j * m + k] * dsc[j]);
   return out;
+}
+
+// Householder QR with column pivoting (numerical rank at rcond |R_00|).
+QRCP qrcp(const std::vector<cd>& A, int m, int n, double rcond) {
+  QRCP f;
+  f.m = m;
+  f.n = n;
+  f.QR = A;
+  f.perm.resize(n);
+  std::iota(f.perm.begin(), f.perm.end(), 0);
+  f.v.assign((size_t)n * m, 0.0);
+  f.vn.assign(n, 0.0);
+  f.r = 0;
+  double r00 = 0;
+  for (int k = 0; k < n && k < m; ++k) {
+    // pivot: remaining column of largest norm
+    int best = k;
+    double bn = -1;
+    for (int j = k; j < n; ++j) {
+      double nn = 0;
+      for (int i = k; i < m; ++i) nn += std::norm(f.QR[(size_t)i * n + j]);
+      if (nn > bn) { bn = nn; best = j; }
+    }
+    if (best != k) {
+      for (int i = 0; i < m; ++i) std::swap(f.QR[(size_t)i * n + k], f.QR[(size_t)i * n + best]);
+      std::swap(f.perm[k], f.perm[best]);
+    }
+    double xn = std::sqrt(bn);
+    if (k == 0) r00 = xn;
+    if (xn <= rcond * r00 || xn == 0.0) break;
+    cd x0 = f.QR[(size_t)k * n + k];
+    cd alpha = -(std::abs(x0) > 0 ? x0 / std::abs(x0) : cd(1.0)) * xn;
+    cd* v = &f.v[(size_t)k * m];
+    for (int i = k; i < m; ++i) v[i] = f.QR[(size_t)i * n + k];
+    v[k] -= alpha;
+    double vn = 0;
+    for (int i = k; i < m; ++i) vn += std::norm(v[i]);
+    f.vn[k] = vn;
+    // apply H = I - 2 v v^H / (v^H v) to the remaining columns
+    for (int j = k + 1; j < n; ++j) {
+      cd dot = 0;
+      for (int i = k; i < m; ++i) dot += std::conj(v[i]) * f.QR[(size_t)i * n + j];
+      cd fct = 2.0 * dot / vn;
+      for (int i = k; i < m; ++i) f.QR[(size_t)i * n + j] -= fct * v[i];
+    }
+    f.QR[(size_t)k * n + k] = alpha;
+    for (int i = k + 1; i < m; ++i) f.QR[(size_t)i * n + k] = 0.0;
+    f.r = k + 1;
+  }
+  return f;
+}
+
+// Basic least-squares solution of the rank-r truncated problem:
+// x = P [R11^{-1} (Q^H b)_{1..r}; 0].
+void qrcp_solve(const QRCP& f, const cd* b, cd* x) {
+  const int m = f.m, n = f.n, r = f.r;
+  std::vector<cd> y(b, b + m);
+  for (int k = 0; k < r; ++k) {
+    const cd* v = &f.v[(size_t)k * m];
+    cd dot = 0;
+    for (int i = k; i < m; ++i) dot += std::conj(v[i]) * y[i];
+    cd fct = 2.0 * dot / f.vn[k];
+    for (int i = k; i < m; ++i) y[i] -= fct * v[i];
+  }
+  std::vector<cd> z(r);
+  for (int i = r - 1; i >= 0; --i) {
+    cd s = y[i];
+    for (int j = i + 1; j < r; ++j) s -= f.QR[(size_t)i * n + j] * z[j];
+    z[i] = s / f.QR[(size_t)i * n + i];
+  }
+  for (int j = 0; j < n; ++j) x[j] = 0.0;
+  for (int i = 0; i < r; ++i) x[f.perm[i]] = z[i];
 }
 
 int next_smooth(int n) {

@@ -609,7 +609,10 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     else if (side == 2) { c[0] = 2 * H - u; c[1] = 2 * H; }
     else { c[0] = -H; c[1] = 2 * H - u; }
   }
-  std::vector<cd> Apinv[2];
+  // least squares per set: QR with column pivoting, numerical rank at
+  // 1e-14 (double-precision apply) and 1e-8 (single precision: smaller
+  // strengths, so rounding in the projection is not amplified)
+  QRCP fac[2][2];
   for (int s = 0; s < 2; ++s) {
     std::vector<cd> A((size_t)ncol * U1);
     for (int k = 0; k < ncol; ++k)
@@ -622,20 +625,15 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
           A[(size_t)k * U1 + col] = green2d(kappa, std::hypot(d[0], d[1]));
           A[(size_t)k * U1 + 2 * q + col] = green2d_dipole(kappa, d, s);
         }
-    Apinv[s] = pinv(A, ncol, U1, 1e-14);
+    fac[0][s] = qrcp(A, ncol, U1, 1e-14);
+    fac[1][s] = qrcp(A, ncol, U1, 1e-8);
   }
   // projection of a source at rel (relative to the cell origin) -> U values
-  auto project_col = [&](const double* rel, cd* out) {
+  auto project_col = [&](const double* rel, cd* out, int which) {
     std::vector<cd> gcol(ncol);
     for (int k = 0; k < ncol; ++k)
       gcol[k] = green2d(kappa, std::hypot(coll[2 * k] - rel[0], coll[2 * k + 1] - rel[1]));
-    for (int s = 0; s < 2; ++s)
-      for (int t = 0; t < U1; ++t) {
-        cd acc = 0;
-        const cd* row = &Apinv[s][(size_t)t * ncol];
-        for (int k = 0; k < ncol; ++k) acc += row[k] * gcol[k];
-        out[s * U1 + t] = acc;
-      }
+    for (int s = 0; s < 2; ++s) qrcp_solve(fac[which][s], gcol.data(), out + s * U1);
   };
   // Dirichlet fit: Fourier–Bessel modes |n| <= n_fb about the cell centre
   const int nf = 2 * p.n_fb + 1;
@@ -669,15 +667,21 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     }
   };
   op.Psh.assign((size_t)U * S, 0.0);
+  op.Psh32.assign((size_t)U * S, 0.0);
   op.Ish.assign((size_t)S * F, 0.0);
   for (int a = 0; a < S; ++a) {
     double rel[2] = {(a % ch) * h, (a / ch) * h};
-    std::vector<cd> col(U);
-    project_col(rel, col.data());
-    for (int t = 0; t < U; ++t) op.Psh[(size_t)t * S + a] = col[t];
+    std::vector<cd> col(U), col32(U);
+    project_col(rel, col.data(), 0);
+    project_col(rel, col32.data(), 1);
+    for (int t = 0; t < U; ++t) {
+      op.Psh[(size_t)t * S + a] = col[t];
+      op.Psh32[(size_t)t * S + a] = col32[t];
+    }
     interp_row(rel, &op.Ish[(size_t)a * F]);
   }
   op.Pbd.assign((size_t)op.n_band * U, 0.0);
+  op.Pbd32.assign((size_t)op.n_band * U, 0.0);
   op.Ibd.assign((size_t)op.n_band * F, 0.0);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int c = 0; c < ncell; ++c) {
@@ -686,7 +690,8 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
       int64_t k = op.cell_start[c] + op.cell_nint[c] + t;
       double rel[2] = {op.xy[2 * k] - ox, op.xy[2 * k + 1] - oy};
       int64_t b = op.cell_boff[c] + t;
-      project_col(rel, &op.Pbd[(size_t)b * U]);
+      project_col(rel, &op.Pbd[(size_t)b * U], 0);
+      project_col(rel, &op.Pbd32[(size_t)b * U], 1);
       interp_row(rel, &op.Ibd[(size_t)b * F]);
     }
   }

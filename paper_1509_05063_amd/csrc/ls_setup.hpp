@@ -46,6 +46,8 @@ struct HostOp {
   int q = 0, U = 0, F = 0, nfb = 0;
   std::vector<cd> Psh;          // [U][S]  projection of interior slots
   std::vector<cd> Pbd;          // [n_band][U] projection column per boundary node
+  std::vector<cd> Psh32, Pbd32; // the same from a more strongly truncated fit,
+                                // for the single-precision apply
   std::vector<cd> Ish;          // [S][F]  face values -> interior slots
   std::vector<cd> Ibd;          // [n_band][F] face values -> boundary node
   std::vector<cd> Toff;         // [9][F][U] adjacent equivalent-source fields
@@ -77,5 +79,16 @@ int64_t centered_base(double pos, int P);
 // major), singular values below rcond * sigma_max dropped.  Result n x m.
 std::vector<cd> pinv(const std::vector<cd>& A, int m, int n, double rcond);
 int next_smooth(int n);                                 // >= n, of the form 2^a 3^b 5^c
+// Householder QR with column pivoting of a complex m x n matrix (row major),
+// truncated at the first |R_kk| <= rcond |R_00|; solve gives the basic
+// least-squares solution of the truncated problem (backward stable).
+struct QRCP {
+  int m = 0, n = 0, r = 0;
+  std::vector<cd> QR, v;
+  std::vector<double> vn;
+  std::vector<int> perm;
+};
+QRCP qrcp(const std::vector<cd>& A, int m, int n, double rcond);
+void qrcp_solve(const QRCP& f, const cd* b, cd* x);
 
 }  // namespace lsx

@@ -1,0 +1,108 @@
+"""GPU parity through the C ABI: the device apply and solve against the CPU
+oracle on the same seeded inputs (disc workload, every row)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1509_05063_amd.inputs import config, match_keys, n2_function, plane_wave, random_density
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def disc():
+    import torch
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd import binding
+    assert torch.cuda.is_available()
+    cfg = config("disc_k2pi")
+    n2 = n2_function(cfg)
+    op = binding.Operator(cfg, n2)
+    orc = Setup2D(cfg, n2)
+    xy, key = op.points()
+    p = match_keys(orc.pts["key"], key)       # oracle index -> library index
+    A = orc.dense_A()
+    return cfg, op, orc, A, p, xy, key
+
+
+def _to_lib(x_or, p, N):
+    out = np.empty(N, complex)
+    out[p] = x_or
+    return out
+
+
+def test_apply_fp64_matches_oracle_every_row(disc):
+    import torch
+    cfg, op, orc, A, p, xy, key = disc
+    for name, u_or in [("random", random_density(orc.pts["key"])),
+                       ("plane", plane_wave(cfg, orc.pts["x"], 0.0))]:
+        v_or = A @ u_or
+        u = torch.tensor(_to_lib(u_or, p, op.N), dtype=torch.complex128, device="cuda")
+        v = torch.empty_like(u)
+        op.apply(u, v)
+        torch.cuda.synchronize()
+        v_lib = v.cpu().numpy()[p]
+        err = np.linalg.norm(v_lib - v_or) / np.linalg.norm(v_or)
+        emax = np.abs(v_lib - v_or).max() / np.abs(v_or).max()
+        print(f"apply fp64 {name}: rel2 {err:.3e} relmax {emax:.3e}", flush=True)
+        assert err < 1e-8 and emax < 1e-8
+
+
+def test_apply_fp32_close_to_oracle(disc):
+    import torch
+    cfg, op, orc, A, p, xy, key = disc
+    u_or = random_density(orc.pts["key"])
+    v_or = A @ u_or
+    u = torch.tensor(_to_lib(u_or, p, op.N), dtype=torch.complex64, device="cuda")
+    v = torch.empty_like(u)
+    op.apply(u, v)
+    torch.cuda.synchronize()
+    v_lib = v.cpu().numpy().astype(complex)[p]
+    err = np.linalg.norm(v_lib - v_or) / np.linalg.norm(v_or)
+    print(f"apply fp32: rel2 {err:.3e}", flush=True)
+    assert err < 1e-4
+
+
+def test_multi_rhs_equals_single(disc):
+    import torch
+    cfg, op, orc, A, p, xy, key = disc
+    U = torch.stack([torch.tensor(_to_lib(random_density(orc.pts["key"], seed=s), p, op.N),
+                                  dtype=torch.complex128) for s in range(3)]).cuda()
+    V = torch.empty_like(U)
+    op.apply(U, V)
+    for k in range(3):
+        v1 = torch.empty_like(U[k])
+        op.apply(U[k].contiguous(), v1)
+        torch.cuda.synchronize()
+        assert torch.equal(v1, V[k])
+
+
+def test_apply_is_deterministic(disc):
+    import torch
+    cfg, op, orc, A, p, xy, key = disc
+    u = torch.tensor(_to_lib(random_density(orc.pts["key"]), p, op.N), dtype=torch.complex128, device="cuda")
+    v1, v2 = torch.empty_like(u), torch.empty_like(u)
+    op.apply(u, v1)
+    op.apply(u, v2)
+    torch.cuda.synchronize()
+    assert torch.equal(v1, v2)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_solve_matches_oracle_lu(disc, mode):
+    import torch
+    from oracle.mie import mie2d_total
+    cfg, op, orc, A, p, xy, key = disc
+    f_or = plane_wave(cfg, orc.pts["x"], 0.0)
+    u_or = np.linalg.solve(A, f_or)
+    f = torch.tensor(_to_lib(f_or, p, op.N), dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(f)
+    st = op.solve(f, x, tol=1e-10, restart=100, max_iter=500, mode=mode, inner_tol=1e-5)
+    u = x.cpu().numpy()[p]
+    err = np.linalg.norm(u - u_or) / np.linalg.norm(u_or)
+    mie = mie2d_total(cfg["kappa"], 1.5, 1.0, orc.pts["x"] * (1 - 1e-15))
+    emie = np.linalg.norm(u - mie) / np.linalg.norm(mie)
+    print(f"solve mode {mode}: {st} vs LU {err:.3e} vs Mie {emie:.3e}", flush=True)
+    assert err < 1e-8
+    assert emie < 5e-3
