@@ -1,0 +1,224 @@
+"""Benchmark of the FFT-accelerated Lippmann–Schwinger solve on one MI355X.
+
+A step is one full pass of the hot path on the workload: a GMRES solve of
+(I + kappa^2 K_h) u = u^i whose every iteration runs the whole operator
+apply (projection, FFT convolution, adjacency subtraction and cell
+interpolation, near-field correction, combine) in single precision inside
+double-precision iterative refinement (FP64 residual and Arnoldi).
+
+Prints one JSON line (rank 0):  metric / value = solves per second at
+<= 1e-6 relative error against the double-precision reference solve, plus
+matvec rates, solve latency percentiles, the roofline of the dominant kernel
+(timed with HIP events on the apply's stream) and the CPU oracle timed on a
+bounded sample of rows.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes(st, N, n_int, s, s_w):
+    """Algorithmic bytes per apply of each stage for one right-hand side
+    (what the method has to move; s bytes per complex value of the data,
+    s_w per stored complex weight)."""
+    Pa, Pb, ncell, U, F, S, Wn = st["Pa"], st["Pb"], st["ncell"], st["U"], st["F"], st["S"], st["Wn"]
+    nb = st["n_band"]
+    na = st["L"] + 1
+    plane = Pa * Pb
+    r = s // 2            # real bytes
+    return {
+        "project": N * (s + r) + nb * U * s_w + U * S * s_w + ncell * U * s,
+        "fill": ncell * U * s + 4 * plane * s,
+        "fft_fwd": 4 * (na * Pb + plane) * 2 * s,
+        "spectral": 2 * (2 + 2 + 1) * plane * s,
+        "fft_inv": 2 * (plane + na * Pb) * 2 * s,
+        "interp": ncell * (F + 9 * U) * s + nb * F * s_w + 2 * N * s,
+        "near_shared": S * Wn * Wn * s_w + n_int * (s + r) + 2 * n_int * s,
+        "near_csr": st["csr_nnz"] * (s_w + 4) + st["csr_rows"] * (8 + 4 + 2 * s) + N * s,
+    }
+
+
+def cpu_oracle_rate(cfg, n2, budget_s=20.0):
+    """Oracle rows per second on a bounded sample of targets (single thread)."""
+    from oracle.op2d import Setup2D
+    t0 = time.time()
+    orc = Setup2D(cfg, n2)
+    log(f"oracle discretisation {time.time() - t0:.1f}s, N={orc.N}")
+    rng = np.random.default_rng(1509)
+    rows = rng.choice(orc.N, 4096, replace=False)
+    u = np.ones(orc.N, complex)
+    done = 0
+    t0 = time.time()
+    for i in rows:
+        orc.K_row(int(i)) @ u
+        done += 1
+        if time.time() - t0 > budget_s:
+            break
+    dt = time.time() - t0
+    return done / dt, done, orc.N
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="star_k32pi")
+    ap.add_argument("--matvec-reps", type=int, default=20)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import config, n2_function, plane_wave
+
+    cfg = config(args.config)
+    n2 = n2_function(cfg)
+    log(f"create {args.config}")
+    t0 = time.time()
+    op = binding.Operator(cfg, n2)
+    setup_s = time.time() - t0
+    st = op.stats()
+    log(f"setup {setup_s:.1f}s stats {st}")
+    xy, key = op.points()
+    N = op.N
+    n_int = int((key[:, 0] == 0).sum())
+    f = torch.tensor(plane_wave(cfg, xy, cfg["incidence"][0]), dtype=torch.complex128, device="cuda")
+    x_ref = torch.empty_like(f)
+    g = cfg["gmres"]
+    t0 = time.time()
+    ref = op.solve(f, x_ref, tol=1e-10, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP64)
+    log(f"FP64 reference solve {time.time() - t0:.2f}s {ref}")
+
+    def step(x):
+        return op.solve(f, x, tol=1e-7, restart=g["restart"], max_iter=3000,
+                        mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-4, max_outer=30)
+
+    x = torch.empty_like(f)
+    for w in range(args.warmup):
+        info = step(x)
+        log(f"warmup {w}: {info}")
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        t1 = time.perf_counter()
+        info = step(x)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+        log(f"step {k}: {lat[-1] * 1e3:.1f} ms {info}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    err = (torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref)).item()
+    log(f"error vs FP64 reference solve {err:.3e}")
+
+    # plain FP64 GMRES form for comparison (same tolerance on the error)
+    xf = torch.empty_like(f)
+    t1 = time.perf_counter()
+    info64 = op.solve(f, xf, tol=1e-7, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP64)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t1
+    err64 = (torch.linalg.norm(xf - x_ref) / torch.linalg.norm(x_ref)).item()
+    log(f"FP64 plain solve {t64 * 1e3:.1f} ms err {err64:.3e} {info64}")
+
+    # matvec rates
+    rates = {}
+    for name, dt in [("fp64", torch.complex128), ("fp32", torch.complex64)]:
+        u = f.to(dt)
+        v = torch.empty_like(u)
+        op.apply(u, v)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.matvec_reps):
+            op.apply(u, v)
+        torch.cuda.synchronize()
+        rates[name] = args.matvec_reps / (time.perf_counter() - t1)
+        log(f"matvecs/s {name}: {rates[name]:.1f}")
+
+    # per-stage times (HIP events on the apply's stream), single precision
+    # (the form the timed solves spend their applies in) and double
+    prof = {}
+    for name, dt, s, s_w in [("fp32", torch.complex64, 8, 8), ("fp64", torch.complex128, 16, 16)]:
+        u = f.to(dt)
+        v = torch.empty_like(u)
+        acc = None
+        reps = 10
+        for _ in range(reps):
+            p = op.apply_profile(u, v)
+            acc = p if acc is None else {k: acc[k] + p[k] for k in p}
+        prof[name] = {k: acc[k] / reps for k in acc}
+        log(f"stage ms {name}: " + " ".join(f"{k}={v:.3f}" for k, v in prof[name].items()))
+    p32 = prof["fp32"]
+    dom = max(p32, key=p32.get)
+    byts = stage_bytes(st, N, n_int, 8, 8)
+    achieved = byts[dom] / (p32[dom] * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "algorithmic_bytes": int(byts[dom]), "avg_ms": round(p32[dom], 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rows_s, nrows, N_or = cpu_oracle_rate(cfg, n2, args.cpu_budget)
+        mv = rows_s / N_or
+        applies_per_solve = info["iterations"] + info["outer"] + 1
+        cpu = {"value": mv / max(applies_per_solve, 1), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{nrows} direct-sum rows of N={N_or} ({rows_s:.2f} rows/s = {mv:.3e} matvecs/s), "
+                         f"scaled by {applies_per_solve} applies per solve"}
+        log(f"cpu baseline {cpu}")
+
+    out = {
+        "metric": "LS solves/s at 1e-6 err vs FP64 reference (FP32 GMRES + FP64 refinement)",
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 bulk + c128 residual/Arnoldi",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: star R=1+0.3cos5t, kappa=32pi, n^2=1+0.8exp(-4|x|^2), "
+                               f"plane wave at 30deg, N={N}", "N": N, "nrhs": 1},
+        "err_vs_fp64_ref": err,
+        "solve_p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
+        "solve_p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),
+        "iterations": info["iterations"],
+        "outer": info["outer"],
+        "fp64_plain_solves_per_s": 1.0 / t64,
+        "fp64_plain_err": err64,
+        "fp64_plain_iterations": info64["iterations"],
+        "matvecs_per_s_fp64": rates["fp64"],
+        "matvecs_per_s_fp32": rates["fp32"],
+        "stage_ms": prof,
+        "setup_s": setup_s,
+        "resident_gb": op.resident_bytes() / 1e9,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

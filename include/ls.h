@@ -129,6 +129,12 @@ ls_status ls_points(const ls_op* op, double* xy, int32_t* key);
 /* Device bytes held by the op (operator data, both precisions). */
 size_t ls_resident_bytes(const ls_op* op);
 
+/* Sizes of the discretisation (first nout of): N, boundary-patch nodes,
+ * occupied cells, cells per axis, near-field CSR rows, CSR entries, padded
+ * face-lattice dims Pa, Pb, equivalent-source unknowns per cell U, face
+ * values per cell F, interior slots per cell S, near-field window side. */
+ls_status ls_op_stats(const ls_op* op, int64_t* out, int nout);
+
 /* Workspace bytes ls_apply needs for nrhs vectors in precision prec. */
 ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* bytes);
 
@@ -140,6 +146,16 @@ ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* byt
  * double-precision set-up).  Errors: LS_EINVAL, LS_EDEVICE. */
 ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec,
                    void* ws, size_t ws_bytes, void* stream);
+
+/* One ls_apply with HIP events recorded on `stream` between its stages;
+ * waits for completion and writes the stage durations (milliseconds) to
+ * stage_ms[0..min(nstage,8)-1]: 0 projection (Sec. 3.2, equiv-conv-loc),
+ * 1 face-lattice fill, 2 forward FFTs, 3 spectral product, 4 inverse FFTs,
+ * 5 adjacency subtraction + cell Dirichlet fit (eq:-PWE) + combine,
+ * 6 near field between interior nodes, 7 near field rows of the boundary
+ * patch (Sec. 3.1).  Same arguments and errors as ls_apply. */
+ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, void* ws,
+                           size_t ws_bytes, void* stream, double* stage_ms, int nstage);
 
 typedef enum { LS_SOLVE_FP64 = 0, LS_SOLVE_FP32_REFINE = 1 } ls_solve_mode;
 

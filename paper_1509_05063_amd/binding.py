@@ -62,9 +62,12 @@ def lib():
             "ls_num_points": (C.c_int, [C.c_void_p, P(C.c_int64)]),
             "ls_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
             "ls_resident_bytes": (C.c_size_t, [C.c_void_p]),
+            "ls_op_stats": (C.c_int, [C.c_void_p, P(C.c_int64), C.c_int]),
             "ls_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, P(C.c_size_t)]),
             "ls_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
                                    C.c_size_t, C.c_void_p]),
+            "ls_apply_profile": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                           C.c_size_t, C.c_void_p, P(C.c_double), C.c_int]),
             "ls_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, P(SolveOpts), P(SolveStats),
                                    C.c_void_p]),
             "ls_status_str": (C.c_char_p, [C.c_int]),
@@ -206,6 +209,12 @@ class Operator:
     def resident_bytes(self):
         return lib().ls_resident_bytes(self._op)
 
+    def stats(self):
+        out = (C.c_int64 * 12)()
+        _check(lib().ls_op_stats(self._op, out, 12), "ls_op_stats")
+        names = ["N", "n_band", "ncell", "L", "csr_rows", "csr_nnz", "Pa", "Pb", "U", "F", "S", "Wn"]
+        return dict(zip(names, list(out)))
+
     def workspace_bytes(self, nrhs, prec):
         b = C.c_size_t()
         _check(lib().ls_workspace_size(self._op, nrhs, prec, C.byref(b)), "ls_workspace_size")
@@ -231,6 +240,19 @@ class Operator:
         _check(lib().ls_apply(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(), _stream(stream)),
                "ls_apply")
         return v
+
+    STAGES = ["project", "fill", "fft_fwd", "spectral", "fft_inv", "interp", "near_shared", "near_csr"]
+
+    def apply_profile(self, u, v, stream=None):
+        """One apply with per-stage HIP event timing; returns {stage: ms}."""
+        import torch
+        prec = LS_C128 if u.dtype == torch.complex128 else LS_C64
+        nrhs = 1 if u.dim() == 1 else u.shape[0]
+        ws = self.workspace(nrhs, prec)
+        out = (C.c_double * 8)()
+        _check(lib().ls_apply_profile(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(),
+                                      _stream(stream), out, 8), "ls_apply_profile")
+        return dict(zip(self.STAGES, list(out)))
 
     def solve(self, u_inc, u_tot, tol=1e-10, max_iter=2000, restart=100, mode=LS_SOLVE_FP64, inner_tol=1e-5,
               max_outer=20, use_x0=False, stream=None, raise_on_noconv=True):

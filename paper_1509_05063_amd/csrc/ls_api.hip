@@ -45,6 +45,7 @@ struct ls_op {
   lsx::DevView<double> d64;
   lsx::DevView<float> d32;
   double kappa = 0;
+  int64_t stats[12] = {0};
   // solver scratch
   void* gm = nullptr;
   size_t gm_bytes = 0;
@@ -115,7 +116,8 @@ void release(ls_op* op) {
 size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
   size_t c = prec == LS_C128 ? 16 : 8;
   const auto& d = op->d64;
-  return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb) + 256;
+  size_t Gw = (size_t)(d.L + 4) * d.ch;
+  return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb + (size_t)nrhs * Gw * Gw) + 256;
 }
 
 }  // namespace
@@ -242,6 +244,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   op->kappa = kappa;
   op->xy = h.xy;
   op->key = h.key;
+  (void)ls_host_stats(hb, op->stats, 12);
 
   auto cleanup = [&](ls_status st) {
     release(op);
@@ -393,6 +396,12 @@ ls_status ls_points(const ls_op* op, double* xy, int32_t* key) {
 
 size_t ls_resident_bytes(const ls_op* op) { return op ? op->resident : 0; }
 
+ls_status ls_op_stats(const ls_op* op, int64_t* out, int nout) {
+  if (!op || !out) return fail(LS_EINVAL, "null argument");
+  for (int i = 0; i < nout && i < 12; ++i) out[i] = op->stats[i];
+  return LS_OK;
+}
+
 ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* bytes) {
   if (!op || !bytes || nrhs < 1 || (prec != LS_C128 && prec != LS_C64)) return fail(LS_EINVAL, "bad argument");
   *bytes = ws_bytes(op, nrhs, prec);
@@ -413,6 +422,28 @@ ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, vo
                                  : lsx::launch_apply<float>(op->d32, u, v, nrhs, ws, st);
   if (e != hipSuccess) return fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
   return LS_OK;
+}
+
+ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, void* ws, size_t wsb,
+                           void* stream, double* stage_ms, int nstage) {
+  if (!op || !u || !v || !ws || nrhs < 1 || !stage_ms || nstage < 1) return fail(LS_EINVAL, "bad argument");
+  if (prec != LS_C128 && prec != LS_C64) return fail(LS_EINVAL, "unknown precision");
+  if (wsb < ws_bytes(op, nrhs, prec)) return fail(LS_EINVAL, "workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[9];
+  for (int i = 0; i < 9; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  hipError_t e = prec == LS_C128 ? lsx::launch_apply<double>(op->d64, u, v, nrhs, ws, st, ev)
+                                 : lsx::launch_apply<float>(op->d32, u, v, nrhs, ws, st, ev);
+  ls_status out = LS_OK;
+  if (e != hipSuccess) out = fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
+  if (out == LS_OK && hipEventSynchronize(ev[8]) != hipSuccess) out = fail(LS_EDEVICE, "apply failed");
+  for (int i = 0; i < 8 && i < nstage && out == LS_OK; ++i) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+    stage_ms[i] = ms;
+  }
+  for (int i = 0; i < 9; ++i) (void)hipEventDestroy(ev[i]);
+  return out;
 }
 
 // ---------------------------------------------------------------------------

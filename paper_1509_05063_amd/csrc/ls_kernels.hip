@@ -436,6 +436,128 @@ __global__ void __launch_bounds__(256) k_near_shared(const typename C2<T>::t* __
   }
 }
 
+// a4, interior x interior on matrix cores.  The interior density
+// psi = m omega u is first laid out on the lattice (two empty cells of
+// padding on each side), so that the 5x5-cell window of a cell is a plain
+// 40 x 40 block of rows.  out[slot][cell] = sum_b W[slot][b] psi[b][cell]
+// is then a dense contraction: a workgroup takes 16*NT cells, wave w the
+// slots 16w..16w+15, K runs over the window row by row (W row and psi rows
+// staged in LDS), complex products as four real MFMA 16x16x4 updates.
+template <typename T>
+__global__ void k_psi_grid(const typename C2<T>::t* __restrict__ u, typename C2<T>::t* __restrict__ grid,
+                           const T* __restrict__ dw, const int32_t* __restrict__ cell_map,
+                           const int32_t* __restrict__ slot_map, int L, int ch, int S, int Gw, int64_t N) {
+  using V = typename C2<T>::t;
+  const int64_t gsz = (int64_t)Gw * Gw;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= gsz) return;
+  const int r = blockIdx.y;
+  const int gy = (int)(idx / Gw), gx = (int)(idx % Gw);
+  const int cx = gx / ch - 2, cy = gy / ch - 2;
+  V val = czero<V>();
+  if (cx >= 0 && cy >= 0 && cx < L && cy < L) {
+    int c = cell_map[cy * L + cx];
+    if (c >= 0) {
+      int j = slot_map[(int64_t)c * S + (gy % ch) * ch + (gx % ch)];
+      if (j >= 0) val = cscale(u[(int64_t)r * N + j], dw[j]);
+    }
+  }
+  grid[(int64_t)r * gsz + idx] = val;
+}
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element held by (lane, r): row lane/16 + 4r, column lane%16
+  static __device__ __forceinline__ int row(int lane, int r) { return lane / 16 + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element held by (lane, r): row 4(lane/16) + r, column lane%16
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::t* __restrict__ grid,
+                                                          typename C2<T>::t* __restrict__ v,
+                                                          const typename C2<T>::t* __restrict__ W,
+                                                          const int32_t* __restrict__ icells,
+                                                          const int32_t* __restrict__ cell_xy,
+                                                          const int32_t* __restrict__ slot_map, int Gw,
+                                                          int nicell, int64_t N, T k2) {
+  using V = typename C2<T>::t;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int CH = 8, S = 64, WN = 40, KP = WN + 1, NC = 16 * NT;
+  __shared__ V Xs[NC * KP];
+  __shared__ V Ws[S * KP];
+  __shared__ int cx0[NC], cy0[NC];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int r = blockIdx.y;
+  const int cb = blockIdx.x * NC;
+  const V* g = grid + (int64_t)r * Gw * Gw;
+  for (int c = tid; c < NC; c += blockDim.x) {
+    int cid = cb + c < nicell ? icells[cb + c] : -1;
+    cx0[c] = cid >= 0 ? cell_xy[2 * cid] * CH : -1;
+    cy0[c] = cid >= 0 ? cell_xy[2 * cid + 1] * CH : -1;
+  }
+  v4 acc_re[NT], acc_im[NT];
+  for (int t = 0; t < NT; ++t) {
+    acc_re[t] = v4{0, 0, 0, 0};
+    acc_im[t] = v4{0, 0, 0, 0};
+  }
+  for (int wy = 0; wy < WN; ++wy) {
+    __syncthreads();
+    for (int i = tid; i < NC * WN; i += blockDim.x) {
+      int c = i / WN, wx = i % WN;
+      V val = czero<V>();
+      if (cx0[c] >= 0) val = g[(int64_t)(cy0[c] + wy) * Gw + cx0[c] + wx];
+      Xs[c * KP + wx] = val;
+    }
+    for (int i = tid; i < S * WN; i += blockDim.x) {
+      int a = i / WN, wx = i % WN;
+      Ws[a * KP + wx] = W[(int64_t)a * WN * WN + wy * WN + wx];
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int kk = 0; kk < WN / 4; ++kk) {
+      const int k = 4 * kk + (lane >> 4);
+      const V wa = Ws[(16 * wave + (lane & 15)) * KP + k];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const V xb = Xs[(16 * t + (lane & 15)) * KP + k];
+        acc_re[t] = M::op(wa.x, xb.x, acc_re[t]);
+        acc_re[t] = M::op(-wa.y, xb.y, acc_re[t]);
+        acc_im[t] = M::op(wa.x, xb.y, acc_im[t]);
+        acc_im[t] = M::op(wa.y, xb.x, acc_im[t]);
+      }
+    }
+  }
+  V* vr = v + (int64_t)r * N;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = cb + 16 * t + (lane & 15);
+    if (c >= nicell) continue;
+    const int cid = icells[c];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = 16 * wave + M::row(lane, q);
+      const int j = slot_map[(int64_t)cid * S + a];
+      if (j < 0) continue;
+      V o = vr[j];
+      o.x += k2 * acc_re[t][q];
+      o.y += k2 * acc_im[t][q];
+      vr[j] = o;
+    }
+  }
+}
+
 // a4, rows touching the boundary patch: one wavefront per row
 template <typename T, typename VT>
 __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __restrict__ u,
@@ -586,7 +708,11 @@ __global__ void k_to_f64(const float2* __restrict__ a, double2* __restrict__ b, 
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs, void* ws_, hipStream_t st) {
+hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs, void* ws_, hipStream_t st,
+                        hipEvent_t* ev) {
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], st);
+  };
   using V = typename C2<T>::t;
   const V* u = static_cast<const V*>(u_);
   V* v = static_cast<V*>(v_);
@@ -594,6 +720,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   V* lat = sigma + (size_t)nrhs * d.ncell * d.U;
   const int64_t plane = (int64_t)d.Pa * d.Pb;
   const T k2 = (T)(d.kappa * d.kappa);
+  mark(0);
   // a0 + a1
   {
     size_t sh = (size_t)(d.S + d.max_nb) * sizeof(V);
@@ -601,9 +728,11 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                        (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
                        d.S, d.U, d.N, d.ncell);
   }
+  mark(1);
   // lattice fill
   hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, sigma, lat,
                      d.cell_map, d.L, d.q, d.U, d.ncell, d.na, d.nb, d.Pa, d.Pb);
+  mark(2);
   // a2: forward transforms of all 4 arrays per rhs
   const int nbatch = nrhs * 4;
   {
@@ -616,8 +745,10 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, lat,
                        (const V*)d.twa, d.pa, d.Pb, TC, plane);
   }
+  mark(3);
   hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, lat,
                      (const V*)d.khat, plane);
+  mark(4);
   {
     // inverse transforms of kind 0 of each set: batch stride 2 planes
     int TC = d.tc;
@@ -628,6 +759,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     hipLaunchKernelGGL((k_fft_rows<T, -1>), dim3(d.na, nrhs * 2), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
                        (int64_t)d.Pb, d.na, 2 * plane);
   }
+  mark(5);
   // a3 + a5
   {
     size_t sh = (size_t)(d.F + 9 * d.U) * sizeof(V) + 16 * sizeof(int);
@@ -636,14 +768,26 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                        d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L, d.q, d.U, d.F, d.S, d.ncell,
                        d.Pa, d.Pb, d.N, k2);
   }
+  mark(6);
   // a4 shared
-  {
+  if (d.ch == 8) {
+    const int Gw = (d.L + 4) * 8;
+    V* grid = lat + (size_t)nrhs * 4 * plane;
+    const int64_t gsz = (int64_t)Gw * Gw;
+    hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, st, u, grid, d.dw,
+                       d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
+    constexpr int NT = 2;
+    hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs), dim3(256), 0,
+                       st, (const V*)grid, v, (const V*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N,
+                       k2);
+  } else {
     constexpr int CT = 16, KC = 32;
     size_t sh = (size_t)(d.S * KC + KC * CT) * sizeof(V) + 25 * CT * sizeof(int);
     hipLaunchKernelGGL((k_near_shared<T, CT, KC>), dim3((d.nicell + CT - 1) / CT, nrhs), dim3(256), sh, st, u, v,
                        (const V*)d.Wsh, d.dw, d.icells, d.cell_xy, d.cell_map, d.slot_map, d.L, d.ch, d.S,
                        d.nicell, d.N, k2);
   }
+  mark(7);
   // a4 csr
   if (d.nrows > 0) {
     if (d.csr_f64)
@@ -653,11 +797,14 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       hipLaunchKernelGGL((k_near_csr<T, float2>), dim3((d.nrows + 3) / 4), dim3(256), 0, st, u, v, d.rowptr,
                          d.rows, d.cols, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
   }
+  mark(8);
   return hipGetLastError();
 }
 
-template hipError_t launch_apply<double>(const DevView<double>&, const void*, void*, int, void*, hipStream_t);
-template hipError_t launch_apply<float>(const DevView<float>&, const void*, void*, int, void*, hipStream_t);
+template hipError_t launch_apply<double>(const DevView<double>&, const void*, void*, int, void*, hipStream_t,
+                                         hipEvent_t*);
+template hipError_t launch_apply<float>(const DevView<float>&, const void*, void*, int, void*, hipStream_t,
+                                        hipEvent_t*);
 
 hipError_t set_fft_lds_limits(size_t bytes) {
   hipError_t e = hipSuccess;

@@ -31,7 +31,8 @@ struct DevView {
 };
 
 template <typename T>
-hipError_t launch_apply(const DevView<T>& d, const void* u, void* v, int nrhs, void* ws, hipStream_t st);
+hipError_t launch_apply(const DevView<T>& d, const void* u, void* v, int nrhs, void* ws, hipStream_t st,
+                        hipEvent_t* ev = nullptr);
 hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st);
 hipError_t set_fft_lds_limits(size_t bytes);
 

@@ -50,8 +50,8 @@ def config(name):
     disc_k2pi   unit disc, n = 1.5, kappa = 2 pi, h = 1/32, annulus 0.8 < r < 1
                 with 64 x 16 intervals (about 4k points)
     star_k32pi  star R = 1 + 0.3 cos 5 theta, n^2 = 1 + 0.8 exp(-4|x|^2),
-                kappa = 32 pi, h = 1/512, band 0.9 < s < 1 with 4096 x 64
-                intervals (about 1.1M points)
+                kappa = 32 pi, h = 1/512, band 0.9 < s < 1 with 4096 x 32
+                intervals (about 950k points)
     star_k16pi  the same star at kappa = 16 pi, h = 1/256, band 2048 x 32
                 (about 270k points; 256 incident directions)
     """
@@ -61,8 +61,7 @@ def config(name):
         c["incidence"] = [0.0]
         c["gmres"] = {"tol": 1e-10, "restart": 100}
     elif name == "star_k32pi":
-        c = _base(32 * math.pi, 1.0 / 512, 0.3, 5, 0.9, 4096, 64, 0.9, 0.975)
-        c["r2"] = 12.0
+        c = _base(32 * math.pi, 1.0 / 512, 0.3, 5, 0.9, 4096, 32, 0.9, 0.975)
         c["n2"] = {"kind": "gauss", "base": 1.0, "amp": 0.8, "decay": 4.0}
         c["incidence"] = [math.pi / 6]
         c["gmres"] = {"tol": 1e-8, "restart": 60}
