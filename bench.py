@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-applies", type=int, default=0,
+                    help="profiling run: only this many applies per precision plus a 512 MiB "
+                         "device copy (the calibration kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs",
@@ -104,6 +107,19 @@ def main():
     N = op.N
     n_int = int((key[:, 0] == 0).sum())
     f = torch.tensor(plane_wave(cfg, xy, cfg["incidence"][0]), dtype=torch.complex128, device="cuda")
+    if args.profile_applies:
+        for dt in (torch.complex64, torch.complex128):
+            u = f.to(dt)
+            v = torch.empty_like(u)
+            for _ in range(args.profile_applies):
+                op.apply(u, v)
+            torch.cuda.synchronize()
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"profile run done: {args.profile_applies} applies per precision, copy of {a.numel()} bytes")
+        return
     x_ref = torch.empty_like(f)
     g = cfg["gmres"]
     t0 = time.time()
