@@ -255,7 +255,8 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   // LDS needed by the FFT kernels
   int lds_max = 0;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device);
-  const int tc = std::max(1, std::min(16, (int)(32768 / (2 * (size_t)h.Pa * 16))));
+  // FFT column tiles of 128 bytes per row (8 double or 16 float complex values)
+  const int tc = std::max(1, std::min(8, (int)(150 * 1024 / (2 * (size_t)h.Pa * 16))));
   size_t need = std::max(2 * (size_t)h.Pb * 16, 2 * (size_t)h.Pa * tc * 16);
   if (need > 160 * 1024) {
     ls_host_destroy(hb);
@@ -307,9 +308,22 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   UP(upload_c(op, h.Pbd, &a.Pbd, nullptr));
   UP(upload_c(op, h.Psh32, nullptr, &b.Psh));
   UP(upload_c(op, h.Pbd32, nullptr, &b.Pbd));
-  UP(upload_c(op, h.Ish, &a.Ish, &b.Ish));
+  {
+    // transposed layouts for coalesced reads in the interpolation kernel
+    std::vector<cd> IshT((size_t)h.F * h.S);
+    for (int a2 = 0; a2 < h.S; ++a2)
+      for (int t = 0; t < h.F; ++t) IshT[(size_t)t * h.S + a2] = h.Ish[(size_t)a2 * h.F + t];
+    UP(upload_c(op, IshT, &a.Ish, &b.Ish));
+  }
   UP(upload_c(op, h.Ibd, &a.Ibd, &b.Ibd));
-  UP(upload_c(op, h.Toff, &a.Toff, &b.Toff));
+  {
+    std::vector<cd> ToffT((size_t)9 * h.U * h.F);
+    for (int o = 0; o < 9; ++o)
+      for (int t = 0; t < h.F; ++t)
+        for (int u2 = 0; u2 < h.U; ++u2)
+          ToffT[((size_t)o * h.U + u2) * h.F + t] = h.Toff[((size_t)o * h.F + t) * h.U + u2];
+    UP(upload_c(op, ToffT, &a.Toff, &b.Toff));
+  }
   UP(upload_c(op, h.Wsh, &a.Wsh, &b.Wsh));
   UP(upload_c(op, h.vals, &a.vals, &b.vals));
   {
@@ -459,7 +473,7 @@ struct Gm {
   int64_t N;
   hipStream_t st;
   char* base;
-  double2 *V, *w, *r, *tmp64, *rout, *e, *hdev, *partial;
+  double2 *V, *w, *r, *tmp64, *rout, *e, *hdev, *hdev2, *ndev, *partial;
   void *ws, *u32, *v32;
   double* sdev;
   size_t wsb;
@@ -471,7 +485,7 @@ struct Gm {
 size_t gm_need(const ls_op* op, int nrhs, int m) {
   size_t N = op->N;
   size_t v = 16 * N * nrhs;
-  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 2 + 16 * 256 * (size_t)(m + 2) * nrhs +
+  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 4 + 16 * nrhs + 16 * 256 * (size_t)(m + 2) * nrhs +
              8 * nrhs + ws_bytes(op, nrhs, LS_C128) + 2 * 8 * N * nrhs + 4096;
   return b;
 }
@@ -499,6 +513,8 @@ ls_status gm_setup(Gm& g) {
   g.rout = (double2*)take(vb);
   g.e = (double2*)take(vb);
   g.hdev = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs * 2);
+  g.hdev2 = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs);
+  g.ndev = (double2*)take(16 * (size_t)g.nrhs);
   g.nparts = 256;
   g.partial = (double2*)take(16 * 256 * (size_t)(g.m + 2) * g.nrhs);
   g.sdev = (double*)take(8 * g.nrhs);
@@ -521,7 +537,6 @@ ls_status gm_apply(Gm& g, const double2* x, double2* y, ls_prec prec) {
     if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
     HIPCHK(lsx::gm_to_f64(g.v32, y, n, g.st));
   }
-  HIPCHK(hipStreamSynchronize(g.st));
   g.apply_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   g.applies++;
   return LS_OK;
@@ -589,21 +604,23 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
       s = gm_apply(g, vk, g.w, prec);
       if (s) return s;
       ++it;
-      std::vector<std::complex<double>> h1, h2;
-      for (int pass = 0; pass < 2; ++pass) {
-        s = gm_dots_host(g, g.V, g.w, k + 1, vstride, pass == 0 ? h1 : h2);
-        if (s) return s;
-        HIPCHK(hipMemcpyAsync(g.hdev, (pass == 0 ? h1 : h2).data(), 16 * (size_t)(k + 1) * R,
-                              hipMemcpyHostToDevice, g.st));
-        HIPCHK(lsx::gm_update(g.V, g.w, g.hdev, k + 1, N, R, vstride, g.st));
-      }
-      s = gm_dots_host(g, g.w, g.w, 1, 0, dd);
-      if (s) return s;
-      std::vector<double> invn(R);
+      // CGS2 on the device: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2,
+      // |w|^2, V_{k+1} = w / |w|; one host synchronisation to read h1, h2, |w|
+      HIPCHK(lsx::gm_dots(g.V, g.w, g.partial, g.hdev, k + 1, N, R, vstride, g.nparts, g.st));
+      HIPCHK(lsx::gm_update(g.V, g.w, g.hdev, k + 1, N, R, vstride, g.st));
+      HIPCHK(lsx::gm_dots(g.V, g.w, g.partial, g.hdev2, k + 1, N, R, vstride, g.nparts, g.st));
+      HIPCHK(lsx::gm_update(g.V, g.w, g.hdev2, k + 1, N, R, vstride, g.st));
+      HIPCHK(lsx::gm_dots(g.w, g.w, g.partial, g.ndev, 1, N, R, 0, g.nparts, g.st));
+      HIPCHK(lsx::gm_inv_norm(g.ndev, g.sdev, R, g.st));
+      HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
+      std::vector<std::complex<double>> h1((size_t)(k + 1) * R), h2((size_t)(k + 1) * R), dn(R);
+      HIPCHK(hipMemcpyAsync(h1.data(), g.hdev, 16 * h1.size(), hipMemcpyDeviceToHost, g.st));
+      HIPCHK(hipMemcpyAsync(h2.data(), g.hdev2, 16 * h2.size(), hipMemcpyDeviceToHost, g.st));
+      HIPCHK(hipMemcpyAsync(dn.data(), g.ndev, 16 * R, hipMemcpyDeviceToHost, g.st));
+      HIPCHK(hipStreamSynchronize(g.st));
       bool all_done = true;
       for (int r = 0; r < R; ++r) {
-        double hn = std::sqrt(std::max(0.0, dd[r].real()));
-        invn[r] = hn > 0 ? 1.0 / hn : 0.0;
+        double hn = std::sqrt(std::max(0.0, dn[r].real()));
         std::complex<double>* col = &Hm[((size_t)r * m + k) * (m + 1)];
         for (int j = 0; j <= k; ++j) col[j] = h1[(size_t)r * (k + 1) + j] + h2[(size_t)r * (k + 1) + j];
         col[k + 1] = hn;
@@ -626,8 +643,6 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
         if (kdone[r] < 0 && (est <= tol || hn == 0.0)) kdone[r] = k + 1;
         if (kdone[r] < 0) all_done = false;
       }
-      HIPCHK(hipMemcpyAsync(g.sdev, invn.data(), 8 * R, hipMemcpyHostToDevice, g.st));
-      HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
       if (all_done) { ++k; break; }
     }
     // x += V y  (each rhs uses its own Krylov dimension)

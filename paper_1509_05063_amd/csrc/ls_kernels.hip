@@ -170,35 +170,47 @@ __device__ __forceinline__ void dft_small(V* v, int R) {
   }
 }
 
+template <typename V, int DIR, int R>
+__device__ __forceinline__ void stockham_pass(const V* __restrict__ src, V* __restrict__ dst, const V* __restrict__ tw,
+                                              int n, int Ns, int stride, int tid, int nthr) {
+  const int nb = n / R;
+  const int twstep = n / (Ns * R);
+  for (int w = tid; w < nb * stride; w += nthr) {
+    const int j = w / stride, lane = w - j * stride;
+    const int jm = j % Ns;
+    V v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      V x = src[(j + m * nb) * stride + lane];
+      if (m > 0 && jm > 0) {
+        V t = tw[(jm * m * twstep) % n];
+        if (DIR < 0) t.y = -t.y;
+        x = cmul(x, t);
+      }
+      v[m] = x;
+    }
+    dft_small<V, DIR>(v, R);
+    const int o = (j / Ns) * Ns * R + jm;
+#pragma unroll
+    for (int m = 0; m < R; ++m) dst[(o + m * Ns) * stride + lane] = v[m];
+  }
+}
+
 template <typename V, int DIR>
 __device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, const int8_t* radix,
                              int npass, int stride, int tid, int nthr, V** result) {
   // stride: distance between consecutive elements of one transform in LDS
-  // (1 for rows; >1 when several columns are interleaved).  The transforms
-  // handled by this call are at offsets 0..stride-1 (one per lane group).
+  // (1 for rows; >1 when several columns are interleaved).
   V* src = buf0;
   V* dst = buf1;
   int Ns = 1;
   for (int p = 0; p < npass; ++p) {
     const int R = radix[p];
-    const int nb = n / R;
-    const int twstep = n / (Ns * R);
-    for (int w = tid; w < nb * stride; w += nthr) {
-      const int j = w / stride, lane = w % stride;
-      V v[5];
-      const int jm = j % Ns;
-      for (int m = 0; m < R; ++m) {
-        V x = src[(j + m * nb) * stride + lane];
-        if (m > 0 && jm > 0) {
-          V t = tw[(jm * m * twstep) % n];
-          if (DIR < 0) t.y = -t.y;
-          x = cmul(x, t);
-        }
-        v[m] = x;
-      }
-      dft_small<V, DIR>(v, R);
-      const int o = (j / Ns) * Ns * R + jm;
-      for (int m = 0; m < R; ++m) dst[(o + m * Ns) * stride + lane] = v[m];
+    switch (R) {
+      case 2: stockham_pass<V, DIR, 2>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 3: stockham_pass<V, DIR, 3>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 4: stockham_pass<V, DIR, 4>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      default: stockham_pass<V, DIR, 5>(src, dst, tw, n, Ns, stride, tid, nthr); break;
     }
     __syncthreads();
     V* t = src;
@@ -279,8 +291,8 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
                                                 typename C2<T>::t* __restrict__ v,
                                                 const typename C2<T>::t* __restrict__ lat,
                                                 const typename C2<T>::t* __restrict__ sigma,
-                                                const typename C2<T>::t* __restrict__ Toff,
-                                                const typename C2<T>::t* __restrict__ Ish,
+                                                const typename C2<T>::t* __restrict__ ToffT,
+                                                const typename C2<T>::t* __restrict__ IshT,
                                                 const typename C2<T>::t* __restrict__ Ibd,
                                                 const int32_t* __restrict__ cell_xy,
                                                 const int32_t* __restrict__ cell_map,
@@ -290,11 +302,13 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
                                                 const int32_t* __restrict__ cell_nb,
                                                 const int32_t* __restrict__ cell_boff, int L, int q, int U,
                                                 int F, int S, int ncell, int Pa, int Pb, int64_t N, T k2) {
+  // ToffT [9][U][F] (transposed adjacency fields), IshT [F][S]
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
   V* f = reinterpret_cast<V*>(smem_raw);      // F face values
   V* sg = f + F;                              // 9 * U neighbour strengths
-  int* nbr = reinterpret_cast<int*>(sg + 9 * U);
+  V* part = sg + 9 * U;                       // 9 * F partial adjacent fields
+  int* nbr = reinterpret_cast<int*>(part + 9 * F);
   const int c = blockIdx.x, r = blockIdx.y;
   const int cx = cell_xy[2 * c], cy = cell_xy[2 * c + 1];
   const int64_t plane = (int64_t)Pa * Pb;
@@ -315,16 +329,23 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
     f[t] = lat[((int64_t)(r * 2 + s) * 2) * plane + (int64_t)cn * Pb + ct * q + j];
   }
   __syncthreads();
-  // subtract adjacent equivalent-source fields (same set only)
-  for (int t = threadIdx.x; t < F; t += blockDim.x) {
-    int s = t / (2 * q);
-    V acc = f[t];
-    for (int o = 0; o < 9; ++o) {
-      if (nbr[o] < 0) continue;
-      const V* Trow = Toff + ((int64_t)o * F + t) * U + s * 4 * q;
+  // adjacent equivalent-source fields at the face nodes (same set only):
+  // part[o][t] = sum_k ToffT[o][s 4q + k][t] sg[o][s 4q + k]
+  for (int i = threadIdx.x; i < 9 * F; i += blockDim.x) {
+    int o = i / F, t = i % F;
+    V acc = czero<V>();
+    if (nbr[o] >= 0) {
+      int s = t / (2 * q);
+      const V* Tcol = ToffT + ((int64_t)o * U + s * 4 * q) * F + t;
       const V* sv = sg + o * U + s * 4 * q;
-      for (int k = 0; k < 4 * q; ++k) acc = csub(acc, cmul(Trow[k], sv[k]));
+      for (int k = 0; k < 4 * q; ++k) acc = cfma(Tcol[(int64_t)k * F], sv[k], acc);
     }
+    part[i] = acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < F; t += blockDim.x) {
+    V acc = f[t];
+    for (int o = 0; o < 9; ++o) acc = csub(acc, part[o * F + t]);
     f[t] = acc;
   }
   __syncthreads();
@@ -335,10 +356,8 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
     int j = slot_map[(int64_t)c * S + a];
     if (j < 0) continue;
     V acc = czero<V>();
-    const V* irow = Ish + (int64_t)a * F;
-    for (int t = 0; t < F; ++t) acc = cfma(irow[t], f[t], acc);
-    V uj = ur[j];
-    vr[j] = cadd(uj, cscale(acc, k2));
+    for (int t = 0; t < F; ++t) acc = cfma(IshT[(int64_t)t * S + a], f[t], acc);
+    vr[j] = cadd(ur[j], cscale(acc, k2));
   }
   const int64_t boff = cell_boff[c];
   const int b0 = cell_start[c] + nint;
@@ -558,7 +577,9 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::
   }
 }
 
-// a4, rows touching the boundary patch: one wavefront per row
+// a4, rows touching the boundary patch: one wavefront per row; each weight
+// is loaded once and applied to up to four right-hand sides; four entries
+// per lane in flight.
 template <typename T, typename VT>
 __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __restrict__ u,
                                                   typename C2<T>::t* __restrict__ v,
@@ -567,29 +588,59 @@ __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __res
                                                   const int32_t* __restrict__ cols, const VT* __restrict__ vals,
                                                   int nrows, int64_t N, int nrhs, T k2) {
   using V = typename C2<T>::t;
+  constexpr int RB = 4;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (row >= nrows) return;
   const int64_t b = rowptr[row], e = rowptr[row + 1];
-  for (int r = 0; r < nrhs; ++r) {
-    const V* ur = u + (int64_t)r * N;
-    V acc = czero<V>();
-    for (int64_t k = b + lane; k < e; k += 64) {
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    const int nr = min(RB, nrhs - r0);
+    V acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = czero<V>();
+    int64_t k = b + lane;
+    for (; k + 3 * 64 < e; k += 4 * 64) {
+      VT w[4];
+      int c[4];
+#pragma unroll
+      for (int z = 0; z < 4; ++z) {
+        w[z] = vals[k + z * 64];
+        c[z] = cols[k + z * 64];
+      }
+#pragma unroll
+      for (int z = 0; z < 4; ++z) {
+        V ww;
+        ww.x = (T)w[z].x;
+        ww.y = (T)w[z].y;
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+          if (q < nr) acc[q] = cfma(ww, u[(int64_t)(r0 + q) * N + c[z]], acc[q]);
+      }
+    }
+    for (; k < e; k += 64) {
       VT w = vals[k];
+      int c = cols[k];
       V ww;
       ww.x = (T)w.x;
       ww.y = (T)w.y;
-      acc = cfma(ww, ur[cols[k]], acc);
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+        if (q < nr) acc[q] = cfma(ww, u[(int64_t)(r0 + q) * N + c], acc[q]);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_down(acc.x, off, 64);
-      acc.y += __shfl_down(acc.y, off, 64);
-    }
-    if (lane == 0) {
-      int64_t j = rows[row];
-      V* vr = v + (int64_t)r * N;
-      V t = vr[j];
-      vr[j] = cadd(t, cscale(acc, k2));
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      if (q >= nr) break;
+      V a = acc[q];
+      for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_down(a.x, off, 64);
+        a.y += __shfl_down(a.y, off, 64);
+      }
+      if (lane == 0) {
+        int64_t j = rows[row];
+        V* vr = v + (int64_t)(r0 + q) * N;
+        V t = vr[j];
+        vr[j] = cadd(t, cscale(a, k2));
+      }
     }
   }
 }
@@ -651,6 +702,13 @@ __global__ void k_update(const double2* __restrict__ Vb, double2* __restrict__ w
     acc.y -= hj.x * a.y + hj.y * a.x;
   }
   w[(int64_t)r * N + i] = acc;
+}
+
+__global__ void k_inv_norm(const double2* __restrict__ dd, double* __restrict__ s, int nrhs) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double v = dd[r].x;
+  s[r] = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
 }
 
 __global__ void k_scale_copy(const double2* __restrict__ src, double2* __restrict__ dst, const double* __restrict__ s,
@@ -735,12 +793,13 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   mark(2);
   // a2: forward transforms of all 4 arrays per rhs
   const int nbatch = nrhs * 4;
+  const int TCP = sizeof(T) == 8 ? d.tc : 2 * d.tc;   // 128-byte column tiles in either precision
   {
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     // rows a >= na are zero padding: their transforms stay zero
     hipLaunchKernelGGL((k_fft_rows<T, 1>), dim3(d.na, nbatch), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
                        (int64_t)d.Pb, d.na, plane);
-    int TC = d.tc;
+    int TC = TCP;
     size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
     hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, lat,
                        (const V*)d.twa, d.pa, d.Pb, TC, plane);
@@ -751,7 +810,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   mark(4);
   {
     // inverse transforms of kind 0 of each set: batch stride 2 planes
-    int TC = d.tc;
+    int TC = TCP;
     size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
     hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
                        (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane);
@@ -762,8 +821,8 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   mark(5);
   // a3 + a5
   {
-    size_t sh = (size_t)(d.F + 9 * d.U) * sizeof(V) + 16 * sizeof(int);
-    hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(128), sh, st, u, v, (const V*)lat, (const V*)sigma,
+    size_t sh = (size_t)(d.F + 9 * d.U + 9 * d.F) * sizeof(V) + 16 * sizeof(int);
+    hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), sh, st, u, v, (const V*)lat, (const V*)sigma,
                        (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.cell_map, d.slot_map,
                        d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L, d.q, d.U, d.F, d.S, d.ncell,
                        d.Pa, d.Pb, d.N, k2);
@@ -844,6 +903,10 @@ hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int 
   int count = nvec * nrhs;
   hipLaunchKernelGGL(k_reduce_partials, dim3((count + 63) / 64), dim3(64), 0, st, (const double2*)partial,
                      (double2*)out, nparts, count);
+  return hipGetLastError();
+}
+hipError_t gm_inv_norm(const void* dd, double* s, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_inv_norm, dim3((nrhs + 63) / 64), dim3(64), 0, st, (const double2*)dd, s, nrhs);
   return hipGetLastError();
 }
 hipError_t gm_update(const void* Vb, void* w, const void* h, int nvec, int64_t N, int nrhs, int64_t vstride,
