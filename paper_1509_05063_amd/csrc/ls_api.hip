@@ -485,7 +485,7 @@ struct Gm {
 size_t gm_need(const ls_op* op, int nrhs, int m) {
   size_t N = op->N;
   size_t v = 16 * N * nrhs;
-  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 4 + 16 * nrhs + 16 * 256 * (size_t)(m + 2) * nrhs +
+  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 4 + 16 * nrhs + 16 * 512 * (size_t)(m + 2) * nrhs +
              8 * nrhs + ws_bytes(op, nrhs, LS_C128) + 2 * 8 * N * nrhs + 4096;
   return b;
 }
@@ -515,8 +515,8 @@ ls_status gm_setup(Gm& g) {
   g.hdev = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs * 2);
   g.hdev2 = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs);
   g.ndev = (double2*)take(16 * (size_t)g.nrhs);
-  g.nparts = 256;
-  g.partial = (double2*)take(16 * 256 * (size_t)(g.m + 2) * g.nrhs);
+  g.nparts = 512;
+  g.partial = (double2*)take(16 * 512 * (size_t)(g.m + 2) * g.nrhs);
   g.sdev = (double*)take(8 * g.nrhs);
   g.wsb = ws_bytes(g.op, g.nrhs, LS_C128);
   g.ws = take(g.wsb);
@@ -606,11 +606,9 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
       ++it;
       // CGS2 on the device: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2,
       // |w|^2, V_{k+1} = w / |w|; one host synchronisation to read h1, h2, |w|
-      HIPCHK(lsx::gm_dots(g.V, g.w, g.partial, g.hdev, k + 1, N, R, vstride, g.nparts, g.st));
-      HIPCHK(lsx::gm_update(g.V, g.w, g.hdev, k + 1, N, R, vstride, g.st));
-      HIPCHK(lsx::gm_dots(g.V, g.w, g.partial, g.hdev2, k + 1, N, R, vstride, g.nparts, g.st));
-      HIPCHK(lsx::gm_update(g.V, g.w, g.hdev2, k + 1, N, R, vstride, g.st));
-      HIPCHK(lsx::gm_dots(g.w, g.w, g.partial, g.ndev, 1, N, R, 0, g.nparts, g.st));
+      HIPCHK(lsx::gm_cgs(g.V, g.w, nullptr, g.partial, g.hdev, k + 1, N, R, vstride, g.nparts, 0, g.st));
+      HIPCHK(lsx::gm_cgs(g.V, g.w, g.hdev, g.partial, g.hdev2, k + 1, N, R, vstride, g.nparts, 1, g.st));
+      HIPCHK(lsx::gm_cgs(g.V, g.w, g.hdev2, g.partial, g.ndev, k + 1, N, R, vstride, g.nparts, 2, g.st));
       HIPCHK(lsx::gm_inv_norm(g.ndev, g.sdev, R, g.st));
       HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
       std::vector<std::complex<double>> h1((size_t)(k + 1) * R), h2((size_t)(k + 1) * R), dn(R);

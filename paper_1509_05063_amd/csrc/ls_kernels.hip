@@ -677,6 +677,73 @@ __global__ void __launch_bounds__(256) k_dots(const double2* __restrict__ Vb, co
   }
 }
 
+// Fused CGS steps.  For a block of basis vectors V_0..V_{n-1} (vstride
+// apart) and the work vector w of each right-hand side:
+//   mode 0:  d_j = <V_j, w>
+//   mode 1:  w -= sum_j h_j V_j, then d_j = <V_j, w> (next CGS pass)
+//   mode 2:  w -= sum_j h_j V_j, then d_0 = <w, w>
+// Partial sums per workgroup go to partial[(r * nout + j) * gridDim.x + block].
+constexpr int GM_JB = 8;
+__global__ void __launch_bounds__(256) k_cgs(const double2* __restrict__ Vb, double2* __restrict__ w,
+                                             const double2* __restrict__ h, double2* __restrict__ partial,
+                                             int nvec, int64_t N, int64_t vstride, int mode) {
+  __shared__ double red[2 * GM_JB][256];
+  const int r = blockIdx.y;
+  double2* wr = w + (int64_t)r * N;
+  const double2* V0 = Vb + (int64_t)r * N;
+  const int nout = mode == 2 ? 1 : nvec;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mode != 0) {
+    for (int64_t i = i0; i < N; i += stride) {
+      double2 acc = wr[i];
+      for (int j = 0; j < nvec; ++j) {
+        double2 hj = h[r * nvec + j];
+        double2 a = V0[j * vstride + i];
+        acc.x -= hj.x * a.x - hj.y * a.y;
+        acc.y -= hj.x * a.y + hj.y * a.x;
+      }
+      wr[i] = acc;
+    }
+  }
+  for (int j0 = 0; j0 < nout; j0 += GM_JB) {
+    double ax[GM_JB], ay[GM_JB];
+#pragma unroll
+    for (int q = 0; q < GM_JB; ++q) ax[q] = ay[q] = 0.0;
+    for (int64_t i = i0; i < N; i += stride) {
+      double2 b = wr[i];
+      if (mode == 2) {
+        ax[0] += b.x * b.x + b.y * b.y;
+      } else {
+#pragma unroll
+        for (int q = 0; q < GM_JB; ++q) {
+          if (j0 + q < nvec) {
+            double2 a = V0[(j0 + q) * vstride + i];
+            ax[q] += a.x * b.x + a.y * b.y;      // conj(a) b
+            ay[q] += a.x * b.y - a.y * b.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GM_JB; ++q) {
+      red[2 * q][threadIdx.x] = ax[q];
+      red[2 * q + 1][threadIdx.x] = ay[q];
+    }
+    __syncthreads();
+    for (int sft = blockDim.x / 2; sft > 0; sft >>= 1) {
+      if (threadIdx.x < sft)
+#pragma unroll
+        for (int q = 0; q < 2 * GM_JB; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + sft];
+      __syncthreads();
+    }
+    if (threadIdx.x < GM_JB && j0 + threadIdx.x < nout)
+      partial[((int64_t)r * nout + j0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+          make_double2(red[2 * threadIdx.x][0], red[2 * threadIdx.x + 1][0]);
+    __syncthreads();
+  }
+}
+
 __global__ void k_reduce_partials(const double2* __restrict__ partial, double2* __restrict__ out, int nparts,
                                   int count) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -901,6 +968,15 @@ hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int 
   hipLaunchKernelGGL(k_dots, dim3(nparts, nrhs), dim3(256), 0, st, (const double2*)Vb, (const double2*)w,
                      (double2*)partial, nvec, N, nrhs, vstride);
   int count = nvec * nrhs;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((count + 63) / 64), dim3(64), 0, st, (const double2*)partial,
+                     (double2*)out, nparts, count);
+  return hipGetLastError();
+}
+hipError_t gm_cgs(const void* Vb, void* w, const void* h, void* partial, void* out, int nvec, int64_t N,
+                  int nrhs, int64_t vstride, int nparts, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(k_cgs, dim3(nparts, nrhs), dim3(256), 0, st, (const double2*)Vb, (double2*)w,
+                     (const double2*)h, (double2*)partial, nvec, N, vstride, mode);
+  int count = (mode == 2 ? 1 : nvec) * nrhs;
   hipLaunchKernelGGL(k_reduce_partials, dim3((count + 63) / 64), dim3(64), 0, st, (const double2*)partial,
                      (double2*)out, nparts, count);
   return hipGetLastError();

@@ -39,6 +39,8 @@ hipError_t set_fft_lds_limits(size_t bytes);
 // GMRES building blocks (double complex)
 hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int nvec, int64_t N, int nrhs,
                    int64_t vstride, int nparts, hipStream_t st);
+hipError_t gm_cgs(const void* Vb, void* w, const void* h, void* partial, void* out, int nvec, int64_t N,
+                  int nrhs, int64_t vstride, int nparts, int mode, hipStream_t st);
 hipError_t gm_inv_norm(const void* dd, double* s, int nrhs, hipStream_t st);
 hipError_t gm_update(const void* Vb, void* w, const void* h, int nvec, int64_t N, int nrhs, int64_t vstride,
                      hipStream_t st);

@@ -1,0 +1,142 @@
+"""GPU parity at the benchmark size (sampled rows, the oracle computes them
+one by one), multi-right-hand-side batching and edge cases, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1509_05063_amd.inputs import (config, match_keys, n2_function, plane_wave, random_density,
+                                         scaled)
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(cfg):
+    from paper_1509_05063_amd import binding
+    return binding.Operator(cfg, n2_function(cfg))
+
+
+@pytest.fixture(scope="module")
+def star32():
+    from oracle.op2d import Setup2D
+    cfg = config("star_k32pi")
+    op = _op(cfg)
+    orc = Setup2D(cfg, n2_function(cfg))
+    _, key = op.points()
+    p = match_keys(orc.pts["key"], key)
+    return cfg, op, orc, p
+
+
+def _sampled_rows(orc, nrows, seed=1509):
+    rng = np.random.default_rng(seed)
+    n_int = orc.pts["n_int"]
+    # half the rows on the boundary patch (they carry the interface rules)
+    a = rng.choice(n_int, nrows // 2, replace=False)
+    b = n_int + rng.choice(orc.N - n_int, nrows - nrows // 2, replace=False)
+    return np.concatenate([a, b])
+
+
+def test_benchmark_size_apply_sampled_rows(star32):
+    import torch
+    cfg, op, orc, p = star32
+    u_or = random_density(orc.pts["key"])
+    rows = _sampled_rows(orc, 24)
+    v_or = orc.A_rows(rows) @ u_or
+    u = np.empty(op.N, complex)
+    u[p] = u_or
+    for dt, tol in [(torch.complex128, 1e-8), (torch.complex64, 1e-4)]:
+        ud = torch.tensor(u, dtype=dt, device="cuda")
+        vd = torch.empty_like(ud)
+        op.apply(ud, vd)
+        torch.cuda.synchronize()
+        v = vd.cpu().numpy().astype(complex)[p][rows]
+        err = np.abs(v - v_or).max() / np.abs(v_or).max()
+        print(f"star_k32pi {dt}: sampled-row rel err {err:.3e}", flush=True)
+        assert err < tol
+
+
+def test_benchmark_size_solve_modes_agree(star32):
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, p = star32
+    xy, _ = op.points()
+    f = torch.tensor(plane_wave(cfg, xy, cfg["incidence"][0]), dtype=torch.complex128, device="cuda")
+    x64, x32 = torch.empty_like(f), torch.empty_like(f)
+    s64 = op.solve(f, x64, tol=1e-10, restart=60, max_iter=3000, mode=binding.LS_SOLVE_FP64)
+    s32 = op.solve(f, x32, tol=1e-8, restart=60, max_iter=3000, mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-4)
+    err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+    print(f"star_k32pi solves: fp64 {s64} fp32+refine {s32} diff {err:.3e}", flush=True)
+    assert s64["converged"] == 1 and s32["converged"] == 1
+    assert err < 1e-6
+    # the solution satisfies the oracle's equation on sampled rows
+    rows = _sampled_rows(orc, 8, seed=7)
+    x_or = x64.cpu().numpy()[p]
+    r = orc.A_rows(rows) @ x_or - plane_wave(cfg, orc.pts["x"][rows], cfg["incidence"][0])
+    assert np.abs(r).max() < 1e-7, np.abs(r).max()
+
+
+def test_multi_rhs_batch_matches_single_and_oracle():
+    import torch
+    from oracle.op2d import Setup2D
+    cfg = config("star_k16pi")
+    op = _op(cfg)
+    xy, key = op.points()
+    R = 8
+    dirs = cfg["incidence"][:: len(cfg["incidence"]) // R][:R]
+    U = torch.tensor(np.stack([plane_wave(cfg, xy, a) for a in dirs]), dtype=torch.complex128, device="cuda")
+    V = torch.empty_like(U)
+    op.apply(U, V)
+    for k in (0, R - 1):
+        v1 = torch.empty_like(U[k])
+        op.apply(U[k].contiguous(), v1)
+        torch.cuda.synchronize()
+        assert torch.equal(v1, V[k])
+    orc = Setup2D(cfg, n2_function(cfg))
+    p = match_keys(orc.pts["key"], key)
+    rows = _sampled_rows(orc, 8)
+    A = orc.A_rows(rows)
+    for k in (0, 5):
+        v_or = A @ plane_wave(cfg, orc.pts["x"], dirs[k])
+        v = V[k].cpu().numpy()[p][rows]
+        assert np.abs(v - v_or).max() / np.abs(v_or).max() < 1e-8
+    # batched solve: every right-hand side converges and matches its own solve
+    X = torch.empty_like(U)
+    st = op.solve(U[:4].contiguous(), X[:4], tol=1e-8, restart=60, max_iter=3000, mode=1, inner_tol=1e-4)
+    assert st["converged"] == 4
+    x1 = torch.empty_like(U[0])
+    op.solve(U[2].contiguous(), x1, tol=1e-8, restart=60, max_iter=3000, mode=1, inner_tol=1e-4)
+    assert (torch.linalg.norm(x1 - X[2]) / torch.linalg.norm(x1)).item() < 1e-6
+
+
+def test_edge_cases_tiny_grid_zero_input_and_errors():
+    import torch
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd import binding
+    # the smallest admissible grid: N2 = Q-1 intervals would not fit the
+    # 8-node stencil, so N2 = 8; lattice h = 1/16
+    cfg = scaled(config("disc_k2pi"), h=1 / 16, band={"N1": 32, "N2": 8}, r_int=6 / 16, r1=6.0, r2=4.0)
+    op = _op(cfg)
+    orc = Setup2D(cfg, n2_function(cfg))
+    _, key = op.points()
+    p = match_keys(orc.pts["key"], key)
+    u_or = random_density(orc.pts["key"], seed=3)
+    v_or = orc.dense_A() @ u_or
+    u = np.empty(op.N, complex)
+    u[p] = u_or
+    ud = torch.tensor(u, dtype=torch.complex128, device="cuda")
+    vd = torch.empty_like(ud)
+    op.apply(ud, vd)
+    torch.cuda.synchronize()
+    v = vd.cpu().numpy()[p]
+    assert np.linalg.norm(v - v_or) / np.linalg.norm(v_or) < 1e-8
+    # zero in, zero out (exactly)
+    z = torch.zeros_like(ud)
+    vz = torch.ones_like(ud)
+    op.apply(z, vz)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(vz).item() == 0
+    # invalid calls are reported, not executed
+    with pytest.raises(binding.LSError):
+        op.apply(ud, ud)                      # u and v overlap
+    with pytest.raises(ValueError):
+        op.apply(ud[:10], vd[:10])            # wrong length

@@ -80,3 +80,17 @@ def test_near_rows_complete_oracle_rows(disc, which):
         scale = np.abs(orow).max()
         err = np.abs(lib_row + far - orow).max() / scale
         assert err < 1e-11, (which, i, err)
+
+
+@pytest.mark.parametrize("over,msg", [
+    ({"kappa": 40.0}, "resonate"),                    # kappa H >= pi sqrt(2)
+    ({"band": {"N2": 18}}, "multiple of Q-1"),
+    ({"r_int": 20 / 32}, "two cells"),
+    ({"P": 7}, "P must be even"),
+    ({"pou": {"s_b": 1.0}}, "s_in <= s_a < s_b < 1"),
+])
+def test_invalid_parameters_rejected(over, msg):
+    cfg = scaled(config("disc_k2pi"), **over)
+    with pytest.raises(binding.LSError) as e:
+        binding.HostOperator(cfg, n2_function(cfg))
+    assert msg in str(e.value)
