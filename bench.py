@@ -49,7 +49,7 @@ def stage_bytes(st, N, n_int, s, s_w):
         "fft_inv": 2 * (plane + na * Pb) * 2 * s,
         "interp": ncell * (F + 9 * U) * s + nb * F * s_w + 2 * N * s,
         "near_shared": S * Wn * Wn * s_w + n_int * (s + r) + 2 * n_int * s,
-        "near_csr": st["csr_nnz"] * (s_w + 4) + st["csr_rows"] * (8 + 4 + 2 * s) + N * s,
+        "near_csr": st["csr_nnz"] * (s_w + 2) + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s,
     }
 
 
@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="profiling run: one single-precision-with-refinement solve only")
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="profiling run: only this many applies per precision plus a 512 MiB "
                          "device copy (the calibration kernel for HBM byte counters)")
@@ -120,8 +122,14 @@ def main():
         torch.cuda.synchronize()
         log(f"profile run done: {args.profile_applies} applies per precision, copy of {a.numel()} bytes")
         return
-    x_ref = torch.empty_like(f)
     g = cfg["gmres"]
+    if args.profile_solve:
+        x = torch.empty_like(f)
+        info = op.solve(f, x, tol=1e-7, restart=g["restart"], max_iter=3000,
+                        mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-4, max_outer=30)
+        log(f"profile solve {info}")
+        return
+    x_ref = torch.empty_like(f)
     t0 = time.time()
     ref = op.solve(f, x_ref, tol=1e-10, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP64)
     log(f"FP64 reference solve {time.time() - t0:.2f}s {ref}")

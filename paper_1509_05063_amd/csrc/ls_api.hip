@@ -49,6 +49,8 @@ struct ls_op {
   // solver scratch
   void* gm = nullptr;
   size_t gm_bytes = 0;
+  std::complex<double>* pinned = nullptr;
+  size_t pinned_n = 0;
 };
 
 namespace {
@@ -111,6 +113,8 @@ void release(ls_op* op) {
   op->allocs.clear();
   if (op->gm) (void)hipFree(op->gm);
   op->gm = nullptr;
+  if (op->pinned) (void)hipHostFree(op->pinned);
+  op->pinned = nullptr;
 }
 
 size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
@@ -342,7 +346,35 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   UP(upload_i(op, h.cell_map, &a.cell_map));
   UP(upload_i(op, icells, &a.icells));
   UP(upload_i(op, h.rows, &a.rows));
-  UP(upload_i(op, h.cols, &a.cols));
+  {
+    // columns as 16-bit offsets from the row's smallest column (a row spans
+    // at most a few cell rows of the cell-sorted order)
+    const size_t nr = h.rows.size();
+    std::vector<int32_t> cbase(nr);
+    bool narrow = true;
+    for (size_t r = 0; r < nr; ++r) {
+      int32_t lo = INT32_MAX, hi = INT32_MIN;
+      for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k) {
+        lo = std::min(lo, h.cols[k]);
+        hi = std::max(hi, h.cols[k]);
+      }
+      if (h.rowptr[r + 1] == h.rowptr[r]) lo = hi = 0;
+      if (hi - lo > 65535) narrow = false;
+      cbase[r] = lo;
+    }
+    UP(upload_i(op, cbase, &a.colbase));
+    if (narrow) {
+      std::vector<uint16_t> coff(h.cols.size());
+      for (size_t r = 0; r < nr; ++r)
+        for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k) coff[k] = (uint16_t)(h.cols[k] - cbase[r]);
+      UP(upload_i(op, coff, &a.coloff));
+    } else {
+      std::vector<int32_t> c32(h.cols.size());
+      for (size_t r = 0; r < nr; ++r)
+        for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k) c32[k] = h.cols[k] - cbase[r];
+      UP(upload_i(op, c32, &a.cols32));
+    }
+  }
   UP(upload_i(op, h.rowptr, &a.rowptr));
   b.slot_map = a.slot_map;
   b.cell_start = a.cell_start;
@@ -353,7 +385,9 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   b.cell_map = a.cell_map;
   b.icells = a.icells;
   b.rows = a.rows;
-  b.cols = a.cols;
+  b.colbase = a.colbase;
+  b.coloff = a.coloff;
+  b.cols32 = a.cols32;
   b.rowptr = a.rowptr;
   // twiddles exp(-2 pi i k / n), computed in double
   for (int which = 0; which < 2; ++which) {
@@ -480,13 +514,14 @@ struct Gm {
   int nparts;
   double apply_s = 0;
   int applies = 0;
+  std::complex<double>* pinned = nullptr;    // host copy of one iteration's h1 | h2 | |w|^2
 };
 
 size_t gm_need(const ls_op* op, int nrhs, int m) {
   size_t N = op->N;
   size_t v = 16 * N * nrhs;
-  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 4 + 16 * nrhs + 16 * 512 * (size_t)(m + 2) * nrhs +
-             8 * nrhs + ws_bytes(op, nrhs, LS_C128) + 2 * 8 * N * nrhs + 4096;
+  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 4 + 32 * nrhs + 16 * 512 * (size_t)(m + 2) * nrhs +
+             8 * nrhs + ws_bytes(op, nrhs, LS_C128) + 2 * 8 * N * nrhs + 16384;
   return b;
 }
 
@@ -513,8 +548,9 @@ ls_status gm_setup(Gm& g) {
   g.rout = (double2*)take(vb);
   g.e = (double2*)take(vb);
   g.hdev = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs * 2);
-  g.hdev2 = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs);
-  g.ndev = (double2*)take(16 * (size_t)g.nrhs);
+  // h1 | h2 | |w|^2 of one iteration, contiguous, copied back in one transfer
+  g.hdev2 = (double2*)take(16 * ((size_t)(g.m + 2) * g.nrhs * 2 + g.nrhs));
+  g.ndev = nullptr;
   g.nparts = 512;
   g.partial = (double2*)take(16 * 512 * (size_t)(g.m + 2) * g.nrhs);
   g.sdev = (double*)take(8 * g.nrhs);
@@ -522,6 +558,17 @@ ls_status gm_setup(Gm& g) {
   g.ws = take(g.wsb);
   g.u32 = take(8 * (size_t)g.N * g.nrhs);
   g.v32 = take(8 * (size_t)g.N * g.nrhs);
+  if (!g.op->pinned || g.op->pinned_n < (size_t)(g.m + 2) * g.nrhs * 2 + g.nrhs) {
+    if (g.op->pinned) (void)hipHostFree(g.op->pinned);
+    g.op->pinned = nullptr;
+    g.op->pinned_n = (size_t)(g.m + 2) * g.nrhs * 2 + g.nrhs;
+    if (hipHostMalloc((void**)&g.op->pinned, 16 * g.op->pinned_n) != hipSuccess) {
+      g.op->pinned = nullptr;
+      g.op->pinned_n = 0;
+      return fail(LS_ENOMEM, "pinned host buffer");
+    }
+  }
+  g.pinned = g.op->pinned;
   return LS_OK;
 }
 
@@ -606,16 +653,20 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
       ++it;
       // CGS2 on the device: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2,
       // |w|^2, V_{k+1} = w / |w|; one host synchronisation to read h1, h2, |w|
-      HIPCHK(lsx::gm_cgs(g.V, g.w, nullptr, g.partial, g.hdev, k + 1, N, R, vstride, g.nparts, 0, g.st));
-      HIPCHK(lsx::gm_cgs(g.V, g.w, g.hdev, g.partial, g.hdev2, k + 1, N, R, vstride, g.nparts, 1, g.st));
-      HIPCHK(lsx::gm_cgs(g.V, g.w, g.hdev2, g.partial, g.ndev, k + 1, N, R, vstride, g.nparts, 2, g.st));
-      HIPCHK(lsx::gm_inv_norm(g.ndev, g.sdev, R, g.st));
+      const size_t nh = (size_t)(k + 1) * R;
+      double2* d1 = g.hdev2;
+      double2* d2 = g.hdev2 + nh;
+      double2* dn_dev = g.hdev2 + 2 * nh;
+      HIPCHK(lsx::gm_cgs(g.V, g.w, nullptr, g.partial, d1, k + 1, N, R, vstride, g.nparts, 0, g.st));
+      HIPCHK(lsx::gm_cgs(g.V, g.w, d1, g.partial, d2, k + 1, N, R, vstride, g.nparts, 1, g.st));
+      HIPCHK(lsx::gm_cgs(g.V, g.w, d2, g.partial, dn_dev, k + 1, N, R, vstride, g.nparts, 2, g.st));
+      HIPCHK(lsx::gm_inv_norm(dn_dev, g.sdev, R, g.st));
       HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
-      std::vector<std::complex<double>> h1((size_t)(k + 1) * R), h2((size_t)(k + 1) * R), dn(R);
-      HIPCHK(hipMemcpyAsync(h1.data(), g.hdev, 16 * h1.size(), hipMemcpyDeviceToHost, g.st));
-      HIPCHK(hipMemcpyAsync(h2.data(), g.hdev2, 16 * h2.size(), hipMemcpyDeviceToHost, g.st));
-      HIPCHK(hipMemcpyAsync(dn.data(), g.ndev, 16 * R, hipMemcpyDeviceToHost, g.st));
+      HIPCHK(hipMemcpyAsync(g.pinned, d1, 16 * (2 * nh + R), hipMemcpyDeviceToHost, g.st));
       HIPCHK(hipStreamSynchronize(g.st));
+      const std::complex<double>* h1 = g.pinned;
+      const std::complex<double>* h2 = g.pinned + nh;
+      const std::complex<double>* dn = g.pinned + 2 * nh;
       bool all_done = true;
       for (int r = 0; r < R; ++r) {
         double hn = std::sqrt(std::max(0.0, dn[r].real()));

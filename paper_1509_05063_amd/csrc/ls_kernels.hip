@@ -580,12 +580,13 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::
 // a4, rows touching the boundary patch: one wavefront per row; each weight
 // is loaded once and applied to up to four right-hand sides; four entries
 // per lane in flight.
-template <typename T, typename VT>
+template <typename T, typename VT, typename CT>
 __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __restrict__ u,
                                                   typename C2<T>::t* __restrict__ v,
                                                   const int64_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ rows,
-                                                  const int32_t* __restrict__ cols, const VT* __restrict__ vals,
+                                                  const int32_t* __restrict__ colbase,
+                                                  const CT* __restrict__ coloff, const VT* __restrict__ vals,
                                                   int nrows, int64_t N, int nrhs, T k2) {
   using V = typename C2<T>::t;
   constexpr int RB = 4;
@@ -593,6 +594,8 @@ __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __res
   const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (row >= nrows) return;
   const int64_t b = rowptr[row], e = rowptr[row + 1];
+  const int cb = colbase[row];
+  const V* __restrict__ ub = u + cb;
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     const int nr = min(RB, nrhs - r0);
     V acc[RB];
@@ -605,7 +608,7 @@ __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __res
 #pragma unroll
       for (int z = 0; z < 4; ++z) {
         w[z] = vals[k + z * 64];
-        c[z] = cols[k + z * 64];
+        c[z] = coloff[k + z * 64];
       }
 #pragma unroll
       for (int z = 0; z < 4; ++z) {
@@ -614,18 +617,18 @@ __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __res
         ww.y = (T)w[z].y;
 #pragma unroll
         for (int q = 0; q < RB; ++q)
-          if (q < nr) acc[q] = cfma(ww, u[(int64_t)(r0 + q) * N + c[z]], acc[q]);
+          if (q < nr) acc[q] = cfma(ww, ub[(int64_t)(r0 + q) * N + c[z]], acc[q]);
       }
     }
     for (; k < e; k += 64) {
       VT w = vals[k];
-      int c = cols[k];
+      int c = coloff[k];
       V ww;
       ww.x = (T)w.x;
       ww.y = (T)w.y;
 #pragma unroll
       for (int q = 0; q < RB; ++q)
-        if (q < nr) acc[q] = cfma(ww, u[(int64_t)(r0 + q) * N + c], acc[q]);
+        if (q < nr) acc[q] = cfma(ww, ub[(int64_t)(r0 + q) * N + c], acc[q]);
     }
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
@@ -744,16 +747,29 @@ __global__ void __launch_bounds__(256) k_cgs(const double2* __restrict__ Vb, dou
   }
 }
 
-__global__ void k_reduce_partials(const double2* __restrict__ partial, double2* __restrict__ out, int nparts,
-                                  int count) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// one workgroup per output: out[i] = sum_p partial[i * nparts + p]
+__global__ void __launch_bounds__(256) k_reduce_partials(const double2* __restrict__ partial,
+                                                         double2* __restrict__ out, int nparts, int count) {
+  __shared__ double rx[256], ry[256];
+  const int i = blockIdx.x;
   if (i >= count) return;
-  double2 s = make_double2(0.0, 0.0);
-  for (int p = 0; p < nparts; ++p) {
-    s.x += partial[(int64_t)i * nparts + p].x;
-    s.y += partial[(int64_t)i * nparts + p].y;
+  double sx = 0.0, sy = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+    double2 v = partial[(int64_t)i * nparts + p];
+    sx += v.x;
+    sy += v.y;
   }
-  out[i] = s;
+  rx[threadIdx.x] = sx;
+  ry[threadIdx.x] = sy;
+  __syncthreads();
+  for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) {
+      rx[threadIdx.x] += rx[threadIdx.x + s2];
+      ry[threadIdx.x] += ry[threadIdx.x + s2];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = make_double2(rx[0], ry[0]);
 }
 
 __global__ void k_update(const double2* __restrict__ Vb, double2* __restrict__ w, const double2* __restrict__ h,
@@ -916,12 +932,22 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   mark(7);
   // a4 csr
   if (d.nrows > 0) {
-    if (d.csr_f64)
-      hipLaunchKernelGGL((k_near_csr<T, double2>), dim3((d.nrows + 3) / 4), dim3(256), 0, st, u, v, d.rowptr,
-                         d.rows, d.cols, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
-    else
-      hipLaunchKernelGGL((k_near_csr<T, float2>), dim3((d.nrows + 3) / 4), dim3(256), 0, st, u, v, d.rowptr,
-                         d.rows, d.cols, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+    const dim3 g((d.nrows + 3) / 4), b(256);
+    if (d.csr_f64) {
+      if (d.coloff)
+        hipLaunchKernelGGL((k_near_csr<T, double2, uint16_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
+                           d.coloff, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
+      else
+        hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
+                           d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
+    } else {
+      if (d.coloff)
+        hipLaunchKernelGGL((k_near_csr<T, float2, uint16_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
+                           d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+      else
+        hipLaunchKernelGGL((k_near_csr<T, float2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
+                           d.cols32, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+    }
   }
   mark(8);
   return hipGetLastError();
@@ -968,8 +994,8 @@ hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int 
   hipLaunchKernelGGL(k_dots, dim3(nparts, nrhs), dim3(256), 0, st, (const double2*)Vb, (const double2*)w,
                      (double2*)partial, nvec, N, nrhs, vstride);
   int count = nvec * nrhs;
-  hipLaunchKernelGGL(k_reduce_partials, dim3((count + 63) / 64), dim3(64), 0, st, (const double2*)partial,
-                     (double2*)out, nparts, count);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(count), dim3(256), 0, st, (const double2*)partial, (double2*)out,
+                     nparts, count);
   return hipGetLastError();
 }
 hipError_t gm_cgs(const void* Vb, void* w, const void* h, void* partial, void* out, int nvec, int64_t N,
@@ -977,8 +1003,8 @@ hipError_t gm_cgs(const void* Vb, void* w, const void* h, void* partial, void* o
   hipLaunchKernelGGL(k_cgs, dim3(nparts, nrhs), dim3(256), 0, st, (const double2*)Vb, (double2*)w,
                      (const double2*)h, (double2*)partial, nvec, N, vstride, mode);
   int count = (mode == 2 ? 1 : nvec) * nrhs;
-  hipLaunchKernelGGL(k_reduce_partials, dim3((count + 63) / 64), dim3(64), 0, st, (const double2*)partial,
-                     (double2*)out, nparts, count);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(count), dim3(256), 0, st, (const double2*)partial, (double2*)out,
+                     nparts, count);
   return hipGetLastError();
 }
 hipError_t gm_inv_norm(const void* dd, double* s, int nrhs, hipStream_t st) {

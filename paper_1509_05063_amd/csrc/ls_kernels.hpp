@@ -25,7 +25,9 @@ struct DevView {
   const T *cw = nullptr, *dw = nullptr;
   const int32_t *slot_map = nullptr, *cell_start = nullptr, *cell_nint = nullptr, *cell_nb = nullptr;
   const int32_t *cell_boff = nullptr, *cell_xy = nullptr, *cell_map = nullptr, *icells = nullptr;
-  const int32_t *rows = nullptr, *cols = nullptr;
+  const int32_t *rows = nullptr, *colbase = nullptr;
+  const uint16_t* coloff = nullptr;   // column = colbase[row] + coloff[k] (16-bit form)
+  const int32_t* cols32 = nullptr;    // column = colbase[row] + cols32[k] (when a row spans > 65535)
   const int64_t* rowptr = nullptr;
   FftPlan pa{}, pb{};
 };
