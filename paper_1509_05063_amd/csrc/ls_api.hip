@@ -761,6 +761,11 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
       for (int k = 0; k < nrhs; ++k)
         if (std::sqrt(dr[k].real()) > opts->tol * std::sqrt(df[k].real())) all = false;
       if (all || total >= opts->max_iter || outer >= std::max(1, opts->max_outer)) break;
+      // right-hand sides that already meet tol get no further correction, so
+      // each one ends exactly where its own solve would
+      for (int k = 0; k < nrhs; ++k)
+        if (std::sqrt(dr[k].real()) <= opts->tol * std::sqrt(df[k].real()))
+          HIPCHK(hipMemsetAsync(g.rout + (size_t)k * op->N, 0, 16 * (size_t)op->N, g.st));
       HIPCHK(hipMemsetAsync(g.e, 0, 16 * (size_t)n, g.st));
       int it = 0;
       std::vector<double> rr;

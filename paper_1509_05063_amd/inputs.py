@@ -139,3 +139,41 @@ def match_keys(keys_a, keys_b):
     if not np.array_equal(cb[p], ca):
         raise ValueError("node sets differ")
     return p
+
+
+def serving_pool(n_ops=6, seed=20509, n_range=(1.1, 1.5)):
+    """A pool of 2-D star scatterers R = 1 + a cos(k theta), a ~ U[0, 0.3],
+    k ~ U{3..7}, constant n ~ U[n_range], kappa ~ U[4 pi, 32 pi]; the lattice
+    spacing keeps about 12 points per interior wavelength (1/h a power of two
+    in 64..256) and the cells below resonance (kappa H < pi sqrt 2)."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(n_ops):
+        a = float(rng.uniform(0.0, 0.3))
+        k = int(rng.integers(3, 8))
+        n = float(rng.uniform(*n_range))
+        kappa = float(rng.uniform(4 * math.pi, 32 * math.pi))
+        level = 64
+        while level < 256 and (kappa * n / level > 2 * math.pi / 12 or kappa * 8 / level >= math.pi * math.sqrt(2)):
+            level *= 2
+        kappa = min(kappa, 0.95 * math.pi * math.sqrt(2) * level / 8)
+        N2 = max(8, 4 * round(level / 64))
+        c = _base(kappa, 1.0 / level, a, k, 0.9, 8 * level, N2, 0.9, 0.975)
+        c["n2"] = {"kind": "const", "value": n * n}
+        c["name"] = f"pool{i}"
+        pool.append(c)
+    return pool
+
+
+def serving_trace(pool, n_requests, rate=50.0, seed=20509):
+    """Poisson arrivals (mean `rate` per second) of solves on a scatterer drawn
+    uniformly from `pool`, incidence angle uniform in [0, 2 pi).
+    Returns [(arrival_s, key, cfg, alpha)]."""
+    rng = np.random.default_rng(seed + 1)
+    t = 0.0
+    out = []
+    for _ in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        c = pool[int(rng.integers(len(pool)))]
+        out.append((t, c["name"], c, float(rng.uniform(0.0, 2 * math.pi))))
+    return out
