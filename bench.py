@@ -53,6 +53,33 @@ def stage_bytes(st, N, n_int, s, s_w):
     }
 
 
+# single-precision kernel of each one-kernel stage (the FFT stages run several)
+STAGE_KERNEL = {"project": "k_project<float>", "fill": "k_fill<float>", "spectral": "k_spectral<float>",
+                "interp": "k_interp<float>", "near_shared": "k_near_shared_mfma<float,2>",
+                "near_csr": "k_near_csr<float>"}
+
+
+def counter_traffic(kernel, summary=os.path.join(ROOT, "profiles", "apply_star_k32pi.md")):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when the summary is missing or was taken on a different kernel
+    source than the one built here."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1509_05063_amd", "csrc", "ls_kernels.hip")
+    try:
+        text = open(summary).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if f"ls_kernels.hip sha256: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 4 and cells[0] == kernel:
+            return int(round((float(cells[1]) + float(cells[2])) * 2 ** 20))
+    return None
+
+
 def cpu_oracle_rate(cfg, n2, budget_s=20.0):
     """Oracle rows per second on a bounded sample of targets (single thread)."""
     from oracle.op2d import Setup2D
@@ -73,6 +100,35 @@ def cpu_oracle_rate(cfg, n2, budget_s=20.0):
     return done / dt, done, orc.N
 
 
+def serving_run(n_requests, rate=20.0):
+    """Poisson stream of solves over a warm pool of resident operators
+    (continuous batching per operator, concurrent solves across operators)."""
+    from paper_1509_05063_amd.inputs import serving_pool, serving_trace
+    from paper_1509_05063_amd.serve import Server, latency_stats, replay
+    pool = serving_pool()
+    srv = Server(budget_bytes=200e9, max_batch=16, workers=4, keep_results=False)
+    try:
+        t0 = time.time()
+        for c in pool:                      # warm: build every operator once
+            srv.submit(c["name"], c, 0.0)
+        srv.drain()
+        warm = time.time() - t0
+        srv.tickets.clear()
+        reqs, wall = replay(srv, serving_trace(pool, n_requests, rate=rate))
+        st = latency_stats(reqs)
+        conv = sum(1 for r in reqs if r.stats["converged"] == r.batch)
+        iters = {}
+        for r in reqs:
+            iters[r.key] = max(iters.get(r.key, 0), r.stats["iterations"])
+        return {"requests": len(reqs), "rate_per_s": rate, "operators": len(pool),
+                "N_range": [min(op.N for op in srv.ops.values()), max(op.N for op in srv.ops.values())],
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch"],
+                "solves_per_s": len(reqs) / wall, "all_converged": conv == len(reqs), "warmup_s": warm,
+                "max_iterations": iters}
+    finally:
+        srv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +138,8 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--profile-solve", action="store_true",
                     help="profiling run: one single-precision-with-refinement solve only")
     ap.add_argument("--profile-applies", type=int, default=0,
@@ -196,9 +254,15 @@ def main():
     dom = max(p32, key=p32.get)
     byts = stage_bytes(st, N, n_int, 8, 8)
     achieved = byts[dom] / (p32[dom] * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+    kname = STAGE_KERNEL.get(dom, dom)
+    roof = {"kernel": kname, "stage": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": counter_traffic(kname),
             "algorithmic_bytes": int(byts[dom]), "avg_ms": round(p32[dom], 4)}
+
+    serving = None
+    if args.serving_requests:
+        serving = serving_run(args.serving_requests)
+        log(f"serving {serving}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -239,6 +303,7 @@ def main():
         "setup_s": setup_s,
         "resident_gb": op.resident_bytes() / 1e9,
         "roofline": roof,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -141,9 +141,9 @@ def match_keys(keys_a, keys_b):
     return p
 
 
-def serving_pool(n_ops=6, seed=20509, n_range=(1.1, 1.5)):
+def serving_pool(n_ops=6, seed=20509, n_range=(1.05, 1.25), kappa_range=(4 * math.pi, 20 * math.pi)):
     """A pool of 2-D star scatterers R = 1 + a cos(k theta), a ~ U[0, 0.3],
-    k ~ U{3..7}, constant n ~ U[n_range], kappa ~ U[4 pi, 32 pi]; the lattice
+    k ~ U{3..7}, constant n ~ U[n_range], kappa ~ U[kappa_range]; the lattice
     spacing keeps about 12 points per interior wavelength (1/h a power of two
     in 64..256) and the cells below resonance (kappa H < pi sqrt 2)."""
     rng = np.random.default_rng(seed)
@@ -152,7 +152,7 @@ def serving_pool(n_ops=6, seed=20509, n_range=(1.1, 1.5)):
         a = float(rng.uniform(0.0, 0.3))
         k = int(rng.integers(3, 8))
         n = float(rng.uniform(*n_range))
-        kappa = float(rng.uniform(4 * math.pi, 32 * math.pi))
+        kappa = float(rng.uniform(*kappa_range))
         level = 64
         while level < 256 and (kappa * n / level > 2 * math.pi / 12 or kappa * 8 / level >= math.pi * math.sqrt(2)):
             level *= 2
