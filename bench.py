@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="requests in the serving measurement (0 skips it)")
+    ap.add_argument("--ortho", choices=["cgs1", "cgs2"], default="cgs1",
+                    help="Gram-Schmidt passes per Arnoldi step of the single-precision inner solves")
     ap.add_argument("--profile-solve", action="store_true",
                     help="profiling run: one single-precision-with-refinement solve only")
     ap.add_argument("--profile-applies", type=int, default=0,
@@ -181,10 +183,11 @@ def main():
         log(f"profile run done: {args.profile_applies} applies per precision, copy of {a.numel()} bytes")
         return
     g = cfg["gmres"]
+    ortho = binding.LS_ORTHO_CGS1 if args.ortho == "cgs1" else binding.LS_ORTHO_CGS2
     if args.profile_solve:
         x = torch.empty_like(f)
         info = op.solve(f, x, tol=1e-7, restart=g["restart"], max_iter=3000,
-                        mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-4, max_outer=30)
+                        mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-4, max_outer=30, ortho=ortho)
         log(f"profile solve {info}")
         return
     x_ref = torch.empty_like(f)
@@ -194,7 +197,7 @@ def main():
 
     def step(x):
         return op.solve(f, x, tol=1e-7, restart=g["restart"], max_iter=3000,
-                        mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-4, max_outer=30)
+                        mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-4, max_outer=30, ortho=ortho)
 
     x = torch.empty_like(f)
     for w in range(args.warmup):
@@ -288,7 +291,8 @@ def main():
         "dtype": "c64 bulk + c128 residual/Arnoldi",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: star R=1+0.3cos5t, kappa=32pi, n^2=1+0.8exp(-4|x|^2), "
-                               f"plane wave at 30deg, N={N}", "N": N, "nrhs": 1},
+                               f"plane wave at 30deg, N={N}", "N": N, "nrhs": 1,
+                   "solver": f"GMRES({g['restart']}), inner {args.ortho} tol 1e-4, outer FP64 residual tol 1e-7"},
         "err_vs_fp64_ref": err,
         "solve_p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
         "solve_p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),

@@ -159,6 +159,10 @@ ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec 
 
 typedef enum { LS_SOLVE_FP64 = 0, LS_SOLVE_FP32_REFINE = 1 } ls_solve_mode;
 
+/* Orthogonalisation of each new Krylov vector: classical Gram–Schmidt applied
+ * twice (default) or once. */
+typedef enum { LS_ORTHO_CGS2 = 0, LS_ORTHO_CGS1 = 1 } ls_ortho;
+
 typedef struct {
   double tol;           /* stop when ||f - A x|| <= tol ||f|| (per vector) */
   int max_iter;         /* total inner iterations per vector */
@@ -167,6 +171,7 @@ typedef struct {
   double inner_tol;     /* relative tolerance of each inner FP32 solve */
   int max_outer;        /* refinement steps */
   int use_x0;           /* nonzero: u_tot holds the initial guess */
+  ls_ortho ortho;       /* Gram–Schmidt passes (zero-initialised = CGS2) */
 } ls_solve_opts;
 
 typedef struct {
@@ -179,9 +184,10 @@ typedef struct {
 } ls_solve_stats;
 
 /* Solve (I + kappa^2 K_h) u = u_inc for nrhs right-hand sides (device
- * [nrhs][N] complex double) with matrix-free complex GMRES (Sec. 2): CGS2
- * Arnoldi in FP64 on the device.  FP32_REFINE runs the inner GMRES with the
- * single-precision apply and corrects with double-precision residuals.
+ * [nrhs][N] complex double) with matrix-free complex GMRES (Sec. 2),
+ * Arnoldi on the device.  FP64: basis, apply and Arnoldi in double.
+ * FP32_REFINE: inner GMRES solves with a single-precision basis and apply
+ * (reductions in double) correct the iterate from double-precision residuals.
  * Synchronous on return.  Scratch memory is allocated by the op on first use
  * and kept.  LS_ENOCONV still writes the best iterate and the stats. */
 ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs,

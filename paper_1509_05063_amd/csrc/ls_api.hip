@@ -51,6 +51,7 @@ struct ls_op {
   size_t gm_bytes = 0;
   std::complex<double>* pinned = nullptr;
   size_t pinned_n = 0;
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -115,6 +116,10 @@ void release(ls_op* op) {
   op->gm = nullptr;
   if (op->pinned) (void)hipHostFree(op->pinned);
   op->pinned = nullptr;
+  for (auto& e : op->gm_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
 }
 
 size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
@@ -506,22 +511,27 @@ struct Gm {
   int nrhs, m;
   int64_t N;
   hipStream_t st;
-  char* base;
-  double2 *V, *w, *r, *tmp64, *rout, *e, *hdev, *hdev2, *ndev, *partial;
+  double2 *V, *w, *r, *tmp64, *rout, *e, *hdev, *partial;
+  double2* hdev2[2];                       // per-step h1 | h2 | |w|^2, two slots (steps alternate)
   void *ws, *u32, *v32;
   double* sdev;
   size_t wsb;
   int nparts;
+  bool cgs2 = true;
   double apply_s = 0;
   int applies = 0;
-  std::complex<double>* pinned = nullptr;    // host copy of one iteration's h1 | h2 | |w|^2
+  std::complex<double>* pinned[2] = {nullptr, nullptr};   // host copies of the two slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
+
+size_t gm_slot(int nrhs, int m) { return (size_t)(m + 2) * nrhs * 2 + nrhs; }
 
 size_t gm_need(const ls_op* op, int nrhs, int m) {
   size_t N = op->N;
   size_t v = 16 * N * nrhs;
-  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 4 + 32 * nrhs + 16 * 512 * (size_t)(m + 2) * nrhs +
-             8 * nrhs + ws_bytes(op, nrhs, LS_C128) + 2 * 8 * N * nrhs + 16384;
+  size_t b = v * (m + 1) + 5 * v + 16 * (size_t)(m + 2) * nrhs * 2 + 2 * 16 * gm_slot(nrhs, m) +
+             16 * 1024 * (size_t)(m + 2) * nrhs + 8 * nrhs + ws_bytes(op, nrhs, LS_C128) + 2 * 8 * N * nrhs +
+             16384;
   return b;
 }
 
@@ -541,34 +551,41 @@ ls_status gm_setup(Gm& g) {
     return q;
   };
   size_t vb = 16 * (size_t)g.N * g.nrhs;
-  g.V = (double2*)take(vb * (g.m + 1));
+  g.V = (double2*)take(vb * (g.m + 1));    // complex double basis, or complex float basis in its first half
   g.w = (double2*)take(vb);
   g.r = (double2*)take(vb);
   g.tmp64 = (double2*)take(vb);
   g.rout = (double2*)take(vb);
   g.e = (double2*)take(vb);
   g.hdev = (double2*)take(16 * (size_t)(g.m + 2) * g.nrhs * 2);
-  // h1 | h2 | |w|^2 of one iteration, contiguous, copied back in one transfer
-  g.hdev2 = (double2*)take(16 * ((size_t)(g.m + 2) * g.nrhs * 2 + g.nrhs));
-  g.ndev = nullptr;
-  g.nparts = 512;
-  g.partial = (double2*)take(16 * 512 * (size_t)(g.m + 2) * g.nrhs);
+  const size_t slot = gm_slot(g.nrhs, g.m);
+  g.hdev2[0] = (double2*)take(16 * slot);
+  g.hdev2[1] = (double2*)take(16 * slot);
+  // workgroups of the reduction passes: about two elements per thread, at most 1024
+  g.nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (g.N + 511) / 512));
+  g.partial = (double2*)take(16 * 1024 * (size_t)(g.m + 2) * g.nrhs);
   g.sdev = (double*)take(8 * g.nrhs);
   g.wsb = ws_bytes(g.op, g.nrhs, LS_C128);
   g.ws = take(g.wsb);
   g.u32 = take(8 * (size_t)g.N * g.nrhs);
   g.v32 = take(8 * (size_t)g.N * g.nrhs);
-  if (!g.op->pinned || g.op->pinned_n < (size_t)(g.m + 2) * g.nrhs * 2 + g.nrhs) {
+  if (!g.op->pinned || g.op->pinned_n < 2 * slot) {
     if (g.op->pinned) (void)hipHostFree(g.op->pinned);
     g.op->pinned = nullptr;
-    g.op->pinned_n = (size_t)(g.m + 2) * g.nrhs * 2 + g.nrhs;
+    g.op->pinned_n = 2 * slot;
     if (hipHostMalloc((void**)&g.op->pinned, 16 * g.op->pinned_n) != hipSuccess) {
       g.op->pinned = nullptr;
       g.op->pinned_n = 0;
       return fail(LS_ENOMEM, "pinned host buffer");
     }
   }
-  g.pinned = g.op->pinned;
+  g.pinned[0] = g.op->pinned;
+  g.pinned[1] = g.op->pinned + slot;
+  for (int i = 0; i < 2; ++i) {
+    if (!g.op->gm_ev[i] && hipEventCreateWithFlags(&g.op->gm_ev[i], hipEventDisableTiming) != hipSuccess)
+      return fail(LS_EDEVICE, "hipEventCreate");
+    g.ev[i] = g.op->gm_ev[i];
+  }
   return LS_OK;
 }
 
@@ -589,6 +606,16 @@ ls_status gm_apply(Gm& g, const double2* x, double2* y, ls_prec prec) {
   return LS_OK;
 }
 
+// single-precision apply between single-precision vectors
+ls_status gm_apply32(Gm& g, const void* x, void* y) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipError_t e = lsx::launch_apply<float>(g.op->d32, x, y, g.nrhs, g.ws, g.st);
+  if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
+  g.apply_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  g.applies++;
+  return LS_OK;
+}
+
 // d[r][j] = <V_j, w>_r for j < nvec (vstride between basis vectors)
 ls_status gm_dots_host(Gm& g, const double2* Vb, const double2* w, int nvec, int64_t vstride,
                        std::vector<std::complex<double>>& out) {
@@ -599,34 +626,160 @@ ls_status gm_dots_host(Gm& g, const double2* Vb, const double2* w, int nvec, int
   return LS_OK;
 }
 
-// Solve A x = f (x holds the initial guess) to relative residual tol; returns
-// the number of iterations and per-rhs estimated relative residuals.
-ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, int max_iter, ls_prec prec,
-                int* iters, std::vector<double>& relres) {
+// Hessenberg matrix of one restart cycle per right-hand side (column-major
+// (m+1) x m), reduced to triangular form by Givens rotations as columns arrive.
+struct Hessenberg {
+  int R = 0, m = 0;
+  std::vector<std::complex<double>> H, cs, sn, gv;
+  std::vector<int> kdone;     // Krylov dimension at which each rhs met its tolerance (-1: not yet)
+
+  void reset(int R_, int m_, const std::vector<double>& beta, const std::vector<double>& relres, double tol) {
+    R = R_;
+    m = m_;
+    H.assign((size_t)R * (m + 1) * m, 0.0);
+    cs.assign((size_t)R * m, 0.0);
+    sn.assign((size_t)R * m, 0.0);
+    gv.assign((size_t)R * (m + 1), 0.0);
+    kdone.assign(R, -1);
+    for (int r = 0; r < R; ++r) {
+      gv[(size_t)r * (m + 1)] = beta[r];
+      if (relres[r] <= tol) kdone[r] = 0;
+    }
+  }
+
+  // column k of rhs r: h_j = h1_j + h2_j (h2 may be null), h_{k+1} = hn.
+  // Returns |residual| estimate after the rotation.
+  double column(int r, int k, const std::complex<double>* h1, const std::complex<double>* h2, double hn) {
+    std::complex<double>* col = &H[((size_t)r * m + k) * (m + 1)];
+    for (int j = 0; j <= k; ++j) col[j] = h2 ? h1[j] + h2[j] : h1[j];
+    col[k + 1] = hn;
+    std::complex<double>* c = &cs[(size_t)r * m];
+    std::complex<double>* sv = &sn[(size_t)r * m];
+    for (int j = 0; j < k; ++j) {
+      std::complex<double> t = c[j] * col[j] + sv[j] * col[j + 1];
+      col[j + 1] = -std::conj(sv[j]) * col[j] + std::conj(c[j]) * col[j + 1];
+      col[j] = t;
+    }
+    double den = std::sqrt(std::norm(col[k]) + std::norm(col[k + 1]));
+    c[k] = den > 0 ? std::conj(col[k]) / den : 1.0;
+    sv[k] = den > 0 ? std::conj(col[k + 1]) / den : 0.0;
+    col[k] = den;
+    col[k + 1] = 0.0;
+    std::complex<double>* gg = &gv[(size_t)r * (m + 1)];
+    gg[k + 1] = -std::conj(sv[k]) * gg[k];
+    gg[k] = c[k] * gg[k];
+    return std::abs(gg[k + 1]);
+  }
+
+  // coefficients y[r][0..k) of the cycle's update (each rhs uses its own dimension)
+  std::vector<std::complex<double>> solve(int k) const {
+    std::vector<std::complex<double>> y((size_t)R * std::max(k, 1), 0.0);
+    for (int r = 0; r < R; ++r) {
+      int kk = kdone[r] >= 0 ? kdone[r] : k;
+      const std::complex<double>* Hr = &H[(size_t)r * m * (m + 1)];
+      const std::complex<double>* gg = &gv[(size_t)r * (m + 1)];
+      std::complex<double>* yr = &y[(size_t)r * k];
+      for (int i = kk - 1; i >= 0; --i) {
+        std::complex<double> sacc = gg[i];
+        for (int j = i + 1; j < kk; ++j) sacc -= Hr[(size_t)j * (m + 1) + i] * yr[j];
+        yr[i] = sacc / Hr[(size_t)i * (m + 1) + i];
+      }
+    }
+    return y;
+  }
+};
+
+// Solve A x = f (x holds the initial guess; f and x complex double) to
+// relative residual tol.  F32: Krylov basis, work vector and operator apply
+// in single precision (reductions and the update of x in double); otherwise
+// everything in double.  The orthogonalisation is classical Gram–Schmidt,
+// applied twice when g.cgs2.  Step k+1 is queued on the stream before the
+// host waits for the Hessenberg column of step k, so the device never waits
+// for the host inside a cycle; when step k meets the tolerance the queued
+// step is discarded.
+extern "C++" {
+template <bool F32>
+ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, int max_iter, int* iters,
+                std::vector<double>& relres) {
   const int R = g.nrhs, m = g.m;
   const int64_t N = g.N;
   const int64_t vstride = N * R;          // distance between basis vectors (elements)
+  float2* V32 = (float2*)g.V;
+  float2* w32 = (float2*)g.w;
   std::vector<std::complex<double>> dd;
   std::vector<double> fnorm(R);
   ls_status s = gm_dots_host(g, f, f, 1, 0, dd);
   if (s) return s;
   for (int r = 0; r < R; ++r) fnorm[r] = std::sqrt(std::max(0.0, dd[r].real()));
   relres.assign(R, 1.0);
+  Hessenberg hs;
   int it = 0;
   bool first = true;
-  while (true) {
-    // r = f - A x
-    if (x_zero && first) {
-      HIPCHK(hipMemcpyAsync(g.r, f, 16 * (size_t)N * R, hipMemcpyDeviceToDevice, g.st));
+
+  // one Arnoldi step: w = A V_k, orthogonalise against V_0..V_k, V_{k+1} = w / |w|,
+  // then h1 | h2 | |w|^2 to the host slot (k & 1)
+  auto step = [&](int k) -> ls_status {
+    const int nv = k + 1;
+    const size_t nh = (size_t)nv * R;
+    double2* d1 = g.hdev2[k & 1];
+    double2* d2 = d1 + nh;
+    double2* dn = d1 + 2 * nh;
+    ls_status st;
+    if (F32) {
+      st = gm_apply32(g, V32 + (size_t)k * vstride, w32);
+      if (st) return st;
+      float2* vnext = V32 + (size_t)(k + 1) * vstride;
+      HIPCHK(lsx::gm32_dots(V32, w32, g.partial, d1, nv, nv, N, R, vstride, g.nparts, g.st));
+      if (g.cgs2) {
+        HIPCHK(lsx::gm32_update(V32, w32, w32, d1, nv, N, R, vstride, g.nparts, g.partial, nullptr, g.st));
+        HIPCHK(lsx::gm32_dots(V32, w32, g.partial, d2, nv, nv, N, R, vstride, g.nparts, g.st));
+        HIPCHK(lsx::gm32_update(V32, w32, vnext, d2, nv, N, R, vstride, g.nparts, g.partial, dn, g.st));
+      } else {
+        HIPCHK(lsx::gm32_update(V32, w32, vnext, d1, nv, N, R, vstride, g.nparts, g.partial, dn, g.st));
+      }
+      HIPCHK(lsx::gm_inv_norm(dn, g.sdev, R, g.st));
+      HIPCHK(lsx::gm32_scale(vnext, g.sdev, N, R, g.st));
     } else {
-      s = gm_apply(g, x, g.w, prec);
+      st = gm_apply(g, g.V + (size_t)k * vstride, g.w, LS_C128);
+      if (st) return st;
+      HIPCHK(lsx::gm_cgs(g.V, g.w, nullptr, g.partial, d1, nv, N, R, vstride, g.nparts, 0, g.st));
+      if (g.cgs2) HIPCHK(lsx::gm_cgs(g.V, g.w, d1, g.partial, d2, nv, N, R, vstride, g.nparts, 1, g.st));
+      HIPCHK(lsx::gm_cgs(g.V, g.w, g.cgs2 ? d2 : d1, g.partial, dn, nv, N, R, vstride, g.nparts, 2, g.st));
+      HIPCHK(lsx::gm_inv_norm(dn, g.sdev, R, g.st));
+      HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
+    }
+    HIPCHK(hipMemcpyAsync(g.pinned[k & 1], d1, 16 * (2 * nh + R), hipMemcpyDeviceToHost, g.st));
+    HIPCHK(hipEventRecord(g.ev[k & 1], g.st));
+    return LS_OK;
+  };
+
+  while (true) {
+    // r = f - A x, V_0 = r / |r|
+    std::vector<double> beta(R);
+    if (F32) {
+      const float2* ax = nullptr;
+      if (!(x_zero && first)) {
+        HIPCHK(lsx::gm_to_f32(x, g.u32, N * R, g.st));
+        s = gm_apply32(g, g.u32, w32);
+        if (s) return s;
+        ax = w32;
+      }
+      HIPCHK(lsx::gm32_resid(f, ax, V32, N, R, g.nparts, g.partial, g.hdev, g.st));
+      dd.resize(R);
+      HIPCHK(hipMemcpyAsync(dd.data(), g.hdev, 16 * R, hipMemcpyDeviceToHost, g.st));
+      HIPCHK(hipStreamSynchronize(g.st));
+    } else {
+      if (x_zero && first) {
+        HIPCHK(hipMemcpyAsync(g.r, f, 16 * (size_t)N * R, hipMemcpyDeviceToDevice, g.st));
+      } else {
+        s = gm_apply(g, x, g.w, LS_C128);
+        if (s) return s;
+        HIPCHK(lsx::gm_sub(f, g.w, g.r, N * R, g.st));
+      }
+      s = gm_dots_host(g, g.r, g.r, 1, 0, dd);
       if (s) return s;
-      HIPCHK(lsx::gm_sub(f, g.w, g.r, N * R, g.st));
     }
     first = false;
-    s = gm_dots_host(g, g.r, g.r, 1, 0, dd);
-    if (s) return s;
-    std::vector<double> beta(R);
     bool all = true;
     for (int r = 0; r < R; ++r) {
       beta[r] = std::sqrt(std::max(0.0, dd[r].real()));
@@ -637,84 +790,49 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
     std::vector<double> inv(R);
     for (int r = 0; r < R; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
     HIPCHK(hipMemcpyAsync(g.sdev, inv.data(), 8 * R, hipMemcpyHostToDevice, g.st));
-    HIPCHK(lsx::gm_scale_copy(g.r, g.V, g.sdev, N, R, g.st));
-    // Hessenberg per rhs, column-major (m+1) x m, Givens state
-    std::vector<std::complex<double>> Hm((size_t)R * (m + 1) * m, 0.0), cs((size_t)R * m), sn((size_t)R * m),
-        gv((size_t)R * (m + 1), 0.0);
-    for (int r = 0; r < R; ++r) gv[(size_t)r * (m + 1)] = beta[r];
-    std::vector<int> kdone(R, -1);
-    for (int r = 0; r < R; ++r)
-      if (relres[r] <= tol) kdone[r] = 0;
+    if (F32)
+      HIPCHK(lsx::gm32_scale(V32, g.sdev, N, R, g.st));
+    else
+      HIPCHK(lsx::gm_scale_copy(g.r, g.V, g.sdev, N, R, g.st));
+    hs.reset(R, m, beta, relres, tol);
     int k = 0;
+    s = step(0);
+    if (s) return s;
     for (; k < m && it < max_iter; ++k) {
-      double2* vk = g.V + (size_t)k * vstride;
-      s = gm_apply(g, vk, g.w, prec);
-      if (s) return s;
+      if (k + 1 < m && it + 1 < max_iter) {
+        s = step(k + 1);
+        if (s) return s;
+      }
+      HIPCHK(hipEventSynchronize(g.ev[k & 1]));
       ++it;
-      // CGS2 on the device: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2,
-      // |w|^2, V_{k+1} = w / |w|; one host synchronisation to read h1, h2, |w|
       const size_t nh = (size_t)(k + 1) * R;
-      double2* d1 = g.hdev2;
-      double2* d2 = g.hdev2 + nh;
-      double2* dn_dev = g.hdev2 + 2 * nh;
-      HIPCHK(lsx::gm_cgs(g.V, g.w, nullptr, g.partial, d1, k + 1, N, R, vstride, g.nparts, 0, g.st));
-      HIPCHK(lsx::gm_cgs(g.V, g.w, d1, g.partial, d2, k + 1, N, R, vstride, g.nparts, 1, g.st));
-      HIPCHK(lsx::gm_cgs(g.V, g.w, d2, g.partial, dn_dev, k + 1, N, R, vstride, g.nparts, 2, g.st));
-      HIPCHK(lsx::gm_inv_norm(dn_dev, g.sdev, R, g.st));
-      HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
-      HIPCHK(hipMemcpyAsync(g.pinned, d1, 16 * (2 * nh + R), hipMemcpyDeviceToHost, g.st));
-      HIPCHK(hipStreamSynchronize(g.st));
-      const std::complex<double>* h1 = g.pinned;
-      const std::complex<double>* h2 = g.pinned + nh;
-      const std::complex<double>* dn = g.pinned + 2 * nh;
+      const std::complex<double>* h1 = g.pinned[k & 1];
+      const std::complex<double>* h2 = g.cgs2 ? h1 + nh : nullptr;
+      const std::complex<double>* dn = h1 + 2 * nh;
       bool all_done = true;
       for (int r = 0; r < R; ++r) {
         double hn = std::sqrt(std::max(0.0, dn[r].real()));
-        std::complex<double>* col = &Hm[((size_t)r * m + k) * (m + 1)];
-        for (int j = 0; j <= k; ++j) col[j] = h1[(size_t)r * (k + 1) + j] + h2[(size_t)r * (k + 1) + j];
-        col[k + 1] = hn;
-        std::complex<double>* c = &cs[(size_t)r * m];
-        std::complex<double>* sv = &sn[(size_t)r * m];
-        for (int j = 0; j < k; ++j) {
-          std::complex<double> t = c[j] * col[j] + sv[j] * col[j + 1];
-          col[j + 1] = -std::conj(sv[j]) * col[j] + std::conj(c[j]) * col[j + 1];
-          col[j] = t;
-        }
-        double den = std::sqrt(std::norm(col[k]) + std::norm(col[k + 1]));
-        c[k] = den > 0 ? std::conj(col[k]) / den : 1.0;
-        sv[k] = den > 0 ? std::conj(col[k + 1]) / den : 0.0;
-        col[k] = den;
-        col[k + 1] = 0.0;
-        std::complex<double>* gg = &gv[(size_t)r * (m + 1)];
-        gg[k + 1] = -std::conj(sv[k]) * gg[k];
-        gg[k] = c[k] * gg[k];
-        double est = fnorm[r] > 0 ? std::abs(gg[k + 1]) / fnorm[r] : 0.0;
-        if (kdone[r] < 0 && (est <= tol || hn == 0.0)) kdone[r] = k + 1;
-        if (kdone[r] < 0) all_done = false;
+        double est = hs.column(r, k, h1 + (size_t)r * (k + 1), h2 ? h2 + (size_t)r * (k + 1) : nullptr, hn);
+        est = fnorm[r] > 0 ? est / fnorm[r] : 0.0;
+        if (hs.kdone[r] < 0 && (est <= tol || hn == 0.0)) hs.kdone[r] = k + 1;
+        if (hs.kdone[r] < 0) all_done = false;
       }
       if (all_done) { ++k; break; }
     }
-    // x += V y  (each rhs uses its own Krylov dimension)
-    std::vector<std::complex<double>> y((size_t)R * m, 0.0);
-    for (int r = 0; r < R; ++r) {
-      int kk = kdone[r] >= 0 ? kdone[r] : k;
-      const std::complex<double>* Hr = &Hm[(size_t)r * m * (m + 1)];
-      const std::complex<double>* gg = &gv[(size_t)r * (m + 1)];
-      for (int i = kk - 1; i >= 0; --i) {
-        std::complex<double> sacc = gg[i];
-        for (int j = i + 1; j < kk; ++j) sacc -= Hr[(size_t)j * (m + 1) + i] * y[(size_t)r * m + j];
-        y[(size_t)r * m + i] = sacc / Hr[(size_t)i * (m + 1) + i];
-      }
-    }
-    std::vector<std::complex<double>> yk((size_t)R * std::max(k, 1), 0.0);
-    for (int r = 0; r < R; ++r)
-      for (int j = 0; j < k; ++j) yk[(size_t)r * k + j] = y[(size_t)r * m + j];
+    // x += V y
+    std::vector<std::complex<double>> yk = hs.solve(k);
     HIPCHK(hipMemcpyAsync(g.hdev, yk.data(), 16 * yk.size(), hipMemcpyHostToDevice, g.st));
-    if (k > 0) HIPCHK(lsx::gm_axpy_combo(x, g.V, g.hdev, k, N, R, vstride, g.st));
+    if (k > 0) {
+      if (F32)
+        HIPCHK(lsx::gm32_axpy_combo(x, V32, g.hdev, k, N, R, vstride, g.st));
+      else
+        HIPCHK(lsx::gm_axpy_combo(x, g.V, g.hdev, k, N, R, vstride, g.st));
+    }
   }
   *iters = it;
   return LS_OK;
 }
+}  // extern "C++"
 
 }  // namespace
 
@@ -729,6 +847,7 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
   g.m = opts->restart;
   g.N = op->N;
   g.st = (hipStream_t)stream;
+  g.cgs2 = opts->ortho != LS_ORTHO_CGS1;
   ls_status s = gm_setup(g);
   if (s) return s;
   const double2* f = (const double2*)u_inc;
@@ -738,7 +857,7 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
   int iters = 0, outer = 0;
   std::vector<double> rel;
   if (opts->mode == LS_SOLVE_FP64) {
-    s = gmres(g, f, x, !opts->use_x0, opts->tol, opts->max_iter, LS_C128, &iters, rel);
+    s = gmres<false>(g, f, x, !opts->use_x0, opts->tol, opts->max_iter, &iters, rel);
     if (s) return s;
   } else {
     // FP64 residual, FP32 inner solves, x += e
@@ -769,7 +888,7 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
       HIPCHK(hipMemsetAsync(g.e, 0, 16 * (size_t)n, g.st));
       int it = 0;
       std::vector<double> rr;
-      s = gmres(g, g.rout, g.e, true, opts->inner_tol, opts->max_iter - total, LS_C64, &it, rr);
+      s = gmres<true>(g, g.rout, g.e, true, opts->inner_tol, opts->max_iter - total, &it, rr);
       if (s) return s;
       total += it;
       HIPCHK(lsx::gm_add(x, g.e, n, g.st));

@@ -846,6 +846,187 @@ __global__ void k_to_f64(const float2* __restrict__ a, double2* __restrict__ b, 
 }
 
 // ---------------------------------------------------------------------------
+// GMRES helpers with a single-precision Krylov basis (complex float vectors;
+// every reduction is finished in double).  Partial sums per workgroup go to
+// partial[(r * nv + j) * gridDim.x + block] and are folded by k_fold.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// d_j = <V_j, w> (conj(V_j) . w) for j < nv <= NV <= 32.  Each thread keeps
+// its own partial sums; the workgroup reduces them by a transpose through LDS
+// (16 basis vectors at a time) rather than by cross-lane shuffles.
+template <int NV>
+__global__ void __launch_bounds__(256) k_dots32(const float2* __restrict__ Vb, const float2* __restrict__ w,
+                                                double2* __restrict__ partial, int nv, int64_t N,
+                                                int64_t vstride) {
+  static_assert(NV <= 32, "at most 32 basis vectors per pass");
+  __shared__ float buf[32][264];
+  const int r = blockIdx.y;
+  const float2* wr = w + (int64_t)r * N;
+  const float2* V0 = Vb + (int64_t)r * N;
+  float ax[NV], ay[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) ax[j] = ay[j] = 0.f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const float2 b = wr[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      if (j < nv) {
+        const float2 a = V0[j * vstride + i];
+        ax[j] += a.x * b.x + a.y * b.y;
+        ay[j] += a.x * b.y - a.y * b.x;
+      }
+    }
+  }
+  const int t = threadIdx.x;
+  const int o = t >> 3, sub = t & 7;       // row o of the transpose (vector h0 + o/2, part o%2), 8 lanes per row
+#pragma unroll
+  for (int h0 = 0; h0 < NV; h0 += 16) {
+    if (h0 < nv) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (h0 + q < NV) {
+          buf[2 * q][t] = ax[h0 + q < NV ? h0 + q : 0];
+          buf[2 * q + 1][t] = ay[h0 + q < NV ? h0 + q : 0];
+        }
+      }
+      __syncthreads();
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < 32; ++q) acc += (double)buf[o][q * 8 + sub];
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      const int j = h0 + (o >> 1);
+      if (sub == 0 && j < nv) {
+        double* pp = (double*)&partial[((int64_t)r * nv + j) * gridDim.x + blockIdx.x];
+        pp[o & 1] = acc;
+      }
+    }
+  }
+}
+
+// dst = src - sum_{j < nv} h[r * ldh + j] V_j, nv <= NV <= 32 (src may equal dst); when
+// partial != nullptr also |dst|^2 per workgroup (partial[r * gridDim.x + block])
+template <int NV>
+__global__ void __launch_bounds__(256) k_update32(const float2* __restrict__ Vb, const float2* src, float2* dst,
+                                                  const double2* __restrict__ h, int nv, int ldh, int64_t N,
+                                                  int64_t vstride, double2* __restrict__ partial) {
+  __shared__ float2 hs[NV];
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if ((int)threadIdx.x < nv) {
+    const double2 t = h[(int64_t)r * ldh + threadIdx.x];
+    hs[threadIdx.x] = make_float2((float)t.x, (float)t.y);
+  }
+  __syncthreads();
+  const float2* sr = src + (int64_t)r * N;
+  float2* dr = dst + (int64_t)r * N;
+  const float2* V0 = Vb + (int64_t)r * N;
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    float2 acc = sr[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      if (j < nv) {
+        const float2 a = V0[j * vstride + i];
+        const float2 c = hs[j];
+        acc.x -= c.x * a.x - c.y * a.y;
+        acc.y -= c.x * a.y + c.y * a.x;
+      }
+    }
+    dr[i] = acc;
+    nrm += (double)acc.x * acc.x + (double)acc.y * acc.y;
+  }
+  if (partial == nullptr) return;
+  nrm = wave_sum(nrm);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+
+// out[r * ldo + off + j] = sum_p partial[(r * nv + j) * nparts + p], one workgroup per output
+__global__ void __launch_bounds__(256) k_fold(const double2* __restrict__ partial, double2* __restrict__ out,
+                                              int nparts, int nv, int ldo, int off) {
+  __shared__ double rx[4], ry[4];
+  const int o = blockIdx.x;
+  double sx = 0.0, sy = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+    const double2 v = partial[(int64_t)o * nparts + p];
+    sx += v.x;
+    sy += v.y;
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  if ((threadIdx.x & 63) == 0) {
+    rx[threadIdx.x >> 6] = sx;
+    ry[threadIdx.x >> 6] = sy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int r = o / nv, j = o % nv;
+    out[(int64_t)r * ldo + off + j] = make_double2(rx[0] + rx[1] + rx[2] + rx[3], ry[0] + ry[1] + ry[2] + ry[3]);
+  }
+}
+
+// dst = f - a (a may be null: dst = f), rounded to single; |f - a|^2 in double per workgroup
+__global__ void __launch_bounds__(256) k_resid32(const double2* __restrict__ f, const float2* __restrict__ a,
+                                                 float2* __restrict__ dst, int64_t N, double2* __restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    double2 t = f[(int64_t)r * N + i];
+    if (a) {
+      const float2 b = a[(int64_t)r * N + i];
+      t.x -= b.x;
+      t.y -= b.y;
+    }
+    dst[(int64_t)r * N + i] = make_float2((float)t.x, (float)t.y);
+    nrm += t.x * t.x + t.y * t.y;
+  }
+  nrm = wave_sum(nrm);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[(int64_t)r * gridDim.x + blockIdx.x] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+
+__global__ void k_scale32(float2* __restrict__ v, const double* __restrict__ s, int64_t N) {
+  const int r = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const float f = (float)s[r];
+  float2 a = v[(int64_t)r * N + i];
+  a.x *= f;
+  a.y *= f;
+  v[(int64_t)r * N + i] = a;
+}
+
+// x_r += sum_j y[r * nvec + j] V_j (basis in single precision, sum in double)
+__global__ void k_axpy_combo32(double2* __restrict__ x, const float2* __restrict__ Vb, const double2* __restrict__ y,
+                               int nvec, int64_t N, int64_t vstride) {
+  const int r = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double2 acc = x[(int64_t)r * N + i];
+  for (int j = 0; j < nvec; ++j) {
+    const double2 c = y[r * nvec + j];
+    const float2 a = Vb[j * vstride + (int64_t)r * N + i];
+    acc.x += c.x * a.x - c.y * a.y;
+    acc.y += c.x * a.y + c.y * a.x;
+  }
+  x[(int64_t)r * N + i] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1043,6 +1224,72 @@ hipError_t gm_to_f32(const void* a, void* b, int64_t n, hipStream_t st) {
 }
 hipError_t gm_to_f64(const void* a, void* b, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const float2*)a, (double2*)b, n);
+  return hipGetLastError();
+}
+
+// single-precision-basis launchers
+namespace {
+int nv_bucket(int nv) { return nv <= 8 ? 8 : nv <= 16 ? 16 : 32; }
+}  // namespace
+
+hipError_t gm32_dots(const void* Vb, const void* w, void* partial, void* out, int nvec, int ldo, int64_t N,
+                     int nrhs, int64_t vstride, int nparts, hipStream_t st) {
+  // at most 32 basis vectors per pass: 64 accumulators per thread keep six waves per SIMD resident
+  for (int c0 = 0; c0 < nvec; c0 += 32) {
+    const int nv = nvec - c0 < 32 ? nvec - c0 : 32;
+    const float2* V = (const float2*)Vb + (int64_t)c0 * vstride;
+    dim3 g(nparts, nrhs);
+    switch (nv_bucket(nv)) {
+      case 8: hipLaunchKernelGGL(k_dots32<8>, g, dim3(256), 0, st, V, (const float2*)w, (double2*)partial, nv, N, vstride); break;
+      case 16: hipLaunchKernelGGL(k_dots32<16>, g, dim3(256), 0, st, V, (const float2*)w, (double2*)partial, nv, N, vstride); break;
+      default: hipLaunchKernelGGL(k_dots32<32>, g, dim3(256), 0, st, V, (const float2*)w, (double2*)partial, nv, N, vstride); break;
+    }
+    hipLaunchKernelGGL(k_fold, dim3(nv * nrhs), dim3(256), 0, st, (const double2*)partial, (double2*)out, nparts, nv,
+                       ldo, c0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t gm32_update(const void* Vb, const void* src, void* dst, const void* h, int nvec, int64_t N, int nrhs,
+                       int64_t vstride, int nparts, void* partial, void* norm_out, hipStream_t st) {
+  // at most 32 basis vectors per pass (64 values per thread in flight at full occupancy)
+  const float2* in = (const float2*)src;
+  for (int c0 = 0; c0 < nvec; c0 += 32) {
+    const int nv = nvec - c0 < 32 ? nvec - c0 : 32;
+    const bool last = c0 + 32 >= nvec;
+    const float2* V = (const float2*)Vb + (int64_t)c0 * vstride;
+    const double2* hh = (const double2*)h + c0;
+    double2* part = (last && norm_out) ? (double2*)partial : nullptr;
+    dim3 g(nparts, nrhs);
+    switch (nv_bucket(nv)) {
+      case 8: hipLaunchKernelGGL(k_update32<8>, g, dim3(256), 0, st, V, in, (float2*)dst, hh, nv, nvec, N, vstride, part); break;
+      case 16: hipLaunchKernelGGL(k_update32<16>, g, dim3(256), 0, st, V, in, (float2*)dst, hh, nv, nvec, N, vstride, part); break;
+      default: hipLaunchKernelGGL(k_update32<32>, g, dim3(256), 0, st, V, in, (float2*)dst, hh, nv, nvec, N, vstride, part); break;
+    }
+    in = (const float2*)dst;
+  }
+  if (norm_out)
+    hipLaunchKernelGGL(k_fold, dim3(nrhs), dim3(256), 0, st, (const double2*)partial, (double2*)norm_out, nparts, 1, 1, 0);
+  return hipGetLastError();
+}
+
+hipError_t gm32_resid(const void* f, const void* a, void* dst, int64_t N, int nrhs, int nparts, void* partial,
+                      void* norm_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid32, dim3(nparts, nrhs), dim3(256), 0, st, (const double2*)f, (const float2*)a,
+                     (float2*)dst, N, (double2*)partial);
+  hipLaunchKernelGGL(k_fold, dim3(nrhs), dim3(256), 0, st, (const double2*)partial, (double2*)norm_out, nparts, 1, 1, 0);
+  return hipGetLastError();
+}
+
+hipError_t gm32_scale(void* v, const double* s, int64_t N, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale32, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, (float2*)v, s, N);
+  return hipGetLastError();
+}
+
+hipError_t gm32_axpy_combo(void* x, const void* Vb, const void* y, int nvec, int64_t N, int nrhs, int64_t vstride,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_combo32, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, (double2*)x,
+                     (const float2*)Vb, (const double2*)y, nvec, N, vstride);
   return hipGetLastError();
 }
 

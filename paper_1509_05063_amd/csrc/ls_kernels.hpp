@@ -54,4 +54,18 @@ hipError_t gm_add(void* x, const void* e, int64_t n, hipStream_t st);
 hipError_t gm_to_f32(const void* a, void* b, int64_t n, hipStream_t st);
 hipError_t gm_to_f64(const void* a, void* b, int64_t n, hipStream_t st);
 
+// GMRES building blocks with a single-precision basis (complex float
+// vectors, reductions in double).  dots: out[r * ldo + j] = <V_j, w_r>.
+// update: dst = src - sum_j h[r * nvec + j] V_j, |dst|^2 to norm_out[r] when
+// norm_out != nullptr.  resid: dst = f - a (a may be null), |f - a|^2.
+hipError_t gm32_dots(const void* Vb, const void* w, void* partial, void* out, int nvec, int ldo, int64_t N,
+                     int nrhs, int64_t vstride, int nparts, hipStream_t st);
+hipError_t gm32_update(const void* Vb, const void* src, void* dst, const void* h, int nvec, int64_t N, int nrhs,
+                       int64_t vstride, int nparts, void* partial, void* norm_out, hipStream_t st);
+hipError_t gm32_resid(const void* f, const void* a, void* dst, int64_t N, int nrhs, int nparts, void* partial,
+                      void* norm_out, hipStream_t st);
+hipError_t gm32_scale(void* v, const double* s, int64_t N, int nrhs, hipStream_t st);
+hipError_t gm32_axpy_combo(void* x, const void* Vb, const void* y, int nvec, int64_t N, int nrhs, int64_t vstride,
+                           hipStream_t st);
+
 }  // namespace lsx

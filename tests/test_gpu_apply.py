@@ -89,8 +89,9 @@ def test_apply_is_deterministic(disc):
     assert torch.equal(v1, v2)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_solve_matches_oracle_lu(disc, mode):
+@pytest.mark.parametrize("mode,ortho,restart", [(0, 0, 100), (1, 0, 100), (0, 1, 100), (1, 1, 100), (0, 0, 7),
+                                                (1, 0, 7)])
+def test_solve_matches_oracle_lu(disc, mode, ortho, restart):
     import torch
     from oracle.mie import mie2d_total
     cfg, op, orc, A, p, xy, key = disc
@@ -98,11 +99,11 @@ def test_solve_matches_oracle_lu(disc, mode):
     u_or = np.linalg.solve(A, f_or)
     f = torch.tensor(_to_lib(f_or, p, op.N), dtype=torch.complex128, device="cuda")
     x = torch.empty_like(f)
-    st = op.solve(f, x, tol=1e-10, restart=100, max_iter=500, mode=mode, inner_tol=1e-5)
+    st = op.solve(f, x, tol=1e-10, restart=restart, max_iter=2000, mode=mode, inner_tol=1e-5, ortho=ortho)
     u = x.cpu().numpy()[p]
     err = np.linalg.norm(u - u_or) / np.linalg.norm(u_or)
     mie = mie2d_total(cfg["kappa"], 1.5, 1.0, orc.pts["x"] * (1 - 1e-15))
     emie = np.linalg.norm(u - mie) / np.linalg.norm(mie)
-    print(f"solve mode {mode}: {st} vs LU {err:.3e} vs Mie {emie:.3e}", flush=True)
+    print(f"solve mode {mode} ortho {ortho} restart {restart}: {st} vs LU {err:.3e} vs Mie {emie:.3e}", flush=True)
     assert err < 1e-8
     assert emie < 5e-3

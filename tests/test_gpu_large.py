@@ -73,6 +73,15 @@ def test_benchmark_size_solve_modes_agree(star32):
     x_or = x64.cpu().numpy()[p]
     r = orc.A_rows(rows) @ x_or - plane_wave(cfg, orc.pts["x"][rows], cfg["incidence"][0])
     assert np.abs(r).max() < 1e-7, np.abs(r).max()
+    # longer restart cycles (more than 64 basis vectors: chunked passes) and
+    # single Gram-Schmidt reach the same solution
+    for restart, ortho in ((80, binding.LS_ORTHO_CGS2), (60, binding.LS_ORTHO_CGS1)):
+        for mode in (binding.LS_SOLVE_FP64, binding.LS_SOLVE_FP32_REFINE):
+            xo = torch.empty_like(f)
+            so = op.solve(f, xo, tol=1e-8, restart=restart, max_iter=3000, mode=mode, inner_tol=1e-4, ortho=ortho)
+            e = (torch.linalg.norm(xo - x64) / torch.linalg.norm(x64)).item()
+            print(f"restart {restart} ortho {ortho} mode {mode}: {so} diff {e:.3e}", flush=True)
+            assert so["converged"] == 1 and e < 1e-6
 
 
 def test_multi_rhs_batch_matches_single_and_oracle():
