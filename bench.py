@@ -55,8 +55,8 @@ def stage_bytes(st, N, n_int, s, s_w):
 
 # single-precision kernel of each one-kernel stage (the FFT stages run several)
 STAGE_KERNEL = {"project": "k_project<float>", "fill": "k_fill<float>", "spectral": "k_spectral<float>",
-                "interp": "k_interp<float>", "near_shared": "k_near_shared_mfma<float,2>",
-                "near_csr": "k_near_csr<float>"}
+                "interp": "k_interp<float>", "near_shared": "k_near_shared_mfma_db",
+                "near_csr": "k_near_csr4"}
 
 
 def counter_traffic(kernel, summary=os.path.join(ROOT, "profiles", "apply_star_k32pi.md")):

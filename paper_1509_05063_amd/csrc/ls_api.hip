@@ -334,7 +334,17 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     UP(upload_c(op, ToffT, &a.Toff, &b.Toff));
   }
   UP(upload_c(op, h.Wsh, &a.Wsh, &b.Wsh));
-  UP(upload_c(op, h.vals, &a.vals, &b.vals));
+  // near-field rows stored padded to a multiple of four entries (zero
+  // weights, column offset 0), so a lane can take four at a time
+  const size_t nrow = h.rows.size();
+  std::vector<int64_t> prow(nrow + 1, 0);
+  for (size_t r = 0; r < nrow; ++r) prow[r + 1] = prow[r] + ((h.rowptr[r + 1] - h.rowptr[r] + 3) & ~int64_t(3));
+  {
+    std::vector<cd> pv((size_t)prow[nrow], cd(0.0, 0.0));
+    for (size_t r = 0; r < nrow; ++r)
+      std::copy(h.vals.begin() + h.rowptr[r], h.vals.begin() + h.rowptr[r + 1], pv.begin() + prow[r]);
+    UP(upload_c(op, pv, &a.vals, &b.vals));
+  }
   {
     std::vector<float> f(h.cw.begin(), h.cw.end()), g2(h.dw.begin(), h.dw.end());
     UP(upload_i(op, h.cw, &a.cw));
@@ -369,18 +379,20 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     }
     UP(upload_i(op, cbase, &a.colbase));
     if (narrow) {
-      std::vector<uint16_t> coff(h.cols.size());
+      std::vector<uint16_t> coff((size_t)prow[nr], 0);
       for (size_t r = 0; r < nr; ++r)
-        for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k) coff[k] = (uint16_t)(h.cols[k] - cbase[r]);
+        for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k)
+          coff[prow[r] + (k - h.rowptr[r])] = (uint16_t)(h.cols[k] - cbase[r]);
       UP(upload_i(op, coff, &a.coloff));
     } else {
-      std::vector<int32_t> c32(h.cols.size());
+      std::vector<int32_t> c32((size_t)prow[nr], 0);
       for (size_t r = 0; r < nr; ++r)
-        for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k) c32[k] = h.cols[k] - cbase[r];
+        for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k)
+          c32[prow[r] + (k - h.rowptr[r])] = h.cols[k] - cbase[r];
       UP(upload_i(op, c32, &a.cols32));
     }
   }
-  UP(upload_i(op, h.rowptr, &a.rowptr));
+  UP(upload_i(op, prow, &a.rowptr));
   b.slot_map = a.slot_map;
   b.cell_start = a.cell_start;
   b.cell_nint = a.cell_nint;

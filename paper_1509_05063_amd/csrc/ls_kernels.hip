@@ -7,6 +7,8 @@
 //   after the spectral product the field of set s sits in kind 0.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ls_kernels.hpp"
 
 namespace lsx {
@@ -577,6 +579,158 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::
   }
 }
 
+// Single-precision form of the window contraction above with the staging
+// double-buffered: while the MFMAs contract window row wy from one LDS
+// buffer, the loads of row wy+1 are in flight in registers and land in the
+// other buffer, so each row costs one barrier and no exposed load latency.
+// A workgroup takes 16 cells (enough workgroups to keep every CU busy).
+__global__ void __launch_bounds__(256) k_near_shared_mfma_db(const float2* __restrict__ grid, float2* __restrict__ v,
+                                                             const float2* __restrict__ W,
+                                                             const int32_t* __restrict__ icells,
+                                                             const int32_t* __restrict__ cell_xy,
+                                                             const int32_t* __restrict__ slot_map, int Gw,
+                                                             int nicell, int64_t N, float k2) {
+  using M = Mfma<float>;
+  using v4 = M::v4;
+  constexpr int CH = 8, S = 64, WN = 40, KP = WN + 1, NC = 16;
+  constexpr int XPT = (NC * WN + 255) / 256, WPT = (S * WN + 255) / 256;
+  __shared__ float2 Xs[2][NC * KP];
+  __shared__ float2 Ws[2][S * KP];
+  __shared__ int cx0[NC], cy0[NC];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int r = blockIdx.y;
+  const int cb = blockIdx.x * NC;
+  const float2* g = grid + (int64_t)r * Gw * Gw;
+  if (tid < NC) {
+    const int cid = cb + tid < nicell ? icells[cb + tid] : -1;
+    cx0[tid] = cid >= 0 ? cell_xy[2 * cid] * CH : -1;
+    cy0[tid] = cid >= 0 ? cell_xy[2 * cid + 1] * CH : -1;
+  }
+  __syncthreads();
+  float2 xr[XPT], wr[WPT];
+  auto gload = [&](int wy) {
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int i = tid + 256 * q;
+      float2 val = make_float2(0.f, 0.f);
+      if (i < NC * WN) {
+        const int c = i / WN, wx = i % WN;
+        if (cx0[c] >= 0) val = g[(int64_t)(cy0[c] + wy) * Gw + cx0[c] + wx];
+      }
+      xr[q] = val;
+    }
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int i = tid + 256 * q;
+      if (i < S * WN) wr[q] = W[(int64_t)(i / WN) * WN * WN + wy * WN + i % WN];
+    }
+  };
+  auto sstore = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int i = tid + 256 * q;
+      if (i < NC * WN) Xs[b][(i / WN) * KP + i % WN] = xr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int i = tid + 256 * q;
+      if (i < S * WN) Ws[b][(i / WN) * KP + i % WN] = wr[q];
+    }
+  };
+  v4 are = v4{0, 0, 0, 0}, aim = v4{0, 0, 0, 0};
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int wy = 0; wy < WN; ++wy) {
+    const int b = wy & 1;
+    if (wy + 1 < WN) gload(wy + 1);
+#pragma unroll 2
+    for (int kk = 0; kk < WN / 4; ++kk) {
+      const int k = 4 * kk + (lane >> 4);
+      const float2 wa = Ws[b][(16 * wave + (lane & 15)) * KP + k];
+      const float2 xb = Xs[b][(lane & 15) * KP + k];
+      are = M::op(wa.x, xb.x, are);
+      are = M::op(-wa.y, xb.y, are);
+      aim = M::op(wa.x, xb.y, aim);
+      aim = M::op(wa.y, xb.x, aim);
+    }
+    if (wy + 1 < WN) sstore(b ^ 1);
+    __syncthreads();
+  }
+  const int c = cb + (lane & 15);
+  if (c >= nicell) return;
+  const int cid = icells[c];
+  float2* vr = v + (int64_t)r * N;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int a = 16 * wave + M::row(lane, q);
+    const int j = slot_map[(int64_t)cid * S + a];
+    if (j < 0) continue;
+    float2 o = vr[j];
+    o.x += k2 * are[q];
+    o.y += k2 * aim[q];
+    vr[j] = o;
+  }
+}
+
+// Single-precision rows touching the boundary patch with 16-bit column
+// offsets, rows stored padded to a multiple of four entries (zero weights,
+// offset 0): each lane takes four consecutive entries per step (one 32-byte
+// weight load and one 8-byte offset load), each weight applied to up to four
+// right-hand sides.
+__global__ void __launch_bounds__(256) k_near_csr4(const float2* __restrict__ u, float2* __restrict__ v,
+                                                   const int64_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ colbase,
+                                                   const uint16_t* __restrict__ coloff,
+                                                   const float2* __restrict__ vals, int nrows, int64_t N, int nrhs,
+                                                   float k2) {
+  constexpr int RB = 4;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (row >= nrows) return;
+  const int64_t b = rowptr[row] >> 2, e = rowptr[row + 1] >> 2;
+  const float2* __restrict__ ub = u + colbase[row];
+  const float4* __restrict__ v4 = (const float4*)vals;
+  const uint2* __restrict__ o4 = (const uint2*)coloff;
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    const int nr = min(RB, nrhs - r0);
+    float2 acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = czero<float2>();
+    for (int64_t k = b + lane; k < e; k += 64) {
+      const float4 wa = v4[2 * k], wb = v4[2 * k + 1];
+      const uint2 cc = o4[k];
+      const int c0 = cc.x & 0xffff, c1 = cc.x >> 16, c2 = cc.y & 0xffff, c3 = cc.y >> 16;
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        if (q < nr) {
+          const float2* uq = ub + (int64_t)(r0 + q) * N;
+          acc[q] = cfma(make_float2(wa.x, wa.y), uq[c0], acc[q]);
+          acc[q] = cfma(make_float2(wa.z, wa.w), uq[c1], acc[q]);
+          acc[q] = cfma(make_float2(wb.x, wb.y), uq[c2], acc[q]);
+          acc[q] = cfma(make_float2(wb.z, wb.w), uq[c3], acc[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      if (q >= nr) break;
+      float2 a = acc[q];
+      for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_down(a.x, off, 64);
+        a.y += __shfl_down(a.y, off, 64);
+      }
+      if (lane == 0) {
+        const int64_t j = rows[row];
+        float2* vr = v + (int64_t)(r0 + q) * N;
+        float2 t = vr[j];
+        vr[j] = cadd(t, cscale(a, k2));
+      }
+    }
+  }
+}
+
 // a4, rows touching the boundary patch: one wavefront per row; each weight
 // is loaded once and applied to up to four right-hand sides; four entries
 // per lane in flight.
@@ -1099,10 +1253,16 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     const int64_t gsz = (int64_t)Gw * Gw;
     hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, st, u, grid, d.dw,
                        d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
-    constexpr int NT = 2;
-    hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs), dim3(256), 0,
-                       st, (const V*)grid, v, (const V*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N,
-                       k2);
+    if constexpr (std::is_same<T, float>::value) {
+      hipLaunchKernelGGL(k_near_shared_mfma_db, dim3((d.nicell + 15) / 16, nrhs), dim3(256), 0, st,
+                         (const float2*)grid, (float2*)v, (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw,
+                         d.nicell, d.N, (float)k2);
+    } else {
+      constexpr int NT = 2;
+      hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs), dim3(256),
+                         0, st, (const V*)grid, v, (const V*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell,
+                         d.N, k2);
+    }
   } else {
     constexpr int CT = 16, KC = 32;
     size_t sh = (size_t)(d.S * KC + KC * CT) * sizeof(V) + 25 * CT * sizeof(int);
@@ -1122,7 +1282,10 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
                            d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
     } else {
-      if (d.coloff)
+      if (d.coloff && std::is_same<T, float>::value)
+        hipLaunchKernelGGL(k_near_csr4, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.colbase,
+                           d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
+      else if (d.coloff)
         hipLaunchKernelGGL((k_near_csr<T, float2, uint16_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
                            d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
       else
