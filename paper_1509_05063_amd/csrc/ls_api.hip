@@ -277,6 +277,10 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     if (e != hipSuccess) return cleanup(fail(LS_EDEVICE, std::string("LDS attribute: ") + hipGetErrorString(e)));
   }
   (void)lds_max;
+  {
+    hipError_t e = lsx::set_cell_lds_limits();
+    if (e != hipSuccess) return cleanup(fail(LS_EDEVICE, std::string("LDS attribute: ") + hipGetErrorString(e)));
+  }
 
   lsx::DevView<double>& a = op->d64;
   lsx::DevView<float>& b = op->d32;
@@ -316,6 +320,17 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   UP(upload_c(op, h.Psh, &a.Psh, nullptr));
   UP(upload_c(op, h.Pbd, &a.Pbd, nullptr));
   UP(upload_c(op, h.Psh32, nullptr, &b.Psh));
+  {
+    // slot projection transposed to [S][U] (the kernel's 96 output lanes read consecutive words)
+    std::vector<cd> t64((size_t)h.S * h.U), t32((size_t)h.S * h.U);
+    for (int t = 0; t < h.U; ++t)
+      for (int a2 = 0; a2 < h.S; ++a2) {
+        t64[(size_t)a2 * h.U + t] = h.Psh[(size_t)t * h.S + a2];
+        t32[(size_t)a2 * h.U + t] = h.Psh32[(size_t)t * h.S + a2];
+      }
+    UP(upload_c(op, t64, &a.PshT, nullptr));
+    UP(upload_c(op, t32, nullptr, &b.PshT));
+  }
   UP(upload_c(op, h.Pbd32, nullptr, &b.Pbd));
   {
     // transposed layouts for coalesced reads in the interpolation kernel

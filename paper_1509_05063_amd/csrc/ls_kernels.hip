@@ -35,6 +35,26 @@ template <typename V> __device__ __forceinline__ V csub(V a, V b) { a.x -= b.x; 
 template <typename V> __device__ __forceinline__ V cscale(V a, decltype(a.x) s) { a.x *= s; a.y *= s; return a; }
 template <typename V> __device__ __forceinline__ V czero() { V r; r.x = 0; r.y = 0; return r; }
 
+// Matrix-core products (16x16x4 tiles).  Operand A: row lane%16, k lane/16;
+// operand B: k lane/16, column lane%16.
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element held by (lane, r): row lane/16 + 4r, column lane%16
+  static __device__ __forceinline__ int row(int lane, int r) { return lane / 16 + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element held by (lane, r): row 4(lane/16) + r, column lane%16
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
 // ---------------------------------------------------------------------------
 // a1: projection onto equivalent sources.  One workgroup per occupied cell
 // and right-hand side; sigma_c = Psh phi_slots + sum_b Pbd_b phi_b with
@@ -72,6 +92,46 @@ __global__ void __launch_bounds__(256) k_project(const typename C2<T>::t* __rest
     for (int b = 0; b < nb; ++b) acc = cfma(Pbd[(boff + b) * U + t], phi[S + b], acc);
     sigma[((int64_t)r * ncell + c) * U + t] = acc;
   }
+}
+
+// Projection, one workgroup of 2 x 96 threads per cell (q = 12: U = 96
+// sources, S = 64 slots): thread (g, t) sums half of the slots (PshT, the
+// transposed slot matrix [S][U], read coalesced over t) and every other band
+// node; the two halves are added through LDS.
+template <typename T>
+__global__ void __launch_bounds__(192) k_project2(const typename C2<T>::t* __restrict__ u,
+                                                  typename C2<T>::t* __restrict__ sigma,
+                                                  const typename C2<T>::t* __restrict__ PshT,
+                                                  const typename C2<T>::t* __restrict__ Pbd,
+                                                  const T* __restrict__ cw, const int32_t* __restrict__ slot_map,
+                                                  const int32_t* __restrict__ cell_start,
+                                                  const int32_t* __restrict__ cell_nint,
+                                                  const int32_t* __restrict__ cell_nb,
+                                                  const int32_t* __restrict__ cell_boff, int64_t N, int ncell) {
+  using V = typename C2<T>::t;
+  constexpr int U = 96, S = 64;
+  extern __shared__ unsigned char smem_raw[];
+  V* red = reinterpret_cast<V*>(smem_raw);   // [U] second half's sums
+  V* phi = red + U;                          // [S + nb]
+  const int c = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const V* ur = u + (int64_t)r * N;
+  const int nb = cell_nb[c];
+  const int64_t b0 = cell_start[c] + cell_nint[c];
+  for (int a = tid; a < S + nb; a += blockDim.x) {
+    const int64_t j = a < S ? slot_map[(int64_t)c * S + a] : b0 + a - S;
+    phi[a] = j >= 0 ? cscale(ur[j], cw[j]) : czero<V>();
+  }
+  __syncthreads();
+  const int t = tid % U, g = tid / U;
+  V acc = czero<V>();
+#pragma unroll 8
+  for (int a = 32 * g; a < 32 * g + 32; ++a) acc = cfma(PshT[a * U + t], phi[a], acc);
+  const V* prow = Pbd + (int64_t)cell_boff[c] * U + t;
+#pragma unroll 4
+  for (int b = g; b < nb; b += 2) acc = cfma(prow[(int64_t)b * U], phi[S + b], acc);
+  if (g == 1) red[t] = acc;
+  __syncthreads();
+  if (g == 0) sigma[((int64_t)r * ncell + c) * U + t] = cadd(acc, red[t]);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,6 +432,150 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
   }
 }
 
+// Interpolation for 16 consecutive cells per workgroup (q = 12: F = 48 face
+// values, U = 96 sources, S = 64 slots) on the matrix cores.  For each of the
+// 9 neighbour offsets, the same-set blocks of its adjacency matrix (2 sets x
+// 48 sources x 24 faces) and the 16 neighbours' strengths are staged in LDS;
+// wave w contracts set w/2, faces 16(w%2)..16(w%2)+15 (rows past 24 are
+// zero) against the 16 cells: C[face][cell] = sum_k T[k][face] sigma[cell][k],
+// complex products as four real MFMA 16x16x4 updates, summed over the 9
+// offsets in the accumulators.  The corrected face values are then fitted to
+// the slots as a second contraction (IshT [F][S] times the 16 cells' face
+// values; wave w takes slots 16w..16w+15), and to the band nodes one row per
+// thread.
+template <typename T, int CB>
+__global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __restrict__ u,
+                                                     typename C2<T>::t* __restrict__ v,
+                                                     const typename C2<T>::t* __restrict__ lat,
+                                                     const typename C2<T>::t* __restrict__ sigma,
+                                                     const typename C2<T>::t* __restrict__ ToffT,
+                                                     const typename C2<T>::t* __restrict__ IshT,
+                                                     const typename C2<T>::t* __restrict__ Ibd,
+                                                     const int32_t* __restrict__ cell_xy,
+                                                     const int32_t* __restrict__ cell_map,
+                                                     const int32_t* __restrict__ slot_map,
+                                                     const int32_t* __restrict__ cell_start,
+                                                     const int32_t* __restrict__ cell_nint,
+                                                     const int32_t* __restrict__ cell_nb,
+                                                     const int32_t* __restrict__ cell_boff, int L, int ncell, int Pa,
+                                                     int Pb, int64_t N, T k2) {
+  using V = typename C2<T>::t;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int q = 12, F = 4 * q, U = 8 * q, S = 64, KS = 4 * q, TS = 2 * q;   // KS sources, TS faces per set
+  static_assert(CB == 16, "one MFMA column per cell");
+  extern __shared__ unsigned char smem_raw[];
+  V* fv = reinterpret_cast<V*>(smem_raw);    // [CB][F] face values
+  V* sg = fv + CB * F;                       // [CB][U] strengths of the neighbour at the current offset
+  V* To = sg + CB * U;                       // [2][KS][TS] same-set adjacency blocks of the current offset
+  int* cinfo = reinterpret_cast<int*>(To + 2 * KS * TS);   // [CB][2] cell x, y (-1: past the end)
+  const int c0 = blockIdx.x * CB, r = blockIdx.y, tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
+  const int64_t plane = (int64_t)Pa * Pb;
+  if (tid < CB) {
+    const int c = c0 + tid;
+    cinfo[2 * tid] = c < ncell ? cell_xy[2 * c] : -1;
+    cinfo[2 * tid + 1] = c < ncell ? cell_xy[2 * c + 1] : -1;
+  }
+  __syncthreads();
+  for (int i = tid; i < CB * F; i += blockDim.x) {
+    const int cb = i / F, t = i % F;
+    const int cx = cinfo[2 * cb], cy = cinfo[2 * cb + 1];
+    V val = czero<V>();
+    if (cx >= 0) {
+      const int s2 = t / (2 * q), fj = t % (2 * q), fc = fj / q, j = fj % q;
+      const int cn = (s2 == 0 ? cx : cy) + fc, ct = (s2 == 0 ? cy : cx);
+      val = lat[((int64_t)(r * 2 + s2) * 2) * plane + (int64_t)cn * Pb + ct * q + j];
+    }
+    fv[i] = val;
+  }
+  const int ws = wave >> 1, mt = wave & 1;   // this wave's set and face tile
+  const int arow = 16 * mt + col;            // face row of the A operand
+  v4 cre = v4{0, 0, 0, 0}, cim = v4{0, 0, 0, 0};
+  for (int o = 0; o < 9; ++o) {
+    const int ox = o % 3 - 1, oy = o / 3 - 1;
+    __syncthreads();
+    for (int i = tid; i < CB * U; i += blockDim.x) {
+      const int cb = i / U, k = i % U;
+      const int cx = cinfo[2 * cb], cy = cinfo[2 * cb + 1];
+      int cn = -1;
+      if (cx >= 0) {
+        const int nx = cx + ox, ny = cy + oy;
+        cn = (nx >= 0 && ny >= 0 && nx < L && ny < L) ? cell_map[ny * L + nx] : -1;
+      }
+      sg[i] = cn >= 0 ? sigma[((int64_t)r * ncell + cn) * U + k] : czero<V>();
+    }
+    for (int i = tid; i < 2 * KS * TS; i += blockDim.x) {
+      const int s2 = i / (KS * TS), k = (i / TS) % KS, tt = i % TS;
+      To[i] = ToffT[((int64_t)o * U + s2 * KS + k) * F + s2 * TS + tt];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < KS / 4; ++kk) {
+      const int k = 4 * kk + kl;
+      const V a = arow < TS ? To[(ws * KS + k) * TS + arow] : czero<V>();
+      const V b = sg[col * U + ws * KS + k];
+      cre = M::op(a.x, b.x, cre);
+      cre = M::op(-a.y, b.y, cre);
+      cim = M::op(a.x, b.y, cim);
+      cim = M::op(a.y, b.x, cim);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int tp = 16 * mt + M::row(lane, rr);
+    if (tp < TS) {
+      V& x = fv[col * F + ws * TS + tp];
+      x.x -= cre[rr];
+      x.y -= cim[rr];
+    }
+  }
+  __syncthreads();
+  const V* ur = u + (int64_t)r * N;
+  V* vr = v + (int64_t)r * N;
+  {
+    v4 dre = v4{0, 0, 0, 0}, dim = v4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < F / 4; ++kk) {
+      const int t = 4 * kk + kl;
+      const V a = IshT[t * S + 16 * wave + col];
+      const V b = fv[col * F + t];
+      dre = M::op(a.x, b.x, dre);
+      dre = M::op(-a.y, b.y, dre);
+      dim = M::op(a.x, b.y, dim);
+      dim = M::op(a.y, b.x, dim);
+    }
+    const int c = c0 + col;
+    if (c < ncell) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int a = 16 * wave + M::row(lane, rr);
+        const int j = slot_map[(int64_t)c * S + a];
+        if (j >= 0) {
+          V o2;
+          o2.x = dre[rr];
+          o2.y = dim[rr];
+          vr[j] = cadd(ur[j], cscale(o2, k2));
+        }
+      }
+    }
+  }
+  const int cl = min(c0 + CB, ncell) - 1;
+  const int64_t bb = cell_boff[c0], be = (int64_t)cell_boff[cl] + cell_nb[cl];
+  for (int64_t ib = bb + tid; ib < be; ib += blockDim.x) {
+    int cb = 0;
+    while (c0 + cb + 1 <= cl && cell_boff[c0 + cb + 1] <= ib) ++cb;
+    const int c = c0 + cb;
+    const V* irow = Ibd + ib * F;
+    V s1 = czero<V>();
+#pragma unroll 8
+    for (int t = 0; t < F; ++t) s1 = cfma(irow[t], fv[cb * F + t], s1);
+    const int64_t j = cell_start[c] + cell_nint[c] + (ib - cell_boff[c]);
+    vr[j] = cadd(ur[j], cscale(s1, k2));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a4, interior x interior: out[a][cell] += sum_b W[a][b] psi[b][cell] over
 // the 5x5-cell window (translation invariant weights).  Tiled: a workgroup
@@ -486,23 +690,6 @@ __global__ void k_psi_grid(const typename C2<T>::t* __restrict__ u, typename C2<
   grid[(int64_t)r * gsz + idx] = val;
 }
 
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // output element held by (lane, r): row lane/16 + 4r, column lane%16
-  static __device__ __forceinline__ int row(int lane, int r) { return lane / 16 + 4 * r; }
-};
-template <> struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  // output element held by (lane, r): row 4(lane/16) + r, column lane%16
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
-};
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::t* __restrict__ grid,
@@ -1200,9 +1387,16 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   // a0 + a1
   {
     size_t sh = (size_t)(d.S + d.max_nb) * sizeof(V);
-    hipLaunchKernelGGL(k_project<T>, dim3(d.ncell, nrhs), dim3(128), sh, st, u, sigma, (const V*)d.Psh,
-                       (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
-                       d.S, d.U, d.N, d.ncell);
+    if (d.q == 12 && d.S == 64 && d.PshT) {
+      const size_t shm = (size_t)(96 + 64 + d.max_nb) * sizeof(V);
+      hipLaunchKernelGGL(k_project2<T>, dim3(d.ncell, nrhs), dim3(192), shm, st, u, sigma, (const V*)d.PshT,
+                         (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N,
+                         d.ncell);
+    } else {
+      hipLaunchKernelGGL(k_project<T>, dim3(d.ncell, nrhs), dim3(128), sh, st, u, sigma, (const V*)d.Psh,
+                         (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
+                         d.S, d.U, d.N, d.ncell);
+    }
   }
   mark(1);
   // lattice fill
@@ -1240,10 +1434,19 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   // a3 + a5
   {
     size_t sh = (size_t)(d.F + 9 * d.U + 9 * d.F) * sizeof(V) + 16 * sizeof(int);
-    hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), sh, st, u, v, (const V*)lat, (const V*)sigma,
-                       (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.cell_map, d.slot_map,
-                       d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L, d.q, d.U, d.F, d.S, d.ncell,
-                       d.Pa, d.Pb, d.N, k2);
+    if (d.q == 12 && d.S == 64) {
+      constexpr int CB = 16;
+      const size_t shm = (size_t)(CB * 48 + CB * 96 + 2 * 48 * 24) * sizeof(V) + 2 * CB * sizeof(int);
+      hipLaunchKernelGGL((k_interp_mfma<T, CB>), dim3((d.ncell + CB - 1) / CB, nrhs), dim3(256), shm, st, u, v,
+                         (const V*)lat, (const V*)sigma, (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd,
+                         d.cell_xy, d.cell_map, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L,
+                         d.ncell, d.Pa, d.Pb, d.N, k2);
+    } else {
+      hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), sh, st, u, v, (const V*)lat,
+                         (const V*)sigma, (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.cell_map,
+                         d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L, d.q, d.U, d.F, d.S,
+                         d.ncell, d.Pa, d.Pb, d.N, k2);
+    }
   }
   mark(6);
   // a4 shared
@@ -1317,6 +1520,13 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
   return e;
+}
+
+hipError_t set_cell_lds_limits() {
+  // the double-precision form of the 16-cell interpolation kernel (74 KB)
+  // exceeds the 64 KB default
+  return hipFuncSetAttribute((const void*)k_interp_mfma<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (16 * 48 + 16 * 96 + 2 * 48 * 24) * 16 + 2 * 16 * 4);
 }
 
 hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st) {

@@ -20,7 +20,7 @@ struct DevView {
   int max_nb = 0, tc = 1, nrows = 0;
   bool csr_f64 = true;
   double kappa = 0;
-  const void *Psh = nullptr, *Pbd = nullptr, *Ish = nullptr, *Ibd = nullptr, *Toff = nullptr, *Wsh = nullptr;
+  const void *Psh = nullptr, *PshT = nullptr, *Pbd = nullptr, *Ish = nullptr, *Ibd = nullptr, *Toff = nullptr, *Wsh = nullptr;
   const void *khat = nullptr, *twa = nullptr, *twb = nullptr, *vals = nullptr;
   const T *cw = nullptr, *dw = nullptr;
   const int32_t *slot_map = nullptr, *cell_start = nullptr, *cell_nint = nullptr, *cell_nb = nullptr;
@@ -37,6 +37,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u, void* v, int nrhs, v
                         hipEvent_t* ev = nullptr);
 hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st);
 hipError_t set_fft_lds_limits(size_t bytes);
+hipError_t set_cell_lds_limits();
 
 // GMRES building blocks (double complex)
 hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int nvec, int64_t N, int nrhs,
