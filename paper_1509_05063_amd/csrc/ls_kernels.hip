@@ -144,14 +144,16 @@ __global__ void k_fill(const typename C2<T>::t* __restrict__ sigma, typename C2<
                        const int32_t* __restrict__ cell_map, int L, int q, int U, int ncell, int na,
                        int nb, int Pa, int Pb) {
   using V = typename C2<T>::t;
+  // only the a < na, b < nb corner is written; the transforms treat the
+  // rest of the plane as zero without reading it
   const int64_t plane = (int64_t)Pa * Pb;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= plane) return;
+  if (idx >= (int64_t)na * nb) return;
   const int s = blockIdx.y;       // set
   const int r = blockIdx.z;       // rhs
-  const int a = (int)(idx / Pb), b = (int)(idx % Pb);
+  const int a = (int)(idx / nb), b = (int)(idx % nb);
   V mono = czero<V>(), dip = czero<V>();
-  if (a < na && b < nb) {
+  {
     const int t = b / q, j = b % q;
     for (int f = 0; f < 2; ++f) {
       int cn = a - f;            // cell index along the set's normal axis
@@ -164,9 +166,9 @@ __global__ void k_fill(const typename C2<T>::t* __restrict__ sigma, typename C2<
       dip = cadd(dip, sg[2 * q + f * q + j]);
     }
   }
-  V* base = lat + ((int64_t)(r * 2 + s) * 2) * plane;
-  base[idx] = mono;
-  base[plane + idx] = dip;
+  V* base = lat + ((int64_t)(r * 2 + s) * 2) * plane + (int64_t)a * Pb + b;
+  base[0] = mono;
+  base[plane] = dip;
 }
 
 // ---------------------------------------------------------------------------
@@ -284,9 +286,11 @@ __device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, 
 }
 
 // transforms along the contiguous axis: one line per workgroup
+// (entries past nload are zero padding: not read; entries past nstore are
+// not needed downstream: not written)
 template <typename T, int DIR>
 __global__ void __launch_bounds__(256) k_fft_rows(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
-                                                  FftPlan plan, int64_t line_stride, int lines_per_batch,
+                                                  FftPlan plan, int64_t line_stride, int nload, int nstore,
                                                   int64_t batch_stride) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
@@ -295,18 +299,19 @@ __global__ void __launch_bounds__(256) k_fft_rows(typename C2<T>::t* data, const
   const int line = blockIdx.x;
   const int batch = blockIdx.y;
   V* x = data + batch * batch_stride + (int64_t)line * line_stride;
-  for (int i = threadIdx.x; i < plan.n; i += blockDim.x) b0[i] = x[i];
+  for (int i = threadIdx.x; i < plan.n; i += blockDim.x) b0[i] = i < nload ? x[i] : czero<V>();
   __syncthreads();
   V* res;
   stockham_lds<V, DIR>(b0, b1, tw, plan.n, plan.radix, plan.npass, 1, threadIdx.x, blockDim.x, &res);
-  for (int i = threadIdx.x; i < plan.n; i += blockDim.x) x[i] = res[i];
-  (void)lines_per_batch;
+  for (int i = threadIdx.x; i < nstore; i += blockDim.x) x[i] = res[i];
 }
 
 // transforms along the strided axis: a workgroup takes TC adjacent columns
 template <typename T, int DIR>
+// (rows past nload are zero padding: not read; rows past nstore: not written)
 __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
-                                                  FftPlan plan, int ncols, int TC, int64_t batch_stride) {
+                                                  FftPlan plan, int ncols, int TC, int64_t batch_stride, int nload,
+                                                  int nstore) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
   V* b0 = reinterpret_cast<V*>(smem_raw);
@@ -317,12 +322,12 @@ __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const
   V* x = data + batch * batch_stride + c0;
   for (int i = threadIdx.x; i < plan.n * TC; i += blockDim.x) {
     int row = i / TC, col = i % TC;
-    b0[i] = col < tc ? x[(int64_t)row * ncols + col] : czero<V>();
+    b0[i] = (col < tc && row < nload) ? x[(int64_t)row * ncols + col] : czero<V>();
   }
   __syncthreads();
   V* res;
   stockham_lds<V, DIR>(b0, b1, tw, plan.n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res);
-  for (int i = threadIdx.x; i < plan.n * TC; i += blockDim.x) {
+  for (int i = threadIdx.x; i < nstore * TC; i += blockDim.x) {
     int row = i / TC, col = i % TC;
     if (col < tc) x[(int64_t)row * ncols + col] = res[i];
   }
@@ -1400,7 +1405,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   }
   mark(1);
   // lattice fill
-  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, sigma, lat,
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)(((int64_t)d.na * d.nb + 255) / 256), 2, nrhs), dim3(256), 0, st, sigma, lat,
                      d.cell_map, d.L, d.q, d.U, d.ncell, d.na, d.nb, d.Pa, d.Pb);
   mark(2);
   // a2: forward transforms of all 4 arrays per rhs
@@ -1410,11 +1415,11 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     // rows a >= na are zero padding: their transforms stay zero
     hipLaunchKernelGGL((k_fft_rows<T, 1>), dim3(d.na, nbatch), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
-                       (int64_t)d.Pb, d.na, plane);
+                       (int64_t)d.Pb, d.nb, d.Pb, plane);
     int TC = TCP;
     size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
     hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, lat,
-                       (const V*)d.twa, d.pa, d.Pb, TC, plane);
+                       (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa);
   }
   mark(3);
   hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, lat,
@@ -1425,10 +1430,10 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     int TC = TCP;
     size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
     hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
-                       (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane);
+                       (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na);
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     hipLaunchKernelGGL((k_fft_rows<T, -1>), dim3(d.na, nrhs * 2), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
-                       (int64_t)d.Pb, d.na, 2 * plane);
+                       (int64_t)d.Pb, d.Pb, d.nb, 2 * plane);
   }
   mark(5);
   // a3 + a5
@@ -1534,11 +1539,11 @@ hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int 
   const int64_t plane = (int64_t)d.Pa * d.Pb;
   size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
   hipLaunchKernelGGL((k_fft_rows<double, 1>), dim3(d.Pa, nbatch), dim3(256), sh, st, (V*)data, (const V*)d.twb,
-                     d.pb, (int64_t)d.Pb, d.Pa, plane);
+                     d.pb, (int64_t)d.Pb, d.Pb, d.Pb, plane);
   int TC = d.tc;
   size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
   hipLaunchKernelGGL((k_fft_cols<double, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, (V*)data,
-                     (const V*)d.twa, d.pa, d.Pb, TC, plane);
+                     (const V*)d.twa, d.pa, d.Pb, TC, plane, d.Pa, d.Pa);
   return hipGetLastError();
 }
 
