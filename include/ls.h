@@ -172,6 +172,12 @@ typedef struct {
   int max_outer;        /* refinement steps */
   int use_x0;           /* nonzero: u_tot holds the initial guess */
   ls_ortho ortho;       /* Gram–Schmidt passes (zero-initialised = CGS2) */
+  int graph;            /* nonzero: each Arnoldi step (apply, orthogonalisation,
+                           normalisation, copy of its Hessenberg column) is
+                           captured once as a HIP graph and replayed; graphs
+                           are kept with the op per (precision, passes, nrhs,
+                           restart, step) and released by ls_destroy.  Results
+                           are bitwise those of the eager launches. */
 } ls_solve_opts;
 
 typedef struct {

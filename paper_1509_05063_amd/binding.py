@@ -36,7 +36,8 @@ class Params(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("mode", C.c_int),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("use_x0", C.c_int), ("ortho", C.c_int)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("use_x0", C.c_int), ("ortho", C.c_int),
+                ("graph", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -256,10 +257,10 @@ class Operator:
         return dict(zip(self.STAGES, list(out)))
 
     def solve(self, u_inc, u_tot, tol=1e-10, max_iter=2000, restart=100, mode=LS_SOLVE_FP64, inner_tol=1e-5,
-              max_outer=20, use_x0=False, stream=None, raise_on_noconv=True, ortho=LS_ORTHO_CGS2):
+              max_outer=20, use_x0=False, stream=None, raise_on_noconv=True, ortho=LS_ORTHO_CGS2, graph=False):
         nrhs = 1 if u_inc.dim() == 1 else u_inc.shape[0]
         opts = SolveOpts(float(tol), int(max_iter), int(restart), int(mode), float(inner_tol), int(max_outer),
-                         int(use_x0), int(ortho))
+                         int(use_x0), int(ortho), int(bool(graph)))
         st = SolveStats()
         rc = lib().ls_solve(self._op, _ptr(u_inc), _ptr(u_tot), nrhs, C.byref(opts), C.byref(st), _stream(stream))
         if rc != LS_OK and (rc != LS_ENOCONV or raise_on_noconv):

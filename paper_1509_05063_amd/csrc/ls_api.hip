@@ -7,6 +7,8 @@
 #include <complex>
 #include <cstring>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "ls.h"
@@ -35,6 +37,8 @@ struct ls_host_op {
   lsx::HostOp h;
 };
 
+using GraphKey = std::tuple<bool, bool, int, int, int, uintptr_t, int64_t>;
+
 struct ls_op {
   int device = 0;
   int64_t N = 0;
@@ -52,6 +56,10 @@ struct ls_op {
   std::complex<double>* pinned = nullptr;
   size_t pinned_n = 0;
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
+  // captured Arnoldi steps: (single precision, CGS2, nrhs, restart, step,
+  // solver buffer, N) -> executable graph; capture runs on cap_stream
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
 };
 
 namespace {
@@ -109,6 +117,11 @@ lsx::FftPlan make_plan(int n) {
   return p;
 }
 
+void clear_graphs(ls_op* op) {
+  for (auto& kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
+  op->graphs.clear();
+}
+
 void release(ls_op* op) {
   for (void* p : op->allocs) (void)hipFree(p);
   op->allocs.clear();
@@ -120,6 +133,9 @@ void release(ls_op* op) {
     if (e) (void)hipEventDestroy(e);
     e = nullptr;
   }
+  clear_graphs(op);
+  if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
+  op->cap_stream = nullptr;
 }
 
 size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
@@ -545,6 +561,7 @@ struct Gm {
   size_t wsb;
   int nparts;
   bool cgs2 = true;
+  bool use_graph = false;
   double apply_s = 0;
   int applies = 0;
   std::complex<double>* pinned[2] = {nullptr, nullptr};   // host copies of the two slots
@@ -568,9 +585,13 @@ ls_status gm_setup(Gm& g) {
     if (g.op->gm) (void)hipFree(g.op->gm);
     g.op->gm = nullptr;
     g.op->gm_bytes = 0;
+    clear_graphs(g.op);     // captured steps point into the old buffer
     if (hipMalloc(&g.op->gm, need) != hipSuccess) return fail(LS_ENOMEM, "solver workspace");
     g.op->gm_bytes = need;
   }
+  if (g.use_graph && !g.op->cap_stream &&
+      hipStreamCreateWithFlags(&g.op->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(LS_EDEVICE, "capture stream");
   char* p = (char*)g.op->gm;
   auto take = [&](size_t bytes) {
     char* q = p;
@@ -597,6 +618,7 @@ ls_status gm_setup(Gm& g) {
   g.u32 = take(8 * (size_t)g.N * g.nrhs);
   g.v32 = take(8 * (size_t)g.N * g.nrhs);
   if (!g.op->pinned || g.op->pinned_n < 2 * slot) {
+    clear_graphs(g.op);     // captured steps copy into the old pinned slots
     if (g.op->pinned) (void)hipHostFree(g.op->pinned);
     g.op->pinned = nullptr;
     g.op->pinned_n = 2 * slot;
@@ -776,6 +798,39 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
       HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
     }
     HIPCHK(hipMemcpyAsync(g.pinned[k & 1], d1, 16 * (2 * nh + R), hipMemcpyDeviceToHost, g.st));
+    return LS_OK;
+  };
+  // one step, replayed from a captured graph when g.use_graph (captured on
+  // first use for this step index and kept with the op), then the event the
+  // host waits on
+  auto launch_step = [&](int k) -> ls_status {
+    if (g.use_graph) {
+      const GraphKey key{F32, g.cgs2, R, m, k, (uintptr_t)g.op->gm, N};
+      auto it = g.op->graphs.find(key);
+      if (it == g.op->graphs.end()) {
+        hipStream_t user = g.st;
+        g.st = g.op->cap_stream;
+        HIPCHK(hipStreamBeginCapture(g.st, hipStreamCaptureModeRelaxed));
+        ls_status st2 = step(k);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(g.st, &graph);
+        g.st = user;
+        if (st2) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return st2;
+        }
+        if (e != hipSuccess) return fail(LS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(LS_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        it = g.op->graphs.emplace(key, exec).first;
+      }
+      HIPCHK(hipGraphLaunch(it->second, g.st));
+    } else {
+      ls_status st2 = step(k);
+      if (st2) return st2;
+    }
     HIPCHK(hipEventRecord(g.ev[k & 1], g.st));
     return LS_OK;
   };
@@ -823,11 +878,11 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
       HIPCHK(lsx::gm_scale_copy(g.r, g.V, g.sdev, N, R, g.st));
     hs.reset(R, m, beta, relres, tol);
     int k = 0;
-    s = step(0);
+    s = launch_step(0);
     if (s) return s;
     for (; k < m && it < max_iter; ++k) {
       if (k + 1 < m && it + 1 < max_iter) {
-        s = step(k + 1);
+        s = launch_step(k + 1);
         if (s) return s;
       }
       HIPCHK(hipEventSynchronize(g.ev[k & 1]));
@@ -875,6 +930,7 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
   g.N = op->N;
   g.st = (hipStream_t)stream;
   g.cgs2 = opts->ortho != LS_ORTHO_CGS1;
+  g.use_graph = opts->graph != 0;
   ls_status s = gm_setup(g);
   if (s) return s;
   const double2* f = (const double2*)u_inc;
