@@ -100,6 +100,42 @@ def cpu_oracle_rate(cfg, n2, budget_s=20.0):
     return done / dt, done, orc.N
 
 
+def multi_rhs_run(nrhs, ortho, autotune):
+    """Batched solves on the kappa = 16 pi star: nrhs equispaced incident
+    directions as the right-hand sides of one solve (FP64 reference, then the
+    single-precision + refinement form), RHS-solves/s and the worst error."""
+    import torch
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import config, n2_function, plane_wave
+    cfg = config("star_k16pi")
+    op = binding.Operator(cfg, n2_function(cfg))
+    try:
+        if autotune:
+            op.autotune(nrhs, binding.LS_C64)
+            op.autotune(nrhs, binding.LS_C128)
+        xy, _ = op.points()
+        F = torch.tensor(np.stack([plane_wave(cfg, xy, 2 * math.pi * r / nrhs) for r in range(nrhs)]),
+                         dtype=torch.complex128, device="cuda")
+        g = cfg["gmres"]
+        X64, X32 = torch.empty_like(F), torch.empty_like(F)
+        t0 = time.perf_counter()
+        s64 = op.solve(F, X64, tol=1e-10, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        s32 = op.solve(F, X32, tol=1e-7, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP32_REFINE,
+                       inner_tol=1e-4, max_outer=30, ortho=ortho)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        err = ((torch.linalg.norm(X32 - X64, dim=1) / torch.linalg.norm(X64, dim=1)).max()).item()
+        return {"workload": f"star_k16pi, N={op.N}, {nrhs} incident directions", "nrhs": nrhs,
+                "rhs_solves_per_s": nrhs / t32, "seconds": t32, "iterations": s32["iterations"],
+                "max_err_vs_fp64_ref": err, "fp64_ref_tol1e-10_rhs_solves_per_s": nrhs / t64,
+                "fp64_ref_iterations": s64["iterations"], "all_converged": s32["converged"] == nrhs}
+    finally:
+        op.close()
+
+
 def serving_run(n_requests, rate=20.0):
     """Poisson stream of solves over a warm pool of resident operators
     (continuous batching per operator, concurrent solves across operators)."""
@@ -142,6 +178,9 @@ def main():
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--ortho", choices=["cgs1", "cgs2"], default="cgs1",
                     help="Gram-Schmidt passes per Arnoldi step of the single-precision inner solves")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel schedules")
+    ap.add_argument("--multi-rhs", type=int, default=256,
+                    help="right-hand sides of the batched measurement on the kappa = 16 pi star (0 skips it)")
     ap.add_argument("--profile-solve", action="store_true",
                     help="profiling run: one single-precision-with-refinement solve only")
     ap.add_argument("--profile-applies", type=int, default=0,
@@ -169,6 +208,11 @@ def main():
     N = op.N
     n_int = int((key[:, 0] == 0).sum())
     f = torch.tensor(plane_wave(cfg, xy, cfg["incidence"][0]), dtype=torch.complex128, device="cuda")
+    tune = None
+    if not args.no_autotune:
+        t0 = time.time()
+        tune = {"fp32": op.autotune(1, binding.LS_C64), "fp64": op.autotune(1, binding.LS_C128)}
+        log(f"autotune {time.time() - t0:.1f}s {tune}")
     if args.profile_applies:
         for dt in (torch.complex64, torch.complex128):
             u = f.to(dt)
@@ -258,9 +302,18 @@ def main():
     byts = stage_bytes(st, N, n_int, 8, 8)
     achieved = byts[dom] / (p32[dom] * 1e-3) / 1e9
     kname = STAGE_KERNEL.get(dom, dom)
+    if tune and dom == "near_csr" and tune["fp32"]["csr_variant"] == 1:
+        kname = "k_near_csr<float>"
+    if tune and dom == "near_shared" and tune["fp32"]["near_variant"] == 1:
+        kname = "k_near_shared_mfma<float,2>"
     roof = {"kernel": kname, "stage": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": counter_traffic(kname),
             "algorithmic_bytes": int(byts[dom]), "avg_ms": round(p32[dom], 4)}
+
+    multi = None
+    if args.multi_rhs:
+        multi = multi_rhs_run(args.multi_rhs, ortho, not args.no_autotune)
+        log(f"multi-rhs {multi}")
 
     serving = None
     if args.serving_requests:
@@ -307,6 +360,8 @@ def main():
         "setup_s": setup_s,
         "resident_gb": op.resident_bytes() / 1e9,
         "roofline": roof,
+        "autotune": tune,
+        "multi_rhs": multi,
         "serving": serving,
         "cpu_baseline": cpu,
     }

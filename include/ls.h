@@ -157,6 +157,27 @@ ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec,
 ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, void* ws,
                            size_t ws_bytes, void* stream, double* stage_ms, int nstage);
 
+/* Kernel schedules chosen by ls_autotune for one precision. */
+typedef struct {
+  int fft_col_tile;     /* columns per workgroup of the column transforms */
+  int near_variant;     /* interior contraction: 0 double-buffered staging, 1 single-buffered */
+  int csr_variant;      /* boundary-patch rows: 0 four entries per lane, 1 one entry per lane */
+  double fft_ms;        /* best time of the transform stages with the chosen tile */
+  double near_ms;       /* best time of the interior contraction stage */
+  double csr_ms;        /* best time of the boundary-patch rows stage */
+  double apply_ms;      /* one apply with all choices in place */
+} ls_tune_result;
+
+/* Time the candidate schedules of the apply's tunable stages on this
+ * operator (each candidate: three applies of a fixed input, best stage time
+ * kept) and keep the fastest for later applies in precision prec.  Allocates
+ * and frees its own buffers; synchronous.  The choices change which kernels
+ * run, not the discrete operator; the near-field row variants sum each row in
+ * a different order, so single-precision results may change in rounding.
+ * Not to be called while other applies or solves on op are in flight.
+ * Errors: LS_EINVAL, LS_ENOMEM, LS_EDEVICE. */
+ls_status ls_autotune(ls_op* op, int nrhs, ls_prec prec, void* stream, ls_tune_result* result);
+
 typedef enum { LS_SOLVE_FP64 = 0, LS_SOLVE_FP32_REFINE = 1 } ls_solve_mode;
 
 /* Orthogonalisation of each new Krylov vector: classical Gram–Schmidt applied

@@ -45,6 +45,11 @@ class SolveStats(C.Structure):
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("apply_seconds", C.c_double)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("fft_col_tile", C.c_int), ("near_variant", C.c_int), ("csr_variant", C.c_int),
+                ("fft_ms", C.c_double), ("near_ms", C.c_double), ("csr_ms", C.c_double), ("apply_ms", C.c_double)]
+
+
 N2FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                    C.c_void_p)
 
@@ -72,6 +77,7 @@ def lib():
                                            C.c_size_t, C.c_void_p, P(C.c_double), C.c_int]),
             "ls_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, P(SolveOpts), P(SolveStats),
                                    C.c_void_p]),
+            "ls_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, P(TuneResult)]),
             "ls_status_str": (C.c_char_p, [C.c_int]),
             "ls_last_error": (C.c_char_p, []),
             "ls_host_build": (C.c_int, [P(Geometry), N2FN, C.c_void_p, C.c_double, P(Params), P(C.c_void_p)]),
@@ -255,6 +261,13 @@ class Operator:
         _check(lib().ls_apply_profile(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(),
                                       _stream(stream), out, 8), "ls_apply_profile")
         return dict(zip(self.STAGES, list(out)))
+
+    def autotune(self, nrhs=1, prec=LS_C64, stream=None):
+        """Time the candidate kernel schedules on this operator and keep the
+        fastest for later applies in precision `prec`; returns the choices."""
+        r = TuneResult()
+        _check(lib().ls_autotune(self._op, int(nrhs), int(prec), _stream(stream), C.byref(r)), "ls_autotune")
+        return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
     def solve(self, u_inc, u_tot, tol=1e-10, max_iter=2000, restart=100, mode=LS_SOLVE_FP64, inner_tol=1e-5,
               max_outer=20, use_x0=False, stream=None, raise_on_noconv=True, ortho=LS_ORTHO_CGS2, graph=False):

@@ -9,6 +9,7 @@
 #include <string>
 #include <map>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "ls.h"
@@ -281,8 +282,12 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   int lds_max = 0;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device);
   // FFT column tiles of 128 bytes per row (8 double or 16 float complex values)
+  // columns per workgroup of the column transforms: default 128-byte row
+  // segments (8 double / 16 float columns), at most what 150 KB of LDS holds;
+  // ls_autotune may pick another value up to that limit
   const int tc = std::max(1, std::min(8, (int)(150 * 1024 / (2 * (size_t)h.Pa * 16))));
-  size_t need = std::max(2 * (size_t)h.Pb * 16, 2 * (size_t)h.Pa * tc * 16);
+  const int tc32 = std::max(1, std::min(16, (int)(150 * 1024 / (2 * (size_t)h.Pa * 8))));
+  size_t need = std::max(2 * (size_t)h.Pb * 16, (size_t)150 * 1024);
   if (need > 160 * 1024) {
     ls_host_destroy(hb);
     delete op;
@@ -312,7 +317,8 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   a.Pa = b.Pa = h.Pa;
   a.Pb = b.Pb = h.Pb;
   a.ch = b.ch = h.p.cell_h;
-  a.tc = b.tc = tc;
+  a.tc = tc;
+  b.tc = tc32;
   a.kappa = b.kappa = kappa;
   a.nrows = b.nrows = (int)h.rows.size();
   a.csr_f64 = true;
@@ -539,6 +545,131 @@ ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec 
     stage_ms[i] = ms;
   }
   for (int i = 0; i < 9; ++i) (void)hipEventDestroy(ev[i]);
+  return out;
+}
+
+extern "C++" {
+namespace {
+// stage times of one apply (HIP events between the stages)
+template <typename T>
+ls_status timed_apply(ls_op* op, lsx::DevView<T>& d, const void* u, void* v, int nrhs, void* ws, hipStream_t st,
+                      hipEvent_t* ev, double* ms8) {
+  hipError_t e = lsx::launch_apply<T>(d, u, v, nrhs, ws, st, ev);
+  if (e != hipSuccess) return fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
+  if (hipEventSynchronize(ev[8]) != hipSuccess) return fail(LS_EDEVICE, "apply failed");
+  for (int i = 0; i < 8; ++i) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+    ms8[i] = ms;
+  }
+  (void)op;
+  return LS_OK;
+}
+
+template <typename T>
+ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, void* v, void* ws, hipStream_t st,
+                        hipEvent_t* ev, ls_tune_result* res) {
+  constexpr int reps = 3;
+  double ms8[8];
+  // best (smallest) of reps applies for the stages [s0, s1]
+  auto measure = [&](int s0, int s1, double* best) -> ls_status {
+    *best = 1e30;
+    for (int r = 0; r < reps; ++r) {
+      ls_status s = timed_apply<T>(op, d, u, v, nrhs, ws, st, ev, ms8);
+      if (s) return s;
+      double t = 0;
+      for (int i = s0; i <= s1; ++i) t += ms8[i];
+      *best = std::min(*best, t);
+    }
+    return LS_OK;
+  };
+  // column tile of the transforms (stages 2-4: forward, spectral, inverse)
+  const int tmax = std::max(1, (int)(150 * 1024 / (2 * (size_t)d.Pa * sizeof(T) * 2)));
+  int best_tc = d.tc;
+  double best = 1e30;
+  for (int tc : {2, 4, 8, 16, 32}) {
+    if (tc > tmax) break;
+    d.tc = tc;
+    double t;
+    ls_status s = measure(2, 4, &t);
+    if (s) return s;
+    if (t < best) {
+      best = t;
+      best_tc = tc;
+    }
+  }
+  d.tc = best_tc;
+  res->fft_col_tile = best_tc;
+  res->fft_ms = best;
+  // interior contraction variant (stage 6) and near-field rows variant (stage 7)
+  const int nvar = std::is_same<T, float>::value ? 2 : 1;
+  int bv = 0;
+  best = 1e30;
+  for (int var = 0; var < nvar; ++var) {
+    d.near_variant = var;
+    double t;
+    ls_status s = measure(6, 6, &t);
+    if (s) return s;
+    if (t < best) {
+      best = t;
+      bv = var;
+    }
+  }
+  d.near_variant = bv;
+  res->near_variant = bv;
+  res->near_ms = best;
+  bv = 0;
+  best = 1e30;
+  for (int var = 0; var < nvar; ++var) {
+    d.csr_variant = var;
+    double t;
+    ls_status s = measure(7, 7, &t);
+    if (s) return s;
+    if (t < best) {
+      best = t;
+      bv = var;
+    }
+  }
+  d.csr_variant = bv;
+  res->csr_variant = bv;
+  res->csr_ms = best;
+  double t;
+  ls_status s = measure(0, 7, &t);
+  if (s) return s;
+  res->apply_ms = t;
+  return LS_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+ls_status ls_autotune(ls_op* op, int nrhs, ls_prec prec, void* stream, ls_tune_result* result) {
+  if (!op || nrhs < 1 || !result) return fail(LS_EINVAL, "bad argument");
+  if (prec != LS_C128 && prec != LS_C64) return fail(LS_EINVAL, "unknown precision");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t c = prec == LS_C128 ? 16 : 8;
+  const size_t vb = c * (size_t)op->N * nrhs, wsb = ws_bytes(op, nrhs, prec);
+  void *u = nullptr, *v = nullptr, *ws = nullptr;
+  if (hipMalloc(&u, vb) != hipSuccess || hipMalloc(&v, vb) != hipSuccess || hipMalloc(&ws, wsb) != hipSuccess) {
+    if (u) (void)hipFree(u);
+    if (v) (void)hipFree(v);
+    return fail(LS_ENOMEM, "autotune buffers");
+  }
+  ls_status out = LS_OK;
+  hipEvent_t ev[9] = {};
+  for (int i = 0; i < 9 && out == LS_OK; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) out = fail(LS_EDEVICE, "hipEventCreate");
+  // a fixed nonzero input (byte pattern 0x3f: about 0.75 in float, 4.8e-4 in double)
+  if (out == LS_OK && hipMemsetAsync(u, 0x3f, vb, st) != hipSuccess) out = fail(LS_EDEVICE, "memset");
+  *result = ls_tune_result{};
+  if (out == LS_OK)
+    out = prec == LS_C128 ? autotune_view<double>(op, op->d64, nrhs, u, v, ws, st, ev, result)
+                          : autotune_view<float>(op, op->d32, nrhs, u, v, ws, st, ev, result);
+  (void)hipStreamSynchronize(st);
+  for (int i = 0; i < 9; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  (void)hipFree(u);
+  (void)hipFree(v);
+  (void)hipFree(ws);
   return out;
 }
 

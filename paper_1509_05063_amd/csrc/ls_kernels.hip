@@ -1410,7 +1410,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   mark(2);
   // a2: forward transforms of all 4 arrays per rhs
   const int nbatch = nrhs * 4;
-  const int TCP = sizeof(T) == 8 ? d.tc : 2 * d.tc;   // 128-byte column tiles in either precision
+  const int TCP = d.tc;   // columns per workgroup in the column transforms
   {
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     // rows a >= na are zero padding: their transforms stay zero
@@ -1461,7 +1461,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     const int64_t gsz = (int64_t)Gw * Gw;
     hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, st, u, grid, d.dw,
                        d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
-    if constexpr (std::is_same<T, float>::value) {
+    if (std::is_same<T, float>::value && d.near_variant == 0) {
       hipLaunchKernelGGL(k_near_shared_mfma_db, dim3((d.nicell + 15) / 16, nrhs), dim3(256), 0, st,
                          (const float2*)grid, (float2*)v, (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw,
                          d.nicell, d.N, (float)k2);
@@ -1490,7 +1490,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
                            d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
     } else {
-      if (d.coloff && std::is_same<T, float>::value)
+      if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
         hipLaunchKernelGGL(k_near_csr4, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.colbase,
                            d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
       else if (d.coloff)

@@ -18,6 +18,10 @@ struct DevView {
   int64_t N = 0;
   int ncell = 0, nicell = 0, S = 0, U = 0, F = 0, q = 0, L = 0, na = 0, nb = 0, Pa = 0, Pb = 0, ch = 0;
   int max_nb = 0, tc = 1, nrows = 0;
+  // kernel variants chosen by ls_autotune: near_variant 0 = double-buffered
+  // interior contraction (single precision), 1 = single-buffered; csr_variant
+  // 0 = four entries per lane (single precision, 16-bit offsets), 1 = one
+  int near_variant = 0, csr_variant = 0;
   bool csr_f64 = true;
   double kappa = 0;
   const void *Psh = nullptr, *PshT = nullptr, *Pbd = nullptr, *Ish = nullptr, *Ibd = nullptr, *Toff = nullptr, *Wsh = nullptr;

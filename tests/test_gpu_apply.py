@@ -107,3 +107,24 @@ def test_solve_matches_oracle_lu(disc, mode, ortho, restart):
     print(f"solve mode {mode} ortho {ortho} restart {restart}: {st} vs LU {err:.3e} vs Mie {emie:.3e}", flush=True)
     assert err < 1e-8
     assert emie < 5e-3
+
+
+def test_autotune_keeps_the_operator(disc):
+    """The tuned schedules apply the same operator: every row still matches
+    the oracle (FP64 to 1e-8, FP32 to 1e-4), and the choices are in range."""
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    x_or = random_density(orc.pts["key"], seed=7)
+    y_or = A @ x_or
+    for prec, dt, tol in ((binding.LS_C128, torch.complex128, 1e-8), (binding.LS_C64, torch.complex64, 1e-4)):
+        ch = op.autotune(nrhs=1, prec=prec)
+        print(f"autotune prec {prec}: {ch}", flush=True)
+        assert ch["fft_col_tile"] in (2, 4, 8, 16, 32) and ch["near_variant"] in (0, 1) and ch["csr_variant"] in (0, 1)
+        u = torch.tensor(_to_lib(x_or, p, op.N), dtype=dt, device="cuda")
+        v = torch.empty_like(u)
+        op.apply(u, v)
+        torch.cuda.synchronize()
+        y = v.cpu().numpy().astype(complex)[p]
+        err = np.linalg.norm(y - y_or) / np.linalg.norm(y_or)
+        assert err < tol, (prec, err)
