@@ -136,13 +136,15 @@ def multi_rhs_run(nrhs, ortho, autotune):
         op.close()
 
 
-def serving_run(n_requests, rate=20.0):
+def serving_run(n_requests, rate=20.0, ortho=None):
     """Poisson stream of solves over a warm pool of resident operators
     (continuous batching per operator, concurrent solves across operators)."""
     from paper_1509_05063_amd.inputs import serving_pool, serving_trace
     from paper_1509_05063_amd.serve import Server, latency_stats, replay
     pool = serving_pool()
-    srv = Server(budget_bytes=200e9, max_batch=16, workers=4, keep_results=False)
+    from paper_1509_05063_amd import binding
+    srv = Server(budget_bytes=200e9, max_batch=16, workers=4, keep_results=False,
+                 ortho=binding.LS_ORTHO_CGS1 if ortho is None else ortho)
     try:
         t0 = time.time()
         for c in pool:                      # warm: build every operator once
@@ -157,7 +159,7 @@ def serving_run(n_requests, rate=20.0):
         for r in reqs:
             iters[r.key] = max(iters.get(r.key, 0), r.stats["iterations"])
         return {"requests": len(reqs), "rate_per_s": rate, "operators": len(pool),
-                "N_range": [min(op.N for op in srv.ops.values()), max(op.N for op in srv.ops.values())],
+                "N_range": [min(r.N for r in reqs), max(r.N for r in reqs)],
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch"],
                 "solves_per_s": len(reqs) / wall, "all_converged": conv == len(reqs), "warmup_s": warm,
                 "max_iterations": iters}
@@ -317,7 +319,7 @@ def main():
 
     serving = None
     if args.serving_requests:
-        serving = serving_run(args.serving_requests)
+        serving = serving_run(args.serving_requests, ortho=ortho)
         log(f"serving {serving}")
 
     cpu = None

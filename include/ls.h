@@ -220,6 +220,73 @@ typedef struct {
 ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs,
                    const ls_solve_opts* opts, ls_solve_stats* stats, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving.  A server owns worker threads (one HIP stream each, on the device
+ * current at ls_server_create) and a set of registered scatterers (operator
+ * descriptions, keyed by the caller).  A request asks for the total field of
+ * one scatterer under the plane wave exp(i kappa (cos a, sin a).x) (Sec. 1,
+ * incident field).  Operators are built on first use and stay resident (near
+ * weights, projection/interpolation matrices, Green's function spectra) while
+ * the HBM budget allows; idle ones are evicted least recently used first.
+ * While a scatterer's solve runs, further requests for it queue and become
+ * the right-hand sides of its next solve (up to max_batch); solves of
+ * different scatterers run concurrently.  A batched solve advances every
+ * right-hand side independently and freezes converged ones, so a request's
+ * result is bitwise the same alone and in any mix.  The n2 callback is called
+ * from a worker thread when its operator is built.
+ * --------------------------------------------------------------------------- */
+typedef struct ls_server ls_server;
+
+typedef struct {
+  int max_batch;        /* right-hand sides per solve */
+  int workers;          /* concurrent solves */
+  double tol;           /* as ls_solve_opts */
+  int max_iter;
+  int restart;
+  ls_solve_mode mode;
+  double inner_tol;
+  int max_outer;
+  ls_ortho ortho;
+} ls_server_opts;
+
+typedef struct {
+  int64_t N;            /* unknowns of the request's operator */
+  int batch;            /* right-hand sides in the solve that served it */
+  ls_solve_stats stats; /* of that solve */
+  double t_submit, t_start, t_done;   /* seconds since ls_server_create */
+} ls_request_info;
+
+typedef struct {
+  size_t resident_bytes;
+  int resident_ops;
+  int64_t queued, running, evictions;
+} ls_server_info;
+
+/* budget_bytes: device memory for resident operators plus solver scratch.
+ * Errors: LS_EINVAL. */
+ls_status ls_server_create(size_t budget_bytes, const ls_server_opts* opts, ls_server** out);
+/* Register a scatterer under `key` (arguments as ls_create; the structs are
+ * copied, ctx and n2 must stay valid while the server lives).  Errors:
+ * LS_EINVAL (duplicate key, bad arguments). */
+ls_status ls_server_add_operator(ls_server* s, uint64_t key, const ls_geometry* geom, ls_n2_fn n2, void* ctx,
+                                 double kappa, const ls_params* params);
+/* Queue a plane-wave request (incidence angle alpha) for scatterer `key`;
+ * returns at once with a ticket.  Errors: LS_EINVAL (unknown key). */
+ls_status ls_server_submit(ls_server* s, uint64_t key, double alpha, int64_t* ticket);
+/* LS_ENOTREADY while the request is queued or running.  When done: the solve's
+ * status (LS_OK, LS_ENOCONV with the best iterate, or its error); u_tot (host,
+ * >= 2N doubles = cap, may be NULL) receives the total field in the
+ * operator's point order, info (may be NULL) the timings and solve stats. */
+ls_status ls_server_poll(ls_server* s, int64_t ticket, double* u_tot, int64_t cap, ls_request_info* info);
+/* Forget a finished request. */
+ls_status ls_server_release(ls_server* s, int64_t ticket);
+/* Node coordinates (2N doubles) of a scatterer's operator once it has been
+ * built (LS_ENOTREADY before). */
+ls_status ls_server_points(ls_server* s, uint64_t key, double* xy, int64_t cap, int64_t* N);
+ls_status ls_server_stats(ls_server* s, ls_server_info* info);
+/* Stop the workers (after their running solves), release every operator. */
+void ls_server_destroy(ls_server* s);
+
 const char* ls_status_str(ls_status s);
 const char* ls_last_error(void);
 

@@ -45,6 +45,22 @@ class SolveStats(C.Structure):
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("apply_seconds", C.c_double)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("max_batch", C.c_int), ("workers", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("restart", C.c_int), ("mode", C.c_int), ("inner_tol", C.c_double), ("max_outer", C.c_int),
+                ("ortho", C.c_int)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("N", C.c_int64), ("batch", C.c_int), ("stats", SolveStats), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("resident_bytes", C.c_size_t), ("resident_ops", C.c_int), ("queued", C.c_int64),
+                ("running", C.c_int64), ("evictions", C.c_int64)]
+
+
 class TuneResult(C.Structure):
     _fields_ = [("fft_col_tile", C.c_int), ("near_variant", C.c_int), ("csr_variant", C.c_int),
                 ("fft_ms", C.c_double), ("near_ms", C.c_double), ("csr_ms", C.c_double), ("apply_ms", C.c_double)]
@@ -78,6 +94,15 @@ def lib():
             "ls_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, P(SolveOpts), P(SolveStats),
                                    C.c_void_p]),
             "ls_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, P(TuneResult)]),
+            "ls_server_create": (C.c_int, [C.c_size_t, P(ServerOpts), P(C.c_void_p)]),
+            "ls_server_add_operator": (C.c_int, [C.c_void_p, C.c_uint64, P(Geometry), N2FN, C.c_void_p,
+                                                 C.c_double, P(Params)]),
+            "ls_server_submit": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double, P(C.c_int64)]),
+            "ls_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, P(RequestInfo)]),
+            "ls_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
+            "ls_server_points": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int64, P(C.c_int64)]),
+            "ls_server_stats": (C.c_int, [C.c_void_p, P(ServerInfo)]),
+            "ls_server_destroy": (None, [C.c_void_p]),
             "ls_status_str": (C.c_char_p, [C.c_int]),
             "ls_last_error": (C.c_char_p, []),
             "ls_host_build": (C.c_int, [P(Geometry), N2FN, C.c_void_p, C.c_double, P(Params), P(C.c_void_p)]),

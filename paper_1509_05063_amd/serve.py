@@ -1,40 +1,40 @@
-"""Serving loop for Lippmann–Schwinger solves on one GPU.
+"""Serving loop for Lippmann–Schwinger solves on one GPU (Python face of the
+library's ls_server_* calls).
 
-Requests name a scatterer (a workload configuration) and an incidence
-angle.  The server keeps operators resident in HBM (set-up once: nodes,
-near-field weights, equivalent-source matrices and the FFT'd Green's kernels),
-admits them under a byte budget (least recently used idle operators are
-evicted when a new one does not fit), and batches requests on the same
+Requests name a scatterer (a workload configuration) and an incidence angle.
+The native server keeps operators resident in HBM (set-up once: nodes,
+near-field weights, equivalent-source matrices and the FFT'd Green's
+kernels), admits them under a byte budget (least recently used idle operators
+are evicted when a new one does not fit), and batches requests on the same
 operator as extra right-hand sides of one solve.  Batching is continuous:
-while an operator's solve runs, new requests for it queue up and form its
-next batch; solves on different operators run at the same time in their own
-worker threads and HIP streams.  All arithmetic happens in the C ABI
-(ls_solve); this module only schedules.
+while an operator's solve runs, new requests for it queue up and form its next
+batch; solves on different operators run at the same time in their own worker
+threads and HIP streams.  This module only registers scatterers, submits,
+polls and keeps latency records.
 
-Results are deterministic per right-hand side: a request gets the same
-answer alone or inside any batch (the batched solve advances every
-right-hand side independently and freezes the ones that have converged).
+Results are deterministic per right-hand side (the batched solve advances
+every right-hand side independently and freezes the ones that have
+converged), so a request gets the same answer alone or inside any batch.
 """
-import collections
-import math
-import threading
+import ctypes as C
 import time
 
 import numpy as np
 
 from . import binding
-from .inputs import n2_function, plane_wave
+from .inputs import n2_function
 
 
 class Request:
-    __slots__ = ("ticket", "key", "cfg", "alpha", "arrival", "start", "done", "result", "stats", "batch")
+    __slots__ = ("ticket", "key", "cfg", "alpha", "arrival", "done", "latency", "result", "stats", "batch", "N",
+                 "status")
 
     def __init__(self, ticket, key, cfg, alpha, arrival):
         self.ticket, self.key, self.cfg, self.alpha, self.arrival = ticket, key, cfg, alpha, arrival
-        self.start = self.done = None
-        self.result = None
-        self.stats = None
+        self.done = self.latency = self.result = self.stats = None
         self.batch = 0
+        self.N = 0
+        self.status = None
 
 
 class Server:
@@ -42,148 +42,94 @@ class Server:
     max_batch: right-hand sides per solve.  workers: concurrent solves."""
 
     def __init__(self, budget_bytes, max_batch=16, workers=4, tol=1e-7, restart=60, inner_tol=1e-4,
-                 keep_results=True):
-        import torch
-        self.torch = torch
-        self.budget = int(budget_bytes)
-        self.max_batch = max_batch
+                 keep_results=True, max_iter=4000, max_outer=30, ortho=binding.LS_ORTHO_CGS2):
+        L = binding.lib()
         self.tol, self.restart, self.inner_tol = tol, restart, inner_tol
         self.keep_results = keep_results
-        self.lock = threading.Condition()
-        self.queues = collections.OrderedDict()       # key -> deque of Request
-        self.ops = collections.OrderedDict()          # key -> binding.Operator (LRU order)
-        self.busy = set()                             # keys with a solve in flight
+        opts = binding.ServerOpts(int(max_batch), int(workers), float(tol), int(max_iter), int(restart),
+                                  binding.LS_SOLVE_FP32_REFINE, float(inner_tol), int(max_outer), int(ortho))
+        self._srv = C.c_void_p()
+        binding._check(L.ls_server_create(C.c_size_t(int(budget_bytes)), C.byref(opts), C.byref(self._srv)),
+                       "ls_server_create")
+        self._ids = {}            # scatterer key -> server key
+        self._keep = []           # callbacks and structs the server refers to
         self.tickets = {}
-        self.next_ticket = 0
-        self.stop = False
-        self.evictions = 0
-        self.threads = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(workers)]
-        for t in self.threads:
-            t.start()
+
+    def _register(self, key, cfg):
+        if key in self._ids:
+            return self._ids[key]
+        sid = len(self._ids)
+        g, p = binding.geometry_from(cfg), binding.params_from(cfg)
+        cb = binding._n2_callback(n2_function(cfg))
+        self._keep.append((g, p, cb))
+        binding._check(binding.lib().ls_server_add_operator(self._srv, sid, C.byref(g), cb, None,
+                                                            float(cfg["kappa"]), C.byref(p)),
+                       "ls_server_add_operator")
+        self._ids[key] = sid
+        return sid
 
     # ------------------------------------------------------------ client API
     def submit(self, key, cfg, alpha, arrival=None):
-        with self.lock:
-            t = self.next_ticket
-            self.next_ticket += 1
-            r = Request(t, key, cfg, alpha, time.perf_counter() if arrival is None else arrival)
-            self.tickets[t] = r
-            self.queues.setdefault(key, collections.deque()).append(r)
-            self.lock.notify_all()
-            return t
+        sid = self._register(key, cfg)
+        t = C.c_int64()
+        binding._check(binding.lib().ls_server_submit(self._srv, sid, float(alpha), C.byref(t)), "ls_server_submit")
+        r = Request(t.value, key, cfg, alpha, time.perf_counter() if arrival is None else arrival)
+        self.tickets[t.value] = r
+        return t.value
 
     def poll(self, ticket):
         """The finished request, or None while it is pending."""
-        with self.lock:
-            r = self.tickets[ticket]
-            return r if r.done is not None else None
+        r = self.tickets[ticket]
+        if r.done is not None:
+            return r
+        L = binding.lib()
+        info = binding.RequestInfo()
+        rc = L.ls_server_poll(self._srv, ticket, None, 0, C.byref(info))
+        if rc == binding.LS_ENOTREADY:
+            return None
+        if self.keep_results and rc in (binding.LS_OK, binding.LS_ENOCONV):
+            buf = np.empty(info.N, complex)
+            L.ls_server_poll(self._srv, ticket, buf.ctypes.data, 2 * info.N, C.byref(info))
+            r.result = buf
+        s = info.stats
+        r.stats = {"iterations": s.iterations, "outer": s.outer, "converged": s.converged,
+                   "rel_residual": s.rel_residual, "seconds": s.seconds}
+        r.status, r.batch, r.N = rc, info.batch, info.N
+        r.latency = info.t_done - info.t_submit
+        r.done = r.arrival + r.latency
+        L.ls_server_release(self._srv, ticket)
+        return r
 
     def drain(self):
-        with self.lock:
-            while any(r.done is None for r in self.tickets.values()):
-                self.lock.wait(0.05)
+        pending = [t for t, r in self.tickets.items() if r.done is None]
+        while pending:
+            pending = [t for t in pending if self.poll(t) is None]
+            if pending:
+                time.sleep(0.002)
+
+    def points(self, key):
+        n = C.c_int64()
+        L = binding.lib()
+        binding._check(L.ls_server_points(self._srv, self._ids[key], None, 0, C.byref(n)), "ls_server_points")
+        xy = np.empty((n.value, 2))
+        binding._check(L.ls_server_points(self._srv, self._ids[key], xy.ctypes.data, 2 * n.value, C.byref(n)),
+                       "ls_server_points")
+        return xy
+
+    def info(self):
+        i = binding.ServerInfo()
+        binding._check(binding.lib().ls_server_stats(self._srv, C.byref(i)), "ls_server_stats")
+        return {"resident_bytes": i.resident_bytes, "resident_ops": i.resident_ops, "queued": i.queued,
+                "running": i.running, "evictions": i.evictions}
+
+    @property
+    def evictions(self):
+        return self.info()["evictions"]
 
     def close(self):
-        with self.lock:
-            self.stop = True
-            self.lock.notify_all()
-        for t in self.threads:
-            t.join()
-        for op in self.ops.values():
-            op.close()
-        self.ops.clear()
-
-    # ------------------------------------------------------------- internals
-    def _resident(self):
-        return sum(op.resident_bytes() for op in self.ops.values())
-
-    @staticmethod
-    def _solve_bytes(N, nrhs, restart):
-        # Krylov basis + work vectors (complex double) + FP32 copies + apply workspace (estimate)
-        return 16 * N * nrhs * (restart + 7) + 16 * N * nrhs + (64 << 20) * nrhs
-
-    def _admit(self, key, n_est):
-        """Make room for operator `key` (lock held): evict idle operators in
-        least-recently-used order until it and one more solve fit the budget.
-        False when the remaining operators are all busy (the caller waits)."""
-        need = self._solve_bytes(n_est, self.max_batch, self.restart)
-        while True:
-            op_bytes = 0 if key in self.ops else int(n_est * 8000)   # resident estimate per unknown
-            if self._resident() + op_bytes + need * (len(self.busy) + 1) <= self.budget:
-                return True
-            victim = next((k for k in self.ops if k not in self.busy and k != key), None)
-            if victim is None:
-                # nothing left to evict: run alone if no other solve is in flight
-                return not (self.busy - {key})
-            self.ops.pop(victim).close()
-            self.evictions += 1
-
-    def _pick(self):
-        for key, q in self.queues.items():
-            if q and key not in self.busy:
-                return key
-        return None
-
-    def _worker(self, wid):
-        torch = self.torch
-        stream = torch.cuda.Stream()
-        while True:
-            with self.lock:
-                key = None
-                while not self.stop:
-                    key = self._pick()
-                    if key is not None:
-                        break
-                    self.lock.wait(0.05)
-                if self.stop:
-                    return
-                q = self.queues[key]
-                cfg = q[0].cfg
-                n_est = self.ops[key].N if key in self.ops else _estimate_points(cfg)
-                if not self._admit(key, n_est):
-                    self.lock.wait(0.05)
-                    continue
-                batch = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
-                self.busy.add(key)
-                op = self.ops.get(key)
-                if op is not None:
-                    self.ops.move_to_end(key)
-            t0 = time.perf_counter()
-            for r in batch:
-                r.start = t0
-            if op is None:
-                op = binding.Operator(cfg, n2_function(cfg))
-                with self.lock:
-                    self.ops[key] = op
-            xy, _ = op.points()
-            with torch.cuda.stream(stream):
-                F = torch.tensor(np.stack([plane_wave(cfg, xy, r.alpha) for r in batch]),
-                                 dtype=torch.complex128, device="cuda")
-                X = torch.empty_like(F)
-                st = op.solve(F, X, tol=self.tol, restart=self.restart, max_iter=4000,
-                              mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=self.inner_tol, max_outer=30,
-                              stream=stream, raise_on_noconv=False)
-                stream.synchronize()
-                host = X.cpu().numpy() if self.keep_results else None
-            t1 = time.perf_counter()
-            with self.lock:
-                for k, r in enumerate(batch):
-                    r.done = t1
-                    r.stats = st
-                    r.batch = len(batch)
-                    if host is not None:
-                        r.result = host[k]
-                self.busy.discard(key)
-                self.lock.notify_all()
-
-
-def _estimate_points(cfg):
-    """Rough node count of a configuration (for admission before set-up)."""
-    a = cfg["shape"]["a"]
-    area = math.pi * (1 + a * a / 2)
-    s_b = cfg["pou"]["s_b"]
-    b = cfg["band"]
-    return int(area * s_b * s_b / cfg["h"] ** 2 + b["N1"] * (b["N2"] + 1))
+        if self._srv:
+            binding.lib().ls_server_destroy(self._srv)
+            self._srv = None
 
 
 def latency_stats(reqs):
