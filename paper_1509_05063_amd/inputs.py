@@ -54,6 +54,9 @@ def config(name):
                 intervals (about 950k points)
     star_k16pi  the same star at kappa = 16 pi, h = 1/256, band 2048 x 32
                 (about 270k points; 256 incident directions)
+    star_sincos_k2  the same star at kappa = 2 with the smooth variable index
+                n = sin(pi x1) cos(pi x2) (vanishing on lines through the
+                scatterer), h = 1/32, band 0.8 < s < 1 with 128 x 16 intervals
     """
     if name == "disc_k2pi":
         c = _base(TWO_PI, 1.0 / 32, 0.0, 0, 0.8, 64, 16, 0.8, 0.95)
@@ -70,6 +73,11 @@ def config(name):
         c["n2"] = {"kind": "gauss", "base": 1.0, "amp": 0.8, "decay": 4.0}
         c["incidence"] = [TWO_PI * r / 256 for r in range(256)]
         c["gmres"] = {"tol": 1e-8, "restart": 60}
+    elif name == "star_sincos_k2":
+        c = _base(2.0, 1.0 / 32, 0.3, 5, 0.8, 128, 16, 0.8, 0.95)
+        c["n2"] = {"kind": "sincos"}
+        c["incidence"] = [0.0]
+        c["gmres"] = {"tol": 1e-10, "restart": 100}
     else:
         raise KeyError(name)
     c["name"] = name
@@ -99,6 +107,8 @@ def n2_function(cfg):
     if spec["kind"] == "gauss":
         b, a, d = float(spec["base"]), float(spec["amp"]), float(spec["decay"])
         return lambda x, on_b: b + a * np.exp(-d * (x[:, 0] ** 2 + x[:, 1] ** 2))
+    if spec["kind"] == "sincos":
+        return lambda x, on_b: (np.sin(math.pi * x[:, 0]) * np.cos(math.pi * x[:, 1])) ** 2
     if spec["kind"] == "zero":
         return lambda x, on_b: np.zeros(x.shape[0])
     raise KeyError(spec["kind"])
