@@ -14,4 +14,5 @@ Modules:
   op2d    the discrete operator I + kappa^2 K_h (dense / row by row)
   mie     closed forms: Mie series (2-D, 3-D), volume potential of a constant
   solve   restarted complex GMRES, dense LU
+  exterior  scattered field off the scatterer by direct summation
 """

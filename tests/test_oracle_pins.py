@@ -251,6 +251,17 @@ def test_disc_solve_against_mie_and_gmres_against_lu(disc_setup):
     ug, info = gmres(lambda z: A @ z, f, tol=1e-10, restart=100)
     assert info["converged"]
     assert np.linalg.norm(ug - u) / np.linalg.norm(u) < 1e-8
+    # the scattered field off the disc, from the discrete solution, against
+    # the Mie series' scattered part (total minus incident)
+    from oracle.exterior import scattered_field
+    rng = np.random.default_rng(3)
+    rad = rng.uniform(1.15, 2.5, 64)
+    th = rng.uniform(0, 2 * np.pi, 64)
+    xt = np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1)
+    us = scattered_field(S, u, xt)
+    ex_s = mie2d_total(cfg["kappa"], 1.5, 1.0, xt) - np.exp(1j * cfg["kappa"] * xt[:, 0])
+    es = np.linalg.norm(us - ex_s) / np.linalg.norm(ex_s)
+    assert es < 5e-3, es
 
 
 def test_interior_stencil_constant_density(disc_setup):
