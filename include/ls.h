@@ -221,6 +221,35 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs,
                    const ls_solve_opts* opts, ls_solve_stats* stats, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The field off the scatterer.  Outside the scatterer the Lippmann–Schwinger
+ * equation (Sec. 1, eq:-Lippmann) gives the scattered field as
+ * u^s = u - u^i = -kappa^2 K[u], with a smooth integrand; the paper plots it
+ * around the scatterer (Sec. 4 figures).  It is evaluated with the
+ * operator's plain quadrature: the accelerator for the sources in cells not
+ * adjacent to the target's cell (the target is fitted like a boundary-patch
+ * node of its cell) and a stored row G(|x - y_j|) c_j for the sources in the
+ * adjacent cells.  Near the interface (closer than a few grid spacings) the
+ * plain rule loses accuracy, as any fixed quadrature of a nearly singular
+ * integrand does.
+ * --------------------------------------------------------------------------- */
+typedef struct ls_targets ls_targets;
+
+/* A set of n target points xy (host, 2n doubles) strictly outside the
+ * scatterer and inside the operator's cell box (the axis-aligned box of
+ * cells that cover the nodes).  Builds the per-target rows on the host and
+ * uploads them.  Errors: LS_EINVAL (a target inside/on the scatterer or
+ * outside the box), LS_ENOMEM. */
+ls_status ls_targets_create(ls_op* op, int64_t n, const double* xy, ls_targets** out);
+void ls_targets_destroy(ls_targets* tg);
+
+/* us [nrhs][n] (device, complex double) = scattered field at the targets
+ * for the totals u_tot [nrhs][N] (device, complex double, operator order, as
+ * returned by ls_solve).  Asynchronous on `stream`; ws as for an LS_C128
+ * apply of nrhs vectors.  Errors: LS_EINVAL, LS_EDEVICE. */
+ls_status ls_scattered_field(ls_op* op, const ls_targets* tg, const void* u_tot, int nrhs, void* us, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Serving.  A server owns worker threads (one HIP stream each, on the device
  * current at ls_server_create) and a set of registered scatterers (operator
  * descriptions, keyed by the caller).  A request asks for the total field of

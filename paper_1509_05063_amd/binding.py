@@ -103,6 +103,10 @@ def lib():
             "ls_server_points": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int64, P(C.c_int64)]),
             "ls_server_stats": (C.c_int, [C.c_void_p, P(ServerInfo)]),
             "ls_server_destroy": (None, [C.c_void_p]),
+            "ls_targets_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, P(C.c_void_p)]),
+            "ls_targets_destroy": (None, [C.c_void_p]),
+            "ls_scattered_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                             C.c_size_t, C.c_void_p]),
             "ls_status_str": (C.c_char_p, [C.c_int]),
             "ls_last_error": (C.c_char_p, []),
             "ls_host_build": (C.c_int, [P(Geometry), N2FN, C.c_void_p, C.c_double, P(Params), P(C.c_void_p)]),
@@ -286,6 +290,24 @@ class Operator:
         _check(lib().ls_apply_profile(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(),
                                       _stream(stream), out, 8), "ls_apply_profile")
         return dict(zip(self.STAGES, list(out)))
+
+    def scattered_field(self, u_tot, xy, stream=None):
+        """Scattered field u^s = -kappa^2 K[u] at points xy (M, 2) outside the
+        scatterer, for totals u_tot ([nrhs,] N complex128, device)."""
+        import torch
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tg = C.c_void_p()
+        _check(lib().ls_targets_create(self._op, xy.shape[0], xy.ctypes.data, C.byref(tg)), "ls_targets_create")
+        try:
+            nrhs = 1 if u_tot.dim() == 1 else u_tot.shape[0]
+            out = torch.empty((nrhs, xy.shape[0]), dtype=torch.complex128, device=u_tot.device)
+            ws = self.workspace(nrhs, LS_C128)
+            _check(lib().ls_scattered_field(self._op, tg, _ptr(u_tot), nrhs, _ptr(out), _ptr(ws), ws.numel(),
+                                            _stream(stream)), "ls_scattered_field")
+            torch.cuda.synchronize()
+        finally:
+            lib().ls_targets_destroy(tg)
+        return out[0] if u_tot.dim() == 1 else out
 
     def autotune(self, nrhs=1, prec=LS_C64, stream=None):
         """Time the candidate kernel schedules on this operator and keep the

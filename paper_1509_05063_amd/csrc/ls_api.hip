@@ -61,6 +61,22 @@ struct ls_op {
   // solver buffer, N) -> executable graph; capture runs on cap_stream
   std::map<GraphKey, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
+  // host data kept for evaluating the field off the scatterer
+  struct {
+    std::vector<double> cw;                         // plain quadrature weights c_j
+    std::vector<int32_t> cell_map, cell_start, cell_nint, cell_nb;
+    std::vector<lsx::cd> Bp;                        // cell Dirichlet fit
+    int L = 0, nfb = 0, F = 0;
+    int64_t c_lo = 0;
+    double H = 0, shape_a = 0;
+    int shape_k = 0;
+  } ext;
+};
+
+struct ls_targets {
+  int64_t n = 0;
+  std::vector<void*> allocs;
+  lsx::TargetView view;
 };
 
 namespace {
@@ -149,6 +165,114 @@ size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
 }  // namespace
 
 extern "C" {
+
+// Field off the scatterer (see ls.h): targets sorted by cell of the lattice
+// box, one Dirichlet-fit row and one row of adjacent-cell sources each.
+ls_status ls_targets_create(ls_op* op, int64_t n, const double* xy, ls_targets** out) {
+  if (!op || !out || n < 1 || !xy) return fail(LS_EINVAL, "bad argument");
+  *out = nullptr;
+  const auto& x = op->ext;
+  const double H = x.H, kappa = op->kappa;
+  const int L = x.L, F = x.F;
+  std::vector<int64_t> cell(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double px = xy[2 * i], py = xy[2 * i + 1];
+    const double rr = std::hypot(px, py), th = std::atan2(py, px);
+    const double R = 1.0 + x.shape_a * std::cos(x.shape_k * th);
+    if (!(rr > R * (1.0 + 1e-12))) return fail(LS_EINVAL, "target inside or on the scatterer");
+    const int64_t cx = (int64_t)std::floor(px / H) - x.c_lo, cy = (int64_t)std::floor(py / H) - x.c_lo;
+    if (cx < 0 || cy < 0 || cx >= L || cy >= L) return fail(LS_EINVAL, "target outside the operator's cell box");
+    cell[i] = cy * L + cx;
+  }
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cell[a] < cell[b]; });
+  std::vector<int32_t> cxy, start;
+  for (int64_t k = 0; k < n; ++k) {
+    if (k == 0 || cell[order[k]] != cell[order[k - 1]]) {
+      cxy.push_back((int32_t)(cell[order[k]] % L));
+      cxy.push_back((int32_t)(cell[order[k]] / L));
+      start.push_back((int32_t)k);
+    }
+  }
+  start.push_back((int32_t)n);
+  // fit rows and adjacent-cell sources, per target (in sorted order)
+  std::vector<lsx::cd> fit((size_t)n * F);
+  std::vector<std::vector<int32_t>> rc(n);
+  std::vector<std::vector<lsx::cd>> rv(n);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t i = order[k];
+    const int cx = (int)(cell[i] % L), cy = (int)(cell[i] / L);
+    const double rel[2] = {xy[2 * i] - (cx + x.c_lo) * H, xy[2 * i + 1] - (cy + x.c_lo) * H};
+    lsx::fit_row(x.Bp, x.nfb, F, kappa, H, rel, &fit[(size_t)k * F]);
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int nx = cx + ox, ny = cy + oy;
+        if (nx < 0 || ny < 0 || nx >= L || ny >= L) continue;
+        const int c = x.cell_map[(size_t)ny * L + nx];
+        if (c < 0) continue;
+        const int64_t j0 = x.cell_start[c], j1 = j0 + x.cell_nint[c] + x.cell_nb[c];
+        for (int64_t j = j0; j < j1; ++j) {
+          const double d = std::hypot(xy[2 * i] - op->xy[2 * j], xy[2 * i + 1] - op->xy[2 * j + 1]);
+          rc[k].push_back((int32_t)j);
+          rv[k].push_back(lsx::green2d(kappa, d) * x.cw[j]);
+        }
+      }
+  }
+  std::vector<int64_t> rowptr(n + 1, 0);
+  for (int64_t k = 0; k < n; ++k) rowptr[k + 1] = rowptr[k] + (int64_t)rc[k].size();
+  std::vector<int32_t> cols((size_t)std::max<int64_t>(rowptr[n], 1), 0);
+  std::vector<lsx::cd> vals((size_t)std::max<int64_t>(rowptr[n], 1), 0.0);
+  for (int64_t k = 0; k < n; ++k) {
+    std::copy(rc[k].begin(), rc[k].end(), cols.begin() + rowptr[k]);
+    std::copy(rv[k].begin(), rv[k].end(), vals.begin() + rowptr[k]);
+  }
+  auto* tg = new (std::nothrow) ls_targets();
+  if (!tg) return fail(LS_ENOMEM, "host allocation");
+  auto put = [&](const void* src, size_t bytes, const void** dst) -> bool {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return false;
+    tg->allocs.push_back(p);
+    *dst = p;
+    return hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  lsx::TargetView& v = tg->view;
+  v.n = n;
+  v.ncell = (int)(start.size() - 1);
+  const void *a1, *a2, *a3, *a5, *a6;
+  bool ok = put(cxy.data(), cxy.size() * 4, &a1) && put(start.data(), start.size() * 4, &a2) &&
+            put(order.data(), order.size() * 4, &a3) && put(fit.data(), fit.size() * 16, &v.fit) &&
+            put(rowptr.data(), rowptr.size() * 8, &a5) && put(cols.data(), cols.size() * 4, &a6) &&
+            put(vals.data(), vals.size() * 16, &v.vals);
+  if (!ok) {
+    ls_targets_destroy(tg);
+    return fail(LS_ENOMEM, "target upload");
+  }
+  v.cell_xy = (const int32_t*)a1;
+  v.start = (const int32_t*)a2;
+  v.orig = (const int32_t*)a3;
+  v.rowptr = (const int64_t*)a5;
+  v.cols = (const int32_t*)a6;
+  tg->n = n;
+  *out = tg;
+  return LS_OK;
+}
+
+void ls_targets_destroy(ls_targets* tg) {
+  if (!tg) return;
+  for (void* p : tg->allocs) (void)hipFree(p);
+  delete tg;
+}
+
+ls_status ls_scattered_field(ls_op* op, const ls_targets* tg, const void* u_tot, int nrhs, void* us, void* ws,
+                             size_t ws_bytes_, void* stream) {
+  if (!op || !tg || !u_tot || !us || !ws || nrhs < 1) return fail(LS_EINVAL, "bad argument");
+  if (ws_bytes_ < ws_bytes(op, nrhs, LS_C128)) return fail(LS_EINVAL, "workspace too small");
+  hipError_t e = lsx::launch_targets(op->d64, tg->view, u_tot, us, nrhs, ws, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(LS_EDEVICE, std::string("scattered field launch: ") + hipGetErrorString(e));
+  return LS_OK;
+}
 
 const char* ls_status_str(ls_status s) {
   switch (s) {
@@ -472,6 +596,19 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     b.khat = kf_d;
   }
 #undef UP
+  op->ext.cw = h.cw;
+  op->ext.cell_map = h.cell_map;
+  op->ext.cell_start = h.cell_start;
+  op->ext.cell_nint = h.cell_nint;
+  op->ext.cell_nb = h.cell_nb;
+  op->ext.Bp = h.Bp;
+  op->ext.L = h.L;
+  op->ext.nfb = h.p.n_fb;
+  op->ext.F = h.F;
+  op->ext.c_lo = h.c_lo;
+  op->ext.H = h.H;
+  op->ext.shape_a = h.g.shape_a;
+  op->ext.shape_k = h.g.shape_k;
   ls_host_destroy(hb);
   *out = op;
   return LS_OK;

@@ -1373,11 +1373,86 @@ __global__ void k_axpy_combo32(double2* __restrict__ x, const float2* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Scattered field at points off the scatterer (outside: no singular part):
+// u^s(x) = -kappa^2 [ far(x) + sum_{j in adjacent cells} G(|x - y_j|) c_j u_j ].
+// One workgroup per target cell (a cell of the lattice box, occupied or
+// not): the cell's face values of the lattice field minus its 3 x 3
+// neighbours' equivalent-source fields give, through the cell's Dirichlet fit
+// (one row per target, like a boundary-patch node), the field of the
+// non-adjacent cells; the adjacent cells' sources are a stored row per target.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_targets(const typename C2<T>::t* __restrict__ u,
+                                                 typename C2<T>::t* __restrict__ out,
+                                                 const typename C2<T>::t* __restrict__ lat,
+                                                 const typename C2<T>::t* __restrict__ sigma,
+                                                 const typename C2<T>::t* __restrict__ ToffT,
+                                                 const int32_t* __restrict__ tcell_xy,
+                                                 const int32_t* __restrict__ tstart,
+                                                 const int32_t* __restrict__ torig,
+                                                 const typename C2<T>::t* __restrict__ Itg,
+                                                 const int64_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ cols,
+                                                 const typename C2<T>::t* __restrict__ vals,
+                                                 const int32_t* __restrict__ cell_map, int L, int q, int U, int F,
+                                                 int ncell, int Pa, int Pb, int64_t N, int64_t ntarg, T scale) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  V* f = reinterpret_cast<V*>(smem_raw);      // F face values
+  V* sg = f + F;                              // 9 * U neighbour strengths
+  V* part = sg + 9 * U;                       // 9 * F adjacent fields
+  int* nbr = reinterpret_cast<int*>(part + 9 * F);
+  const int c = blockIdx.x, r = blockIdx.y;
+  const int cx = tcell_xy[2 * c], cy = tcell_xy[2 * c + 1];
+  const int64_t plane = (int64_t)Pa * Pb;
+  if (threadIdx.x < 9) {
+    const int nx = cx + (int)threadIdx.x % 3 - 1, ny = cy + (int)threadIdx.x / 3 - 1;
+    nbr[threadIdx.x] = (nx >= 0 && ny >= 0 && nx < L && ny < L) ? cell_map[ny * L + nx] : -1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 9 * U; i += blockDim.x) {
+    const int cn = nbr[i / U];
+    sg[i] = cn >= 0 ? sigma[((int64_t)r * ncell + cn) * U + i % U] : czero<V>();
+  }
+  for (int t = threadIdx.x; t < F; t += blockDim.x) {
+    const int s2 = t / (2 * q), fj = t % (2 * q), fc = fj / q, j = fj % q;
+    const int cn = (s2 == 0 ? cx : cy) + fc, ct = (s2 == 0 ? cy : cx);
+    f[t] = lat[((int64_t)(r * 2 + s2) * 2) * plane + (int64_t)cn * Pb + ct * q + j];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 9 * F; i += blockDim.x) {
+    const int o = i / F, t = i % F, s2 = t / (2 * q);
+    V acc = czero<V>();
+    if (nbr[o] >= 0) {
+      const V* Tcol = ToffT + ((int64_t)o * U + s2 * 4 * q) * F + t;
+      const V* sv = sg + o * U + s2 * 4 * q;
+      for (int k = 0; k < 4 * q; ++k) acc = cfma(Tcol[(int64_t)k * F], sv[k], acc);
+    }
+    part[i] = acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < F; t += blockDim.x) {
+    V acc = f[t];
+    for (int o = 0; o < 9; ++o) acc = csub(acc, part[o * F + t]);
+    f[t] = acc;
+  }
+  __syncthreads();
+  const V* ur = u + (int64_t)r * N;
+  for (int ti = tstart[c] + threadIdx.x; ti < tstart[c + 1]; ti += blockDim.x) {
+    V acc = czero<V>();
+    const V* irow = Itg + (int64_t)ti * F;
+    for (int t = 0; t < F; ++t) acc = cfma(irow[t], f[t], acc);
+    for (int64_t k = rowptr[ti]; k < rowptr[ti + 1]; ++k) acc = cfma(vals[k], ur[cols[k]], acc);
+    out[(int64_t)r * ntarg + torig[ti]] = cscale(acc, scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs, void* ws_, hipStream_t st,
-                        hipEvent_t* ev) {
+                        hipEvent_t* ev, bool lattice_only) {
   auto mark = [&](int i) {
     if (ev) (void)hipEventRecord(ev[i], st);
   };
@@ -1436,6 +1511,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                        (int64_t)d.Pb, d.Pb, d.nb, 2 * plane);
   }
   mark(5);
+  if (lattice_only) return hipGetLastError();   // the caller evaluates the field itself
   // a3 + a5
   {
     size_t sh = (size_t)(d.F + 9 * d.U + 9 * d.F) * sizeof(V) + 16 * sizeof(int);
@@ -1506,9 +1582,9 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
 }
 
 template hipError_t launch_apply<double>(const DevView<double>&, const void*, void*, int, void*, hipStream_t,
-                                         hipEvent_t*);
+                                         hipEvent_t*, bool);
 template hipError_t launch_apply<float>(const DevView<float>&, const void*, void*, int, void*, hipStream_t,
-                                        hipEvent_t*);
+                                        hipEvent_t*, bool);
 
 hipError_t set_fft_lds_limits(size_t bytes) {
   hipError_t e = hipSuccess;
@@ -1668,6 +1744,21 @@ hipError_t gm32_axpy_combo(void* x, const void* Vb, const void* y, int nvec, int
                            hipStream_t st) {
   hipLaunchKernelGGL(k_axpy_combo32, dim3((unsigned)((N + 255) / 256), nrhs), dim3(256), 0, st, (double2*)x,
                      (const float2*)Vb, (const double2*)y, nvec, N, vstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const DevView<double>& d, const TargetView& tg, const void* u, void* out, int nrhs,
+                          void* ws, hipStream_t st) {
+  hipError_t e = launch_apply<double>(d, u, nullptr, nrhs, ws, st, nullptr, true);
+  if (e != hipSuccess) return e;
+  using V = double2;
+  const V* sigma = static_cast<const V*>(ws);
+  const V* lat = sigma + (size_t)nrhs * d.ncell * d.U;
+  const size_t sh = (size_t)(d.F + 9 * d.U + 9 * d.F) * sizeof(V) + 16 * sizeof(int);
+  hipLaunchKernelGGL(k_targets<double>, dim3(tg.ncell, nrhs), dim3(256), sh, st, (const V*)u, (V*)out, lat, sigma,
+                     (const V*)d.Toff, tg.cell_xy, tg.start, tg.orig, (const V*)tg.fit, tg.rowptr, tg.cols,
+                     (const V*)tg.vals, d.cell_map, d.L, d.q, d.U, d.F, d.ncell, d.Pa, d.Pb, d.N, tg.n,
+                     -d.kappa * d.kappa);
   return hipGetLastError();
 }
 

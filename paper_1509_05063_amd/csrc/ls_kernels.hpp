@@ -36,9 +36,25 @@ struct DevView {
   FftPlan pa{}, pb{};
 };
 
+// lattice_only: stop after the inverse transforms (workspace holds the
+// strengths and the face-lattice field; v is not touched)
 template <typename T>
 hipError_t launch_apply(const DevView<T>& d, const void* u, void* v, int nrhs, void* ws, hipStream_t st,
-                        hipEvent_t* ev = nullptr);
+                        hipEvent_t* ev = nullptr, bool lattice_only = false);
+
+// Targets off the scatterer, sorted by their cell of the lattice box.
+struct TargetView {
+  int64_t n = 0;                 // targets
+  int ncell = 0;                 // target cells
+  const int32_t *cell_xy = nullptr, *start = nullptr, *orig = nullptr;   // [ncell][2], [ncell+1], [n]
+  const void* fit = nullptr;     // [n][F] complex double: face values -> field at the target
+  const int64_t* rowptr = nullptr;   // [n+1] adjacent-cell sources
+  const int32_t* cols = nullptr;
+  const void* vals = nullptr;    // complex double G(|x - y_j|) c_j
+};
+// out[r][n] = scattered field at the targets for the totals u [nrhs][N]
+hipError_t launch_targets(const DevView<double>& d, const TargetView& tg, const void* u, void* out, int nrhs,
+                          void* ws, hipStream_t st);
 hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st);
 hipError_t set_fft_lds_limits(size_t bytes);
 hipError_t set_cell_lds_limits();

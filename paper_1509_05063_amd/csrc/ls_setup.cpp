@@ -204,6 +204,29 @@ Stencil interior_stencil(double f1, double f2, const std::vector<double>& rho,
 }  // namespace
 
 // ============================================================================
+void fb_basis(int nfb, double kappa, double H, const double* rel, cd* out) {
+  const double Rc = H / std::sqrt(2.0);
+  const double dx = rel[0] - 0.5 * H, dy = rel[1] - 0.5 * H;
+  const double rr = std::hypot(dx, dy), th = std::atan2(dy, dx);
+  for (int n = -nfb; n <= nfb; ++n) {
+    const int an = std::abs(n);
+    double jn = std::cyl_bessel_j((double)an, kappa * rr) / std::cyl_bessel_j((double)an, kappa * Rc);
+    if (n < 0 && (an & 1)) jn = -jn;
+    out[n + nfb] = jn * std::exp(cd(0.0, n * th));
+  }
+}
+
+void fit_row(const std::vector<cd>& Bp, int nfb, int F, double kappa, double H, const double* rel, cd* out) {
+  const int nf = 2 * nfb + 1;
+  std::vector<cd> e(nf);
+  fb_basis(nfb, kappa, H, rel, e.data());
+  for (int t = 0; t < F; ++t) {
+    cd acc = 0;
+    for (int n = 0; n < nf; ++n) acc += e[n] * Bp[(size_t)n * F + t];
+    out[t] = acc;
+  }
+}
+
 ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double kappa,
                         const ls_params* pp, HostOp& op, std::string& err) {
   const ls_geometry& g = *gp;
@@ -637,35 +660,16 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   };
   // Dirichlet fit: Fourier–Bessel modes |n| <= n_fb about the cell centre
   const int nf = 2 * p.n_fb + 1;
-  const double Rc = H / std::sqrt(2.0);
-  auto fb_row = [&](const double* rel, cd* out) {
-    double dx = rel[0] - 0.5 * H, dy = rel[1] - 0.5 * H;
-    double rr = std::hypot(dx, dy), th = std::atan2(dy, dx);
-    for (int n = -p.n_fb; n <= p.n_fb; ++n) {
-      int an = std::abs(n);
-      double jn = std::cyl_bessel_j((double)an, kappa * rr) / std::cyl_bessel_j((double)an, kappa * Rc);
-      if (n < 0 && (an & 1)) jn = -jn;
-      out[n + p.n_fb] = jn * std::exp(cd(0.0, n * th));
-    }
-  };
   std::vector<cd> B((size_t)F * nf);
   for (int s = 0; s < 2; ++s)
     for (int f = 0; f < 2; ++f)
       for (int j = 0; j < q; ++j) {
         double x[2];
         node_pos(s, f, j, x);
-        fb_row(x, &B[(size_t)(s * 2 * q + f * q + j) * nf]);
+        fb_basis(p.n_fb, kappa, H, x, &B[(size_t)(s * 2 * q + f * q + j) * nf]);
       }
-  std::vector<cd> Bp = pinv(B, F, nf, 1e-14);   // nf x F
-  auto interp_row = [&](const double* rel, cd* out) {
-    std::vector<cd> e(nf);
-    fb_row(rel, e.data());
-    for (int t = 0; t < F; ++t) {
-      cd acc = 0;
-      for (int n = 0; n < nf; ++n) acc += e[n] * Bp[(size_t)n * F + t];
-      out[t] = acc;
-    }
-  };
+  op.Bp = pinv(B, F, nf, 1e-14);   // nf x F
+  auto interp_row = [&](const double* rel, cd* out) { fit_row(op.Bp, p.n_fb, F, kappa, H, rel, out); };
   op.Psh.assign((size_t)U * S, 0.0);
   op.Psh32.assign((size_t)U * S, 0.0);
   op.Ish.assign((size_t)S * F, 0.0);

@@ -51,6 +51,7 @@ struct HostOp {
   std::vector<cd> Ish;          // [S][F]  face values -> interior slots
   std::vector<cd> Ibd;          // [n_band][F] face values -> boundary node
   std::vector<cd> Toff;         // [9][F][U] adjacent equivalent-source fields
+  std::vector<cd> Bp;           // [nf][F] Dirichlet fit: face values -> Fourier–Bessel coefficients
   int na = 0, nb = 0, Pa = 0, Pb = 0;
   std::vector<cd> kern;         // [2 sets][2 kinds][Pa*Pb] kernel / (Pa Pb)
 
@@ -65,6 +66,13 @@ struct HostOp {
 // Returns LS_OK or an error code with a message in err.
 ls_status build_host_op(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa,
                         const ls_params* p, HostOp& op, std::string& err);
+
+// Cell Dirichlet fit (Sec. 3.2, eq:-PWE read as Fourier–Bessel modes
+// |n| <= nfb about the cell centre, normalised at the half diagonal):
+// basis values at rel (relative to the cell origin), and the row of weights
+// that maps the cell's F face values to the field at rel.
+void fb_basis(int nfb, double kappa, double H, const double* rel, cd* out);
+void fit_row(const std::vector<cd>& Bp, int nfb, int F, double kappa, double H, const double* rel, cd* out);
 
 // ---- numerical helpers shared by the set-up (ls_math.cpp) ----------------
 cd green2d(double kappa, double r);                    // (i/4) H0(kappa r)

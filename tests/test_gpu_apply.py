@@ -164,3 +164,35 @@ def test_variable_index_medium_matches_oracle():
         print(f"sin cos medium, N={op.N}, mode {mode}: {st} vs LU {e:.2e}, apply {err:.2e}", flush=True)
         assert st["converged"] == 1 and e < 1e-8, e
     op.close()
+
+
+def test_scattered_field_off_the_disc(disc):
+    """The device scattered field at points outside the disc (inside its cell
+    box) equals the oracle's direct sum over the same solution, and the Mie
+    scattered field to the discretisation's accuracy."""
+    import torch
+    from oracle.exterior import scattered_field
+    from oracle.mie import mie2d_total
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    f_or = plane_wave(cfg, orc.pts["x"], 0.0)
+    f = torch.tensor(_to_lib(f_or, p, op.N), dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(f)
+    op.solve(f, x, tol=1e-12, restart=100, max_iter=500, mode=binding.LS_SOLVE_FP64)
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-0.999, 0.999, (4000, 2))
+    rad = np.hypot(pts[:, 0], pts[:, 1])
+    far = pts[rad > 1.12][:200]                      # a few grid spacings off the interface
+    near = pts[(rad > 1.0 + 1e-6) & (rad < 1.03)][:50]
+    xt = np.concatenate([far, near])
+    us = op.scattered_field(x, xt).cpu().numpy()
+    u_or = x.cpu().numpy()[p]
+    ref = scattered_field(orc, u_or, xt)
+    err = np.linalg.norm(us - ref) / np.linalg.norm(ref)
+    ex = mie2d_total(cfg["kappa"], 1.5, 1.0, far) - np.exp(1j * cfg["kappa"] * far[:, 0])
+    emie = np.linalg.norm(us[:len(far)] - ex) / np.linalg.norm(ex)
+    print(f"scattered field: {len(xt)} targets, vs direct sum {err:.2e}, vs Mie {emie:.2e}", flush=True)
+    assert err < 1e-9, err
+    assert emie < 5e-3, emie
+    with pytest.raises(binding.LSError):
+        op.scattered_field(x, np.array([[0.1, 0.2]]))    # inside the scatterer
