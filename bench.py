@@ -54,8 +54,8 @@ def stage_bytes(st, N, n_int, s, s_w):
 
 
 # single-precision kernel of each one-kernel stage (the FFT stages run several)
-STAGE_KERNEL = {"project": "k_project<float>", "fill": "k_fill<float>", "spectral": "k_spectral<float>",
-                "interp": "k_interp<float>", "near_shared": "k_near_shared_mfma_db",
+STAGE_KERNEL = {"project": "k_project2<float>", "fill": "k_fill<float>", "spectral": "k_spectral<float>",
+                "interp": "k_interp_mfma<float,16>", "near_shared": "k_near_shared_mfma_db<1>",
                 "near_csr": "k_near_csr4"}
 
 
@@ -306,8 +306,9 @@ def main():
     kname = STAGE_KERNEL.get(dom, dom)
     if tune and dom == "near_csr" and tune["fp32"]["csr_variant"] == 1:
         kname = "k_near_csr<float>"
-    if tune and dom == "near_shared" and tune["fp32"]["near_variant"] == 1:
-        kname = "k_near_shared_mfma<float,2>"
+    if tune and dom == "near_shared":
+        nv = tune["fp32"]["near_variant"]
+        kname = "k_near_shared_mfma<float,2>" if nv == 1 else f"k_near_shared_mfma_db<{ {0: 1, 2: 2, 3: 4}[nv] }>"
     roof = {"kernel": kname, "stage": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": counter_traffic(kname),
             "algorithmic_bytes": int(byts[dom]), "avg_ms": round(p32[dom], 4)}

@@ -160,7 +160,8 @@ ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec 
 /* Kernel schedules chosen by ls_autotune for one precision. */
 typedef struct {
   int fft_col_tile;     /* columns per workgroup of the column transforms */
-  int near_variant;     /* interior contraction: 0 double-buffered staging, 1 single-buffered */
+  int near_variant;     /* interior contraction: 0 double-buffered staging (16 cells per
+                           workgroup), 1 single-buffered, 2 / 3 double-buffered with 32 / 64 cells */
   int csr_variant;      /* boundary-patch rows: 0 four entries per lane, 1 one entry per lane */
   double fft_ms;        /* best time of the transform stages with the chosen tile */
   double near_ms;       /* best time of the interior contraction stage */

@@ -724,7 +724,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   const int tmax = std::max(1, (int)(150 * 1024 / (2 * (size_t)d.Pa * sizeof(T) * 2)));
   int best_tc = d.tc;
   double best = 1e30;
-  for (int tc : {2, 4, 8, 16, 32}) {
+  for (int tc : {1, 2, 4, 8, 16, 32}) {
     if (tc > tmax) break;
     d.tc = tc;
     double t;
@@ -740,9 +740,10 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
   const int nvar = std::is_same<T, float>::value ? 2 : 1;
+  const int nnear = std::is_same<T, float>::value ? 4 : 1;
   int bv = 0;
   best = 1e30;
-  for (int var = 0; var < nvar; ++var) {
+  for (int var = 0; var < nnear; ++var) {
     d.near_variant = var;
     double t;
     ls_status s = measure(6, 6, &t);

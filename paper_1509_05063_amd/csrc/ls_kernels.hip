@@ -470,10 +470,14 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
   constexpr int q = 12, F = 4 * q, U = 8 * q, S = 64, KS = 4 * q, TS = 2 * q;   // KS sources, TS faces per set
   static_assert(CB == 16, "one MFMA column per cell");
   extern __shared__ unsigned char smem_raw[];
+  // LDS: face values, then two buffers (offsets alternate) of the neighbours'
+  // strengths and the same-set adjacency blocks
   V* fv = reinterpret_cast<V*>(smem_raw);    // [CB][F] face values
-  V* sg = fv + CB * F;                       // [CB][U] strengths of the neighbour at the current offset
-  V* To = sg + CB * U;                       // [2][KS][TS] same-set adjacency blocks of the current offset
-  int* cinfo = reinterpret_cast<int*>(To + 2 * KS * TS);   // [CB][2] cell x, y (-1: past the end)
+  V* sgb = fv + CB * F;                      // [2][CB][U] strengths of the neighbour at the offset
+  V* Tob = sgb + 2 * CB * U;                 // [2][2][KS][TS] same-set adjacency blocks of the offset
+  int* cinfo = reinterpret_cast<int*>(Tob + 2 * 2 * KS * TS);   // [CB][2] cell x, y (-1: past the end)
+  constexpr int SPT = CB * U / 256, TPT = 2 * KS * TS / 256;    // staged values per thread
+  static_assert(CB * U % 256 == 0 && 2 * KS * TS % 256 == 0, "staging split over 256 threads");
   const int c0 = blockIdx.x * CB, r = blockIdx.y, tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
   const int64_t plane = (int64_t)Pa * Pb;
@@ -496,25 +500,43 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
   }
   const int ws = wave >> 1, mt = wave & 1;   // this wave's set and face tile
   const int arow = 16 * mt + col;            // face row of the A operand
-  v4 cre = v4{0, 0, 0, 0}, cim = v4{0, 0, 0, 0};
-  for (int o = 0; o < 9; ++o) {
+  V sreg[SPT], treg[TPT];
+  auto gload = [&](int o) {
     const int ox = o % 3 - 1, oy = o / 3 - 1;
-    __syncthreads();
-    for (int i = tid; i < CB * U; i += blockDim.x) {
-      const int cb = i / U, k = i % U;
+#pragma unroll
+    for (int qq = 0; qq < SPT; ++qq) {
+      const int i = tid + 256 * qq, cb = i / U, k = i % U;
       const int cx = cinfo[2 * cb], cy = cinfo[2 * cb + 1];
       int cn = -1;
       if (cx >= 0) {
         const int nx = cx + ox, ny = cy + oy;
         cn = (nx >= 0 && ny >= 0 && nx < L && ny < L) ? cell_map[ny * L + nx] : -1;
       }
-      sg[i] = cn >= 0 ? sigma[((int64_t)r * ncell + cn) * U + k] : czero<V>();
+      sreg[qq] = cn >= 0 ? sigma[((int64_t)r * ncell + cn) * U + k] : czero<V>();
     }
-    for (int i = tid; i < 2 * KS * TS; i += blockDim.x) {
+#pragma unroll
+    for (int qq = 0; qq < TPT; ++qq) {
+      const int i = tid + 256 * qq;
       const int s2 = i / (KS * TS), k = (i / TS) % KS, tt = i % TS;
-      To[i] = ToffT[((int64_t)o * U + s2 * KS + k) * F + s2 * TS + tt];
+      treg[qq] = ToffT[((int64_t)o * U + s2 * KS + k) * F + s2 * TS + tt];
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int b) {
+#pragma unroll
+    for (int qq = 0; qq < SPT; ++qq) sgb[b * CB * U + tid + 256 * qq] = sreg[qq];
+#pragma unroll
+    for (int qq = 0; qq < TPT; ++qq) Tob[b * 2 * KS * TS + tid + 256 * qq] = treg[qq];
+  };
+  v4 cre = v4{0, 0, 0, 0}, cim = v4{0, 0, 0, 0};
+  __syncthreads();
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int o = 0; o < 9; ++o) {
+    const int buf = o & 1;
+    const V* sg = sgb + buf * CB * U;
+    const V* To = Tob + buf * 2 * KS * TS;
+    if (o + 1 < 9) gload(o + 1);
 #pragma unroll 4
     for (int kk = 0; kk < KS / 4; ++kk) {
       const int k = 4 * kk + kl;
@@ -525,8 +547,9 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
       cim = M::op(a.x, b.y, cim);
       cim = M::op(a.y, b.x, cim);
     }
+    if (o + 1 < 9) sstore(buf ^ 1);
+    __syncthreads();
   }
-  __syncthreads();
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int tp = 16 * mt + M::row(lane, rr);
@@ -775,21 +798,26 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::
 // double-buffered: while the MFMAs contract window row wy from one LDS
 // buffer, the loads of row wy+1 are in flight in registers and land in the
 // other buffer, so each row costs one barrier and no exposed load latency.
-// A workgroup takes 16 cells (enough workgroups to keep every CU busy).
-__global__ void __launch_bounds__(256) k_near_shared_mfma_db(const float2* __restrict__ grid, float2* __restrict__ v,
-                                                             const float2* __restrict__ W,
-                                                             const int32_t* __restrict__ icells,
-                                                             const int32_t* __restrict__ cell_xy,
-                                                             const int32_t* __restrict__ slot_map, int Gw,
-                                                             int nicell, int64_t N, float k2) {
+// A workgroup of 4 CT waves takes 16 CT cells: wave w contracts slots
+// 16 (w % 4) .. +15 against cells 16 (w / 4) .. +15, so one staged row of W
+// serves 16 CT cells (CT = 1: most workgroups, CT = 4: least W traffic).
+template <int CT>
+__global__ void __launch_bounds__(256 * CT) k_near_shared_mfma_db(const float2* __restrict__ grid,
+                                                                  float2* __restrict__ v,
+                                                                  const float2* __restrict__ W,
+                                                                  const int32_t* __restrict__ icells,
+                                                                  const int32_t* __restrict__ cell_xy,
+                                                                  const int32_t* __restrict__ slot_map, int Gw,
+                                                                  int nicell, int64_t N, float k2) {
   using M = Mfma<float>;
   using v4 = M::v4;
-  constexpr int CH = 8, S = 64, WN = 40, KP = WN + 1, NC = 16;
-  constexpr int XPT = (NC * WN + 255) / 256, WPT = (S * WN + 255) / 256;
+  constexpr int CH = 8, S = 64, WN = 40, KP = WN + 1, NC = 16 * CT, NTH = 256 * CT;
+  constexpr int XPT = (NC * WN + NTH - 1) / NTH, WPT = (S * WN + NTH - 1) / NTH;
   __shared__ float2 Xs[2][NC * KP];
   __shared__ float2 Ws[2][S * KP];
   __shared__ int cx0[NC], cy0[NC];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int st = wave & 3, ct = wave >> 2;     // slot tile, cell tile
   const int r = blockIdx.y;
   const int cb = blockIdx.x * NC;
   const float2* g = grid + (int64_t)r * Gw * Gw;
@@ -803,7 +831,7 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma_db(const float2* __res
   auto gload = [&](int wy) {
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
-      const int i = tid + 256 * q;
+      const int i = tid + NTH * q;
       float2 val = make_float2(0.f, 0.f);
       if (i < NC * WN) {
         const int c = i / WN, wx = i % WN;
@@ -813,19 +841,19 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma_db(const float2* __res
     }
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
-      const int i = tid + 256 * q;
+      const int i = tid + NTH * q;
       if (i < S * WN) wr[q] = W[(int64_t)(i / WN) * WN * WN + wy * WN + i % WN];
     }
   };
   auto sstore = [&](int b) {
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
-      const int i = tid + 256 * q;
+      const int i = tid + NTH * q;
       if (i < NC * WN) Xs[b][(i / WN) * KP + i % WN] = xr[q];
     }
 #pragma unroll
     for (int q = 0; q < WPT; ++q) {
-      const int i = tid + 256 * q;
+      const int i = tid + NTH * q;
       if (i < S * WN) Ws[b][(i / WN) * KP + i % WN] = wr[q];
     }
   };
@@ -839,8 +867,8 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma_db(const float2* __res
 #pragma unroll 2
     for (int kk = 0; kk < WN / 4; ++kk) {
       const int k = 4 * kk + (lane >> 4);
-      const float2 wa = Ws[b][(16 * wave + (lane & 15)) * KP + k];
-      const float2 xb = Xs[b][(lane & 15) * KP + k];
+      const float2 wa = Ws[b][(16 * st + (lane & 15)) * KP + k];
+      const float2 xb = Xs[b][(16 * ct + (lane & 15)) * KP + k];
       are = M::op(wa.x, xb.x, are);
       are = M::op(-wa.y, xb.y, are);
       aim = M::op(wa.x, xb.y, aim);
@@ -849,13 +877,13 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma_db(const float2* __res
     if (wy + 1 < WN) sstore(b ^ 1);
     __syncthreads();
   }
-  const int c = cb + (lane & 15);
+  const int c = cb + 16 * ct + (lane & 15);
   if (c >= nicell) return;
   const int cid = icells[c];
   float2* vr = v + (int64_t)r * N;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int a = 16 * wave + M::row(lane, q);
+    const int a = 16 * st + M::row(lane, q);
     const int j = slot_map[(int64_t)cid * S + a];
     if (j < 0) continue;
     float2 o = vr[j];
@@ -1517,7 +1545,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     size_t sh = (size_t)(d.F + 9 * d.U + 9 * d.F) * sizeof(V) + 16 * sizeof(int);
     if (d.q == 12 && d.S == 64) {
       constexpr int CB = 16;
-      const size_t shm = (size_t)(CB * 48 + CB * 96 + 2 * 48 * 24) * sizeof(V) + 2 * CB * sizeof(int);
+      const size_t shm = (size_t)(CB * 48 + 2 * CB * 96 + 2 * 2 * 48 * 24) * sizeof(V) + 2 * CB * sizeof(int);
       hipLaunchKernelGGL((k_interp_mfma<T, CB>), dim3((d.ncell + CB - 1) / CB, nrhs), dim3(256), shm, st, u, v,
                          (const V*)lat, (const V*)sigma, (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd,
                          d.cell_xy, d.cell_map, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L,
@@ -1537,10 +1565,18 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     const int64_t gsz = (int64_t)Gw * Gw;
     hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, st, u, grid, d.dw,
                        d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
-    if (std::is_same<T, float>::value && d.near_variant == 0) {
-      hipLaunchKernelGGL(k_near_shared_mfma_db, dim3((d.nicell + 15) / 16, nrhs), dim3(256), 0, st,
-                         (const float2*)grid, (float2*)v, (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw,
-                         d.nicell, d.N, (float)k2);
+    if (std::is_same<T, float>::value && d.near_variant != 1) {
+      const int CT = d.near_variant == 2 ? 2 : d.near_variant == 3 ? 4 : 1;
+      const dim3 gr((d.nicell + 16 * CT - 1) / (16 * CT), nrhs), bl(256 * CT);
+      if (CT == 1)
+        hipLaunchKernelGGL(k_near_shared_mfma_db<1>, gr, bl, 0, st, (const float2*)grid, (float2*)v,
+                           (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
+      else if (CT == 2)
+        hipLaunchKernelGGL(k_near_shared_mfma_db<2>, gr, bl, 0, st, (const float2*)grid, (float2*)v,
+                           (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
+      else
+        hipLaunchKernelGGL(k_near_shared_mfma_db<4>, gr, bl, 0, st, (const float2*)grid, (float2*)v,
+                           (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
     } else {
       constexpr int NT = 2;
       hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs), dim3(256),
@@ -1604,10 +1640,14 @@ hipError_t set_fft_lds_limits(size_t bytes) {
 }
 
 hipError_t set_cell_lds_limits() {
-  // the double-precision form of the 16-cell interpolation kernel (74 KB)
-  // exceeds the 64 KB default
-  return hipFuncSetAttribute((const void*)k_interp_mfma<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (16 * 48 + 16 * 96 + 2 * 48 * 24) * 16 + 2 * 16 * 4);
+  // the 16-cell interpolation kernel with double-buffered staging needs
+  // 68 KB (single) / 135 KB (double precision), past the 64 KB default
+  const int base = 16 * 48 + 2 * 16 * 96 + 2 * 2 * 48 * 24;
+  hipError_t e = hipFuncSetAttribute((const void*)k_interp_mfma<double, 16>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, base * 16 + 2 * 16 * 4);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_interp_mfma<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             base * 8 + 2 * 16 * 4);
 }
 
 hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st) {

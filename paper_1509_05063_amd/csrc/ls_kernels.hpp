@@ -19,7 +19,8 @@ struct DevView {
   int ncell = 0, nicell = 0, S = 0, U = 0, F = 0, q = 0, L = 0, na = 0, nb = 0, Pa = 0, Pb = 0, ch = 0;
   int max_nb = 0, tc = 1, nrows = 0;
   // kernel variants chosen by ls_autotune: near_variant 0 = double-buffered
-  // interior contraction (single precision), 1 = single-buffered; csr_variant
+  // interior contraction, 16 cells per workgroup (single precision), 1 =
+  // single-buffered, 2 / 3 = double-buffered with 32 / 64 cells; csr_variant
   // 0 = four entries per lane (single precision, 16-bit offsets), 1 = one
   int near_variant = 0, csr_variant = 0;
   bool csr_f64 = true;
