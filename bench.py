@@ -32,10 +32,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_bytes(st, N, n_int, s, s_w):
+def stage_bytes(st, N, n_int, s, s_w, csr_variant=0):
     """Algorithmic bytes per apply of each stage for one right-hand side
     (what the method has to move; s bytes per complex value of the data,
-    s_w per stored complex weight)."""
+    s_w per stored complex weight).  The near-field rows' column information
+    is what the chosen row format stores: a 16-bit offset per entry, or
+    8 bytes (start column, first entry) per run of consecutive columns."""
     Pa, Pb, ncell, U, F, S, Wn = st["Pa"], st["Pb"], st["ncell"], st["U"], st["F"], st["S"], st["Wn"]
     nb = st["n_band"]
     na = st["L"] + 1
@@ -49,7 +51,9 @@ def stage_bytes(st, N, n_int, s, s_w):
         "fft_inv": 2 * (plane + na * Pb) * 2 * s,
         "interp": ncell * (F + 9 * U) * s + nb * F * s_w + 2 * N * s,
         "near_shared": S * Wn * Wn * s_w + n_int * (s + r) + 2 * n_int * s,
-        "near_csr": st["csr_nnz"] * (s_w + 2) + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s,
+        "near_csr": (st["csr_nnz"] * (s_w + 2) + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s
+                     if csr_variant != 2 else
+                     st["csr_nnz"] * s_w + st["csr_runs"] * 8 + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s),
     }
 
 
@@ -301,11 +305,11 @@ def main():
         log(f"stage ms {name}: " + " ".join(f"{k}={v:.3f}" for k, v in prof[name].items()))
     p32 = prof["fp32"]
     dom = max(p32, key=p32.get)
-    byts = stage_bytes(st, N, n_int, 8, 8)
+    byts = stage_bytes(st, N, n_int, 8, 8, tune["fp32"]["csr_variant"] if tune else 0)
     achieved = byts[dom] / (p32[dom] * 1e-3) / 1e9
     kname = STAGE_KERNEL.get(dom, dom)
-    if tune and dom == "near_csr" and tune["fp32"]["csr_variant"] == 1:
-        kname = "k_near_csr<float>"
+    if tune and dom == "near_csr":
+        kname = {0: "k_near_csr4", 1: "k_near_csr<float>", 2: "k_near_csr4r"}[tune["fp32"]["csr_variant"]]
     if tune and dom == "near_shared":
         nv = tune["fp32"]["near_variant"]
         kname = "k_near_shared_mfma<float,2>" if nv == 1 else f"k_near_shared_mfma_db<{ {0: 1, 2: 2, 3: 4}[nv] }>"

@@ -132,7 +132,8 @@ size_t ls_resident_bytes(const ls_op* op);
 /* Sizes of the discretisation (first nout of): N, boundary-patch nodes,
  * occupied cells, cells per axis, near-field CSR rows, CSR entries, padded
  * face-lattice dims Pa, Pb, equivalent-source unknowns per cell U, face
- * values per cell F, interior slots per cell S, near-field window side. */
+ * values per cell F, interior slots per cell S, near-field window side,
+ * column runs of the CSR rows (0 when the run form is not kept). */
 ls_status ls_op_stats(const ls_op* op, int64_t* out, int nout);
 
 /* Workspace bytes ls_apply needs for nrhs vectors in precision prec. */
@@ -162,7 +163,8 @@ typedef struct {
   int fft_col_tile;     /* columns per workgroup of the column transforms */
   int near_variant;     /* interior contraction: 0 double-buffered staging (16 cells per
                            workgroup), 1 single-buffered, 2 / 3 double-buffered with 32 / 64 cells */
-  int csr_variant;      /* boundary-patch rows: 0 four entries per lane, 1 one entry per lane */
+  int csr_variant;      /* boundary-patch rows: 0 four entries per lane, 1 one entry per lane,
+                           2 four entries per lane with run-length column storage */
   double fft_ms;        /* best time of the transform stages with the chosen tile */
   double near_ms;       /* best time of the interior contraction stage */
   double csr_ms;        /* best time of the boundary-patch rows stage */

@@ -247,9 +247,9 @@ class Operator:
         return lib().ls_resident_bytes(self._op)
 
     def stats(self):
-        out = (C.c_int64 * 12)()
-        _check(lib().ls_op_stats(self._op, out, 12), "ls_op_stats")
-        names = ["N", "n_band", "ncell", "L", "csr_rows", "csr_nnz", "Pa", "Pb", "U", "F", "S", "Wn"]
+        out = (C.c_int64 * 13)()
+        _check(lib().ls_op_stats(self._op, out, 13), "ls_op_stats")
+        names = ["N", "n_band", "ncell", "L", "csr_rows", "csr_nnz", "Pa", "Pb", "U", "F", "S", "Wn", "csr_runs"]
         return dict(zip(names, list(out)))
 
     def workspace_bytes(self, nrhs, prec):

@@ -50,7 +50,7 @@ struct ls_op {
   lsx::DevView<double> d64;
   lsx::DevView<float> d32;
   double kappa = 0;
-  int64_t stats[12] = {0};
+  int64_t stats[13] = {0};
   // solver scratch
   void* gm = nullptr;
   size_t gm_bytes = 0;
@@ -554,6 +554,33 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     }
   }
   UP(upload_i(op, prow, &a.rowptr));
+  {
+    // the same columns as runs of consecutive indices (padding: a final run
+    // at column 0); not used when some row needs more than 256 runs
+    const size_t nr = h.rows.size();
+    std::vector<int32_t> rptr(nr + 1, 0), rcs, rpre;
+    bool fits = true;
+    for (size_t r = 0; r < nr && fits; ++r) {
+      const int64_t b0 = h.rowptr[r], len = h.rowptr[r + 1] - b0;
+      for (int64_t k = 0; k < len; ++k)
+        if (k == 0 || h.cols[b0 + k] != h.cols[b0 + k - 1] + 1) {
+          rcs.push_back(h.cols[b0 + k]);
+          rpre.push_back((int32_t)k);
+        }
+      if (prow[r + 1] - prow[r] > len) {
+        rcs.push_back(0);
+        rpre.push_back((int32_t)len);
+      }
+      rptr[r + 1] = (int32_t)rcs.size();
+      if (rptr[r + 1] - rptr[r] > 256) fits = false;
+    }
+    if (fits && !rcs.empty()) {
+      op->stats[12] = (int64_t)rcs.size();
+      UP(upload_i(op, rptr, &a.run_ptr));
+      UP(upload_i(op, rcs, &a.run_cs));
+      UP(upload_i(op, rpre, &a.run_pre));
+    }
+  }
   b.slot_map = a.slot_map;
   b.cell_start = a.cell_start;
   b.cell_nint = a.cell_nint;
@@ -567,6 +594,9 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   b.coloff = a.coloff;
   b.cols32 = a.cols32;
   b.rowptr = a.rowptr;
+  b.run_ptr = a.run_ptr;
+  b.run_cs = a.run_cs;
+  b.run_pre = a.run_pre;
   // twiddles exp(-2 pi i k / n), computed in double
   for (int which = 0; which < 2; ++which) {
     int n = which == 0 ? h.Pa : h.Pb;
@@ -637,7 +667,7 @@ size_t ls_resident_bytes(const ls_op* op) { return op ? op->resident : 0; }
 
 ls_status ls_op_stats(const ls_op* op, int64_t* out, int nout) {
   if (!op || !out) return fail(LS_EINVAL, "null argument");
-  for (int i = 0; i < nout && i < 12; ++i) out[i] = op->stats[i];
+  for (int i = 0; i < nout && i < 13; ++i) out[i] = op->stats[i];
   return LS_OK;
 }
 
@@ -739,7 +769,6 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->fft_col_tile = best_tc;
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
-  const int nvar = std::is_same<T, float>::value ? 2 : 1;
   const int nnear = std::is_same<T, float>::value ? 4 : 1;
   int bv = 0;
   best = 1e30;
@@ -758,7 +787,8 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->near_ms = best;
   bv = 0;
   best = 1e30;
-  for (int var = 0; var < nvar; ++var) {
+  const int ncsr = std::is_same<T, float>::value ? (d.run_ptr ? 3 : 2) : 1;
+  for (int var = 0; var < ncsr; ++var) {
     d.csr_variant = var;
     double t;
     ls_status s = measure(7, 7, &t);

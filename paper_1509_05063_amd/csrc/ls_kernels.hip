@@ -951,6 +951,89 @@ __global__ void __launch_bounds__(256) k_near_csr4(const float2* __restrict__ u,
   }
 }
 
+// Single-precision rows touching the boundary patch, columns stored as runs
+// of consecutive operator indices (the nodes are sorted by cell, so a row is
+// a few dozen runs): run r of a row covers its entries [pre[r], pre[r+1]) at
+// columns cs[r], cs[r]+1, ...  One wavefront per row stages the row's run
+// table in LDS; each lane finds the run of its four consecutive entries by
+// bisection.  Weights as in k_near_csr4 (rows padded to four entries; the
+// padding sits in a final run at column 0 with zero weights).
+constexpr int CSR_MAX_RUNS = 256;
+__global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u, float2* __restrict__ v,
+                                                    const int64_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ rows,
+                                                    const int32_t* __restrict__ run_ptr,
+                                                    const int32_t* __restrict__ run_cs,
+                                                    const int32_t* __restrict__ run_pre,
+                                                    const float2* __restrict__ vals, int nrows, int64_t N, int nrhs,
+                                                    float k2) {
+  constexpr int RB = 4;
+  __shared__ int cs_s[4][CSR_MAX_RUNS], pre_s[4][CSR_MAX_RUNS + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = blockIdx.x * 4 + wv;
+  const bool valid = row < nrows;
+  const int64_t b = valid ? rowptr[row] : 0, e = valid ? rowptr[row + 1] : 0;
+  const int len = (int)(e - b);
+  const int r0 = valid ? run_ptr[row] : 0, nr = valid ? run_ptr[row + 1] - r0 : 0;
+  int* cs = cs_s[wv];
+  int* pre = pre_s[wv];
+  for (int i = lane; i < nr; i += 64) {
+    cs[i] = run_cs[r0 + i];
+    pre[i] = run_pre[r0 + i];
+  }
+  if (lane == 0) pre[nr] = len;
+  __syncthreads();
+  if (!valid) return;
+  const float4* __restrict__ v4 = (const float4*)(vals + b);
+  for (int r00 = 0; r00 < nrhs; r00 += RB) {
+    const int nrr = min(RB, nrhs - r00);
+    float2 acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = czero<float2>();
+    for (int k = lane; 4 * k < len; k += 64) {
+      const float4 wa = v4[2 * k], wb = v4[2 * k + 1];
+      const int e0 = 4 * k;
+      int lo = 0, hi = nr;          // largest r with pre[r] <= e0
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= e0) lo = mid; else hi = mid;
+      }
+      int c[4];
+      int rr = lo;
+#pragma unroll
+      for (int z = 0; z < 4; ++z) {
+        while (pre[rr + 1] <= e0 + z) ++rr;
+        c[z] = cs[rr] + (e0 + z - pre[rr]);
+      }
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        if (q < nrr) {
+          const float2* uq = u + (int64_t)(r00 + q) * N;
+          acc[q] = cfma(make_float2(wa.x, wa.y), uq[c[0]], acc[q]);
+          acc[q] = cfma(make_float2(wa.z, wa.w), uq[c[1]], acc[q]);
+          acc[q] = cfma(make_float2(wb.x, wb.y), uq[c[2]], acc[q]);
+          acc[q] = cfma(make_float2(wb.z, wb.w), uq[c[3]], acc[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      if (q >= nrr) break;
+      float2 a = acc[q];
+      for (int off = 32; off > 0; off >>= 1) {
+        a.x += __shfl_down(a.x, off, 64);
+        a.y += __shfl_down(a.y, off, 64);
+      }
+      if (lane == 0) {
+        const int64_t j = rows[row];
+        float2* vr = v + (int64_t)(r00 + q) * N;
+        float2 t = vr[j];
+        vr[j] = cadd(t, cscale(a, k2));
+      }
+    }
+  }
+}
+
 // a4, rows touching the boundary patch: one wavefront per row; each weight
 // is loaded once and applied to up to four right-hand sides; four entries
 // per lane in flight.
@@ -1602,7 +1685,10 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
                            d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
     } else {
-      if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
+      if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant == 2)
+        hipLaunchKernelGGL(k_near_csr4r, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.run_ptr,
+                           d.run_cs, d.run_pre, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
+      else if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
         hipLaunchKernelGGL(k_near_csr4, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.colbase,
                            d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
       else if (d.coloff)

@@ -21,7 +21,8 @@ struct DevView {
   // kernel variants chosen by ls_autotune: near_variant 0 = double-buffered
   // interior contraction, 16 cells per workgroup (single precision), 1 =
   // single-buffered, 2 / 3 = double-buffered with 32 / 64 cells; csr_variant
-  // 0 = four entries per lane (single precision, 16-bit offsets), 1 = one
+  // 0 = four entries per lane (single precision, 16-bit offsets), 1 = one,
+  // 2 = four entries per lane with run-length columns
   int near_variant = 0, csr_variant = 0;
   bool csr_f64 = true;
   double kappa = 0;
@@ -34,6 +35,10 @@ struct DevView {
   const uint16_t* coloff = nullptr;   // column = colbase[row] + coloff[k] (16-bit form)
   const int32_t* cols32 = nullptr;    // column = colbase[row] + cols32[k] (when a row spans > 65535)
   const int64_t* rowptr = nullptr;
+  // the same columns as runs of consecutive indices: run r of row i is
+  // run_ptr[i] + r, covering the row's entries from run_pre on at columns
+  // run_cs, run_cs + 1, ... (null when some row has more than 256 runs)
+  const int32_t *run_ptr = nullptr, *run_cs = nullptr, *run_pre = nullptr;
   FftPlan pa{}, pb{};
 };
 
@@ -49,7 +54,11 @@ struct TargetView {
   int ncell = 0;                 // target cells
   const int32_t *cell_xy = nullptr, *start = nullptr, *orig = nullptr;   // [ncell][2], [ncell+1], [n]
   const void* fit = nullptr;     // [n][F] complex double: face values -> field at the target
-  const int64_t* rowptr = nullptr;   // [n+1] adjacent-cell sources
+  const int64_t* rowptr = nullptr;
+  // the same columns as runs of consecutive indices: run r of row i is
+  // run_ptr[i] + r, covering the row's entries from run_pre on at columns
+  // run_cs, run_cs + 1, ... (null when some row has more than 256 runs)
+  const int32_t *run_ptr = nullptr, *run_cs = nullptr, *run_pre = nullptr;   // [n+1] adjacent-cell sources
   const int32_t* cols = nullptr;
   const void* vals = nullptr;    // complex double G(|x - y_j|) c_j
 };
