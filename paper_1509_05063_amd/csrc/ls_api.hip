@@ -127,10 +127,20 @@ lsx::FftPlan make_plan(int n) {
   p.n = n;
   int r = n;
   p.npass = 0;
-  while (r % 4 == 0) { p.radix[p.npass++] = 4; r /= 4; }
-  while (r % 2 == 0) { p.radix[p.npass++] = 2; r /= 2; }
-  while (r % 3 == 0) { p.radix[p.npass++] = 3; r /= 3; }
-  while (r % 5 == 0) { p.radix[p.npass++] = 5; r /= 5; }
+  // fewest passes: the largest supported radix (<= 16, in-register DFT)
+  // that divides what is left
+  static const int rad[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+  while (r > 1) {
+    int pick = 0;
+    for (int R : rad)
+      if (r % R == 0) {
+        pick = R;
+        break;
+      }
+    if (!pick) break;       // next_smooth sizes only have factors 2, 3, 5
+    p.radix[p.npass++] = (int8_t)pick;
+    r /= pick;
+  }
   return p;
 }
 

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "ls_kernels.hpp"
 
@@ -234,6 +235,82 @@ __device__ __forceinline__ void dft_small(V* v, int R) {
   }
 }
 
+// Composite radices R = A B (A the smallest factor) in registers, by one
+// Cooley–Tukey step: x[B n1 + n2] -> A-point DFTs over n1, twiddle by
+// W_R^{n2 k1}, B-point DFTs over n2 -> X[k1 + A k2].  Twiddles are
+// compile-time constants (cosine / sine of 2 pi p / R by a Taylor series on
+// [-pi, pi]), so the whole R-point DFT is straight-line code.
+constexpr double ce_pi = 3.14159265358979323846264338327950288;
+constexpr double ce_sin(double x) {
+  double t = x, s = x;
+  for (int k = 1; k < 30; ++k) {
+    t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double ce_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    s += t;
+  }
+  return s;
+}
+// angle of W^p with p folded into (-R/2, R/2]
+constexpr double ce_angle(int p, int R) { return 2.0 * ce_pi * (double)(p * 2 > R ? p - R : p) / (double)R; }
+
+template <int R> struct RadixSplit {
+  static constexpr int A = R % 2 == 0 ? 2 : R % 3 == 0 ? 3 : 5;
+  static constexpr int B = R / A;
+};
+
+template <int... I, typename Fn>
+__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, I...>, Fn&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename Fn> __device__ __forceinline__ void sfor(Fn&& f) {
+  sfor_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+template <typename V, int DIR, int R>
+__device__ __forceinline__ void dft_r(V* x) {
+  if constexpr (R == 2 || R == 3 || R == 4 || R == 5) {
+    dft_small<V, DIR>(x, R);
+  } else {
+    using T = decltype(x[0].x);
+    constexpr int A = RadixSplit<R>::A, B = RadixSplit<R>::B;
+    V y[R];
+    sfor<B>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      V t[A];
+      sfor<A>([&](auto n1c) { t[decltype(n1c)::value] = x[B * decltype(n1c)::value + n2]; });
+      dft_r<V, DIR, A>(t);
+      sfor<A>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        constexpr int p = (n2 * k1) % R;
+        if constexpr (p == 0) {
+          y[n2 * A + k1] = t[k1];
+        } else {
+          // W_R^p = exp(-2 pi i p / R) forward, conjugate inverse
+          constexpr double c = ce_cos(ce_angle(p, R)), sn = ce_sin(ce_angle(p, R));
+          V w;
+          w.x = (T)c;
+          w.y = (T)(DIR > 0 ? -sn : sn);
+          y[n2 * A + k1] = cmul(t[k1], w);
+        }
+      });
+    });
+    sfor<A>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      V t[B];
+      sfor<B>([&](auto n2c) { t[decltype(n2c)::value] = y[decltype(n2c)::value * A + k1]; });
+      dft_r<V, DIR, B>(t);
+      sfor<B>([&](auto k2c) { x[k1 + A * decltype(k2c)::value] = t[decltype(k2c)::value]; });
+    });
+  }
+}
+
 template <typename V, int DIR, int R>
 __device__ __forceinline__ void stockham_pass(const V* __restrict__ src, V* __restrict__ dst, const V* __restrict__ tw,
                                               int n, int Ns, int stride, int tid, int nthr) {
@@ -247,13 +324,13 @@ __device__ __forceinline__ void stockham_pass(const V* __restrict__ src, V* __re
     for (int m = 0; m < R; ++m) {
       V x = src[(j + m * nb) * stride + lane];
       if (m > 0 && jm > 0) {
-        V t = tw[(jm * m * twstep) % n];
+        V t = tw[jm * m * twstep];     // jm m < Ns R, so the index stays below n
         if (DIR < 0) t.y = -t.y;
         x = cmul(x, t);
       }
       v[m] = x;
     }
-    dft_small<V, DIR>(v, R);
+    dft_r<V, DIR, R>(v);
     const int o = (j / Ns) * Ns * R + jm;
 #pragma unroll
     for (int m = 0; m < R; ++m) dst[(o + m * Ns) * stride + lane] = v[m];
@@ -274,7 +351,14 @@ __device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, 
       case 2: stockham_pass<V, DIR, 2>(src, dst, tw, n, Ns, stride, tid, nthr); break;
       case 3: stockham_pass<V, DIR, 3>(src, dst, tw, n, Ns, stride, tid, nthr); break;
       case 4: stockham_pass<V, DIR, 4>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      default: stockham_pass<V, DIR, 5>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 5: stockham_pass<V, DIR, 5>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 6: stockham_pass<V, DIR, 6>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 8: stockham_pass<V, DIR, 8>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 9: stockham_pass<V, DIR, 9>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 10: stockham_pass<V, DIR, 10>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 12: stockham_pass<V, DIR, 12>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 15: stockham_pass<V, DIR, 15>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      default: stockham_pass<V, DIR, 16>(src, dst, tw, n, Ns, stride, tid, nthr); break;
     }
     __syncthreads();
     V* t = src;
