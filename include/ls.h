@@ -165,6 +165,7 @@ typedef struct {
                            workgroup), 1 single-buffered, 2 / 3 double-buffered with 32 / 64 cells */
   int csr_variant;      /* boundary-patch rows: 0 four entries per lane, 1 one entry per lane,
                            2 four entries per lane with run-length column storage */
+  int fft_variant;      /* 0 separate column transforms and spectral product, 1 fused per column tile */
   double fft_ms;        /* best time of the transform stages with the chosen tile */
   double near_ms;       /* best time of the interior contraction stage */
   double csr_ms;        /* best time of the boundary-patch rows stage */

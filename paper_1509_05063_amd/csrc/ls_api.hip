@@ -761,22 +761,29 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
     return LS_OK;
   };
   // column tile of the transforms (stages 2-4: forward, spectral, inverse)
-  const int tmax = std::max(1, (int)(150 * 1024 / (2 * (size_t)d.Pa * sizeof(T) * 2)));
-  int best_tc = d.tc;
+  // (separate kernels: two buffers of tc columns; fused: two of 2 tc)
+  int best_tc = d.tc, best_fv = d.fft_variant;
   double best = 1e30;
-  for (int tc : {1, 2, 4, 8, 16, 32}) {
-    if (tc > tmax) break;
-    d.tc = tc;
-    double t;
-    ls_status s = measure(2, 4, &t);
-    if (s) return s;
-    if (t < best) {
-      best = t;
-      best_tc = tc;
+  for (int fv = 0; fv < 2; ++fv) {
+    const int tmax = std::max(1, (int)(150 * 1024 / (2 * (size_t)d.Pa * sizeof(T) * 2 * (fv + 1))));
+    for (int tc : {1, 2, 4, 8, 16, 32}) {
+      if (tc > tmax) break;
+      d.tc = tc;
+      d.fft_variant = fv;
+      double t;
+      ls_status s = measure(2, 4, &t);
+      if (s) return s;
+      if (t < best) {
+        best = t;
+        best_tc = tc;
+        best_fv = fv;
+      }
     }
   }
   d.tc = best_tc;
+  d.fft_variant = best_fv;
   res->fft_col_tile = best_tc;
+  res->fft_variant = best_fv;
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
   const int nnear = std::is_same<T, float>::value ? 4 : 1;

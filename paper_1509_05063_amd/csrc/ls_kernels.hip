@@ -417,6 +417,53 @@ __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const
   }
 }
 
+// Column transforms, spectral product and inverse column transform in one
+// workgroup per TC-column tile of one set: the tile's monopole and dipole
+// columns are transformed together (2 TC interleaved columns), multiplied by
+// the set's two kernel spectra and summed, and the sum is transformed back;
+// only rows < na (the ones the interpolation reads) go back to memory, in the
+// set's kind-0 plane.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fft_cols_conv(typename C2<T>::t* lat, const typename C2<T>::t* __restrict__ tw,
+                                                       const typename C2<T>::t* __restrict__ khat, FftPlan plan,
+                                                       int ncols, int TC, int64_t plane, int na) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  const int n = plan.n, W = 2 * TC;
+  V* b0 = reinterpret_cast<V*>(smem_raw);   // [n][2 TC]: monopole columns, then dipole columns
+  V* b1 = b0 + (size_t)n * W;
+  const int c0 = blockIdx.x * TC;
+  const int s = blockIdx.y & 1, r = blockIdx.y >> 1;
+  const int tc = min(TC, ncols - c0);
+  V* mp = lat + ((int64_t)(r * 2 + s) * 2) * plane + c0;
+  for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
+    const int row = i / W, cc = i % W, kind = cc / TC, col = cc % TC;
+    b0[i] = (col < tc && row < na) ? mp[kind * plane + (int64_t)row * ncols + col] : czero<V>();
+  }
+  __syncthreads();
+  V* res;
+  stockham_lds<V, 1>(b0, b1, tw, n, plan.radix, plan.npass, W, threadIdx.x, blockDim.x, &res);
+  V* fr = res == b0 ? b1 : b0;               // free buffer: two [n][TC] halves
+  const V* km = khat + (int64_t)(s * 2) * plane + c0;
+  for (int i = threadIdx.x; i < n * TC; i += blockDim.x) {
+    const int row = i / TC, col = i % TC;
+    V o = czero<V>();
+    if (col < tc) {
+      const int64_t k = (int64_t)row * ncols + col;
+      o = cmul(res[row * W + col], km[k]);
+      o = cfma(res[row * W + TC + col], km[plane + k], o);
+    }
+    fr[i] = o;
+  }
+  __syncthreads();
+  V* res2;
+  stockham_lds<V, -1>(fr, fr + (size_t)n * TC, tw, n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res2);
+  for (int i = threadIdx.x; i < na * TC; i += blockDim.x) {
+    const int row = i / TC, col = i % TC;
+    if (col < tc) mp[(int64_t)row * ncols + col] = res2[i];
+  }
+}
+
 // spectral product: set s field = FFT(mono) Khat_m + FFT(dip) Khat_d (into kind 0)
 template <typename T>
 __global__ void k_spectral(typename C2<T>::t* __restrict__ lat, const typename C2<T>::t* __restrict__ khat,
@@ -1687,20 +1734,29 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     hipLaunchKernelGGL((k_fft_rows<T, 1>), dim3(d.na, nbatch), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
                        (int64_t)d.Pb, d.nb, d.Pb, plane);
     int TC = TCP;
-    size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
-    hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, lat,
-                       (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa);
+    if (d.fft_variant == 1) {
+      // fused column transforms + spectral product + inverse column transforms
+      size_t shc = 4 * (size_t)d.pa.n * TC * sizeof(V);
+      hipLaunchKernelGGL(k_fft_cols_conv<T>, dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
+                         (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na);
+    } else {
+      size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
+      hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, lat,
+                         (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa);
+    }
   }
   mark(3);
-  hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, lat,
-                     (const V*)d.khat, plane);
+  if (d.fft_variant != 1)
+    hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, lat,
+                       (const V*)d.khat, plane);
   mark(4);
   {
     // inverse transforms of kind 0 of each set: batch stride 2 planes
     int TC = TCP;
     size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
-    hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
-                       (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na);
+    if (d.fft_variant != 1)
+      hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
+                         (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na);
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     hipLaunchKernelGGL((k_fft_rows<T, -1>), dim3(d.na, nrhs * 2), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
                        (int64_t)d.Pb, d.Pb, d.nb, 2 * plane);
@@ -1806,6 +1862,8 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_rows<float, -1>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
+  set((const void*)k_fft_cols_conv<double>);
+  set((const void*)k_fft_cols_conv<float>);
   return e;
 }
 

@@ -24,6 +24,9 @@ struct DevView {
   // 0 = four entries per lane (single precision, 16-bit offsets), 1 = one,
   // 2 = four entries per lane with run-length columns
   int near_variant = 0, csr_variant = 0;
+  // fft_variant 0 = separate column transforms and spectral product, 1 =
+  // fused per column tile
+  int fft_variant = 0;
   bool csr_f64 = true;
   double kappa = 0;
   const void *Psh = nullptr, *PshT = nullptr, *Pbd = nullptr, *Ish = nullptr, *Ibd = nullptr, *Toff = nullptr, *Wsh = nullptr;

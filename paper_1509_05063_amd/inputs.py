@@ -67,7 +67,7 @@ def config(name):
         c = _base(32 * math.pi, 1.0 / 512, 0.3, 5, 0.9, 4096, 32, 0.9, 0.975)
         c["n2"] = {"kind": "gauss", "base": 1.0, "amp": 0.8, "decay": 4.0}
         c["incidence"] = [math.pi / 6]
-        c["gmres"] = {"tol": 1e-8, "restart": 60}
+        c["gmres"] = {"tol": 1e-8, "restart": 100}
     elif name == "star_k16pi":
         c = _base(16 * math.pi, 1.0 / 256, 0.3, 5, 0.9, 2048, 32, 0.9, 0.975)
         c["n2"] = {"kind": "gauss", "base": 1.0, "amp": 0.8, "decay": 4.0}
