@@ -52,7 +52,7 @@ def stage_bytes(st, N, n_int, s, s_w, csr_variant=0):
         "interp": ncell * (F + 9 * U) * s + nb * F * s_w + 2 * N * s,
         "near_shared": S * Wn * Wn * s_w + n_int * (s + r) + 2 * n_int * s,
         "near_csr": (st["csr_nnz"] * (s_w + 2) + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s
-                     if csr_variant != 2 else
+                     if csr_variant not in (2, 3) else
                      st["csr_nnz"] * s_w + st["csr_runs"] * 8 + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s),
     }
 
@@ -309,7 +309,8 @@ def main():
     achieved = byts[dom] / (p32[dom] * 1e-3) / 1e9
     kname = STAGE_KERNEL.get(dom, dom)
     if tune and dom == "near_csr":
-        kname = {0: "k_near_csr4", 1: "k_near_csr<float>", 2: "k_near_csr4r"}[tune["fp32"]["csr_variant"]]
+        kname = {0: "k_near_csr4", 1: "k_near_csr<float>", 2: "k_near_csr4r", 3: "k_near_blk<4>"}[
+            tune["fp32"]["csr_variant"]]
     if tune and dom == "near_shared":
         nv = tune["fp32"]["near_variant"]
         kname = "k_near_shared_mfma<float,2>" if nv == 1 else f"k_near_shared_mfma_db<{ {0: 1, 2: 2, 3: 4}[nv] }>"

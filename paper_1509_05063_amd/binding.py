@@ -78,6 +78,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1509_05063_amd.build`")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so both share one runtime (and one device context)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         sig = {
@@ -248,9 +251,10 @@ class Operator:
         return lib().ls_resident_bytes(self._op)
 
     def stats(self):
-        out = (C.c_int64 * 13)()
-        _check(lib().ls_op_stats(self._op, out, 13), "ls_op_stats")
-        names = ["N", "n_band", "ncell", "L", "csr_rows", "csr_nnz", "Pa", "Pb", "U", "F", "S", "Wn", "csr_runs"]
+        out = (C.c_int64 * 15)()
+        _check(lib().ls_op_stats(self._op, out, 15), "ls_op_stats")
+        names = ["N", "n_band", "ncell", "L", "csr_rows", "csr_nnz", "Pa", "Pb", "U", "F", "S", "Wn", "csr_runs",
+                 "blk_entries", "res_nnz"]
         return dict(zip(names, list(out)))
 
     def workspace_bytes(self, nrhs, prec):

@@ -5,6 +5,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <map>
@@ -50,7 +52,7 @@ struct ls_op {
   lsx::DevView<double> d64;
   lsx::DevView<float> d32;
   double kappa = 0;
-  int64_t stats[13] = {0};
+  int64_t stats[15] = {0};
   // solver scratch
   void* gm = nullptr;
   size_t gm_bytes = 0;
@@ -591,6 +593,125 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
       UP(upload_i(op, rpre, &a.run_pre));
     }
   }
+  {
+    // Single precision, batched use: the rows split into dense blocks (one
+    // cell's targets of one kind against the points of its 3 x 3 adjacent
+    // cells, which they all couple to) and the remainder entries.
+    const int64_t N = h.N;
+    std::vector<int32_t> cell_of((size_t)N, -1);
+    for (int c = 0; c < h.ncell; ++c)
+      for (int64_t j = h.cell_start[c]; j < (int64_t)h.cell_start[c] + h.cell_nint[c] + h.cell_nb[c]; ++j)
+        cell_of[(size_t)j] = c;
+    std::vector<int32_t> bt_rows, bt_info, bt_cols, res_rows, res_cols;
+    std::vector<int64_t> bt_woff, res_ptr{0};
+    std::vector<Fp32c> bt_w;
+    std::vector<cd> res_vals;
+    std::vector<int32_t> pos((size_t)h.ncell, -1);   // block column of an adjacent cell's first point
+    const size_t nr = h.rows.size();
+    auto is_band = [&](int32_t i) { return h.key[3 * (size_t)i] == 1; };
+    size_t r = 0;
+    while (r < nr) {
+      const int c = cell_of[(size_t)h.rows[r]];
+      const bool tb = is_band(h.rows[r]);
+      size_t r1 = r;
+      while (r1 < nr && cell_of[(size_t)h.rows[r1]] == c && is_band(h.rows[r1]) == tb) ++r1;
+      std::vector<int> adj;
+      const int cx = h.cell_xy[2 * c], cy = h.cell_xy[2 * c + 1];
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int x = cx + ox, y = cy + oy;
+          if (x < 0 || y < 0 || x >= h.L || y >= h.L) continue;
+          const int cc = h.cell_map[(size_t)y * h.L + x];
+          if (cc >= 0) adj.push_back(cc);
+        }
+      std::sort(adj.begin(), adj.end());
+      auto first = [&](int cc) { return h.cell_start[cc] + (tb ? 0 : h.cell_nint[cc]); };
+      const int32_t coff = (int32_t)bt_cols.size();
+      for (int cc : adj) {
+        pos[cc] = (int32_t)bt_cols.size() - coff;
+        for (int32_t j = first(cc); j < h.cell_start[cc] + h.cell_nint[cc] + h.cell_nb[cc]; ++j) bt_cols.push_back(j);
+      }
+      const int K = (int)bt_cols.size() - coff, Kp = (K + 3) & ~3;
+      for (int k = K; k < Kp; ++k) bt_cols.push_back(bt_cols[coff]);
+      for (size_t t0 = r; t0 < r1; t0 += 16) {
+        int64_t woff = -1;
+        if (Kp > 0) {
+          woff = (int64_t)bt_w.size();
+          bt_w.resize(bt_w.size() + (size_t)Kp * 16, Fp32c{0.f, 0.f});
+          bt_woff.push_back(woff);
+          bt_info.push_back(Kp);
+          bt_info.push_back(coff);
+        }
+        for (int q = 0; q < 16; ++q) {
+          const size_t rr = t0 + q;
+          if (Kp > 0) bt_rows.push_back(rr < r1 ? h.rows[rr] : -1);
+          if (rr >= r1) continue;
+          const size_t rs = res_cols.size();
+          for (int64_t k = h.rowptr[rr]; k < h.rowptr[rr + 1]; ++k) {
+            const int32_t j = h.cols[k];
+            const int cj = cell_of[(size_t)j];
+            if (Kp > 0 && pos[cj] >= 0 && j >= first(cj)) {
+              const int kk = pos[cj] + (j - first(cj));
+              Fp32c& w = bt_w[(size_t)woff + (size_t)(kk / 4) * 64 + (kk % 4) * 16 + q];
+              w.x += (float)h.vals[k].real();
+              w.y += (float)h.vals[k].imag();
+            } else {
+              res_cols.push_back(j);
+              res_vals.push_back(h.vals[k]);
+            }
+          }
+          if (res_cols.size() > rs) {
+            res_rows.push_back(h.rows[rr]);
+            res_ptr.push_back((int64_t)res_cols.size());
+          }
+        }
+      }
+      for (int cc : adj) pos[cc] = -1;
+      r = r1;
+    }
+    // remainder rows padded to four entries, columns as runs
+    const size_t nq = res_rows.size();
+    std::vector<int64_t> qrow(nq + 1, 0);
+    for (size_t k = 0; k < nq; ++k) qrow[k + 1] = qrow[k] + ((res_ptr[k + 1] - res_ptr[k] + 3) & ~int64_t(3));
+    std::vector<int32_t> qptr(nq + 1, 0), qcs, qpre;
+    bool fits = true;
+    for (size_t k = 0; k < nq && fits; ++k) {
+      const int64_t b0 = res_ptr[k], len = res_ptr[k + 1] - b0;
+      for (int64_t e = 0; e < len; ++e)
+        if (e == 0 || res_cols[b0 + e] != res_cols[b0 + e - 1] + 1) {
+          qcs.push_back(res_cols[b0 + e]);
+          qpre.push_back((int32_t)e);
+        }
+      if (qrow[k + 1] - qrow[k] > len) {
+        qcs.push_back(0);
+        qpre.push_back((int32_t)len);
+      }
+      qptr[k + 1] = (int32_t)qcs.size();
+      if (qptr[k + 1] - qptr[k] > 256) fits = false;
+    }
+    if (fits && !bt_woff.empty()) {
+      std::vector<cd> qv((size_t)qrow[nq], cd(0.0, 0.0));
+      for (size_t k = 0; k < nq; ++k)
+        std::copy(res_vals.begin() + res_ptr[k], res_vals.begin() + res_ptr[k + 1], qv.begin() + qrow[k]);
+      void* wd = nullptr;
+      UP(upload(op, bt_w.data(), bt_w.size(), &wd));
+      b.bt_w = wd;
+      UP(upload_i(op, bt_rows, &b.bt_rows));
+      UP(upload_i(op, bt_info, &b.bt_info));
+      UP(upload_i(op, bt_cols, &b.bt_cols));
+      UP(upload_i(op, bt_woff, &b.bt_woff));
+      UP(upload_c(op, qv, nullptr, &b.res_vals));
+      UP(upload_i(op, qrow, &b.res_rowptr));
+      UP(upload_i(op, res_rows, &b.res_rows));
+      UP(upload_i(op, qptr, &b.res_run_ptr));
+      UP(upload_i(op, qcs, &b.res_run_cs));
+      UP(upload_i(op, qpre, &b.res_run_pre));
+      b.bt_ntiles = (int)bt_woff.size();
+      b.res_nrows = (int)nq;
+      op->stats[13] = (int64_t)bt_w.size();
+      op->stats[14] = (int64_t)res_cols.size();
+    }
+  }
   b.slot_map = a.slot_map;
   b.cell_start = a.cell_start;
   b.cell_nint = a.cell_nint;
@@ -677,7 +798,7 @@ size_t ls_resident_bytes(const ls_op* op) { return op ? op->resident : 0; }
 
 ls_status ls_op_stats(const ls_op* op, int64_t* out, int nout) {
   if (!op || !out) return fail(LS_EINVAL, "null argument");
-  for (int i = 0; i < nout && i < 13; ++i) out[i] = op->stats[i];
+  for (int i = 0; i < nout && i < 15; ++i) out[i] = op->stats[i];
   return LS_OK;
 }
 
@@ -748,6 +869,12 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
                         hipEvent_t* ev, ls_tune_result* res) {
   constexpr int reps = 3;
   double ms8[8];
+  // LS_TUNE_LOG=1 prints every candidate's time to stderr
+  const char* lg = std::getenv("LS_TUNE_LOG");
+  const bool logc = lg && lg[0] == '1';
+  auto log = [&](const char* what, int a, int b, double t) {
+    if (logc) std::fprintf(stderr, "ls_autotune nrhs=%d %s %d %d: %.4f ms\n", nrhs, what, a, b, t);
+  };
   // best (smallest) of reps applies for the stages [s0, s1]
   auto measure = [&](int s0, int s1, double* best) -> ls_status {
     *best = 1e30;
@@ -773,6 +900,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
       double t;
       ls_status s = measure(2, 4, &t);
       if (s) return s;
+      log("fft variant/tile", fv, tc, t);
       if (t < best) {
         best = t;
         best_tc = tc;
@@ -794,6 +922,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
     double t;
     ls_status s = measure(6, 6, &t);
     if (s) return s;
+    log("near variant", var, 0, t);
     if (t < best) {
       best = t;
       bv = var;
@@ -804,12 +933,18 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->near_ms = best;
   bv = 0;
   best = 1e30;
-  const int ncsr = std::is_same<T, float>::value ? (d.run_ptr ? 3 : 2) : 1;
-  for (int var = 0; var < ncsr; ++var) {
+  std::vector<int> csr_cands{0};
+  if (std::is_same<T, float>::value) {
+    csr_cands.push_back(1);
+    if (d.run_ptr) csr_cands.push_back(2);
+    if (d.bt_ntiles > 0 && nrhs % 16 == 0) csr_cands.push_back(3);
+  }
+  for (int var : csr_cands) {
     d.csr_variant = var;
     double t;
     ls_status s = measure(7, 7, &t);
     if (s) return s;
+    log("csr variant", var, 0, t);
     if (t < best) {
       best = t;
       bv = var;

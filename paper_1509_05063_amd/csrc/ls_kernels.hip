@@ -1165,6 +1165,94 @@ __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u
   }
 }
 
+// Right-hand-side-major copy for the batched row kernel: ut[i * R + r] = u[r * N + i]
+// (32 x 32 tiles through LDS, both sides coalesced).
+__global__ void __launch_bounds__(256) k_rhs_major(const float2* __restrict__ u, float2* __restrict__ ut, int64_t N,
+                                                   int R) {
+  __shared__ float2 tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32;
+  const int r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k;
+    const int64_t i = i0 + tx;
+    tile[k][tx] = (r < R && i < N) ? u[(int64_t)r * N + i] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t i = i0 + k;
+    const int r = r0 + tx;
+    if (i < N && r < R) ut[i * R + r] = tile[tx][k];
+  }
+}
+
+// a4 on the matrix cores, dense adjacent-cell blocks (single precision, R
+// a multiple of 16 right-hand sides, input right-hand-side-major).  One
+// wavefront per (16-row tile, 16 NT right-hand sides) computes the tile's
+// product as V^T = U^T W^T: MFMA A operand = 16 right-hand sides x 4 columns
+// of the input (row = lane % 16, column k = lane / 16: 16 consecutive words
+// per column), B operand = 4 columns x 16 target rows of the tile's weights
+// (stored so that a step reads 64 consecutive values), complex products as
+// four real products.  Output element (right-hand side 4 (lane / 16) + r,
+// target lane % 16): the 16 lanes of a group add into 16 targets of one
+// right-hand side.  Rows of different tiles are distinct, so the adds do not
+// race.
+template <int NT>
+__global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut, float2* __restrict__ v,
+                                                  const int32_t* __restrict__ bt_rows,
+                                                  const int32_t* __restrict__ bt_info,
+                                                  const int64_t* __restrict__ bt_woff,
+                                                  const int32_t* __restrict__ bt_cols,
+                                                  const float2* __restrict__ bt_w, int ntiles, int64_t N, int R,
+                                                  float k2) {
+  using M = Mfma<float>;
+  typedef M::v4 v4;
+  const int lane = threadIdx.x & 63;
+  const int nch = (R + 16 * NT - 1) / (16 * NT);
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t t = gw / nch;
+  if (t >= ntiles) return;
+  const int n0 = (int)(gw % nch) * 16 * NT;
+  const int ntv = min(NT, (R - n0) / 16);
+  const int K = bt_info[2 * t];
+  const float2* __restrict__ W = bt_w + bt_woff[t] + lane;
+  const int32_t* __restrict__ cols = bt_cols + bt_info[2 * t + 1] + (lane >> 4);
+  const float2* __restrict__ ub = ut + n0 + (lane & 15);
+  v4 re[NT], im[NT];
+#pragma unroll
+  for (int g = 0; g < NT; ++g) {
+    re[g] = v4{0.f, 0.f, 0.f, 0.f};
+    im[g] = v4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll 2
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const float2 w = W[(int64_t)k0 * 16];
+    const float2* __restrict__ uc = ub + (int64_t)cols[k0] * R;
+    float2 a[NT];
+#pragma unroll
+    for (int g = 0; g < NT; ++g) a[g] = g < ntv ? uc[16 * g] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int g = 0; g < NT; ++g) {
+      re[g] = M::op(a[g].x, w.x, re[g]);
+      re[g] = M::op(-a[g].y, w.y, re[g]);
+      im[g] = M::op(a[g].x, w.y, im[g]);
+      im[g] = M::op(a[g].y, w.x, im[g]);
+    }
+  }
+  const int j = bt_rows[t * 16 + (lane & 15)];
+  if (j < 0) return;
+#pragma unroll
+  for (int g = 0; g < NT; ++g) {
+    if (g >= ntv) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float2* p = v + (int64_t)(n0 + 16 * g + M::row(lane, r)) * N + j;
+      const float2 o = *p;
+      *p = cadd(o, cscale(make_float2(re[g][r], im[g][r]), k2));
+    }
+  }
+}
+
 // a4, rows touching the boundary patch: one wavefront per row; each weight
 // is loaded once and applied to up to four right-hand sides; four entries
 // per lane in flight.
@@ -1825,7 +1913,25 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
                            d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
     } else {
-      if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant == 2)
+      // dense blocks: right-hand-side-major input copied into the lattice
+      // region (free after the interpolation; large enough, checked here),
+      // then the remainder rows
+      const bool blk = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant == 3 && nrhs % 16 == 0 &&
+                       (int64_t)4 * plane >= d.N;
+      if (blk) {
+        float2* ut = (float2*)lat;
+        hipLaunchKernelGGL(k_rhs_major, dim3((unsigned)((d.N + 31) / 32), (nrhs + 31) / 32), dim3(256), 0, st,
+                           (const float2*)u, ut, d.N, nrhs);
+        constexpr int NT = 4;
+        const int64_t waves = (int64_t)d.bt_ntiles * ((nrhs + 16 * NT - 1) / (16 * NT));
+        hipLaunchKernelGGL(k_near_blk<NT>, dim3((unsigned)((waves + 3) / 4)), b, 0, st, (const float2*)ut,
+                           (float2*)v, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
+                           d.bt_ntiles, d.N, nrhs, (float)k2);
+        if (d.res_nrows > 0)
+          hipLaunchKernelGGL(k_near_csr4r, dim3((d.res_nrows + 3) / 4), b, 0, st, (const float2*)u, (float2*)v,
+                             d.res_rowptr, d.res_rows, d.res_run_ptr, d.res_run_cs, d.res_run_pre,
+                             (const float2*)d.res_vals, d.res_nrows, d.N, nrhs, (float)k2);
+      } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
         hipLaunchKernelGGL(k_near_csr4r, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.run_ptr,
                            d.run_cs, d.run_pre, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
       else if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
