@@ -133,10 +133,9 @@ size_t ls_resident_bytes(const ls_op* op);
  * occupied cells, cells per axis, near-field CSR rows, CSR entries, padded
  * face-lattice dims Pa, Pb, equivalent-source unknowns per cell U, face
  * values per cell F, interior slots per cell S, near-field window side,
- * column runs of the CSR rows (0 when the run form is not kept), stored
- * entries of the dense adjacent-cell blocks (16-row tiles, single precision)
- * and entries left to the remainder rows (both 0 when the block form is not
- * kept). */
+ * column runs of the CSR rows (0 when the run form is not kept), weights
+ * stored in the dense 16-row tiles (single precision, zeros included) and
+ * of those the ones in columns beyond the rows' adjacent cells. */
 ls_status ls_op_stats(const ls_op* op, int64_t* out, int nout);
 
 /* Workspace bytes ls_apply needs for nrhs vectors in precision prec. */
@@ -168,8 +167,8 @@ typedef struct {
                            workgroup), 1 single-buffered, 2 / 3 double-buffered with 32 / 64 cells */
   int csr_variant;      /* boundary-patch rows: 0 four entries per lane, 1 one entry per lane,
                            2 four entries per lane with run-length column storage,
-                           3 dense adjacent-cell blocks on the matrix cores plus the remaining
-                           entries as in 2 (candidate for multiples of 16 right-hand sides) */
+                           3 dense 16-row tiles on the matrix cores (candidate for multiples
+                           of 16 right-hand sides) */
   int fft_variant;      /* 0 separate column transforms and spectral product, 1 fused per column tile */
   double fft_ms;        /* best time of the transform stages with the chosen tile */
   double near_ms;       /* best time of the interior contraction stage */

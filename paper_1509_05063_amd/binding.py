@@ -254,7 +254,7 @@ class Operator:
         out = (C.c_int64 * 15)()
         _check(lib().ls_op_stats(self._op, out, 15), "ls_op_stats")
         names = ["N", "n_band", "ncell", "L", "csr_rows", "csr_nnz", "Pa", "Pb", "U", "F", "S", "Wn", "csr_runs",
-                 "blk_entries", "res_nnz"]
+                 "tile_weights", "tile_extra_weights"]
         return dict(zip(names, list(out)))
 
     def workspace_bytes(self, nrhs, prec):

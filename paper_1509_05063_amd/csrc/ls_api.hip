@@ -594,19 +594,21 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     }
   }
   {
-    // Single precision, batched use: the rows split into dense blocks (one
-    // cell's targets of one kind against the points of its 3 x 3 adjacent
-    // cells, which they all couple to) and the remainder entries.
+    // Single precision, batched use: the rows as dense tiles of 16 rows of
+    // one cell and kind.  A tile's columns are the points of the 3 x 3
+    // adjacent cells that all its rows couple to (every point for
+    // boundary-patch targets, the boundary-patch points for interior
+    // targets), followed by the union of its rows' other columns.
     const int64_t N = h.N;
     std::vector<int32_t> cell_of((size_t)N, -1);
     for (int c = 0; c < h.ncell; ++c)
       for (int64_t j = h.cell_start[c]; j < (int64_t)h.cell_start[c] + h.cell_nint[c] + h.cell_nb[c]; ++j)
         cell_of[(size_t)j] = c;
-    std::vector<int32_t> bt_rows, bt_info, bt_cols, res_rows, res_cols;
-    std::vector<int64_t> bt_woff, res_ptr{0};
+    std::vector<int32_t> bt_rows, bt_info, bt_cols, adjcols, extra;
+    std::vector<int64_t> bt_woff;
     std::vector<Fp32c> bt_w;
-    std::vector<cd> res_vals;
-    std::vector<int32_t> pos((size_t)h.ncell, -1);   // block column of an adjacent cell's first point
+    int64_t n_extra = 0;
+    std::vector<int32_t> pos((size_t)h.ncell, -1);   // column of an adjacent cell's first point
     const size_t nr = h.rows.size();
     auto is_band = [&](int32_t i) { return h.key[3 * (size_t)i] == 1; };
     size_t r = 0;
@@ -626,73 +628,50 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
         }
       std::sort(adj.begin(), adj.end());
       auto first = [&](int cc) { return h.cell_start[cc] + (tb ? 0 : h.cell_nint[cc]); };
-      const int32_t coff = (int32_t)bt_cols.size();
+      adjcols.clear();
       for (int cc : adj) {
-        pos[cc] = (int32_t)bt_cols.size() - coff;
-        for (int32_t j = first(cc); j < h.cell_start[cc] + h.cell_nint[cc] + h.cell_nb[cc]; ++j) bt_cols.push_back(j);
+        pos[cc] = (int32_t)adjcols.size();
+        for (int32_t j = first(cc); j < h.cell_start[cc] + h.cell_nint[cc] + h.cell_nb[cc]; ++j) adjcols.push_back(j);
       }
-      const int K = (int)bt_cols.size() - coff, Kp = (K + 3) & ~3;
-      for (int k = K; k < Kp; ++k) bt_cols.push_back(bt_cols[coff]);
+      auto in_adj = [&](int32_t j) { const int cj = cell_of[(size_t)j]; return pos[cj] >= 0 && j >= first(cj); };
+      const int Ka = (int)adjcols.size();
       for (size_t t0 = r; t0 < r1; t0 += 16) {
-        int64_t woff = -1;
-        if (Kp > 0) {
-          woff = (int64_t)bt_w.size();
-          bt_w.resize(bt_w.size() + (size_t)Kp * 16, Fp32c{0.f, 0.f});
-          bt_woff.push_back(woff);
-          bt_info.push_back(Kp);
-          bt_info.push_back(coff);
-        }
+        const size_t t1 = std::min(r1, t0 + 16);
+        extra.clear();
+        for (size_t rr = t0; rr < t1; ++rr)
+          for (int64_t k = h.rowptr[rr]; k < h.rowptr[rr + 1]; ++k)
+            if (!in_adj(h.cols[k])) extra.push_back(h.cols[k]);
+        std::sort(extra.begin(), extra.end());
+        extra.erase(std::unique(extra.begin(), extra.end()), extra.end());
+        const int K = Ka + (int)extra.size(), Kp = (K + 3) & ~3;
+        const int32_t coff = (int32_t)bt_cols.size();
+        bt_cols.insert(bt_cols.end(), adjcols.begin(), adjcols.end());
+        bt_cols.insert(bt_cols.end(), extra.begin(), extra.end());
+        for (int k = K; k < Kp; ++k) bt_cols.push_back(bt_cols[coff]);
+        const int64_t woff = (int64_t)bt_w.size();
+        bt_w.resize(bt_w.size() + (size_t)Kp * 16, Fp32c{0.f, 0.f});
+        bt_woff.push_back(woff);
+        bt_info.push_back(Kp);
+        bt_info.push_back(coff);
+        n_extra += (int64_t)(Kp - Ka) * 16;
         for (int q = 0; q < 16; ++q) {
           const size_t rr = t0 + q;
-          if (Kp > 0) bt_rows.push_back(rr < r1 ? h.rows[rr] : -1);
-          if (rr >= r1) continue;
-          const size_t rs = res_cols.size();
+          bt_rows.push_back(rr < t1 ? h.rows[rr] : -1);
+          if (rr >= t1) continue;
           for (int64_t k = h.rowptr[rr]; k < h.rowptr[rr + 1]; ++k) {
             const int32_t j = h.cols[k];
-            const int cj = cell_of[(size_t)j];
-            if (Kp > 0 && pos[cj] >= 0 && j >= first(cj)) {
-              const int kk = pos[cj] + (j - first(cj));
-              Fp32c& w = bt_w[(size_t)woff + (size_t)(kk / 4) * 64 + (kk % 4) * 16 + q];
-              w.x += (float)h.vals[k].real();
-              w.y += (float)h.vals[k].imag();
-            } else {
-              res_cols.push_back(j);
-              res_vals.push_back(h.vals[k]);
-            }
-          }
-          if (res_cols.size() > rs) {
-            res_rows.push_back(h.rows[rr]);
-            res_ptr.push_back((int64_t)res_cols.size());
+            const int kk = in_adj(j) ? pos[cell_of[(size_t)j]] + (j - first(cell_of[(size_t)j]))
+                                     : Ka + (int)(std::lower_bound(extra.begin(), extra.end(), j) - extra.begin());
+            Fp32c& w = bt_w[(size_t)woff + (size_t)(kk / 4) * 64 + (kk % 4) * 16 + q];
+            w.x += (float)h.vals[k].real();
+            w.y += (float)h.vals[k].imag();
           }
         }
       }
       for (int cc : adj) pos[cc] = -1;
       r = r1;
     }
-    // remainder rows padded to four entries, columns as runs
-    const size_t nq = res_rows.size();
-    std::vector<int64_t> qrow(nq + 1, 0);
-    for (size_t k = 0; k < nq; ++k) qrow[k + 1] = qrow[k] + ((res_ptr[k + 1] - res_ptr[k] + 3) & ~int64_t(3));
-    std::vector<int32_t> qptr(nq + 1, 0), qcs, qpre;
-    bool fits = true;
-    for (size_t k = 0; k < nq && fits; ++k) {
-      const int64_t b0 = res_ptr[k], len = res_ptr[k + 1] - b0;
-      for (int64_t e = 0; e < len; ++e)
-        if (e == 0 || res_cols[b0 + e] != res_cols[b0 + e - 1] + 1) {
-          qcs.push_back(res_cols[b0 + e]);
-          qpre.push_back((int32_t)e);
-        }
-      if (qrow[k + 1] - qrow[k] > len) {
-        qcs.push_back(0);
-        qpre.push_back((int32_t)len);
-      }
-      qptr[k + 1] = (int32_t)qcs.size();
-      if (qptr[k + 1] - qptr[k] > 256) fits = false;
-    }
-    if (fits && !bt_woff.empty()) {
-      std::vector<cd> qv((size_t)qrow[nq], cd(0.0, 0.0));
-      for (size_t k = 0; k < nq; ++k)
-        std::copy(res_vals.begin() + res_ptr[k], res_vals.begin() + res_ptr[k + 1], qv.begin() + qrow[k]);
+    if (!bt_woff.empty()) {
       void* wd = nullptr;
       UP(upload(op, bt_w.data(), bt_w.size(), &wd));
       b.bt_w = wd;
@@ -700,16 +679,9 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
       UP(upload_i(op, bt_info, &b.bt_info));
       UP(upload_i(op, bt_cols, &b.bt_cols));
       UP(upload_i(op, bt_woff, &b.bt_woff));
-      UP(upload_c(op, qv, nullptr, &b.res_vals));
-      UP(upload_i(op, qrow, &b.res_rowptr));
-      UP(upload_i(op, res_rows, &b.res_rows));
-      UP(upload_i(op, qptr, &b.res_run_ptr));
-      UP(upload_i(op, qcs, &b.res_run_cs));
-      UP(upload_i(op, qpre, &b.res_run_pre));
       b.bt_ntiles = (int)bt_woff.size();
-      b.res_nrows = (int)nq;
       op->stats[13] = (int64_t)bt_w.size();
-      op->stats[14] = (int64_t)res_cols.size();
+      op->stats[14] = n_extra;
     }
   }
   b.slot_map = a.slot_map;

@@ -1186,8 +1186,8 @@ __global__ void __launch_bounds__(256) k_rhs_major(const float2* __restrict__ u,
   }
 }
 
-// a4 on the matrix cores, dense adjacent-cell blocks (single precision, R
-// a multiple of 16 right-hand sides, input right-hand-side-major).  One
+// a4 on the matrix cores, dense tiles of 16 rows (single precision, R a
+// multiple of 16 right-hand sides, input right-hand-side-major).  One
 // wavefront per (16-row tile, 16 NT right-hand sides) computes the tile's
 // product as V^T = U^T W^T: MFMA A operand = 16 right-hand sides x 4 columns
 // of the input (row = lane % 16, column k = lane / 16: 16 consecutive words
@@ -1216,7 +1216,7 @@ __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut,
   const int ntv = min(NT, (R - n0) / 16);
   const int K = bt_info[2 * t];
   const float2* __restrict__ W = bt_w + bt_woff[t] + lane;
-  const int32_t* __restrict__ cols = bt_cols + bt_info[2 * t + 1] + (lane >> 4);
+  const int32_t* __restrict__ cl = bt_cols + bt_info[2 * t + 1];
   const float2* __restrict__ ub = ut + n0 + (lane & 15);
   v4 re[NT], im[NT];
 #pragma unroll
@@ -1224,13 +1224,30 @@ __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut,
     re[g] = v4{0.f, 0.f, 0.f, 0.f};
     im[g] = v4{0.f, 0.f, 0.f, 0.f};
   }
-#pragma unroll 2
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const float2 w = W[(int64_t)k0 * 16];
-    const float2* __restrict__ uc = ub + (int64_t)cols[k0] * R;
+  // the tile's columns 64 at a time, one per lane; step s (4 columns) takes
+  // its column from lane 4 (s % 16) + lane / 16.  Operands of step s + 1 are
+  // loaded before the products of step s.
+  const int nsteps = K / 4;
+  int colreg = cl[min(lane, K - 1)];
+  float2 wn = W[0], an[NT];
+  {
+    const float2* __restrict__ uc = ub + (int64_t)__shfl(colreg, lane >> 4, 64) * R;
+#pragma unroll
+    for (int g = 0; g < NT; ++g) an[g] = g < ntv ? uc[16 * g] : make_float2(0.f, 0.f);
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    const float2 w = wn;
     float2 a[NT];
 #pragma unroll
-    for (int g = 0; g < NT; ++g) a[g] = g < ntv ? uc[16 * g] : make_float2(0.f, 0.f);
+    for (int g = 0; g < NT; ++g) a[g] = an[g];
+    const int s1 = s + 1;
+    if (s1 < nsteps) {
+      if ((s1 & 15) == 0) colreg = cl[min(4 * s1 + lane, K - 1)];
+      wn = W[(int64_t)s1 * 64];
+      const float2* __restrict__ uc = ub + (int64_t)__shfl(colreg, 4 * (s1 & 15) + (lane >> 4), 64) * R;
+#pragma unroll
+      for (int g = 0; g < NT; ++g) an[g] = g < ntv ? uc[16 * g] : make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int g = 0; g < NT; ++g) {
       re[g] = M::op(a[g].x, w.x, re[g]);
@@ -1913,9 +1930,8 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
                            d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
     } else {
-      // dense blocks: right-hand-side-major input copied into the lattice
-      // region (free after the interpolation; large enough, checked here),
-      // then the remainder rows
+      // dense tiles: right-hand-side-major input copied into the lattice
+      // region (free after the interpolation; large enough, checked here)
       const bool blk = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant == 3 && nrhs % 16 == 0 &&
                        (int64_t)4 * plane >= d.N;
       if (blk) {
@@ -1927,10 +1943,6 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         hipLaunchKernelGGL(k_near_blk<NT>, dim3((unsigned)((waves + 3) / 4)), b, 0, st, (const float2*)ut,
                            (float2*)v, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
                            d.bt_ntiles, d.N, nrhs, (float)k2);
-        if (d.res_nrows > 0)
-          hipLaunchKernelGGL(k_near_csr4r, dim3((d.res_nrows + 3) / 4), b, 0, st, (const float2*)u, (float2*)v,
-                             d.res_rowptr, d.res_rows, d.res_run_ptr, d.res_run_cs, d.res_run_pre,
-                             (const float2*)d.res_vals, d.res_nrows, d.N, nrhs, (float)k2);
       } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
         hipLaunchKernelGGL(k_near_csr4r, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.run_ptr,
                            d.run_cs, d.run_pre, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);

@@ -22,10 +22,9 @@ struct DevView {
   // interior contraction, 16 cells per workgroup (single precision), 1 =
   // single-buffered, 2 / 3 = double-buffered with 32 / 64 cells; csr_variant
   // 0 = four entries per lane (single precision, 16-bit offsets), 1 = one,
-  // 2 = four entries per lane with run-length columns, 3 = dense
-  // adjacent-cell blocks on the matrix cores plus the remainder rows as in 2
-  // (right-hand-side-major input; used when nrhs is a multiple of 16, else
-  // as 2)
+  // 2 = four entries per lane with run-length columns, 3 = dense tiles on
+  // the matrix cores (right-hand-side-major input; used when nrhs is a
+  // multiple of 16, else as 2)
   int near_variant = 0, csr_variant = 0;
   // fft_variant 0 = separate column transforms and spectral product, 1 =
   // fused per column tile
@@ -45,22 +44,17 @@ struct DevView {
   // run_ptr[i] + r, covering the row's entries from run_pre on at columns
   // run_cs, run_cs + 1, ... (null when some row has more than 256 runs)
   const int32_t *run_ptr = nullptr, *run_cs = nullptr, *run_pre = nullptr;
-  // Single precision only: the same rows split into dense blocks and a
-  // remainder.  A block is one cell's rows of one kind (boundary-patch
-  // targets: every point of the 3 x 3 adjacent cells; interior targets: the
-  // boundary-patch points of those cells), cut into tiles of 16 rows.  Tile
-  // t: target rows bt_rows[16 t ..] (-1 = padding), K = bt_info[2 t]
-  // (multiple of 4) columns listed at bt_cols + bt_info[2 t + 1], weights at
-  // bt_w + bt_woff[t] as [K / 4][4 columns][16 rows].  Entries outside the
-  // blocks form the remainder rows (res_*, padded to four entries, columns as
-  // runs like run_*).
-  int bt_ntiles = 0, res_nrows = 0;
+  // Single precision only: the same rows as dense tiles of 16 rows of one
+  // cell and kind (boundary-patch or interior targets).  Tile t: target rows
+  // bt_rows[16 t ..] (-1 = padding), K = bt_info[2 t] (multiple of 4)
+  // columns listed at bt_cols + bt_info[2 t + 1] (the points of the 3 x 3
+  // adjacent cells the rows all couple to, then the union of the rows'
+  // other columns), weights at bt_w + bt_woff[t] as [K / 4][4 columns][16
+  // rows], zero where a row has no entry.
+  int bt_ntiles = 0;
   const int32_t *bt_rows = nullptr, *bt_info = nullptr, *bt_cols = nullptr;
   const int64_t* bt_woff = nullptr;
   const void* bt_w = nullptr;
-  const int64_t* res_rowptr = nullptr;
-  const int32_t *res_rows = nullptr, *res_run_ptr = nullptr, *res_run_cs = nullptr, *res_run_pre = nullptr;
-  const void* res_vals = nullptr;
   FftPlan pa{}, pb{};
 };
 
