@@ -197,7 +197,9 @@ typedef struct {
   int max_iter;         /* total inner iterations per vector */
   int restart;          /* GMRES(m) restart length */
   ls_solve_mode mode;   /* FP64 GMRES, or FP32 GMRES inside FP64 refinement */
-  double inner_tol;     /* relative tolerance of each inner FP32 solve */
+  double inner_tol;     /* relative tolerance of each inner FP32 solve (per vector, an inner
+                           solve stops earlier once it has half the reduction still needed
+                           to reach tol) */
   int max_outer;        /* refinement steps */
   int use_x0;           /* nonzero: u_tot holds the initial guess */
   ls_ortho ortho;       /* Gram–Schmidt passes (zero-initialised = CGS2) */

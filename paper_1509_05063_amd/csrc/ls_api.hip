@@ -1105,7 +1105,8 @@ struct Hessenberg {
   std::vector<std::complex<double>> H, cs, sn, gv;
   std::vector<int> kdone;     // Krylov dimension at which each rhs met its tolerance (-1: not yet)
 
-  void reset(int R_, int m_, const std::vector<double>& beta, const std::vector<double>& relres, double tol) {
+  void reset(int R_, int m_, const std::vector<double>& beta, const std::vector<double>& relres,
+             const std::vector<double>& tol) {
     R = R_;
     m = m_;
     H.assign((size_t)R * (m + 1) * m, 0.0);
@@ -1115,7 +1116,7 @@ struct Hessenberg {
     kdone.assign(R, -1);
     for (int r = 0; r < R; ++r) {
       gv[(size_t)r * (m + 1)] = beta[r];
-      if (relres[r] <= tol) kdone[r] = 0;
+      if (relres[r] <= tol[r]) kdone[r] = 0;
     }
   }
 
@@ -1171,8 +1172,8 @@ struct Hessenberg {
 // step is discarded.
 extern "C++" {
 template <bool F32>
-ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, int max_iter, int* iters,
-                std::vector<double>& relres) {
+ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vector<double>& tol, int max_iter,
+                int* iters, std::vector<double>& relres) {
   const int R = g.nrhs, m = g.m;
   const int64_t N = g.N;
   const int64_t vstride = N * R;          // distance between basis vectors (elements)
@@ -1289,7 +1290,7 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
     for (int r = 0; r < R; ++r) {
       beta[r] = std::sqrt(std::max(0.0, dd[r].real()));
       relres[r] = fnorm[r] > 0 ? beta[r] / fnorm[r] : 0.0;
-      if (relres[r] > tol) all = false;
+      if (relres[r] > tol[r]) all = false;
     }
     if (all || it >= max_iter) break;
     std::vector<double> inv(R);
@@ -1319,7 +1320,7 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, double tol, in
         double hn = std::sqrt(std::max(0.0, dn[r].real()));
         double est = hs.column(r, k, h1 + (size_t)r * (k + 1), h2 ? h2 + (size_t)r * (k + 1) : nullptr, hn);
         est = fnorm[r] > 0 ? est / fnorm[r] : 0.0;
-        if (hs.kdone[r] < 0 && (est <= tol || hn == 0.0)) hs.kdone[r] = k + 1;
+        if (hs.kdone[r] < 0 && (est <= tol[r] || hn == 0.0)) hs.kdone[r] = k + 1;
         if (hs.kdone[r] < 0) all_done = false;
       }
       if (all_done) { ++k; break; }
@@ -1362,11 +1363,15 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
   if (!opts->use_x0) HIPCHK(hipMemsetAsync(x, 0, 16 * (size_t)n, g.st));
   int iters = 0, outer = 0;
   std::vector<double> rel;
+  bool have_r = false;   // g.r holds f - A x of the final iterate
   if (opts->mode == LS_SOLVE_FP64) {
-    s = gmres<false>(g, f, x, !opts->use_x0, opts->tol, opts->max_iter, &iters, rel);
+    s = gmres<false>(g, f, x, !opts->use_x0, std::vector<double>(nrhs, opts->tol), opts->max_iter, &iters, rel);
     if (s) return s;
   } else {
-    // FP64 residual, FP32 inner solves, x += e
+    // FP64 residual, FP32 inner solves, x += e.  Each inner solve stops at
+    // the looser of inner_tol and half the reduction its right-hand side
+    // still needs to reach tol, so the last correction is no longer than
+    // necessary.
     int total = 0;
     bool xzero = !opts->use_x0;
     for (outer = 0;; ++outer) {
@@ -1385,7 +1390,16 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
       bool all = true;
       for (int k = 0; k < nrhs; ++k)
         if (std::sqrt(dr[k].real()) > opts->tol * std::sqrt(df[k].real())) all = false;
-      if (all || total >= opts->max_iter || outer >= std::max(1, opts->max_outer)) break;
+      if (all || total >= opts->max_iter || outer >= std::max(1, opts->max_outer)) {
+        HIPCHK(hipMemcpyAsync(g.r, g.rout, 16 * (size_t)n, hipMemcpyDeviceToDevice, g.st));
+        have_r = true;
+        break;
+      }
+      std::vector<double> itol(nrhs);
+      for (int k = 0; k < nrhs; ++k) {
+        const double rn = std::sqrt(dr[k].real()), fn = std::sqrt(df[k].real());
+        itol[k] = rn > 0 ? std::min(0.5, std::max(opts->inner_tol, 0.5 * opts->tol * fn / rn)) : opts->inner_tol;
+      }
       // right-hand sides that already meet tol get no further correction, so
       // each one ends exactly where its own solve would
       for (int k = 0; k < nrhs; ++k)
@@ -1394,7 +1408,7 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
       HIPCHK(hipMemsetAsync(g.e, 0, 16 * (size_t)n, g.st));
       int it = 0;
       std::vector<double> rr;
-      s = gmres<true>(g, g.rout, g.e, true, opts->inner_tol, opts->max_iter - total, &it, rr);
+      s = gmres<true>(g, g.rout, g.e, true, itol, opts->max_iter - total, &it, rr);
       if (s) return s;
       total += it;
       HIPCHK(lsx::gm_add(x, g.e, n, g.st));
@@ -1402,10 +1416,12 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
     }
     iters = total;
   }
-  // true FP64 residual
-  s = gm_apply(g, x, g.w, LS_C128);
-  if (s) return s;
-  HIPCHK(lsx::gm_sub(f, g.w, g.r, n, g.st));
+  // true FP64 residual (the refinement loop ends with it in g.r)
+  if (!have_r) {
+    s = gm_apply(g, x, g.w, LS_C128);
+    if (s) return s;
+    HIPCHK(lsx::gm_sub(f, g.w, g.r, n, g.st));
+  }
   std::vector<std::complex<double>> dr, df;
   s = gm_dots_host(g, g.r, g.r, 1, 0, dr);
   if (s) return s;
