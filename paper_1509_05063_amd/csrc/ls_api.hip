@@ -434,10 +434,6 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     if (e != hipSuccess) return cleanup(fail(LS_EDEVICE, std::string("LDS attribute: ") + hipGetErrorString(e)));
   }
   (void)lds_max;
-  {
-    hipError_t e = lsx::set_cell_lds_limits();
-    if (e != hipSuccess) return cleanup(fail(LS_EDEVICE, std::string("LDS attribute: ") + hipGetErrorString(e)));
-  }
 
   lsx::DevView<double>& a = op->d64;
   lsx::DevView<float>& b = op->d32;
@@ -506,7 +502,17 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
           ToffT[((size_t)o * h.U + u2) * h.F + t] = h.Toff[((size_t)o * h.F + t) * h.U + u2];
     UP(upload_c(op, ToffT, &a.Toff, &b.Toff));
   }
-  UP(upload_c(op, h.Wsh, &a.Wsh, &b.Wsh));
+  {
+    // shared window with the adjacent far-field subtraction of each
+    // precision folded in
+    std::vector<cd> w64(h.Wsh), w32(h.Wsh);
+    for (size_t i = 0; i < w64.size(); ++i) {
+      w64[i] += h.Wadj[i];
+      w32[i] += h.Wadj32[i];
+    }
+    UP(upload_c(op, w64, &a.Wsh, nullptr));
+    UP(upload_c(op, w32, nullptr, &b.Wsh));
+  }
   // near-field rows stored padded to a multiple of four entries (zero
   // weights, column offset 0), so a lane can take four at a time
   const size_t nrow = h.rows.size();
@@ -593,6 +599,45 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
       UP(upload_i(op, rpre, &a.run_pre));
     }
   }
+  // adjacent far-field subtraction folded into the stored row weights (both
+  // precisions); the single-precision weights then come back for the tiles
+  std::vector<Fp32c> vals32((size_t)prow[nrow]);
+  {
+    std::vector<int64_t> olen(nrow);
+    for (size_t r = 0; r < nrow; ++r) olen[r] = h.rowptr[r + 1] - h.rowptr[r];
+    std::vector<int32_t> pt_cell((size_t)h.N, -1), pt_idx((size_t)h.N, 0);
+    for (int c = 0; c < h.ncell; ++c) {
+      for (int a2 = 0; a2 < h.S; ++a2) {
+        const int32_t j = h.slot_map[(size_t)c * h.S + a2];
+        if (j >= 0) {
+          pt_cell[j] = c;
+          pt_idx[j] = a2;
+        }
+      }
+      for (int t = 0; t < h.cell_nb[c]; ++t) {
+        const int32_t j = h.cell_start[c] + h.cell_nint[c] + t;
+        pt_cell[j] = c;
+        pt_idx[j] = -(h.cell_boff[c] + t + 1);
+      }
+    }
+    for (int64_t j = 0; j < h.N; ++j)
+      if (pt_cell[(size_t)j] < 0) return cleanup(fail(LS_EINVAL, "a node outside every cell"));
+    void *d_olen = nullptr, *d_cell = nullptr, *d_idx = nullptr;
+    bool ok = hipMalloc(&d_olen, 8 * std::max<size_t>(1, nrow)) == hipSuccess &&
+              hipMalloc(&d_cell, 4 * (size_t)h.N) == hipSuccess && hipMalloc(&d_idx, 4 * (size_t)h.N) == hipSuccess;
+    ok = ok && hipMemcpy(d_olen, olen.data(), 8 * nrow, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(d_cell, pt_cell.data(), 4 * (size_t)h.N, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(d_idx, pt_idx.data(), 4 * (size_t)h.N, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && lsx::launch_fold_rows(a, b, (const int64_t*)d_olen, (const int32_t*)d_cell, (const int32_t*)d_idx,
+                                     0) == hipSuccess;
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
+    ok = ok && (vals32.empty() || hipMemcpy(vals32.data(), b.vals, 8 * vals32.size(), hipMemcpyDeviceToHost) ==
+                                      hipSuccess);
+    if (d_olen) (void)hipFree(d_olen);
+    if (d_cell) (void)hipFree(d_cell);
+    if (d_idx) (void)hipFree(d_idx);
+    if (!ok) return cleanup(fail(LS_EDEVICE, "near-field fold failed"));
+  }
   {
     // Single precision, batched use: the rows as dense tiles of 16 rows of
     // one cell and kind.  A tile's columns are the points of the 3 x 3
@@ -663,8 +708,9 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
             const int kk = in_adj(j) ? pos[cell_of[(size_t)j]] + (j - first(cell_of[(size_t)j]))
                                      : Ka + (int)(std::lower_bound(extra.begin(), extra.end(), j) - extra.begin());
             Fp32c& w = bt_w[(size_t)woff + (size_t)(kk / 4) * 64 + (kk % 4) * 16 + q];
-            w.x += (float)h.vals[k].real();
-            w.y += (float)h.vals[k].imag();
+            const Fp32c& src = vals32[(size_t)(prow[rr] + (k - h.rowptr[rr]))];
+            w.x += src.x;
+            w.y += src.y;
           }
         }
       }

@@ -480,71 +480,35 @@ __global__ void k_spectral(typename C2<T>::t* __restrict__ lat, const typename C
 }
 
 // ---------------------------------------------------------------------------
-// a3 + a5: per cell, face values of the lattice field minus the adjacent
-// cells' equivalent-source fields, Dirichlet fit to the cell's nodes,
-// v = u + kappa^2 far.
+// a3 + a5: per cell, the face values of the lattice field, Dirichlet fit
+// to the cell's nodes, v = u + kappa^2 far.  The adjacent cells' part of
+// the field (their equivalent sources seen at the faces) is subtracted
+// through the near-field weights, where it was folded in at set-up.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restrict__ u,
                                                 typename C2<T>::t* __restrict__ v,
                                                 const typename C2<T>::t* __restrict__ lat,
-                                                const typename C2<T>::t* __restrict__ sigma,
-                                                const typename C2<T>::t* __restrict__ ToffT,
                                                 const typename C2<T>::t* __restrict__ IshT,
                                                 const typename C2<T>::t* __restrict__ Ibd,
                                                 const int32_t* __restrict__ cell_xy,
-                                                const int32_t* __restrict__ cell_map,
                                                 const int32_t* __restrict__ slot_map,
                                                 const int32_t* __restrict__ cell_start,
                                                 const int32_t* __restrict__ cell_nint,
                                                 const int32_t* __restrict__ cell_nb,
-                                                const int32_t* __restrict__ cell_boff, int L, int q, int U,
-                                                int F, int S, int ncell, int Pa, int Pb, int64_t N, T k2) {
-  // ToffT [9][U][F] (transposed adjacency fields), IshT [F][S]
+                                                const int32_t* __restrict__ cell_boff, int q, int F, int S,
+                                                int Pa, int Pb, int64_t N, T k2) {
+  // IshT [F][S]
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
   V* f = reinterpret_cast<V*>(smem_raw);      // F face values
-  V* sg = f + F;                              // 9 * U neighbour strengths
-  V* part = sg + 9 * U;                       // 9 * F partial adjacent fields
-  int* nbr = reinterpret_cast<int*>(part + 9 * F);
   const int c = blockIdx.x, r = blockIdx.y;
   const int cx = cell_xy[2 * c], cy = cell_xy[2 * c + 1];
   const int64_t plane = (int64_t)Pa * Pb;
-  if (threadIdx.x < 9) {
-    int ox = threadIdx.x % 3 - 1, oy = threadIdx.x / 3 - 1;
-    int nx = cx + ox, ny = cy + oy;
-    nbr[threadIdx.x] = (nx >= 0 && ny >= 0 && nx < L && ny < L) ? cell_map[ny * L + nx] : -1;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 9 * U; i += blockDim.x) {
-    int o = i / U;
-    int cn = nbr[o];
-    sg[i] = cn >= 0 ? sigma[((int64_t)r * ncell + cn) * U + (i % U)] : czero<V>();
-  }
   for (int t = threadIdx.x; t < F; t += blockDim.x) {
     int s = t / (2 * q), fj = t % (2 * q), fc = fj / q, j = fj % q;
     int cn = (s == 0 ? cx : cy) + fc, ct = (s == 0 ? cy : cx);
     f[t] = lat[((int64_t)(r * 2 + s) * 2) * plane + (int64_t)cn * Pb + ct * q + j];
-  }
-  __syncthreads();
-  // adjacent equivalent-source fields at the face nodes (same set only):
-  // part[o][t] = sum_k ToffT[o][s 4q + k][t] sg[o][s 4q + k]
-  for (int i = threadIdx.x; i < 9 * F; i += blockDim.x) {
-    int o = i / F, t = i % F;
-    V acc = czero<V>();
-    if (nbr[o] >= 0) {
-      int s = t / (2 * q);
-      const V* Tcol = ToffT + ((int64_t)o * U + s * 4 * q) * F + t;
-      const V* sv = sg + o * U + s * 4 * q;
-      for (int k = 0; k < 4 * q; ++k) acc = cfma(Tcol[(int64_t)k * F], sv[k], acc);
-    }
-    part[i] = acc;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < F; t += blockDim.x) {
-    V acc = f[t];
-    for (int o = 0; o < 9; ++o) acc = csub(acc, part[o * F + t]);
-    f[t] = acc;
   }
   __syncthreads();
   const V* ur = u + (int64_t)r * N;
@@ -569,46 +533,33 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
 }
 
 // Interpolation for 16 consecutive cells per workgroup (q = 12: F = 48 face
-// values, U = 96 sources, S = 64 slots) on the matrix cores.  For each of the
-// 9 neighbour offsets, the same-set blocks of its adjacency matrix (2 sets x
-// 48 sources x 24 faces) and the 16 neighbours' strengths are staged in LDS;
-// wave w contracts set w/2, faces 16(w%2)..16(w%2)+15 (rows past 24 are
-// zero) against the 16 cells: C[face][cell] = sum_k T[k][face] sigma[cell][k],
-// complex products as four real MFMA 16x16x4 updates, summed over the 9
-// offsets in the accumulators.  The corrected face values are then fitted to
-// the slots as a second contraction (IshT [F][S] times the 16 cells' face
-// values; wave w takes slots 16w..16w+15), and to the band nodes one row per
-// thread.
+// values, S = 64 slots) on the matrix cores: the cells' face values are
+// staged in LDS and fitted to the slots as one contraction (IshT [F][S]
+// times the 16 cells' face values, complex products as four real MFMA
+// 16x16x4 updates; wave w takes slots 16w..16w+15), and to the band nodes
+// one row per thread.  The adjacent cells' part of the lattice field is
+// removed by the near-field weights (folded in at set-up), not here.
 template <typename T, int CB>
 __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __restrict__ u,
                                                      typename C2<T>::t* __restrict__ v,
                                                      const typename C2<T>::t* __restrict__ lat,
-                                                     const typename C2<T>::t* __restrict__ sigma,
-                                                     const typename C2<T>::t* __restrict__ ToffT,
                                                      const typename C2<T>::t* __restrict__ IshT,
                                                      const typename C2<T>::t* __restrict__ Ibd,
                                                      const int32_t* __restrict__ cell_xy,
-                                                     const int32_t* __restrict__ cell_map,
                                                      const int32_t* __restrict__ slot_map,
                                                      const int32_t* __restrict__ cell_start,
                                                      const int32_t* __restrict__ cell_nint,
                                                      const int32_t* __restrict__ cell_nb,
-                                                     const int32_t* __restrict__ cell_boff, int L, int ncell, int Pa,
-                                                     int Pb, int64_t N, T k2) {
+                                                     const int32_t* __restrict__ cell_boff, int ncell, int Pa, int Pb,
+                                                     int64_t N, T k2) {
   using V = typename C2<T>::t;
   using M = Mfma<T>;
   using v4 = typename M::v4;
-  constexpr int q = 12, F = 4 * q, U = 8 * q, S = 64, KS = 4 * q, TS = 2 * q;   // KS sources, TS faces per set
+  constexpr int q = 12, F = 4 * q, S = 64;
   static_assert(CB == 16, "one MFMA column per cell");
   extern __shared__ unsigned char smem_raw[];
-  // LDS: face values, then two buffers (offsets alternate) of the neighbours'
-  // strengths and the same-set adjacency blocks
-  V* fv = reinterpret_cast<V*>(smem_raw);    // [CB][F] face values
-  V* sgb = fv + CB * F;                      // [2][CB][U] strengths of the neighbour at the offset
-  V* Tob = sgb + 2 * CB * U;                 // [2][2][KS][TS] same-set adjacency blocks of the offset
-  int* cinfo = reinterpret_cast<int*>(Tob + 2 * 2 * KS * TS);   // [CB][2] cell x, y (-1: past the end)
-  constexpr int SPT = CB * U / 256, TPT = 2 * KS * TS / 256;    // staged values per thread
-  static_assert(CB * U % 256 == 0 && 2 * KS * TS % 256 == 0, "staging split over 256 threads");
+  V* fv = reinterpret_cast<V*>(smem_raw);                    // [CB][F] face values
+  int* cinfo = reinterpret_cast<int*>(fv + CB * F);          // [CB][2] cell x, y (-1: past the end)
   const int c0 = blockIdx.x * CB, r = blockIdx.y, tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
   const int64_t plane = (int64_t)Pa * Pb;
@@ -628,67 +579,6 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
       val = lat[((int64_t)(r * 2 + s2) * 2) * plane + (int64_t)cn * Pb + ct * q + j];
     }
     fv[i] = val;
-  }
-  const int ws = wave >> 1, mt = wave & 1;   // this wave's set and face tile
-  const int arow = 16 * mt + col;            // face row of the A operand
-  V sreg[SPT], treg[TPT];
-  auto gload = [&](int o) {
-    const int ox = o % 3 - 1, oy = o / 3 - 1;
-#pragma unroll
-    for (int qq = 0; qq < SPT; ++qq) {
-      const int i = tid + 256 * qq, cb = i / U, k = i % U;
-      const int cx = cinfo[2 * cb], cy = cinfo[2 * cb + 1];
-      int cn = -1;
-      if (cx >= 0) {
-        const int nx = cx + ox, ny = cy + oy;
-        cn = (nx >= 0 && ny >= 0 && nx < L && ny < L) ? cell_map[ny * L + nx] : -1;
-      }
-      sreg[qq] = cn >= 0 ? sigma[((int64_t)r * ncell + cn) * U + k] : czero<V>();
-    }
-#pragma unroll
-    for (int qq = 0; qq < TPT; ++qq) {
-      const int i = tid + 256 * qq;
-      const int s2 = i / (KS * TS), k = (i / TS) % KS, tt = i % TS;
-      treg[qq] = ToffT[((int64_t)o * U + s2 * KS + k) * F + s2 * TS + tt];
-    }
-  };
-  auto sstore = [&](int b) {
-#pragma unroll
-    for (int qq = 0; qq < SPT; ++qq) sgb[b * CB * U + tid + 256 * qq] = sreg[qq];
-#pragma unroll
-    for (int qq = 0; qq < TPT; ++qq) Tob[b * 2 * KS * TS + tid + 256 * qq] = treg[qq];
-  };
-  v4 cre = v4{0, 0, 0, 0}, cim = v4{0, 0, 0, 0};
-  __syncthreads();
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int o = 0; o < 9; ++o) {
-    const int buf = o & 1;
-    const V* sg = sgb + buf * CB * U;
-    const V* To = Tob + buf * 2 * KS * TS;
-    if (o + 1 < 9) gload(o + 1);
-#pragma unroll 4
-    for (int kk = 0; kk < KS / 4; ++kk) {
-      const int k = 4 * kk + kl;
-      const V a = arow < TS ? To[(ws * KS + k) * TS + arow] : czero<V>();
-      const V b = sg[col * U + ws * KS + k];
-      cre = M::op(a.x, b.x, cre);
-      cre = M::op(-a.y, b.y, cre);
-      cim = M::op(a.x, b.y, cim);
-      cim = M::op(a.y, b.x, cim);
-    }
-    if (o + 1 < 9) sstore(buf ^ 1);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int tp = 16 * mt + M::row(lane, rr);
-    if (tp < TS) {
-      V& x = fv[col * F + ws * TS + tp];
-      x.x -= cre[rr];
-      x.y -= cim[rr];
-    }
   }
   __syncthreads();
   const V* ur = u + (int64_t)r * N;
@@ -1163,6 +1053,86 @@ __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u
       }
     }
   }
+}
+
+// Set-up: folds the adjacent far-field subtraction into the rows touching
+// the boundary patch.  The far field at target i of cell c leaves out the
+// equivalent sources of the 3 x 3 adjacent cells, i.e. it carries
+// -I_i T_off P_j c_j u_j for every source j of the adjacent cell c + off
+// (P_j: j's projection column, I_i: i's fit row).  The rows of boundary-patch
+// targets hold every point of those cells, the rows of interior targets
+// every boundary-patch point, so the term is added to the stored weights
+// (once per precision, with that precision's projection; the far-field
+// stage then skips it).  One workgroup per row: g_off = I_i T_off for the 9
+// offsets in LDS, then one dot of length U per entry.
+__global__ void __launch_bounds__(256) k_fold_rows(const int64_t* __restrict__ rowptr,
+                                                   const int64_t* __restrict__ olen,
+                                                   const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ colbase,
+                                                   const uint16_t* __restrict__ coloff,
+                                                   const int32_t* __restrict__ cols32,
+                                                   const int32_t* __restrict__ pt_cell,
+                                                   const int32_t* __restrict__ pt_idx,
+                                                   const int32_t* __restrict__ cell_xy,
+                                                   const double2* __restrict__ IshT, const double2* __restrict__ Ibd,
+                                                   const double2* __restrict__ ToffT,
+                                                   const double2* __restrict__ PshT64,
+                                                   const float2* __restrict__ PshT32,
+                                                   const double2* __restrict__ Pbd64,
+                                                   const float2* __restrict__ Pbd32, const double* __restrict__ cw,
+                                                   double2* __restrict__ vals64, float2* __restrict__ vals32,
+                                                   int F, int U, int S) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* I = reinterpret_cast<double2*>(smem_raw);   // [F]
+  double2* g = I + F;                                  // [9][U]
+  const int r = blockIdx.x;
+  const int i = rows[r], c = pt_cell[i], idx = pt_idx[i];
+  const bool tb = idx < 0;
+  const int cx = cell_xy[2 * c], cy = cell_xy[2 * c + 1];
+  for (int t = threadIdx.x; t < F; t += blockDim.x)
+    I[t] = tb ? Ibd[(int64_t)(-idx - 1) * F + t] : IshT[(int64_t)t * S + idx];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 9 * U; e += blockDim.x) {
+    const double2* Tr = ToffT + (int64_t)e * F;   // [o][u][t]
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = 0; t < F; ++t) acc = cfma(I[t], Tr[t], acc);
+    g[e] = acc;
+  }
+  __syncthreads();
+  const int64_t b0 = rowptr[r], len = olen[r];
+  for (int64_t k = threadIdx.x; k < len; k += blockDim.x) {
+    const int32_t j = colbase[r] + (coloff ? (int32_t)coloff[b0 + k] : cols32[b0 + k]);
+    const int cj = pt_cell[j];
+    const int dx = cell_xy[2 * cj] - cx, dy = cell_xy[2 * cj + 1] - cy;
+    if (dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;
+    const int jdx = pt_idx[j];
+    const bool jb = jdx < 0;
+    if (!tb && !jb) continue;      // interior to interior: in the shared window
+    const double2* go = g + ((dy + 1) * 3 + dx + 1) * U;
+    const double2* p64 = jb ? Pbd64 + (int64_t)(-jdx - 1) * U : PshT64 + (int64_t)jdx * U;
+    const float2* p32 = jb ? Pbd32 + (int64_t)(-jdx - 1) * U : PshT32 + (int64_t)jdx * U;
+    double2 a64 = make_double2(0.0, 0.0), a32 = make_double2(0.0, 0.0);
+    for (int u2 = 0; u2 < U; ++u2) {
+      a64 = cfma(go[u2], p64[u2], a64);
+      const float2 pf = p32[u2];
+      a32 = cfma(go[u2], make_double2(pf.x, pf.y), a32);
+    }
+    const double w = cw[j];
+    const double2 base = vals64[b0 + k];
+    vals32[b0 + k] = make_float2((float)(base.x - w * a32.x), (float)(base.y - w * a32.y));
+    vals64[b0 + k] = make_double2(base.x - w * a64.x, base.y - w * a64.y);
+  }
+}
+
+hipError_t launch_fold_rows(const DevView<double>& a, const DevView<float>& b, const int64_t* olen,
+                            const int32_t* pt_cell, const int32_t* pt_idx, hipStream_t st) {
+  if (a.nrows == 0) return hipSuccess;
+  const size_t sh = (size_t)(a.F + 9 * a.U) * sizeof(double2);
+  hipLaunchKernelGGL(k_fold_rows, dim3(a.nrows), dim3(256), sh, st, a.rowptr, olen, a.rows, a.colbase, a.coloff,
+                     a.cols32, pt_cell, pt_idx, a.cell_xy, (const double2*)a.Ish, (const double2*)a.Ibd,
+                     (const double2*)a.Toff, (const double2*)a.PshT, (const float2*)b.PshT, (const double2*)a.Pbd,
+                     (const float2*)b.Pbd, a.cw, (double2*)a.vals, (float2*)b.vals, a.F, a.U, a.S);
+  return hipGetLastError();
 }
 
 // Right-hand-side-major copy for the batched row kernel: ut[i * R + r] = u[r * N + i]
@@ -1870,19 +1840,16 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   if (lattice_only) return hipGetLastError();   // the caller evaluates the field itself
   // a3 + a5
   {
-    size_t sh = (size_t)(d.F + 9 * d.U + 9 * d.F) * sizeof(V) + 16 * sizeof(int);
     if (d.q == 12 && d.S == 64) {
       constexpr int CB = 16;
-      const size_t shm = (size_t)(CB * 48 + 2 * CB * 96 + 2 * 2 * 48 * 24) * sizeof(V) + 2 * CB * sizeof(int);
+      const size_t shm = (size_t)CB * 48 * sizeof(V) + 2 * CB * sizeof(int);
       hipLaunchKernelGGL((k_interp_mfma<T, CB>), dim3((d.ncell + CB - 1) / CB, nrhs), dim3(256), shm, st, u, v,
-                         (const V*)lat, (const V*)sigma, (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd,
-                         d.cell_xy, d.cell_map, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L,
-                         d.ncell, d.Pa, d.Pb, d.N, k2);
+                         (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
+                         d.cell_nint, d.cell_nb, d.cell_boff, d.ncell, d.Pa, d.Pb, d.N, k2);
     } else {
-      hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), sh, st, u, v, (const V*)lat,
-                         (const V*)sigma, (const V*)d.Toff, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.cell_map,
-                         d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.L, d.q, d.U, d.F, d.S,
-                         d.ncell, d.Pa, d.Pb, d.N, k2);
+      hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), (size_t)d.F * sizeof(V), st, u, v,
+                         (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
+                         d.cell_nint, d.cell_nb, d.cell_boff, d.q, d.F, d.S, d.Pa, d.Pb, d.N, k2);
     }
   }
   mark(6);
@@ -1983,17 +1950,6 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_cols_conv<double>);
   set((const void*)k_fft_cols_conv<float>);
   return e;
-}
-
-hipError_t set_cell_lds_limits() {
-  // the 16-cell interpolation kernel with double-buffered staging needs
-  // 68 KB (single) / 135 KB (double precision), past the 64 KB default
-  const int base = 16 * 48 + 2 * 16 * 96 + 2 * 2 * 48 * 24;
-  hipError_t e = hipFuncSetAttribute((const void*)k_interp_mfma<double, 16>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, base * 16 + 2 * 16 * 4);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_interp_mfma<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             base * 8 + 2 * 16 * 4);
 }
 
 hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st) {

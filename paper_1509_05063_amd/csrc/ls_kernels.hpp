@@ -82,8 +82,13 @@ struct TargetView {
 hipError_t launch_targets(const DevView<double>& d, const TargetView& tg, const void* u, void* out, int nrhs,
                           void* ws, hipStream_t st);
 hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int nbatch, hipStream_t st);
+// Set-up: adds the adjacent far-field subtraction to the stored weights of
+// the rows touching the boundary patch, both precisions (olen: entries per
+// row before padding; pt_cell: cell of each point; pt_idx: slot of an
+// interior point, -(boundary ordinal + 1) of a boundary-patch point).
+hipError_t launch_fold_rows(const DevView<double>& a, const DevView<float>& b, const int64_t* olen,
+                            const int32_t* pt_cell, const int32_t* pt_idx, hipStream_t st);
 hipError_t set_fft_lds_limits(size_t bytes);
-hipError_t set_cell_lds_limits();
 
 // GMRES building blocks (double complex)
 hipError_t gm_dots(const void* Vb, const void* w, void* partial, void* out, int nvec, int64_t N, int nrhs,

@@ -521,7 +521,13 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
         int64_t j0 = op.cell_start[c], j1e = j0 + op.cell_nint[c] + op.cell_nb[c];
         int64_t jb = tb ? j0 : j0 + op.cell_nint[c];      // interior targets: boundary sources only
         for (int64_t j = jb; j < j1e; ++j) {
-          if (j == i) continue;
+          // every adjacent source gets an entry (zero where the plain rule
+          // gives none): the adjacent equivalent-source fields are folded
+          // into these rows after the projections are known
+          if (j == i) {
+            ent.emplace_back((int32_t)j, cd(0.0, 0.0));
+            continue;
+          }
           double eta;
           if (op.key[3 * j] == 0) {
             double d = std::hypot(op.xy[2 * j] - xi[0], op.xy[2 * j + 1] - xi[1]);
@@ -530,7 +536,10 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
             eta = in_band[i] ? eta_band(tv[i], tu[i], tv[j], tu[j]) : 0.0;
           }
           double f = 1.0 - eta;
-          if (f == 0.0) continue;
+          if (f == 0.0) {
+            ent.emplace_back((int32_t)j, cd(0.0, 0.0));
+            continue;
+          }
           double d = std::hypot(op.xy[2 * j] - xi[0], op.xy[2 * j + 1] - xi[1]);
           ent.emplace_back((int32_t)j, f * green2d(kappa, d) * op.cw[j]);
         }
@@ -726,6 +735,39 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
               }
           }
     }
+  // The far field at a cell's targets leaves out its 3 x 3 adjacent cells'
+  // equivalent sources: -I T_off P applied to those cells' weighted
+  // densities c u.  For interior slot sources seen from interior slot
+  // targets this is the same for every cell, a window term like Wsh (in
+  // terms of psi = m omega u: c = h^2 psi there), once per precision with
+  // that precision's projection.  Rows touching the boundary patch take it
+  // on the device (ls_create).
+  {
+    const int Wn = op.Wn;
+    for (int prec = 0; prec < 2; ++prec) {
+      const std::vector<cd>& Ps = prec == 0 ? op.Psh : op.Psh32;
+      std::vector<cd>& Wt = prec == 0 ? op.Wadj : op.Wadj32;
+      Wt.assign((size_t)S * Wn * Wn, 0.0);
+      std::vector<cd> TP((size_t)F * S);
+      for (int o = 0; o < 9; ++o) {
+        const int ox = o % 3 - 1, oy = o / 3 - 1;
+        std::fill(TP.begin(), TP.end(), cd(0.0, 0.0));
+        for (int t = 0; t < F; ++t)
+          for (int u2 = 0; u2 < U; ++u2) {
+            const cd tv2 = op.Toff[((size_t)o * F + t) * U + u2];
+            if (tv2 == 0.0) continue;
+            for (int s2 = 0; s2 < S; ++s2) TP[(size_t)t * S + s2] += tv2 * Ps[(size_t)u2 * S + s2];
+          }
+        for (int a = 0; a < S; ++a)
+          for (int s2 = 0; s2 < S; ++s2) {
+            cd acc = 0.0;
+            for (int t = 0; t < F; ++t) acc += op.Ish[(size_t)a * F + t] * TP[(size_t)t * S + s2];
+            const int wx = (ox + 2) * ch + s2 % ch, wy = (oy + 2) * ch + s2 / ch;
+            Wt[(size_t)a * Wn * Wn + (size_t)wy * Wn + wx] -= h * h * acc;
+          }
+      }
+    }
+  }
   // Green's function on the face lattices, zero padded for linear
   // convolution: set s, normal offset da (units H), tangential db (H/q)
   op.na = L + 1;

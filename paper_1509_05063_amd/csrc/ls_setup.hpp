@@ -58,6 +58,8 @@ struct HostOp {
   // ---- near field ----------------------------------------------------------
   int Wn = 0;                   // window side in lattice nodes (5 cell_h)
   std::vector<cd> Wsh;          // [S][Wn*Wn]
+  std::vector<cd> Wadj, Wadj32; // [S][Wn*Wn] adjacent far-field subtraction
+                                // (double / single precision projection)
   std::vector<int64_t> rowptr;  // CSR over `rows`
   std::vector<int32_t> rows, cols;
   std::vector<cd> vals;
