@@ -493,7 +493,15 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
       for (int t = 0; t < h.F; ++t) IshT[(size_t)t * h.S + a2] = h.Ish[(size_t)a2 * h.F + t];
     UP(upload_c(op, IshT, &a.Ish, &b.Ish));
   }
-  UP(upload_c(op, h.Ibd, &a.Ibd, &b.Ibd));
+  {
+    // band fit rows transposed to [F][n_band] (lanes of the interpolation
+    // kernel take consecutive nodes)
+    std::vector<cd> IbdT((size_t)h.F * h.n_band);
+    for (int64_t bb = 0; bb < h.n_band; ++bb)
+      for (int t = 0; t < h.F; ++t) IbdT[(size_t)t * h.n_band + bb] = h.Ibd[(size_t)bb * h.F + t];
+    UP(upload_c(op, IbdT, &a.Ibd, &b.Ibd));
+    a.nband = b.nband = h.n_band;
+  }
   {
     std::vector<cd> ToffT((size_t)9 * h.U * h.F);
     for (int o = 0; o < 9; ++o)

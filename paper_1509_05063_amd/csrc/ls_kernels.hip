@@ -497,8 +497,8 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
                                                 const int32_t* __restrict__ cell_nint,
                                                 const int32_t* __restrict__ cell_nb,
                                                 const int32_t* __restrict__ cell_boff, int q, int F, int S,
-                                                int Pa, int Pb, int64_t N, T k2) {
-  // IshT [F][S]
+                                                int Pa, int Pb, int64_t N, int64_t nband, T k2) {
+  // IshT [F][S], IbdT [F][nband]
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
   V* f = reinterpret_cast<V*>(smem_raw);      // F face values
@@ -525,8 +525,8 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
   const int b0 = cell_start[c] + nint;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     V acc = czero<V>();
-    const V* irow = Ibd + (boff + b) * F;
-    for (int t = 0; t < F; ++t) acc = cfma(irow[t], f[t], acc);
+    const V* icol = Ibd + boff + b;
+    for (int t = 0; t < F; ++t) acc = cfma(icol[t * nband], f[t], acc);
     int64_t j = b0 + b;
     vr[j] = cadd(ur[j], cscale(acc, k2));
   }
@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
 // staged in LDS and fitted to the slots as one contraction (IshT [F][S]
 // times the 16 cells' face values, complex products as four real MFMA
 // 16x16x4 updates; wave w takes slots 16w..16w+15), and to the band nodes
-// one row per thread.  The adjacent cells' part of the lattice field is
+// one row per thread (IbdT [F][nband]).  The adjacent cells' part of the lattice field is
 // removed by the near-field weights (folded in at set-up), not here.
 template <typename T, int CB>
 __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __restrict__ u,
@@ -551,7 +551,7 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
                                                      const int32_t* __restrict__ cell_nint,
                                                      const int32_t* __restrict__ cell_nb,
                                                      const int32_t* __restrict__ cell_boff, int ncell, int Pa, int Pb,
-                                                     int64_t N, T k2) {
+                                                     int64_t N, int64_t nband, T k2) {
   using V = typename C2<T>::t;
   using M = Mfma<T>;
   using v4 = typename M::v4;
@@ -616,10 +616,10 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
     int cb = 0;
     while (c0 + cb + 1 <= cl && cell_boff[c0 + cb + 1] <= ib) ++cb;
     const int c = c0 + cb;
-    const V* irow = Ibd + ib * F;
+    const V* icol = Ibd + ib;     // IbdT [F][nband]: lanes read consecutive words
     V s1 = czero<V>();
 #pragma unroll 8
-    for (int t = 0; t < F; ++t) s1 = cfma(irow[t], fv[cb * F + t], s1);
+    for (int t = 0; t < F; ++t) s1 = cfma(icol[t * nband], fv[cb * F + t], s1);
     const int64_t j = cell_start[c] + cell_nint[c] + (ib - cell_boff[c]);
     vr[j] = cadd(ur[j], cscale(s1, k2));
   }
@@ -1074,14 +1074,14 @@ __global__ void __launch_bounds__(256) k_fold_rows(const int64_t* __restrict__ r
                                                    const int32_t* __restrict__ pt_cell,
                                                    const int32_t* __restrict__ pt_idx,
                                                    const int32_t* __restrict__ cell_xy,
-                                                   const double2* __restrict__ IshT, const double2* __restrict__ Ibd,
+                                                   const double2* __restrict__ IshT, const double2* __restrict__ IbdT,
                                                    const double2* __restrict__ ToffT,
                                                    const double2* __restrict__ PshT64,
                                                    const float2* __restrict__ PshT32,
                                                    const double2* __restrict__ Pbd64,
                                                    const float2* __restrict__ Pbd32, const double* __restrict__ cw,
                                                    double2* __restrict__ vals64, float2* __restrict__ vals32,
-                                                   int F, int U, int S) {
+                                                   int F, int U, int S, int64_t nband) {
   extern __shared__ unsigned char smem_raw[];
   double2* I = reinterpret_cast<double2*>(smem_raw);   // [F]
   double2* g = I + F;                                  // [9][U]
@@ -1090,7 +1090,7 @@ __global__ void __launch_bounds__(256) k_fold_rows(const int64_t* __restrict__ r
   const bool tb = idx < 0;
   const int cx = cell_xy[2 * c], cy = cell_xy[2 * c + 1];
   for (int t = threadIdx.x; t < F; t += blockDim.x)
-    I[t] = tb ? Ibd[(int64_t)(-idx - 1) * F + t] : IshT[(int64_t)t * S + idx];
+    I[t] = tb ? IbdT[(int64_t)t * nband + (-idx - 1)] : IshT[(int64_t)t * S + idx];
   __syncthreads();
   for (int e = threadIdx.x; e < 9 * U; e += blockDim.x) {
     const double2* Tr = ToffT + (int64_t)e * F;   // [o][u][t]
@@ -1131,7 +1131,7 @@ hipError_t launch_fold_rows(const DevView<double>& a, const DevView<float>& b, c
   hipLaunchKernelGGL(k_fold_rows, dim3(a.nrows), dim3(256), sh, st, a.rowptr, olen, a.rows, a.colbase, a.coloff,
                      a.cols32, pt_cell, pt_idx, a.cell_xy, (const double2*)a.Ish, (const double2*)a.Ibd,
                      (const double2*)a.Toff, (const double2*)a.PshT, (const float2*)b.PshT, (const double2*)a.Pbd,
-                     (const float2*)b.Pbd, a.cw, (double2*)a.vals, (float2*)b.vals, a.F, a.U, a.S);
+                     (const float2*)b.Pbd, a.cw, (double2*)a.vals, (float2*)b.vals, a.F, a.U, a.S, a.nband);
   return hipGetLastError();
 }
 
@@ -1878,11 +1878,11 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       const size_t shm = (size_t)CB * 48 * sizeof(V) + 2 * CB * sizeof(int);
       hipLaunchKernelGGL((k_interp_mfma<T, CB>), dim3((d.ncell + CB - 1) / CB, nrhs), dim3(256), shm, st, u, v,
                          (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
-                         d.cell_nint, d.cell_nb, d.cell_boff, d.ncell, d.Pa, d.Pb, d.N, k2);
+                         d.cell_nint, d.cell_nb, d.cell_boff, d.ncell, d.Pa, d.Pb, d.N, d.nband, k2);
     } else {
       hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), (size_t)d.F * sizeof(V), st, u, v,
                          (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
-                         d.cell_nint, d.cell_nb, d.cell_boff, d.q, d.F, d.S, d.Pa, d.Pb, d.N, k2);
+                         d.cell_nint, d.cell_nb, d.cell_boff, d.q, d.F, d.S, d.Pa, d.Pb, d.N, d.nband, k2);
     }
   }
   mark(6);

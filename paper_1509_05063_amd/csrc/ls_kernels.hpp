@@ -18,6 +18,7 @@ struct DevView {
   int64_t N = 0;
   int ncell = 0, nicell = 0, S = 0, U = 0, F = 0, q = 0, L = 0, na = 0, nb = 0, Pa = 0, Pb = 0, ch = 0;
   int max_nb = 0, tc = 1, nrows = 0;
+  int64_t nband = 0;   // boundary-patch nodes (Ibd is stored as [F][nband])
   // kernel variants chosen by ls_autotune: near_variant 0 = double-buffered
   // interior contraction, 16 cells per workgroup (single precision), 1 =
   // single-buffered, 2 / 3 = double-buffered with 32 / 64 cells; csr_variant
