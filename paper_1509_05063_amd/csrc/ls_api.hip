@@ -936,8 +936,24 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   }
   d.tc = best_tc;
   d.fft_variant = best_fv;
+  // threads per row transform (a few hundred rows of a few thousand points:
+  // more threads per row keep more waves resident)
+  int best_nth = d.rows_nth;
+  for (int nth : {256, 512, 1024}) {
+    d.rows_nth = nth;
+    double t;
+    ls_status s = measure(2, 4, &t);
+    if (s) return s;
+    log("fft row threads", nth, 0, t);
+    if (t < best) {
+      best = t;
+      best_nth = nth;
+    }
+  }
+  d.rows_nth = best_nth;
   res->fft_col_tile = best_tc;
   res->fft_variant = best_fv;
+  res->fft_row_threads = best_nth;
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
   const int nnear = std::is_same<T, float>::value ? 4 : 1;

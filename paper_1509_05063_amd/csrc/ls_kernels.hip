@@ -372,8 +372,8 @@ __device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, 
 // transforms along the contiguous axis: one line per workgroup
 // (entries past nload are zero padding: not read; entries past nstore are
 // not needed downstream: not written)
-template <typename T, int DIR>
-__global__ void __launch_bounds__(256) k_fft_rows(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
+template <typename T, int DIR, int NTH>
+__global__ void __launch_bounds__(NTH) k_fft_rows(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
                                                   FftPlan plan, int64_t line_stride, int nload, int nstore,
                                                   int64_t batch_stride) {
   using V = typename C2<T>::t;
@@ -1839,7 +1839,9 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   {
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     // rows a >= na are zero padding: their transforms stay zero
-    hipLaunchKernelGGL((k_fft_rows<T, 1>), dim3(d.na, nbatch), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
+    auto rows_f = d.rows_nth == 1024 ? k_fft_rows<T, 1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, 1, 512>
+                                                                                   : k_fft_rows<T, 1, 256>;
+    hipLaunchKernelGGL(rows_f, dim3(d.na, nbatch), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
                        (int64_t)d.Pb, d.nb, d.Pb, plane);
     int TC = TCP;
     if (d.fft_variant == 1) {
@@ -1866,7 +1868,9 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
                          (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na);
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
-    hipLaunchKernelGGL((k_fft_rows<T, -1>), dim3(d.na, nrhs * 2), dim3(256), sh, st, lat, (const V*)d.twb, d.pb,
+    auto rows_i = d.rows_nth == 1024 ? k_fft_rows<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, -1, 512>
+                                                                                    : k_fft_rows<T, -1, 256>;
+    hipLaunchKernelGGL(rows_i, dim3(d.na, nrhs * 2), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
                        (int64_t)d.Pb, d.Pb, d.nb, 2 * plane);
   }
   mark(5);
@@ -1972,12 +1976,20 @@ hipError_t set_fft_lds_limits(size_t bytes) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (r != hipSuccess) e = r;
   };
-  set((const void*)k_fft_rows<double, 1>);
-  set((const void*)k_fft_rows<double, -1>);
+  set((const void*)k_fft_rows<double, 1, 256>);
+  set((const void*)k_fft_rows<double, -1, 256>);
+  set((const void*)k_fft_rows<double, 1, 512>);
+  set((const void*)k_fft_rows<double, -1, 512>);
+  set((const void*)k_fft_rows<double, 1, 1024>);
+  set((const void*)k_fft_rows<double, -1, 1024>);
+  set((const void*)k_fft_rows<float, 1, 512>);
+  set((const void*)k_fft_rows<float, -1, 512>);
+  set((const void*)k_fft_rows<float, 1, 1024>);
+  set((const void*)k_fft_rows<float, -1, 1024>);
   set((const void*)k_fft_cols<double, 1>);
   set((const void*)k_fft_cols<double, -1>);
-  set((const void*)k_fft_rows<float, 1>);
-  set((const void*)k_fft_rows<float, -1>);
+  set((const void*)k_fft_rows<float, 1, 256>);
+  set((const void*)k_fft_rows<float, -1, 256>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
   set((const void*)k_fft_cols_conv<double>);
@@ -1989,7 +2001,7 @@ hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int 
   using V = double2;
   const int64_t plane = (int64_t)d.Pa * d.Pb;
   size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
-  hipLaunchKernelGGL((k_fft_rows<double, 1>), dim3(d.Pa, nbatch), dim3(256), sh, st, (V*)data, (const V*)d.twb,
+  hipLaunchKernelGGL((k_fft_rows<double, 1, 256>), dim3(d.Pa, nbatch), dim3(256), sh, st, (V*)data, (const V*)d.twb,
                      d.pb, (int64_t)d.Pb, d.Pb, d.Pb, plane);
   int TC = d.tc;
   size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);

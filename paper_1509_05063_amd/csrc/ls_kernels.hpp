@@ -30,6 +30,7 @@ struct DevView {
   // fft_variant 0 = separate column transforms and spectral product, 1 =
   // fused per column tile
   int fft_variant = 0;
+  int rows_nth = 256;   // threads per workgroup of the row transforms (256, 512, 1024)
   bool csr_f64 = true;
   double kappa = 0;
   const void *Psh = nullptr, *PshT = nullptr, *Pbd = nullptr, *Ish = nullptr, *Ibd = nullptr, *Toff = nullptr, *Wsh = nullptr;
