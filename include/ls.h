@@ -171,6 +171,7 @@ typedef struct {
                            of 16 right-hand sides) */
   int fft_variant;      /* 0 separate column transforms and spectral product, 1 fused per column tile */
   int fft_row_threads;  /* threads per workgroup of the row transforms (256, 512 or 1024) */
+  int fft_col_threads;  /* threads per workgroup of the fused column kernel (256 or 512) */
   double fft_ms;        /* best time of the transform stages with the chosen tile */
   double near_ms;       /* best time of the interior contraction stage */
   double csr_ms;        /* best time of the boundary-patch rows stage */

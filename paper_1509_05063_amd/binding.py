@@ -63,7 +63,7 @@ class ServerInfo(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("fft_col_tile", C.c_int), ("near_variant", C.c_int), ("csr_variant", C.c_int),
-                ("fft_variant", C.c_int), ("fft_row_threads", C.c_int),
+                ("fft_variant", C.c_int), ("fft_row_threads", C.c_int), ("fft_col_threads", C.c_int),
                 ("fft_ms", C.c_double), ("near_ms", C.c_double), ("csr_ms", C.c_double), ("apply_ms", C.c_double)]
 
 

@@ -915,27 +915,33 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   };
   // column tile of the transforms (stages 2-4: forward, spectral, inverse)
   // (separate kernels: two buffers of tc columns; fused: two of 2 tc)
-  int best_tc = d.tc, best_fv = d.fft_variant;
+  int best_tc = d.tc, best_fv = d.fft_variant, best_cn = d.cols_nth;
   double best = 1e30;
   for (int fv = 0; fv < 2; ++fv) {
     const int tmax = std::max(1, (int)(150 * 1024 / (2 * (size_t)d.Pa * sizeof(T) * 2 * (fv + 1))));
     for (int tc : {1, 2, 4, 8, 16, 32}) {
       if (tc > tmax) break;
-      d.tc = tc;
-      d.fft_variant = fv;
-      double t;
-      ls_status s = measure(2, 4, &t);
-      if (s) return s;
-      log("fft variant/tile", fv, tc, t);
-      if (t < best) {
-        best = t;
-        best_tc = tc;
-        best_fv = fv;
+      for (int cn : {256, 512}) {
+        if (fv == 0 && cn != 256) continue;   // threads only tuned for the fused kernel
+        d.tc = tc;
+        d.fft_variant = fv;
+        d.cols_nth = cn;
+        double t;
+        ls_status s = measure(2, 4, &t);
+        if (s) return s;
+        log("fft variant/tile", fv, tc * 10000 + cn, t);
+        if (t < best) {
+          best = t;
+          best_tc = tc;
+          best_fv = fv;
+          best_cn = cn;
+        }
       }
     }
   }
   d.tc = best_tc;
   d.fft_variant = best_fv;
+  d.cols_nth = best_cn;
   // threads per row transform (a few hundred rows of a few thousand points:
   // more threads per row keep more waves resident)
   int best_nth = d.rows_nth;
@@ -954,6 +960,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->fft_col_tile = best_tc;
   res->fft_variant = best_fv;
   res->fft_row_threads = best_nth;
+  res->fft_col_threads = d.cols_nth;
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
   const int nnear = std::is_same<T, float>::value ? 4 : 1;

@@ -423,8 +423,8 @@ __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const
 // the set's two kernel spectra and summed, and the sum is transformed back;
 // only rows < na (the ones the interpolation reads) go back to memory, in the
 // set's kind-0 plane.
-template <typename T>
-__global__ void __launch_bounds__(256) k_fft_cols_conv(typename C2<T>::t* lat, const typename C2<T>::t* __restrict__ tw,
+template <typename T, int NTH>
+__global__ void __launch_bounds__(NTH) k_fft_cols_conv(typename C2<T>::t* lat, const typename C2<T>::t* __restrict__ tw,
                                                        const typename C2<T>::t* __restrict__ khat, FftPlan plan,
                                                        int ncols, int TC, int64_t plane, int na) {
   using V = typename C2<T>::t;
@@ -1847,7 +1847,8 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     if (d.fft_variant == 1) {
       // fused column transforms + spectral product + inverse column transforms
       size_t shc = 4 * (size_t)d.pa.n * TC * sizeof(V);
-      hipLaunchKernelGGL(k_fft_cols_conv<T>, dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
+      auto conv = d.cols_nth == 512 ? k_fft_cols_conv<T, 512> : k_fft_cols_conv<T, 256>;
+      hipLaunchKernelGGL(conv, dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(d.cols_nth), shc, st, lat,
                          (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na);
     } else {
       size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
@@ -1992,8 +1993,10 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_rows<float, -1, 256>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
-  set((const void*)k_fft_cols_conv<double>);
-  set((const void*)k_fft_cols_conv<float>);
+  set((const void*)k_fft_cols_conv<double, 256>);
+  set((const void*)k_fft_cols_conv<float, 256>);
+  set((const void*)k_fft_cols_conv<double, 512>);
+  set((const void*)k_fft_cols_conv<float, 512>);
   return e;
 }
 

@@ -31,6 +31,7 @@ struct DevView {
   // fused per column tile
   int fft_variant = 0;
   int rows_nth = 256;   // threads per workgroup of the row transforms (256, 512, 1024)
+  int cols_nth = 256;   // threads per workgroup of the fused column kernel (256, 512)
   bool csr_f64 = true;
   double kappa = 0;
   const void *Psh = nullptr, *PshT = nullptr, *Pbd = nullptr, *Ish = nullptr, *Ibd = nullptr, *Toff = nullptr, *Wsh = nullptr;
