@@ -992,10 +992,10 @@ __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u
   __shared__ int cs_s[4][CSR_MAX_RUNS], pre_s[4][CSR_MAX_RUNS + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = blockIdx.x * 4 + wv;
-  const bool valid = row < nrows;
-  const int64_t b = valid ? rowptr[row] : 0, e = valid ? rowptr[row + 1] : 0;
+  if (row >= nrows) return;
+  const int64_t b = rowptr[row], e = rowptr[row + 1];
   const int len = (int)(e - b);
-  const int r0 = valid ? run_ptr[row] : 0, nr = valid ? run_ptr[row + 1] - r0 : 0;
+  const int r0 = run_ptr[row], nr = run_ptr[row + 1] - r0;
   int* cs = cs_s[wv];
   int* pre = pre_s[wv];
   for (int i = lane; i < nr; i += 64) {
@@ -1003,8 +1003,11 @@ __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u
     pre[i] = run_pre[r0 + i];
   }
   if (lane == 0) pre[nr] = len;
-  __syncthreads();
-  if (!valid) return;
+  // each wave reads only its own row's table: a wavefront-scope barrier
+  // (release / acquire on LDS) is enough, the other rows do not wait
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const float4* __restrict__ v4 = (const float4*)(vals + b);
   for (int r00 = 0; r00 < nrhs; r00 += RB) {
     const int nrr = min(RB, nrhs - r00);
