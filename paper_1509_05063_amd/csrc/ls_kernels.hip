@@ -135,6 +135,65 @@ __global__ void __launch_bounds__(192) k_project2(const typename C2<T>::t* __res
   if (g == 0) sigma[((int64_t)r * ncell + c) * U + t] = cadd(acc, red[t]);
 }
 
+// a1 for RB right-hand sides per workgroup (batched applies): the weighted
+// densities of the cell's nodes for RB right-hand sides are staged in LDS
+// ([node][rhs]); each projection value is loaded once and applied to all
+// RB of them (per right-hand side the band columns would be re-read from
+// L2 every time).  Thread (t, g): output t, half g of the node range.
+template <typename T, int RB>
+__global__ void __launch_bounds__(192) k_project_rb(const typename C2<T>::t* __restrict__ u,
+                                                    typename C2<T>::t* __restrict__ sigma,
+                                                    const typename C2<T>::t* __restrict__ PshT,
+                                                    const typename C2<T>::t* __restrict__ Pbd,
+                                                    const T* __restrict__ cw, const int32_t* __restrict__ slot_map,
+                                                    const int32_t* __restrict__ cell_start,
+                                                    const int32_t* __restrict__ cell_nint,
+                                                    const int32_t* __restrict__ cell_nb,
+                                                    const int32_t* __restrict__ cell_boff, int64_t N, int ncell,
+                                                    int nrhs) {
+  using V = typename C2<T>::t;
+  constexpr int U = 96, S = 64;
+  extern __shared__ unsigned char smem_raw[];
+  const int c = blockIdx.x, r0 = blockIdx.y * RB, tid = threadIdx.x;
+  const int nb = cell_nb[c], K = S + nb;
+  V* phi = reinterpret_cast<V*>(smem_raw);   // [K][RB]
+  V* red = phi + (size_t)K * RB;             // [RB][U] second half's sums
+  const int64_t b0 = cell_start[c] + cell_nint[c];
+  for (int i = tid; i < K * RB; i += blockDim.x) {
+    const int a = i % K, q = i / K, r = r0 + q;    // consecutive threads: consecutive nodes
+    const int64_t j = a < S ? slot_map[(int64_t)c * S + a] : b0 + a - S;
+    phi[a * RB + q] = (j >= 0 && r < nrhs) ? cscale(u[(int64_t)r * N + j], cw[j]) : czero<V>();
+  }
+  __syncthreads();
+  const int t = tid % U, g = tid / U;
+  V acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) acc[q] = czero<V>();
+  for (int a = 32 * g; a < 32 * g + 32; ++a) {
+    const V p = PshT[a * U + t];
+    const V* ph = phi + a * RB;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = cfma(p, ph[q], acc[q]);
+  }
+  const V* prow = Pbd + (int64_t)cell_boff[c] * U + t;
+  for (int b = g; b < nb; b += 2) {
+    const V p = prow[(int64_t)b * U];
+    const V* ph = phi + (S + b) * RB;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = cfma(p, ph[q], acc[q]);
+  }
+  if (g == 1) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) red[q * U + t] = acc[q];
+  }
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (r0 + q < nrhs) sigma[((int64_t)(r0 + q) * ncell + c) * U + t] = cadd(acc[q], red[q * U + t]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Lattice fill: node (a, b) of set s gathers face 0 of the cell whose
 // normal index is a and face 1 of the cell a-1 (at most two cells, no
@@ -622,6 +681,94 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
     for (int t = 0; t < F; ++t) s1 = cfma(icol[t * nband], fv[cb * F + t], s1);
     const int64_t j = cell_start[c] + cell_nint[c] + (ib - cell_boff[c]);
     vr[j] = cadd(ur[j], cscale(s1, k2));
+  }
+}
+
+// The same interpolation for 16 right-hand sides of one cell per workgroup
+// (batched applies): the MFMA columns are the 16 right-hand sides instead of
+// 16 cells, and each band node's fit row is read once for all of them.  Every
+// output goes through the same products in the same order as in
+// k_interp_mfma, so results are bitwise those of the per-right-hand-side
+// launch.
+template <typename T>
+__global__ void __launch_bounds__(256) k_interp_rb(const typename C2<T>::t* __restrict__ u,
+                                                   typename C2<T>::t* __restrict__ v,
+                                                   const typename C2<T>::t* __restrict__ lat,
+                                                   const typename C2<T>::t* __restrict__ IshT,
+                                                   const typename C2<T>::t* __restrict__ Ibd,
+                                                   const int32_t* __restrict__ cell_xy,
+                                                   const int32_t* __restrict__ slot_map,
+                                                   const int32_t* __restrict__ cell_start,
+                                                   const int32_t* __restrict__ cell_nint,
+                                                   const int32_t* __restrict__ cell_nb,
+                                                   const int32_t* __restrict__ cell_boff, int Pa, int Pb, int64_t N,
+                                                   int64_t nband, int nrhs, T k2) {
+  using V = typename C2<T>::t;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int q = 12, F = 4 * q, S = 64, RB = 16;
+  __shared__ V fv[RB * F];   // [rhs][F] face values
+  const int c = blockIdx.x, r0 = blockIdx.y * RB, tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
+  const int64_t plane = (int64_t)Pa * Pb;
+  const int cx = cell_xy[2 * c], cy = cell_xy[2 * c + 1];
+  for (int i = tid; i < RB * F; i += blockDim.x) {
+    const int qr = i / F, t = i % F, r = r0 + qr;
+    V val = czero<V>();
+    if (r < nrhs) {
+      const int s2 = t / (2 * q), fj = t % (2 * q), fc = fj / q, j = fj % q;
+      const int cn = (s2 == 0 ? cx : cy) + fc, ct = (s2 == 0 ? cy : cx);
+      val = lat[((int64_t)(r * 2 + s2) * 2) * plane + (int64_t)cn * Pb + ct * q + j];
+    }
+    fv[i] = val;
+  }
+  __syncthreads();
+  {
+    v4 dre = v4{0, 0, 0, 0}, dim = v4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < F / 4; ++kk) {
+      const int t = 4 * kk + kl;
+      const V a = IshT[t * S + 16 * wave + col];
+      const V b = fv[col * F + t];
+      dre = M::op(a.x, b.x, dre);
+      dre = M::op(-a.y, b.y, dre);
+      dim = M::op(a.x, b.y, dim);
+      dim = M::op(a.y, b.x, dim);
+    }
+    const int r = r0 + col;
+    if (r < nrhs) {
+      const V* ur = u + (int64_t)r * N;
+      V* vr = v + (int64_t)r * N;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int a = 16 * wave + M::row(lane, rr);
+        const int j = slot_map[(int64_t)c * S + a];
+        if (j >= 0) {
+          V o2;
+          o2.x = dre[rr];
+          o2.y = dim[rr];
+          vr[j] = cadd(ur[j], cscale(o2, k2));
+        }
+      }
+    }
+  }
+  const int nb = cell_nb[c];
+  const int64_t boff = cell_boff[c], b0 = cell_start[c] + cell_nint[c];
+  const int nr = min(RB, nrhs - r0);
+  for (int b = tid; b < nb; b += blockDim.x) {
+    const V* icol = Ibd + boff + b;     // IbdT [F][nband]
+    V s1[RB];
+#pragma unroll
+    for (int qr = 0; qr < RB; ++qr) s1[qr] = czero<V>();
+    for (int t = 0; t < F; ++t) {
+      const V w = icol[t * nband];
+#pragma unroll
+      for (int qr = 0; qr < RB; ++qr) s1[qr] = cfma(w, fv[qr * F + t], s1[qr]);
+    }
+    const int64_t j = b0 + b;
+#pragma unroll
+    for (int qr = 0; qr < RB; ++qr)
+      if (qr < nr) v[(int64_t)(r0 + qr) * N + j] = cadd(u[(int64_t)(r0 + qr) * N + j], cscale(s1[qr], k2));
   }
 }
 
@@ -1820,7 +1967,13 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   // a0 + a1
   {
     size_t sh = (size_t)(d.S + d.max_nb) * sizeof(V);
-    if (d.q == 12 && d.S == 64 && d.PshT) {
+    constexpr int RB = sizeof(T) == 4 ? 16 : 8;
+    const size_t shb = ((size_t)(64 + d.max_nb) * RB + (size_t)RB * 96) * sizeof(V);
+    if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
+      hipLaunchKernelGGL((k_project_rb<T, RB>), dim3(d.ncell, (nrhs + RB - 1) / RB), dim3(192), shb, st, u, sigma,
+                         (const V*)d.PshT, (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb,
+                         d.cell_boff, d.N, d.ncell, nrhs);
+    } else if (d.q == 12 && d.S == 64 && d.PshT) {
       const size_t shm = (size_t)(96 + 64 + d.max_nb) * sizeof(V);
       hipLaunchKernelGGL(k_project2<T>, dim3(d.ncell, nrhs), dim3(192), shm, st, u, sigma, (const V*)d.PshT,
                          (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N,
@@ -1881,7 +2034,11 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   if (lattice_only) return hipGetLastError();   // the caller evaluates the field itself
   // a3 + a5
   {
-    if (d.q == 12 && d.S == 64) {
+    if (d.q == 12 && d.S == 64 && nrhs >= 16) {
+      hipLaunchKernelGGL(k_interp_rb<T>, dim3(d.ncell, (nrhs + 15) / 16), dim3(256), 0, st, u, v, (const V*)lat,
+                         (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start, d.cell_nint,
+                         d.cell_nb, d.cell_boff, d.Pa, d.Pb, d.N, d.nband, nrhs, k2);
+    } else if (d.q == 12 && d.S == 64) {
       constexpr int CB = 16;
       const size_t shm = (size_t)CB * 48 * sizeof(V) + 2 * CB * sizeof(int);
       hipLaunchKernelGGL((k_interp_mfma<T, CB>), dim3((d.ncell + CB - 1) / CB, nrhs), dim3(256), shm, st, u, v,

@@ -78,6 +78,25 @@ def test_multi_rhs_equals_single(disc):
         assert torch.equal(v1, V[k])
 
 
+@pytest.mark.parametrize("cdt", ["complex128", "complex64"])
+def test_batched_kernels_equal_single_applies(disc, cdt):
+    """17 right-hand sides: the first 16 take the batched projection and
+    interpolation kernels (16 right-hand sides per workgroup), the 17th a
+    group of one; each result is bitwise that of its own single apply."""
+    import torch
+    cfg, op, orc, A, p, xy, key = disc
+    dt = getattr(torch, cdt)
+    U = torch.stack([torch.tensor(_to_lib(random_density(orc.pts["key"], seed=s), p, op.N), dtype=dt)
+                     for s in range(17)]).cuda()
+    V = torch.empty_like(U)
+    op.apply(U, V)
+    for k in (0, 7, 15, 16):
+        v1 = torch.empty_like(U[k])
+        op.apply(U[k].contiguous(), v1)
+        torch.cuda.synchronize()
+        assert torch.equal(v1, V[k]), k
+
+
 def test_apply_is_deterministic(disc):
     import torch
     cfg, op, orc, A, p, xy, key = disc
