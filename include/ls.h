@@ -88,13 +88,19 @@ typedef struct {
  *   cell_h       cell side H = cell_h * h
  *   q            equivalent-source nodes per cell face
  *   n_fb         Dirichlet fit order: Fourier–Bessel modes |n| <= n_fb
- *   coll_factor  collocation points = coll_factor * 4q per source set */
+ *   coll_factor  collocation points = coll_factor * 4q per source set
+ *   skip_tiles   (storage, not the discretisation) nonzero: do not keep the
+ *                single-precision near-field rows a second time as dense
+ *                16-row tiles; batched applies then use the row kernels.
+ *                Saves the tiles' memory (about 1.3x the single-precision
+ *                row weights) and their set-up time. */
 typedef struct {
   int Q, P;
   double chi_c0, r_int, r1, r2;
   int polar_n_in, polar_grade, polar_n_out, polar_n_theta;
   int band_M, band_n_in, band_n_out;
   int cell_h, q, n_fb, coll_factor;
+  int skip_tiles;
 } ls_params;
 
 /* Refractive index callback: writes n^2 at n points (x, y interleaved);

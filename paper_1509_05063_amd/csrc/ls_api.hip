@@ -609,7 +609,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   }
   // adjacent far-field subtraction folded into the stored row weights (both
   // precisions); the single-precision weights then come back for the tiles
-  std::vector<Fp32c> vals32((size_t)prow[nrow]);
+  std::vector<Fp32c> vals32(p->skip_tiles ? 0 : (size_t)prow[nrow]);
   {
     std::vector<int64_t> olen(nrow);
     for (size_t r = 0; r < nrow; ++r) olen[r] = h.rowptr[r + 1] - h.rowptr[r];
@@ -639,14 +639,14 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     ok = ok && lsx::launch_fold_rows(a, b, (const int64_t*)d_olen, (const int32_t*)d_cell, (const int32_t*)d_idx,
                                      0) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
-    ok = ok && (vals32.empty() || hipMemcpy(vals32.data(), b.vals, 8 * vals32.size(), hipMemcpyDeviceToHost) ==
-                                      hipSuccess);
+    ok = ok && (vals32.empty() ||
+                hipMemcpy(vals32.data(), b.vals, 8 * vals32.size(), hipMemcpyDeviceToHost) == hipSuccess);
     if (d_olen) (void)hipFree(d_olen);
     if (d_cell) (void)hipFree(d_cell);
     if (d_idx) (void)hipFree(d_idx);
     if (!ok) return cleanup(fail(LS_EDEVICE, "near-field fold failed"));
   }
-  {
+  if (!p->skip_tiles) {
     // Single precision, batched use: the rows as dense tiles of 16 rows of
     // one cell and kind.  A tile's columns are the points of the 3 x 3
     // adjacent cells that all its rows couple to (every point for

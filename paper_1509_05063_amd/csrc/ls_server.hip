@@ -262,6 +262,7 @@ ls_status ls_server_add_operator(ls_server* s, uint64_t key, const ls_geometry* 
   SrvOp& e = s->ops[key];
   e.g = *geom;
   e.p = *params;
+  e.p.skip_tiles = 1;   // the server does not tune its operators, so batches use the row kernels
   e.n2 = n2;
   e.ctx = ctx;
   e.kappa = kappa;

@@ -97,6 +97,30 @@ def test_batched_kernels_equal_single_applies(disc, cdt):
         assert torch.equal(v1, V[k]), k
 
 
+def test_operator_without_tiles(disc):
+    """skip_tiles: no dense tiles are kept (less device memory), the tuner
+    does not offer them for batches, and applies are unchanged."""
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    cfg2 = dict(cfg, skip_tiles=1)
+    op2 = binding.Operator(cfg2, n2_function(cfg2))
+    try:
+        assert op2.stats()["tile_weights"] == 0 and op.stats()["tile_weights"] > 0
+        assert op2.resident_bytes() < op.resident_bytes()
+        ch = op2.autotune(16, binding.LS_C64)
+        assert ch["csr_variant"] != 3
+        U = torch.stack([torch.tensor(_to_lib(random_density(orc.pts["key"], seed=s), p, op.N),
+                                      dtype=torch.complex128) for s in range(2)]).cuda()
+        V1, V2 = torch.empty_like(U), torch.empty_like(U)
+        op.apply(U, V1)
+        op2.apply(U, V2)
+        torch.cuda.synchronize()
+        assert (torch.linalg.norm(V1 - V2) / torch.linalg.norm(V1)).item() < 1e-13
+    finally:
+        op2.close()
+
+
 def test_apply_is_deterministic(disc):
     import torch
     cfg, op, orc, A, p, xy, key = disc
