@@ -449,6 +449,19 @@ __global__ void __launch_bounds__(NTH) k_fft_rows(typename C2<T>::t* data, const
   for (int i = threadIdx.x; i < nstore; i += blockDim.x) x[i] = res[i];
 }
 
+// XCD-aware column tiles: workgroups are dispatched round-robin over the 8
+// XCDs (block b on XCD b % 8), so XCD x is given the contiguous tiles
+// [x per, (x + 1) per); a workgroup reads TC columns (a quarter of a 128-byte
+// line at TC = 4 in single precision), and its neighbours, now on the same
+// XCD, find the rest of the line in that XCD's L2 instead of fetching it
+// again.  Launch with grid.x = 8 per; -1 past the last tile.
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int per = gridDim.x / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  return t < ntiles ? t : -1;
+}
+inline unsigned xcd_grid(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
+
 // transforms along the strided axis: a workgroup takes TC adjacent columns
 template <typename T, int DIR>
 // (rows past nload are zero padding: not read; rows past nstore: not written)
@@ -459,7 +472,9 @@ __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const
   extern __shared__ unsigned char smem_raw[];
   V* b0 = reinterpret_cast<V*>(smem_raw);
   V* b1 = b0 + plan.n * TC;
-  const int c0 = blockIdx.x * TC;
+  const int tile = xcd_tile((ncols + TC - 1) / TC);
+  if (tile < 0) return;
+  const int c0 = tile * TC;
   const int batch = blockIdx.y;
   const int tc = min(TC, ncols - c0);
   V* x = data + batch * batch_stride + c0;
@@ -491,7 +506,9 @@ __global__ void __launch_bounds__(NTH) k_fft_cols_conv(typename C2<T>::t* lat, c
   const int n = plan.n, W = 2 * TC;
   V* b0 = reinterpret_cast<V*>(smem_raw);   // [n][2 TC]: monopole columns, then dipole columns
   V* b1 = b0 + (size_t)n * W;
-  const int c0 = blockIdx.x * TC;
+  const int tile = xcd_tile((ncols + TC - 1) / TC);
+  if (tile < 0) return;
+  const int c0 = tile * TC;
   const int s = blockIdx.y & 1, r = blockIdx.y >> 1;
   const int tc = min(TC, ncols - c0);
   V* mp = lat + ((int64_t)(r * 2 + s) * 2) * plane + c0;
@@ -2004,11 +2021,11 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       // fused column transforms + spectral product + inverse column transforms
       size_t shc = 4 * (size_t)d.pa.n * TC * sizeof(V);
       auto conv = d.cols_nth == 512 ? k_fft_cols_conv<T, 512> : k_fft_cols_conv<T, 256>;
-      hipLaunchKernelGGL(conv, dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(d.cols_nth), shc, st, lat,
+      hipLaunchKernelGGL(conv, dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(d.cols_nth), shc, st, lat,
                          (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na);
     } else {
       size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
-      hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, lat,
+      hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st, lat,
                          (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa);
     }
   }
@@ -2022,7 +2039,8 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     int TC = TCP;
     size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
     if (d.fft_variant != 1)
-      hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3((d.Pb + TC - 1) / TC, nrhs * 2), dim3(256), shc, st, lat,
+      hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(256), shc, st,
+                         lat,
                          (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na);
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     auto rows_i = d.rows_nth == 1024 ? k_fft_rows<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, -1, 512>
@@ -2168,7 +2186,8 @@ hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int 
                      d.pb, (int64_t)d.Pb, d.Pb, d.Pb, plane);
   int TC = d.tc;
   size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
-  hipLaunchKernelGGL((k_fft_cols<double, 1>), dim3((d.Pb + TC - 1) / TC, nbatch), dim3(256), shc, st, (V*)data,
+  hipLaunchKernelGGL((k_fft_cols<double, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st,
+                     (V*)data,
                      (const V*)d.twa, d.pa, d.Pb, TC, plane, d.Pa, d.Pa);
   return hipGetLastError();
 }
