@@ -140,14 +140,14 @@ def multi_rhs_run(nrhs, ortho, autotune):
         op.close()
 
 
-def serving_run(n_requests, rate=20.0, ortho=None):
+def serving_run(n_requests, rate=20.0, ortho=None, restart=100):
     """Poisson stream of solves over a warm pool of resident operators
     (continuous batching per operator, concurrent solves across operators)."""
     from paper_1509_05063_amd.inputs import serving_pool, serving_trace
     from paper_1509_05063_amd.serve import Server, latency_stats, replay
     pool = serving_pool()
     from paper_1509_05063_amd import binding
-    srv = Server(budget_bytes=200e9, max_batch=16, workers=4, keep_results=False,
+    srv = Server(budget_bytes=200e9, max_batch=16, workers=4, keep_results=False, restart=restart,
                  ortho=binding.LS_ORTHO_CGS1 if ortho is None else ortho)
     try:
         t0 = time.time()
