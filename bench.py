@@ -140,7 +140,7 @@ def multi_rhs_run(nrhs, ortho, autotune):
         op.close()
 
 
-def serving_run(n_requests, rate=20.0, ortho=None, restart=100):
+def serving_run(n_requests, rate=20.0, ortho=None, restart=60):
     """Poisson stream of solves over a warm pool of resident operators
     (continuous batching per operator, concurrent solves across operators)."""
     from paper_1509_05063_amd.inputs import serving_pool, serving_trace
