@@ -2,9 +2,10 @@
 
 A step is one full pass of the hot path on the workload: a GMRES solve of
 (I + kappa^2 K_h) u = u^i whose every iteration runs the whole operator
-apply (projection, FFT convolution, adjacency subtraction and cell
-interpolation, near-field correction, combine) in single precision inside
-double-precision iterative refinement (FP64 residual and Arnoldi).
+apply (projection, FFT convolution, cell interpolation, near-field
+correction with the adjacency subtraction folded in, combine) in single
+precision inside double-precision iterative refinement (FP64 residual and
+Arnoldi).
 
 Prints one JSON line (rank 0):  metric / value = solves per second at
 <= 1e-6 relative error against the double-precision reference solve, plus

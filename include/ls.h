@@ -17,9 +17,12 @@
  * projection onto equivalent sources on cell faces (Sec. 3.2,
  * equiv-conv-loc), FFT convolution with the Green's function on the face
  * lattices (Sec. 3.2), interpolation back to the Nystrom nodes through cell
- * Dirichlet fits (Sec. 3.2, eq:-PWE) after subtracting the adjacent cells,
- * and a sparse near-field correction that carries the singular and interface
- * quadrature weights (Sec. 3.1, eq:-VolInt-Adj-NonAdj-I).
+ * Dirichlet fits (Sec. 3.2, eq:-PWE), and a sparse near-field correction
+ * that carries the singular and interface quadrature weights (Sec. 3.1,
+ * eq:-VolInt-Adj-NonAdj-I).  The subtraction of the adjacent cells'
+ * equivalent-source fields from the face values (Sec. 3.2) is linear and
+ * touches only pairs the near field stores, so ls_create folds it into the
+ * near-field weights once.
  *
  * Conventions shared by every entry point
  *   - Complex vectors are interleaved (re, im).  LS_C128: double, LS_C64:
