@@ -1689,14 +1689,32 @@ __device__ __forceinline__ double wave_sum(double v) {
 // d_j = <V_j, w> (conj(V_j) . w) for j < nv <= NV <= 32.  Each thread keeps
 // its own partial sums; the workgroup reduces them by a transpose through LDS
 // (16 basis vectors at a time) rather than by cross-lane shuffles.
-// VW complex values per lane and step (2: 16-byte loads; needs N and
-// vstride even so that every vector slice starts 16-byte aligned)
-template <int NV, int VW>
+// Element pair (2i, 2i+1) of a vector slice: one 16-byte access when the
+// slice starts 16-byte aligned, else two 8-byte ones (same values, so the
+// arithmetic, and the result, is the same either way).
+__device__ __forceinline__ bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+__device__ __forceinline__ float4 ld_pair(const float2* p, int64_t i, bool al) {
+  if (al) return reinterpret_cast<const float4*>(p)[i];
+  const float2 a = p[2 * i], b = p[2 * i + 1];
+  return make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void st_pair(float2* p, int64_t i, bool al, float4 v) {
+  if (al) {
+    reinterpret_cast<float4*>(p)[i] = v;
+  } else {
+    p[2 * i] = make_float2(v.x, v.y);
+    p[2 * i + 1] = make_float2(v.z, v.w);
+  }
+}
+
+// Two complex values (an element pair) per lane and step, 16-byte accesses
+// where the slice is aligned; an odd last element is taken by thread 0 of
+// workgroup 0.
+template <int NV>
 __global__ void __launch_bounds__(256) k_dots32(const float2* __restrict__ Vb, const float2* __restrict__ w,
                                                 double2* __restrict__ partial, int nv, int64_t N,
                                                 int64_t vstride) {
   static_assert(NV <= 32, "at most 32 basis vectors per pass");
-  static_assert(VW == 1 || VW == 2, "one or two complex values per lane");
   __shared__ float buf[32][264];
   const int r = blockIdx.y;
   const float2* wr = w + (int64_t)r * N;
@@ -1705,26 +1723,30 @@ __global__ void __launch_bounds__(256) k_dots32(const float2* __restrict__ Vb, c
 #pragma unroll
   for (int j = 0; j < NV; ++j) ax[j] = ay[j] = 0.f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N / VW; i += stride) {
-    if constexpr (VW == 2) {
-      const float4 b = reinterpret_cast<const float4*>(wr)[i];
+  unsigned amask = 0;     // bit j: slice of V_j 16-byte aligned
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        if (j < nv) {
-          const float4 a = reinterpret_cast<const float4*>(V0 + j * vstride)[i];
-          ax[j] += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
-          ay[j] += a.x * b.y - a.y * b.x + a.z * b.w - a.w * b.z;
-        }
+  for (int j = 0; j < NV; ++j)
+    if (j < nv && al16(V0 + j * vstride)) amask |= 1u << j;
+  const bool wal = al16(wr);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N / 2; i += stride) {
+    const float4 b = ld_pair(wr, i, wal);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      if (j < nv) {
+        const float4 a = ld_pair(V0 + j * vstride, i, (amask >> j) & 1u);
+        ax[j] += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+        ay[j] += a.x * b.y - a.y * b.x + a.z * b.w - a.w * b.z;
       }
-    } else {
-      const float2 b = wr[i];
+    }
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const float2 b = wr[N - 1];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        if (j < nv) {
-          const float2 a = V0[j * vstride + i];
-          ax[j] += a.x * b.x + a.y * b.y;
-          ay[j] += a.x * b.y - a.y * b.x;
-        }
+    for (int j = 0; j < NV; ++j) {
+      if (j < nv) {
+        const float2 a = V0[j * vstride + N - 1];
+        ax[j] += a.x * b.x + a.y * b.y;
+        ay[j] += a.x * b.y - a.y * b.x;
       }
     }
   }
@@ -1759,11 +1781,10 @@ __global__ void __launch_bounds__(256) k_dots32(const float2* __restrict__ Vb, c
 
 // dst = src - sum_{j < nv} h[r * ldh + j] V_j, nv <= NV <= 32 (src may equal dst); when
 // partial != nullptr also |dst|^2 per workgroup (partial[r * gridDim.x + block])
-template <int NV, int VW>
+template <int NV>
 __global__ void __launch_bounds__(256) k_update32(const float2* __restrict__ Vb, const float2* src, float2* dst,
                                                   const double2* __restrict__ h, int nv, int ldh, int64_t N,
                                                   int64_t vstride, double2* __restrict__ partial) {
-  static_assert(VW == 1 || VW == 2, "one or two complex values per lane");
   __shared__ float2 hs[NV];
   __shared__ double red[4];
   const int r = blockIdx.y;
@@ -1777,36 +1798,40 @@ __global__ void __launch_bounds__(256) k_update32(const float2* __restrict__ Vb,
   const float2* V0 = Vb + (int64_t)r * N;
   double nrm = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N / VW; i += stride) {
-    if constexpr (VW == 2) {
-      float4 acc = reinterpret_cast<const float4*>(sr)[i];
+  unsigned amask = 0;     // bit j: slice of V_j 16-byte aligned
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        if (j < nv) {
-          const float4 a = reinterpret_cast<const float4*>(V0 + j * vstride)[i];
-          const float2 c = hs[j];
-          acc.x -= c.x * a.x - c.y * a.y;
-          acc.y -= c.x * a.y + c.y * a.x;
-          acc.z -= c.x * a.z - c.y * a.w;
-          acc.w -= c.x * a.w + c.y * a.z;
-        }
-      }
-      reinterpret_cast<float4*>(dr)[i] = acc;
-      nrm += (double)acc.x * acc.x + (double)acc.y * acc.y + ((double)acc.z * acc.z + (double)acc.w * acc.w);
-    } else {
-      float2 acc = sr[i];
+  for (int j = 0; j < NV; ++j)
+    if (j < nv && al16(V0 + j * vstride)) amask |= 1u << j;
+  const bool sal = al16(sr), dal = al16(dr);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N / 2; i += stride) {
+    float4 acc = ld_pair(sr, i, sal);
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        if (j < nv) {
-          const float2 a = V0[j * vstride + i];
-          const float2 c = hs[j];
-          acc.x -= c.x * a.x - c.y * a.y;
-          acc.y -= c.x * a.y + c.y * a.x;
-        }
+    for (int j = 0; j < NV; ++j) {
+      if (j < nv) {
+        const float4 a = ld_pair(V0 + j * vstride, i, (amask >> j) & 1u);
+        const float2 c = hs[j];
+        acc.x -= c.x * a.x - c.y * a.y;
+        acc.y -= c.x * a.y + c.y * a.x;
+        acc.z -= c.x * a.z - c.y * a.w;
+        acc.w -= c.x * a.w + c.y * a.z;
       }
-      dr[i] = acc;
-      nrm += (double)acc.x * acc.x + (double)acc.y * acc.y;
     }
+    st_pair(dr, i, dal, acc);
+    nrm += (double)acc.x * acc.x + (double)acc.y * acc.y + ((double)acc.z * acc.z + (double)acc.w * acc.w);
+  }
+  if ((N & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    float2 acc = sr[N - 1];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      if (j < nv) {
+        const float2 a = V0[j * vstride + N - 1];
+        const float2 c = hs[j];
+        acc.x -= c.x * a.x - c.y * a.y;
+        acc.y -= c.x * a.y + c.y * a.x;
+      }
+    }
+    dr[N - 1] = acc;
+    nrm += (double)acc.x * acc.x + (double)acc.y * acc.y;
   }
   if (partial == nullptr) return;
   nrm = wave_sum(nrm);
@@ -2262,9 +2287,7 @@ hipError_t gm32_dots(const void* Vb, const void* w, void* partial, void* out, in
     const int nv = nvec - c0 < 32 ? nvec - c0 : 32;
     const float2* V = (const float2*)Vb + (int64_t)c0 * vstride;
     dim3 g(nparts, nrhs);
-    const bool pair = N % 2 == 0 && vstride % 2 == 0;
-    auto kern = pair ? (nv_bucket(nv) == 8 ? k_dots32<8, 2> : nv_bucket(nv) == 16 ? k_dots32<16, 2> : k_dots32<32, 2>)
-                     : (nv_bucket(nv) == 8 ? k_dots32<8, 1> : nv_bucket(nv) == 16 ? k_dots32<16, 1> : k_dots32<32, 1>);
+    auto kern = nv_bucket(nv) == 8 ? k_dots32<8> : nv_bucket(nv) == 16 ? k_dots32<16> : k_dots32<32>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, st, V, (const float2*)w, (double2*)partial, nv, N, vstride);
     hipLaunchKernelGGL(k_fold, dim3(nv * nrhs), dim3(256), 0, st, (const double2*)partial, (double2*)out, nparts, nv,
                        ldo, c0);
@@ -2283,11 +2306,7 @@ hipError_t gm32_update(const void* Vb, const void* src, void* dst, const void* h
     const double2* hh = (const double2*)h + c0;
     double2* part = (last && norm_out) ? (double2*)partial : nullptr;
     dim3 g(nparts, nrhs);
-    const bool pair = N % 2 == 0 && vstride % 2 == 0;
-    auto kern = pair ? (nv_bucket(nv) == 8 ? k_update32<8, 2> : nv_bucket(nv) == 16 ? k_update32<16, 2>
-                                                                                     : k_update32<32, 2>)
-                     : (nv_bucket(nv) == 8 ? k_update32<8, 1> : nv_bucket(nv) == 16 ? k_update32<16, 1>
-                                                                                     : k_update32<32, 1>);
+    auto kern = nv_bucket(nv) == 8 ? k_update32<8> : nv_bucket(nv) == 16 ? k_update32<16> : k_update32<32>;
     hipLaunchKernelGGL(kern, g, dim3(256), 0, st, V, in, (float2*)dst, hh, nv, nvec, N, vstride, part);
     in = (const float2*)dst;
   }
