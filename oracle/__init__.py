@@ -15,4 +15,5 @@ Modules:
   mie     closed forms: Mie series (2-D, 3-D), volume potential of a constant
   solve   restarted complex GMRES, dense LU
   exterior  scattered field off the scatterer by direct summation
+  conv3d  the 3-D face-lattice convolution (monopole + dipole) by direct summation
 """
