@@ -172,6 +172,69 @@ def serving_run(n_requests, rate=20.0, ortho=None, restart=60):
         srv.close()
 
 
+SPHERE_LATTICE = dict(na=33, nb=128, nc=128, hn=4 / 64, ht=1 / 64, kappa=8 * math.pi, nsets=3)
+
+
+def conv3d_textbook_bytes(Pa, Pb, Pc, nsets):
+    """Textbook pencil count of the FFT convolution (complex float): per set
+    three full transforms (two forward, one inverse) of three passes, each
+    reading and writing the padded volume, plus the two kernel spectra."""
+    P = Pa * Pb * Pc
+    return 8 * nsets * (3 * 3 * 2 * P + 2 * P)
+
+
+def conv3d_pass_bytes(na, nb, nc, Pa, Pb, Pc, nsets):
+    """Bytes the implemented passes have to move (complex float): padding
+    rows are neither read nor written.  Per array (2 nsets: both kinds of
+    every set) pad, lines along c, columns along b; per set the fused pass
+    along a (both kinds' na rows and the two spectra in, kind 0's na rows
+    out), then columns along b, lines along c and unpad of kind 0."""
+    e = 8
+    fwd = (2 * na * nb * nc) + (na * nb * nc + na * nb * Pc) + (na * nb * Pc + na * Pb * Pc)
+    conv = 2 * na * Pb * Pc + 2 * Pa * Pb * Pc + na * Pb * Pc
+    inv = (na * Pb * Pc + na * nb * Pc) + (na * nb * Pc + na * nb * nc) + 2 * na * nb * nc
+    return e * (2 * nsets * fwd + nsets * (conv + inv))
+
+
+def conv3d_run(reps):
+    """The 3-D method's FFT convolution step (monopole + dipole face-lattice
+    sums, Sec. 3.2) on the face lattices of the unit-sphere workload
+    (kappa = 8 pi, h = 1/64, cells of 4 h, 4 nodes per face edge): three
+    sets of 33 x 128 x 128 nodes.  Timed with HIP events on the stream the
+    library launches on (torch's current stream)."""
+    import torch
+    from paper_1509_05063_amd import binding
+    L = SPHERE_LATTICE
+    c = binding.Conv3D(L["na"], L["nb"], L["nc"], L["hn"], L["ht"], L["kappa"], L["nsets"])
+    Pa, Pb, Pc = c.padded
+    g = torch.Generator(device="cuda").manual_seed(1509)
+    sig = torch.randn(L["nsets"], 2, L["na"], L["nb"], L["nc"], dtype=torch.complex64, device="cuda", generator=g)
+    fld = torch.empty(L["nsets"], L["na"], L["nb"], L["nc"], dtype=torch.complex64, device="cuda")
+    st = torch.cuda.current_stream()
+    c.apply(sig, fld)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        c.apply(sig, fld)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    byts = conv3d_textbook_bytes(Pa, Pb, Pc, L["nsets"])
+    pbyts = conv3d_pass_bytes(L["na"], L["nb"], L["nc"], Pa, Pb, Pc, L["nsets"])
+    gbs, pgbs = byts / (ms * 1e-3) / 1e9, pbyts / (ms * 1e-3) / 1e9
+    # achieved / frac: the bytes the implemented passes must move (a lower
+    # bound on their HBM traffic); textbook_*: the pencil count of three
+    # unfused padded transforms per set, for comparison with that design
+    out = {"stage": "fft3d", "bound": "hbm", "achieved": round(pgbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(pgbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(pbyts), "avg_ms": round(ms, 4),
+           "textbook_bytes": int(byts), "textbook_gbs": round(gbs, 1), "textbook_frac": round(gbs / PEAK_HBM_GBS, 4),
+           "lattice": f"{L['nsets']} sets x {L['na']}x{L['nb']}x{L['nc']} padded to {Pa}x{Pb}x{Pc}",
+           "workspace_gb": c.ws_bytes / 1e9}
+    c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,11 +256,19 @@ def main():
     ap.add_argument("--profile-applies", type=int, default=0,
                     help="profiling run: only this many applies per precision plus a 512 MiB "
                          "device copy (the calibration kernel for HBM byte counters)")
+    ap.add_argument("--fft3d-reps", type=int, default=20,
+                    help="applies of the 3-D face-lattice convolution in its measurement (0 skips it)")
+    ap.add_argument("--profile-fft3d", type=int, default=0,
+                    help="profiling run: only this many 3-D face-lattice convolutions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.profile_fft3d:
+        log(f"profile fft3d {conv3d_run(args.profile_fft3d)}")
+        return
 
     import torch
     from paper_1509_05063_amd import binding
@@ -327,6 +398,11 @@ def main():
                 "frac": round(fft_gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(fft_b), "avg_ms": round(fft_ms, 4),
                 "note": "2-D face lattices (2 sets x 2 kinds x Pa x Pb complex float) fit in the 256 MB MALL"}
 
+    fft3d = None
+    if args.fft3d_reps:
+        fft3d = conv3d_run(args.fft3d_reps)
+        log(f"fft3d {fft3d}")
+
     multi = None
     if args.multi_rhs:
         multi = multi_rhs_run(args.multi_rhs, ortho, not args.no_autotune)
@@ -378,6 +454,7 @@ def main():
         "resident_gb": op.resident_bytes() / 1e9,
         "roofline": roof,
         "roofline_fft": roof_fft,
+        "roofline_fft3d": fft3d,
         "autotune": tune,
         "multi_rhs": multi,
         "serving": serving,

@@ -340,6 +340,41 @@ void ls_server_destroy(ls_server* s);
 const char* ls_status_str(ls_status s);
 const char* ls_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Three-dimensional face-lattice convolution (the FFT step of the 3-D
+ * method, Sec. 3.2, equiv-conv-loc).  In 3-D each source set of a cubic cell
+ * lattice lives on a lattice of na x nb x nc nodes indexed [a][b][c] =
+ * (normal, tangential, tangential) with spacings hn, ht, ht.  For every set
+ *   F(x) = sum over nodes y != x of G(x - y) sigma_m(y) + D(x - y) sigma_d(y)
+ * with G(r) = exp(i kappa r) / (4 pi r) and D = dG(|x - y|)/dy along the
+ * normal axis (the K(0) = 0 convention), computed by zero-padded FFTs
+ * (padded sizes next 2^i 3^j 5^k >= 2n - 1; spectra computed once in double
+ * and kept in single precision).  Single precision (LS_C64) only.  Only
+ * this step of the 3-D method is built.
+ * ------------------------------------------------------------------------ */
+typedef struct ls_conv3d ls_conv3d;
+
+/* LS_EINVAL for non-positive sizes, spacings or kappa, or lattices whose
+ * padded sizes exceed what one workgroup transforms in LDS (Pc <= 2048,
+ * Pb <= 256 tangential, Pa <= 128 normal); LS_ENOMEM / LS_EDEVICE on device
+ * failures.  Synchronous (uses the null stream once). */
+ls_status ls_conv3d_create(int na, int nb, int nc, double hn, double ht, double kappa, int nsets,
+                           ls_conv3d** out);
+
+/* padded[3] = (Pa, Pb, Pc); ws_bytes = workspace one apply needs
+ * (nsets * 2 * Pa * Pb * Pc complex float); resident_bytes = device memory
+ * the object holds (spectra, twiddles).  Any pointer may be NULL. */
+ls_status ls_conv3d_info(const ls_conv3d* c, int* padded, size_t* ws_bytes, size_t* resident_bytes);
+
+/* sigma: device [nsets][2][na][nb][nc] complex float (kind 0 monopole,
+ * kind 1 dipole strengths); field: device [nsets][na][nb][nc] complex float
+ * (written); ws: device workspace of at least ws_bytes (caller-owned;
+ * concurrent applies need separate workspaces).  Asynchronous on `stream`.
+ * LS_EINVAL for null pointers or a short workspace. */
+ls_status ls_conv3d_apply(ls_conv3d* c, const void* sigma, void* field, void* ws, size_t ws_bytes, void* stream);
+
+void ls_conv3d_destroy(ls_conv3d* c);
+
 #ifdef __cplusplus
 }
 #endif

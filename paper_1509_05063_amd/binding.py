@@ -107,6 +107,12 @@ def lib():
             "ls_server_points": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_int64, P(C.c_int64)]),
             "ls_server_stats": (C.c_int, [C.c_void_p, P(ServerInfo)]),
             "ls_server_destroy": (None, [C.c_void_p]),
+            "ls_conv3d_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
+                                           P(C.c_void_p)]),
+            "ls_conv3d_info": (C.c_int, [C.c_void_p, P(C.c_int), P(C.c_size_t), P(C.c_size_t)]),
+            "ls_conv3d_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                          C.c_void_p]),
+            "ls_conv3d_destroy": (None, [C.c_void_p]),
             "ls_targets_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, P(C.c_void_p)]),
             "ls_targets_destroy": (None, [C.c_void_p]),
             "ls_scattered_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
@@ -223,6 +229,48 @@ def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+class Conv3D:
+    """3-D face-lattice convolution (ls_conv3d_*): nsets lattices of
+    na x nb x nc nodes, spacings hn (normal) and ht (tangential)."""
+
+    def __init__(self, na, nb, nc, hn, ht, kappa, nsets=3):
+        self._c = C.c_void_p()
+        _check(lib().ls_conv3d_create(int(na), int(nb), int(nc), float(hn), float(ht), float(kappa), int(nsets),
+                                      C.byref(self._c)), "ls_conv3d_create")
+        self.shape = (int(nsets), int(na), int(nb), int(nc))
+        pad = (C.c_int * 3)()
+        ws, res = C.c_size_t(), C.c_size_t()
+        _check(lib().ls_conv3d_info(self._c, pad, C.byref(ws), C.byref(res)), "ls_conv3d_info")
+        self.padded, self.ws_bytes, self.resident_bytes = tuple(pad), ws.value, res.value
+        self._ws = None
+
+    def apply(self, sigma, field, stream=None):
+        """sigma: complex64 CUDA tensor [nsets][2][na][nb][nc]; field:
+        complex64 CUDA tensor [nsets][na][nb][nc] (written)."""
+        import torch
+        s, a, b, c = self.shape
+        if tuple(sigma.shape) != (s, 2, a, b, c) or tuple(field.shape) != (s, a, b, c):
+            raise ValueError("sigma / field shapes do not match the lattice")
+        if sigma.dtype != torch.complex64 or field.dtype != torch.complex64 or not (sigma.is_contiguous()
+                                                                                    and field.is_contiguous()):
+            raise ValueError("contiguous complex64 tensors expected")
+        if self._ws is None:
+            self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=sigma.device)
+        _check(lib().ls_conv3d_apply(self._c, sigma.data_ptr(), field.data_ptr(), self._ws.data_ptr(),
+                                     self.ws_bytes, _stream(stream)), "ls_conv3d_apply")
+
+    def close(self):
+        if self._c:
+            lib().ls_conv3d_destroy(self._c)
+            self._c = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Operator:

@@ -176,6 +176,10 @@ size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
 
 }  // namespace
 
+namespace lsx {
+FftPlan make_fft_plan(int n) { return make_plan(n); }
+}  // namespace lsx
+
 extern "C" {
 
 // Field off the scatterer (see ls.h): targets sorted by cell of the lattice

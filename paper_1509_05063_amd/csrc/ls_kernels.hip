@@ -434,14 +434,14 @@ __device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, 
 template <typename T, int DIR, int NTH>
 __global__ void __launch_bounds__(NTH) k_fft_rows(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
                                                   FftPlan plan, int64_t line_stride, int nload, int nstore,
-                                                  int64_t batch_stride) {
+                                                  int64_t batch_stride, int64_t zstride = 0) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
   V* b0 = reinterpret_cast<V*>(smem_raw);
   V* b1 = b0 + plan.n;
   const int line = blockIdx.x;
   const int batch = blockIdx.y;
-  V* x = data + batch * batch_stride + (int64_t)line * line_stride;
+  V* x = data + blockIdx.z * zstride + batch * batch_stride + (int64_t)line * line_stride;
   for (int i = threadIdx.x; i < plan.n; i += blockDim.x) b0[i] = i < nload ? x[i] : czero<V>();
   __syncthreads();
   V* res;
@@ -467,7 +467,7 @@ template <typename T, int DIR>
 // (rows past nload are zero padding: not read; rows past nstore: not written)
 __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
                                                   FftPlan plan, int ncols, int TC, int64_t batch_stride, int nload,
-                                                  int nstore) {
+                                                  int nstore, int64_t zstride = 0) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
   V* b0 = reinterpret_cast<V*>(smem_raw);
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const
   const int c0 = tile * TC;
   const int batch = blockIdx.y;
   const int tc = min(TC, ncols - c0);
-  V* x = data + batch * batch_stride + c0;
+  V* x = data + blockIdx.z * zstride + batch * batch_stride + c0;
   for (int i = threadIdx.x; i < plan.n * TC; i += blockDim.x) {
     int row = i / TC, col = i % TC;
     b0[i] = (col < tc && row < nload) ? x[(int64_t)row * ncols + col] : czero<V>();
@@ -494,13 +494,15 @@ __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const
 // Column transforms, spectral product and inverse column transform in one
 // workgroup per TC-column tile of one set: the tile's monopole and dipole
 // columns are transformed together (2 TC interleaved columns), multiplied by
-// the set's two kernel spectra and summed, and the sum is transformed back;
+// the set's two kernel spectra (set s's pair at khat + s kset_stride; a
+// stride of 0 gives every set the same pair) and summed, and the sum is
+// transformed back;
 // only rows < na (the ones the interpolation reads) go back to memory, in the
 // set's kind-0 plane.
 template <typename T, int NTH>
 __global__ void __launch_bounds__(NTH) k_fft_cols_conv(typename C2<T>::t* lat, const typename C2<T>::t* __restrict__ tw,
                                                        const typename C2<T>::t* __restrict__ khat, FftPlan plan,
-                                                       int ncols, int TC, int64_t plane, int na) {
+                                                       int ncols, int TC, int64_t plane, int na, int64_t kset_stride) {
   using V = typename C2<T>::t;
   extern __shared__ unsigned char smem_raw[];
   const int n = plan.n, W = 2 * TC;
@@ -520,7 +522,7 @@ __global__ void __launch_bounds__(NTH) k_fft_cols_conv(typename C2<T>::t* lat, c
   V* res;
   stockham_lds<V, 1>(b0, b1, tw, n, plan.radix, plan.npass, W, threadIdx.x, blockDim.x, &res);
   V* fr = res == b0 ? b1 : b0;               // free buffer: two [n][TC] halves
-  const V* km = khat + (int64_t)(s * 2) * plane + c0;
+  const V* km = khat + s * kset_stride + c0;
   for (int i = threadIdx.x; i < n * TC; i += blockDim.x) {
     const int row = i / TC, col = i % TC;
     V o = czero<V>();
@@ -2040,18 +2042,18 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     auto rows_f = d.rows_nth == 1024 ? k_fft_rows<T, 1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, 1, 512>
                                                                                    : k_fft_rows<T, 1, 256>;
     hipLaunchKernelGGL(rows_f, dim3(d.na, nbatch), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
-                       (int64_t)d.Pb, d.nb, d.Pb, plane);
+                       (int64_t)d.Pb, d.nb, d.Pb, plane, (int64_t)0);
     int TC = TCP;
     if (d.fft_variant == 1) {
       // fused column transforms + spectral product + inverse column transforms
       size_t shc = 4 * (size_t)d.pa.n * TC * sizeof(V);
       auto conv = d.cols_nth == 512 ? k_fft_cols_conv<T, 512> : k_fft_cols_conv<T, 256>;
       hipLaunchKernelGGL(conv, dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(d.cols_nth), shc, st, lat,
-                         (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na);
+                         (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na, 2 * plane);
     } else {
       size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
       hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st, lat,
-                         (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa);
+                         (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa, (int64_t)0);
     }
   }
   mark(3);
@@ -2066,12 +2068,12 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     if (d.fft_variant != 1)
       hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(256), shc, st,
                          lat,
-                         (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na);
+                         (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na, (int64_t)0);
     size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
     auto rows_i = d.rows_nth == 1024 ? k_fft_rows<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, -1, 512>
                                                                                     : k_fft_rows<T, -1, 256>;
     hipLaunchKernelGGL(rows_i, dim3(d.na, nrhs * 2), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
-                       (int64_t)d.Pb, d.Pb, d.nb, 2 * plane);
+                       (int64_t)d.Pb, d.Pb, d.nb, 2 * plane, (int64_t)0);
   }
   mark(5);
   if (lattice_only) return hipGetLastError();   // the caller evaluates the field itself
@@ -2174,6 +2176,54 @@ template hipError_t launch_apply<double>(const DevView<double>&, const void*, vo
 template hipError_t launch_apply<float>(const DevView<float>&, const void*, void*, int, void*, hipStream_t,
                                         hipEvent_t*, bool);
 
+// Transforms along one axis of a multi-dimensional array (3-D face
+// lattices): `lines` launches contiguous lines (grid nlines x nbatch x nz),
+// `strided` launches columns of an nrows x ncols slab in tiles of TC columns
+// (grid tiles x nbatch x nz); precision from `dbl`, direction from `dir`.
+hipError_t launch_fft_lines(bool dbl, int dir, void* data, const void* tw, const FftPlan& plan, int64_t line_stride,
+                            int nlines, int nload, int nstore, int64_t batch_stride, int nbatch, int64_t zstride, int nz,
+                            hipStream_t st) {
+  const dim3 g(nlines, nbatch, nz), b(256);
+  if (dbl) {
+    const size_t sh = 2 * (size_t)plan.n * sizeof(double2);
+    auto k = dir > 0 ? k_fft_rows<double, 1, 256> : k_fft_rows<double, -1, 256>;
+    hipLaunchKernelGGL(k, g, b, sh, st, (double2*)data, (const double2*)tw, plan, line_stride, nload, nstore,
+                       batch_stride, zstride);
+  } else {
+    const size_t sh = 2 * (size_t)plan.n * sizeof(float2);
+    auto k = dir > 0 ? k_fft_rows<float, 1, 256> : k_fft_rows<float, -1, 256>;
+    hipLaunchKernelGGL(k, g, b, sh, st, (float2*)data, (const float2*)tw, plan, line_stride, nload, nstore,
+                       batch_stride, zstride);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, const FftPlan& plan, int ncols, int TC,
+                              int64_t batch_stride, int nbatch, int nload, int nstore, int64_t zstride, int nz,
+                              hipStream_t st) {
+  const dim3 g(xcd_grid((ncols + TC - 1) / TC), nbatch, nz), b(256);
+  if (dbl) {
+    const size_t sh = 2 * (size_t)plan.n * TC * sizeof(double2);
+    auto k = dir > 0 ? k_fft_cols<double, 1> : k_fft_cols<double, -1>;
+    hipLaunchKernelGGL(k, g, b, sh, st, (double2*)data, (const double2*)tw, plan, ncols, TC, batch_stride, nload,
+                       nstore, zstride);
+  } else {
+    const size_t sh = 2 * (size_t)plan.n * TC * sizeof(float2);
+    auto k = dir > 0 ? k_fft_cols<float, 1> : k_fft_cols<float, -1>;
+    hipLaunchKernelGGL(k, g, b, sh, st, (float2*)data, (const float2*)tw, plan, ncols, TC, batch_stride, nload,
+                       nstore, zstride);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_conv_strided(void* data, const void* tw, const void* khat, const FftPlan& plan, int ncols,
+                                   int TC, int64_t plane, int na, int nsets, hipStream_t st) {
+  const size_t sh = 4 * (size_t)plan.n * TC * sizeof(float2);
+  hipLaunchKernelGGL((k_fft_cols_conv<float, 256>), dim3(xcd_grid((ncols + TC - 1) / TC), nsets), dim3(256), sh, st,
+                     (float2*)data, (const float2*)tw, (const float2*)khat, plan, ncols, TC, plane, na, (int64_t)0);
+  return hipGetLastError();
+}
+
 hipError_t set_fft_lds_limits(size_t bytes) {
   hipError_t e = hipSuccess;
   auto set = [&](const void* f) {
@@ -2208,12 +2258,12 @@ hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int 
   const int64_t plane = (int64_t)d.Pa * d.Pb;
   size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
   hipLaunchKernelGGL((k_fft_rows<double, 1, 256>), dim3(d.Pa, nbatch), dim3(256), sh, st, (V*)data, (const V*)d.twb,
-                     d.pb, (int64_t)d.Pb, d.Pb, d.Pb, plane);
+                     d.pb, (int64_t)d.Pb, d.Pb, d.Pb, plane, (int64_t)0);
   int TC = d.tc;
   size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
   hipLaunchKernelGGL((k_fft_cols<double, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st,
                      (V*)data,
-                     (const V*)d.twa, d.pa, d.Pb, TC, plane, d.Pa, d.Pa);
+                     (const V*)d.twa, d.pa, d.Pb, TC, plane, d.Pa, d.Pa, (int64_t)0);
   return hipGetLastError();
 }
 

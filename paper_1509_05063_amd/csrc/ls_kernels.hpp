@@ -91,6 +91,20 @@ hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int 
 // interior point, -(boundary ordinal + 1) of a boundary-patch point).
 hipError_t launch_fold_rows(const DevView<double>& a, const DevView<float>& b, const int64_t* olen,
                             const int32_t* pt_cell, const int32_t* pt_idx, hipStream_t st);
+// One-axis transforms of multi-dimensional arrays (3-D face lattices).
+hipError_t launch_fft_lines(bool dbl, int dir, void* data, const void* tw, const FftPlan& plan, int64_t line_stride,
+                            int nlines, int nload, int nstore, int64_t batch_stride, int nbatch, int64_t zstride, int nz,
+                            hipStream_t st);
+hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, const FftPlan& plan, int ncols, int TC,
+                              int64_t batch_stride, int nbatch, int nload, int nstore, int64_t zstride, int nz,
+                              hipStream_t st);
+// Fused transform of the strided axis, spectral product and inverse
+// transform, single precision: nsets sets of [2 kinds][nrows][ncols] spaced
+// 2 plane apart, one kernel-spectra pair [2][plane] shared by all sets; rows
+// < na are read and, in kind 0, written back
+hipError_t launch_fft_conv_strided(void* data, const void* tw, const void* khat, const FftPlan& plan, int ncols,
+                                   int TC, int64_t plane, int na, int nsets, hipStream_t st);
+FftPlan make_fft_plan(int n);
 hipError_t set_fft_lds_limits(size_t bytes);
 
 // GMRES building blocks (double complex)
