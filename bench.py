@@ -207,6 +207,7 @@ def conv3d_run(reps):
     L = SPHERE_LATTICE
     c = binding.Conv3D(L["na"], L["nb"], L["nc"], L["hn"], L["ht"], L["kappa"], L["nsets"])
     Pa, Pb, Pc = c.padded
+    sched = c.autotune()
     g = torch.Generator(device="cuda").manual_seed(1509)
     sig = torch.randn(L["nsets"], 2, L["na"], L["nb"], L["nc"], dtype=torch.complex64, device="cuda", generator=g)
     fld = torch.empty(L["nsets"], L["na"], L["nb"], L["nc"], dtype=torch.complex64, device="cuda")
@@ -230,7 +231,9 @@ def conv3d_run(reps):
            "frac": round(pgbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(pbyts), "avg_ms": round(ms, 4),
            "textbook_bytes": int(byts), "textbook_gbs": round(gbs, 1), "textbook_frac": round(gbs / PEAK_HBM_GBS, 4),
            "lattice": f"{L['nsets']} sets x {L['na']}x{L['nb']}x{L['nc']} padded to {Pa}x{Pb}x{Pc}",
-           "workspace_gb": c.ws_bytes / 1e9}
+           "workspace_gb": c.ws_bytes / 1e9,
+           "schedule": {"normal_tile": sched[0], "normal_threads": sched[1], "second_tile": sched[2],
+                        "plane_skew": sched[3]}}
     c.close()
     return out
 

@@ -349,21 +349,24 @@ const char* ls_last_error(void);
  * with G(r) = exp(i kappa r) / (4 pi r) and D = dG(|x - y|)/dy along the
  * normal axis (the K(0) = 0 convention), computed by zero-padded FFTs
  * (padded sizes next 2^i 3^j 5^k >= 2n - 1; spectra computed once in double
- * and kept in single precision).  Single precision (LS_C64) only.  Only
- * this step of the 3-D method is built.
+ * and kept in single precision, one octant of each: the monopole spectrum is
+ * even per axis, the dipole one odd along the normal axis and even along the
+ * other two).  Single precision (LS_C64) only.  Only this step of the 3-D
+ * method is built.
  * ------------------------------------------------------------------------ */
 typedef struct ls_conv3d ls_conv3d;
 
-/* LS_EINVAL for non-positive sizes, spacings or kappa, or lattices whose
- * padded sizes exceed what one workgroup transforms in LDS (Pc <= 2048,
- * Pb <= 256 tangential, Pa <= 128 normal); LS_ENOMEM / LS_EDEVICE on device
- * failures.  Synchronous (uses the null stream once). */
+/* LS_EINVAL for non-positive sizes, spacings or kappa, nsets > 1024, or
+ * lattices whose padded sizes exceed what one workgroup transforms in LDS
+ * (Pc <= 2048, Pb <= 512 tangential, Pa <= 128 normal); LS_ENOMEM /
+ * LS_EDEVICE on device failures.  Synchronous (uses the null stream once). */
 ls_status ls_conv3d_create(int na, int nb, int nc, double hn, double ht, double kappa, int nsets,
                            ls_conv3d** out);
 
 /* padded[3] = (Pa, Pb, Pc); ws_bytes = workspace one apply needs
- * (nsets * 2 * Pa * Pb * Pc complex float); resident_bytes = device memory
- * the object holds (spectra, twiddles).  Any pointer may be NULL. */
+ * (nsets * 2 * Pa * (Pb * Pc + 512) complex float: room for any plane
+ * skew); resident_bytes = device memory the object holds (spectra,
+ * twiddles).  Any pointer may be NULL. */
 ls_status ls_conv3d_info(const ls_conv3d* c, int* padded, size_t* ws_bytes, size_t* resident_bytes);
 
 /* sigma: device [nsets][2][na][nb][nc] complex float (kind 0 monopole,
@@ -372,6 +375,23 @@ ls_status ls_conv3d_info(const ls_conv3d* c, int* padded, size_t* ws_bytes, size
  * concurrent applies need separate workspaces).  Asynchronous on `stream`.
  * LS_EINVAL for null pointers or a short workspace. */
 ls_status ls_conv3d_apply(ls_conv3d* c, const void* sigma, void* field, void* ws, size_t ws_bytes, void* stream);
+
+/* Time candidate schedules of the apply on ws (cleared first) and keep the
+ * fastest: the plane skew of the workspace layout (0, 32, 64, 512 complex
+ * values of padding after each normal-axis plane), columns (4 ... 64) and
+ * threads (256, 512) per workgroup of the fused normal-axis pass, columns
+ * (4, 8, 16) per workgroup of the second-axis passes.  schedule[4] (may be
+ * NULL) receives (normal tile, threads, second tile, skew).  Synchronous on
+ * `stream`; LS_TUNE_LOG set in the environment prints every candidate's
+ * time to stderr.  The default schedule (16, 256, 8, 0) is used until this
+ * is called. */
+ls_status ls_conv3d_autotune(ls_conv3d* c, void* ws, size_t ws_bytes, void* stream, int* schedule);
+
+/* Set the schedule[4] (same order as ls_conv3d_autotune's): normal-axis
+ * tile 1 ... 64, threads 256 or 512, second-axis tile 1 ... 16 (tiles
+ * within 160 KB of LDS), skew 0 ... 512; LS_EINVAL otherwise (the schedule
+ * is then unchanged). */
+ls_status ls_conv3d_set_schedule(ls_conv3d* c, const int* schedule);
 
 void ls_conv3d_destroy(ls_conv3d* c);
 

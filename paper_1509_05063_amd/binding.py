@@ -112,6 +112,8 @@ def lib():
             "ls_conv3d_info": (C.c_int, [C.c_void_p, P(C.c_int), P(C.c_size_t), P(C.c_size_t)]),
             "ls_conv3d_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                           C.c_void_p]),
+            "ls_conv3d_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_int)]),
+            "ls_conv3d_set_schedule": (C.c_int, [C.c_void_p, P(C.c_int)]),
             "ls_conv3d_destroy": (None, [C.c_void_p]),
             "ls_targets_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, P(C.c_void_p)]),
             "ls_targets_destroy": (None, [C.c_void_p]),
@@ -260,6 +262,21 @@ class Conv3D:
             self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=sigma.device)
         _check(lib().ls_conv3d_apply(self._c, sigma.data_ptr(), field.data_ptr(), self._ws.data_ptr(),
                                      self.ws_bytes, _stream(stream)), "ls_conv3d_apply")
+
+    def autotune(self, device="cuda", stream=None):
+        """Time candidate schedules and keep the fastest; returns
+        (normal-axis tile, its threads, second-axis tile, plane skew)."""
+        import torch
+        if self._ws is None:
+            self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        sch = (C.c_int * 4)()
+        _check(lib().ls_conv3d_autotune(self._c, self._ws.data_ptr(), self.ws_bytes, _stream(stream), sch),
+               "ls_conv3d_autotune")
+        return tuple(sch)
+
+    def set_schedule(self, normal_tile, normal_threads, second_tile, skew=0):
+        sch = (C.c_int * 4)(int(normal_tile), int(normal_threads), int(second_tile), int(skew))
+        _check(lib().ls_conv3d_set_schedule(self._c, sch), "ls_conv3d_set_schedule")
 
     def close(self):
         if self._c:

@@ -421,20 +421,20 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   // LDS needed by the FFT kernels
   int lds_max = 0;
   (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device);
-  // FFT column tiles of 128 bytes per row (8 double or 16 float complex values)
   // columns per workgroup of the column transforms: default 128-byte row
-  // segments (8 double / 16 float columns), at most what 150 KB of LDS holds;
-  // ls_autotune may pick another value up to that limit
-  const int tc = std::max(1, std::min(8, (int)(150 * 1024 / (2 * (size_t)h.Pa * 16))));
-  const int tc32 = std::max(1, std::min(16, (int)(150 * 1024 / (2 * (size_t)h.Pa * 8))));
-  size_t need = std::max(2 * (size_t)h.Pb * 16, (size_t)150 * 1024);
-  if (need > 160 * 1024) {
+  // segments (8 double / 16 float columns), at most what 150 KB of LDS holds
+  // beside the staged twiddles (Pa values); ls_autotune may pick another
+  // value up to that limit.  The FFT kernels may use all 160 KB.
+  const size_t lds_cap = 150 * 1024;
+  if ((size_t)h.Pa * 16 * 3 > lds_cap || 2 * (size_t)h.Pb * 16 > 160 * 1024) {
     ls_host_destroy(hb);
     delete op;
     return fail(LS_EINVAL, "FFT line too long for one workgroup's LDS");
   }
-  if (need > 64 * 1024) {
-    hipError_t e = lsx::set_fft_lds_limits(need);
+  const int tc = std::max(1, std::min(8, (int)((lds_cap - (size_t)h.Pa * 16) / (2 * (size_t)h.Pa * 16))));
+  const int tc32 = std::max(1, std::min(16, (int)((lds_cap - (size_t)h.Pa * 8) / (2 * (size_t)h.Pa * 8))));
+  {
+    hipError_t e = lsx::set_fft_lds_limits(160 * 1024);
     if (e != hipSuccess) return cleanup(fail(LS_EDEVICE, std::string("LDS attribute: ") + hipGetErrorString(e)));
   }
   (void)lds_max;
@@ -922,7 +922,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   int best_tc = d.tc, best_fv = d.fft_variant, best_cn = d.cols_nth;
   double best = 1e30;
   for (int fv = 0; fv < 2; ++fv) {
-    const int tmax = std::max(1, (int)(150 * 1024 / (2 * (size_t)d.Pa * sizeof(T) * 2 * (fv + 1))));
+    const int tmax = (int)((150 * 1024 - d.Pa * sizeof(T) * 2) / (2 * (size_t)d.Pa * sizeof(T) * 2 * (fv + 1)));
     for (int tc : {1, 2, 4, 8, 16, 32}) {
       if (tc > tmax) break;
       for (int cn : {256, 512}) {

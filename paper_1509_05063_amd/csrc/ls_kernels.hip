@@ -370,14 +370,27 @@ __device__ __forceinline__ void dft_r(V* x) {
   }
 }
 
+// Division by a divisor d >= 1 fixed at run time, without the integer
+// divide sequence: q = floor(x m / 2^32) with m = floor((2^32 - 1) / d) + 1,
+// exact for 0 <= x with x d < 2^32 (the error x (m d - 2^32) / (d 2^32)
+// stays below 1/d), which every index here satisfies (x < 2^20, d < 2^12).
+struct FastDiv {
+  uint64_t m;
+  int d;
+  __device__ __forceinline__ explicit FastDiv(int d_) : m((uint64_t)(0xFFFFFFFFu / (unsigned)d_) + 1), d(d_) {}
+  __device__ __forceinline__ int div(int x) const { return (int)(((uint64_t)(unsigned)x * m) >> 32); }
+};
+
 template <typename V, int DIR, int R>
 __device__ __forceinline__ void stockham_pass(const V* __restrict__ src, V* __restrict__ dst, const V* __restrict__ tw,
-                                              int n, int Ns, int stride, int tid, int nthr) {
+                                              int n, int Ns, const FastDiv& fs, int tid, int nthr) {
+  const int stride = fs.d;
   const int nb = n / R;
   const int twstep = n / (Ns * R);
+  const FastDiv fn(Ns);
   for (int w = tid; w < nb * stride; w += nthr) {
-    const int j = w / stride, lane = w - j * stride;
-    const int jm = j % Ns;
+    const int j = fs.div(w), lane = w - j * stride;
+    const int jq = fn.div(j), jm = j - jq * Ns;
     V v[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -390,10 +403,33 @@ __device__ __forceinline__ void stockham_pass(const V* __restrict__ src, V* __re
       v[m] = x;
     }
     dft_r<V, DIR, R>(v);
-    const int o = (j / Ns) * Ns * R + jm;
+    const int o = jq * Ns * R + jm;
 #pragma unroll
     for (int m = 0; m < R; ++m) dst[(o + m * Ns) * stride + lane] = v[m];
   }
+}
+
+// Stage nvalid values into LDS: value i = load(i) (a global load) goes to
+// dst[slot(i)].  A thread issues the loads of U strides before it waits on
+// any: no load sits under a branch (the last strip's indices past nvalid are
+// clamped to nvalid - 1, loaded and dropped), so U loads per thread are in
+// flight at once.  zero_lds fills slots that stand for zero padding.
+template <int U, typename V, typename Ld, typename Sl>
+__device__ __forceinline__ void stage_lds(V* dst, int nvalid, Ld&& load, Sl&& slot) {
+  for (int base = threadIdx.x; base < nvalid; base += U * (int)blockDim.x) {
+    V r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = load(min(base + u * (int)blockDim.x, nvalid - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * (int)blockDim.x;
+      if (i < nvalid) dst[slot(i)] = r[u];
+    }
+  }
+}
+template <typename V, typename Sl>
+__device__ __forceinline__ void zero_lds(V* dst, int count, Sl&& slot) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[slot(i)] = czero<V>();
 }
 
 template <typename V, int DIR>
@@ -404,20 +440,21 @@ __device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, 
   V* src = buf0;
   V* dst = buf1;
   int Ns = 1;
+  const FastDiv fs(stride);
   for (int p = 0; p < npass; ++p) {
     const int R = radix[p];
     switch (R) {
-      case 2: stockham_pass<V, DIR, 2>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 3: stockham_pass<V, DIR, 3>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 4: stockham_pass<V, DIR, 4>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 5: stockham_pass<V, DIR, 5>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 6: stockham_pass<V, DIR, 6>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 8: stockham_pass<V, DIR, 8>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 9: stockham_pass<V, DIR, 9>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 10: stockham_pass<V, DIR, 10>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 12: stockham_pass<V, DIR, 12>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      case 15: stockham_pass<V, DIR, 15>(src, dst, tw, n, Ns, stride, tid, nthr); break;
-      default: stockham_pass<V, DIR, 16>(src, dst, tw, n, Ns, stride, tid, nthr); break;
+      case 2: stockham_pass<V, DIR, 2>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 3: stockham_pass<V, DIR, 3>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 4: stockham_pass<V, DIR, 4>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 5: stockham_pass<V, DIR, 5>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 6: stockham_pass<V, DIR, 6>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 8: stockham_pass<V, DIR, 8>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 9: stockham_pass<V, DIR, 9>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 10: stockham_pass<V, DIR, 10>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 12: stockham_pass<V, DIR, 12>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      case 15: stockham_pass<V, DIR, 15>(src, dst, tw, n, Ns, fs, tid, nthr); break;
+      default: stockham_pass<V, DIR, 16>(src, dst, tw, n, Ns, fs, tid, nthr); break;
     }
     __syncthreads();
     V* t = src;
@@ -442,11 +479,67 @@ __global__ void __launch_bounds__(NTH) k_fft_rows(typename C2<T>::t* data, const
   const int line = blockIdx.x;
   const int batch = blockIdx.y;
   V* x = data + blockIdx.z * zstride + batch * batch_stride + (int64_t)line * line_stride;
-  for (int i = threadIdx.x; i < plan.n; i += blockDim.x) b0[i] = i < nload ? x[i] : czero<V>();
+  const int nl = min(nload, plan.n);
+  stage_lds<8>(b0, nl, [&](int i) { return x[i]; }, [](int i) { return i; });
+  zero_lds(b0 + nl, plan.n - nl, [](int i) { return i; });
   __syncthreads();
   V* res;
   stockham_lds<V, DIR>(b0, b1, tw, plan.n, plan.radix, plan.npass, 1, threadIdx.x, blockDim.x, &res);
   for (int i = threadIdx.x; i < nstore; i += blockDim.x) x[i] = res[i];
+}
+
+// transforms of short contiguous lines, L lines per workgroup: the lines are
+// read along their length (coalesced) and interleaved in LDS with stride
+// S = L + 1 (a padding lane against bank conflicts; S = 1 for one line), so
+// the Stockham passes run over all L lines at once.  Separate source and
+// destination (they may alias: a workgroup reads its lines whole before it
+// writes them); source entries past nload are zero padding (not read),
+// destination entries past nstore are not written.  Grid: (lines / L,
+// batch, z).
+template <typename T, int DIR>
+__global__ void __launch_bounds__(256) k_fft_lines(const typename C2<T>::t* src, typename C2<T>::t* dst,
+                                                   const typename C2<T>::t* __restrict__ tw, FftPlan plan, int nlines,
+                                                   int L, int64_t s_line, int64_t s_batch, int64_t s_z, int64_t d_line,
+                                                   int64_t d_batch, int64_t d_z, int nload, int nstore) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  const int n = plan.n, S = L == 1 ? 1 : L + 1;
+  V* b0 = reinterpret_cast<V*>(smem_raw);
+  V* b1 = b0 + (size_t)n * S;
+  V* twl = b1 + (size_t)n * S;   // the twiddles, staged with the data
+  const int l0 = blockIdx.x * L;
+  const int nl = min(L, nlines - l0);
+  const V* x = src + blockIdx.z * s_z + blockIdx.y * s_batch + (int64_t)l0 * s_line;
+  // lanes l >= nl transform a copy of the last line and are not stored
+  const int ne = min(nload, n), nz = n - ne;
+  const FastDiv fe(ne);
+  stage_lds<8>(
+      b0, L * ne,
+      [&](int i) {
+        const int l = fe.div(i);
+        return x[(int64_t)min(l, nl - 1) * s_line + (i - l * ne)];
+      },
+      [&](int i) {
+        const int l = fe.div(i);
+        return (i - l * ne) * S + l;
+      });
+  if (nz > 0) {
+    const FastDiv fz(nz);
+    zero_lds(b0, L * nz, [&](int i) {
+      const int l = fz.div(i);
+      return (ne + i - l * nz) * S + l;
+    });
+  }
+  stage_lds<4>(twl, n, [&](int i) { return tw[i]; }, [](int i) { return i; });
+  __syncthreads();
+  V* res;
+  stockham_lds<V, DIR>(b0, b1, twl, n, plan.radix, plan.npass, S, threadIdx.x, blockDim.x, &res);
+  V* y = dst + blockIdx.z * d_z + blockIdx.y * d_batch + (int64_t)l0 * d_line;
+  const FastDiv fst(nstore);
+  for (int i = threadIdx.x; i < nstore * L; i += blockDim.x) {
+    const int l = fst.div(i), e = i - l * nstore;
+    if (l < nl) y[(int64_t)l * d_line + e] = res[e * S + l];
+  }
 }
 
 // XCD-aware column tiles: workgroups are dispatched round-robin over the 8
@@ -472,22 +565,128 @@ __global__ void __launch_bounds__(256) k_fft_cols(typename C2<T>::t* data, const
   extern __shared__ unsigned char smem_raw[];
   V* b0 = reinterpret_cast<V*>(smem_raw);
   V* b1 = b0 + plan.n * TC;
+  V* twl = b1 + plan.n * TC;   // the twiddles, staged with the data
   const int tile = xcd_tile((ncols + TC - 1) / TC);
   if (tile < 0) return;
   const int c0 = tile * TC;
   const int batch = blockIdx.y;
   const int tc = min(TC, ncols - c0);
   V* x = data + blockIdx.z * zstride + batch * batch_stride + c0;
-  for (int i = threadIdx.x; i < plan.n * TC; i += blockDim.x) {
-    int row = i / TC, col = i % TC;
-    b0[i] = (col < tc && row < nload) ? x[(int64_t)row * ncols + col] : czero<V>();
+  // columns col >= tc (last tile) transform copies of column tc - 1 and are
+  // not stored; rows >= nload are zero padding
+  const int nr = min(nload, plan.n);
+  const FastDiv ft(TC);
+  stage_lds<8>(
+      b0, nr * TC,
+      [&](int i) {
+        const int row = ft.div(i), col = i - row * TC;
+        return x[(int64_t)row * ncols + min(col, tc - 1)];
+      },
+      [](int i) { return i; });
+  zero_lds(b0 + nr * TC, (plan.n - nr) * TC, [](int i) { return i; });
+  stage_lds<4>(twl, plan.n, [&](int i) { return tw[i]; }, [](int i) { return i; });
+  __syncthreads();
+  V* res;
+  stockham_lds<V, DIR>(b0, b1, twl, plan.n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res);
+  for (int i = threadIdx.x; i < nstore * TC; i += blockDim.x) {
+    const int row = ft.div(i), col = i - row * TC;
+    if (col < tc) x[(int64_t)row * ncols + col] = res[i];
+  }
+}
+
+// The fused pass along the normal axis of the 3-D face lattices: as
+// k_fft_cols_conv (forward transform of both kinds of a TC-column tile,
+// spectral product, inverse transform, rows < na of kind 0 written back),
+// with the kernel spectra read from one octant.  The monopole kernel
+// lattice is even in each axis offset and the dipole one odd in the normal
+// offset and even in the other two, so their spectra are even per axis,
+// except the dipole's, odd along the normal axis: the entry at frequency
+// (ka, kb, kc) is that at (min(ka, Pa - ka), min(kb, Pb - kb), min(kc, Pc -
+// kc)) in khs [2][Pa/2 + 1][Pb/2 + 1][Pc/2 + 1], the dipole's negated when
+// ka > Pa / 2.  Rows (normal-axis planes) are rstride >= Pb Pc apart, a
+// kind's array vol; grid: (tiles, sets), set s at lat + 2 s vol.
+template <typename T, int NTH>
+__global__ void __launch_bounds__(NTH) k_fft_conv_octant(typename C2<T>::t* lat, const typename C2<T>::t* __restrict__ tw,
+                                                         const typename C2<T>::t* __restrict__ khs, FftPlan plan,
+                                                         int Pb, int Pc, int TC, int64_t rstride, int64_t vol, int na) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  const int n = plan.n, W = 2 * TC, ncols = Pb * Pc;
+  const int hb = Pb / 2 + 1, hc = Pc / 2 + 1;
+  const int64_t hsz = (int64_t)(n / 2 + 1) * hb * hc;
+  V* b0 = reinterpret_cast<V*>(smem_raw);   // [n][2 TC]: monopole columns, then dipole columns
+  V* b1 = b0 + (size_t)n * W;
+  V* twl = b1 + (size_t)n * W;               // the twiddles, staged with the data
+  const int tile = xcd_tile((ncols + TC - 1) / TC);
+  if (tile < 0) return;
+  const int c0 = tile * TC;
+  const int tc = min(TC, ncols - c0);
+  V* mp = lat + (int64_t)blockIdx.y * 2 * vol + c0;
+  // columns col >= tc (last tile) transform copies of column tc - 1 and
+  // give zero products (not stored); rows >= na are zero padding
+  const int nr = min(na, n);
+  const FastDiv fw(W), ft(TC);
+  stage_lds<8>(
+      b0, nr * W,
+      [&](int i) {
+        const int row = fw.div(i), cc = i - row * W, kind = cc >= TC, col = cc - kind * TC;
+        return mp[kind * vol + (int64_t)row * rstride + min(col, tc - 1)];
+      },
+      [](int i) { return i; });
+  zero_lds(b0 + nr * W, (n - nr) * W, [](int i) { return i; });
+  stage_lds<4>(twl, n, [&](int i) { return tw[i]; }, [](int i) { return i; });
+  // octant entry of product entry i (row = normal frequency, column
+  // within the tile; columns past tc read a valid entry, their product is 0)
+  const FastDiv fpc(Pc);
+  auto kidx = [&](int i) {
+    const int row = ft.div(i), cg = c0 + min(i - row * TC, tc - 1), kb = fpc.div(cg), kc = cg - kb * Pc;
+    const int ma = row <= n - row ? row : n - row, mb = kb <= Pb - kb ? kb : Pb - kb,
+              mc = kc <= Pc - kc ? kc : Pc - kc;
+    return ((int64_t)ma * hb + mb) * hc + mc;
+  };
+  // the spectra of this thread's first KP product entries, loaded now so
+  // they arrive during the forward transform
+  constexpr int KP = 8;
+  const int np = n * TC;
+  V pg[KP], pd[KP];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int64_t k = kidx(min((int)threadIdx.x + u * NTH, np - 1));
+    pg[u] = khs[k];
+    pd[u] = khs[hsz + k];
   }
   __syncthreads();
   V* res;
-  stockham_lds<V, DIR>(b0, b1, tw, plan.n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res);
-  for (int i = threadIdx.x; i < nstore * TC; i += blockDim.x) {
-    int row = i / TC, col = i % TC;
-    if (col < tc) x[(int64_t)row * ncols + col] = res[i];
+  stockham_lds<V, 1>(b0, b1, twl, n, plan.radix, plan.npass, W, threadIdx.x, blockDim.x, &res);
+  V* fr = res == b0 ? b1 : b0;               // free buffer: two [n][TC] halves
+  auto product = [&](int i, V g, V d) {
+    const int row = ft.div(i), col = i - row * TC;
+    V o = czero<V>();
+    if (col < tc) {
+      if (row > n - row) {   // the dipole spectrum is odd along the normal axis
+        d.x = -d.x;
+        d.y = -d.y;
+      }
+      o = cmul(res[row * W + col], g);
+      o = cfma(res[row * W + TC + col], d, o);
+    }
+    fr[i] = o;
+  };
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int i = threadIdx.x + u * NTH;
+    if (i < np) product(i, pg[u], pd[u]);
+  }
+  for (int i = threadIdx.x + KP * NTH; i < np; i += NTH) {
+    const int64_t k = kidx(i);
+    product(i, khs[k], khs[hsz + k]);
+  }
+  __syncthreads();
+  V* res2;
+  stockham_lds<V, -1>(fr, fr + (size_t)n * TC, twl, n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res2);
+  for (int i = threadIdx.x; i < na * TC; i += blockDim.x) {
+    const int row = ft.div(i), col = i - row * TC;
+    if (col < tc) mp[(int64_t)row * rstride + col] = res2[i];
   }
 }
 
@@ -508,26 +707,64 @@ __global__ void __launch_bounds__(NTH) k_fft_cols_conv(typename C2<T>::t* lat, c
   const int n = plan.n, W = 2 * TC;
   V* b0 = reinterpret_cast<V*>(smem_raw);   // [n][2 TC]: monopole columns, then dipole columns
   V* b1 = b0 + (size_t)n * W;
+  V* twl = b1 + (size_t)n * W;               // the twiddles, staged with the data
   const int tile = xcd_tile((ncols + TC - 1) / TC);
   if (tile < 0) return;
   const int c0 = tile * TC;
   const int s = blockIdx.y & 1, r = blockIdx.y >> 1;
   const int tc = min(TC, ncols - c0);
   V* mp = lat + ((int64_t)(r * 2 + s) * 2) * plane + c0;
-  for (int i = threadIdx.x; i < n * W; i += blockDim.x) {
-    const int row = i / W, cc = i % W, kind = cc / TC, col = cc % TC;
-    b0[i] = (col < tc && row < na) ? mp[kind * plane + (int64_t)row * ncols + col] : czero<V>();
+  // columns col >= tc (last tile) transform copies of column tc - 1 and
+  // give zero products (not stored); rows >= na are zero padding
+  const int nr = min(na, n);
+  const FastDiv fw(W), ft(TC);
+  stage_lds<8>(
+      b0, nr * W,
+      [&](int i) {
+        const int row = fw.div(i), cc = i - row * W, kind = cc >= TC, col = cc - kind * TC;
+        return mp[kind * plane + (int64_t)row * ncols + min(col, tc - 1)];
+      },
+      [](int i) { return i; });
+  zero_lds(b0 + nr * W, (n - nr) * W, [](int i) { return i; });
+  stage_lds<4>(twl, n, [&](int i) { return tw[i]; }, [](int i) { return i; });
+  // the spectra of this thread's first KP product entries, loaded now so
+  // they arrive during the forward transform
+  constexpr int KP = sizeof(T) == 4 ? 8 : 4;
+  const int np = n * TC;
+  const V* km = khat + s * kset_stride + c0;
+  auto kidx = [&](int i) {
+    const int row = ft.div(i), col = i - row * TC;
+    return (int64_t)row * ncols + min(col, tc - 1);
+  };
+  V pg[KP], pd[KP];
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int64_t k = kidx(min((int)threadIdx.x + u * NTH, np - 1));
+    pg[u] = km[k];
+    pd[u] = km[plane + k];
   }
   __syncthreads();
   V* res;
-  stockham_lds<V, 1>(b0, b1, tw, n, plan.radix, plan.npass, W, threadIdx.x, blockDim.x, &res);
+  stockham_lds<V, 1>(b0, b1, twl, n, plan.radix, plan.npass, W, threadIdx.x, blockDim.x, &res);
   V* fr = res == b0 ? b1 : b0;               // free buffer: two [n][TC] halves
-  const V* km = khat + s * kset_stride + c0;
-  for (int i = threadIdx.x; i < n * TC; i += blockDim.x) {
-    const int row = i / TC, col = i % TC;
+#pragma unroll
+  for (int u = 0; u < KP; ++u) {
+    const int i = threadIdx.x + u * NTH;
+    if (i < np) {
+      const int row = ft.div(i), col = i - row * TC;
+      V o = czero<V>();
+      if (col < tc) {
+        o = cmul(res[row * W + col], pg[u]);
+        o = cfma(res[row * W + TC + col], pd[u], o);
+      }
+      fr[i] = o;
+    }
+  }
+  for (int i = threadIdx.x + KP * NTH; i < np; i += NTH) {
+    const int row = ft.div(i), col = i - row * TC;
     V o = czero<V>();
     if (col < tc) {
-      const int64_t k = (int64_t)row * ncols + col;
+      const int64_t k = kidx(i);
       o = cmul(res[row * W + col], km[k]);
       o = cfma(res[row * W + TC + col], km[plane + k], o);
     }
@@ -535,9 +772,9 @@ __global__ void __launch_bounds__(NTH) k_fft_cols_conv(typename C2<T>::t* lat, c
   }
   __syncthreads();
   V* res2;
-  stockham_lds<V, -1>(fr, fr + (size_t)n * TC, tw, n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res2);
+  stockham_lds<V, -1>(fr, fr + (size_t)n * TC, twl, n, plan.radix, plan.npass, TC, threadIdx.x, blockDim.x, &res2);
   for (int i = threadIdx.x; i < na * TC; i += blockDim.x) {
-    const int row = i / TC, col = i % TC;
+    const int row = ft.div(i), col = i - row * TC;
     if (col < tc) mp[(int64_t)row * ncols + col] = res2[i];
   }
 }
@@ -2046,12 +2283,12 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     int TC = TCP;
     if (d.fft_variant == 1) {
       // fused column transforms + spectral product + inverse column transforms
-      size_t shc = 4 * (size_t)d.pa.n * TC * sizeof(V);
+      size_t shc = (4 * (size_t)TC + 1) * d.pa.n * sizeof(V);
       auto conv = d.cols_nth == 512 ? k_fft_cols_conv<T, 512> : k_fft_cols_conv<T, 256>;
       hipLaunchKernelGGL(conv, dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(d.cols_nth), shc, st, lat,
                          (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na, 2 * plane);
     } else {
-      size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
+      size_t shc = (2 * (size_t)TC + 1) * d.pa.n * sizeof(V);
       hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st, lat,
                          (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa, (int64_t)0);
     }
@@ -2064,7 +2301,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   {
     // inverse transforms of kind 0 of each set: batch stride 2 planes
     int TC = TCP;
-    size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
+    size_t shc = (2 * (size_t)TC + 1) * d.pa.n * sizeof(V);
     if (d.fft_variant != 1)
       hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(256), shc, st,
                          lat,
@@ -2177,23 +2414,27 @@ template hipError_t launch_apply<float>(const DevView<float>&, const void*, void
                                         hipEvent_t*, bool);
 
 // Transforms along one axis of a multi-dimensional array (3-D face
-// lattices): `lines` launches contiguous lines (grid nlines x nbatch x nz),
-// `strided` launches columns of an nrows x ncols slab in tiles of TC columns
-// (grid tiles x nbatch x nz); precision from `dbl`, direction from `dir`.
-hipError_t launch_fft_lines(bool dbl, int dir, void* data, const void* tw, const FftPlan& plan, int64_t line_stride,
-                            int nlines, int nload, int nstore, int64_t batch_stride, int nbatch, int64_t zstride, int nz,
-                            hipStream_t st) {
-  const dim3 g(nlines, nbatch, nz), b(256);
+// lattices): `lines` transforms contiguous lines, several per workgroup
+// (grid lines / L x nbatch x nz), from src to dst; `strided` transforms
+// columns of an nrows x ncols slab in tiles of TC columns (grid tiles x
+// nbatch x nz); precision from `dbl`, direction from `dir`.
+int fft_lines_per_group(bool dbl, int n) { return std::max(1, std::min(16, (dbl ? 1024 : 2048) / n)); }
+
+hipError_t launch_fft_lines(bool dbl, int dir, const void* src, void* dst, const void* tw, const FftPlan& plan,
+                            int nlines, int64_t s_line, int64_t s_batch, int64_t s_z, int64_t d_line, int64_t d_batch,
+                            int64_t d_z, int nbatch, int nz, int nload, int nstore, hipStream_t st) {
+  const int L = fft_lines_per_group(dbl, plan.n), S = L == 1 ? 1 : L + 1;
+  const dim3 g((nlines + L - 1) / L, nbatch, nz), b(256);
   if (dbl) {
-    const size_t sh = 2 * (size_t)plan.n * sizeof(double2);
-    auto k = dir > 0 ? k_fft_rows<double, 1, 256> : k_fft_rows<double, -1, 256>;
-    hipLaunchKernelGGL(k, g, b, sh, st, (double2*)data, (const double2*)tw, plan, line_stride, nload, nstore,
-                       batch_stride, zstride);
+    const size_t sh = (2 * (size_t)S + 1) * plan.n * sizeof(double2);
+    auto k = dir > 0 ? k_fft_lines<double, 1> : k_fft_lines<double, -1>;
+    hipLaunchKernelGGL(k, g, b, sh, st, (const double2*)src, (double2*)dst, (const double2*)tw, plan, nlines, L,
+                       s_line, s_batch, s_z, d_line, d_batch, d_z, nload, nstore);
   } else {
-    const size_t sh = 2 * (size_t)plan.n * sizeof(float2);
-    auto k = dir > 0 ? k_fft_rows<float, 1, 256> : k_fft_rows<float, -1, 256>;
-    hipLaunchKernelGGL(k, g, b, sh, st, (float2*)data, (const float2*)tw, plan, line_stride, nload, nstore,
-                       batch_stride, zstride);
+    const size_t sh = (2 * (size_t)S + 1) * plan.n * sizeof(float2);
+    auto k = dir > 0 ? k_fft_lines<float, 1> : k_fft_lines<float, -1>;
+    hipLaunchKernelGGL(k, g, b, sh, st, (const float2*)src, (float2*)dst, (const float2*)tw, plan, nlines, L,
+                       s_line, s_batch, s_z, d_line, d_batch, d_z, nload, nstore);
   }
   return hipGetLastError();
 }
@@ -2203,12 +2444,12 @@ hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, con
                               hipStream_t st) {
   const dim3 g(xcd_grid((ncols + TC - 1) / TC), nbatch, nz), b(256);
   if (dbl) {
-    const size_t sh = 2 * (size_t)plan.n * TC * sizeof(double2);
+    const size_t sh = (2 * (size_t)TC + 1) * plan.n * sizeof(double2);
     auto k = dir > 0 ? k_fft_cols<double, 1> : k_fft_cols<double, -1>;
     hipLaunchKernelGGL(k, g, b, sh, st, (double2*)data, (const double2*)tw, plan, ncols, TC, batch_stride, nload,
                        nstore, zstride);
   } else {
-    const size_t sh = 2 * (size_t)plan.n * TC * sizeof(float2);
+    const size_t sh = (2 * (size_t)TC + 1) * plan.n * sizeof(float2);
     auto k = dir > 0 ? k_fft_cols<float, 1> : k_fft_cols<float, -1>;
     hipLaunchKernelGGL(k, g, b, sh, st, (float2*)data, (const float2*)tw, plan, ncols, TC, batch_stride, nload,
                        nstore, zstride);
@@ -2216,11 +2457,12 @@ hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, con
   return hipGetLastError();
 }
 
-hipError_t launch_fft_conv_strided(void* data, const void* tw, const void* khat, const FftPlan& plan, int ncols,
-                                   int TC, int64_t plane, int na, int nsets, hipStream_t st) {
-  const size_t sh = 4 * (size_t)plan.n * TC * sizeof(float2);
-  hipLaunchKernelGGL((k_fft_cols_conv<float, 256>), dim3(xcd_grid((ncols + TC - 1) / TC), nsets), dim3(256), sh, st,
-                     (float2*)data, (const float2*)tw, (const float2*)khat, plan, ncols, TC, plane, na, (int64_t)0);
+hipError_t launch_fft_conv_octant(void* data, const void* tw, const void* khs, const FftPlan& plan, int Pb, int Pc,
+                                  int TC, int nth, int64_t rstride, int64_t vol, int na, int nsets, hipStream_t st) {
+  const size_t sh = (4 * (size_t)TC + 1) * plan.n * sizeof(float2);
+  auto k = nth == 512 ? k_fft_conv_octant<float, 512> : k_fft_conv_octant<float, 256>;
+  hipLaunchKernelGGL(k, dim3(xcd_grid((Pb * Pc + TC - 1) / TC), nsets), dim3(nth == 512 ? 512 : 256), sh, st,
+                     (float2*)data, (const float2*)tw, (const float2*)khs, plan, Pb, Pc, TC, rstride, vol, na);
   return hipGetLastError();
 }
 
@@ -2250,6 +2492,12 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_cols_conv<float, 256>);
   set((const void*)k_fft_cols_conv<double, 512>);
   set((const void*)k_fft_cols_conv<float, 512>);
+  set((const void*)k_fft_lines<double, 1>);
+  set((const void*)k_fft_lines<double, -1>);
+  set((const void*)k_fft_lines<float, 1>);
+  set((const void*)k_fft_lines<float, -1>);
+  set((const void*)k_fft_conv_octant<float, 256>);
+  set((const void*)k_fft_conv_octant<float, 512>);
   return e;
 }
 
@@ -2260,7 +2508,7 @@ hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int 
   hipLaunchKernelGGL((k_fft_rows<double, 1, 256>), dim3(d.Pa, nbatch), dim3(256), sh, st, (V*)data, (const V*)d.twb,
                      d.pb, (int64_t)d.Pb, d.Pb, d.Pb, plane, (int64_t)0);
   int TC = d.tc;
-  size_t shc = 2 * (size_t)d.pa.n * TC * sizeof(V);
+  size_t shc = (2 * (size_t)TC + 1) * d.pa.n * sizeof(V);
   hipLaunchKernelGGL((k_fft_cols<double, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st,
                      (V*)data,
                      (const V*)d.twa, d.pa, d.Pb, TC, plane, d.Pa, d.Pa, (int64_t)0);

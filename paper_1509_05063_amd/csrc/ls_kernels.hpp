@@ -92,18 +92,20 @@ hipError_t launch_fft_kernels_forward(const DevView<double>& d, void* data, int 
 hipError_t launch_fold_rows(const DevView<double>& a, const DevView<float>& b, const int64_t* olen,
                             const int32_t* pt_cell, const int32_t* pt_idx, hipStream_t st);
 // One-axis transforms of multi-dimensional arrays (3-D face lattices).
-hipError_t launch_fft_lines(bool dbl, int dir, void* data, const void* tw, const FftPlan& plan, int64_t line_stride,
-                            int nlines, int nload, int nstore, int64_t batch_stride, int nbatch, int64_t zstride, int nz,
-                            hipStream_t st);
+int fft_lines_per_group(bool dbl, int n);
+hipError_t launch_fft_lines(bool dbl, int dir, const void* src, void* dst, const void* tw, const FftPlan& plan,
+                            int nlines, int64_t s_line, int64_t s_batch, int64_t s_z, int64_t d_line, int64_t d_batch,
+                            int64_t d_z, int nbatch, int nz, int nload, int nstore, hipStream_t st);
 hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, const FftPlan& plan, int ncols, int TC,
                               int64_t batch_stride, int nbatch, int nload, int nstore, int64_t zstride, int nz,
                               hipStream_t st);
-// Fused transform of the strided axis, spectral product and inverse
-// transform, single precision: nsets sets of [2 kinds][nrows][ncols] spaced
-// 2 plane apart, one kernel-spectra pair [2][plane] shared by all sets; rows
-// < na are read and, in kind 0, written back
-hipError_t launch_fft_conv_strided(void* data, const void* tw, const void* khat, const FftPlan& plan, int ncols,
-                                   int TC, int64_t plane, int na, int nsets, hipStream_t st);
+// Fused transform along the normal axis of 3-D face lattices, spectral
+// product with octant-stored kernel spectra khs [2][Pa/2+1][Pb/2+1][Pc/2+1]
+// and inverse transform, single precision: nsets sets of [2 kinds][Pa][Pb][Pc]
+// (planes rstride >= Pb Pc apart, vol per kind); rows < na are read and, in
+// kind 0, written back
+hipError_t launch_fft_conv_octant(void* data, const void* tw, const void* khs, const FftPlan& plan, int Pb, int Pc,
+                                  int TC, int nth, int64_t rstride, int64_t vol, int na, int nsets, hipStream_t st);
 FftPlan make_fft_plan(int n);
 hipError_t set_fft_lds_limits(size_t bytes);
 

@@ -1,7 +1,8 @@
 """GPU parity of the 3-D face-lattice convolution (ls_conv3d_*, the FFT step
 of the 3-D method) against the oracle's direct sum: every node of small
-ragged lattices, sampled nodes at the sphere workload's lattice shape
-(33 x 128 x 128 per set, three sets), and the edge cases."""
+ragged lattices (default schedule), sampled nodes at the sphere workload's
+lattice shape (33 x 128 x 128 per set, three sets) under the autotuned
+schedule and under every candidate schedule, and the edge cases."""
 import numpy as np
 import pytest
 
@@ -24,7 +25,7 @@ def _run(c, sig):
 
 
 @pytest.mark.parametrize("na,nb,nc,hn,ht,kappa", [(4, 9, 7, 0.25, 0.0625, 8.0), (1, 5, 3, 0.5, 0.1, 3.0),
-                                                  (6, 4, 11, 0.1, 0.05, 25.0)])
+                                                  (6, 4, 11, 0.1, 0.05, 25.0), (2, 5, 300, 0.3, 0.01, 10.0)])
 def test_every_node_against_direct_sum(na, nb, nc, hn, ht, kappa):
     from paper_1509_05063_amd import binding
     rng = np.random.default_rng(1509 + na * 100 + nb)
@@ -53,6 +54,8 @@ def test_sphere_lattice_shape_sampled_nodes():
     c = binding.Conv3D(na, nb, nc, hn, ht, kappa, 3)
     try:
         assert c.padded == (72, 256, 256)
+        sched = c.autotune()
+        print(f"sphere lattice schedule {sched}", flush=True)
         F = _run(c, sig)
     finally:
         c.close()
@@ -65,6 +68,36 @@ def test_sphere_lattice_shape_sampled_nodes():
         assert err < 1e-4
 
 
+def test_every_schedule_sphere_lattice():
+    """Every candidate schedule (tiles that leave partial last tiles, both
+    thread counts, product entries past the prefetched ones) gives the
+    oracle's values at sampled nodes of the sphere lattices."""
+    from paper_1509_05063_amd import binding
+    H = 4 / 64
+    na, nb, nc, hn, ht, kappa = 33, 128, 128, H, H / 4, 8 * np.pi
+    rng = np.random.default_rng(77)
+    sig = _sigma(rng, 3, na, nb, nc)
+    pick = [(0, 0, 0), (na - 1, nb - 1, nc - 1), (16, 64, 64), (3, 100, 7)]
+    ref = [conv3d_at(sig[s, 0], sig[s, 1], hn, ht, kappa, pick) for s in range(3)]
+    c = binding.Conv3D(na, nb, nc, hn, ht, kappa, 3)
+    try:
+        for ta in (3, 4, 8, 16, 32, 64):
+            for nth in (256, 512):
+                for tb, sk in ((4, 0), (8, 32), (16, 512), (8, 7)):
+                    c.set_schedule(ta, nth, tb, sk)
+                    F = _run(c, sig)
+                    err = max(np.linalg.norm(np.array([F[s][p] for p in pick]) - ref[s]) / np.linalg.norm(ref[s])
+                              for s in range(3))
+                    assert err < 1e-4, (ta, nth, tb, sk, err)
+        print(f"every schedule: last sampled rel err {err:.2e}", flush=True)
+        for bad in [(0, 256, 8), (16, 128, 8), (16, 256, 0), (128, 256, 8), (16, 256, 32), (16, 256, 8, -1),
+                    (16, 256, 8, 513)]:
+            with pytest.raises(binding.LSError):
+                c.set_schedule(*bad)
+    finally:
+        c.close()
+
+
 def test_zero_input_and_bad_arguments():
     from paper_1509_05063_amd import binding
     c = binding.Conv3D(3, 8, 8, 0.2, 0.05, 5.0, 1)
@@ -74,6 +107,6 @@ def test_zero_input_and_bad_arguments():
     finally:
         c.close()
     for args in [(0, 8, 8, 0.2, 0.05, 5.0, 1), (3, 8, 8, -0.2, 0.05, 5.0, 1), (3, 8, 8, 0.2, 0.05, 0.0, 1),
-                 (3, 400, 8, 0.2, 0.05, 5.0, 1)]:
+                 (3, 400, 8, 0.2, 0.05, 5.0, 1), (3, 8, 8, 0.2, 0.05, 5.0, 2000)]:
         with pytest.raises(binding.LSError):
             binding.Conv3D(*args)
