@@ -384,7 +384,7 @@ def main():
     achieved = byts[dom] / (p32[dom] * 1e-3) / 1e9
     kname = STAGE_KERNEL.get(dom, dom)
     if tune and dom == "near_csr":
-        kname = {0: "k_near_csr4", 1: "k_near_csr<float,float2,unsigned short>", 2: "k_near_csr4r", 3: "k_near_blk<4>"}[
+        kname = {0: "k_near_csr4", 1: "k_near_csr<float,float2,unsigned short>", 2: "k_near_csr4r", 3: "k_near_csr4r"}[
             tune["fp32"]["csr_variant"]]
     if tune and dom == "near_shared":
         nv = tune["fp32"]["near_variant"]
