@@ -212,7 +212,8 @@ def conv3d_run(reps):
     sig = torch.randn(L["nsets"], 2, L["na"], L["nb"], L["nc"], dtype=torch.complex64, device="cuda", generator=g)
     fld = torch.empty(L["nsets"], L["na"], L["nb"], L["nc"], dtype=torch.complex64, device="cuda")
     st = torch.cuda.current_stream()
-    c.apply(sig, fld)
+    for _ in range(reps):       # untimed: a cold GPU's clocks ramp up over the first milliseconds
+        c.apply(sig, fld)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
@@ -236,6 +237,46 @@ def conv3d_run(reps):
                         "plane_skew": sched[3]}}
     c.close()
     return out
+
+
+def fft256_run(reps):
+    """The dense 3-D complex FFT of the sphere workload's 256^3 equivalent-
+    source grid (complex float, in place): forward and inverse transforms
+    timed with HIP events on torch's current stream.  Textbook bytes per
+    transform: three one-axis passes, each reading and writing the cube."""
+    import torch
+    from paper_1509_05063_amd import binding
+    n = 256
+    f = binding.FFT3D(n, n, n)
+    g = torch.Generator(device="cuda").manual_seed(256)
+    a = torch.randn(n, n, n, dtype=torch.complex64, device="cuda", generator=g)
+    st = torch.cuda.current_stream()
+    for _ in range(reps):       # untimed: a cold GPU's clocks ramp up over the first milliseconds
+        f.exec(a, 1)
+        f.exec(a, -1)
+        a.mul_(1.0 / n ** 3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        f.exec(a, 1)
+        f.exec(a, -1)
+        a.mul_(1.0 / n ** 3)    # keep the values bounded (a scaling kernel, timed apart below)
+    e1.record(st)
+    torch.cuda.synchronize()
+    tot = e0.elapsed_time(e1)
+    e0.record(st)
+    for _ in range(reps):
+        a.mul_(1.0)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = (tot - e0.elapsed_time(e1)) / (2 * reps)
+    byts = 3 * 2 * n ** 3 * 8
+    gbs = byts / (ms * 1e-3) / 1e9
+    f.close()
+    return {"stage": "fft256", "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": byts, "avg_ms": round(ms, 4),
+            "grid": "256^3 complex float, in place, one transform (forward and inverse averaged)"}
 
 
 def main():
@@ -263,6 +304,10 @@ def main():
                     help="applies of the 3-D face-lattice convolution in its measurement (0 skips it)")
     ap.add_argument("--profile-fft3d", type=int, default=0,
                     help="profiling run: only this many 3-D face-lattice convolutions")
+    ap.add_argument("--fft256-reps", type=int, default=20,
+                    help="forward + inverse pairs of the 256^3 transform in its measurement (0 skips it)")
+    ap.add_argument("--profile-fft256", type=int, default=0,
+                    help="profiling run: only this many forward + inverse pairs of the 256^3 transform")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is not sharded across GPUs",
@@ -271,6 +316,9 @@ def main():
 
     if args.profile_fft3d:
         log(f"profile fft3d {conv3d_run(args.profile_fft3d)}")
+        return
+    if args.profile_fft256:
+        log(f"profile fft256 {fft256_run(args.profile_fft256)}")
         return
 
     import torch
@@ -406,6 +454,11 @@ def main():
         fft3d = conv3d_run(args.fft3d_reps)
         log(f"fft3d {fft3d}")
 
+    fft256 = None
+    if args.fft256_reps:
+        fft256 = fft256_run(args.fft256_reps)
+        log(f"fft256 {fft256}")
+
     multi = None
     if args.multi_rhs:
         multi = multi_rhs_run(args.multi_rhs, ortho, not args.no_autotune)
@@ -458,6 +511,7 @@ def main():
         "roofline": roof,
         "roofline_fft": roof_fft,
         "roofline_fft3d": fft3d,
+        "roofline_fft256": fft256,
         "autotune": tune,
         "multi_rhs": multi,
         "serving": serving,

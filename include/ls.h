@@ -395,6 +395,28 @@ ls_status ls_conv3d_set_schedule(ls_conv3d* c, const int* schedule);
 
 void ls_conv3d_destroy(ls_conv3d* c);
 
+/* ------------------------------------------------------------------------
+ * Dense three-dimensional complex FFT (the zero-padded equivalent-source
+ * grid of the 3-D method, Sec. 4, transformed as one cube, e.g. 256^3).
+ * In place on a device array [n0][n1][n2] of complex float (n2 fastest),
+ * unnormalised: direction +1 computes sum_x a(x) exp(-2 pi i k.x / n),
+ * direction -1 the same with exp(+2 pi i k.x / n) (so -1 after +1 returns
+ * n0 n1 n2 times the input).
+ * ------------------------------------------------------------------------ */
+typedef struct ls_fft3d ls_fft3d;
+
+/* LS_EINVAL unless every size is >= 1 with no prime factor other than 2, 3
+ * and 5, n2 <= 2048, n1 <= 1204, n0 <= 620 (one workgroup transforms a line
+ * or a column tile in LDS) and n0 n1 n2 <= 2^31; LS_ENOMEM / LS_EDEVICE on
+ * device failures.  Synchronous (twiddle upload). */
+ls_status ls_fft3d_create(int n0, int n1, int n2, ls_fft3d** out);
+
+/* Transform `data` (device, owned by the caller) in place, asynchronously on
+ * `stream`.  LS_EINVAL for a null pointer or a direction other than +1 / -1. */
+ls_status ls_fft3d_exec(ls_fft3d* f, void* data, int direction, void* stream);
+
+void ls_fft3d_destroy(ls_fft3d* f);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,9 @@ def lib():
             "ls_conv3d_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_int)]),
             "ls_conv3d_set_schedule": (C.c_int, [C.c_void_p, P(C.c_int)]),
             "ls_conv3d_destroy": (None, [C.c_void_p]),
+            "ls_fft3d_create": (C.c_int, [C.c_int, C.c_int, C.c_int, P(C.c_void_p)]),
+            "ls_fft3d_exec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+            "ls_fft3d_destroy": (None, [C.c_void_p]),
             "ls_targets_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, P(C.c_void_p)]),
             "ls_targets_destroy": (None, [C.c_void_p]),
             "ls_scattered_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
@@ -282,6 +285,33 @@ class Conv3D:
         if self._c:
             lib().ls_conv3d_destroy(self._c)
             self._c = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FFT3D:
+    """Dense in-place 3-D complex float FFT (ls_fft3d_*) of an n0 x n1 x n2
+    array, unnormalised; direction +1 forward, -1 inverse."""
+
+    def __init__(self, n0, n1, n2):
+        self._f = C.c_void_p()
+        _check(lib().ls_fft3d_create(int(n0), int(n1), int(n2), C.byref(self._f)), "ls_fft3d_create")
+        self.shape = (int(n0), int(n1), int(n2))
+
+    def exec(self, data, direction=1, stream=None):
+        import torch
+        if tuple(data.shape) != self.shape or data.dtype != torch.complex64 or not data.is_contiguous():
+            raise ValueError("contiguous complex64 tensor of the plan's shape expected")
+        _check(lib().ls_fft3d_exec(self._f, data.data_ptr(), int(direction), _stream(stream)), "ls_fft3d_exec")
+
+    def close(self):
+        if self._f:
+            lib().ls_fft3d_destroy(self._f)
+            self._f = C.c_void_p()
 
     def __del__(self):
         try:

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libls.so")
 
 HOST_SRC = ["ls_math.cpp", "ls_setup.cpp"]
-DEV_SRC = ["ls_kernels.hip", "ls_api.hip", "ls_server.hip", "ls_conv3d.hip"]
+DEV_SRC = ["ls_kernels.hip", "ls_api.hip", "ls_server.hip", "ls_conv3d.hip", "ls_fft3d.hip"]
 ARCH = "gfx950"
 
 
