@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--profile-solve", action="store_true",
                     help="profiling run: one single-precision-with-refinement solve only")
     ap.add_argument("--profile-applies", type=int, default=0,
-                    help="profiling run: only this many applies per precision plus a 512 MiB "
+                    help="profiling run: only this many staged applies per precision plus a 512 MiB "
                          "device copy (the calibration kernel for HBM byte counters)")
     ap.add_argument("--fft3d-reps", type=int, default=20,
                     help="applies of the 3-D face-lattice convolution in its measurement (0 skips it)")
@@ -343,11 +343,13 @@ def main():
         tune = {"fp32": op.autotune(1, binding.LS_C64), "fp64": op.autotune(1, binding.LS_C128)}
         log(f"autotune {time.time() - t0:.1f}s {tune}")
     if args.profile_applies:
+        # the staged apply (stages in order on one stream, as the roofline
+        # figures are timed), not the concurrent one the solves use
         for dt in (torch.complex64, torch.complex128):
             u = f.to(dt)
             v = torch.empty_like(u)
             for _ in range(args.profile_applies):
-                op.apply(u, v)
+                op.apply_profile(u, v)
             torch.cuda.synchronize()
         a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)

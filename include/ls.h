@@ -155,12 +155,17 @@ ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* byt
  * ls_workspace_size bytes) is scratch owned by the caller; applies that run
  * concurrently need distinct workspaces.  u and v must not overlap.
  * LS_C64 runs every step in single precision (weights rounded from the
- * double-precision set-up).  Errors: LS_EINVAL, LS_EDEVICE. */
+ * double-precision set-up).  The near-field correction runs on a stream of
+ * the operator's own, forked from `stream` by an event and joined back
+ * into it before the apply's last kernel (so the work enqueued on `stream`
+ * is complete exactly when the apply is; stream capture records the fork
+ * and the join).  Errors: LS_EINVAL, LS_EDEVICE. */
 ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec,
                    void* ws, size_t ws_bytes, void* stream);
 
-/* One ls_apply with HIP events recorded on `stream` between its stages;
- * waits for completion and writes the stage durations (milliseconds) to
+/* One ls_apply with its stages in order on `stream` (the near field not
+ * forked) and HIP events recorded between them; waits for completion and
+ * writes the stage durations (milliseconds) to
  * stage_ms[0..min(nstage,8)-1]: 0 projection (Sec. 3.2, equiv-conv-loc),
  * 1 face-lattice fill, 2 forward FFTs, 3 spectral product, 4 inverse FFTs,
  * 5 adjacency subtraction + cell Dirichlet fit (eq:-PWE) + combine,

@@ -165,13 +165,22 @@ void release(ls_op* op) {
   clear_graphs(op);
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
   op->cap_stream = nullptr;
+  for (hipEvent_t* e : {&op->d64.ev_fork, &op->d64.ev_join, &op->d32.ev_fork, &op->d32.ev_join}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
+  if (op->d64.side) (void)hipStreamDestroy(op->d64.side);
+  op->d64.side = op->d32.side = nullptr;
 }
 
 size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
   size_t c = prec == LS_C128 ? 16 : 8;
   const auto& d = op->d64;
   size_t Gw = (size_t)(d.L + 4) * d.ch;
-  return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb + (size_t)nrhs * Gw * Gw) + 256;
+  // projections, lattices, interior grid, near-field buffer of the
+  // concurrent near field
+  return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb + (size_t)nrhs * Gw * Gw +
+              (size_t)nrhs * op->N) + 256;
 }
 
 }  // namespace
@@ -456,6 +465,17 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   a.tc = tc;
   b.tc = tc32;
   a.kappa = b.kappa = kappa;
+  // the near field's own stream (default priority, non-blocking) and the
+  // fork / join events of the concurrent apply
+  {
+    hipStream_t side = nullptr;
+    if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess)
+      return cleanup(fail(LS_EDEVICE, "side stream"));
+    a.side = b.side = side;
+    for (hipEvent_t* e : {&a.ev_fork, &a.ev_join, &b.ev_fork, &b.ev_join})
+      if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(LS_EDEVICE, "fork / join events"));
+  }
   a.nrows = b.nrows = (int)h.rows.size();
   a.csr_f64 = true;
   b.csr_f64 = false;

@@ -2231,6 +2231,20 @@ __global__ void __launch_bounds__(256) k_targets(const typename C2<T>::t* __rest
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
+// x[i] = 0 and v[i] += x[i] over n complex values (the concurrent near
+// field's buffer: cleared by a kernel, not a memset, so that graph capture
+// records a kernel node)
+template <typename V>
+__global__ void k_zero_c(V* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = czero<V>();
+}
+template <typename V>
+__global__ void k_add_c(V* __restrict__ v, const V* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = cadd(v[i], x[i]);
+}
+
 template <typename T>
 hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs, void* ws_, hipStream_t st,
                         hipEvent_t* ev, bool lattice_only) {
@@ -2245,164 +2259,209 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   const int64_t plane = (int64_t)d.Pa * d.Pb;
   const T k2 = (T)(d.kappa * d.kappa);
   mark(0);
-  // a0 + a1
-  {
-    size_t sh = (size_t)(d.S + d.max_nb) * sizeof(V);
-    constexpr int RB = sizeof(T) == 4 ? 16 : 8;
-    const size_t shb = ((size_t)(64 + d.max_nb) * RB + (size_t)RB * 96) * sizeof(V);
-    if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
-      hipLaunchKernelGGL((k_project_rb<T, RB>), dim3(d.ncell, (nrhs + RB - 1) / RB), dim3(192), shb, st, u, sigma,
-                         (const V*)d.PshT, (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb,
-                         d.cell_boff, d.N, d.ncell, nrhs);
-    } else if (d.q == 12 && d.S == 64 && d.PshT) {
-      const size_t shm = (size_t)(96 + 64 + d.max_nb) * sizeof(V);
-      hipLaunchKernelGGL(k_project2<T>, dim3(d.ncell, nrhs), dim3(192), shm, st, u, sigma, (const V*)d.PshT,
-                         (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N,
-                         d.ncell);
-    } else {
-      hipLaunchKernelGGL(k_project<T>, dim3(d.ncell, nrhs), dim3(128), sh, st, u, sigma, (const V*)d.Psh,
-                         (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
-                         d.S, d.U, d.N, d.ncell);
+  // far field: a0 - a3 + a5 on the caller's stream (writes v)
+  auto far_field = [&]() {
+    // a0 + a1
+    {
+      size_t sh = (size_t)(d.S + d.max_nb) * sizeof(V);
+      constexpr int RB = sizeof(T) == 4 ? 16 : 8;
+      const size_t shb = ((size_t)(64 + d.max_nb) * RB + (size_t)RB * 96) * sizeof(V);
+      if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
+        hipLaunchKernelGGL((k_project_rb<T, RB>), dim3(d.ncell, (nrhs + RB - 1) / RB), dim3(192), shb, st, u, sigma,
+                           (const V*)d.PshT, (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb,
+                           d.cell_boff, d.N, d.ncell, nrhs);
+      } else if (d.q == 12 && d.S == 64 && d.PshT) {
+        const size_t shm = (size_t)(96 + 64 + d.max_nb) * sizeof(V);
+        hipLaunchKernelGGL(k_project2<T>, dim3(d.ncell, nrhs), dim3(192), shm, st, u, sigma, (const V*)d.PshT,
+                           (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N,
+                           d.ncell);
+      } else {
+        hipLaunchKernelGGL(k_project<T>, dim3(d.ncell, nrhs), dim3(128), sh, st, u, sigma, (const V*)d.Psh,
+                           (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
+                           d.S, d.U, d.N, d.ncell);
+      }
     }
-  }
-  mark(1);
-  // lattice fill
-  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)(((int64_t)d.na * d.nb + 255) / 256), 2, nrhs), dim3(256), 0, st, sigma, lat,
-                     d.cell_map, d.L, d.q, d.U, d.ncell, d.na, d.nb, d.Pa, d.Pb);
-  mark(2);
-  // a2: forward transforms of all 4 arrays per rhs
-  const int nbatch = nrhs * 4;
-  const int TCP = d.tc;   // columns per workgroup in the column transforms
-  {
-    size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
-    // rows a >= na are zero padding: their transforms stay zero
-    auto rows_f = d.rows_nth == 1024 ? k_fft_rows<T, 1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, 1, 512>
-                                                                                   : k_fft_rows<T, 1, 256>;
-    hipLaunchKernelGGL(rows_f, dim3(d.na, nbatch), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
-                       (int64_t)d.Pb, d.nb, d.Pb, plane, (int64_t)0);
-    int TC = TCP;
-    if (d.fft_variant == 1) {
-      // fused column transforms + spectral product + inverse column transforms
-      size_t shc = (4 * (size_t)TC + 1) * d.pa.n * sizeof(V);
-      auto conv = d.cols_nth == 512 ? k_fft_cols_conv<T, 512> : k_fft_cols_conv<T, 256>;
-      hipLaunchKernelGGL(conv, dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(d.cols_nth), shc, st, lat,
-                         (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na, 2 * plane);
-    } else {
-      size_t shc = (2 * (size_t)TC + 1) * d.pa.n * sizeof(V);
-      hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st, lat,
-                         (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa, (int64_t)0);
+    mark(1);
+    // lattice fill
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)(((int64_t)d.na * d.nb + 255) / 256), 2, nrhs), dim3(256), 0, st, sigma, lat,
+                       d.cell_map, d.L, d.q, d.U, d.ncell, d.na, d.nb, d.Pa, d.Pb);
+    mark(2);
+    // a2: forward transforms of all 4 arrays per rhs
+    const int nbatch = nrhs * 4;
+    const int TCP = d.tc;   // columns per workgroup in the column transforms
+    {
+      size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
+      // rows a >= na are zero padding: their transforms stay zero
+      auto rows_f = d.rows_nth == 1024 ? k_fft_rows<T, 1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, 1, 512>
+                                                                                     : k_fft_rows<T, 1, 256>;
+      hipLaunchKernelGGL(rows_f, dim3(d.na, nbatch), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
+                         (int64_t)d.Pb, d.nb, d.Pb, plane, (int64_t)0);
+      int TC = TCP;
+      if (d.fft_variant == 1) {
+        // fused column transforms + spectral product + inverse column transforms
+        size_t shc = (4 * (size_t)TC + 1) * d.pa.n * sizeof(V);
+        auto conv = d.cols_nth == 512 ? k_fft_cols_conv<T, 512> : k_fft_cols_conv<T, 256>;
+        hipLaunchKernelGGL(conv, dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(d.cols_nth), shc, st, lat,
+                           (const V*)d.twa, (const V*)d.khat, d.pa, d.Pb, TC, plane, d.na, 2 * plane);
+      } else {
+        size_t shc = (2 * (size_t)TC + 1) * d.pa.n * sizeof(V);
+        hipLaunchKernelGGL((k_fft_cols<T, 1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nbatch), dim3(256), shc, st, lat,
+                           (const V*)d.twa, d.pa, d.Pb, TC, plane, d.na, d.Pa, (int64_t)0);
+      }
     }
-  }
-  mark(3);
-  if (d.fft_variant != 1)
-    hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, lat,
-                       (const V*)d.khat, plane);
-  mark(4);
-  {
-    // inverse transforms of kind 0 of each set: batch stride 2 planes
-    int TC = TCP;
-    size_t shc = (2 * (size_t)TC + 1) * d.pa.n * sizeof(V);
+    mark(3);
     if (d.fft_variant != 1)
-      hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(256), shc, st,
-                         lat,
-                         (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na, (int64_t)0);
-    size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
-    auto rows_i = d.rows_nth == 1024 ? k_fft_rows<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, -1, 512>
-                                                                                    : k_fft_rows<T, -1, 256>;
-    hipLaunchKernelGGL(rows_i, dim3(d.na, nrhs * 2), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
-                       (int64_t)d.Pb, d.Pb, d.nb, 2 * plane, (int64_t)0);
-  }
-  mark(5);
-  if (lattice_only) return hipGetLastError();   // the caller evaluates the field itself
-  // a3 + a5
-  {
-    if (d.q == 12 && d.S == 64 && nrhs >= 16) {
-      hipLaunchKernelGGL(k_interp_rb<T>, dim3(d.ncell, (nrhs + 15) / 16), dim3(256), 0, st, u, v, (const V*)lat,
-                         (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start, d.cell_nint,
-                         d.cell_nb, d.cell_boff, d.Pa, d.Pb, d.N, d.nband, nrhs, k2);
-    } else if (d.q == 12 && d.S == 64) {
-      constexpr int CB = 16;
-      const size_t shm = (size_t)CB * 48 * sizeof(V) + 2 * CB * sizeof(int);
-      hipLaunchKernelGGL((k_interp_mfma<T, CB>), dim3((d.ncell + CB - 1) / CB, nrhs), dim3(256), shm, st, u, v,
-                         (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
-                         d.cell_nint, d.cell_nb, d.cell_boff, d.ncell, d.Pa, d.Pb, d.N, d.nband, k2);
-    } else {
-      hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), (size_t)d.F * sizeof(V), st, u, v,
-                         (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
-                         d.cell_nint, d.cell_nb, d.cell_boff, d.q, d.F, d.S, d.Pa, d.Pb, d.N, d.nband, k2);
+      hipLaunchKernelGGL(k_spectral<T>, dim3((unsigned)((plane + 255) / 256), 2, nrhs), dim3(256), 0, st, lat,
+                         (const V*)d.khat, plane);
+    mark(4);
+    {
+      // inverse transforms of kind 0 of each set: batch stride 2 planes
+      int TC = TCP;
+      size_t shc = (2 * (size_t)TC + 1) * d.pa.n * sizeof(V);
+      if (d.fft_variant != 1)
+        hipLaunchKernelGGL((k_fft_cols<T, -1>), dim3(xcd_grid((d.Pb + TC - 1) / TC), nrhs * 2), dim3(256), shc, st,
+                           lat,
+                           (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na, (int64_t)0);
+      size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
+      auto rows_i = d.rows_nth == 1024 ? k_fft_rows<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, -1, 512>
+                                                                                      : k_fft_rows<T, -1, 256>;
+      hipLaunchKernelGGL(rows_i, dim3(d.na, nrhs * 2), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
+                         (int64_t)d.Pb, d.Pb, d.nb, 2 * plane, (int64_t)0);
     }
-  }
-  mark(6);
-  // a4 shared
-  if (d.ch == 8) {
-    const int Gw = (d.L + 4) * 8;
-    V* grid = lat + (size_t)nrhs * 4 * plane;
-    const int64_t gsz = (int64_t)Gw * Gw;
-    hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, st, u, grid, d.dw,
-                       d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
-    if (std::is_same<T, float>::value && d.near_variant != 1) {
-      const int CT = d.near_variant == 2 ? 2 : d.near_variant == 3 ? 4 : 1;
-      const dim3 gr((d.nicell + 16 * CT - 1) / (16 * CT), nrhs), bl(256 * CT);
-      if (CT == 1)
-        hipLaunchKernelGGL(k_near_shared_mfma_db<1>, gr, bl, 0, st, (const float2*)grid, (float2*)v,
-                           (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
-      else if (CT == 2)
-        hipLaunchKernelGGL(k_near_shared_mfma_db<2>, gr, bl, 0, st, (const float2*)grid, (float2*)v,
-                           (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
-      else
-        hipLaunchKernelGGL(k_near_shared_mfma_db<4>, gr, bl, 0, st, (const float2*)grid, (float2*)v,
-                           (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
-    } else {
-      constexpr int NT = 2;
-      hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs), dim3(256),
-                         0, st, (const V*)grid, v, (const V*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell,
-                         d.N, k2);
+    mark(5);
+    if (lattice_only) return;   // the caller evaluates the field itself
+    // a3 + a5
+    {
+      if (d.q == 12 && d.S == 64 && nrhs >= 16) {
+        hipLaunchKernelGGL(k_interp_rb<T>, dim3(d.ncell, (nrhs + 15) / 16), dim3(256), 0, st, u, v, (const V*)lat,
+                           (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start, d.cell_nint,
+                           d.cell_nb, d.cell_boff, d.Pa, d.Pb, d.N, d.nband, nrhs, k2);
+      } else if (d.q == 12 && d.S == 64) {
+        constexpr int CB = 16;
+        const size_t shm = (size_t)CB * 48 * sizeof(V) + 2 * CB * sizeof(int);
+        hipLaunchKernelGGL((k_interp_mfma<T, CB>), dim3((d.ncell + CB - 1) / CB, nrhs), dim3(256), shm, st, u, v,
+                           (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
+                           d.cell_nint, d.cell_nb, d.cell_boff, d.ncell, d.Pa, d.Pb, d.N, d.nband, k2);
+      } else {
+        hipLaunchKernelGGL(k_interp<T>, dim3(d.ncell, nrhs), dim3(256), (size_t)d.F * sizeof(V), st, u, v,
+                           (const V*)lat, (const V*)d.Ish, (const V*)d.Ibd, d.cell_xy, d.slot_map, d.cell_start,
+                           d.cell_nint, d.cell_nb, d.cell_boff, d.q, d.F, d.S, d.Pa, d.Pb, d.N, d.nband, k2);
+      }
     }
+  };
+  if (lattice_only) {
+    far_field();
+    return hipGetLastError();
+  }
+  // a4 between interior nodes, into vt on stream ns
+  auto near_shared = [&](hipStream_t ns, V* vt) {
+    if (d.ch == 8) {
+      const int Gw = (d.L + 4) * 8;
+      V* grid = lat + (size_t)nrhs * 4 * plane;
+      const int64_t gsz = (int64_t)Gw * Gw;
+      hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, ns, u, grid, d.dw,
+                         d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
+      if (std::is_same<T, float>::value && d.near_variant != 1) {
+        const int CT = d.near_variant == 2 ? 2 : d.near_variant == 3 ? 4 : 1;
+        const dim3 gr((d.nicell + 16 * CT - 1) / (16 * CT), nrhs), bl(256 * CT);
+        if (CT == 1)
+          hipLaunchKernelGGL(k_near_shared_mfma_db<1>, gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
+                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
+        else if (CT == 2)
+          hipLaunchKernelGGL(k_near_shared_mfma_db<2>, gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
+                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
+        else
+          hipLaunchKernelGGL(k_near_shared_mfma_db<4>, gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
+                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
+      } else {
+        constexpr int NT = 2;
+        hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs), dim3(256),
+                           0, ns, (const V*)grid, vt, (const V*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell,
+                           d.N, k2);
+      }
+    } else {
+      constexpr int CT = 16, KC = 32;
+      size_t sh = (size_t)(d.S * KC + KC * CT) * sizeof(V) + 25 * CT * sizeof(int);
+      hipLaunchKernelGGL((k_near_shared<T, CT, KC>), dim3((d.nicell + CT - 1) / CT, nrhs), dim3(256), sh, ns, u, vt,
+                         (const V*)d.Wsh, d.dw, d.icells, d.cell_xy, d.cell_map, d.slot_map, d.L, d.ch, d.S,
+                         d.nicell, d.N, k2);
+    }
+  };
+  // a4 rows of the boundary patch, into vt on stream ns
+  auto near_rows = [&](hipStream_t ns, V* vt) {
+    if (d.nrows > 0) {
+      const dim3 g((d.nrows + 3) / 4), b(256);
+      if (d.csr_f64) {
+        if (d.coloff)
+          hipLaunchKernelGGL((k_near_csr<T, double2, uint16_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
+                             d.coloff, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
+        else
+          hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
+                             d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
+      } else {
+        // dense tiles: right-hand-side-major input copied into the lattice
+        // region (free after the interpolation; large enough, checked here)
+        const bool blk = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant == 3 && nrhs % 16 == 0 &&
+                         (int64_t)4 * plane >= d.N;
+        if (blk) {
+          float2* ut = (float2*)lat;
+          hipLaunchKernelGGL(k_rhs_major, dim3((unsigned)((d.N + 31) / 32), (nrhs + 31) / 32), dim3(256), 0, ns,
+                             (const float2*)u, ut, d.N, nrhs);
+          constexpr int NT = 4;
+          const int64_t waves = (int64_t)d.bt_ntiles * ((nrhs + 16 * NT - 1) / (16 * NT));
+          hipLaunchKernelGGL(k_near_blk<NT>, dim3((unsigned)((waves + 3) / 4)), b, 0, ns, (const float2*)ut,
+                             (float2*)vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
+                             d.bt_ntiles, d.N, nrhs, (float)k2);
+        } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
+          hipLaunchKernelGGL(k_near_csr4r, g, b, 0, ns, (const float2*)u, (float2*)vt, d.rowptr, d.rows, d.run_ptr,
+                             d.run_cs, d.run_pre, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
+        else if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
+          hipLaunchKernelGGL(k_near_csr4, g, b, 0, ns, (const float2*)u, (float2*)vt, d.rowptr, d.rows, d.colbase,
+                             d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
+        else if (d.coloff)
+          hipLaunchKernelGGL((k_near_csr<T, float2, uint16_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
+                             d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+        else
+          hipLaunchKernelGGL((k_near_csr<T, float2, int32_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
+                             d.cols32, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+      }
+    }
+  };
+  // The far field (projection through interpolation, which writes v) and the
+  // near field touch disjoint workspace regions and read only u, so unless
+  // the stages are being timed one by one, the near field runs concurrently
+  // on the side stream into a cleared buffer after the interior grid, added
+  // into v once both are done.  (Measured: the interior near field on the
+  // caller's stream after the interpolation instead slows the concurrent
+  // rows more than it shortens the side stream.)  The dense-tile form
+  // borrows the lattice region and stays on the caller's stream after the
+  // far field.
+  const bool blk_rows = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant == 3 && nrhs % 16 == 0;
+  const bool fork = d.side && !ev && !blk_rows;
+  const int64_t nv = d.N * nrhs;
+  const unsigned nvb = (unsigned)((nv + 255) / 256);
+  V* vn = lat + (size_t)nrhs * 4 * plane + (size_t)nrhs * ((size_t)(d.L + 4) * d.ch) * ((size_t)(d.L + 4) * d.ch);
+  if (fork) {
+    // cleared before the fork: on the side stream the clear would queue
+    // behind the projection's workgroups and delay the whole near field
+    hipLaunchKernelGGL(k_zero_c<V>, dim3(nvb), dim3(256), 0, st, vn, nv);
+    hipError_t e = hipEventRecord(d.ev_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(d.side, d.ev_fork, 0);
+    if (e != hipSuccess) return e;
+    near_shared(d.side, vn);
+    near_rows(d.side, vn);
+    if ((e = hipEventRecord(d.ev_join, d.side)) != hipSuccess) return e;
+  }
+  far_field();
+  if (fork) {
+    hipError_t e = hipStreamWaitEvent(st, d.ev_join, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_add_c<V>, dim3(nvb), dim3(256), 0, st, v, (const V*)vn, nv);
   } else {
-    constexpr int CT = 16, KC = 32;
-    size_t sh = (size_t)(d.S * KC + KC * CT) * sizeof(V) + 25 * CT * sizeof(int);
-    hipLaunchKernelGGL((k_near_shared<T, CT, KC>), dim3((d.nicell + CT - 1) / CT, nrhs), dim3(256), sh, st, u, v,
-                       (const V*)d.Wsh, d.dw, d.icells, d.cell_xy, d.cell_map, d.slot_map, d.L, d.ch, d.S,
-                       d.nicell, d.N, k2);
-  }
-  mark(7);
-  // a4 csr
-  if (d.nrows > 0) {
-    const dim3 g((d.nrows + 3) / 4), b(256);
-    if (d.csr_f64) {
-      if (d.coloff)
-        hipLaunchKernelGGL((k_near_csr<T, double2, uint16_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
-                           d.coloff, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
-      else
-        hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
-                           d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
-    } else {
-      // dense tiles: right-hand-side-major input copied into the lattice
-      // region (free after the interpolation; large enough, checked here)
-      const bool blk = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant == 3 && nrhs % 16 == 0 &&
-                       (int64_t)4 * plane >= d.N;
-      if (blk) {
-        float2* ut = (float2*)lat;
-        hipLaunchKernelGGL(k_rhs_major, dim3((unsigned)((d.N + 31) / 32), (nrhs + 31) / 32), dim3(256), 0, st,
-                           (const float2*)u, ut, d.N, nrhs);
-        constexpr int NT = 4;
-        const int64_t waves = (int64_t)d.bt_ntiles * ((nrhs + 16 * NT - 1) / (16 * NT));
-        hipLaunchKernelGGL(k_near_blk<NT>, dim3((unsigned)((waves + 3) / 4)), b, 0, st, (const float2*)ut,
-                           (float2*)v, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
-                           d.bt_ntiles, d.N, nrhs, (float)k2);
-      } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
-        hipLaunchKernelGGL(k_near_csr4r, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.run_ptr,
-                           d.run_cs, d.run_pre, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
-      else if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
-        hipLaunchKernelGGL(k_near_csr4, g, b, 0, st, (const float2*)u, (float2*)v, d.rowptr, d.rows, d.colbase,
-                           d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
-      else if (d.coloff)
-        hipLaunchKernelGGL((k_near_csr<T, float2, uint16_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
-                           d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
-      else
-        hipLaunchKernelGGL((k_near_csr<T, float2, int32_t>), g, b, 0, st, u, v, d.rowptr, d.rows, d.colbase,
-                           d.cols32, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
-    }
+    mark(6);
+    near_shared(st, v);
+    mark(7);
+    near_rows(st, v);
   }
   mark(8);
   return hipGetLastError();

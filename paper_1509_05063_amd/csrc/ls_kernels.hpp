@@ -58,6 +58,13 @@ struct DevView {
   const int32_t *bt_rows = nullptr, *bt_info = nullptr, *bt_cols = nullptr;
   const int64_t* bt_woff = nullptr;
   const void* bt_w = nullptr;
+  // Concurrent near field: when set, an apply that is not being profiled
+  // runs the near-field kernels on `side` (forked from the caller's stream
+  // at ev_fork, accumulating into a workspace buffer) while the far field
+  // runs on the caller's stream, and joins at ev_join before adding the
+  // buffer into v.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   FftPlan pa{}, pb{};
 };
 
