@@ -186,13 +186,14 @@ def conv3d_textbook_bytes(Pa, Pb, Pc, nsets):
 def conv3d_pass_bytes(na, nb, nc, Pa, Pb, Pc, nsets):
     """Bytes the implemented passes have to move (complex float): padding
     rows are neither read nor written.  Per array (2 nsets: both kinds of
-    every set) pad, lines along c, columns along b; per set the fused pass
-    along a (both kinds' na rows and the two spectra in, kind 0's na rows
-    out), then columns along b, lines along c and unpad of kind 0."""
+    every set) lines along c read straight from the compact strengths, then
+    columns along b; per set the fused pass along a (both kinds' na rows and
+    the two spectra in, kind 0's na rows out), then columns along b and lines
+    along c written straight into the compact field (kind 0)."""
     e = 8
-    fwd = (2 * na * nb * nc) + (na * nb * nc + na * nb * Pc) + (na * nb * Pc + na * Pb * Pc)
+    fwd = (na * nb * nc + na * nb * Pc) + (na * nb * Pc + na * Pb * Pc)
     conv = 2 * na * Pb * Pc + 2 * Pa * Pb * Pc + na * Pb * Pc
-    inv = (na * Pb * Pc + na * nb * Pc) + (na * nb * Pc + na * nb * nc) + 2 * na * nb * nc
+    inv = (na * Pb * Pc + na * nb * Pc) + (na * nb * Pc + na * nb * nc)
     return e * (2 * nsets * fwd + nsets * (conv + inv))
 
 
