@@ -3,7 +3,8 @@
 // (Sec. 4) transformed as one cube rather than per face-lattice set.  Three
 // one-axis passes with the Stockham kernels of the face-lattice
 // convolution: lines along the contiguous axis n2 (several per workgroup),
-// 8-column tiles along n1, 16-column tiles along n0.
+// 8-column tiles along n1 (16 for a 256-point axis), 16-column tiles along
+// n0.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -73,8 +74,12 @@ ls_status ls_fft3d_exec(ls_fft3d* f, void* data, int direction, void* stream) {
   const int64_t plane = (int64_t)n1 * n2;
   hipError_t e = lsx::launch_fft_lines(false, direction, data, data, f->tw[2], f->plan[2], n1, n2, plane, 0, n2,
                                        plane, 0, n0, 1, n2, n2, st);
+  // 16-column tiles where the middle axis is two radix-16 passes (one LDS
+  // buffer: 256 butterflies per pass for 256 threads), else 8
+  const bool r16 = f->plan[1].npass == 2 && f->plan[1].radix[0] == 16 && f->plan[1].radix[1] == 16;
   if (e == hipSuccess)
-    e = lsx::launch_fft_strided(false, direction, data, f->tw[1], f->plan[1], n2, 8, plane, n0, n1, n1, 0, 1, st);
+    e = lsx::launch_fft_strided(false, direction, data, f->tw[1], f->plan[1], n2, r16 ? 16 : 8, plane, n0, n1, n1, 0,
+                                1, st);
   if (e == hipSuccess)
     e = lsx::launch_fft_strided(false, direction, data, f->tw[0], f->plan[0], (int)plane, 16, 0, 1, n0, n0, 0, 1, st);
   return e == hipSuccess ? LS_OK : LS_EDEVICE;

@@ -690,6 +690,70 @@ __global__ void __launch_bounds__(NTH) k_fft_conv_octant(typename C2<T>::t* lat,
   }
 }
 
+// Column transforms of length n = R1 R2 (two Stockham passes) without
+// staging: the first pass reads its R1 inputs per column straight from
+// memory (rows past nload are zero padding: clamped loads, zeroed), writes
+// the intermediate to one LDS buffer; after one barrier the second pass
+// (twiddles from LDS) writes rows < nstore straight back.  Same grid,
+// arguments and results as k_fft_cols, half its LDS and none of its staging
+// copies.
+template <int DIR, int R1, int R2>
+__global__ void __launch_bounds__(256) k_fft_cols2(float2* data, const float2* __restrict__ tw, int ncols, int TC,
+                                                   int64_t batch_stride, int nload, int nstore, int64_t zstride) {
+  using V = float2;
+  constexpr int n = R1 * R2;
+  extern __shared__ unsigned char smem_raw[];
+  V* buf = reinterpret_cast<V*>(smem_raw);   // [n][TC]
+  V* twl = buf + (size_t)n * TC;              // [n] twiddles
+  const int tile = xcd_tile((ncols + TC - 1) / TC);
+  if (tile < 0) return;
+  const int c0 = tile * TC;
+  const int tc = min(TC, ncols - c0);
+  V* x = data + blockIdx.z * zstride + blockIdx.y * batch_stride + c0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) twl[i] = tw[i];
+  const FastDiv ft(TC);
+  const int nl = min(nload, n);
+  // pass 1 (span 1): column lane, butterfly j reads rows j + m R2
+  for (int w = threadIdx.x; w < R2 * TC; w += blockDim.x) {
+    const int j = ft.div(w), lane = w - j * TC, col = min(lane, tc - 1);
+    V v[R1];
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const int row = j + m * R2;
+      const V t = x[(int64_t)min(row, nl - 1) * ncols + col];
+      v[m] = row < nl ? t : czero<V>();
+    }
+    dft_r<V, DIR, R1>(v);
+#pragma unroll
+    for (int m = 0; m < R1; ++m) buf[(j * R1 + m) * TC + lane] = v[m];
+  }
+  __syncthreads();
+  // pass 2 (span R1): butterfly j < R1 reads rows j + m R1, twiddles
+  // W_n^(j m), writes rows j + m R1
+  for (int w = threadIdx.x; w < R1 * TC; w += blockDim.x) {
+    const int j = ft.div(w), lane = w - j * TC;
+    V v[R2];
+#pragma unroll
+    for (int m = 0; m < R2; ++m) {
+      V t = buf[(j + m * R1) * TC + lane];
+      if (m > 0 && j > 0) {
+        V wv = twl[j * m];
+        if (DIR < 0) wv.y = -wv.y;
+        t = cmul(t, wv);
+      }
+      v[m] = t;
+    }
+    dft_r<V, DIR, R2>(v);
+    if (lane < tc) {
+#pragma unroll
+      for (int m = 0; m < R2; ++m) {
+        const int row = j + m * R1;
+        if (row < nstore) x[(int64_t)row * ncols + lane] = v[m];
+      }
+    }
+  }
+}
+
 // Column transforms, spectral product and inverse column transform in one
 // workgroup per TC-column tile of one set: the tile's monopole and dipole
 // columns are transformed together (2 TC interleaved columns), multiplied by
@@ -2507,6 +2571,11 @@ hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, con
     auto k = dir > 0 ? k_fft_cols<double, 1> : k_fft_cols<double, -1>;
     hipLaunchKernelGGL(k, g, b, sh, st, (double2*)data, (const double2*)tw, plan, ncols, TC, batch_stride, nload,
                        nstore, zstride);
+  } else if (plan.npass == 2 && plan.radix[0] == 16 && plan.radix[1] == 16) {
+    const size_t sh = ((size_t)TC + 1) * plan.n * sizeof(float2);
+    auto k = dir > 0 ? k_fft_cols2<1, 16, 16> : k_fft_cols2<-1, 16, 16>;
+    hipLaunchKernelGGL(k, g, b, sh, st, (float2*)data, (const float2*)tw, ncols, TC, batch_stride, nload, nstore,
+                       zstride);
   } else {
     const size_t sh = (2 * (size_t)TC + 1) * plan.n * sizeof(float2);
     auto k = dir > 0 ? k_fft_cols<float, 1> : k_fft_cols<float, -1>;
@@ -2557,6 +2626,8 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_lines<float, -1>);
   set((const void*)k_fft_conv_octant<float, 256>);
   set((const void*)k_fft_conv_octant<float, 512>);
+  set((const void*)k_fft_cols2<1, 16, 16>);
+  set((const void*)k_fft_cols2<-1, 16, 16>);
   return e;
 }
 
