@@ -690,6 +690,70 @@ __global__ void __launch_bounds__(NTH) k_fft_conv_octant(typename C2<T>::t* lat,
   }
 }
 
+// Lines of n = R1 R2 points (two Stockham passes) without staging: 16
+// threads per line (one per butterfly), 16 lines per workgroup.  The first
+// pass reads its R1 inputs straight from memory (for each of them the 16
+// threads of a line read 16 consecutive points: coalesced; points past
+// nload are zero), writes the intermediate to LDS with a span of R1 + 1 per
+// R1 values (no bank conflicts), and after one barrier the second pass
+// writes points < nstore straight to the destination.  Same arguments and
+// results as k_fft_lines.  Requires R1 == R2 == 16.
+template <int DIR, int R1, int R2>
+__global__ void __launch_bounds__(256) k_fft_lines2(const float2* src, float2* dst, const float2* __restrict__ tw,
+                                                    int nlines, int64_t s_line, int64_t s_batch, int64_t s_z,
+                                                    int64_t d_line, int64_t d_batch, int64_t d_z, int nload,
+                                                    int nstore) {
+  static_assert(R1 == 16 && R2 == 16, "one thread per butterfly of each pass");
+  using V = float2;
+  constexpr int n = R1 * R2, TPL = 16, L = 256 / TPL, SPAN = R2 * (R1 + 1);
+  extern __shared__ unsigned char smem_raw[];
+  V* buf = reinterpret_cast<V*>(smem_raw);   // [L][R2][R1 + 1]
+  V* twl = buf + (size_t)L * SPAN;           // [n] twiddles
+  for (int i = threadIdx.x; i < n; i += blockDim.x) twl[i] = tw[i];
+  const int l = threadIdx.x / TPL, j = threadIdx.x % TPL;
+  const int l0 = blockIdx.x * L;
+  const int nl = min(L, nlines - l0);
+  const int lc = min(l, nl - 1);             // lines past the last: a copy of it, not stored
+  const V* x = src + blockIdx.z * s_z + blockIdx.y * s_batch + (int64_t)(l0 + lc) * s_line;
+  const int ne = min(nload, n);
+  V* b = buf + l * SPAN;
+  {
+    V v[R1];
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const int e = j + m * R2;
+      const V t = x[min(e, ne - 1)];
+      v[m] = e < ne ? t : czero<V>();
+    }
+    dft_r<V, DIR, R1>(v);
+#pragma unroll
+    for (int m = 0; m < R1; ++m) b[j * (R1 + 1) + m] = v[m];
+  }
+  __syncthreads();
+  {
+    V v[R2];
+#pragma unroll
+    for (int m = 0; m < R2; ++m) {
+      V t = b[m * (R1 + 1) + j];   // intermediate row j + m R1
+      if (m > 0 && j > 0) {
+        V wv = twl[j * m];
+        if (DIR < 0) wv.y = -wv.y;
+        t = cmul(t, wv);
+      }
+      v[m] = t;
+    }
+    dft_r<V, DIR, R2>(v);
+    if (l < nl) {
+      V* y = dst + blockIdx.z * d_z + blockIdx.y * d_batch + (int64_t)(l0 + l) * d_line;
+#pragma unroll
+      for (int m = 0; m < R2; ++m) {
+        const int e = j + m * R1;
+        if (e < nstore) y[e] = v[m];
+      }
+    }
+  }
+}
+
 // Column transforms of length n = R1 R2 (two Stockham passes) without
 // staging: the first pass reads its R1 inputs per column straight from
 // memory (rows past nload are zero padding: clamped loads, zeroed), writes
@@ -2553,6 +2617,11 @@ hipError_t launch_fft_lines(bool dbl, int dir, const void* src, void* dst, const
     auto k = dir > 0 ? k_fft_lines<double, 1> : k_fft_lines<double, -1>;
     hipLaunchKernelGGL(k, g, b, sh, st, (const double2*)src, (double2*)dst, (const double2*)tw, plan, nlines, L,
                        s_line, s_batch, s_z, d_line, d_batch, d_z, nload, nstore);
+  } else if (plan.npass == 2 && plan.radix[0] == 16 && plan.radix[1] == 16) {
+    const size_t sh = ((size_t)16 * 16 * 17 + 256) * sizeof(float2);
+    auto k = dir > 0 ? k_fft_lines2<1, 16, 16> : k_fft_lines2<-1, 16, 16>;
+    hipLaunchKernelGGL(k, dim3((nlines + 15) / 16, nbatch, nz), b, sh, st, (const float2*)src, (float2*)dst,
+                       (const float2*)tw, nlines, s_line, s_batch, s_z, d_line, d_batch, d_z, nload, nstore);
   } else {
     const size_t sh = (2 * (size_t)S + 1) * plan.n * sizeof(float2);
     auto k = dir > 0 ? k_fft_lines<float, 1> : k_fft_lines<float, -1>;
@@ -2627,6 +2696,8 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_conv_octant<float, 256>);
   set((const void*)k_fft_conv_octant<float, 512>);
   set((const void*)k_fft_cols2<1, 16, 16>);
+  set((const void*)k_fft_lines2<1, 16, 16>);
+  set((const void*)k_fft_lines2<-1, 16, 16>);
   set((const void*)k_fft_cols2<-1, 16, 16>);
   return e;
 }
