@@ -818,6 +818,127 @@ __global__ void __launch_bounds__(256) k_fft_cols2(float2* data, const float2* _
   }
 }
 
+// The fused normal-axis pass of k_fft_conv_octant for n = R1 R2 with two
+// Stockham passes each way, 16-column tiles (both kinds: 32 columns) and
+// 256 threads, without staging: the forward radix-R1 pass loads straight
+// from memory, the forward radix-R2 pass goes through LDS, the spectral
+// product is taken inside the inverse radix-R1 pass (its octant entries
+// loaded at entry, so they arrive during the forward transform), and the
+// inverse radix-R2 pass stores the na lattice rows straight back.  Same grid,
+// arguments and results as k_fft_conv_octant with TC = 16.
+template <int R1, int R2>
+__global__ void __launch_bounds__(256) k_fft_conv_octant2(float2* lat, const float2* __restrict__ tw,
+                                                          const float2* __restrict__ khs, int Pb, int Pc,
+                                                          int64_t rstride, int64_t vol, int na) {
+  using V = float2;
+  constexpr int n = R1 * R2, TC = 16, W = 32;
+  extern __shared__ unsigned char smem_raw[];
+  V* A = reinterpret_cast<V*>(smem_raw);     // [n][W], later [n][TC]
+  V* B = A + n * W;                          // [n][W]
+  V* twl = B + n * W;                        // [n]
+  const int ncols = Pb * Pc;
+  const int hb = Pb / 2 + 1, hc = Pc / 2 + 1;
+  const int64_t hsz = (int64_t)(n / 2 + 1) * hb * hc;
+  const int tile = xcd_tile((ncols + TC - 1) / TC);
+  if (tile < 0) return;
+  const int c0 = tile * TC;
+  const int tc = min(TC, ncols - c0);
+  V* mp = lat + (int64_t)blockIdx.y * 2 * vol + c0;
+  const int t = threadIdx.x;
+  for (int i = t; i < n; i += 256) twl[i] = tw[i];
+  // octant entries for this thread's product rows (inverse pass 1: column
+  // c = t % TC, rows j + m R2 with j = t / TC < R2)
+  V pg[R1], pd[R1];
+  {
+    const int c = t % TC, jj = min(t / TC, R2 - 1);
+    const FastDiv fpc(Pc);
+    const int cg = c0 + min(c, tc - 1), kb = fpc.div(cg), kc = cg - kb * Pc;
+    const int mb = kb <= Pb - kb ? kb : Pb - kb, mc = kc <= Pc - kc ? kc : Pc - kc;
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const int row = jj + m * R2, ma = row <= n - row ? row : n - row;
+      const int64_t k = ((int64_t)ma * hb + mb) * hc + mc;
+      pg[m] = khs[k];
+      pd[m] = khs[hsz + k];
+    }
+  }
+  const int nr = min(na, n);
+  // forward pass 1 (radix R1, span 1): butterfly j < R2 of column lane
+  if (t < R2 * W) {
+    const int j = t / W, lane = t % W, kind = lane / TC, col = min(lane % TC, tc - 1);
+    V v[R1];
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const int row = j + m * R2;
+      const V x = mp[kind * vol + (int64_t)min(row, nr - 1) * rstride + col];
+      v[m] = row < nr ? x : czero<V>();
+    }
+    dft_r<V, 1, R1>(v);
+#pragma unroll
+    for (int m = 0; m < R1; ++m) A[(j * R1 + m) * W + lane] = v[m];
+  }
+  __syncthreads();
+  // forward pass 2 (radix R2, span R1): butterfly j < R1
+  for (int w = t; w < R1 * W; w += 256) {
+    const int j = w / W, lane = w % W;
+    V v[R2];
+#pragma unroll
+    for (int m = 0; m < R2; ++m) {
+      V x = A[(j + m * R1) * W + lane];
+      if (m > 0 && j > 0) x = cmul(x, twl[j * m]);
+      v[m] = x;
+    }
+    dft_r<V, 1, R2>(v);
+#pragma unroll
+    for (int m = 0; m < R2; ++m) B[(j + m * R1) * W + lane] = v[m];
+  }
+  __syncthreads();
+  // spectral product and inverse pass 1 (radix R1, span 1): butterfly j < R2
+  // of column c; the dipole spectrum is odd along the normal axis
+  if (t < R2 * TC) {
+    const int j = t / TC, c = t % TC;
+    V v[R1];
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const int row = j + m * R2;
+      V d = pd[m];
+      if (row > n - row) {
+        d.x = -d.x;
+        d.y = -d.y;
+      }
+      V o = cmul(B[row * W + c], pg[m]);
+      v[m] = cfma(B[row * W + TC + c], d, o);
+    }
+    dft_r<V, -1, R1>(v);
+#pragma unroll
+    for (int m = 0; m < R1; ++m) A[(j * R1 + m) * TC + c] = v[m];
+  }
+  __syncthreads();
+  // inverse pass 2 (radix R2, span R1): butterfly j < R1; rows < na stored
+  if (t < R1 * TC) {
+    const int j = t / TC, c = t % TC;
+    V v[R2];
+#pragma unroll
+    for (int m = 0; m < R2; ++m) {
+      V x = A[(j + m * R1) * TC + c];
+      if (m > 0 && j > 0) {
+        V wv = twl[j * m];
+        wv.y = -wv.y;
+        x = cmul(x, wv);
+      }
+      v[m] = x;
+    }
+    dft_r<V, -1, R2>(v);
+    if (c < tc) {
+#pragma unroll
+      for (int m = 0; m < R2; ++m) {
+        const int row = j + m * R1;
+        if (row < nr) mp[(int64_t)row * rstride + c] = v[m];
+      }
+    }
+  }
+}
+
 // Column transforms, spectral product and inverse column transform in one
 // workgroup per TC-column tile of one set: the tile's monopole and dipole
 // columns are transformed together (2 TC interleaved columns), multiplied by
@@ -2656,6 +2777,12 @@ hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, con
 
 hipError_t launch_fft_conv_octant(void* data, const void* tw, const void* khs, const FftPlan& plan, int Pb, int Pc,
                                   int TC, int nth, int64_t rstride, int64_t vol, int na, int nsets, hipStream_t st) {
+  if (TC == 16 && nth == 256 && plan.npass == 2 && plan.radix[0] == 12 && plan.radix[1] == 6) {
+    const size_t sh2 = (2 * 32 + 1) * (size_t)plan.n * sizeof(float2);
+    hipLaunchKernelGGL((k_fft_conv_octant2<12, 6>), dim3(xcd_grid((Pb * Pc + 15) / 16), nsets), dim3(256), sh2, st,
+                       (float2*)data, (const float2*)tw, (const float2*)khs, Pb, Pc, rstride, vol, na);
+    return hipGetLastError();
+  }
   const size_t sh = (4 * (size_t)TC + 1) * plan.n * sizeof(float2);
   auto k = nth == 512 ? k_fft_conv_octant<float, 512> : k_fft_conv_octant<float, 256>;
   hipLaunchKernelGGL(k, dim3(xcd_grid((Pb * Pc + TC - 1) / TC), nsets), dim3(nth == 512 ? 512 : 256), sh, st,
