@@ -1,4 +1,4 @@
-"""CPU checks of two facts the transform kernels rely on.
+"""CPU checks of three facts the transform kernels rely on.
 
 1. Division by a run-time divisor d as q = floor(x m / 2^32) with
    m = floor((2^32 - 1) / d) + 1 is exact whenever x d < 2^32 (the FFT
@@ -12,6 +12,10 @@
    normal-axis pass reads only that octant).  Built from the oracle's own
    kernel functions and numpy's FFT on small ragged lattices, odd and even
    padded sizes.
+3. The index map of the register-first two-pass transforms (radix R1 then
+   radix R2, intermediate rows j R1 + m, twiddles W^(j m)) is the DFT, for
+   the 16 x 16 and 12 x 6 splits the kernels instantiate and the reverse
+   order.
 """
 import numpy as np
 
@@ -82,3 +86,32 @@ def test_kernel_spectra_octant_symmetry():
         assert np.abs(Dh - sign * Dh[ma, mb, mc]).max() < 1e-12 * np.abs(Dh).max()
         # the dipole really is odd along the normal axis (not trivially even)
         assert np.abs(Dh - Dh[ma, mb, mc]).max() > 1e-3 * np.abs(Dh).max()
+
+
+def _two_pass(x, R1, R2, sign):
+    """The index map of the register-first two-pass kernels: pass 1
+    (radix R1) butterfly j < R2 takes rows j + m R2 and leaves its outputs at
+    intermediate rows j R1 + m; pass 2 (radix R2) butterfly j < R1 takes
+    rows j + m R1, multiplies entry m by W_n^(j m), and writes rows
+    j + m R1 of the result."""
+    n = R1 * R2
+    w = np.exp(sign * 2j * np.pi * np.arange(n) / n)
+    mid = np.empty(n, complex)
+    for j in range(R2):
+        v = x[[j + m * R2 for m in range(R1)]]
+        f = np.array([sum(v[a] * np.exp(sign * 2j * np.pi * a * b / R1) for a in range(R1)) for b in range(R1)])
+        mid[[j * R1 + m for m in range(R1)]] = f
+    out = np.empty(n, complex)
+    for j in range(R1):
+        v = mid[[j + m * R1 for m in range(R2)]] * w[[j * m for m in range(R2)]]
+        f = np.array([sum(v[a] * np.exp(sign * 2j * np.pi * a * b / R2) for a in range(R2)) for b in range(R2)])
+        out[[j + m * R1 for m in range(R2)]] = f
+    return out
+
+
+def test_two_pass_index_map_is_the_dft():
+    rng = np.random.default_rng(5)
+    for R1, R2 in [(16, 16), (12, 6), (6, 12)]:
+        x = rng.standard_normal(R1 * R2) + 1j * rng.standard_normal(R1 * R2)
+        assert np.abs(_two_pass(x, R1, R2, -1) - np.fft.fft(x)).max() < 1e-9
+        assert np.abs(_two_pass(x, R1, R2, 1) - np.fft.ifft(x) * x.size).max() < 1e-9
