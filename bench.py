@@ -85,24 +85,87 @@ def counter_traffic(kernel, summary=os.path.join(ROOT, "profiles", "apply_star_k
     return None
 
 
-def cpu_oracle_rate(cfg, n2, budget_s=20.0):
-    """Oracle rows per second on a bounded sample of targets (single thread)."""
+def host_cpu():
+    """Host CPU model and the threads the oracle legs use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_oracle_rate(cfg, n2, budget_s=15.0, x_ref=None, f_ref=None, key_lib=None):
+    """Oracle rows per second on a bounded sample of targets, the rows
+    spread over the host's cores (numpy releases the interpreter lock inside
+    its array kernels, so threads run the rows side by side).  With the
+    double-precision reference solution x_ref (library order, keys key_lib)
+    and its right-hand side f_ref, the same rows also give the oracle's
+    residual A x_ref - f on them (relative to max |f|)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from oracle.op2d import Setup2D
+    from paper_1509_05063_amd.inputs import match_keys
     t0 = time.time()
     orc = Setup2D(cfg, n2)
     log(f"oracle discretisation {time.time() - t0:.1f}s, N={orc.N}")
+    x_or = f_or = None
+    if x_ref is not None:
+        p = match_keys(orc.pts["key"], key_lib)
+        x_or, f_or = x_ref[p], f_ref[p]
     rng = np.random.default_rng(1509)
     rows = rng.choice(orc.N, 4096, replace=False)
-    u = np.ones(orc.N, complex)
-    done = 0
+    _, nth = host_cpu()
+    deadline = time.time() + budget_s
+    res = {}
+
+    def work(chunk):
+        out = []
+        for i in chunk:
+            if time.time() > deadline:
+                break
+            row = orc.A_rows([int(i)])[0]
+            out.append((int(i), row @ x_or - f_or[i] if x_or is not None else row.sum()))
+        return out
+
     t0 = time.time()
-    for i in rows:
-        orc.K_row(int(i)) @ u
-        done += 1
-        if time.time() - t0 > budget_s:
-            break
+    with ThreadPoolExecutor(nth) as ex:
+        for part in ex.map(work, np.array_split(rows, nth)):
+            res.update(part)
     dt = time.time() - t0
-    return done / dt, done, orc.N
+    resid = None
+    if x_or is not None and res:
+        resid = max(abs(v) for v in res.values()) / np.abs(f_or).max()
+    return len(res) / dt, len(res), orc.N, nth, resid
+
+
+def cpu_disc_oracle():
+    """The oracle on the 4k-unknown disc: the dense operator built row by
+    row (one thread: these short rows are interpreter-bound, threads slow
+    them down), one matvec with it (ZGEMV, BLAS threads) and the dense LU
+    solve."""
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd.inputs import config, n2_function, plane_wave
+    cfg = config("disc_k2pi")
+    orc = Setup2D(cfg, n2_function(cfg))
+    _, nth = host_cpu()
+    t0 = time.time()
+    A = orc.dense_A()
+    t_build = time.time() - t0
+    f = plane_wave(cfg, orc.pts["x"], 0.0)
+    t0 = time.time()
+    for _ in range(5):
+        A @ f
+    t_mv = (time.time() - t0) / 5
+    t0 = time.time()
+    np.linalg.solve(A, f)
+    t_lu = time.time() - t0
+    return {"workload": f"disc_k2pi, N={orc.N}", "blas_threads": nth, "dense_rows_s": round(t_build, 2),
+            "matvecs_per_s_dense": round(1 / t_mv, 1), "lu_solve_s": round(t_lu, 2),
+            "solves_per_s_incl_rows": round(1 / (t_build + t_lu), 4)}
 
 
 def multi_rhs_run(nrhs, ortho, autotune):
@@ -133,9 +196,18 @@ def multi_rhs_run(nrhs, ortho, autotune):
         torch.cuda.synchronize()
         t32 = time.perf_counter() - t0
         err = ((torch.linalg.norm(X32 - X64, dim=1) / torch.linalg.norm(X64, dim=1)).max()).item()
+        # the plain double-precision form at the same tolerance as the timed one
+        Xp = torch.empty_like(F)
+        t0 = time.perf_counter()
+        sp = op.solve(F, Xp, tol=1e-7, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP64)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        errp = ((torch.linalg.norm(Xp - X64, dim=1) / torch.linalg.norm(X64, dim=1)).max()).item()
         return {"workload": f"star_k16pi, N={op.N}, {nrhs} incident directions", "nrhs": nrhs,
                 "rhs_solves_per_s": nrhs / t32, "seconds": t32, "iterations": s32["iterations"],
-                "max_err_vs_fp64_ref": err, "fp64_ref_tol1e-10_rhs_solves_per_s": nrhs / t64,
+                "max_err_vs_fp64_ref": err, "fp64_tol1e-7_rhs_solves_per_s": nrhs / tp,
+                "fp64_tol1e-7_err": errp, "fp64_tol1e-7_iterations": sp["iterations"],
+                "fp64_ref_tol1e-10_rhs_solves_per_s": nrhs / t64,
                 "fp64_ref_iterations": s64["iterations"], "all_converged": s32["converged"] == nrhs}
     finally:
         op.close()
@@ -188,11 +260,13 @@ def conv3d_pass_bytes(na, nb, nc, Pa, Pb, Pc, nsets):
     rows are neither read nor written.  Per array (2 nsets: both kinds of
     every set) lines along c read straight from the compact strengths, then
     columns along b; per set the fused pass along a (both kinds' na rows and
-    the two spectra in, kind 0's na rows out), then columns along b and lines
-    along c written straight into the compact field (kind 0)."""
+    the one stored octant of each of the two kernel spectra in, kind 0's na
+    rows out), then columns along b and lines along c written straight into
+    the compact field (kind 0)."""
     e = 8
+    octant = (Pa // 2 + 1) * (Pb // 2 + 1) * (Pc // 2 + 1)
     fwd = (na * nb * nc + na * nb * Pc) + (na * nb * Pc + na * Pb * Pc)
-    conv = 2 * na * Pb * Pc + 2 * Pa * Pb * Pc + na * Pb * Pc
+    conv = 2 * na * Pb * Pc + 2 * octant + na * Pb * Pc
     inv = (na * Pb * Pc + na * nb * Pc) + (na * nb * Pc + na * nb * nc)
     return e * (2 * nsets * fwd + nsets * (conv + inv))
 
@@ -287,8 +361,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="star_k32pi")
     ap.add_argument("--matvec-reps", type=int, default=20)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-disc-oracle", action="store_true",
+                    help="skip the dense oracle timing on the 4k-unknown disc in the CPU baseline")
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--ortho", choices=["cgs1", "cgs2"], default="cgs1",
@@ -393,6 +469,25 @@ def main():
     err = (torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref)).item()
     log(f"error vs FP64 reference solve {err:.3e}")
 
+    # the same single-precision apply inside a complex-double inner Arnoldi
+    # (the precision split north of the bulk work: FP64 basis and
+    # orthogonalisation, FP32 operator)
+    xa = torch.empty_like(f)
+    ta = []
+    for _ in range(max(1, min(args.steps, 3))):
+        t1 = time.perf_counter()
+        info_a = op.solve(f, xa, tol=1e-7, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP32_REFINE,
+                          inner_tol=1e-4, max_outer=30, ortho=ortho, inner_f64_basis=True)
+        torch.cuda.synchronize()
+        ta.append(time.perf_counter() - t1)
+    err_a = (torch.linalg.norm(xa - x_ref) / torch.linalg.norm(x_ref)).item()
+    log(f"FP32 apply + FP64 Arnoldi solve {min(ta) * 1e3:.1f} ms err {err_a:.3e} {info_a}")
+    # one profiled solve of the timed form: device time per stage
+    xp = torch.empty_like(f)
+    info_p = op.solve(f, xp, tol=1e-7, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP32_REFINE,
+                      inner_tol=1e-4, max_outer=30, ortho=ortho, profile=True)
+    log(f"profiled solve stage us {info_p['stage_us']}")
+
     # plain FP64 GMRES form for comparison (same tolerance on the error)
     xf = torch.empty_like(f)
     t1 = time.perf_counter()
@@ -474,12 +569,18 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        rows_s, nrows, N_or = cpu_oracle_rate(cfg, n2, args.cpu_budget)
+        model, _ = host_cpu()
+        rows_s, nrows, N_or, nth, resid = cpu_oracle_rate(cfg, n2, args.cpu_budget, x_ref=x_ref.cpu().numpy(),
+                                                          f_ref=f.cpu().numpy(), key_lib=key)
         mv = rows_s / N_or
         applies_per_solve = info["iterations"] + info["outer"] + 1
-        cpu = {"value": mv / max(applies_per_solve, 1), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"{nrows} direct-sum rows of N={N_or} ({rows_s:.2f} rows/s = {mv:.3e} matvecs/s), "
-                         f"scaled by {applies_per_solve} applies per solve"}
+        cpu = {"value": mv / max(applies_per_solve, 1), "unit": "solves/s", "cores": nth, "kind": "oracle",
+               "cpu_model": model,
+               "sample": f"{nrows} direct-sum rows of N={N_or} on {nth} threads ({rows_s:.2f} rows/s = "
+                         f"{mv:.3e} matvecs/s), scaled by {applies_per_solve} applies per solve",
+               "fp64_ref_oracle_row_residual": resid, "fp64_ref_residual_rows": nrows}
+        if not args.no_disc_oracle:
+            cpu["disc_oracle"] = cpu_disc_oracle()
         log(f"cpu baseline {cpu}")
 
     out = {
@@ -493,7 +594,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 bulk + c128 residual/Arnoldi",
+        "dtype": "c64 apply + c64 inner Arnoldi (f64 block reductions) + c128 residual",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: star R=1+0.3cos5t, kappa=32pi, n^2=1+0.8exp(-4|x|^2), "
                                f"plane wave at 30deg, N={N}", "N": N, "nrhs": 1,
@@ -503,6 +604,10 @@ def main():
         "solve_p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),
         "iterations": info["iterations"],
         "outer": info["outer"],
+        "fp32_apply_f64_arnoldi_solves_per_s": 1.0 / min(ta),
+        "fp32_apply_f64_arnoldi_err": err_a,
+        "fp32_apply_f64_arnoldi_iterations": info_a["iterations"],
+        "solve_stage_us": info_p["stage_us"],
         "fp64_plain_solves_per_s": 1.0 / t64,
         "fp64_plain_err": err64,
         "fp64_plain_iterations": info64["iterations"],

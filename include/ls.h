@@ -53,7 +53,8 @@ typedef enum {
   LS_EDEVICE = 3,     /* HIP runtime error (no device, launch failure, fault) */
   LS_ENOCONV = 4,     /* solver stopped before the tolerance; iterate written */
   LS_EBUDGET = 5,     /* request does not fit the memory budget */
-  LS_ENOTREADY = 6    /* serving ticket not finished yet */
+  LS_ENOTREADY = 6,   /* serving ticket not finished yet */
+  LS_ENUMERIC = 7     /* non-finite value (NaN / Inf) in the data or during an iteration */
 } ls_status;
 
 typedef enum { LS_C128 = 0, LS_C64 = 1 } ls_prec;
@@ -114,15 +115,32 @@ typedef void (*ls_n2_fn)(int64_t n, const double* xy, const int32_t* on_boundary
 
 typedef struct ls_op ls_op;
 
+/* Device memory provider.  alloc returns device memory of at least `bytes`
+ * bytes on the current device, aligned to 256 bytes, or NULL on failure;
+ * release gives back a block alloc returned (with its size).  Both are
+ * called on the thread that calls into the library, with the op's device
+ * current.  A caching allocator (e.g. PyTorch's) can supply the operator's
+ * memory this way, so one pool serves both. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*release)(void* ptr, size_t bytes, void* ctx);
+  void* ctx;
+} ls_allocator;
+
 /* Build the discrete operator for wavenumber kappa on the current HIP device.
  * Set-up (nodes, weights, near-field quadratures, equivalent-source least
  * squares, Green's function spectra) runs on the host with OpenMP; the
- * results are copied to the device once.  The op owns all its memory.
+ * results are copied to the device once.  The op owns all its memory: every
+ * device block it keeps (operator data, the solver scratch of ls_solve
+ * without a caller workspace, targets of ls_targets_create) comes from
+ * `alloc` when it is not NULL (it is copied; its ctx must stay valid while
+ * the op lives), else from hipMalloc; temporary set-up blocks too.
  * Errors: LS_EINVAL (bad geometry/params, kappa <= 0, cell resonance
- * kappa H >= pi sqrt(2), cut-off reach beyond two cells), LS_ENOMEM,
+ * kappa H >= pi sqrt(2), cut-off reach beyond two cells), LS_ENOMEM (also
+ * when alloc returns NULL; everything taken so far is released),
  * LS_EDEVICE. */
 ls_status ls_create(const ls_geometry* geom, ls_n2_fn n2, void* ctx, double kappa,
-                    const ls_params* params, ls_op** out);
+                    const ls_params* params, const ls_allocator* alloc, ls_op** out);
 
 /* Release everything the op holds (NULL is accepted). */
 void ls_destroy(ls_op* op);
@@ -159,7 +177,11 @@ ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* byt
  * the operator's own, forked from `stream` by an event and joined back
  * into it before the apply's last kernel (so the work enqueued on `stream`
  * is complete exactly when the apply is; stream capture records the fork
- * and the join).  Errors: LS_EINVAL, LS_EDEVICE. */
+ * and the join).  Applies on one op may be issued from several host
+ * threads: the fork / join sequence on the op's stream is taken under a
+ * lock of the op, so their near fields queue one after another on that
+ * stream while their far fields overlap on the callers' streams.
+ * Errors: LS_EINVAL, LS_EDEVICE. */
 ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec,
                    void* ws, size_t ws_bytes, void* stream);
 
@@ -191,6 +213,22 @@ typedef struct {
   double csr_ms;        /* best time of the boundary-patch rows stage */
   double apply_ms;      /* one apply with all choices in place */
 } ls_tune_result;
+
+/* Set the kernel schedule for later applies in precision prec (fields
+ * fft_col_tile ... fft_col_threads of *sched; the timing fields are
+ * ignored), e.g. to force one variant.  The schedule changes which kernels
+ * run, not the discrete operator.  Ranges: fft_col_tile 1 ... the LDS limit
+ * (LS_EINVAL beyond it), near_variant 0-3 (single precision; double
+ * precision has one interior kernel and accepts 0), csr_variant 0-3
+ * (single precision; 2 needs the run-length columns, 3 the dense tiles, and
+ * falls back to 2 when nrhs is not a multiple of 16; double precision
+ * accepts 0), fft_variant 0 / 1, fft_row_threads 256 / 512 / 1024,
+ * fft_col_threads 256 / 512.  LS_EINVAL leaves the schedule unchanged.  Not
+ * to be called while applies or solves on op are in flight. */
+ls_status ls_set_schedule(ls_op* op, ls_prec prec, const ls_tune_result* sched);
+
+/* The current schedule of precision prec (timing fields zero). */
+ls_status ls_get_schedule(const ls_op* op, ls_prec prec, ls_tune_result* sched);
 
 /* Time the candidate schedules of the apply's tunable stages on this
  * operator (each candidate: three applies of a fixed input, best stage time
@@ -225,6 +263,12 @@ typedef struct {
                            are kept with the op per (precision, passes, nrhs,
                            restart, step) and released by ls_destroy.  Results
                            are bitwise those of the eager launches. */
+  int profile;          /* nonzero: HIP events around each stage fill
+                           ls_solve_stats.stage_us (ignored with graph) */
+  int inner_f64_basis;  /* FP32_REFINE only: nonzero keeps the inner solves'
+                           Krylov basis and Arnoldi in complex double around
+                           the single-precision apply (the apply's input is
+                           rounded to single precision, its output widened) */
 } ls_solve_opts;
 
 typedef struct {
@@ -233,18 +277,37 @@ typedef struct {
   int converged;        /* vectors that met tol */
   double rel_residual;  /* max over vectors of ||f - A x|| / ||f|| (FP64 apply) */
   double seconds;       /* wall time of the call */
-  double apply_seconds; /* time spent in operator applies */
+  double apply_seconds; /* host time spent enqueueing operator applies */
+  /* device time per stage in microseconds when opts->profile is set (else
+   * zero): 0 double-precision applies, 1 single-precision applies (with
+   * their precision conversions), 2 Arnoldi orthogonalisation and
+   * normalisation, 3 the rest (residuals, refinement updates, the update
+   * x += V y) */
+  double stage_us[4];
 } ls_solve_stats;
+
+/* Device workspace bytes ls_solve needs for nrhs right-hand sides with
+ * these options (restart length and mode decide the Krylov basis). */
+ls_status ls_solve_workspace_size(const ls_op* op, int nrhs, const ls_solve_opts* opts, size_t* bytes);
 
 /* Solve (I + kappa^2 K_h) u = u_inc for nrhs right-hand sides (device
  * [nrhs][N] complex double) with matrix-free complex GMRES (Sec. 2),
  * Arnoldi on the device.  FP64: basis, apply and Arnoldi in double.
- * FP32_REFINE: inner GMRES solves with a single-precision basis and apply
- * (reductions in double) correct the iterate from double-precision residuals.
- * Synchronous on return.  Scratch memory is allocated by the op on first use
- * and kept.  LS_ENOCONV still writes the best iterate and the stats. */
+ * FP32_REFINE: inner GMRES solves with a single-precision apply correct the
+ * iterate from double-precision residuals; the inner basis is complex float
+ * with double-precision block reductions, or complex double with
+ * opts->inner_f64_basis.  Synchronous on return.
+ * ws: device workspace of at least ls_solve_workspace_size bytes owned by
+ * the caller, or NULL: then the op allocates its own scratch on first use
+ * and keeps it (through the op's allocator).  Solves on one op run one at a
+ * time (a lock of the op; the Givens buffers are the op's).
+ * LS_ENOCONV (tolerance not met within max_iter, or a restart cycle that
+ * no longer reduces the residual) and LS_ENUMERIC (a non-finite right-hand
+ * side, residual or Hessenberg entry; the iteration stops at the last
+ * finite step) still write the best iterate and the stats. */
 ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs,
-                   const ls_solve_opts* opts, ls_solve_stats* stats, void* stream);
+                   const ls_solve_opts* opts, ls_solve_stats* stats, void* ws, size_t ws_bytes,
+                   void* stream);
 
 /* ---------------------------------------------------------------------------
  * The field off the scatterer.  Outside the scatterer the Lippmann–Schwinger
@@ -317,8 +380,10 @@ typedef struct {
   int64_t queued, running, evictions;
 } ls_server_info;
 
-/* budget_bytes: device memory for resident operators plus solver scratch.
- * Errors: LS_EINVAL. */
+/* budget_bytes: device memory for resident operators plus solver scratch
+ * (each solve's workspace, ls_solve_workspace_size, and its right-hand
+ * sides).  A request whose operator and single-right-hand-side solve alone
+ * exceed the budget finishes with LS_EBUDGET.  Errors: LS_EINVAL. */
 ls_status ls_server_create(size_t budget_bytes, const ls_server_opts* opts, ls_server** out);
 /* Register a scatterer under `key` (arguments as ls_create; the structs are
  * copied, ctx and n2 must stay valid while the server lives).  Errors:

@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libls.so")
 
-LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOCONV, LS_EBUDGET, LS_ENOTREADY = range(7)
+LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOCONV, LS_EBUDGET, LS_ENOTREADY, LS_ENUMERIC = range(8)
 LS_C128, LS_C64 = 0, 1
 LS_SOLVE_FP64, LS_SOLVE_FP32_REFINE = 0, 1
 LS_ORTHO_CGS2, LS_ORTHO_CGS1 = 0, 1
@@ -37,12 +37,21 @@ class Params(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int), ("mode", C.c_int),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int), ("use_x0", C.c_int), ("ortho", C.c_int),
-                ("graph", C.c_int)]
+                ("graph", C.c_int), ("profile", C.c_int), ("inner_f64_basis", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("converged", C.c_int),
-                ("rel_residual", C.c_double), ("seconds", C.c_double), ("apply_seconds", C.c_double)]
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("apply_seconds", C.c_double),
+                ("stage_us", C.c_double * 4)]
+
+
+ALLOCFN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASEFN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOCFN), ("release", RELEASEFN), ("ctx", C.c_void_p)]
 
 
 class ServerOpts(C.Structure):
@@ -84,7 +93,11 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.POINTER
         sig = {
-            "ls_create": (C.c_int, [P(Geometry), N2FN, C.c_void_p, C.c_double, P(Params), P(C.c_void_p)]),
+            "ls_create": (C.c_int, [P(Geometry), N2FN, C.c_void_p, C.c_double, P(Params), P(Allocator),
+                                    P(C.c_void_p)]),
+            "ls_set_schedule": (C.c_int, [C.c_void_p, C.c_int, P(TuneResult)]),
+            "ls_get_schedule": (C.c_int, [C.c_void_p, C.c_int, P(TuneResult)]),
+            "ls_solve_workspace_size": (C.c_int, [C.c_void_p, C.c_int, P(SolveOpts), P(C.c_size_t)]),
             "ls_destroy": (None, [C.c_void_p]),
             "ls_num_points": (C.c_int, [C.c_void_p, P(C.c_int64)]),
             "ls_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -96,7 +109,7 @@ def lib():
             "ls_apply_profile": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
                                            C.c_size_t, C.c_void_p, P(C.c_double), C.c_int]),
             "ls_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, P(SolveOpts), P(SolveStats),
-                                   C.c_void_p]),
+                                   C.c_void_p, C.c_size_t, C.c_void_p]),
             "ls_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, P(TuneResult)]),
             "ls_server_create": (C.c_int, [C.c_size_t, P(ServerOpts), P(C.c_void_p)]),
             "ls_server_add_operator": (C.c_int, [C.c_void_p, C.c_uint64, P(Geometry), N2FN, C.c_void_p,
@@ -320,16 +333,61 @@ class FFT3D:
             pass
 
 
-class Operator:
-    """Device operator: ls_create / ls_apply / ls_solve."""
+def check_vectors(t, N, dtypes, name, nrhs=None):
+    """Validate a device vector block before it crosses the ABI (the C side
+    cannot see a tensor's length or dtype): a contiguous tensor on the HIP
+    device, of one of `dtypes`, holding nrhs x N values ([N] or [nrhs, N]).
+    Returns nrhs.  Raises ValueError otherwise."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: a torch tensor is expected")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype} is not one of {[str(d) for d in dtypes]}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: a contiguous tensor is expected")
+    if t.dim() not in (1, 2) or t.shape[-1] != N:
+        raise ValueError(f"{name}: shape {tuple(t.shape)} is not [N] or [nrhs, N] with N = {N}")
+    r = 1 if t.dim() == 1 else t.shape[0]
+    if r < 1 or (nrhs is not None and r != nrhs):
+        raise ValueError(f"{name}: {r} vectors where {nrhs} are expected")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: a device (HIP) tensor is expected, got {t.device}")
+    return r
 
-    def __init__(self, cfg, n2_fn):
+
+def torch_allocator():
+    """An ls_allocator backed by PyTorch's caching allocator (the current
+    device and stream when the library calls it).  Keep the returned object
+    alive while the operator lives."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def _release(ptr, nbytes, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = Allocator(ALLOCFN(_alloc), RELEASEFN(_release), None)
+    a._keep = (_alloc, _release)
+    return a
+
+
+class Operator:
+    """Device operator: ls_create / ls_apply / ls_solve.  `allocator`: None
+    (hipMalloc), "torch" (PyTorch's caching allocator) or an Allocator."""
+
+    def __init__(self, cfg, n2_fn, allocator=None):
         L = lib()
         self.cfg = cfg
         self._cb = _n2_callback(n2_fn)
+        self._alloc = torch_allocator() if allocator == "torch" else allocator
         op = C.c_void_p()
         g, p = geometry_from(cfg), params_from(cfg)
-        _check(L.ls_create(C.byref(g), self._cb, None, float(cfg["kappa"]), C.byref(p), C.byref(op)), "ls_create")
+        _check(L.ls_create(C.byref(g), self._cb, None, float(cfg["kappa"]), C.byref(p),
+                           C.byref(self._alloc) if self._alloc is not None else None, C.byref(op)), "ls_create")
         self._op = op
         n = C.c_int64()
         _check(L.ls_num_points(op, C.byref(n)), "ls_num_points")
@@ -367,12 +425,9 @@ class Operator:
     def apply(self, u, v, stream=None):
         """v = u + kappa^2 K_h u; u, v: torch complex128/complex64 [nrhs, N] or [N] on the device."""
         import torch
+        nrhs = check_vectors(u, self.N, (torch.complex128, torch.complex64), "u")
+        check_vectors(v, self.N, (u.dtype,), "v", nrhs)
         prec = LS_C128 if u.dtype == torch.complex128 else LS_C64
-        if v.dtype != u.dtype or not u.is_contiguous() or not v.is_contiguous():
-            raise ValueError("u and v must be contiguous and of one dtype")
-        nrhs = 1 if u.dim() == 1 else u.shape[0]
-        if u.numel() != nrhs * self.N or v.numel() != nrhs * self.N:
-            raise ValueError("shape does not match the operator")
         ws = self.workspace(nrhs, prec)
         _check(lib().ls_apply(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(), _stream(stream)),
                "ls_apply")
@@ -383,8 +438,9 @@ class Operator:
     def apply_profile(self, u, v, stream=None):
         """One apply with per-stage HIP event timing; returns {stage: ms}."""
         import torch
+        nrhs = check_vectors(u, self.N, (torch.complex128, torch.complex64), "u")
+        check_vectors(v, self.N, (u.dtype,), "v", nrhs)
         prec = LS_C128 if u.dtype == torch.complex128 else LS_C64
-        nrhs = 1 if u.dim() == 1 else u.shape[0]
         ws = self.workspace(nrhs, prec)
         out = (C.c_double * 8)()
         _check(lib().ls_apply_profile(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(),
@@ -395,11 +451,13 @@ class Operator:
         """Scattered field u^s = -kappa^2 K[u] at points xy (M, 2) outside the
         scatterer, for totals u_tot ([nrhs,] N complex128, device)."""
         import torch
+        nrhs = check_vectors(u_tot, self.N, (torch.complex128,), "u_tot")
         xy = np.ascontiguousarray(xy, dtype=np.float64)
+        if xy.ndim != 2 or xy.shape[1] != 2 or xy.shape[0] < 1:
+            raise ValueError("xy: an (M, 2) array of target points is expected")
         tg = C.c_void_p()
         _check(lib().ls_targets_create(self._op, xy.shape[0], xy.ctypes.data, C.byref(tg)), "ls_targets_create")
         try:
-            nrhs = 1 if u_tot.dim() == 1 else u_tot.shape[0]
             out = torch.empty((nrhs, xy.shape[0]), dtype=torch.complex128, device=u_tot.device)
             ws = self.workspace(nrhs, LS_C128)
             _check(lib().ls_scattered_field(self._op, tg, _ptr(u_tot), nrhs, _ptr(out), _ptr(ws), ws.numel(),
@@ -416,17 +474,62 @@ class Operator:
         _check(lib().ls_autotune(self._op, int(nrhs), int(prec), _stream(stream), C.byref(r)), "ls_autotune")
         return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
+    SCHEDULE_FIELDS = ("fft_col_tile", "near_variant", "csr_variant", "fft_variant", "fft_row_threads",
+                       "fft_col_threads")
+
+    def get_schedule(self, prec=LS_C64):
+        r = TuneResult()
+        _check(lib().ls_get_schedule(self._op, int(prec), C.byref(r)), "ls_get_schedule")
+        return {f: getattr(r, f) for f in self.SCHEDULE_FIELDS}
+
+    def set_schedule(self, prec=LS_C64, **fields):
+        """Force kernel schedule fields (the rest keep their current values)."""
+        cur = self.get_schedule(prec)
+        for k, v in fields.items():
+            if k not in cur:
+                raise ValueError(f"unknown schedule field {k}")
+            cur[k] = int(v)
+        r = TuneResult(**cur)
+        _check(lib().ls_set_schedule(self._op, int(prec), C.byref(r)), "ls_set_schedule")
+        return cur
+
+    @staticmethod
+    def _opts(tol, max_iter, restart, mode, inner_tol, max_outer, use_x0, ortho, graph, profile, inner_f64_basis):
+        return SolveOpts(float(tol), int(max_iter), int(restart), int(mode), float(inner_tol), int(max_outer),
+                         int(use_x0), int(ortho), int(bool(graph)), int(bool(profile)), int(bool(inner_f64_basis)))
+
+    def solve_workspace_bytes(self, nrhs, restart=100):
+        b = C.c_size_t()
+        opts = self._opts(1e-10, 1, restart, LS_SOLVE_FP64, 1e-5, 1, 0, 0, 0, 0, 0)
+        _check(lib().ls_solve_workspace_size(self._op, int(nrhs), C.byref(opts), C.byref(b)),
+               "ls_solve_workspace_size")
+        return b.value
+
     def solve(self, u_inc, u_tot, tol=1e-10, max_iter=2000, restart=100, mode=LS_SOLVE_FP64, inner_tol=1e-5,
-              max_outer=20, use_x0=False, stream=None, raise_on_noconv=True, ortho=LS_ORTHO_CGS2, graph=False):
-        nrhs = 1 if u_inc.dim() == 1 else u_inc.shape[0]
-        opts = SolveOpts(float(tol), int(max_iter), int(restart), int(mode), float(inner_tol), int(max_outer),
-                         int(use_x0), int(ortho), int(bool(graph)))
+              max_outer=20, use_x0=False, stream=None, raise_on_noconv=True, ortho=LS_ORTHO_CGS2, graph=False,
+              profile=False, inner_f64_basis=False, workspace=None):
+        """GMRES solve; u_inc, u_tot complex128 [N] or [nrhs, N] on the device.
+        workspace: None (the op's own scratch) or a uint8 device tensor of at
+        least solve_workspace_bytes(nrhs, restart) bytes."""
+        import torch
+        nrhs = check_vectors(u_inc, self.N, (torch.complex128,), "u_inc")
+        check_vectors(u_tot, self.N, (torch.complex128,), "u_tot", nrhs)
+        wsp, wsb = None, 0
+        if workspace is not None:
+            if workspace.device.type != "cuda" or not workspace.is_contiguous():
+                raise ValueError("workspace: a contiguous device tensor is expected")
+            wsp, wsb = _ptr(workspace), workspace.numel() * workspace.element_size()
+        opts = self._opts(tol, max_iter, restart, mode, inner_tol, max_outer, use_x0, ortho, graph, profile,
+                          inner_f64_basis)
         st = SolveStats()
-        rc = lib().ls_solve(self._op, _ptr(u_inc), _ptr(u_tot), nrhs, C.byref(opts), C.byref(st), _stream(stream))
-        if rc != LS_OK and (rc != LS_ENOCONV or raise_on_noconv):
+        rc = lib().ls_solve(self._op, _ptr(u_inc), _ptr(u_tot), nrhs, C.byref(opts), C.byref(st), wsp, wsb,
+                            _stream(stream))
+        if rc not in (LS_OK, LS_ENOCONV, LS_ENUMERIC) or (rc != LS_OK and raise_on_noconv):
             raise LSError(rc, "ls_solve")
         return {"iterations": st.iterations, "outer": st.outer, "converged": st.converged,
                 "rel_residual": st.rel_residual, "seconds": st.seconds, "apply_seconds": st.apply_seconds,
+                "stage_us": {"apply_fp64": st.stage_us[0], "apply_fp32": st.stage_us[1], "arnoldi": st.stage_us[2],
+                             "other": st.stage_us[3]},
                 "status": rc}
 
     def close(self):

@@ -8,8 +8,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -47,15 +49,23 @@ struct ls_op {
   int64_t N = 0;
   std::vector<double> xy;
   std::vector<int32_t> key;
-  std::vector<void*> allocs;
+  // device blocks the op holds, with their sizes (for the allocator's release)
+  std::vector<std::pair<void*, size_t>> allocs;
   size_t resident = 0;
+  ls_allocator alloc{};           // alloc.alloc == nullptr: hipMalloc / hipFree
+  // the fork / join sequence of an apply on the op's side stream and events
+  // (and graph capture, which records it) is taken under this lock
+  std::recursive_mutex apply_mu;
+  // solves run one at a time (they share the Givens buffers and events)
+  std::mutex solve_mu;
   lsx::DevView<double> d64;
   lsx::DevView<float> d32;
   double kappa = 0;
   int64_t stats[15] = {0};
-  // solver scratch
+  // solver scratch (ls_solve without a caller workspace)
   void* gm = nullptr;
   size_t gm_bytes = 0;
+  void* gm_last = nullptr;        // workspace base the last solve used (captured graphs point into it)
   std::complex<double>* pinned = nullptr;
   size_t pinned_n = 0;
   hipEvent_t gm_ev[2] = {nullptr, nullptr};
@@ -77,19 +87,36 @@ struct ls_op {
 
 struct ls_targets {
   int64_t n = 0;
-  std::vector<void*> allocs;
+  std::vector<std::pair<void*, size_t>> allocs;
+  ls_allocator alloc{};
   lsx::TargetView view;
 };
 
 namespace {
 
+// device memory through the op's allocator (or hipMalloc)
+void* dev_alloc(const ls_allocator& a, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (a.alloc) return a.alloc(bytes, a.ctx);
+  void* p = nullptr;
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+void dev_free(const ls_allocator& a, void* p, size_t bytes) {
+  if (!p) return;
+  if (a.alloc) {
+    if (a.release) a.release(p, bytes, a.ctx);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
 template <typename X>
 ls_status upload(ls_op* op, const X* src, size_t count, void** dst) {
   *dst = nullptr;
   if (count == 0) return LS_OK;
-  void* p = nullptr;
-  if (hipMalloc(&p, count * sizeof(X)) != hipSuccess) return fail(LS_ENOMEM, "hipMalloc failed");
-  op->allocs.push_back(p);
+  void* p = dev_alloc(op->alloc, count * sizeof(X));
+  if (!p) return fail(LS_ENOMEM, "device allocation failed");
+  op->allocs.emplace_back(p, count * sizeof(X));
   op->resident += count * sizeof(X);
   if (hipMemcpy(p, src, count * sizeof(X), hipMemcpyHostToDevice) != hipSuccess)
     return fail(LS_EDEVICE, "hipMemcpy H2D failed");
@@ -152,10 +179,14 @@ void clear_graphs(ls_op* op) {
 }
 
 void release(ls_op* op) {
-  for (void* p : op->allocs) (void)hipFree(p);
+  // a caching allocator hands blocks out again at once: let every kernel
+  // that may still read them finish first (hipFree waits by itself)
+  if (op->alloc.alloc) (void)hipDeviceSynchronize();
+  for (auto& pb : op->allocs) dev_free(op->alloc, pb.first, pb.second);
   op->allocs.clear();
-  if (op->gm) (void)hipFree(op->gm);
+  dev_free(op->alloc, op->gm, op->gm_bytes);
   op->gm = nullptr;
+  op->gm_bytes = 0;
   if (op->pinned) (void)hipHostFree(op->pinned);
   op->pinned = nullptr;
   for (auto& e : op->gm_ev) {
@@ -255,10 +286,11 @@ ls_status ls_targets_create(ls_op* op, int64_t n, const double* xy, ls_targets**
   }
   auto* tg = new (std::nothrow) ls_targets();
   if (!tg) return fail(LS_ENOMEM, "host allocation");
+  tg->alloc = op->alloc;
   auto put = [&](const void* src, size_t bytes, const void** dst) -> bool {
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return false;
-    tg->allocs.push_back(p);
+    void* p = dev_alloc(tg->alloc, bytes);
+    if (!p) return false;
+    tg->allocs.emplace_back(p, bytes);
     *dst = p;
     return hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
   };
@@ -286,7 +318,7 @@ ls_status ls_targets_create(ls_op* op, int64_t n, const double* xy, ls_targets**
 
 void ls_targets_destroy(ls_targets* tg) {
   if (!tg) return;
-  for (void* p : tg->allocs) (void)hipFree(p);
+  for (auto& pb : tg->allocs) dev_free(tg->alloc, pb.first, pb.second);
   delete tg;
 }
 
@@ -294,6 +326,7 @@ ls_status ls_scattered_field(ls_op* op, const ls_targets* tg, const void* u_tot,
                              size_t ws_bytes_, void* stream) {
   if (!op || !tg || !u_tot || !us || !ws || nrhs < 1) return fail(LS_EINVAL, "bad argument");
   if (ws_bytes_ < ws_bytes(op, nrhs, LS_C128)) return fail(LS_EINVAL, "workspace too small");
+  std::lock_guard<std::recursive_mutex> lk(op->apply_mu);
   hipError_t e = lsx::launch_targets(op->d64, tg->view, u_tot, us, nrhs, ws, (hipStream_t)stream);
   if (e != hipSuccess) return fail(LS_EDEVICE, std::string("scattered field launch: ") + hipGetErrorString(e));
   return LS_OK;
@@ -308,6 +341,7 @@ const char* ls_status_str(ls_status s) {
     case LS_ENOCONV: return "not converged";
     case LS_EBUDGET: return "over memory budget";
     case LS_ENOTREADY: return "not ready";
+    case LS_ENUMERIC: return "non-finite value";
   }
   return "unknown status";
 }
@@ -403,7 +437,7 @@ ls_status ls_host_near_row(const ls_host_op* h, int64_t i, int64_t cap, int32_t*
 }
 
 ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, const ls_params* p,
-                    ls_op** out) {
+                    const ls_allocator* alloc, ls_op** out) {
   if (!out) return fail(LS_EINVAL, "null argument");
   *out = nullptr;
   int ndev = 0;
@@ -415,6 +449,14 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   ls_op* op = new (std::nothrow) ls_op();
   if (!op) { ls_host_destroy(hb); return fail(LS_ENOMEM, "host allocation"); }
   (void)hipGetDevice(&op->device);
+  if (alloc) {
+    if (!alloc->alloc || !alloc->release) {
+      ls_host_destroy(hb);
+      delete op;
+      return fail(LS_EINVAL, "allocator without alloc or release");
+    }
+    op->alloc = *alloc;
+  }
   op->N = h.N;
   op->kappa = kappa;
   op->xy = h.xy;
@@ -654,9 +696,16 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     }
     for (int64_t j = 0; j < h.N; ++j)
       if (pt_cell[(size_t)j] < 0) return cleanup(fail(LS_EINVAL, "a node outside every cell"));
-    void *d_olen = nullptr, *d_cell = nullptr, *d_idx = nullptr;
-    bool ok = hipMalloc(&d_olen, 8 * std::max<size_t>(1, nrow)) == hipSuccess &&
-              hipMalloc(&d_cell, 4 * (size_t)h.N) == hipSuccess && hipMalloc(&d_idx, 4 * (size_t)h.N) == hipSuccess;
+    const size_t b_olen = 8 * std::max<size_t>(1, nrow), b_pt = 4 * (size_t)h.N;
+    void* d_olen = dev_alloc(op->alloc, b_olen);
+    void* d_cell = d_olen ? dev_alloc(op->alloc, b_pt) : nullptr;
+    void* d_idx = d_cell ? dev_alloc(op->alloc, b_pt) : nullptr;
+    if (!d_idx) {
+      dev_free(op->alloc, d_olen, b_olen);
+      dev_free(op->alloc, d_cell, b_pt);
+      return cleanup(fail(LS_ENOMEM, "device allocation failed (near-field fold)"));
+    }
+    bool ok = true;
     ok = ok && hipMemcpy(d_olen, olen.data(), 8 * nrow, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(d_cell, pt_cell.data(), 4 * (size_t)h.N, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(d_idx, pt_idx.data(), 4 * (size_t)h.N, hipMemcpyHostToDevice) == hipSuccess;
@@ -665,9 +714,9 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     ok = ok && (vals32.empty() ||
                 hipMemcpy(vals32.data(), b.vals, 8 * vals32.size(), hipMemcpyDeviceToHost) == hipSuccess);
-    if (d_olen) (void)hipFree(d_olen);
-    if (d_cell) (void)hipFree(d_cell);
-    if (d_idx) (void)hipFree(d_idx);
+    dev_free(op->alloc, d_olen, b_olen);
+    dev_free(op->alloc, d_cell, b_pt);
+    dev_free(op->alloc, d_idx, b_pt);
     if (!ok) return cleanup(fail(LS_EDEVICE, "near-field fold failed"));
   }
   if (!p->skip_tiles) {
@@ -868,6 +917,7 @@ ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, vo
   const char* vc = (const char*)v;
   if (uc < vc + vb && vc < uc + vb) return fail(LS_EINVAL, "u and v overlap");
   hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::recursive_mutex> lk(op->apply_mu);
   hipError_t e = prec == LS_C128 ? lsx::launch_apply<double>(op->d64, u, v, nrhs, ws, st)
                                  : lsx::launch_apply<float>(op->d32, u, v, nrhs, ws, st);
   if (e != hipSuccess) return fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
@@ -882,6 +932,7 @@ ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec 
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t ev[9];
   for (int i = 0; i < 9; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  std::lock_guard<std::recursive_mutex> lk(op->apply_mu);
   hipError_t e = prec == LS_C128 ? lsx::launch_apply<double>(op->d64, u, v, nrhs, ws, st, ev)
                                  : lsx::launch_apply<float>(op->d32, u, v, nrhs, ws, st, ev);
   ls_status out = LS_OK;
@@ -1041,10 +1092,13 @@ ls_status ls_autotune(ls_op* op, int nrhs, ls_prec prec, void* stream, ls_tune_r
   hipStream_t st = (hipStream_t)stream;
   const size_t c = prec == LS_C128 ? 16 : 8;
   const size_t vb = c * (size_t)op->N * nrhs, wsb = ws_bytes(op, nrhs, prec);
-  void *u = nullptr, *v = nullptr, *ws = nullptr;
-  if (hipMalloc(&u, vb) != hipSuccess || hipMalloc(&v, vb) != hipSuccess || hipMalloc(&ws, wsb) != hipSuccess) {
-    if (u) (void)hipFree(u);
-    if (v) (void)hipFree(v);
+  std::lock_guard<std::recursive_mutex> lk(op->apply_mu);
+  void* u = dev_alloc(op->alloc, vb);
+  void* v = u ? dev_alloc(op->alloc, vb) : nullptr;
+  void* ws = v ? dev_alloc(op->alloc, wsb) : nullptr;
+  if (!ws) {
+    dev_free(op->alloc, u, vb);
+    dev_free(op->alloc, v, vb);
     return fail(LS_ENOMEM, "autotune buffers");
   }
   ls_status out = LS_OK;
@@ -1060,10 +1114,65 @@ ls_status ls_autotune(ls_op* op, int nrhs, ls_prec prec, void* stream, ls_tune_r
   (void)hipStreamSynchronize(st);
   for (int i = 0; i < 9; ++i)
     if (ev[i]) (void)hipEventDestroy(ev[i]);
-  (void)hipFree(u);
-  (void)hipFree(v);
-  (void)hipFree(ws);
+  dev_free(op->alloc, u, vb);
+  dev_free(op->alloc, v, vb);
+  dev_free(op->alloc, ws, wsb);
   return out;
+}
+
+extern "C++" {
+namespace {
+template <typename T>
+ls_status set_schedule_view(const ls_op* op, lsx::DevView<T>& d, const ls_tune_result* r) {
+  const bool f32 = std::is_same<T, float>::value;
+  const int fv = r->fft_variant;
+  if (fv != 0 && fv != 1) return fail(LS_EINVAL, "fft_variant must be 0 or 1");
+  const int tmax = (int)((150 * 1024 - d.Pa * sizeof(T) * 2) / (2 * (size_t)d.Pa * sizeof(T) * 2 * (fv + 1)));
+  if (r->fft_col_tile < 1 || r->fft_col_tile > tmax)
+    return fail(LS_EINVAL, "fft_col_tile outside 1 .. " + std::to_string(tmax));
+  if (r->fft_row_threads != 256 && r->fft_row_threads != 512 && r->fft_row_threads != 1024)
+    return fail(LS_EINVAL, "fft_row_threads must be 256, 512 or 1024");
+  if (r->fft_col_threads != 256 && r->fft_col_threads != 512)
+    return fail(LS_EINVAL, "fft_col_threads must be 256 or 512");
+  if (r->near_variant < 0 || r->near_variant > (f32 ? 3 : 0)) return fail(LS_EINVAL, "near_variant out of range");
+  if (r->csr_variant < 0 || r->csr_variant > (f32 ? 3 : 0)) return fail(LS_EINVAL, "csr_variant out of range");
+  if (r->csr_variant == 2 && !d.run_ptr) return fail(LS_EINVAL, "csr_variant 2: the op keeps no run-length columns");
+  if (r->csr_variant == 3 && d.bt_ntiles == 0) return fail(LS_EINVAL, "csr_variant 3: the op keeps no dense tiles");
+  (void)op;
+  d.fft_variant = fv;
+  d.tc = r->fft_col_tile;
+  d.rows_nth = r->fft_row_threads;
+  d.cols_nth = r->fft_col_threads;
+  d.near_variant = r->near_variant;
+  d.csr_variant = r->csr_variant;
+  return LS_OK;
+}
+template <typename T>
+void get_schedule_view(const lsx::DevView<T>& d, ls_tune_result* r) {
+  *r = ls_tune_result{};
+  r->fft_col_tile = d.tc;
+  r->near_variant = d.near_variant;
+  r->csr_variant = d.csr_variant;
+  r->fft_variant = d.fft_variant;
+  r->fft_row_threads = d.rows_nth;
+  r->fft_col_threads = d.cols_nth;
+}
+}  // namespace
+}  // extern "C++"
+
+ls_status ls_set_schedule(ls_op* op, ls_prec prec, const ls_tune_result* sched) {
+  if (!op || !sched) return fail(LS_EINVAL, "null argument");
+  if (prec != LS_C128 && prec != LS_C64) return fail(LS_EINVAL, "unknown precision");
+  std::lock_guard<std::recursive_mutex> lk(op->apply_mu);
+  return prec == LS_C128 ? set_schedule_view<double>(op, op->d64, sched) : set_schedule_view<float>(op, op->d32, sched);
+}
+
+ls_status ls_get_schedule(const ls_op* op, ls_prec prec, ls_tune_result* sched) {
+  if (!op || !sched) return fail(LS_EINVAL, "null argument");
+  if (prec != LS_C128 && prec != LS_C64) return fail(LS_EINVAL, "unknown precision");
+  if (prec == LS_C128) get_schedule_view<double>(op->d64, sched);
+  else get_schedule_view<float>(op->d32, sched);
+  return LS_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1086,11 +1195,40 @@ struct Gm {
   int nparts;
   bool cgs2 = true;
   bool use_graph = false;
+  ls_prec inner_prec = LS_C128;            // apply precision of the double-basis GMRES
+  char* base = nullptr;                    // workspace the buffers are carved from
   double apply_s = 0;
   int applies = 0;
   std::complex<double>* pinned[2] = {nullptr, nullptr};   // host copies of the two slots
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // per-stage device time (opts->profile): events in stream order, each
+  // tagged with the stage of the interval that ends at it
+  bool profile = false;
+  std::vector<hipEvent_t> marks;
+  std::vector<int> tags;
 };
+
+// record a profiling event closing an interval of stage `tag` (-1: start)
+ls_status prof(Gm& g, int tag) {
+  if (!g.profile) return LS_OK;
+  hipEvent_t e = nullptr;
+  HIPCHK(hipEventCreate(&e));
+  g.marks.push_back(e);
+  g.tags.push_back(tag);
+  HIPCHK(hipEventRecord(e, g.st));
+  return LS_OK;
+}
+
+void prof_collect(Gm& g, double* us4) {
+  for (size_t i = 1; i < g.marks.size(); ++i) {
+    float ms = 0;
+    if (g.tags[i] >= 0 && hipEventElapsedTime(&ms, g.marks[i - 1], g.marks[i]) == hipSuccess)
+      us4[g.tags[i]] += 1e3 * ms;
+  }
+  for (hipEvent_t e : g.marks) (void)hipEventDestroy(e);
+  g.marks.clear();
+  g.tags.clear();
+}
 
 size_t gm_slot(int nrhs, int m) { return (size_t)(m + 2) * nrhs * 2 + nrhs; }
 
@@ -1103,20 +1241,32 @@ size_t gm_need(const ls_op* op, int nrhs, int m) {
   return b;
 }
 
-ls_status gm_setup(Gm& g) {
+// carve the solver buffers from `ws` (caller's) or from the op's own scratch
+ls_status gm_setup(Gm& g, void* ws, size_t ws_size) {
   size_t need = gm_need(g.op, g.nrhs, g.m);
-  if (g.op->gm_bytes < need) {
-    if (g.op->gm) (void)hipFree(g.op->gm);
-    g.op->gm = nullptr;
-    g.op->gm_bytes = 0;
-    clear_graphs(g.op);     // captured steps point into the old buffer
-    if (hipMalloc(&g.op->gm, need) != hipSuccess) return fail(LS_ENOMEM, "solver workspace");
-    g.op->gm_bytes = need;
+  char* p = nullptr;
+  if (ws) {
+    if (ws_size < need) return fail(LS_EINVAL, "solver workspace too small");
+    p = (char*)ws;
+  } else {
+    if (g.op->gm_bytes < need) {
+      dev_free(g.op->alloc, g.op->gm, g.op->gm_bytes);
+      g.op->gm = nullptr;
+      g.op->gm_bytes = 0;
+      g.op->gm = dev_alloc(g.op->alloc, need);
+      if (!g.op->gm) return fail(LS_ENOMEM, "solver workspace");
+      g.op->gm_bytes = need;
+    }
+    p = (char*)g.op->gm;
   }
+  if (p != g.op->gm_last) {
+    clear_graphs(g.op);     // captured steps point into the previous workspace
+    g.op->gm_last = p;
+  }
+  g.base = p;
   if (g.use_graph && !g.op->cap_stream &&
       hipStreamCreateWithFlags(&g.op->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(LS_EDEVICE, "capture stream");
-  char* p = (char*)g.op->gm;
   auto take = [&](size_t bytes) {
     char* q = p;
     p += (bytes + 255) & ~size_t(255);
@@ -1162,18 +1312,27 @@ ls_status gm_setup(Gm& g) {
   return LS_OK;
 }
 
+// y = A x between double vectors, the apply in precision prec (single: the
+// input rounded, the output widened)
 ls_status gm_apply(Gm& g, const double2* x, double2* y, ls_prec prec) {
   auto t0 = std::chrono::steady_clock::now();
   int64_t n = g.N * g.nrhs;
-  if (prec == LS_C128) {
-    hipError_t e = lsx::launch_apply<double>(g.op->d64, x, y, g.nrhs, g.ws, g.st);
-    if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
-  } else {
-    HIPCHK(lsx::gm_to_f32(x, g.u32, n, g.st));
-    hipError_t e = lsx::launch_apply<float>(g.op->d32, g.u32, g.v32, g.nrhs, g.ws, g.st);
-    if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
-    HIPCHK(lsx::gm_to_f64(g.v32, y, n, g.st));
+  ls_status s = prof(g, 3);
+  if (s) return s;
+  {
+    std::lock_guard<std::recursive_mutex> lk(g.op->apply_mu);
+    if (prec == LS_C128) {
+      hipError_t e = lsx::launch_apply<double>(g.op->d64, x, y, g.nrhs, g.ws, g.st);
+      if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
+    } else {
+      HIPCHK(lsx::gm_to_f32(x, g.u32, n, g.st));
+      hipError_t e = lsx::launch_apply<float>(g.op->d32, g.u32, g.v32, g.nrhs, g.ws, g.st);
+      if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
+      HIPCHK(lsx::gm_to_f64(g.v32, y, n, g.st));
+    }
   }
+  s = prof(g, prec == LS_C128 ? 0 : 1);
+  if (s) return s;
   g.apply_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   g.applies++;
   return LS_OK;
@@ -1182,8 +1341,15 @@ ls_status gm_apply(Gm& g, const double2* x, double2* y, ls_prec prec) {
 // single-precision apply between single-precision vectors
 ls_status gm_apply32(Gm& g, const void* x, void* y) {
   auto t0 = std::chrono::steady_clock::now();
-  hipError_t e = lsx::launch_apply<float>(g.op->d32, x, y, g.nrhs, g.ws, g.st);
-  if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
+  ls_status s = prof(g, 3);
+  if (s) return s;
+  {
+    std::lock_guard<std::recursive_mutex> lk(g.op->apply_mu);
+    hipError_t e = lsx::launch_apply<float>(g.op->d32, x, y, g.nrhs, g.ws, g.st);
+    if (e != hipSuccess) return fail(LS_EDEVICE, hipGetErrorString(e));
+  }
+  s = prof(g, 1);
+  if (s) return s;
   g.apply_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   g.applies++;
   return LS_OK;
@@ -1199,6 +1365,8 @@ ls_status gm_dots_host(Gm& g, const double2* Vb, const double2* w, int nvec, int
   return LS_OK;
 }
 
+bool finite_c(const std::complex<double>& z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
+
 // Hessenberg matrix of one restart cycle per right-hand side (column-major
 // (m+1) x m), reduced to triangular form by Givens rotations as columns arrive.
 struct Hessenberg {
@@ -1207,7 +1375,7 @@ struct Hessenberg {
   std::vector<int> kdone;     // Krylov dimension at which each rhs met its tolerance (-1: not yet)
 
   void reset(int R_, int m_, const std::vector<double>& beta, const std::vector<double>& relres,
-             const std::vector<double>& tol) {
+             const std::vector<double>& tol, const std::vector<char>& frozen) {
     R = R_;
     m = m_;
     H.assign((size_t)R * (m + 1) * m, 0.0);
@@ -1217,7 +1385,7 @@ struct Hessenberg {
     kdone.assign(R, -1);
     for (int r = 0; r < R; ++r) {
       gv[(size_t)r * (m + 1)] = beta[r];
-      if (relres[r] <= tol[r]) kdone[r] = 0;
+      if (frozen[r] || relres[r] <= tol[r]) kdone[r] = 0;
     }
   }
 
@@ -1245,13 +1413,15 @@ struct Hessenberg {
     return std::abs(gg[k + 1]);
   }
 
-  // coefficients y[r][0..k) of the cycle's update (each rhs uses its own dimension)
+  // coefficients y[r][0..k) of the cycle's update (each rhs uses its own
+  // dimension; a zero diagonal, an exact breakdown, ends that rhs's sum)
   std::vector<std::complex<double>> solve(int k) const {
     std::vector<std::complex<double>> y((size_t)R * std::max(k, 1), 0.0);
     for (int r = 0; r < R; ++r) {
       int kk = kdone[r] >= 0 ? kdone[r] : k;
       const std::complex<double>* Hr = &H[(size_t)r * m * (m + 1)];
       const std::complex<double>* gg = &gv[(size_t)r * (m + 1)];
+      while (kk > 0 && Hr[(size_t)(kk - 1) * (m + 1) + kk - 1] == 0.0) --kk;
       std::complex<double>* yr = &y[(size_t)r * k];
       for (int i = kk - 1; i >= 0; --i) {
         std::complex<double> sacc = gg[i];
@@ -1263,28 +1433,38 @@ struct Hessenberg {
   }
 };
 
+// Per right-hand side outcome flags of a solve
+enum : char { RHS_OK = 0, RHS_NUMERIC = 1, RHS_STAGNANT = 2 };
+
 // Solve A x = f (x holds the initial guess; f and x complex double) to
 // relative residual tol.  F32: Krylov basis, work vector and operator apply
 // in single precision (reductions and the update of x in double); otherwise
-// everything in double.  The orthogonalisation is classical Gram–Schmidt,
-// applied twice when g.cgs2.  Step k+1 is queued on the stream before the
-// host waits for the Hessenberg column of step k, so the device never waits
-// for the host inside a cycle; when step k meets the tolerance the queued
-// step is discarded.
+// basis and Arnoldi in double with the apply in g.inner_prec.  The
+// orthogonalisation is classical Gram–Schmidt, applied twice when g.cgs2.
+// Step k+1 is queued on the stream before the host waits for the Hessenberg
+// column of step k, so the device never waits for the host inside a cycle;
+// when step k meets the tolerance the queued step is discarded.
+// flag[r]: a non-finite norm or Hessenberg entry freezes the right-hand side
+// at its last finite step (RHS_NUMERIC); a restart cycle that leaves its
+// residual unchanged (to 1e-12 relative) freezes it as RHS_STAGNANT: the
+// next cycle would build the same Krylov space again.
 extern "C++" {
 template <bool F32>
 ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vector<double>& tol, int max_iter,
-                int* iters, std::vector<double>& relres) {
+                int* iters, std::vector<double>& relres, std::vector<char>& flag) {
   const int R = g.nrhs, m = g.m;
   const int64_t N = g.N;
   const int64_t vstride = N * R;          // distance between basis vectors (elements)
   float2* V32 = (float2*)g.V;
   float2* w32 = (float2*)g.w;
   std::vector<std::complex<double>> dd;
-  std::vector<double> fnorm(R);
+  std::vector<double> fnorm(R), prev_beta(R, -1.0);
   ls_status s = gm_dots_host(g, f, f, 1, 0, dd);
   if (s) return s;
-  for (int r = 0; r < R; ++r) fnorm[r] = std::sqrt(std::max(0.0, dd[r].real()));
+  for (int r = 0; r < R; ++r) {
+    fnorm[r] = std::sqrt(std::max(0.0, dd[r].real()));
+    if (!std::isfinite(dd[r].real())) flag[r] = RHS_NUMERIC;
+  }
   relres.assign(R, 1.0);
   Hessenberg hs;
   int it = 0;
@@ -1314,7 +1494,7 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vec
       HIPCHK(lsx::gm_inv_norm(dn, g.sdev, R, g.st));
       HIPCHK(lsx::gm32_scale(vnext, g.sdev, N, R, g.st));
     } else {
-      st = gm_apply(g, g.V + (size_t)k * vstride, g.w, LS_C128);
+      st = gm_apply(g, g.V + (size_t)k * vstride, g.w, g.inner_prec);
       if (st) return st;
       HIPCHK(lsx::gm_cgs(g.V, g.w, nullptr, g.partial, d1, nv, N, R, vstride, g.nparts, 0, g.st));
       if (g.cgs2) HIPCHK(lsx::gm_cgs(g.V, g.w, d1, g.partial, d2, nv, N, R, vstride, g.nparts, 1, g.st));
@@ -1322,6 +1502,8 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vec
       HIPCHK(lsx::gm_inv_norm(dn, g.sdev, R, g.st));
       HIPCHK(lsx::gm_scale_copy(g.w, g.V + (size_t)(k + 1) * vstride, g.sdev, N, R, g.st));
     }
+    st = prof(g, 2);
+    if (st) return st;
     HIPCHK(hipMemcpyAsync(g.pinned[k & 1], d1, 16 * (2 * nh + R), hipMemcpyDeviceToHost, g.st));
     return LS_OK;
   };
@@ -1330,9 +1512,10 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vec
   // host waits on
   auto launch_step = [&](int k) -> ls_status {
     if (g.use_graph) {
-      const GraphKey key{F32, g.cgs2, R, m, k, (uintptr_t)g.op->gm, N};
+      const GraphKey key{F32, g.cgs2, R, m, k, (uintptr_t)g.base, N * 4 + (int64_t)g.inner_prec};
       auto it = g.op->graphs.find(key);
       if (it == g.op->graphs.end()) {
+        std::lock_guard<std::recursive_mutex> lk(g.op->apply_mu);
         hipStream_t user = g.st;
         g.st = g.op->cap_stream;
         HIPCHK(hipStreamBeginCapture(g.st, hipStreamCaptureModeRelaxed));
@@ -1379,7 +1562,7 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vec
       if (x_zero && first) {
         HIPCHK(hipMemcpyAsync(g.r, f, 16 * (size_t)N * R, hipMemcpyDeviceToDevice, g.st));
       } else {
-        s = gm_apply(g, x, g.w, LS_C128);
+        s = gm_apply(g, x, g.w, g.inner_prec);
         if (s) return s;
         HIPCHK(lsx::gm_sub(f, g.w, g.r, N * R, g.st));
       }
@@ -1390,18 +1573,22 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vec
     bool all = true;
     for (int r = 0; r < R; ++r) {
       beta[r] = std::sqrt(std::max(0.0, dd[r].real()));
+      if (!std::isfinite(dd[r].real())) flag[r] = RHS_NUMERIC;
       relres[r] = fnorm[r] > 0 ? beta[r] / fnorm[r] : 0.0;
-      if (relres[r] > tol[r]) all = false;
+      if (!flag[r] && prev_beta[r] >= 0 && relres[r] > tol[r] && beta[r] >= prev_beta[r] * (1.0 - 1e-12))
+        flag[r] = RHS_STAGNANT;
+      prev_beta[r] = beta[r];
+      if (!flag[r] && relres[r] > tol[r]) all = false;
     }
     if (all || it >= max_iter) break;
     std::vector<double> inv(R);
-    for (int r = 0; r < R; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+    for (int r = 0; r < R; ++r) inv[r] = (beta[r] > 0 && !flag[r]) ? 1.0 / beta[r] : 0.0;
     HIPCHK(hipMemcpyAsync(g.sdev, inv.data(), 8 * R, hipMemcpyHostToDevice, g.st));
     if (F32)
       HIPCHK(lsx::gm32_scale(V32, g.sdev, N, R, g.st));
     else
       HIPCHK(lsx::gm_scale_copy(g.r, g.V, g.sdev, N, R, g.st));
-    hs.reset(R, m, beta, relres, tol);
+    hs.reset(R, m, beta, relres, tol, flag);
     int k = 0;
     s = launch_step(0);
     if (s) return s;
@@ -1418,10 +1605,21 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vec
       const std::complex<double>* dn = h1 + 2 * nh;
       bool all_done = true;
       for (int r = 0; r < R; ++r) {
+        if (hs.kdone[r] >= 0) continue;
+        const std::complex<double>* c1 = h1 + (size_t)r * (k + 1);
+        const std::complex<double>* c2 = h2 ? h2 + (size_t)r * (k + 1) : nullptr;
+        bool fin = std::isfinite(dn[r].real());
+        for (int j = 0; j <= k && fin; ++j) fin = finite_c(c1[j]) && (!c2 || finite_c(c2[j]));
+        if (!fin) {
+          // keep the k finite columns of this cycle; freeze the rhs
+          flag[r] = RHS_NUMERIC;
+          hs.kdone[r] = k;
+          continue;
+        }
         double hn = std::sqrt(std::max(0.0, dn[r].real()));
-        double est = hs.column(r, k, h1 + (size_t)r * (k + 1), h2 ? h2 + (size_t)r * (k + 1) : nullptr, hn);
+        double est = hs.column(r, k, c1, c2, hn);
         est = fnorm[r] > 0 ? est / fnorm[r] : 0.0;
-        if (hs.kdone[r] < 0 && (est <= tol[r] || hn == 0.0)) hs.kdone[r] = k + 1;
+        if (est <= tol[r] || hn == 0.0) hs.kdone[r] = k + 1;
         if (hs.kdone[r] < 0) all_done = false;
       }
       if (all_done) { ++k; break; }
@@ -1443,20 +1641,40 @@ ls_status gmres(Gm& g, const double2* f, double2* x, bool x_zero, const std::vec
 
 }  // namespace
 
-ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls_solve_opts* opts,
-                   ls_solve_stats* stats, void* stream) {
-  if (!op || !u_inc || !u_tot || !opts || nrhs < 1) return fail(LS_EINVAL, "null argument");
-  if (opts->restart < 1 || opts->max_iter < 1 || !(opts->tol > 0)) return fail(LS_EINVAL, "bad solver options");
+ls_status ls_solve_workspace_size(const ls_op* op, int nrhs, const ls_solve_opts* opts, size_t* bytes) {
+  if (!op || !opts || !bytes || nrhs < 1 || opts->restart < 1) return fail(LS_EINVAL, "bad argument");
+  *bytes = gm_need(op, nrhs, opts->restart);
+  return LS_OK;
+}
+
+extern "C++" {
+namespace {
+ls_status solve_locked(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls_solve_opts* opts,
+                       ls_solve_stats* stats, void* ws, size_t ws_size, hipStream_t stream) {
   auto t0 = std::chrono::steady_clock::now();
   Gm g{};
   g.op = op;
   g.nrhs = nrhs;
   g.m = opts->restart;
   g.N = op->N;
-  g.st = (hipStream_t)stream;
+  g.st = stream;
   g.cgs2 = opts->ortho != LS_ORTHO_CGS1;
   g.use_graph = opts->graph != 0;
-  ls_status s = gm_setup(g);
+  g.profile = opts->profile != 0 && !g.use_graph;
+  ls_status s = gm_setup(g, ws, ws_size);
+  if (s) return s;
+  double us4[4] = {0, 0, 0, 0};
+  struct ProfGuard {
+    Gm& g;
+    double* us;
+    ~ProfGuard() {
+      if (!g.marks.empty()) {
+        (void)hipEventSynchronize(g.marks.back());
+        prof_collect(g, us);
+      }
+    }
+  } guard{g, us4};
+  s = prof(g, -1);
   if (s) return s;
   const double2* f = (const double2*)u_inc;
   double2* x = (double2*)u_tot;
@@ -1464,17 +1682,21 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
   if (!opts->use_x0) HIPCHK(hipMemsetAsync(x, 0, 16 * (size_t)n, g.st));
   int iters = 0, outer = 0;
   std::vector<double> rel;
+  std::vector<char> flag(nrhs, RHS_OK);
   bool have_r = false;   // g.r holds f - A x of the final iterate
   if (opts->mode == LS_SOLVE_FP64) {
-    s = gmres<false>(g, f, x, !opts->use_x0, std::vector<double>(nrhs, opts->tol), opts->max_iter, &iters, rel);
+    s = gmres<false>(g, f, x, !opts->use_x0, std::vector<double>(nrhs, opts->tol), opts->max_iter, &iters, rel,
+                     flag);
     if (s) return s;
   } else {
     // FP64 residual, FP32 inner solves, x += e.  Each inner solve stops at
     // the looser of inner_tol and half the reduction its right-hand side
     // still needs to reach tol, so the last correction is no longer than
-    // necessary.
+    // necessary.  A refinement step that no longer reduces a right-hand
+    // side's residual (to 1e-12 relative) freezes it as stagnant.
     int total = 0;
     bool xzero = !opts->use_x0;
+    std::vector<double> prev(nrhs, -1.0);
     for (outer = 0;; ++outer) {
       if (xzero) {
         HIPCHK(hipMemcpyAsync(g.rout, f, 16 * (size_t)n, hipMemcpyDeviceToDevice, g.st));
@@ -1489,8 +1711,15 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
       s = gm_dots_host(g, f, f, 1, 0, df);
       if (s) return s;
       bool all = true;
-      for (int k = 0; k < nrhs; ++k)
-        if (std::sqrt(dr[k].real()) > opts->tol * std::sqrt(df[k].real())) all = false;
+      std::vector<char> done(nrhs, 0);
+      for (int k = 0; k < nrhs; ++k) {
+        const double rn = std::sqrt(std::max(0.0, dr[k].real())), fn = std::sqrt(std::max(0.0, df[k].real()));
+        if (!std::isfinite(dr[k].real()) || !std::isfinite(df[k].real())) flag[k] = RHS_NUMERIC;
+        if (!flag[k] && prev[k] >= 0 && rn > opts->tol * fn && rn >= prev[k] * (1.0 - 1e-12)) flag[k] = RHS_STAGNANT;
+        prev[k] = rn;
+        done[k] = flag[k] || rn <= opts->tol * fn;
+        if (!done[k]) all = false;
+      }
       if (all || total >= opts->max_iter || outer >= std::max(1, opts->max_outer)) {
         HIPCHK(hipMemcpyAsync(g.r, g.rout, 16 * (size_t)n, hipMemcpyDeviceToDevice, g.st));
         have_r = true;
@@ -1498,19 +1727,27 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
       }
       std::vector<double> itol(nrhs);
       for (int k = 0; k < nrhs; ++k) {
-        const double rn = std::sqrt(dr[k].real()), fn = std::sqrt(df[k].real());
+        const double rn = std::sqrt(std::max(0.0, dr[k].real())), fn = std::sqrt(std::max(0.0, df[k].real()));
         itol[k] = rn > 0 ? std::min(0.5, std::max(opts->inner_tol, 0.5 * opts->tol * fn / rn)) : opts->inner_tol;
       }
-      // right-hand sides that already meet tol get no further correction, so
-      // each one ends exactly where its own solve would
+      // right-hand sides that are done get no further correction, so each
+      // one ends exactly where its own solve would
       for (int k = 0; k < nrhs; ++k)
-        if (std::sqrt(dr[k].real()) <= opts->tol * std::sqrt(df[k].real()))
-          HIPCHK(hipMemsetAsync(g.rout + (size_t)k * op->N, 0, 16 * (size_t)op->N, g.st));
+        if (done[k]) HIPCHK(hipMemsetAsync(g.rout + (size_t)k * op->N, 0, 16 * (size_t)op->N, g.st));
       HIPCHK(hipMemsetAsync(g.e, 0, 16 * (size_t)n, g.st));
       int it = 0;
       std::vector<double> rr;
-      s = gmres<true>(g, g.rout, g.e, true, itol, opts->max_iter - total, &it, rr);
+      std::vector<char> iflag(nrhs, RHS_OK);
+      if (opts->inner_f64_basis) {
+        g.inner_prec = LS_C64;
+        s = gmres<false>(g, g.rout, g.e, true, itol, opts->max_iter - total, &it, rr, iflag);
+        g.inner_prec = LS_C128;
+      } else {
+        s = gmres<true>(g, g.rout, g.e, true, itol, opts->max_iter - total, &it, rr, iflag);
+      }
       if (s) return s;
+      for (int k = 0; k < nrhs; ++k)
+        if (iflag[k] == RHS_NUMERIC) flag[k] = RHS_NUMERIC;
       total += it;
       HIPCHK(lsx::gm_add(x, g.e, n, g.st));
       xzero = false;
@@ -1528,11 +1765,23 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
   if (s) return s;
   s = gm_dots_host(g, f, f, 1, 0, df);
   if (s) return s;
+  s = prof(g, 3);
+  if (s) return s;
+  HIPCHK(hipStreamSynchronize(g.st));
   double worst = 0;
   int conv = 0;
+  bool numeric = false;
   for (int k = 0; k < nrhs; ++k) {
-    double rr = df[k].real() > 0 ? std::sqrt(dr[k].real() / df[k].real()) : 0.0;
-    worst = std::max(worst, rr);
+    const bool fin = std::isfinite(dr[k].real()) && std::isfinite(df[k].real());
+    double rr = !fin ? std::numeric_limits<double>::quiet_NaN()
+                     : df[k].real() > 0 ? std::sqrt(dr[k].real() / df[k].real()) : 0.0;
+    if (!fin) flag[k] = RHS_NUMERIC;
+    if (flag[k] == RHS_NUMERIC) {
+      numeric = true;
+      worst = std::numeric_limits<double>::quiet_NaN();
+      continue;
+    }
+    if (!std::isnan(worst)) worst = std::max(worst, rr);
     if (rr <= opts->tol) ++conv;
   }
   if (stats) {
@@ -1542,8 +1791,23 @@ ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls
     stats->rel_residual = worst;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats->apply_seconds = g.apply_s;
+    prof_collect(g, us4);
+    for (int i = 0; i < 4; ++i) stats->stage_us[i] = us4[i];
   }
+  if (numeric) return fail(LS_ENUMERIC, "non-finite value in the right-hand side or the iteration");
   return conv == nrhs ? LS_OK : fail(LS_ENOCONV, "tolerance not reached");
+}
+}  // namespace
+}  // extern "C++"
+
+ls_status ls_solve(ls_op* op, const void* u_inc, void* u_tot, int nrhs, const ls_solve_opts* opts,
+                   ls_solve_stats* stats, void* ws, size_t ws_size, void* stream) {
+  if (!op || !u_inc || !u_tot || !opts || nrhs < 1) return fail(LS_EINVAL, "null argument");
+  if (opts->restart < 1 || opts->max_iter < 1 || !(opts->tol > 0)) return fail(LS_EINVAL, "bad solver options");
+  if (opts->mode != LS_SOLVE_FP64 && opts->mode != LS_SOLVE_FP32_REFINE) return fail(LS_EINVAL, "unknown mode");
+  if (stats) *stats = ls_solve_stats{};
+  std::lock_guard<std::mutex> lk(op->solve_mu);
+  return solve_locked(op, u_inc, u_tot, nrhs, opts, stats, ws, ws_size, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -2131,6 +2131,9 @@ __global__ void k_axpy_combo(double2* __restrict__ x, const double2* __restrict_
   double2 acc = x[(int64_t)r * N + i];
   for (int j = 0; j < nvec; ++j) {
     double2 c = y[r * nvec + j];
+    // a zero coefficient (a right-hand side the solver froze) leaves x as it
+    // is even where its basis vector holds non-finite values
+    if (c.x == 0.0 && c.y == 0.0) continue;
     double2 a = Vb[j * vstride + (int64_t)r * N + i];
     acc.x += c.x * a.x - c.y * a.y;
     acc.y += c.x * a.y + c.y * a.x;
@@ -2395,6 +2398,7 @@ __global__ void k_axpy_combo32(double2* __restrict__ x, const float2* __restrict
   double2 acc = x[(int64_t)r * N + i];
   for (int j = 0; j < nvec; ++j) {
     const double2 c = y[r * nvec + j];
+    if (c.x == 0.0 && c.y == 0.0) continue;   // frozen right-hand side (see k_axpy_combo)
     const float2 a = Vb[j * vstride + (int64_t)r * N + i];
     acc.x += c.x * a.x - c.y * a.y;
     acc.y += c.x * a.y + c.y * a.x;

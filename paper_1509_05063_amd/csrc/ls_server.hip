@@ -6,6 +6,7 @@
 // a solve runs in the library's kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -46,6 +47,7 @@ struct SrvOp {
   int64_t N = 0;                  // 0 until first built
   std::vector<double> xy;         // node coordinates, kept across evictions
   bool busy = false;
+  size_t reserved = 0;            // solve memory reserved while busy
   uint64_t last_use = 0;
   std::deque<Req*> q;
 };
@@ -78,42 +80,58 @@ struct ls_server {
   bool stop = false;
   std::vector<std::thread> workers;
 
-  // bytes a solve of nrhs right-hand sides needs besides the operator
-  size_t solve_bytes(int64_t N, int nrhs) const {
+  // bytes a solve of nrhs right-hand sides needs besides the operator: its
+  // workspace (exact once the operator exists, else an estimate) and the
+  // right-hand sides and solutions
+  size_t solve_bytes(const SrvOp& e, int64_t N, int nrhs) const {
+    size_t ws = 0;
+    ls_solve_opts so{};
+    so.restart = o.restart;
+    if (e.op && ls_solve_workspace_size(e.op, nrhs, &so, &ws) == LS_OK) return ws + (size_t)32 * N * nrhs;
     return (size_t)16 * N * nrhs * (o.restart + 9) + ((size_t)64 << 20) * nrhs;
   }
-  // resident operators plus those being built (their estimate)
+  size_t op_bytes(const SrvOp& e, int64_t n) const { return e.op || e.bytes ? e.bytes : (size_t)n * 8000; }
+  // resident operators, those being built (their estimate) and the solve
+  // memory reserved by running solves
   size_t resident() const {
     size_t s = 0;
-    for (auto& kv : ops)
+    for (auto& kv : ops) {
       if (kv.second.op || kv.second.busy) s += kv.second.bytes;
+      if (kv.second.busy) s += kv.second.reserved;
+    }
     return s;
   }
-  // lock held: make room for op `e`; false = wait (everything else is busy)
-  bool admit(uint64_t key, SrvOp& e) {
+  // lock held: make room for op `e` and a solve of *R right-hand sides
+  // (lowered when only fewer fit).  1 = admitted, 0 = wait (others are busy),
+  // -1 = the operator and a one-right-hand-side solve alone exceed the budget
+  int admit(uint64_t key, SrvOp& e, int* R) {
     const int64_t n = e.N ? e.N : estimate_points(e.g);
-    size_t need = solve_bytes(n, o.max_batch);
-    int nbusy = 0;
-    for (auto& kv : ops)
-      if (kv.second.busy) ++nbusy;
+    const size_t ob = op_bytes(e, n);
+    if (ob + solve_bytes(e, n, 1) > budget) return -1;
     while (true) {
-      const size_t op_bytes = e.op ? 0 : (e.bytes ? e.bytes : (size_t)n * 8000);
-      if (resident() + op_bytes + need * (nbusy + 1) <= budget) {
-        if (!e.op) e.bytes = op_bytes;       // counted while it is being built
-        return true;
-      }
-      // least recently used idle resident operator, preferring ones with no queued work
+      const size_t cur = resident() + (e.op ? 0 : ob);
+      int r = *R;
+      while (r > 1 && cur + solve_bytes(e, n, r) > budget) --r;
+      // evict while the whole batch does not fit and something idle can go
       SrvOp* victim = nullptr;
-      for (int pass = 0; pass < 2 && !victim; ++pass)
-        for (auto& kv : ops) {
-          SrvOp& c = kv.second;
-          if (kv.first == key || !c.op || c.busy || (pass == 0 && !c.q.empty())) continue;
-          if (!victim || c.last_use < victim->last_use) victim = &c;
-        }
-      if (!victim) return nbusy == 0;          // nothing to evict: run alone
-      ls_destroy(victim->op);
-      victim->op = nullptr;
-      ++evictions;
+      if (cur + solve_bytes(e, n, *R) > budget)
+        for (int pass = 0; pass < 2 && !victim; ++pass)
+          for (auto& kv : ops) {
+            SrvOp& c = kv.second;
+            if (kv.first == key || !c.op || c.busy || (pass == 0 && !c.q.empty())) continue;
+            if (!victim || c.last_use < victim->last_use) victim = &c;
+          }
+      if (victim) {
+        ls_destroy(victim->op);
+        victim->op = nullptr;
+        ++evictions;
+        continue;
+      }
+      if (cur + solve_bytes(e, n, r) > budget) return 0;
+      if (!e.op) e.bytes = ob;       // counted while it is being built
+      *R = r;
+      e.reserved = solve_bytes(e, n, r);
+      return 1;
     }
   }
   // lock held: the idle operator whose oldest queued request is the oldest
@@ -140,12 +158,26 @@ struct ls_server {
       SrvOp* e = nullptr;
       while (!stop && !(e = pick(&key))) cv.wait(lk);
       if (stop) break;
-      if (!admit(key, *e)) {
+      int nb = std::min<int>((int)e->q.size(), o.max_batch);
+      const int adm = admit(key, *e, &nb);
+      if (adm == 0) {
         cv.wait_for(lk, std::chrono::milliseconds(20));
         continue;
       }
+      if (adm < 0) {
+        // can never fit: every queued request of this operator fails
+        const double td = now_s(t0);
+        for (Req* r : e->q) {
+          r->status = LS_EBUDGET;
+          r->state = 2;
+          r->t_start = r->t_done = td;
+        }
+        e->q.clear();
+        cv.notify_all();
+        continue;
+      }
       std::vector<Req*> batch;
-      while (!e->q.empty() && (int)batch.size() < o.max_batch) {
+      while (!e->q.empty() && (int)batch.size() < nb) {
         batch.push_back(e->q.front());
         e->q.pop_front();
       }
@@ -160,7 +192,7 @@ struct ls_server {
       if (!e->op) {
         // build outside the lock (host set-up takes seconds), publish under it
         ls_op* op = nullptr;
-        s = ls_create(&e->g, e->n2, e->ctx, e->kappa, &e->p, &op);
+        s = ls_create(&e->g, e->n2, e->ctx, e->kappa, &e->p, nullptr, &op);
         if (s == LS_OK) {
           int64_t n = 0;
           (void)ls_num_points(op, &n);
@@ -192,22 +224,26 @@ struct ls_server {
             h[2 * i + 1] = std::sin(ph);
           }
         }
-        void *F = nullptr, *X = nullptr;
+        void *F = nullptr, *X = nullptr, *W = nullptr;
         const size_t bytes = 16 * (size_t)R * N;
-        if (hipMalloc(&F, bytes) != hipSuccess || hipMalloc(&X, bytes) != hipSuccess) {
+        ls_solve_opts so{};
+        so.tol = o.tol;
+        so.max_iter = o.max_iter;
+        so.restart = o.restart;
+        so.mode = o.mode;
+        so.inner_tol = o.inner_tol;
+        so.max_outer = o.max_outer;
+        so.ortho = o.ortho;
+        size_t wsb = 0;
+        if (ls_solve_workspace_size(e->op, R, &so, &wsb) != LS_OK) {
+          s = LS_EINVAL;
+        } else if (hipMalloc(&F, bytes) != hipSuccess || hipMalloc(&X, bytes) != hipSuccess ||
+                   hipMalloc(&W, wsb) != hipSuccess) {
           s = LS_ENOMEM;
         } else if (hipMemcpyAsync(F, host.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
           s = LS_EDEVICE;
         } else {
-          ls_solve_opts so{};
-          so.tol = o.tol;
-          so.max_iter = o.max_iter;
-          so.restart = o.restart;
-          so.mode = o.mode;
-          so.inner_tol = o.inner_tol;
-          so.max_outer = o.max_outer;
-          so.ortho = o.ortho;
-          s = ls_solve(e->op, F, X, R, &so, &stats, st);
+          s = ls_solve(e->op, F, X, R, &so, &stats, W, wsb, st);
           if ((s == LS_OK || s == LS_ENOCONV) &&
               (hipMemcpyAsync(host.data(), X, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
                hipStreamSynchronize(st) != hipSuccess))
@@ -215,6 +251,7 @@ struct ls_server {
         }
         if (F) (void)hipFree(F);
         if (X) (void)hipFree(X);
+        if (W) (void)hipFree(W);
       }
       lk.lock();
       const double td = now_s(t0);
@@ -230,6 +267,7 @@ struct ls_server {
         q->state = 2;
       }
       e->busy = false;
+      e->reserved = 0;
       e->last_use = ++clock;
       cv.notify_all();
     }

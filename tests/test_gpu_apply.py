@@ -5,9 +5,15 @@ import math
 import numpy as np
 import pytest
 
+from gpu_helpers import fused_tile_max, schedule_cases
 from paper_1509_05063_amd.inputs import config, match_keys, n2_function, plane_wave, random_density
 
 pytestmark = pytest.mark.gpu
+
+# FP32 apply against the FP64 oracle: rounding of about 800 products per row
+# in single precision (unit roundoff 6e-8) on values of mixed sign; measured
+# 6.6e-7 on the disc
+F32_TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -61,7 +67,7 @@ def test_apply_fp32_close_to_oracle(disc):
     v_lib = v.cpu().numpy().astype(complex)[p]
     err = np.linalg.norm(v_lib - v_or) / np.linalg.norm(v_or)
     print(f"apply fp32: rel2 {err:.3e}", flush=True)
-    assert err < 1e-4
+    assert err < F32_TOL
 
 
 def test_multi_rhs_equals_single(disc):
@@ -154,13 +160,13 @@ def test_solve_matches_oracle_lu(disc, mode, ortho, restart):
 
 def test_autotune_keeps_the_operator(disc):
     """The tuned schedules apply the same operator: every row still matches
-    the oracle (FP64 to 1e-8, FP32 to 1e-4), and the choices are in range."""
+    the oracle (FP64 to 1e-8, FP32 to F32_TOL), and the choices are in range."""
     import torch
     from paper_1509_05063_amd import binding
     cfg, op, orc, A, p, xy, key = disc
     x_or = random_density(orc.pts["key"], seed=7)
     y_or = A @ x_or
-    for prec, dt, tol in ((binding.LS_C128, torch.complex128, 1e-8), (binding.LS_C64, torch.complex64, 1e-4)):
+    for prec, dt, tol in ((binding.LS_C128, torch.complex128, 1e-8), (binding.LS_C64, torch.complex64, F32_TOL)):
         ch = op.autotune(nrhs=1, prec=prec)
         print(f"autotune prec {prec}: {ch}", flush=True)
         assert ch["fft_col_tile"] in (1, 2, 4, 8, 16, 32) and ch["near_variant"] in (0, 1, 2, 3) and ch["csr_variant"] in (0, 1, 2, 3)
@@ -239,3 +245,207 @@ def test_scattered_field_off_the_disc(disc):
     assert emie < 5e-3, emie
     with pytest.raises(binding.LSError):
         op.scattered_field(x, np.array([[0.1, 0.2]]))    # inside the scatterer
+
+
+@pytest.mark.parametrize("prec_name", ["c128", "c64"])
+def test_forced_schedules_match_oracle_every_row(disc, prec_name):
+    """Every kernel variant the tuner can choose, forced through
+    ls_set_schedule, applies the oracle's operator on every row of the disc
+    (FP64 to 1e-8, FP32 to F32_TOL)."""
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    prec = binding.LS_C128 if prec_name == "c128" else binding.LS_C64
+    dt, tol = (torch.complex128, 1e-8) if prec == binding.LS_C128 else (torch.complex64, F32_TOL)
+    saved = op.get_schedule(prec)
+    x_or = random_density(orc.pts["key"], seed=21)
+    y_or = A @ x_or
+    u = torch.tensor(_to_lib(x_or, p, op.N), dtype=dt, device="cuda")
+    try:
+        for name, fields in schedule_cases(prec, fused_tile_max(op, prec)):
+            op.set_schedule(prec, **saved)
+            sch = op.set_schedule(prec, **fields)
+            v = torch.empty_like(u)
+            op.apply(u, v)
+            torch.cuda.synchronize()
+            y = v.cpu().numpy().astype(complex)[p]
+            err = np.linalg.norm(y - y_or) / np.linalg.norm(y_or)
+            emax = np.abs(y - y_or).max() / np.abs(y_or).max()
+            print(f"{prec_name} schedule {name} {sch}: rel2 {err:.2e} relmax {emax:.2e}", flush=True)
+            assert err < tol and emax < 10 * tol, (name, err, emax)
+    finally:
+        op.set_schedule(prec, **saved)
+
+
+def test_schedule_setter_rejects_out_of_range(disc):
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    saved = op.get_schedule(binding.LS_C64)
+    for bad in (dict(csr_variant=4), dict(near_variant=-1), dict(fft_variant=2), dict(fft_row_threads=128),
+                dict(fft_col_threads=1024), dict(fft_col_tile=0), dict(fft_col_tile=100000)):
+        with pytest.raises(binding.LSError):
+            op.set_schedule(binding.LS_C64, **bad)
+        assert op.get_schedule(binding.LS_C64) == saved
+    with pytest.raises(binding.LSError):
+        op.set_schedule(binding.LS_C128, csr_variant=2)      # double precision has one row kernel
+
+
+@pytest.mark.parametrize("nrhs", [16, 32])
+def test_dense_tile_rows_match_oracle(disc, nrhs):
+    """The dense-tile row kernel on the matrix cores (csr_variant 3, taken for
+    multiples of 16 right-hand sides) against the oracle on every row of every
+    right-hand side, and against the single-right-hand-side run-length rows."""
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    saved = op.get_schedule(binding.LS_C64)
+    X = np.stack([random_density(orc.pts["key"], seed=100 + r) for r in range(nrhs)])
+    Y = X @ A.T
+    U = torch.tensor(np.stack([_to_lib(x, p, op.N) for x in X]), dtype=torch.complex64, device="cuda")
+    try:
+        op.set_schedule(binding.LS_C64, csr_variant=3)
+        V = torch.empty_like(U)
+        op.apply(U, V)
+        op.set_schedule(binding.LS_C64, csr_variant=2)
+        V2 = torch.empty_like(U)
+        op.apply(U, V2)
+        torch.cuda.synchronize()
+    finally:
+        op.set_schedule(binding.LS_C64, **saved)
+    Vn = V.cpu().numpy().astype(complex)[:, p]
+    err = (np.linalg.norm(Vn - Y, axis=1) / np.linalg.norm(Y, axis=1)).max()
+    dif = (torch.linalg.norm(V - V2, dim=1) / torch.linalg.norm(V2, dim=1)).max().item()
+    print(f"dense tiles, {nrhs} right-hand sides: vs oracle {err:.2e}, vs run-length rows {dif:.2e}", flush=True)
+    assert err < F32_TOL and dif < F32_TOL
+
+
+def test_solve_inner_f64_basis_and_profile(disc):
+    """FP32 apply inside a complex-double inner Arnoldi (inner_f64_basis)
+    reaches the oracle's LU solution like the other forms; with profile set
+    the stage times are positive and bounded by the wall time."""
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    f_or = plane_wave(cfg, orc.pts["x"], 0.0)
+    u_or = np.linalg.solve(A, f_or)
+    f = torch.tensor(_to_lib(f_or, p, op.N), dtype=torch.complex128, device="cuda")
+    for basis64 in (True, False):
+        x = torch.empty_like(f)
+        st = op.solve(f, x, tol=1e-10, restart=100, max_iter=2000, mode=binding.LS_SOLVE_FP32_REFINE,
+                      inner_tol=1e-5, inner_f64_basis=basis64, profile=True)
+        err = np.linalg.norm(x.cpu().numpy()[p] - u_or) / np.linalg.norm(u_or)
+        us = st["stage_us"]
+        print(f"inner f64 basis {basis64}: {st} vs LU {err:.2e}", flush=True)
+        assert st["converged"] == 1 and err < 1e-8
+        assert us["apply_fp32"] > 0 and us["apply_fp64"] > 0 and us["arnoldi"] > 0
+        assert sum(us.values()) < 1e6 * st["seconds"]
+
+
+def test_solve_with_caller_workspace_equals_own_scratch(disc):
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    f = torch.tensor(plane_wave(cfg, xy, 0.3), dtype=torch.complex128, device="cuda")
+    kw = dict(tol=1e-10, restart=30, max_iter=2000, mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-5)
+    x0, x1 = torch.empty_like(f), torch.empty_like(f)
+    op.solve(f, x0, **kw)
+    nb = op.solve_workspace_bytes(1, restart=30)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    op.solve(f, x1, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(x0, x1)
+    with pytest.raises(binding.LSError):
+        op.solve(f, x1, workspace=ws[: nb // 2], **kw)      # too small
+
+
+def test_nan_input_reports_numeric_status(disc):
+    """A non-finite right-hand side is reported (LS_ENUMERIC) at once in both
+    modes, without running to max_iter; in a batch the finite right-hand
+    sides still converge to their own solutions."""
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    F = torch.tensor(np.stack([plane_wave(cfg, xy, a) for a in (0.0, 0.5, 1.0)]), dtype=torch.complex128,
+                     device="cuda")
+    F[1, 17] = float("nan")
+    for mode in (binding.LS_SOLVE_FP64, binding.LS_SOLVE_FP32_REFINE):
+        X = torch.empty_like(F)
+        st = op.solve(F, X, tol=1e-10, restart=100, max_iter=2000, mode=mode, inner_tol=1e-5,
+                      raise_on_noconv=False)
+        print(f"NaN right-hand side, mode {mode}: {st}", flush=True)
+        assert st["status"] == binding.LS_ENUMERIC
+        assert st["converged"] == 2 and st["iterations"] < 400
+        for k in (0, 2):
+            x1 = torch.empty_like(F[k])
+            op.solve(F[k].contiguous(), x1, tol=1e-10, restart=100, max_iter=2000, mode=mode, inner_tol=1e-5)
+            assert torch.isfinite(X[k]).all()
+            assert (torch.linalg.norm(X[k] - x1) / torch.linalg.norm(x1)).item() < 1e-8
+
+
+def test_stagnation_stops_early(disc):
+    """A tolerance below what double precision can reach stops once a
+    restart cycle no longer reduces the residual (LS_ENOCONV with the best
+    iterate), long before max_iter."""
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg, op, orc, A, p, xy, key = disc
+    f = torch.tensor(plane_wave(cfg, xy, 0.0), dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(f)
+    st = op.solve(f, x, tol=1e-30, restart=20, max_iter=100000, mode=binding.LS_SOLVE_FP64, raise_on_noconv=False)
+    print(f"tol 1e-30: {st}", flush=True)
+    assert st["status"] == binding.LS_ENOCONV and st["iterations"] < 5000 and st["rel_residual"] < 1e-12
+
+
+def test_torch_allocator_and_failing_allocator():
+    """Operator memory from PyTorch's caching allocator: the same applies as
+    with hipMalloc, the bytes show up in torch's accounting and go back at
+    destroy.  An allocator that fails on its k-th call makes ls_create return
+    LS_ENOMEM with every block it handed out released."""
+    import ctypes as C
+    import torch
+    from paper_1509_05063_amd import binding
+    cfg = config("disc_k2pi")
+    n2 = n2_function(cfg)
+    ref = binding.Operator(cfg, n2)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    op = binding.Operator(cfg, n2, allocator="torch")
+    try:
+        assert torch.cuda.memory_allocated() - before >= op.resident_bytes()
+        xy, _ = op.points()
+        u = torch.tensor(plane_wave(cfg, xy, 0.2), dtype=torch.complex128, device="cuda")
+        v0, v1 = torch.empty_like(u), torch.empty_like(u)
+        ref.apply(u, v0)
+        op.apply(u, v1)
+        x0, x1 = torch.empty_like(u), torch.empty_like(u)
+        ref.solve(u, x0, tol=1e-10, restart=50)
+        op.solve(u, x1, tol=1e-10, restart=50)
+        torch.cuda.synchronize()
+        assert torch.equal(v0, v1) and torch.equal(x0, x1)
+    finally:
+        op.close()
+        ref.close()
+    del u, v0, v1, x0, x1
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before
+
+    for fail_at in (1, 5, 40):
+        live = {}
+        calls = [0]
+
+        def _alloc(nbytes, ctx):
+            calls[0] += 1
+            if calls[0] >= fail_at:
+                return None
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            live[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _release(ptr, nbytes, ctx):
+            live.pop(ptr)
+
+        al = binding.Allocator(binding.ALLOCFN(_alloc), binding.RELEASEFN(_release), None)
+        with pytest.raises(binding.LSError) as ei:
+            binding.Operator(cfg, n2, allocator=al)
+        assert ei.value.status == binding.LS_ENOMEM
+        assert calls[0] == fail_at and not live, (fail_at, calls[0], len(live))

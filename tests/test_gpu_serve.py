@@ -43,11 +43,13 @@ def test_serving_mix_equals_solo(budget_gb, workers):
 
 
 def test_server_results_solve_the_scatterer():
-    """A served request's total field equals the operator solve of the same
-    plane wave (same point order), and polling before completion says so."""
+    """A served request's total field equals the oracle's dense LU solution
+    of the same plane wave (nodes matched by key) and the operator solve in
+    the library's point order."""
     import torch
+    from oracle.op2d import Setup2D
     from paper_1509_05063_amd import binding
-    from paper_1509_05063_amd.inputs import config, n2_function
+    from paper_1509_05063_amd.inputs import config, match_keys, n2_function
     from paper_1509_05063_amd.serve import Server
     cfg = config("disc_k2pi")
     srv = Server(budget_bytes=10e9, max_batch=4, workers=1, tol=1e-10, inner_tol=1e-5)
@@ -56,17 +58,50 @@ def test_server_results_solve_the_scatterer():
         srv.drain()
         xy = srv.points("disc")
         op = binding.Operator(cfg, n2_function(cfg))
-        xo, _ = op.points()
+        xo, key = op.points()
         assert np.array_equal(xy, xo)
+        orc = Setup2D(cfg, n2_function(cfg))
+        p = match_keys(orc.pts["key"], key)
+        A = orc.dense_A()
         for t in tickets:
             r = srv.tickets[t]
             assert r.status == binding.LS_OK and r.stats["converged"] == r.batch
+            u_or = np.linalg.solve(A, plane_wave(cfg, orc.pts["x"], r.alpha))
+            e_or = np.linalg.norm(r.result[p] - u_or) / np.linalg.norm(u_or)
             f = torch.tensor(plane_wave(cfg, xo, r.alpha), dtype=torch.complex128, device="cuda")
             x = torch.empty_like(f)
             op.solve(f, x, tol=1e-10, restart=60, max_iter=4000, mode=binding.LS_SOLVE_FP64)
             ref = x.cpu().numpy()
             err = np.linalg.norm(r.result - ref) / np.linalg.norm(ref)
+            print(f"served alpha {r.alpha}: batch {r.batch}, vs oracle LU {e_or:.2e}, vs op solve {err:.2e}",
+                  flush=True)
+            assert e_or < 1e-8, e_or
             assert err < 1e-8, err
         op.close()
+    finally:
+        srv.close()
+
+
+def test_server_rejects_an_operator_over_budget():
+    """An operator whose data and one-right-hand-side solve alone exceed the
+    budget is not run: its requests finish with LS_EBUDGET, and a scatterer
+    that fits is still served."""
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import config, scaled
+    from paper_1509_05063_amd.serve import Server
+    small = scaled(config("disc_k2pi"), h=1 / 16, band={"N1": 32, "N2": 8}, r_int=6 / 16, r1=6.0, r2=4.0)
+    big = config("star_k16pi")
+    # 300 MB: the small operator (about 1k unknowns) and its solve fit; the
+    # 270k-unknown star (estimated at 8 kB per unknown before it is built)
+    # does not, so it is never built
+    srv = Server(budget_bytes=300e6, max_batch=2, workers=1, tol=1e-8)
+    try:
+        tb = srv.submit("big", big, 0.0)
+        ts = srv.submit("small", small, 0.0)
+        srv.drain()
+        rb, rs = srv.tickets[tb], srv.tickets[ts]
+        print(f"over budget: {rb.status}, fitting: {rs.status} {rs.stats}", flush=True)
+        assert rb.status == binding.LS_EBUDGET
+        assert rs.status == binding.LS_OK
     finally:
         srv.close()
