@@ -63,11 +63,21 @@ typedef enum { LS_C128 = 0, LS_C64 = 1 } ls_prec;
  * gives none).  Boundary R(theta) = 1 + shape_a cos(shape_k theta).
  *   interior patch: lattice x = h (i1, i2), nodes where its partition of
  *                   unity is positive (s(x) = |x|/R(arg x) < s_b);
- *   boundary patch: x = s R(theta) (cos, sin), theta = 2 pi t1,
- *                   s = 1 - (1 - s_in) t2, t1 = i1/N1 (periodic),
+ *   boundary patches: x = s R(theta) (cos, sin), s = 1 - (1 - s_in) t2,
  *                   t2 = i2/N2 (0 <= i2 <= N2), interface at t2 = 0;
+ *                   n_patches <= 1: one periodic band, theta = 2 pi t1,
+ *                   t1 = i1/N1 (0 <= i1 < N1);
+ *                   n_patches = P >= 2: P overlapping patches, patch p
+ *                   spanning theta in [theta_p - D, theta_p + D] with
+ *                   theta_p = 2 pi p / P, D = pi / P + overlap, t1 = i1/N1
+ *                   (0 <= i1 <= N1) mapped linearly onto that range;
  *   partition of unity: omega_band = step((s - s_a)/(s_b - s_a)),
- *                   omega_int = 1 - omega_band. */
+ *                   omega_int = 1 - omega_band; with P >= 2 patches a
+ *                   boundary node also carries the tangential partition of
+ *                   unity b_p / sum_q b_q, b_p = step((D - |theta -
+ *                   theta_p|) / (2 overlap)), which vanishes to all orders
+ *                   at the patch ends (nodes with zero weight are not
+ *                   unknowns). */
 typedef struct {
   int dim;            /* 2 (the only value accepted) */
   double shape_a;
@@ -76,6 +86,8 @@ typedef struct {
   double s_in;
   int N1, N2;
   double s_a, s_b;
+  int n_patches;      /* boundary patches (0 or 1: one periodic band) */
+  double overlap;     /* P >= 2: half-overlap of neighbouring patches, radians, in (0, pi / P) */
 } ls_geometry;
 
 /* Quadrature and accelerator parameters (names follow the paper).
@@ -150,7 +162,7 @@ ls_status ls_num_points(const ls_op* op, int64_t* N);
 
 /* Node coordinates xy[2N] (host) in operator order and, if key != NULL,
  * key[3N] = (patch, i1, i2): patch 0 = interior lattice (i1, i2) = x/h,
- * patch 1 = boundary patch grid indices. */
+ * patch 1 + p = grid indices of boundary patch p. */
 ls_status ls_points(const ls_op* op, double* xy, int32_t* key);
 
 /* Device bytes held by the op (operator data, both precisions). */

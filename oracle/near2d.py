@@ -46,10 +46,12 @@ def eta_interior(xt, xs, cfg):
 
 
 def eta_band(vt, ut, vs, us, cfg):
-    """eta for a source on the boundary patch (grid units, t1 periodic)."""
+    """eta for a source on a boundary patch (grid units of that patch; t1
+    periodic for the single periodic band)."""
     N1 = cfg["band"]["N1"]
     dv = np.abs(vs - vt)
-    dv = np.minimum(dv, N1 - dv)
+    if cfg["band"].get("patches", 1) == 1:
+        dv = np.minimum(dv, N1 - dv)
     return chi(dv / cfg["r1"], cfg["chi_c0"]) * chi(np.abs(us - ut) / cfg["r2"], cfg["chi_c0"])
 
 
@@ -209,13 +211,18 @@ def interior_sing_row(xt, pts, lat_idx, cfg, kappa, rule=None, cache=None):
     return j[sel], w[ok][sel]
 
 
-def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None):
-    """Row of the boundary-patch singular part at a target with patch
-    coordinates (vt, ut) (grid units): K_sing = sum_j wt_j (m omega J)_j u_j."""
+def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None, patch=0):
+    """Row of boundary patch `patch`'s singular part at a target with patch
+    coordinates (vt, ut) (grid units): K_sing = sum_j wt_j (m omega J)_j u_j.
+    On a non-periodic patch the t1 rule's nodes beyond the patch ends are
+    dropped (the partition of unity makes the density vanish there) and the
+    t1 interpolation stencils are shifted one-sided at the ends, like the t2
+    stencils at the interface."""
     from .geom2d import band_map
     b = cfg["band"]
     N1, N2 = b["N1"], b["N2"]
     P = cfg["P"]
+    periodic = b.get("patches", 1) == 1
     if t1rule is None:
         t1rule = varrho_rule(cfg)
     d1, w1 = t1rule
@@ -223,14 +230,21 @@ def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None):
     if lines.size == 0:
         return np.zeros(0, np.int64), np.zeros(0, complex)
     V = vt + d1                        # (n1,)
+    if not periodic:
+        keep = (V >= 0.0) & (V <= N1)
+        V, w1 = V[keep], w1[keep]
+        if V.size == 0:
+            return np.zeros(0, np.int64), np.zeros(0, complex)
     T1 = np.broadcast_to(V[None, :] / N1, (lines.size, V.size))
     T2 = np.broadcast_to((lines / N2)[:, None], (lines.size, V.size))
-    Y = band_map(T1, T2, cfg)
+    Y = band_map(T1, T2, cfg, patch)
     r = np.hypot(Y[..., 0] - xt[0], Y[..., 1] - xt[1])
     # a node that rounds onto the target itself has zero measure: drop it
     Gr = np.where(r > 0.0, green2d(kappa, np.where(r > 0.0, r, 1.0)), 0.0)
     Wq = (w2[:, None] / N2) * (w1[None, :] / N1) * Gr                    # (nl, n1)
     bv = centered_base(V, P)
+    if not periodic:
+        bv = np.clip(bv, 0, N1 - P + 1)
     Lv = lagrange_weights(V, bv, P)                                        # (n1,P)
     bu = np.clip(centered_base(lines, P), 0, N2 - P + 1)
     Lu = lagrange_weights(lines, bu, P)                                    # (nl,P)
@@ -249,8 +263,11 @@ def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None):
         Su[bu - lo_u + bb, np.arange(lines.size)] += Lu[:, bb]
     win = Su @ Rv                                                          # (nu, nv)
     iu, iv = np.nonzero(win)
-    j = band_idx[np.mod(iv + lo_v, N1), iu + lo_u]
+    vv = np.mod(iv + lo_v, N1) if periodic else iv + lo_v
+    j = band_idx[patch][vv, iu + lo_u]
     wt = win[iu, iv]
+    # grid nodes that are not unknowns (zero partition of unity) carry no density
+    wt, j = wt[j >= 0], j[j >= 0]
     # several window columns can wrap onto one periodic index
     uj, inv = np.unique(j, return_inverse=True)
     acc = np.zeros(uj.shape[0], complex)

@@ -10,6 +10,8 @@ K_h[u](x_i) = sum_j (1 - eta_ij) G(x_i - x_j) c_j u_j          (plain part)
   boundary patch; eq:-disctete-conv for the far part).
 * eta_ij is the localisation of the patch that owns node j, centred at the
   target (eq:-VolInt-Adj-NonAdj-I); it is zero when x_i is not in that patch.
+  With several boundary patches each one contributes its own eta and its own
+  singular part at every target it contains.
   The terms with eta_ij = 1 (including j = i) drop out.
 * The split of K_h into adjacent and non-adjacent cells (eq:-VolInt-Adj-NonAdj)
   only reorganises this sum; the oracle sums every pair directly (the
@@ -41,8 +43,12 @@ class Setup2D:
         eta = np.zeros(self.N)
         n_int = p["n_int"]
         eta[:n_int] = eta_interior(x[i], x[:n_int], cfg)
-        if p["in_band"][i]:
-            eta[n_int:] = eta_band(p["v"][i], p["u"][i], p["v"][n_int:], p["u"][n_int:], cfg)
+        # sources of boundary patch k: eta centred at the target's own
+        # coordinates in patch k when it lies in patch k, else 0
+        for k in range(p["vp"].shape[0]):
+            if p["inp"][k, i]:
+                own = np.nonzero(p["chart"] == 1 + k)[0]
+                eta[own] = eta_band(p["vp"][k, i], p["u"][i], p["vp"][k, own], p["u"][own], cfg)
         f = 1.0 - eta
         row = np.zeros(self.N, complex)
         nz = f != 0.0
@@ -58,10 +64,11 @@ class Setup2D:
         j, w = interior_sing_row(p["x"][i], p, self.lat, cfg, self.kappa, self.polar_rule,
                                  self._cache)
         np.add.at(row, j, w * p["dens"][j])
-        if p["in_band"][i]:
-            j, w = band_sing_row(p["x"][i], p["v"][i], p["u"][i], p, self.bidx, cfg,
-                                 self.kappa, self.t1_rule)
-            np.add.at(row, j, w * p["dens"][j])
+        for k in range(p["vp"].shape[0]):
+            if p["inp"][k, i]:
+                j, w = band_sing_row(p["x"][i], p["vp"][k, i], p["u"][i], p, self.bidx, cfg,
+                                     self.kappa, self.t1_rule, patch=k)
+                np.add.at(row, j, w * p["dens"][j])
         return row
 
     def K_row(self, i):

@@ -23,7 +23,7 @@ LS_ORTHO_CGS2, LS_ORTHO_CGS1 = 0, 1
 class Geometry(C.Structure):
     _fields_ = [("dim", C.c_int), ("shape_a", C.c_double), ("shape_k", C.c_int), ("h", C.c_double),
                 ("s_in", C.c_double), ("N1", C.c_int), ("N2", C.c_int), ("s_a", C.c_double),
-                ("s_b", C.c_double)]
+                ("s_b", C.c_double), ("n_patches", C.c_int), ("overlap", C.c_double)]
 
 
 class Params(C.Structure):
@@ -169,7 +169,8 @@ def _check(status, where):
 def geometry_from(cfg):
     b, pou, sh = cfg["band"], cfg["pou"], cfg["shape"]
     return Geometry(2, float(sh["a"]), int(sh["k"]), float(cfg["h"]), float(b["s_in"]), int(b["N1"]),
-                    int(b["N2"]), float(pou["s_a"]), float(pou["s_b"]))
+                    int(b["N2"]), float(pou["s_a"]), float(pou["s_b"]), int(b.get("patches", 1)),
+                    float(b.get("overlap", 0.0)))
 
 
 def params_from(cfg):
@@ -536,6 +537,7 @@ class Operator:
         if getattr(self, "_op", None):
             lib().ls_destroy(self._op)
             self._op = None
+        getattr(self, "_ws", {}).clear()
 
     def __del__(self):
         try:

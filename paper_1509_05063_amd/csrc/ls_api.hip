@@ -42,6 +42,7 @@ struct ls_host_op {
   lsx::HostOp h;
 };
 
+
 using GraphKey = std::tuple<bool, bool, int, int, int, uintptr_t, int64_t>;
 
 struct ls_op {
@@ -736,7 +737,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     int64_t n_extra = 0;
     std::vector<int32_t> pos((size_t)h.ncell, -1);   // column of an adjacent cell's first point
     const size_t nr = h.rows.size();
-    auto is_band = [&](int32_t i) { return h.key[3 * (size_t)i] == 1; };
+    auto is_band = [&](int32_t i) { return h.key[3 * (size_t)i] >= 1; };
     size_t r = 0;
     while (r < nr) {
       const int c = cell_of[(size_t)h.rows[r]];

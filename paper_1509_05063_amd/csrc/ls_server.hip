@@ -60,7 +60,8 @@ double now_s(std::chrono::steady_clock::time_point t0) {
 // nodes inside s < s_b plus the boundary patch grid
 int64_t estimate_points(const ls_geometry& g) {
   const double area = M_PI * (1.0 + 0.5 * g.shape_a * g.shape_a);
-  return (int64_t)(area * g.s_b * g.s_b / (g.h * g.h)) + (int64_t)g.N1 * (g.N2 + 1);
+  const int64_t np = g.n_patches > 1 ? g.n_patches : 1;
+  return (int64_t)(area * g.s_b * g.s_b / (g.h * g.h)) + np * (int64_t)(g.N1 + 1) * (g.N2 + 1);
 }
 
 }  // namespace
@@ -103,11 +104,16 @@ struct ls_server {
   }
   // lock held: make room for op `e` and a solve of *R right-hand sides
   // (lowered when only fewer fit).  1 = admitted, 0 = wait (others are busy),
-  // -1 = the operator and a one-right-hand-side solve alone exceed the budget
+  // -1 = the operator (its exact size, known once it has been built) and a
+  // one-right-hand-side solve alone exceed the budget.  An operator never
+  // built is admitted on its size estimate, or, when the estimate alone is
+  // over the budget, once nothing else is resident or busy: its exact size
+  // is checked right after the build.
   int admit(uint64_t key, SrvOp& e, int* R) {
-    const int64_t n = e.N ? e.N : estimate_points(e.g);
+    const bool exact = e.N != 0;
+    const int64_t n = exact ? e.N : estimate_points(e.g);
     const size_t ob = op_bytes(e, n);
-    if (ob + solve_bytes(e, n, 1) > budget) return -1;
+    if (exact && ob + solve_bytes(e, n, 1) > budget) return -1;
     while (true) {
       const size_t cur = resident() + (e.op ? 0 : ob);
       int r = *R;
@@ -127,12 +133,32 @@ struct ls_server {
         ++evictions;
         continue;
       }
-      if (cur + solve_bytes(e, n, r) > budget) return 0;
+      if (cur + solve_bytes(e, n, r) > budget) {
+        bool alone = !e.op;
+        for (auto& kv : ops)
+          if (kv.first != key && (kv.second.op || kv.second.busy)) alone = false;
+        if (exact || !alone) return 0;
+        r = 1;                         // learn the exact size by building it
+      }
       if (!e.op) e.bytes = ob;       // counted while it is being built
       *R = r;
       e.reserved = solve_bytes(e, n, r);
       return 1;
     }
+  }
+  // lock held, after e was built: right-hand sides of a batch of R that fit
+  // with the exact sizes (0: not even one)
+  int fit_after_build(uint64_t key, SrvOp& e, int R) {
+    size_t others = 0;
+    for (auto& kv : ops)
+      if (kv.first != key) {
+        if (kv.second.op || kv.second.busy) others += kv.second.bytes;
+        if (kv.second.busy) others += kv.second.reserved;
+      }
+    int r = R;
+    while (r > 0 && others + e.bytes + solve_bytes(e, e.N, r) > budget) --r;
+    if (r == 0 && e.bytes + solve_bytes(e, e.N, 1) <= budget) r = 1;   // fits once the others finish
+    return r;
   }
   // lock held: the idle operator whose oldest queued request is the oldest
   SrvOp* pick(uint64_t* key) {
@@ -206,6 +232,22 @@ struct ls_server {
           e->bytes = ls_resident_bytes(op);
           e->N = n;
           if (e->xy.empty()) e->xy.swap(xy);
+          // exact sizes: drop the operator if even one right-hand side can
+          // never fit, hand back the requests that do not fit now
+          const int rf = fit_after_build(key, *e, (int)batch.size());
+          if (rf == 0) {
+            ls_destroy(e->op);
+            e->op = nullptr;
+            s = LS_EBUDGET;
+          } else {
+            while ((int)batch.size() > rf) {
+              Req* back = batch.back();
+              batch.pop_back();
+              back->state = 0;
+              e->q.push_front(back);
+            }
+            e->reserved = solve_bytes(*e, n, rf);
+          }
         }
       }
       const int R = (int)batch.size();

@@ -20,40 +20,72 @@ struct Geo {
   int k;
   double s_in, s_a, s_b;
   int N1, N2;
+  int P = 1;              // boundary patches (1: one periodic band)
+  double overlap = 0;     // half-overlap of neighbouring patches (radians), P >= 2
   double R(double th) const { return 1.0 + a * std::cos(k * th); }
-  // boundary-patch map xi(t1, t2) (Sec. 2: t2 = 0 is the interface)
-  void map(double t1, double t2, double* x) const {
-    double th = 2.0 * M_PI * t1;
+  // theta at t1 = 0 and the theta span of boundary patch p
+  double th0(int p) const { return P == 1 ? 0.0 : 2.0 * M_PI * p / P - (M_PI / P + overlap); }
+  double span() const { return P == 1 ? 2.0 * M_PI : 2.0 * (M_PI / P + overlap); }
+  // angle difference wrapped to (-pi, pi]
+  static double wrap(double d) {
+    double m = std::fmod(M_PI - d, 2.0 * M_PI);
+    if (m < 0) m += 2.0 * M_PI;
+    return M_PI - m;
+  }
+  // tangential partition of unity of patch p at angle th: normalised bumps
+  // that vanish to all orders at their patch's ends (Sec. 2, patches with a
+  // partition of unity; the formula is a reading)
+  double tan_pou(double th, int p) const {
+    if (P == 1) return 1.0;
+    const double D = M_PI / P + overlap;
+    double bp = 0, sum = 0;
+    for (int q = 0; q < P; ++q) {
+      const double b = smooth_step((D - std::fabs(wrap(th - 2.0 * M_PI * q / P))) / (2.0 * overlap));
+      sum += b;
+      if (q == p) bp = b;
+    }
+    return sum > 0 ? bp / sum : 0.0;
+  }
+  // boundary-patch map xi(t1, t2) of patch p (Sec. 2: t2 = 0 is the interface)
+  void map(double t1, double t2, double* x, int p = 0) const {
+    double th = th0(p) + span() * t1;
     double s = 1.0 - (1.0 - s_in) * t2;
     double r = s * R(th);
     x[0] = r * std::cos(th);
     x[1] = r * std::sin(th);
   }
-  double jac(double t1, double t2) const {
-    double th = 2.0 * M_PI * t1;
+  double jac(double t1, double t2, int p = 0) const {
+    double th = th0(p) + span() * t1;
     double s = 1.0 - (1.0 - s_in) * t2;
     double r = R(th);
-    return 2.0 * M_PI * (1.0 - s_in) * s * r * r;
+    return span() * (1.0 - s_in) * s * r * r;
   }
   double omega_band(double s) const { return smooth_step((s - s_a) / (s_b - s_a)); }
   double srad(const double* x) const {
     double th = std::atan2(x[1], x[0]);
     return std::hypot(x[0], x[1]) / R(th);
   }
-  // boundary-patch grid coordinates (v = t1 N1, u = t2 N2) of any point;
-  // u within 1e-9 of a grid line is put on it.  Returns whether the point is
+  // grid coordinates in patch p (v = t1 N1, u = t2 N2) of any point; u
+  // within 1e-9 of a grid line is put on it.  Returns whether the point is
   // in the closed patch.
-  bool coords(const double* x, double& v, double& u) const {
+  bool coords(const double* x, double& v, double& u, int p = 0) const {
     double th = std::atan2(x[1], x[0]);
-    double t1 = std::fmod(th / (2.0 * M_PI), 1.0);
-    if (t1 < 0) t1 += 1.0;
-    v = t1 * N1;
-    if (v >= N1) v -= N1;
+    bool vin = true;
+    if (P == 1) {
+      double t1 = std::fmod(th / (2.0 * M_PI), 1.0);
+      if (t1 < 0) t1 += 1.0;
+      v = t1 * N1;
+      if (v >= N1) v -= N1;
+    } else {
+      const double half = 0.5 * span();
+      v = (wrap(th - th0(p) - half) + half) / span() * N1;
+      vin = v >= 0.0 && v <= (double)N1;
+    }
     double s = std::hypot(x[0], x[1]) / R(th);
     u = (1.0 - s) / (1.0 - s_in) * N2;
     double ur = std::nearbyint(u);
     if (std::fabs(u - ur) < 1e-9) u = ur;
-    return u >= 0.0 && u <= (double)N2;
+    return vin && u >= 0.0 && u <= (double)N2;
   }
 };
 
@@ -252,8 +284,15 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   if (4 * p.q < 2 * p.n_fb + 1) { err = "need 4q >= 2 n_fb + 1 face values"; return LS_EINVAL; }
   if (p.r1 <= 0 || p.r2 <= 0 || p.r_int <= 0 || p.r1 > g.N1 / 2 - p.P) { err = "bad cut-off radii"; return LS_EINVAL; }
 
-  Geo G{g.shape_a, g.shape_k, g.s_in, g.s_a, g.s_b, g.N1, g.N2};
+  const int NP = g.n_patches < 1 ? 1 : g.n_patches;
+  if (NP > 1 && !(g.overlap > 0.0 && g.overlap < M_PI / NP)) {
+    err = "several boundary patches need 0 < overlap < pi / n_patches"; return LS_EINVAL;
+  }
+  if (NP > 64) { err = "at most 64 boundary patches"; return LS_EINVAL; }
+  Geo G{g.shape_a, g.shape_k, g.s_in, g.s_a, g.s_b, g.N1, g.N2, NP, NP > 1 ? g.overlap : 0.0};
   const int N1 = g.N1, N2 = g.N2;
+  const bool periodic = NP == 1;
+  const int n1g = periodic ? N1 : N1 + 1;      // t1 grid nodes per patch
 
   // ---------------------------------------------------------------- nodes
   struct Node { int chart; int64_t i1, i2; double x, y, w, om, J; };
@@ -270,14 +309,23 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   std::vector<double> ncw(N2 + 1, 0.0);
   for (int pnl = 0; pnl < N2 / (p.Q - 1); ++pnl)
     for (int k = 0; k < p.Q; ++k) ncw[pnl * (p.Q - 1) + k] += nc[k];
-  for (int j1 = 0; j1 < N1; ++j1)
-    for (int j2 = 0; j2 <= N2; ++j2) {
-      double t1 = (double)j1 / N1, t2 = (double)j2 / N2;
-      double x[2];
-      G.map(t1, t2, x);
-      double s = 1.0 - (1.0 - g.s_in) * t2;
-      double J = G.jac(t1, t2);
-      nodes.push_back({1, j1, j2, x[0], x[1], ncw[j2] * J / ((double)N1 * N2), G.omega_band(s), J});
+  // boundary patches: trapezoid in t1 (non-periodic patches: the end nodes
+  // carry a zero partition of unity and are not unknowns) x composite
+  // Newton–Cotes in t2; the node's partition of unity is the transverse one
+  // times the tangential one
+  for (int pp = 0; pp < NP; ++pp)
+    for (int j1 = 0; j1 < n1g; ++j1) {
+      const double t1 = (double)j1 / N1;
+      const double omt = G.tan_pou(G.th0(pp) + G.span() * t1, pp);
+      if (!(omt > 0.0)) continue;
+      for (int j2 = 0; j2 <= N2; ++j2) {
+        double t2 = (double)j2 / N2;
+        double x[2];
+        G.map(t1, t2, x, pp);
+        double s = 1.0 - (1.0 - g.s_in) * t2;
+        double J = G.jac(t1, t2, pp);
+        nodes.push_back({1 + pp, j1, j2, x[0], x[1], ncw[j2] * J / ((double)N1 * N2), G.omega_band(s) * omt, J});
+      }
     }
   const int64_t N = (int64_t)nodes.size();
   op.N = N;
@@ -289,7 +337,7 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   for (int64_t i = 0; i < N; ++i) {
     xy0[2 * i] = nodes[i].x;
     xy0[2 * i + 1] = nodes[i].y;
-    onb[i] = (nodes[i].chart == 1 && nodes[i].i2 == 0) ? 1 : 0;
+    onb[i] = (nodes[i].chart >= 1 && nodes[i].i2 == 0) ? 1 : 0;
   }
   n2fn(N, xy0.data(), onb.data(), n2v.data(), ctx);
 
@@ -391,11 +439,15 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   // lattice (i1, i2) -> op index; boundary grid (j1, j2) -> op index
   const int64_t lside = 2 * imax + 1;
   std::vector<int32_t> lat(lside * lside, -1);
-  std::vector<int32_t> bgrid((size_t)N1 * (N2 + 1), -1);
+  // boundary grids: patch p, (j1, j2) -> op index (-1: not an unknown)
+  std::vector<int32_t> bgrid((size_t)NP * n1g * (N2 + 1), -1);
+  auto bg = [&](int pp, int64_t j1, int64_t j2) -> int32_t& {
+    return bgrid[((size_t)pp * n1g + j1) * (N2 + 1) + j2];
+  };
   for (int64_t k = 0; k < N; ++k) {
     int32_t c = op.key[3 * k], i1 = op.key[3 * k + 1], i2 = op.key[3 * k + 2];
     if (c == 0) lat[(i1 + imax) * lside + (i2 + imax)] = (int32_t)k;
-    else bgrid[(size_t)i1 * (N2 + 1) + i2] = (int32_t)k;
+    else bg(c - 1, i1, i2) = (int32_t)k;
   }
   auto lat_at = [&](int64_t i1, int64_t i2) -> int32_t {
     if (i1 < -imax || i1 > imax || i2 < -imax || i2 > imax) return -1;
@@ -410,22 +462,35 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   Stencil Ton = interior_stencil(0.0, 0.0, prho, pw, p, h, kappa);
 
   // boundary singular row at (vt, ut) for target point xt -> (op index, coeff)
-  auto band_sing = [&](const double* xt, double vt, double ut, std::vector<std::pair<int32_t, cd>>& out) {
+  // On a non-periodic patch the t1 rule's nodes beyond the patch ends are
+  // dropped (the partition of unity makes the density vanish there) and the
+  // t1 stencils are shifted one-sided at the ends.
+  auto band_sing = [&](const double* xt, double vt, double ut, int pp, std::vector<std::pair<int32_t, cd>>& out) {
     std::vector<double> lines, w2;
     multisplit(ut, N2, p.Q, p.r2, p.chi_c0, nc, lines, w2);
     if (lines.empty()) return;
     const int P = p.P;
     const int nk = (int)d1.size();
     int64_t vlo = centered_base(vt - p.r1, P) - 1, vhi = centered_base(vt + p.r1, P) + P + 1;
+    if (!periodic) {
+      vlo = std::max<int64_t>(vlo, 0);
+      vhi = std::min<int64_t>(vhi, N1);
+    }
     int nvw = (int)(vhi - vlo + 1);
     int64_t ulo = 0, uhi = N2;
     int nuw = (int)(uhi - ulo + 1);
     std::vector<cd> win((size_t)nvw * nuw, 0.0), Rv(nvw);
     std::vector<double> Lv((size_t)nk * P);
     std::vector<int64_t> bv(nk);
+    std::vector<char> use(nk, 1);
     for (int k = 0; k < nk; ++k) {
       double V = vt + d1[k];
+      if (!periodic && (V < 0.0 || V > (double)N1)) {
+        use[k] = 0;
+        continue;
+      }
       bv[k] = centered_base(V, P);
+      if (!periodic) bv[k] = std::min<int64_t>(std::max<int64_t>(bv[k], 0), N1 - P + 1);
       lagrange(V, bv[k], P, &Lv[(size_t)k * P]);
     }
     double Lu[32];
@@ -433,9 +498,10 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
       std::fill(Rv.begin(), Rv.end(), cd(0.0));
       double T2 = lines[l] / N2;
       for (int k = 0; k < nk; ++k) {
+        if (!use[k]) continue;
         double V = vt + d1[k];
         double y[2];
-        G.map(V / N1, T2, y);
+        G.map(V / N1, T2, y, pp);
         double r = std::hypot(y[0] - xt[0], y[1] - xt[1]);
         if (!(r > 0.0)) continue;
         cd W = (w2[l] / N2) * (w1[k] / N1) * green2d(kappa, r);
@@ -452,9 +518,9 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
       for (int v = 0; v < nvw; ++v) {
         cd c = win[(size_t)u * nvw + v];
         if (c == 0.0) continue;
-        int64_t vv = ((vlo + v) % N1 + N1) % N1;
-        int32_t j = bgrid[(size_t)vv * (N2 + 1) + (ulo + u)];
-        out.emplace_back(j, c * dens[j]);
+        int64_t vv = periodic ? ((vlo + v) % N1 + N1) % N1 : vlo + v;
+        int32_t j = bg(pp, vv, ulo + u);
+        if (j >= 0) out.emplace_back(j, c * dens[j]);
       }
   };
 
@@ -484,27 +550,35 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   // ------------------------------------------------------ CSR rows
   // Rows: every boundary-patch target (all sources) and every interior
   // target with boundary-patch sources (adjacent, cut-off or singular rule).
-  std::vector<char> in_band(N, 0);
-  std::vector<double> tv(N), tu(N);
+  // every point's grid coordinates in every boundary patch (inp: whether it
+  // lies in that patch); t2 (tu) is the same in all patches
+  std::vector<char> inp((size_t)NP * N, 0);
+  std::vector<double> tvp((size_t)NP * N), tu(N);
   for (int64_t k = 0; k < N; ++k) {
-    if (op.key[3 * k] == 1) {
-      in_band[k] = 1;
-      tv[k] = op.key[3 * k + 1];
-      tu[k] = op.key[3 * k + 2];
-    } else {
-      in_band[k] = G.coords(&op.xy[2 * k], tv[k], tu[k]) ? 1 : 0;
+    const int ck = op.key[3 * k];
+    for (int pp = 0; pp < NP; ++pp) {
+      double v, u;
+      bool in = G.coords(&op.xy[2 * k], v, u, pp);
+      if (ck == 1 + pp) {     // a node of this patch: exact grid coordinates
+        in = true;
+        v = op.key[3 * k + 1];
+        u = op.key[3 * k + 2];
+      }
+      inp[(size_t)pp * N + k] = in ? 1 : 0;
+      tvp[(size_t)pp * N + k] = v;
+      tu[k] = u;
     }
   }
   auto eta_band = [&](double vt, double ut, double vs, double us) {
     double dv = std::fabs(vs - vt);
-    dv = std::min(dv, N1 - dv);
+    if (periodic) dv = std::min(dv, N1 - dv);
     return chi(dv / p.r1, p.chi_c0) * chi(std::fabs(us - ut) / p.r2, p.chi_c0);
   };
   std::vector<std::vector<std::pair<int32_t, cd>>> rowdata(N);
   std::vector<char> has_row(N, 0);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t i = 0; i < N; ++i) {
-    const bool tb = op.key[3 * i] == 1;
+    const bool tb = op.key[3 * i] >= 1;
     const double* xi = &op.xy[2 * i];
     const int ci = cell_of_op[i];
     const int cx = op.cell_xy[2 * ci], cy = op.cell_xy[2 * ci + 1];
@@ -529,11 +603,15 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
             continue;
           }
           double eta;
-          if (op.key[3 * j] == 0) {
+          const int cj = op.key[3 * j];
+          if (cj == 0) {
             double d = std::hypot(op.xy[2 * j] - xi[0], op.xy[2 * j + 1] - xi[1]);
             eta = chi(d / p.r_int, p.chi_c0);
           } else {
-            eta = in_band[i] ? eta_band(tv[i], tu[i], tv[j], tu[j]) : 0.0;
+            // the localisation of the source's own patch, centred at the
+            // target's coordinates in that patch (0 if the target is not in it)
+            const size_t o = (size_t)(cj - 1) * N;
+            eta = inp[o + i] ? eta_band(tvp[o + i], tu[i], tvp[o + j], tu[j]) : 0.0;
           }
           double f = 1.0 - eta;
           if (f == 0.0) {
@@ -557,21 +635,28 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
           if (eta != 0.0) ent.emplace_back(j, -eta * green2d(kappa, d) * op.cw[j]);
         }
     }
-    if (in_band[i]) {
-      int64_t v0 = (int64_t)std::floor(tv[i] - p.r1) - 1, v1 = (int64_t)std::ceil(tv[i] + p.r1) + 1;
+    for (int pp = 0; pp < NP; ++pp) {
+      const size_t o = (size_t)pp * N;
+      if (!inp[o + i]) continue;
+      const double tvi = tvp[o + i];
+      int64_t v0 = (int64_t)std::floor(tvi - p.r1) - 1, v1 = (int64_t)std::ceil(tvi + p.r1) + 1;
+      if (!periodic) {
+        v0 = std::max<int64_t>(v0, 0);
+        v1 = std::min<int64_t>(v1, N1);
+      }
       int64_t u0 = std::max<int64_t>(0, (int64_t)std::floor(tu[i] - p.r2) - 1);
       int64_t u1 = std::min<int64_t>(N2, (int64_t)std::ceil(tu[i] + p.r2) + 1);
       for (int64_t v = v0; v <= v1; ++v)
         for (int64_t u = u0; u <= u1; ++u) {
-          int64_t vv = ((v % N1) + N1) % N1;
-          int32_t j = bgrid[(size_t)vv * (N2 + 1) + u];
-          if (j == i || adjacent(j)) continue;
-          double eta = eta_band(tv[i], tu[i], tv[j], tu[j]);
+          int64_t vv = periodic ? ((v % N1) + N1) % N1 : v;
+          int32_t j = bg(pp, vv, u);
+          if (j < 0 || j == i || adjacent(j)) continue;
+          double eta = eta_band(tvi, tu[i], tvp[o + j], tu[j]);
           if (eta == 0.0) continue;
           double d = std::hypot(op.xy[2 * j] - xi[0], op.xy[2 * j + 1] - xi[1]);
           ent.emplace_back(j, -eta * green2d(kappa, d) * op.cw[j]);
         }
-      band_sing(xi, tv[i], tu[i], ent);
+      band_sing(xi, tvi, tu[i], pp, ent);
     }
     if (tb) {
       // interior polar rule centred off the lattice

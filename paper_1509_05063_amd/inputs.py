@@ -57,6 +57,12 @@ def config(name):
     star_sincos_k2  the same star at kappa = 2 with the smooth variable index
                 n = sin(pi x1) cos(pi x2) (vanishing on lines through the
                 scatterer), h = 1/32, band 0.8 < s < 1 with 128 x 16 intervals
+    disc_k2pi_p2    disc_k2pi with the band covered by two overlapping
+                boundary patches (half-overlap 0.35 rad) with a tangential
+                partition of unity, 40 x 16 intervals each (about the
+                periodic band's t1 spacing)
+    star_sincos_k2_p3  star_sincos_k2 with three boundary patches
+                (half-overlap 0.3 rad), 56 x 16 intervals each
     """
     if name == "disc_k2pi":
         c = _base(TWO_PI, 1.0 / 32, 0.0, 0, 0.8, 64, 16, 0.8, 0.95)
@@ -78,6 +84,12 @@ def config(name):
         c["n2"] = {"kind": "sincos"}
         c["incidence"] = [0.0]
         c["gmres"] = {"tol": 1e-10, "restart": 100}
+    elif name == "disc_k2pi_p2":
+        c = config("disc_k2pi")
+        c["band"].update({"N1": 40, "patches": 2, "overlap": 0.35})
+    elif name == "star_sincos_k2_p3":
+        c = config("star_sincos_k2")
+        c["band"].update({"N1": 56, "patches": 3, "overlap": 0.3})
     else:
         raise KeyError(name)
     c["name"] = name

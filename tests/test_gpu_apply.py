@@ -449,3 +449,41 @@ def test_torch_allocator_and_failing_allocator():
             binding.Operator(cfg, n2, allocator=al)
         assert ei.value.status == binding.LS_ENOMEM
         assert calls[0] == fail_at and not live, (fail_at, calls[0], len(live))
+
+
+@pytest.mark.parametrize("name", ["disc_k2pi_p2", "star_sincos_k2_p3"])
+def test_several_boundary_patches_match_oracle(name):
+    """Boundary covered by two / three overlapping patches with a tangential
+    partition of unity: both precisions' applies against the oracle on every
+    row, and both solve forms against the oracle's dense LU solution."""
+    import torch
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd import binding
+    cfg = config(name)
+    n2 = n2_function(cfg)
+    op = binding.Operator(cfg, n2)
+    orc = Setup2D(cfg, n2)
+    xy, key = op.points()
+    p = match_keys(orc.pts["key"], key)
+    A = orc.dense_A()
+    x_or = random_density(orc.pts["key"], seed=13)
+    y_or = A @ x_or
+    for dt, tol in ((torch.complex128, 1e-8), (torch.complex64, F32_TOL)):
+        u = torch.tensor(_to_lib(x_or, p, op.N), dtype=dt, device="cuda")
+        v = torch.empty_like(u)
+        op.apply(u, v)
+        torch.cuda.synchronize()
+        y = v.cpu().numpy().astype(complex)[p]
+        err = np.linalg.norm(y - y_or) / np.linalg.norm(y_or)
+        print(f"{name} N={op.N} apply {dt}: {err:.2e}", flush=True)
+        assert err < tol, (dt, err)
+    f_or = plane_wave(cfg, orc.pts["x"], 0.4)
+    u_or = np.linalg.solve(A, f_or)
+    f = torch.tensor(_to_lib(f_or, p, op.N), dtype=torch.complex128, device="cuda")
+    for mode in (binding.LS_SOLVE_FP64, binding.LS_SOLVE_FP32_REFINE):
+        x = torch.empty_like(f)
+        st = op.solve(f, x, tol=1e-10, restart=100, max_iter=2000, mode=mode, inner_tol=1e-5)
+        e = np.linalg.norm(x.cpu().numpy()[p] - u_or) / np.linalg.norm(u_or)
+        print(f"{name} solve mode {mode}: {st} vs LU {e:.2e}", flush=True)
+        assert st["converged"] == 1 and e < 1e-8, e
+    op.close()

@@ -9,11 +9,30 @@ from paper_1509_05063_amd.inputs import plane_wave, serving_pool, serving_trace
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("budget_gb,workers", [(40, 3), (0.05, 2)])
+def _one_op_budget(pool):
+    """A budget that holds any one of the pool's operators with a solve of
+    four right-hand sides but not two operators with a solve of one."""
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import n2_function
+    need = []
+    for c in pool:
+        op = binding.Operator(dict(c, skip_tiles=1), n2_function(c))
+        need.append((op.resident_bytes(), op.solve_workspace_bytes(1, restart=60) + 32 * op.N,
+                     op.solve_workspace_bytes(4, restart=60) + 128 * op.N))
+        op.close()
+    budget = max(a + c for a, _, c in need)
+    print(f"pool sizes (operator, solve of 1, solve of 4): {need}, budget {budget}", flush=True)
+    assert 2 * min(a for a, _, _ in need) + min(b for _, b, _ in need) > budget
+    return budget
+
+
+@pytest.mark.parametrize("budget_gb,workers", [(40, 3), (None, 2)])
 def test_serving_mix_equals_solo(budget_gb, workers):
     from paper_1509_05063_amd.serve import Server, latency_stats, replay
     pool = [c for c in serving_pool() if 1 / c["h"] <= 64]      # the small scatterers (~17k unknowns)
     trace = serving_trace(pool, 40, rate=50.0)
+    if budget_gb is None:
+        budget_gb = _one_op_budget(pool) / 1e9
     srv = Server(budget_bytes=budget_gb * 1e9, max_batch=8, workers=workers)
     try:
         reqs, wall = replay(srv, trace)

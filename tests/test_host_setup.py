@@ -48,9 +48,38 @@ def _cells(cfg, key, xy):
     return c
 
 
+@pytest.fixture(scope="module", params=["disc_k2pi_p2", "star_sincos_k2_p3"])
+def patches(request):
+    cfg = config(request.param)
+    n2 = n2_function(cfg)
+    return cfg, binding.HostOperator(cfg, n2), Setup2D(cfg, n2)
+
+
+def test_several_patches_same_nodes_and_weights(patches):
+    """Several boundary patches: the library and the oracle build the same
+    nodes and plain quadrature weights, the partition of unity sums to one
+    at every node, and the weights integrate the area of the scatterer."""
+    cfg, host, orc = patches
+    xy, key = host.points()
+    p = match_keys(orc.pts["key"], key)
+    assert np.abs(xy[p] - orc.pts["x"]).max() < 1e-14
+    assert set(np.unique(key[:, 0])) == set(range(cfg["band"]["patches"] + 1))
+    a = cfg["shape"]["a"]
+    assert abs(np.sum(orc.pts["w"] * orc.pts["omega"]) - math.pi * (1 + a * a / 2)) < 5e-4
+
+
+@pytest.mark.parametrize("which", ["interior", "band", "interior_in_band", "overlap"])
+def test_near_rows_complete_oracle_rows_several_patches(patches, which):
+    _check_rows(patches, which)
+
+
 @pytest.mark.parametrize("which", ["interior", "band", "interior_in_band"])
 def test_near_rows_complete_oracle_rows(disc, which):
-    cfg, host, orc = disc
+    _check_rows(disc, which)
+
+
+def _check_rows(setup, which):
+    cfg, host, orc = setup
     xy, key = host.points()
     p = match_keys(orc.pts["key"], key)       # p[i_oracle] = library index
     inv = np.empty_like(p)
@@ -60,7 +89,11 @@ def test_near_rows_complete_oracle_rows(disc, which):
     if which == "interior":
         cand = np.where((key[:, 0] == 0) & (s < 0.5))[0]
     elif which == "band":
-        cand = np.where(key[:, 0] == 1)[0]
+        cand = np.where(key[:, 0] >= 1)[0]
+    elif which == "overlap":
+        # points of a boundary patch that also lie in another patch
+        inp = orc.pts["inp"][:, inv]
+        cand = np.where((key[:, 0] >= 1) & (inp.sum(axis=0) >= 2))[0]
     else:
         cand = np.where((key[:, 0] == 0) & (s > 0.82))[0]
     rng = np.random.default_rng(7)
