@@ -197,6 +197,23 @@ ls_status ls_workspace_size(const ls_op* op, int nrhs, ls_prec prec, size_t* byt
 ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* ls_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result as ls_apply, with the workspace taken from a
+ * static device array of the library (LS_NOALLOC_SCRATCH_BYTES = 96 MiB per
+ * device, held from the first ls_create on that device until the process
+ * ends) instead of a caller buffer.  Allocates nothing.  Every call on one
+ * device shares that device's array and no call needs it cleared first;
+ * calls that overlap in time on one device (any op, any stream) race on it
+ * and must be ordered by the caller.  LS_EINVAL when the apply needs more
+ * than the array holds (ls_workspace_size tells how much it needs; e.g.
+ * about 75 MiB for one single-precision vector at 946k unknowns), or as
+ * ls_apply; LS_EDEVICE as ls_apply. */
+ls_status ls_apply_noalloc(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, void* stream);
+
+/* Size of the static scratch of ls_apply_noalloc, in bytes. */
+ls_status ls_noalloc_scratch_bytes(size_t* bytes);
+
 /* One ls_apply with its stages in order on `stream` (the near field not
  * forked) and HIP events recorded between them; waits for completion and
  * writes the stage durations (milliseconds) to

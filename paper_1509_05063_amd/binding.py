@@ -106,6 +106,8 @@ def lib():
             "ls_workspace_size": (C.c_int, [C.c_void_p, C.c_int, C.c_int, P(C.c_size_t)]),
             "ls_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
                                    C.c_size_t, C.c_void_p]),
+            "ls_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]),
+            "ls_noalloc_scratch_bytes": (C.c_int, [P(C.c_size_t)]),
             "ls_apply_profile": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p,
                                            C.c_size_t, C.c_void_p, P(C.c_double), C.c_int]),
             "ls_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, P(SolveOpts), P(SolveStats),
@@ -432,6 +434,16 @@ class Operator:
         ws = self.workspace(nrhs, prec)
         _check(lib().ls_apply(self._op, _ptr(u), _ptr(v), nrhs, prec, _ptr(ws), ws.numel(), _stream(stream)),
                "ls_apply")
+        return v
+
+    def apply_noalloc(self, u, v, stream=None):
+        """v = u + kappa^2 K_h u with the library's static device scratch
+        (ls_apply_noalloc: no workspace, no allocation)."""
+        import torch
+        nrhs = check_vectors(u, self.N, (torch.complex128, torch.complex64), "u")
+        check_vectors(v, self.N, (u.dtype,), "v", nrhs)
+        prec = LS_C128 if u.dtype == torch.complex128 else LS_C64
+        _check(lib().ls_apply_noalloc(self._op, _ptr(u), _ptr(v), nrhs, prec, _stream(stream)), "ls_apply_noalloc")
         return v
 
     STAGES = ["project", "fill", "fft_fwd", "spectral", "fft_inv", "interp", "near_shared", "near_csr"]

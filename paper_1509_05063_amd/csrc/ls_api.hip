@@ -42,6 +42,33 @@ struct ls_host_op {
   lsx::HostOp h;
 };
 
+// Device scratch of ls_apply_noalloc: a file-scope array (each device that
+// loads the library holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel: it is a host-side stand-in;
+// the per-device address comes from hipGetSymbolAddress at set-up.
+constexpr size_t LS_NOALLOC_SCRATCH_BYTES = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[LS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;     // device -> address of its scratch copy
+
+// called with `device` current (ls_create); once per device
+hipError_t init_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return hipSuccess;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) g_scratch_ptr[device] = ptr;
+  return e;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+}  // namespace
 
 using GraphKey = std::tuple<bool, bool, int, int, int, uintptr_t, int64_t>;
 
@@ -450,6 +477,15 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   ls_op* op = new (std::nothrow) ls_op();
   if (!op) { ls_host_destroy(hb); return fail(LS_ENOMEM, "host allocation"); }
   (void)hipGetDevice(&op->device);
+  {
+    // address of this device's copy of the no-allocation scratch
+    hipError_t e = init_scratch(op->device);
+    if (e != hipSuccess) {
+      ls_host_destroy(hb);
+      delete op;
+      return fail(LS_EDEVICE, std::string("scratch symbol address: ") + hipGetErrorString(e));
+    }
+  }
   if (alloc) {
     if (!alloc->alloc || !alloc->release) {
       ls_host_destroy(hb);
@@ -922,6 +958,33 @@ ls_status ls_apply(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, vo
   hipError_t e = prec == LS_C128 ? lsx::launch_apply<double>(op->d64, u, v, nrhs, ws, st)
                                  : lsx::launch_apply<float>(op->d32, u, v, nrhs, ws, st);
   if (e != hipSuccess) return fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
+  return LS_OK;
+}
+
+ls_status ls_apply_noalloc(ls_op* op, const void* u, void* v, int nrhs, ls_prec prec, void* stream) {
+  if (!op || !u || !v || nrhs < 1) return fail(LS_EINVAL, "null argument or nrhs < 1");
+  if (prec != LS_C128 && prec != LS_C64) return fail(LS_EINVAL, "unknown precision");
+  const size_t need = ws_bytes(op, nrhs, prec);
+  if (need > LS_NOALLOC_SCRATCH_BYTES)
+    return fail(LS_EINVAL, "apply needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                               std::to_string(LS_NOALLOC_SCRATCH_BYTES));
+  const size_t vb = (size_t)nrhs * op->N * (prec == LS_C128 ? 16 : 8);
+  const char* uc = (const char*)u;
+  const char* vc = (const char*)v;
+  if (uc < vc + vb && vc < uc + vb) return fail(LS_EINVAL, "u and v overlap");
+  void* ws = scratch_of(op->device);
+  if (!ws) return fail(LS_EDEVICE, "no scratch address for the op's device");
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::recursive_mutex> lk(op->apply_mu);
+  hipError_t e = prec == LS_C128 ? lsx::launch_apply<double>(op->d64, u, v, nrhs, ws, st)
+                                 : lsx::launch_apply<float>(op->d32, u, v, nrhs, ws, st);
+  if (e != hipSuccess) return fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
+  return LS_OK;
+}
+
+ls_status ls_noalloc_scratch_bytes(size_t* bytes) {
+  if (!bytes) return fail(LS_EINVAL, "null argument");
+  *bytes = LS_NOALLOC_SCRATCH_BYTES;
   return LS_OK;
 }
 
