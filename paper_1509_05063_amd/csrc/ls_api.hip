@@ -559,11 +559,16 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   a.csr_f64 = true;
   b.csr_f64 = false;
   int max_nb = 0;
-  std::vector<int32_t> icells;
+  std::vector<int32_t> icells, bcells;
   for (int c = 0; c < h.ncell; ++c) {
     max_nb = std::max(max_nb, h.cell_nb[c]);
     if (h.cell_nint[c] > 0) icells.push_back(c);
+    if (h.cell_nb[c] > 0) bcells.push_back(c);
   }
+  a.nbcell = b.nbcell = (int)bcells.size();
+  // the band projection kernel stages a cell's nodes for 16 right-hand
+  // sides in LDS
+  if ((size_t)(max_nb + 96) * 16 * 16 > 150 * 1024) a.proj_mfma = b.proj_mfma = false;
   a.max_nb = b.max_nb = max_nb;
   a.nicell = b.nicell = (int)icells.size();
   a.pa = b.pa = make_plan(h.Pa);
@@ -650,6 +655,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   UP(upload_i(op, h.cell_xy, &a.cell_xy));
   UP(upload_i(op, h.cell_map, &a.cell_map));
   UP(upload_i(op, icells, &a.icells));
+  if (!bcells.empty()) UP(upload_i(op, bcells, &a.bcells));
   UP(upload_i(op, h.rows, &a.rows));
   {
     // columns as 16-bit offsets from the row's smallest column (a row spans
@@ -856,6 +862,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   b.cell_xy = a.cell_xy;
   b.cell_map = a.cell_map;
   b.icells = a.icells;
+  b.bcells = a.bcells;
   b.rows = a.rows;
   b.colbase = a.colbase;
   b.coloff = a.coloff;

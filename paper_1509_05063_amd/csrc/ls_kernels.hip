@@ -194,6 +194,134 @@ __global__ void __launch_bounds__(192) k_project_rb(const typename C2<T>::t* __r
   }
 }
 
+// a1 on the matrix cores, interior slots (q = 12: U = 96 sources, S = 64
+// slots).  The slot projection Psh is the same for every cell, so the
+// interior part of all cells and right-hand sides is one product
+// Psh [96 x 64] x Phi [64 x (cells x rhs)]: a column is one (interior cell,
+// right-hand side) pair, phi = c u gathered through the slot map.  Psh sits
+// transposed in LDS; each wave takes 16 columns, 6 row tiles of 16 sources,
+// 16 steps of 4 slots; complex products as four real 16x16x4 MFMAs.  Every
+// column's sums run in one fixed order, so a vector's strengths do not
+// depend on the other columns of its launch (alone or in a batch).
+template <typename T>
+__global__ void __launch_bounds__(256) k_project_int(const typename C2<T>::t* __restrict__ u,
+                                                     typename C2<T>::t* __restrict__ sigma,
+                                                     const typename C2<T>::t* __restrict__ PshT,
+                                                     const T* __restrict__ cw, const int32_t* __restrict__ slot_map,
+                                                     const int32_t* __restrict__ icells, int nicell, int ncell,
+                                                     int64_t N, int nrhs) {
+  using V = typename C2<T>::t;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int U = 96, S = 64;
+  extern __shared__ unsigned char smem_raw[];
+  V* A = reinterpret_cast<V*>(smem_raw);      // PshT [S][U]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
+  for (int i = tid; i < S * U; i += blockDim.x) A[i] = PshT[i];
+  const int64_t ncols = (int64_t)nicell * nrhs;
+  const int64_t gc = ((int64_t)blockIdx.x * 4 + wave) * 16 + col;
+  const bool valid = gc < ncols;
+  const int r = valid ? (int)(gc / nicell) : 0;
+  const int c = valid ? icells[gc % nicell] : 0;
+  // this lane's operand B: slots kl, kl + 4, ... of its column
+  V b[S / 4];
+#pragma unroll
+  for (int kk = 0; kk < S / 4; ++kk) {
+    b[kk] = czero<V>();
+    if (valid) {
+      const int j = slot_map[(int64_t)c * S + 4 * kk + kl];
+      if (j >= 0) b[kk] = cscale(u[(int64_t)r * N + j], cw[j]);
+    }
+  }
+  __syncthreads();
+  v4 re[U / 16], im[U / 16];
+#pragma unroll
+  for (int rt = 0; rt < U / 16; ++rt) {
+    re[rt] = v4{0, 0, 0, 0};
+    im[rt] = v4{0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int kk = 0; kk < S / 4; ++kk) {
+    const V bb = b[kk];
+    const V* arow = A + (4 * kk + kl) * U + col;
+#pragma unroll
+    for (int rt = 0; rt < U / 16; ++rt) {
+      const V a = arow[16 * rt];
+      re[rt] = M::op(a.x, bb.x, re[rt]);
+      re[rt] = M::op(-a.y, bb.y, re[rt]);
+      im[rt] = M::op(a.x, bb.y, im[rt]);
+      im[rt] = M::op(a.y, bb.x, im[rt]);
+    }
+  }
+  if (!valid) return;
+  V* out = sigma + ((int64_t)r * ncell + c) * U;
+#pragma unroll
+  for (int rt = 0; rt < U / 16; ++rt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      V o;
+      o.x = re[rt][q];
+      o.y = im[rt][q];
+      out[16 * rt + M::row(lane, q)] = o;
+    }
+}
+
+// a1, boundary-patch nodes of a cell (their projection columns Pbd differ
+// node by node): sigma[r][c] += sum_b Pbd_b phi_b for RB right-hand sides
+// per workgroup, added to the interior part k_project_int wrote (cells with
+// interior nodes) or started from zero.  Thread (t, g): source t, the nodes
+// b = g mod 2; the odd half is added to the even one through LDS.  The sums
+// of one output run in the same order for every RB, so results do not
+// depend on the batch.
+template <typename T, int RB>
+__global__ void __launch_bounds__(192) k_project_band(const typename C2<T>::t* __restrict__ u,
+                                                      typename C2<T>::t* __restrict__ sigma,
+                                                      const typename C2<T>::t* __restrict__ Pbd,
+                                                      const T* __restrict__ cw, const int32_t* __restrict__ bcells,
+                                                      const int32_t* __restrict__ cell_start,
+                                                      const int32_t* __restrict__ cell_nint,
+                                                      const int32_t* __restrict__ cell_nb,
+                                                      const int32_t* __restrict__ cell_boff, int64_t N, int ncell,
+                                                      int nrhs) {
+  using V = typename C2<T>::t;
+  constexpr int U = 96;
+  extern __shared__ unsigned char smem_raw[];
+  const int c = bcells[blockIdx.x], r0 = blockIdx.y * RB, tid = threadIdx.x;
+  const int nb = cell_nb[c];
+  V* phi = reinterpret_cast<V*>(smem_raw);   // [nb][RB]
+  V* red = phi + (size_t)nb * RB;            // [RB][U] odd half's sums
+  const int64_t b0 = cell_start[c] + cell_nint[c];
+  for (int i = tid; i < nb * RB; i += blockDim.x) {
+    const int bb = i % nb, q = i / nb, r = r0 + q;    // consecutive threads: consecutive nodes
+    const int64_t j = b0 + bb;
+    phi[bb * RB + q] = r < nrhs ? cscale(u[(int64_t)r * N + j], cw[j]) : czero<V>();
+  }
+  __syncthreads();
+  const int t = tid % U, g = tid / U;
+  const bool has_int = cell_nint[c] > 0;
+  V acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q)
+    acc[q] = (g == 0 && has_int && r0 + q < nrhs) ? sigma[((int64_t)(r0 + q) * ncell + c) * U + t] : czero<V>();
+  const V* prow = Pbd + (int64_t)cell_boff[c] * U + t;
+  for (int bb = g; bb < nb; bb += 2) {
+    const V p = prow[(int64_t)bb * U];
+    const V* ph = phi + bb * RB;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = cfma(p, ph[q], acc[q]);
+  }
+  if (g == 1) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) red[q * U + t] = acc[q];
+  }
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (r0 + q < nrhs) sigma[((int64_t)(r0 + q) * ncell + c) * U + t] = cadd(acc[q], red[q * U + t]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Lattice fill: node (a, b) of set s gathers face 0 of the cell whose
 // normal index is a and face 1 of the cell a-1 (at most two cells, no
@@ -2519,7 +2647,30 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       size_t sh = (size_t)(d.S + d.max_nb) * sizeof(V);
       constexpr int RB = sizeof(T) == 4 ? 16 : 8;
       const size_t shb = ((size_t)(64 + d.max_nb) * RB + (size_t)RB * 96) * sizeof(V);
-      if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
+      if (d.q == 12 && d.S == 64 && d.PshT && d.bcells && d.proj_mfma) {
+        // interior slots of every cell on the matrix cores, then the
+        // boundary-patch nodes cell by cell
+        if (d.nicell > 0) {
+          const int64_t ncols = (int64_t)d.nicell * nrhs;
+          hipLaunchKernelGGL(k_project_int<T>, dim3((unsigned)((ncols + 63) / 64)), dim3(256),
+                             (size_t)64 * 96 * sizeof(V), st, u, sigma, (const V*)d.PshT, d.cw, d.slot_map,
+                             d.icells, d.nicell, d.ncell, d.N, nrhs);
+        }
+        if (d.nbcell > 0) {
+          const int RBB = nrhs >= 16 ? 16 : nrhs >= 4 ? 4 : 1;
+          const size_t shp = ((size_t)d.max_nb * RBB + (size_t)RBB * 96) * sizeof(V);
+          const dim3 gb(d.nbcell, (nrhs + RBB - 1) / RBB);
+          if (RBB == 16)
+            hipLaunchKernelGGL((k_project_band<T, 16>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
+                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
+          else if (RBB == 4)
+            hipLaunchKernelGGL((k_project_band<T, 4>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
+                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
+          else
+            hipLaunchKernelGGL((k_project_band<T, 1>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
+                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
+        }
+      } else if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
         hipLaunchKernelGGL((k_project_rb<T, RB>), dim3(d.ncell, (nrhs + RB - 1) / RB), dim3(192), shb, st, u, sigma,
                            (const V*)d.PshT, (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb,
                            d.cell_boff, d.N, d.ncell, nrhs);
@@ -2816,6 +2967,14 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_rows<float, -1, 256>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
+  set((const void*)k_project_int<double>);
+  set((const void*)k_project_int<float>);
+  set((const void*)k_project_band<double, 16>);
+  set((const void*)k_project_band<double, 4>);
+  set((const void*)k_project_band<double, 1>);
+  set((const void*)k_project_band<float, 16>);
+  set((const void*)k_project_band<float, 4>);
+  set((const void*)k_project_band<float, 1>);
   set((const void*)k_fft_cols_conv<double, 256>);
   set((const void*)k_fft_cols_conv<float, 256>);
   set((const void*)k_fft_cols_conv<double, 512>);

@@ -39,6 +39,12 @@ struct DevView {
   const T *cw = nullptr, *dw = nullptr;
   const int32_t *slot_map = nullptr, *cell_start = nullptr, *cell_nint = nullptr, *cell_nb = nullptr;
   const int32_t *cell_boff = nullptr, *cell_xy = nullptr, *cell_map = nullptr, *icells = nullptr;
+  // cells holding boundary-patch nodes, and whether the projection runs on
+  // the matrix cores (k_project_int + k_project_band; else the older
+  // per-cell kernels)
+  const int32_t* bcells = nullptr;
+  int nbcell = 0;
+  bool proj_mfma = true;
   const int32_t *rows = nullptr, *colbase = nullptr;
   const uint16_t* coloff = nullptr;   // column = colbase[row] + coloff[k] (16-bit form)
   const int32_t* cols32 = nullptr;    // column = colbase[row] + cols32[k] (when a row spans > 65535)
