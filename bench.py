@@ -221,12 +221,16 @@ def multi_rhs_run(nrhs, ortho, autotune):
         op.close()
 
 
-def serving_run(n_requests, rate=20.0, ortho=None, restart=60):
+def serving_run(n_requests, rate=50.0, ortho=None, restart=60, wide=True):
     """Poisson stream of solves over a warm pool of resident operators
-    (continuous batching per operator, concurrent solves across operators)."""
-    from paper_1509_05063_amd.inputs import serving_pool, serving_trace
+    (continuous batching per operator, concurrent solves across operators).
+    wide: the 2-D part of the mixed stream (8 stars, N log-uniform in 16k-1M,
+    kappa up to 32 pi); else six small stars.  When the offered rate exceeds
+    what the server completes, requests queue: reported as the backlog (time
+    from the last arrival to the last completion) and the sustained rate."""
+    from paper_1509_05063_amd.inputs import serving_pool, serving_pool_wide, serving_trace
     from paper_1509_05063_amd.serve import Server, latency_stats, replay
-    pool = serving_pool()
+    pool = serving_pool_wide() if wide else serving_pool()
     from paper_1509_05063_amd import binding
     srv = Server(budget_bytes=200e9, max_batch=16, workers=4, keep_results=False, restart=restart,
                  ortho=binding.LS_ORTHO_CGS1 if ortho is None else ortho)
@@ -236,18 +240,28 @@ def serving_run(n_requests, rate=20.0, ortho=None, restart=60):
             srv.submit(c["name"], c, 0.0)
         srv.drain()
         warm = time.time() - t0
+        warm_stats = {r.key: (r.N, r.stats["iterations"], round(r.latency * 1e3, 1)) for r in srv.tickets.values()}
         srv.tickets.clear()
-        reqs, wall = replay(srv, serving_trace(pool, n_requests, rate=rate))
+        trace = serving_trace(pool, n_requests, rate=rate)
+        reqs, wall = replay(srv, trace)
         st = latency_stats(reqs)
         conv = sum(1 for r in reqs if r.stats["converged"] == r.batch)
-        iters = {}
+        iters, lat_by = {}, {}
         for r in reqs:
             iters[r.key] = max(iters.get(r.key, 0), r.stats["iterations"])
+            lat_by.setdefault(r.key, []).append((r.done - r.arrival) * 1e3)
+        t_first = min(r.arrival for r in reqs)
+        last_arrival = max(r.arrival for r in reqs) - t_first
+        last_done = max(r.done for r in reqs) - t_first
         return {"requests": len(reqs), "rate_per_s": rate, "operators": len(pool),
                 "N_range": [min(r.N for r in reqs), max(r.N for r in reqs)],
+                "kappa_over_pi_range": [round(min(c["kappa"] for c in pool) / math.pi, 2),
+                                        round(max(c["kappa"] for c in pool) / math.pi, 2)],
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch"],
-                "solves_per_s": len(reqs) / wall, "all_converged": conv == len(reqs), "warmup_s": warm,
-                "max_iterations": iters}
+                "solves_per_s": len(reqs) / wall, "sustained_solves_per_s": len(reqs) / last_done,
+                "backlog_s": last_done - last_arrival, "all_converged": conv == len(reqs), "warmup_s": warm,
+                "solo_N_iterations_ms": warm_stats, "max_iterations": iters,
+                "median_latency_ms_by_scatterer": {k: round(float(np.median(v)), 1) for k, v in lat_by.items()}}
     finally:
         srv.close()
 
@@ -375,6 +389,10 @@ def main():
                     help="skip the dense oracle timing on the 4k-unknown disc in the CPU baseline")
     ap.add_argument("--serving-requests", type=int, default=300,
                     help="requests in the serving measurement (0 skips it)")
+    ap.add_argument("--serving-rate", type=float, default=50.0, help="mean Poisson arrival rate (requests/s)")
+    ap.add_argument("--serving-small", action="store_true",
+                    help="serve the six small stars (16.7k-230k unknowns) instead of the wide 2-D mix")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving measurement")
     ap.add_argument("--ortho", choices=["cgs1", "cgs2"], default="cgs1",
                     help="Gram-Schmidt passes per Arnoldi step of the single-precision inner solves")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel schedules")
@@ -409,6 +427,9 @@ def main():
         return
     if args.profile_fft256:
         log(f"profile fft256 {fft256_run(args.profile_fft256)}")
+        return
+    if args.serving_only:
+        log(f"serving {serving_run(args.serving_requests, rate=args.serving_rate, wide=not args.serving_small)}")
         return
 
     import torch
@@ -577,7 +598,7 @@ def main():
 
     serving = None
     if args.serving_requests:
-        serving = serving_run(args.serving_requests, ortho=ortho)
+        serving = serving_run(args.serving_requests, rate=args.serving_rate, ortho=ortho, wide=not args.serving_small)
         log(f"serving {serving}")
 
     cpu = None

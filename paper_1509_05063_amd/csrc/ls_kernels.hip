@@ -850,8 +850,7 @@ __global__ void __launch_bounds__(256) k_fft_lines2(const float2* src, float2* d
 #pragma unroll
     for (int m = 0; m < R1; ++m) {
       const int e = j + m * R2;
-      const V t = x[min(e, ne - 1)];
-      v[m] = e < ne ? t : czero<V>();
+      v[m] = e < ne ? x[e] : czero<V>();     // masked: padding is not loaded
     }
     dft_r<V, DIR, R1>(v);
 #pragma unroll
@@ -884,7 +883,7 @@ __global__ void __launch_bounds__(256) k_fft_lines2(const float2* src, float2* d
 
 // Column transforms of length n = R1 R2 (two Stockham passes) without
 // staging: the first pass reads its R1 inputs per column straight from
-// memory (rows past nload are zero padding: clamped loads, zeroed), writes
+// memory (rows past nload are zero padding, not loaded), writes
 // the intermediate to one LDS buffer; after one barrier the second pass
 // (twiddles from LDS) writes rows < nstore straight back.  Same grid,
 // arguments and results as k_fft_cols, half its LDS and none of its staging
@@ -912,8 +911,7 @@ __global__ void __launch_bounds__(256) k_fft_cols2(float2* data, const float2* _
 #pragma unroll
     for (int m = 0; m < R1; ++m) {
       const int row = j + m * R2;
-      const V t = x[(int64_t)min(row, nl - 1) * ncols + col];
-      v[m] = row < nl ? t : czero<V>();
+      v[m] = row < nl ? x[(int64_t)row * ncols + col] : czero<V>();   // masked: padding is not loaded
     }
     dft_r<V, DIR, R1>(v);
 #pragma unroll
@@ -961,9 +959,11 @@ __global__ void __launch_bounds__(256) k_fft_conv_octant2(float2* lat, const flo
   using V = float2;
   constexpr int n = R1 * R2, TC = 16, W = 32;
   extern __shared__ unsigned char smem_raw[];
-  V* A = reinterpret_cast<V*>(smem_raw);     // [n][W], later [n][TC]
-  V* B = A + n * W;                          // [n][W]
-  V* twl = B + n * W;                        // [n]
+  // one buffer (19 KB, so eight workgroups fit a compute unit): [n][W]
+  // through the forward passes (the radix-R2 pass writes back exactly the
+  // entries it read), then [n][TC] from the inverse radix-R1 pass on
+  V* A = reinterpret_cast<V*>(smem_raw);
+  V* twl = A + n * W;                        // [n]
   const int ncols = Pb * Pc;
   const int hb = Pb / 2 + 1, hc = Pc / 2 + 1;
   const int64_t hsz = (int64_t)(n / 2 + 1) * hb * hc;
@@ -974,39 +974,38 @@ __global__ void __launch_bounds__(256) k_fft_conv_octant2(float2* lat, const flo
   V* mp = lat + (int64_t)blockIdx.y * 2 * vol + c0;
   const int t = threadIdx.x;
   for (int i = t; i < n; i += 256) twl[i] = tw[i];
-  // octant entries for this thread's product rows (inverse pass 1: column
-  // c = t % TC, rows j + m R2 with j = t / TC < R2)
-  V pg[R1], pd[R1];
-  {
-    const int c = t % TC, jj = min(t / TC, R2 - 1);
+  // octant offset of this thread's product column (inverse pass 1: column
+  // c = t % TC); the entries are loaded in that pass, from L2 (holding them
+  // in registers through the forward transform, or staging the tile's
+  // octant rows in LDS, measured slower)
+  int64_t koff = 0;
+  if (t < R2 * TC) {
+    const int c = t % TC;
     const FastDiv fpc(Pc);
     const int cg = c0 + min(c, tc - 1), kb = fpc.div(cg), kc = cg - kb * Pc;
     const int mb = kb <= Pb - kb ? kb : Pb - kb, mc = kc <= Pc - kc ? kc : Pc - kc;
-#pragma unroll
-    for (int m = 0; m < R1; ++m) {
-      const int row = jj + m * R2, ma = row <= n - row ? row : n - row;
-      const int64_t k = ((int64_t)ma * hb + mb) * hc + mc;
-      pg[m] = khs[k];
-      pd[m] = khs[hsz + k];
-    }
+    koff = (int64_t)mb * hc + mc;
   }
   const int nr = min(na, n);
-  // forward pass 1 (radix R1, span 1): butterfly j < R2 of column lane
+  // forward pass 1 (radix R1, span 1): butterfly j < R2 of column lane;
+  // rows >= nr are zero padding and not loaded (masked loads, so a wave
+  // whose rows all lie in the padding issues no request)
   if (t < R2 * W) {
     const int j = t / W, lane = t % W, kind = lane / TC, col = min(lane % TC, tc - 1);
+    const V* src = mp + kind * vol + col;
     V v[R1];
 #pragma unroll
     for (int m = 0; m < R1; ++m) {
       const int row = j + m * R2;
-      const V x = mp[kind * vol + (int64_t)min(row, nr - 1) * rstride + col];
-      v[m] = row < nr ? x : czero<V>();
+      v[m] = row < nr ? src[(int64_t)row * rstride] : czero<V>();
     }
     dft_r<V, 1, R1>(v);
 #pragma unroll
     for (int m = 0; m < R1; ++m) A[(j * R1 + m) * W + lane] = v[m];
   }
   __syncthreads();
-  // forward pass 2 (radix R2, span R1): butterfly j < R1
+  // forward pass 2 (radix R2, span R1): butterfly j < R1, in place (it
+  // writes back the rows j + m R1 it read, so no barrier between)
   for (int w = t; w < R1 * W; w += 256) {
     const int j = w / W, lane = w % W;
     V v[R2];
@@ -1018,14 +1017,23 @@ __global__ void __launch_bounds__(256) k_fft_conv_octant2(float2* lat, const flo
     }
     dft_r<V, 1, R2>(v);
 #pragma unroll
-    for (int m = 0; m < R2; ++m) B[(j + m * R1) * W + lane] = v[m];
+    for (int m = 0; m < R2; ++m) A[(j + m * R1) * W + lane] = v[m];
   }
   __syncthreads();
   // spectral product and inverse pass 1 (radix R1, span 1): butterfly j < R2
-  // of column c; the dipole spectrum is odd along the normal axis
+  // of column c; the dipole spectrum is odd along the normal axis.  Its
+  // output layout [n][TC] overlaps other threads' inputs: all read first.
+  V vi[R1];
   if (t < R2 * TC) {
     const int j = t / TC, c = t % TC;
-    V v[R1];
+    V pg[R1], pd[R1];
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const int row = j + m * R2, ma = row <= n - row ? row : n - row;
+      const int64_t k = (int64_t)ma * hb * hc + koff;
+      pg[m] = khs[k];
+      pd[m] = khs[hsz + k];
+    }
 #pragma unroll
     for (int m = 0; m < R1; ++m) {
       const int row = j + m * R2;
@@ -1034,12 +1042,16 @@ __global__ void __launch_bounds__(256) k_fft_conv_octant2(float2* lat, const flo
         d.x = -d.x;
         d.y = -d.y;
       }
-      V o = cmul(B[row * W + c], pg[m]);
-      v[m] = cfma(B[row * W + TC + c], d, o);
+      V o = cmul(A[row * W + c], pg[m]);
+      vi[m] = cfma(A[row * W + TC + c], d, o);
     }
-    dft_r<V, -1, R1>(v);
+    dft_r<V, -1, R1>(vi);
+  }
+  __syncthreads();
+  if (t < R2 * TC) {
+    const int j = t / TC, c = t % TC;
 #pragma unroll
-    for (int m = 0; m < R1; ++m) A[(j * R1 + m) * TC + c] = v[m];
+    for (int m = 0; m < R1; ++m) A[(j * R1 + m) * TC + c] = vi[m];
   }
   __syncthreads();
   // inverse pass 2 (radix R2, span R1): butterfly j < R1; rows < na stored
@@ -2933,7 +2945,7 @@ hipError_t launch_fft_strided(bool dbl, int dir, void* data, const void* tw, con
 hipError_t launch_fft_conv_octant(void* data, const void* tw, const void* khs, const FftPlan& plan, int Pb, int Pc,
                                   int TC, int nth, int64_t rstride, int64_t vol, int na, int nsets, hipStream_t st) {
   if (TC == 16 && nth == 256 && plan.npass == 2 && plan.radix[0] == 12 && plan.radix[1] == 6) {
-    const size_t sh2 = (2 * 32 + 1) * (size_t)plan.n * sizeof(float2);
+    const size_t sh2 = (32 + 1) * (size_t)plan.n * sizeof(float2);
     hipLaunchKernelGGL((k_fft_conv_octant2<12, 6>), dim3(xcd_grid((Pb * Pc + 15) / 16), nsets), dim3(256), sh2, st,
                        (float2*)data, (const float2*)tw, (const float2*)khs, Pb, Pc, rstride, vol, na);
     return hipGetLastError();

@@ -187,6 +187,32 @@ def serving_pool(n_ops=6, seed=20509, n_range=(1.05, 1.25), kappa_range=(4 * mat
     return pool
 
 
+def serving_pool_wide(n_ops=8, seed=20509, N_range=(16e3, 1e6), kappa_range=(4 * math.pi, 32 * math.pi),
+                      n_range=(1.05, 1.25)):
+    """The 2-D part of the mixed serving stream: star scatterers
+    R = 1 + a cos(k theta), a ~ U[0, 0.3], k ~ U{3..7}, unknowns log-uniform
+    in N_range (lattice 1/h the power of two in 64..512 nearest to it on a log
+    scale: about 3.6 / h^2 unknowns), kappa ~ U[kappa_range] lowered where
+    needed to keep at least 10 points per interior wavelength and the cells
+    below resonance (kappa H < pi sqrt 2), constant n ~ U[n_range]."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(n_ops):
+        a = float(rng.uniform(0.0, 0.3))
+        k = int(rng.integers(3, 8))
+        n = float(rng.uniform(*n_range))
+        target = math.exp(rng.uniform(math.log(N_range[0]), math.log(N_range[1])))
+        level = min((64, 128, 256, 512), key=lambda L: abs(math.log(3.6 * L * L / target)))
+        kappa = float(rng.uniform(*kappa_range))
+        kappa = min(kappa, 2 * math.pi * level / (10 * n), 0.95 * math.pi * math.sqrt(2) * level / 8)
+        N2 = max(8, 4 * round(level / 64))
+        c = _base(kappa, 1.0 / level, a, k, 0.9, 8 * level, N2, 0.9, 0.975)
+        c["n2"] = {"kind": "const", "value": n * n}
+        c["name"] = f"wide{i}"
+        pool.append(c)
+    return pool
+
+
 def serving_trace(pool, n_requests, rate=50.0, seed=20509):
     """Poisson arrivals (mean `rate` per second) of solves on a scatterer drawn
     uniformly from `pool`, incidence angle uniform in [0, 2 pi).
