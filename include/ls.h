@@ -229,11 +229,13 @@ ls_status ls_apply_profile(ls_op* op, const void* u, void* v, int nrhs, ls_prec 
 typedef struct {
   int fft_col_tile;     /* columns per workgroup of the column transforms */
   int near_variant;     /* interior contraction: 0 double-buffered staging (16 cells per
-                           workgroup), 1 single-buffered, 2 / 3 double-buffered with 32 / 64 cells */
+                           workgroup), 1 single-buffered, 2 / 3 double-buffered with 32 / 64 cells,
+                           4 as 3 with each complex product as three real matrix products */
   int csr_variant;      /* boundary-patch rows: 0 four entries per lane, 1 one entry per lane,
                            2 four entries per lane with run-length column storage,
                            3 dense 16-row tiles on the matrix cores (candidate for multiples
-                           of 16 right-hand sides) */
+                           of 16 right-hand sides), 4 as 3 with three real products per
+                           complex product */
   int fft_variant;      /* 0 separate column transforms and spectral product, 1 fused per column tile */
   int fft_row_threads;  /* threads per workgroup of the row transforms (256, 512 or 1024) */
   int fft_col_threads;  /* threads per workgroup of the fused column kernel (256 or 512) */
@@ -247,11 +249,11 @@ typedef struct {
  * fft_col_tile ... fft_col_threads of *sched; the timing fields are
  * ignored), e.g. to force one variant.  The schedule changes which kernels
  * run, not the discrete operator.  Ranges: fft_col_tile 1 ... the LDS limit
- * (LS_EINVAL beyond it), near_variant 0-3 (single precision; double
- * precision has one interior kernel and accepts 0), csr_variant 0-3
- * (single precision; 2 needs the run-length columns, 3 the dense tiles, and
- * falls back to 2 when nrhs is not a multiple of 16; double precision
- * accepts 0), fft_variant 0 / 1, fft_row_threads 256 / 512 / 1024,
+ * (LS_EINVAL beyond it), near_variant 0-4 (single precision; double
+ * precision has one interior kernel and accepts 0), csr_variant 0-4
+ * (single precision; 2 needs the run-length columns, 3 and 4 the dense
+ * tiles, and fall back to 2 when nrhs is not a multiple of 16; double
+ * precision accepts 0), fft_variant 0 / 1, fft_row_threads 256 / 512 / 1024,
  * fft_col_threads 256 / 512.  LS_EINVAL leaves the schedule unchanged.  Not
  * to be called while applies or solves on op are in flight. */
 ls_status ls_set_schedule(ls_op* op, ls_prec prec, const ls_tune_result* sched);

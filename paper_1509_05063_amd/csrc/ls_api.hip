@@ -1109,7 +1109,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->fft_col_threads = d.cols_nth;
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
-  const int nnear = std::is_same<T, float>::value ? 4 : 1;
+  const int nnear = std::is_same<T, float>::value ? 5 : 1;
   int bv = 0;
   best = 1e30;
   for (int var = 0; var < nnear; ++var) {
@@ -1132,7 +1132,10 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   if (std::is_same<T, float>::value) {
     csr_cands.push_back(1);
     if (d.run_ptr) csr_cands.push_back(2);
-    if (d.bt_ntiles > 0 && nrhs % 16 == 0) csr_cands.push_back(3);
+    if (d.bt_ntiles > 0 && nrhs % 16 == 0) {
+      csr_cands.push_back(3);
+      csr_cands.push_back(4);
+    }
   }
   for (int var : csr_cands) {
     d.csr_variant = var;
@@ -1205,10 +1208,10 @@ ls_status set_schedule_view(const ls_op* op, lsx::DevView<T>& d, const ls_tune_r
     return fail(LS_EINVAL, "fft_row_threads must be 256, 512 or 1024");
   if (r->fft_col_threads != 256 && r->fft_col_threads != 512)
     return fail(LS_EINVAL, "fft_col_threads must be 256 or 512");
-  if (r->near_variant < 0 || r->near_variant > (f32 ? 3 : 0)) return fail(LS_EINVAL, "near_variant out of range");
-  if (r->csr_variant < 0 || r->csr_variant > (f32 ? 3 : 0)) return fail(LS_EINVAL, "csr_variant out of range");
+  if (r->near_variant < 0 || r->near_variant > (f32 ? 4 : 0)) return fail(LS_EINVAL, "near_variant out of range");
+  if (r->csr_variant < 0 || r->csr_variant > (f32 ? 4 : 0)) return fail(LS_EINVAL, "csr_variant out of range");
   if (r->csr_variant == 2 && !d.run_ptr) return fail(LS_EINVAL, "csr_variant 2: the op keeps no run-length columns");
-  if (r->csr_variant == 3 && d.bt_ntiles == 0) return fail(LS_EINVAL, "csr_variant 3: the op keeps no dense tiles");
+  if (r->csr_variant >= 3 && d.bt_ntiles == 0) return fail(LS_EINVAL, "csr_variant 3 / 4: the op keeps no dense tiles");
   (void)op;
   d.fft_variant = fv;
   d.tc = r->fft_col_tile;

@@ -197,14 +197,18 @@ __global__ void __launch_bounds__(192) k_project_rb(const typename C2<T>::t* __r
 // a1 on the matrix cores, interior slots (q = 12: U = 96 sources, S = 64
 // slots).  The slot projection Psh is the same for every cell, so the
 // interior part of all cells and right-hand sides is one product
-// Psh [96 x 64] x Phi [64 x (cells x rhs)]: a column is one (interior cell,
-// right-hand side) pair, phi = c u gathered through the slot map.  Psh sits
-// transposed in LDS; each wave takes 16 columns, 6 row tiles of 16 sources,
-// 16 steps of 4 slots; complex products as four real 16x16x4 MFMAs.  Every
-// column's sums run in one fixed order, so a vector's strengths do not
-// depend on the other columns of its launch (alone or in a batch).
-template <typename T>
-__global__ void __launch_bounds__(256) k_project_int(const typename C2<T>::t* __restrict__ u,
+// Sigma^T [(cells x rhs) x 96] = Phi^T [(cells x rhs) x 64] Psh^T [64 x 96]:
+// a row of Phi^T is one (interior cell, right-hand side) pair, phi = c u
+// gathered through the slot map.  Psh^T sits in LDS (one copy for the 8
+// waves of a workgroup); each wave takes 16 pairs (MFMA A operand: pair
+// lane % 16, slots 4 kk + lane / 16), 6 column tiles of 16 sources, 16
+// steps of 4 slots.  Output element (pair, source): the 16 lanes of a group
+// write 16 consecutive sources of one pair.  G3 (single precision): complex
+// products as three real products (Gauss), else four.  Every pair's sums
+// run in one fixed order, so a vector's strengths do not depend on the
+// other pairs of its launch (alone or in a batch).
+template <typename T, bool G3>
+__global__ void __launch_bounds__(512) k_project_int(const typename C2<T>::t* __restrict__ u,
                                                      typename C2<T>::t* __restrict__ sigma,
                                                      const typename C2<T>::t* __restrict__ PshT,
                                                      const T* __restrict__ cw, const int32_t* __restrict__ slot_map,
@@ -213,68 +217,91 @@ __global__ void __launch_bounds__(256) k_project_int(const typename C2<T>::t* __
   using V = typename C2<T>::t;
   using M = Mfma<T>;
   using v4 = typename M::v4;
-  constexpr int U = 96, S = 64;
+  constexpr int U = 96, S = 64, NW = 8;
   extern __shared__ unsigned char smem_raw[];
-  V* A = reinterpret_cast<V*>(smem_raw);      // PshT [S][U]
+  V* B = reinterpret_cast<V*>(smem_raw);      // PshT [S][U]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
-  for (int i = tid; i < S * U; i += blockDim.x) A[i] = PshT[i];
+  for (int i = tid; i < S * U; i += blockDim.x) B[i] = PshT[i];
   const int64_t ncols = (int64_t)nicell * nrhs;
-  const int64_t gc = ((int64_t)blockIdx.x * 4 + wave) * 16 + col;
+  const int64_t gc = ((int64_t)blockIdx.x * NW + wave) * 16 + col;
   const bool valid = gc < ncols;
   const int r = valid ? (int)(gc / nicell) : 0;
   const int c = valid ? icells[gc % nicell] : 0;
-  // this lane's operand B: slots kl, kl + 4, ... of its column
-  V b[S / 4];
+  // this lane's operand A: slots kl, kl + 4, ... of its pair
+  V a[S / 4];
 #pragma unroll
   for (int kk = 0; kk < S / 4; ++kk) {
-    b[kk] = czero<V>();
+    a[kk] = czero<V>();
     if (valid) {
       const int j = slot_map[(int64_t)c * S + 4 * kk + kl];
-      if (j >= 0) b[kk] = cscale(u[(int64_t)r * N + j], cw[j]);
+      if (j >= 0) a[kk] = cscale(u[(int64_t)r * N + j], cw[j]);
     }
   }
   __syncthreads();
-  v4 re[U / 16], im[U / 16];
+  v4 re[U / 16], im[U / 16], r3[G3 ? U / 16 : 1];
 #pragma unroll
   for (int rt = 0; rt < U / 16; ++rt) {
     re[rt] = v4{0, 0, 0, 0};
     im[rt] = v4{0, 0, 0, 0};
+    if (G3) r3[rt] = v4{0, 0, 0, 0};
   }
 #pragma unroll
   for (int kk = 0; kk < S / 4; ++kk) {
-    const V bb = b[kk];
-    const V* arow = A + (4 * kk + kl) * U + col;
+    const V x = a[kk];
+    const V* brow = B + (4 * kk + kl) * U + col;
+    if (G3) {
+      const T xs = x.x + x.y;
 #pragma unroll
-    for (int rt = 0; rt < U / 16; ++rt) {
-      const V a = arow[16 * rt];
-      re[rt] = M::op(a.x, bb.x, re[rt]);
-      re[rt] = M::op(-a.y, bb.y, re[rt]);
-      im[rt] = M::op(a.x, bb.y, im[rt]);
-      im[rt] = M::op(a.y, bb.x, im[rt]);
+      for (int rt = 0; rt < U / 16; ++rt) {
+        const V w = brow[16 * rt];
+        re[rt] = M::op(xs, w.x, re[rt]);
+        im[rt] = M::op(x.y, w.x + w.y, im[rt]);
+        r3[rt] = M::op(x.x, w.y - w.x, r3[rt]);
+      }
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < U / 16; ++rt) {
+        const V w = brow[16 * rt];
+        re[rt] = M::op(x.x, w.x, re[rt]);
+        re[rt] = M::op(-x.y, w.y, re[rt]);
+        im[rt] = M::op(x.x, w.y, im[rt]);
+        im[rt] = M::op(x.y, w.x, im[rt]);
+      }
     }
   }
-  if (!valid) return;
-  V* out = sigma + ((int64_t)r * ncell + c) * U;
+  // lane m < 16 holds pair m's (r, c)
 #pragma unroll
-  for (int rt = 0; rt < U / 16; ++rt)
+  for (int q = 0; q < 4; ++q) {
+    const int m = M::row(lane, q);
+    const int rq = __shfl(r, m, 64), cq = __shfl(c, m, 64);
+    if (((int64_t)blockIdx.x * NW + wave) * 16 + m >= ncols) continue;
+    V* out = sigma + ((int64_t)rq * ncell + cq) * U + col;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int rt = 0; rt < U / 16; ++rt) {
       V o;
-      o.x = re[rt][q];
-      o.y = im[rt][q];
-      out[16 * rt + M::row(lane, q)] = o;
+      if (G3) {
+        o.x = re[rt][q] - im[rt][q];
+        o.y = re[rt][q] + r3[rt][q];
+      } else {
+        o.x = re[rt][q];
+        o.y = im[rt][q];
+      }
+      out[16 * rt] = o;
     }
+  }
 }
 
-// a1, boundary-patch nodes of a cell (their projection columns Pbd differ
-// node by node): sigma[r][c] += sum_b Pbd_b phi_b for RB right-hand sides
-// per workgroup, added to the interior part k_project_int wrote (cells with
-// interior nodes) or started from zero.  Thread (t, g): source t, the nodes
-// b = g mod 2; the odd half is added to the even one through LDS.  The sums
-// of one output run in the same order for every RB, so results do not
-// depend on the batch.
-template <typename T, int RB>
-__global__ void __launch_bounds__(192) k_project_band(const typename C2<T>::t* __restrict__ u,
+// a1 on the matrix cores, boundary-patch nodes of a cell (their projection
+// columns Pbd differ node by node): Sigma^T [rhs x 96] += Phi^T [rhs x nb]
+// Pbd^T [nb x 96] for the cell's nb nodes, added to the interior part
+// k_project_int wrote (cells with interior nodes) or started from zero.
+// One workgroup per (cell, 64 right-hand sides), one wave per 16
+// right-hand sides (MFMA A operand: right-hand side lane % 16, nodes
+// 4 kk + lane / 16; B operand: 16 consecutive sources of Pbd), the next
+// step's operands loaded before the current products.  Each right-hand
+// side's sums run in one fixed order whatever the batch.
+template <typename T, bool G3>
+__global__ void __launch_bounds__(256) k_project_band(const typename C2<T>::t* __restrict__ u,
                                                       typename C2<T>::t* __restrict__ sigma,
                                                       const typename C2<T>::t* __restrict__ Pbd,
                                                       const T* __restrict__ cw, const int32_t* __restrict__ bcells,
@@ -284,41 +311,83 @@ __global__ void __launch_bounds__(192) k_project_band(const typename C2<T>::t* _
                                                       const int32_t* __restrict__ cell_boff, int64_t N, int ncell,
                                                       int nrhs) {
   using V = typename C2<T>::t;
-  constexpr int U = 96;
-  extern __shared__ unsigned char smem_raw[];
-  const int c = bcells[blockIdx.x], r0 = blockIdx.y * RB, tid = threadIdx.x;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int U = 96, RT = U / 16;
+  const int lane = threadIdx.x & 63, kl = lane >> 4, col = lane & 15;
+  const int r0 = blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
+  if (r0 >= nrhs) return;                       // whole wave; no barriers below
+  const int c = bcells[blockIdx.x];
   const int nb = cell_nb[c];
-  V* phi = reinterpret_cast<V*>(smem_raw);   // [nb][RB]
-  V* red = phi + (size_t)nb * RB;            // [RB][U] odd half's sums
   const int64_t b0 = cell_start[c] + cell_nint[c];
-  for (int i = tid; i < nb * RB; i += blockDim.x) {
-    const int bb = i % nb, q = i / nb, r = r0 + q;    // consecutive threads: consecutive nodes
-    const int64_t j = b0 + bb;
-    phi[bb * RB + q] = r < nrhs ? cscale(u[(int64_t)r * N + j], cw[j]) : czero<V>();
+  const bool rv = r0 + col < nrhs;
+  const typename C2<T>::t* __restrict__ ur = u + (int64_t)(rv ? r0 + col : r0) * N + b0;
+  const T* __restrict__ cwb = cw + b0;
+  const V* __restrict__ prow = Pbd + (int64_t)cell_boff[c] * U + col;
+  v4 re[RT], im[RT], r3[G3 ? RT : 1];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    re[rt] = v4{0, 0, 0, 0};
+    im[rt] = v4{0, 0, 0, 0};
+    if (G3) r3[rt] = v4{0, 0, 0, 0};
   }
-  __syncthreads();
-  const int t = tid % U, g = tid / U;
+  const int nsteps = (nb + 3) / 4;
+  auto load = [&](int kk, V& x, V* w) {
+    const int node = 4 * kk + kl;
+    x = czero<V>();
+    if (node < nb) {
+      if (rv) x = cscale(ur[node], cwb[node]);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) w[rt] = prow[(int64_t)node * U + 16 * rt];
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) w[rt] = czero<V>();
+    }
+  };
+  V xn, wn[RT];
+  if (nsteps > 0) load(0, xn, wn);
+  for (int kk = 0; kk < nsteps; ++kk) {
+    const V x = xn;
+    V w[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) w[rt] = wn[rt];
+    if (kk + 1 < nsteps) load(kk + 1, xn, wn);
+    if (G3) {
+      const T xs = x.x + x.y;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        re[rt] = M::op(xs, w[rt].x, re[rt]);
+        im[rt] = M::op(x.y, w[rt].x + w[rt].y, im[rt]);
+        r3[rt] = M::op(x.x, w[rt].y - w[rt].x, r3[rt]);
+      }
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        re[rt] = M::op(x.x, w[rt].x, re[rt]);
+        re[rt] = M::op(-x.y, w[rt].y, re[rt]);
+        im[rt] = M::op(x.x, w[rt].y, im[rt]);
+        im[rt] = M::op(x.y, w[rt].x, im[rt]);
+      }
+    }
+  }
   const bool has_int = cell_nint[c] > 0;
-  V acc[RB];
 #pragma unroll
-  for (int q = 0; q < RB; ++q)
-    acc[q] = (g == 0 && has_int && r0 + q < nrhs) ? sigma[((int64_t)(r0 + q) * ncell + c) * U + t] : czero<V>();
-  const V* prow = Pbd + (int64_t)cell_boff[c] * U + t;
-  for (int bb = g; bb < nb; bb += 2) {
-    const V p = prow[(int64_t)bb * U];
-    const V* ph = phi + bb * RB;
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + M::row(lane, q);
+    if (r >= nrhs) continue;
+    V* out = sigma + ((int64_t)r * ncell + c) * U + col;
 #pragma unroll
-    for (int q = 0; q < RB; ++q) acc[q] = cfma(p, ph[q], acc[q]);
-  }
-  if (g == 1) {
-#pragma unroll
-    for (int q = 0; q < RB; ++q) red[q * U + t] = acc[q];
-  }
-  __syncthreads();
-  if (g == 0) {
-#pragma unroll
-    for (int q = 0; q < RB; ++q)
-      if (r0 + q < nrhs) sigma[((int64_t)(r0 + q) * ncell + c) * U + t] = cadd(acc[q], red[q * U + t]);
+    for (int rt = 0; rt < RT; ++rt) {
+      V o;
+      if (G3) {
+        o.x = re[rt][q] - im[rt][q];
+        o.y = re[rt][q] + r3[rt][q];
+      } else {
+        o.x = re[rt][q];
+        o.y = im[rt][q];
+      }
+      out[16 * rt] = has_int ? cadd(out[16 * rt], o) : o;
+    }
   }
 }
 
@@ -1614,7 +1683,7 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::
 // A workgroup of 4 CT waves takes 16 CT cells: wave w contracts slots
 // 16 (w % 4) .. +15 against cells 16 (w / 4) .. +15, so one staged row of W
 // serves 16 CT cells (CT = 1: most workgroups, CT = 4: least W traffic).
-template <int CT>
+template <int CT, bool G3 = false>
 __global__ void __launch_bounds__(256 * CT) k_near_shared_mfma_db(const float2* __restrict__ grid,
                                                                   float2* __restrict__ v,
                                                                   const float2* __restrict__ W,
@@ -1670,7 +1739,10 @@ __global__ void __launch_bounds__(256 * CT) k_near_shared_mfma_db(const float2* 
       if (i < S * WN) Ws[b][(i / WN) * KP + i % WN] = wr[q];
     }
   };
-  v4 are = v4{0, 0, 0, 0}, aim = v4{0, 0, 0, 0};
+  // G3: complex products as three real products (Gauss): with
+  // p1 = Wr (Xr + Xi), p2 = (Wr + Wi) Xi, p3 = (Wi - Wr) Xr the result is
+  // p1 - p2 + i (p1 + p3); else the four real products
+  v4 are = v4{0, 0, 0, 0}, aim = v4{0, 0, 0, 0}, a3 = v4{0, 0, 0, 0};
   gload(0);
   sstore(0);
   __syncthreads();
@@ -1682,13 +1754,27 @@ __global__ void __launch_bounds__(256 * CT) k_near_shared_mfma_db(const float2* 
       const int k = 4 * kk + (lane >> 4);
       const float2 wa = Ws[b][(16 * st + (lane & 15)) * KP + k];
       const float2 xb = Xs[b][(16 * ct + (lane & 15)) * KP + k];
-      are = M::op(wa.x, xb.x, are);
-      are = M::op(-wa.y, xb.y, are);
-      aim = M::op(wa.x, xb.y, aim);
-      aim = M::op(wa.y, xb.x, aim);
+      if (G3) {
+        are = M::op(wa.x, xb.x + xb.y, are);
+        aim = M::op(wa.x + wa.y, xb.y, aim);
+        a3 = M::op(wa.y - wa.x, xb.x, a3);
+      } else {
+        are = M::op(wa.x, xb.x, are);
+        are = M::op(-wa.y, xb.y, are);
+        aim = M::op(wa.x, xb.y, aim);
+        aim = M::op(wa.y, xb.x, aim);
+      }
     }
     if (wy + 1 < WN) sstore(b ^ 1);
     __syncthreads();
+  }
+  if (G3) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float p1 = are[q];
+      are[q] = p1 - aim[q];
+      aim[q] = p1 + a3[q];
+    }
   }
   const int c = cb + 16 * ct + (lane & 15);
   if (c >= nicell) return;
@@ -1962,7 +2048,7 @@ __global__ void __launch_bounds__(256) k_rhs_major(const float2* __restrict__ u,
 // target lane % 16): the 16 lanes of a group add into 16 targets of one
 // right-hand side.  Rows of different tiles are distinct, so the adds do not
 // race.
-template <int NT>
+template <int NT, bool G3 = false>
 __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut, float2* __restrict__ v,
                                                   const int32_t* __restrict__ bt_rows,
                                                   const int32_t* __restrict__ bt_info,
@@ -1983,11 +2069,12 @@ __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut,
   const float2* __restrict__ W = bt_w + bt_woff[t] + lane;
   const int32_t* __restrict__ cl = bt_cols + bt_info[2 * t + 1];
   const float2* __restrict__ ub = ut + n0 + (lane & 15);
-  v4 re[NT], im[NT];
+  v4 re[NT], im[NT], r3[G3 ? NT : 1];
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
     re[g] = v4{0.f, 0.f, 0.f, 0.f};
     im[g] = v4{0.f, 0.f, 0.f, 0.f};
+    if (G3) r3[g] = v4{0.f, 0.f, 0.f, 0.f};
   }
   // the tile's columns 64 at a time, one per lane; step s (4 columns) takes
   // its column from lane 4 (s % 16) + lane / 16.  Operands of step s + 1 are
@@ -2013,13 +2100,35 @@ __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut,
 #pragma unroll
       for (int g = 0; g < NT; ++g) an[g] = g < ntv ? uc[16 * g] : make_float2(0.f, 0.f);
     }
+    if (G3) {
+      // three real products (Gauss): p1 = (Ur + Ui) Wr, p2 = Ui (Wr + Wi),
+      // p3 = Ur (Wi - Wr); real part p1 - p2, imaginary part p1 + p3
+      const float ws = w.x + w.y, wd = w.y - w.x;
 #pragma unroll
-    for (int g = 0; g < NT; ++g) {
-      re[g] = M::op(a[g].x, w.x, re[g]);
-      re[g] = M::op(-a[g].y, w.y, re[g]);
-      im[g] = M::op(a[g].x, w.y, im[g]);
-      im[g] = M::op(a[g].y, w.x, im[g]);
+      for (int g = 0; g < NT; ++g) {
+        re[g] = M::op(a[g].x + a[g].y, w.x, re[g]);
+        im[g] = M::op(a[g].y, ws, im[g]);
+        r3[g] = M::op(a[g].x, wd, r3[g]);
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < NT; ++g) {
+        re[g] = M::op(a[g].x, w.x, re[g]);
+        re[g] = M::op(-a[g].y, w.y, re[g]);
+        im[g] = M::op(a[g].x, w.y, im[g]);
+        im[g] = M::op(a[g].y, w.x, im[g]);
+      }
     }
+  }
+  if (G3) {
+#pragma unroll
+    for (int g = 0; g < NT; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float p1 = re[g][r];
+        re[g][r] = p1 - im[g][r];
+        im[g][r] = p1 + r3[g][r];
+      }
   }
   const int j = bt_rows[t * 16 + (lane & 15)];
   if (j < 0) return;
@@ -2662,26 +2771,17 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       if (d.q == 12 && d.S == 64 && d.PshT && d.bcells && d.proj_mfma) {
         // interior slots of every cell on the matrix cores, then the
         // boundary-patch nodes cell by cell
+        constexpr bool G3 = std::is_same<T, float>::value;
         if (d.nicell > 0) {
           const int64_t ncols = (int64_t)d.nicell * nrhs;
-          hipLaunchKernelGGL(k_project_int<T>, dim3((unsigned)((ncols + 63) / 64)), dim3(256),
+          hipLaunchKernelGGL((k_project_int<T, G3>), dim3((unsigned)((ncols + 127) / 128)), dim3(512),
                              (size_t)64 * 96 * sizeof(V), st, u, sigma, (const V*)d.PshT, d.cw, d.slot_map,
                              d.icells, d.nicell, d.ncell, d.N, nrhs);
         }
-        if (d.nbcell > 0) {
-          const int RBB = nrhs >= 16 ? 16 : nrhs >= 4 ? 4 : 1;
-          const size_t shp = ((size_t)d.max_nb * RBB + (size_t)RBB * 96) * sizeof(V);
-          const dim3 gb(d.nbcell, (nrhs + RBB - 1) / RBB);
-          if (RBB == 16)
-            hipLaunchKernelGGL((k_project_band<T, 16>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
-                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
-          else if (RBB == 4)
-            hipLaunchKernelGGL((k_project_band<T, 4>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
-                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
-          else
-            hipLaunchKernelGGL((k_project_band<T, 1>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
-                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
-        }
+        if (d.nbcell > 0)
+          hipLaunchKernelGGL((k_project_band<T, G3>), dim3(d.nbcell, (nrhs + 63) / 64), dim3(256), 0, st, u, sigma,
+                             (const V*)d.Pbd, d.cw, d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
+                             d.N, d.ncell, nrhs);
       } else if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
         hipLaunchKernelGGL((k_project_rb<T, RB>), dim3(d.ncell, (nrhs + RB - 1) / RB), dim3(192), shb, st, u, sigma,
                            (const V*)d.PshT, (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb,
@@ -2778,9 +2878,12 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, ns, u, grid, d.dw,
                          d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
       if (std::is_same<T, float>::value && d.near_variant != 1) {
-        const int CT = d.near_variant == 2 ? 2 : d.near_variant == 3 ? 4 : 1;
+        const int CT = d.near_variant == 2 ? 2 : d.near_variant >= 3 ? 4 : 1;
         const dim3 gr((d.nicell + 16 * CT - 1) / (16 * CT), nrhs), bl(256 * CT);
-        if (CT == 1)
+        if (d.near_variant == 4)
+          hipLaunchKernelGGL((k_near_shared_mfma_db<4, true>), gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
+                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
+        else if (CT == 1)
           hipLaunchKernelGGL(k_near_shared_mfma_db<1>, gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
                              (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
         else if (CT == 2)
@@ -2817,7 +2920,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       } else {
         // dense tiles: right-hand-side-major input copied into the lattice
         // region (free after the interpolation; large enough, checked here)
-        const bool blk = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant == 3 && nrhs % 16 == 0 &&
+        const bool blk = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant >= 3 && nrhs % 16 == 0 &&
                          (int64_t)4 * plane >= d.N;
         if (blk) {
           float2* ut = (float2*)lat;
@@ -2825,9 +2928,14 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                              (const float2*)u, ut, d.N, nrhs);
           constexpr int NT = 4;
           const int64_t waves = (int64_t)d.bt_ntiles * ((nrhs + 16 * NT - 1) / (16 * NT));
-          hipLaunchKernelGGL(k_near_blk<NT>, dim3((unsigned)((waves + 3) / 4)), b, 0, ns, (const float2*)ut,
-                             (float2*)vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
-                             d.bt_ntiles, d.N, nrhs, (float)k2);
+          if (d.csr_variant == 4)
+            hipLaunchKernelGGL((k_near_blk<NT, true>), dim3((unsigned)((waves + 3) / 4)), b, 0, ns,
+                               (const float2*)ut, (float2*)vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols,
+                               (const float2*)d.bt_w, d.bt_ntiles, d.N, nrhs, (float)k2);
+          else
+            hipLaunchKernelGGL(k_near_blk<NT>, dim3((unsigned)((waves + 3) / 4)), b, 0, ns, (const float2*)ut,
+                               (float2*)vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
+                               d.bt_ntiles, d.N, nrhs, (float)k2);
         } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
           hipLaunchKernelGGL(k_near_csr4r, g, b, 0, ns, (const float2*)u, (float2*)vt, d.rowptr, d.rows, d.run_ptr,
                              d.run_cs, d.run_pre, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
@@ -2852,7 +2960,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   // rows more than it shortens the side stream.)  The dense-tile form
   // borrows the lattice region and stays on the caller's stream after the
   // far field.
-  const bool blk_rows = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant == 3 && nrhs % 16 == 0;
+  const bool blk_rows = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant >= 3 && nrhs % 16 == 0;
   const bool fork = d.side && !ev && !blk_rows;
   const int64_t nv = d.N * nrhs;
   const unsigned nvb = (unsigned)((nv + 255) / 256);
@@ -2979,14 +3087,8 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_rows<float, -1, 256>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
-  set((const void*)k_project_int<double>);
-  set((const void*)k_project_int<float>);
-  set((const void*)k_project_band<double, 16>);
-  set((const void*)k_project_band<double, 4>);
-  set((const void*)k_project_band<double, 1>);
-  set((const void*)k_project_band<float, 16>);
-  set((const void*)k_project_band<float, 4>);
-  set((const void*)k_project_band<float, 1>);
+  set((const void*)k_project_int<double, false>);
+  set((const void*)k_project_int<float, true>);
   set((const void*)k_fft_cols_conv<double, 256>);
   set((const void*)k_fft_cols_conv<float, 256>);
   set((const void*)k_fft_cols_conv<double, 512>);

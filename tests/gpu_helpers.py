@@ -11,7 +11,7 @@ def schedule_cases(prec, tile_max):
     cases = [("default", {})]
     if prec == binding.LS_C64:
         cases += [(f"csr{v}", dict(csr_variant=v)) for v in (0, 1, 2)]
-        cases += [(f"near{v}", dict(near_variant=v)) for v in (0, 1, 2, 3)]
+        cases += [(f"near{v}", dict(near_variant=v)) for v in (0, 1, 2, 3, 4)]
     for fv in (0, 1):
         for tc in sorted({1, 4, tile_max}):
             cases.append((f"fft{fv}-tile{tc}", dict(fft_variant=fv, fft_col_tile=tc)))

@@ -115,7 +115,7 @@ def test_operator_without_tiles(disc):
         assert op2.stats()["tile_weights"] == 0 and op.stats()["tile_weights"] > 0
         assert op2.resident_bytes() < op.resident_bytes()
         ch = op2.autotune(16, binding.LS_C64)
-        assert ch["csr_variant"] != 3
+        assert ch["csr_variant"] not in (3, 4)
         U = torch.stack([torch.tensor(_to_lib(random_density(orc.pts["key"], seed=s), p, op.N),
                                       dtype=torch.complex128) for s in range(2)]).cuda()
         V1, V2 = torch.empty_like(U), torch.empty_like(U)
@@ -169,7 +169,7 @@ def test_autotune_keeps_the_operator(disc):
     for prec, dt, tol in ((binding.LS_C128, torch.complex128, 1e-8), (binding.LS_C64, torch.complex64, F32_TOL)):
         ch = op.autotune(nrhs=1, prec=prec)
         print(f"autotune prec {prec}: {ch}", flush=True)
-        assert ch["fft_col_tile"] in (1, 2, 4, 8, 16, 32) and ch["near_variant"] in (0, 1, 2, 3) and ch["csr_variant"] in (0, 1, 2, 3)
+        assert ch["fft_col_tile"] in (1, 2, 4, 8, 16, 32) and ch["near_variant"] in (0, 1, 2, 3, 4) and ch["csr_variant"] in (0, 1, 2, 3, 4)
         u = torch.tensor(_to_lib(x_or, p, op.N), dtype=dt, device="cuda")
         v = torch.empty_like(u)
         op.apply(u, v)
@@ -281,7 +281,7 @@ def test_schedule_setter_rejects_out_of_range(disc):
     from paper_1509_05063_amd import binding
     cfg, op, orc, A, p, xy, key = disc
     saved = op.get_schedule(binding.LS_C64)
-    for bad in (dict(csr_variant=4), dict(near_variant=-1), dict(fft_variant=2), dict(fft_row_threads=128),
+    for bad in (dict(csr_variant=5), dict(near_variant=5), dict(near_variant=-1), dict(fft_variant=2), dict(fft_row_threads=128),
                 dict(fft_col_threads=1024), dict(fft_col_tile=0), dict(fft_col_tile=100000)):
         with pytest.raises(binding.LSError):
             op.set_schedule(binding.LS_C64, **bad)
@@ -290,11 +290,12 @@ def test_schedule_setter_rejects_out_of_range(disc):
         op.set_schedule(binding.LS_C128, csr_variant=2)      # double precision has one row kernel
 
 
-@pytest.mark.parametrize("nrhs", [16, 32])
-def test_dense_tile_rows_match_oracle(disc, nrhs):
+@pytest.mark.parametrize("nrhs,variant", [(16, 3), (32, 3), (16, 4), (32, 4)])
+def test_dense_tile_rows_match_oracle(disc, nrhs, variant):
     """The dense-tile row kernel on the matrix cores (csr_variant 3, taken for
-    multiples of 16 right-hand sides) against the oracle on every row of every
-    right-hand side, and against the single-right-hand-side run-length rows."""
+    multiples of 16 right-hand sides; 4: three real products per complex
+    product) against the oracle on every row of every right-hand side, and
+    against the single-right-hand-side run-length rows."""
     import torch
     from paper_1509_05063_amd import binding
     cfg, op, orc, A, p, xy, key = disc
@@ -303,7 +304,7 @@ def test_dense_tile_rows_match_oracle(disc, nrhs):
     Y = X @ A.T
     U = torch.tensor(np.stack([_to_lib(x, p, op.N) for x in X]), dtype=torch.complex64, device="cuda")
     try:
-        op.set_schedule(binding.LS_C64, csr_variant=3)
+        op.set_schedule(binding.LS_C64, csr_variant=variant)
         V = torch.empty_like(U)
         op.apply(U, V)
         op.set_schedule(binding.LS_C64, csr_variant=2)
@@ -315,7 +316,8 @@ def test_dense_tile_rows_match_oracle(disc, nrhs):
     Vn = V.cpu().numpy().astype(complex)[:, p]
     err = (np.linalg.norm(Vn - Y, axis=1) / np.linalg.norm(Y, axis=1)).max()
     dif = (torch.linalg.norm(V - V2, dim=1) / torch.linalg.norm(V2, dim=1)).max().item()
-    print(f"dense tiles, {nrhs} right-hand sides: vs oracle {err:.2e}, vs run-length rows {dif:.2e}", flush=True)
+    print(f"dense tiles (variant {variant}), {nrhs} right-hand sides: vs oracle {err:.2e}, "
+          f"vs run-length rows {dif:.2e}", flush=True)
     assert err < F32_TOL and dif < F32_TOL
 
 
