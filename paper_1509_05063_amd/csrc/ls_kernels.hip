@@ -199,16 +199,16 @@ __global__ void __launch_bounds__(192) k_project_rb(const typename C2<T>::t* __r
 // interior part of all cells and right-hand sides is one product
 // Sigma^T [(cells x rhs) x 96] = Phi^T [(cells x rhs) x 64] Psh^T [64 x 96]:
 // a row of Phi^T is one (interior cell, right-hand side) pair, phi = c u
-// gathered through the slot map.  Psh^T sits in LDS (one copy for the 8
-// waves of a workgroup); each wave takes 16 pairs (MFMA A operand: pair
-// lane % 16, slots 4 kk + lane / 16), 6 column tiles of 16 sources, 16
+// gathered through the slot map.  Psh^T sits in LDS (one copy for the NW
+// waves of a workgroup); each wave walks tiles of 16 pairs (MFMA A operand:
+// pair lane % 16, slots 4 kk + lane / 16), 6 column tiles of 16 sources, 16
 // steps of 4 slots.  Output element (pair, source): the 16 lanes of a group
 // write 16 consecutive sources of one pair.  G3 (single precision): complex
 // products as three real products (Gauss), else four.  Every pair's sums
 // run in one fixed order, so a vector's strengths do not depend on the
 // other pairs of its launch (alone or in a batch).
-template <typename T, bool G3>
-__global__ void __launch_bounds__(512) k_project_int(const typename C2<T>::t* __restrict__ u,
+template <typename T, bool G3, int NW>
+__global__ void __launch_bounds__(64 * NW) k_project_int(const typename C2<T>::t* __restrict__ u,
                                                      typename C2<T>::t* __restrict__ sigma,
                                                      const typename C2<T>::t* __restrict__ PshT,
                                                      const T* __restrict__ cw, const int32_t* __restrict__ slot_map,
@@ -217,77 +217,130 @@ __global__ void __launch_bounds__(512) k_project_int(const typename C2<T>::t* __
   using V = typename C2<T>::t;
   using M = Mfma<T>;
   using v4 = typename M::v4;
-  constexpr int U = 96, S = 64, NW = 8;
+  constexpr int U = 96, S = 64, KS = S / 4;
   extern __shared__ unsigned char smem_raw[];
   V* B = reinterpret_cast<V*>(smem_raw);      // PshT [S][U]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
   for (int i = tid; i < S * U; i += blockDim.x) B[i] = PshT[i];
-  const int64_t ncols = (int64_t)nicell * nrhs;
-  const int64_t gc = ((int64_t)blockIdx.x * NW + wave) * 16 + col;
-  const bool valid = gc < ncols;
-  const int r = valid ? (int)(gc / nicell) : 0;
-  const int c = valid ? icells[gc % nicell] : 0;
-  // this lane's operand A: slots kl, kl + 4, ... of its pair
-  V a[S / 4];
-#pragma unroll
-  for (int kk = 0; kk < S / 4; ++kk) {
-    a[kk] = czero<V>();
-    if (valid) {
-      const int j = slot_map[(int64_t)c * S + 4 * kk + kl];
-      if (j >= 0) a[kk] = cscale(u[(int64_t)r * N + j], cw[j]);
-    }
-  }
   __syncthreads();
-  v4 re[U / 16], im[U / 16], r3[G3 ? U / 16 : 1];
+  // each wave walks tiles of 16 pairs with a stride of the whole grid,
+  // three tiles in flight: while tile t's products run, the densities of
+  // t + 1 (raw values, scaled after the products), the slot indices of
+  // t + 2 and the cells of t + 3 are being loaded
+  const int64_t ncols = (int64_t)nicell * nrhs;
+  const int64_t ntiles = (ncols + 15) / 16, stride = (int64_t)gridDim.x * NW;
+  auto pair_of = [&](int64_t t, int& r, int& c) {
+    const int64_t gc = t * 16 + col;
+    r = gc < ncols ? (int)(gc / nicell) : -1;
+    c = gc < ncols ? icells[gc % nicell] : 0;
+  };
+  auto slots = [&](int r, int c, int* j) {
 #pragma unroll
-  for (int rt = 0; rt < U / 16; ++rt) {
-    re[rt] = v4{0, 0, 0, 0};
-    im[rt] = v4{0, 0, 0, 0};
-    if (G3) r3[rt] = v4{0, 0, 0, 0};
+    for (int kk = 0; kk < KS; ++kk) j[kk] = r >= 0 ? slot_map[(int64_t)c * S + 4 * kk + kl] : -1;
+  };
+  auto raw = [&](int r, const int* j, V* x, T* w) {
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      x[kk] = j[kk] >= 0 ? u[(int64_t)r * N + j[kk]] : czero<V>();
+      w[kk] = j[kk] >= 0 ? cw[j[kk]] : (T)0;
+    }
+  };
+  int64_t t = (int64_t)blockIdx.x * NW + wave;
+  if (t >= ntiles) return;
+  int r, c, r1, c1, r2, c2;
+  int j1[KS];
+  V a[KS];
+  {
+    int j[KS];
+    V x[KS];
+    T w[KS];
+    pair_of(t, r, c);
+    slots(r, c, j);
+    raw(r, j, x, w);
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) a[kk] = cscale(x[kk], w[kk]);
   }
+  pair_of(t + stride, r1, c1);
+  slots(r1, c1, j1);
+  pair_of(t + 2 * stride, r2, c2);
+  for (; t < ntiles; t += stride) {
+    // keeps the Psh reads from LDS inside the loop (hoisted out of it they
+    // would hold the whole matrix in registers)
+    asm volatile("" ::: "memory");
+    V xn[KS];
+    T wn[KS];
+    raw(r1, j1, xn, wn);             // densities of t + 1 (r1 < 0: none)
+    int j2[KS];
+    slots(r2, c2, j2);               // slot indices of t + 2
+    int r3, c3;
+    pair_of(t + 3 * stride, r3, c3); // cells of t + 3
+    // the 96 sources in two halves of 3 column tiles (fewer accumulators)
 #pragma unroll
-  for (int kk = 0; kk < S / 4; ++kk) {
-    const V x = a[kk];
-    const V* brow = B + (4 * kk + kl) * U + col;
-    if (G3) {
-      const T xs = x.x + x.y;
+    for (int h = 0; h < 2; ++h) {
+      constexpr int RH = U / 32;
+      v4 re[RH], im[RH], r3[G3 ? RH : 1];
 #pragma unroll
-      for (int rt = 0; rt < U / 16; ++rt) {
-        const V w = brow[16 * rt];
-        re[rt] = M::op(xs, w.x, re[rt]);
-        im[rt] = M::op(x.y, w.x + w.y, im[rt]);
-        r3[rt] = M::op(x.x, w.y - w.x, r3[rt]);
+      for (int rt = 0; rt < RH; ++rt) {
+        re[rt] = v4{0, 0, 0, 0};
+        im[rt] = v4{0, 0, 0, 0};
+        if (G3) r3[rt] = v4{0, 0, 0, 0};
       }
-    } else {
 #pragma unroll
-      for (int rt = 0; rt < U / 16; ++rt) {
-        const V w = brow[16 * rt];
-        re[rt] = M::op(x.x, w.x, re[rt]);
-        re[rt] = M::op(-x.y, w.y, re[rt]);
-        im[rt] = M::op(x.x, w.y, im[rt]);
-        im[rt] = M::op(x.y, w.x, im[rt]);
+      for (int kk = 0; kk < KS; ++kk) {
+        const V x = a[kk];
+        const V* brow = B + (4 * kk + kl) * U + 48 * h + col;
+        if (G3) {
+          const T xs = x.x + x.y;
+#pragma unroll
+          for (int rt = 0; rt < RH; ++rt) {
+            const V w = brow[16 * rt];
+            re[rt] = M::op(xs, w.x, re[rt]);
+            im[rt] = M::op(x.y, w.x + w.y, im[rt]);
+            r3[rt] = M::op(x.x, w.y - w.x, r3[rt]);
+          }
+        } else {
+#pragma unroll
+          for (int rt = 0; rt < RH; ++rt) {
+            const V w = brow[16 * rt];
+            re[rt] = M::op(x.x, w.x, re[rt]);
+            re[rt] = M::op(-x.y, w.y, re[rt]);
+            im[rt] = M::op(x.x, w.y, im[rt]);
+            im[rt] = M::op(x.y, w.x, im[rt]);
+          }
+        }
+      }
+      // lane m < 16 holds pair m's (r, c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = M::row(lane, q);
+        const int rq = __shfl(r, m, 64), cq = __shfl(c, m, 64);
+        if (rq < 0) continue;
+        V* out = sigma + ((int64_t)rq * ncell + cq) * U + 48 * h + col;
+#pragma unroll
+        for (int rt = 0; rt < RH; ++rt) {
+          V o;
+          if (G3) {
+            o.x = re[rt][q] - im[rt][q];
+            o.y = re[rt][q] + r3[rt][q];
+          } else {
+            o.x = re[rt][q];
+            o.y = im[rt][q];
+          }
+          out[16 * rt] = o;
+        }
       }
     }
-  }
-  // lane m < 16 holds pair m's (r, c)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int m = M::row(lane, q);
-    const int rq = __shfl(r, m, 64), cq = __shfl(c, m, 64);
-    if (((int64_t)blockIdx.x * NW + wave) * 16 + m >= ncols) continue;
-    V* out = sigma + ((int64_t)rq * ncell + cq) * U + col;
-#pragma unroll
-    for (int rt = 0; rt < U / 16; ++rt) {
-      V o;
-      if (G3) {
-        o.x = re[rt][q] - im[rt][q];
-        o.y = re[rt][q] + r3[rt][q];
-      } else {
-        o.x = re[rt][q];
-        o.y = im[rt][q];
-      }
-      out[16 * rt] = o;
+    for (int kk = 0; kk < KS; ++kk) {
+      a[kk] = cscale(xn[kk], wn[kk]);
+      j1[kk] = j2[kk];
     }
+    r = r1;
+    c = c1;
+    r1 = r2;
+    c1 = c2;
+    r2 = r3;
+    c2 = c3;
   }
 }
 
@@ -2774,9 +2827,24 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         constexpr bool G3 = std::is_same<T, float>::value;
         if (d.nicell > 0) {
           const int64_t ncols = (int64_t)d.nicell * nrhs;
-          hipLaunchKernelGGL((k_project_int<T, G3>), dim3((unsigned)((ncols + 127) / 128)), dim3(512),
-                             (size_t)64 * 96 * sizeof(V), st, u, sigma, (const V*)d.PshT, d.cw, d.slot_map,
-                             d.icells, d.nicell, d.ncell, d.N, nrhs);
+          // tiles of 16 pairs; single-precision batches: 8 waves per
+          // workgroup, one workgroup per compute unit (each keeps one LDS
+          // copy of Psh and walks its tiles); otherwise 2 waves per
+          // workgroup, one tile each (the same sums per pair either way)
+          const int64_t ntl = (ncols + 15) / 16;
+          bool done = false;
+          if constexpr (G3) {
+            if (ntl >= 256 * 8) {
+              hipLaunchKernelGGL((k_project_int<T, G3, 8>), dim3(256), dim3(512), (size_t)64 * 96 * sizeof(V), st,
+                                 u, sigma, (const V*)d.PshT, d.cw, d.slot_map, d.icells, d.nicell, d.ncell, d.N,
+                                 nrhs);
+              done = true;
+            }
+          }
+          if (!done)
+            hipLaunchKernelGGL((k_project_int<T, G3, 2>), dim3((unsigned)((ntl + 1) / 2)), dim3(128),
+                               (size_t)64 * 96 * sizeof(V), st, u, sigma, (const V*)d.PshT, d.cw, d.slot_map,
+                               d.icells, d.nicell, d.ncell, d.N, nrhs);
         }
         if (d.nbcell > 0)
           hipLaunchKernelGGL((k_project_band<T, G3>), dim3(d.nbcell, (nrhs + 63) / 64), dim3(256), 0, st, u, sigma,
@@ -3087,8 +3155,9 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_rows<float, -1, 256>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
-  set((const void*)k_project_int<double, false>);
-  set((const void*)k_project_int<float, true>);
+  set((const void*)k_project_int<float, true, 8>);
+  set((const void*)k_project_int<double, false, 2>);
+  set((const void*)k_project_int<float, true, 2>);
   set((const void*)k_fft_cols_conv<double, 256>);
   set((const void*)k_fft_cols_conv<float, 256>);
   set((const void*)k_fft_cols_conv<double, 512>);
