@@ -1358,11 +1358,55 @@ __global__ void __launch_bounds__(256) k_interp(const typename C2<T>::t* __restr
   }
 }
 
+// Dirichlet fit on the matrix cores (q = 12: F = 48 face values, 64 slots):
+// D [16 x 16] = FV [16 x F] IshT [F x slots 16 w .. 16 w + 15] for wave w,
+// FV from LDS (row = lane % 16, face values 4 kk + lane / 16), IshT from
+// global memory (16 consecutive slots per group).  Single precision: complex
+// products as three real products (Gauss), else four.  Shared by the
+// per-cell and the per-right-hand-side launches, so both give bitwise the
+// same values.
+template <typename T>
+__device__ __forceinline__ void fit_mfma(const typename C2<T>::t* fv, const typename C2<T>::t* __restrict__ IshT,
+                                         int wave, int kl, int col, typename Mfma<T>::v4& dre,
+                                         typename Mfma<T>::v4& dim) {
+  using V = typename C2<T>::t;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int F = 48, S = 64;
+  constexpr bool G3 = std::is_same<T, float>::value;
+  v4 p3 = v4{0, 0, 0, 0};
+  dre = v4{0, 0, 0, 0};
+  dim = v4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int kk = 0; kk < F / 4; ++kk) {
+    const int t = 4 * kk + kl;
+    const V x = fv[col * F + t];
+    const V w = IshT[t * S + 16 * wave + col];
+    if (G3) {
+      dre = M::op(x.x + x.y, w.x, dre);
+      dim = M::op(x.y, w.x + w.y, dim);
+      p3 = M::op(x.x, w.y - w.x, p3);
+    } else {
+      dre = M::op(x.x, w.x, dre);
+      dre = M::op(-x.y, w.y, dre);
+      dim = M::op(x.x, w.y, dim);
+      dim = M::op(x.y, w.x, dim);
+    }
+  }
+  if (G3) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T p1 = dre[q];
+      dre[q] = p1 - dim[q];
+      dim[q] = p1 + p3[q];
+    }
+  }
+}
+
 // Interpolation for 16 consecutive cells per workgroup (q = 12: F = 48 face
 // values, S = 64 slots) on the matrix cores: the cells' face values are
-// staged in LDS and fitted to the slots as one contraction (IshT [F][S]
-// times the 16 cells' face values, complex products as four real MFMA
-// 16x16x4 updates; wave w takes slots 16w..16w+15), and to the band nodes
+// staged in LDS and fitted to the slots as one contraction (fit_mfma; wave
+// w takes slots 16w..16w+15), and to the band nodes
 // one row per thread (IbdT [F][nband]).  The adjacent cells' part of the lattice field is
 // removed by the near-field weights (folded in at set-up), not here.
 template <typename T, int CB>
@@ -1382,7 +1426,7 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
   using M = Mfma<T>;
   using v4 = typename M::v4;
   constexpr int q = 12, F = 4 * q, S = 64;
-  static_assert(CB == 16, "one MFMA column per cell");
+  static_assert(CB == 16, "one MFMA row per cell");
   extern __shared__ unsigned char smem_raw[];
   V* fv = reinterpret_cast<V*>(smem_raw);                    // [CB][F] face values
   int* cinfo = reinterpret_cast<int*>(fv + CB * F);          // [CB][2] cell x, y (-1: past the end)
@@ -1410,29 +1454,20 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
   const V* ur = u + (int64_t)r * N;
   V* vr = v + (int64_t)r * N;
   {
-    v4 dre = v4{0, 0, 0, 0}, dim = v4{0, 0, 0, 0};
-#pragma unroll 4
-    for (int kk = 0; kk < F / 4; ++kk) {
-      const int t = 4 * kk + kl;
-      const V a = IshT[t * S + 16 * wave + col];
-      const V b = fv[col * F + t];
-      dre = M::op(a.x, b.x, dre);
-      dre = M::op(-a.y, b.y, dre);
-      dim = M::op(a.x, b.y, dim);
-      dim = M::op(a.y, b.x, dim);
-    }
-    const int c = c0 + col;
-    if (c < ncell) {
+    // fit = FV [cells x F] IshT [F x slots]: output element (cell, slot),
+    // the 16 lanes of a group on 16 consecutive slots of one cell
+    v4 dre, dim;
+    fit_mfma<T>(fv, IshT, wave, kl, col, dre, dim);
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int a = 16 * wave + M::row(lane, rr);
-        const int j = slot_map[(int64_t)c * S + a];
-        if (j >= 0) {
-          V o2;
-          o2.x = dre[rr];
-          o2.y = dim[rr];
-          vr[j] = cadd(ur[j], cscale(o2, k2));
-        }
+    for (int rr = 0; rr < 4; ++rr) {
+      const int c = c0 + M::row(lane, rr);
+      if (c >= ncell) continue;
+      const int j = slot_map[(int64_t)c * S + 16 * wave + col];
+      if (j >= 0) {
+        V o2;
+        o2.x = dre[rr];
+        o2.y = dim[rr];
+        vr[j] = cadd(ur[j], cscale(o2, k2));
       }
     }
   }
@@ -1452,7 +1487,7 @@ __global__ void __launch_bounds__(256) k_interp_mfma(const typename C2<T>::t* __
 }
 
 // The same interpolation for 16 right-hand sides of one cell per workgroup
-// (batched applies): the MFMA columns are the 16 right-hand sides instead of
+// (batched applies): the MFMA rows are the 16 right-hand sides instead of
 // 16 cells, and each band node's fit row is read once for all of them.  Every
 // output goes through the same products in the same order as in
 // k_interp_mfma, so results are bitwise those of the per-right-hand-side
@@ -1491,31 +1526,20 @@ __global__ void __launch_bounds__(256) k_interp_rb(const typename C2<T>::t* __re
   }
   __syncthreads();
   {
-    v4 dre = v4{0, 0, 0, 0}, dim = v4{0, 0, 0, 0};
-#pragma unroll 4
-    for (int kk = 0; kk < F / 4; ++kk) {
-      const int t = 4 * kk + kl;
-      const V a = IshT[t * S + 16 * wave + col];
-      const V b = fv[col * F + t];
-      dre = M::op(a.x, b.x, dre);
-      dre = M::op(-a.y, b.y, dre);
-      dim = M::op(a.x, b.y, dim);
-      dim = M::op(a.y, b.x, dim);
-    }
-    const int r = r0 + col;
-    if (r < nrhs) {
-      const V* ur = u + (int64_t)r * N;
-      V* vr = v + (int64_t)r * N;
+    // fit = FV [rhs x F] IshT [F x slots]: output element (rhs, slot), the
+    // 16 lanes of a group on 16 consecutive slots of one right-hand side
+    v4 dre, dim;
+    fit_mfma<T>(fv, IshT, wave, kl, col, dre, dim);
+    const int j = slot_map[(int64_t)c * S + 16 * wave + col];
+    if (j >= 0) {
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int a = 16 * wave + M::row(lane, rr);
-        const int j = slot_map[(int64_t)c * S + a];
-        if (j >= 0) {
-          V o2;
-          o2.x = dre[rr];
-          o2.y = dim[rr];
-          vr[j] = cadd(ur[j], cscale(o2, k2));
-        }
+        const int r = r0 + M::row(lane, rr);
+        if (r >= nrhs) continue;
+        V o2;
+        o2.x = dre[rr];
+        o2.y = dim[rr];
+        v[(int64_t)r * N + j] = cadd(u[(int64_t)r * N + j], cscale(o2, k2));
       }
     }
   }
