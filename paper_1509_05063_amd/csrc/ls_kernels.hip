@@ -199,34 +199,135 @@ __global__ void __launch_bounds__(192) k_project_rb(const typename C2<T>::t* __r
 // interior part of all cells and right-hand sides is one product
 // Sigma^T [(cells x rhs) x 96] = Phi^T [(cells x rhs) x 64] Psh^T [64 x 96]:
 // a row of Phi^T is one (interior cell, right-hand side) pair, phi = c u
-// gathered through the slot map.  Psh^T sits in LDS (one copy for the NW
-// waves of a workgroup); each wave walks tiles of 16 pairs (MFMA A operand:
-// pair lane % 16, slots 4 kk + lane / 16), 6 column tiles of 16 sources, 16
+// gathered through the slot map.  Psh^T sits in LDS (one copy per
+// workgroup); a wave takes tiles of 16 pairs (MFMA A operand: pair
+// lane % 16, slots 4 kk + lane / 16), 6 column tiles of 16 sources, 16
 // steps of 4 slots.  Output element (pair, source): the 16 lanes of a group
 // write 16 consecutive sources of one pair.  G3 (single precision): complex
 // products as three real products (Gauss), else four.  Every pair's sums
 // run in one fixed order, so a vector's strengths do not depend on the
 // other pairs of its launch (alone or in a batch).
-template <typename T, bool G3, int NW>
-__global__ void __launch_bounds__(64 * NW) k_project_int(const typename C2<T>::t* __restrict__ u,
+//
+// One tile of 16 pairs: the products against Psh^T in LDS (the 96 sources
+// in two halves of 3 column tiles) and the stores; a[kk]: this lane's
+// densities (pair lane % 16, slot 4 kk + lane / 16); lane m < 16 holds
+// pair m's right-hand side r (< 0: no pair) and cell c.
+template <typename T, bool G3>
+__device__ __forceinline__ void proj_tile(const typename C2<T>::t* B, const typename C2<T>::t* a, int r, int c,
+                                          int lane, typename C2<T>::t* __restrict__ sigma, int ncell) {
+  using V = typename C2<T>::t;
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  constexpr int U = 96, KS = 16, RH = U / 32;
+  const int kl = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    v4 re[RH], im[RH], p3[G3 ? RH : 1];
+#pragma unroll
+    for (int rt = 0; rt < RH; ++rt) {
+      re[rt] = v4{0, 0, 0, 0};
+      im[rt] = v4{0, 0, 0, 0};
+      if (G3) p3[rt] = v4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const V x = a[kk];
+      const V* brow = B + (4 * kk + kl) * U + 48 * h + col;
+      if (G3) {
+        const T xs = x.x + x.y;
+#pragma unroll
+        for (int rt = 0; rt < RH; ++rt) {
+          const V w = brow[16 * rt];
+          re[rt] = M::op(xs, w.x, re[rt]);
+          im[rt] = M::op(x.y, w.x + w.y, im[rt]);
+          p3[rt] = M::op(x.x, w.y - w.x, p3[rt]);
+        }
+      } else {
+#pragma unroll
+        for (int rt = 0; rt < RH; ++rt) {
+          const V w = brow[16 * rt];
+          re[rt] = M::op(x.x, w.x, re[rt]);
+          re[rt] = M::op(-x.y, w.y, re[rt]);
+          im[rt] = M::op(x.x, w.y, im[rt]);
+          im[rt] = M::op(x.y, w.x, im[rt]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = M::row(lane, q);
+      const int rq = __shfl(r, m, 64), cq = __shfl(c, m, 64);
+      if (rq < 0) continue;
+      V* out = sigma + ((int64_t)rq * ncell + cq) * U + 48 * h + col;
+#pragma unroll
+      for (int rt = 0; rt < RH; ++rt) {
+        V o;
+        if (G3) {
+          o.x = re[rt][q] - im[rt][q];
+          o.y = re[rt][q] + p3[rt][q];
+        } else {
+          o.x = re[rt][q];
+          o.y = im[rt][q];
+        }
+        out[16 * rt] = o;
+      }
+    }
+  }
+}
+
+// One tile of 16 pairs per wave, 4 waves per workgroup (each workgroup
+// copies Psh^T to LDS).
+template <typename T, bool G3>
+__global__ void __launch_bounds__(256) k_project_int(const typename C2<T>::t* __restrict__ u,
                                                      typename C2<T>::t* __restrict__ sigma,
                                                      const typename C2<T>::t* __restrict__ PshT,
                                                      const T* __restrict__ cw, const int32_t* __restrict__ slot_map,
                                                      const int32_t* __restrict__ icells, int nicell, int ncell,
                                                      int64_t N, int nrhs) {
   using V = typename C2<T>::t;
-  using M = Mfma<T>;
-  using v4 = typename M::v4;
   constexpr int U = 96, S = 64, KS = S / 4;
   extern __shared__ unsigned char smem_raw[];
   V* B = reinterpret_cast<V*>(smem_raw);      // PshT [S][U]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
   for (int i = tid; i < S * U; i += blockDim.x) B[i] = PshT[i];
+  const int64_t ncols = (int64_t)nicell * nrhs;
+  const int64_t gc = ((int64_t)blockIdx.x * 4 + wave) * 16 + col;
+  const int r = gc < ncols ? (int)(gc / nicell) : -1;
+  const int c = gc < ncols ? icells[gc % nicell] : 0;
+  V a[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    a[kk] = czero<V>();
+    if (r >= 0) {
+      const int j = slot_map[(int64_t)c * S + 4 * kk + kl];
+      if (j >= 0) a[kk] = cscale(u[(int64_t)r * N + j], cw[j]);
+    }
+  }
   __syncthreads();
-  // each wave walks tiles of 16 pairs with a stride of the whole grid,
-  // three tiles in flight: while tile t's products run, the densities of
-  // t + 1 (raw values, scaled after the products), the slot indices of
-  // t + 2 and the cells of t + 3 are being loaded
+  proj_tile<T, G3>(B, a, r, c, lane, sigma, ncell);
+}
+
+// The same for large batches as a persistent kernel: 8 waves per workgroup
+// and one workgroup per compute unit (one copy of Psh^T each); each wave
+// walks tiles with a stride of the whole grid, three tiles in flight: while
+// tile t's products run, the densities of t + 1 (raw values, scaled after
+// the products), the slot indices of t + 2 and the cells of t + 3 are being
+// loaded.  The products of a pair are those of k_project_int.
+template <typename T, bool G3>
+__global__ void __launch_bounds__(512) k_project_int_walk(const typename C2<T>::t* __restrict__ u,
+                                                          typename C2<T>::t* __restrict__ sigma,
+                                                          const typename C2<T>::t* __restrict__ PshT,
+                                                          const T* __restrict__ cw,
+                                                          const int32_t* __restrict__ slot_map,
+                                                          const int32_t* __restrict__ icells, int nicell, int ncell,
+                                                          int64_t N, int nrhs) {
+  using V = typename C2<T>::t;
+  constexpr int U = 96, S = 64, KS = S / 4, NW = 8;
+  extern __shared__ unsigned char smem_raw[];
+  V* B = reinterpret_cast<V*>(smem_raw);      // PshT [S][U]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kl = lane >> 4, col = lane & 15;
+  for (int i = tid; i < S * U; i += blockDim.x) B[i] = PshT[i];
+  __syncthreads();
   const int64_t ncols = (int64_t)nicell * nrhs;
   const int64_t ntiles = (ncols + 15) / 16, stride = (int64_t)gridDim.x * NW;
   auto pair_of = [&](int64_t t, int& r, int& c) {
@@ -274,62 +375,7 @@ __global__ void __launch_bounds__(64 * NW) k_project_int(const typename C2<T>::t
     slots(r2, c2, j2);               // slot indices of t + 2
     int r3, c3;
     pair_of(t + 3 * stride, r3, c3); // cells of t + 3
-    // the 96 sources in two halves of 3 column tiles (fewer accumulators)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      constexpr int RH = U / 32;
-      v4 re[RH], im[RH], r3[G3 ? RH : 1];
-#pragma unroll
-      for (int rt = 0; rt < RH; ++rt) {
-        re[rt] = v4{0, 0, 0, 0};
-        im[rt] = v4{0, 0, 0, 0};
-        if (G3) r3[rt] = v4{0, 0, 0, 0};
-      }
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        const V x = a[kk];
-        const V* brow = B + (4 * kk + kl) * U + 48 * h + col;
-        if (G3) {
-          const T xs = x.x + x.y;
-#pragma unroll
-          for (int rt = 0; rt < RH; ++rt) {
-            const V w = brow[16 * rt];
-            re[rt] = M::op(xs, w.x, re[rt]);
-            im[rt] = M::op(x.y, w.x + w.y, im[rt]);
-            r3[rt] = M::op(x.x, w.y - w.x, r3[rt]);
-          }
-        } else {
-#pragma unroll
-          for (int rt = 0; rt < RH; ++rt) {
-            const V w = brow[16 * rt];
-            re[rt] = M::op(x.x, w.x, re[rt]);
-            re[rt] = M::op(-x.y, w.y, re[rt]);
-            im[rt] = M::op(x.x, w.y, im[rt]);
-            im[rt] = M::op(x.y, w.x, im[rt]);
-          }
-        }
-      }
-      // lane m < 16 holds pair m's (r, c)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int m = M::row(lane, q);
-        const int rq = __shfl(r, m, 64), cq = __shfl(c, m, 64);
-        if (rq < 0) continue;
-        V* out = sigma + ((int64_t)rq * ncell + cq) * U + 48 * h + col;
-#pragma unroll
-        for (int rt = 0; rt < RH; ++rt) {
-          V o;
-          if (G3) {
-            o.x = re[rt][q] - im[rt][q];
-            o.y = re[rt][q] + r3[rt][q];
-          } else {
-            o.x = re[rt][q];
-            o.y = im[rt][q];
-          }
-          out[16 * rt] = o;
-        }
-      }
-    }
+    proj_tile<T, G3>(B, a, r, c, lane, sigma, ncell);
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       a[kk] = cscale(xn[kk], wn[kk]);
@@ -348,13 +394,12 @@ __global__ void __launch_bounds__(64 * NW) k_project_int(const typename C2<T>::t
 // columns Pbd differ node by node): Sigma^T [rhs x 96] += Phi^T [rhs x nb]
 // Pbd^T [nb x 96] for the cell's nb nodes, added to the interior part
 // k_project_int wrote (cells with interior nodes) or started from zero.
-// One workgroup per (cell, 64 right-hand sides), one wave per 16
-// right-hand sides (MFMA A operand: right-hand side lane % 16, nodes
-// 4 kk + lane / 16; B operand: 16 consecutive sources of Pbd), the next
-// step's operands loaded before the current products.  Each right-hand
-// side's sums run in one fixed order whatever the batch.
+// One workgroup per (cell, 16 right-hand sides), wave w on sources
+// 16 w .. 16 w + 15 (MFMA A operand: right-hand side lane % 16, nodes
+// 4 kk + lane / 16; B operand: 16 consecutive sources of Pbd).  Each
+// right-hand side's sums run in one fixed order whatever the batch.
 template <typename T, bool G3>
-__global__ void __launch_bounds__(256) k_project_band(const typename C2<T>::t* __restrict__ u,
+__global__ void __launch_bounds__(384) k_project_band(const typename C2<T>::t* __restrict__ u,
                                                       typename C2<T>::t* __restrict__ sigma,
                                                       const typename C2<T>::t* __restrict__ Pbd,
                                                       const T* __restrict__ cw, const int32_t* __restrict__ bcells,
@@ -366,60 +411,54 @@ __global__ void __launch_bounds__(256) k_project_band(const typename C2<T>::t* _
   using V = typename C2<T>::t;
   using M = Mfma<T>;
   using v4 = typename M::v4;
-  constexpr int U = 96, RT = U / 16;
-  const int lane = threadIdx.x & 63, kl = lane >> 4, col = lane & 15;
-  const int r0 = blockIdx.y * 64 + (threadIdx.x >> 6) * 16;
-  if (r0 >= nrhs) return;                       // whole wave; no barriers below
+  constexpr int U = 96;
+  const int lane = threadIdx.x & 63, kl = lane >> 4, col = lane & 15, rt = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * 16;
   const int c = bcells[blockIdx.x];
   const int nb = cell_nb[c];
   const int64_t b0 = cell_start[c] + cell_nint[c];
   const bool rv = r0 + col < nrhs;
   const typename C2<T>::t* __restrict__ ur = u + (int64_t)(rv ? r0 + col : r0) * N + b0;
   const T* __restrict__ cwb = cw + b0;
-  const V* __restrict__ prow = Pbd + (int64_t)cell_boff[c] * U + col;
-  v4 re[RT], im[RT], r3[G3 ? RT : 1];
+  const V* __restrict__ prow = Pbd + (int64_t)cell_boff[c] * U + 16 * rt + col;
+  v4 re = v4{0, 0, 0, 0}, im = v4{0, 0, 0, 0}, p3 = v4{0, 0, 0, 0};
+  // steps of 4 nodes in groups of D = 4 steps; the next group's operands
+  // (raw densities and weights) are loaded while the current group's
+  // products run
+  constexpr int D = 4;
+  const int ngroups = (nb + 4 * D - 1) / (4 * D);
+  auto load = [&](int g, V* x, T* wc, V* w) {
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    re[rt] = v4{0, 0, 0, 0};
-    im[rt] = v4{0, 0, 0, 0};
-    if (G3) r3[rt] = v4{0, 0, 0, 0};
-  }
-  const int nsteps = (nb + 3) / 4;
-  auto load = [&](int kk, V& x, V* w) {
-    const int node = 4 * kk + kl;
-    x = czero<V>();
-    if (node < nb) {
-      if (rv) x = cscale(ur[node], cwb[node]);
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) w[rt] = prow[(int64_t)node * U + 16 * rt];
-    } else {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) w[rt] = czero<V>();
+    for (int z = 0; z < D; ++z) {
+      const int node = 4 * (D * g + z) + kl;
+      const bool ok = node < nb;
+      x[z] = ok && rv ? ur[node] : czero<V>();
+      wc[z] = ok && rv ? cwb[node] : (T)0;
+      w[z] = ok ? prow[(int64_t)node * U] : czero<V>();
     }
   };
-  V xn, wn[RT];
-  if (nsteps > 0) load(0, xn, wn);
-  for (int kk = 0; kk < nsteps; ++kk) {
-    const V x = xn;
-    V w[RT];
+  V xn[D], wn[D];
+  T cn[D];
+  if (ngroups > 0) load(0, xn, cn, wn);
+  for (int g = 0; g < ngroups; ++g) {
+    V x[D], w[D];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) w[rt] = wn[rt];
-    if (kk + 1 < nsteps) load(kk + 1, xn, wn);
-    if (G3) {
-      const T xs = x.x + x.y;
+    for (int z = 0; z < D; ++z) {
+      x[z] = cscale(xn[z], cn[z]);
+      w[z] = wn[z];
+    }
+    if (g + 1 < ngroups) load(g + 1, xn, cn, wn);
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        re[rt] = M::op(xs, w[rt].x, re[rt]);
-        im[rt] = M::op(x.y, w[rt].x + w[rt].y, im[rt]);
-        r3[rt] = M::op(x.x, w[rt].y - w[rt].x, r3[rt]);
-      }
-    } else {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        re[rt] = M::op(x.x, w[rt].x, re[rt]);
-        re[rt] = M::op(-x.y, w[rt].y, re[rt]);
-        im[rt] = M::op(x.x, w[rt].y, im[rt]);
-        im[rt] = M::op(x.y, w[rt].x, im[rt]);
+    for (int z = 0; z < D; ++z) {
+      if (G3) {
+        re = M::op(x[z].x + x[z].y, w[z].x, re);
+        im = M::op(x[z].y, w[z].x + w[z].y, im);
+        p3 = M::op(x[z].x, w[z].y - w[z].x, p3);
+      } else {
+        re = M::op(x[z].x, w[z].x, re);
+        re = M::op(-x[z].y, w[z].y, re);
+        im = M::op(x[z].x, w[z].y, im);
+        im = M::op(x[z].y, w[z].x, im);
       }
     }
   }
@@ -428,19 +467,16 @@ __global__ void __launch_bounds__(256) k_project_band(const typename C2<T>::t* _
   for (int q = 0; q < 4; ++q) {
     const int r = r0 + M::row(lane, q);
     if (r >= nrhs) continue;
-    V* out = sigma + ((int64_t)r * ncell + c) * U + col;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      V o;
-      if (G3) {
-        o.x = re[rt][q] - im[rt][q];
-        o.y = re[rt][q] + r3[rt][q];
-      } else {
-        o.x = re[rt][q];
-        o.y = im[rt][q];
-      }
-      out[16 * rt] = has_int ? cadd(out[16 * rt], o) : o;
+    V* out = sigma + ((int64_t)r * ncell + c) * U + 16 * rt + col;
+    V o;
+    if (G3) {
+      o.x = re[q] - im[q];
+      o.y = re[q] + p3[q];
+    } else {
+      o.x = re[q];
+      o.y = im[q];
     }
+    *out = has_int ? cadd(*out, o) : o;
   }
 }
 
@@ -2851,27 +2887,26 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
         constexpr bool G3 = std::is_same<T, float>::value;
         if (d.nicell > 0) {
           const int64_t ncols = (int64_t)d.nicell * nrhs;
-          // tiles of 16 pairs; single-precision batches: 8 waves per
-          // workgroup, one workgroup per compute unit (each keeps one LDS
-          // copy of Psh and walks its tiles); otherwise 2 waves per
-          // workgroup, one tile each (the same sums per pair either way)
+          // tiles of 16 pairs; single-precision batches: the persistent
+          // kernel, one workgroup per compute unit; otherwise one tile per
+          // wave (the same products per pair either way)
           const int64_t ntl = (ncols + 15) / 16;
           bool done = false;
           if constexpr (G3) {
             if (ntl >= 256 * 8) {
-              hipLaunchKernelGGL((k_project_int<T, G3, 8>), dim3(256), dim3(512), (size_t)64 * 96 * sizeof(V), st,
-                                 u, sigma, (const V*)d.PshT, d.cw, d.slot_map, d.icells, d.nicell, d.ncell, d.N,
+              hipLaunchKernelGGL((k_project_int_walk<T, G3>), dim3(256), dim3(512), (size_t)64 * 96 * sizeof(V),
+                                 st, u, sigma, (const V*)d.PshT, d.cw, d.slot_map, d.icells, d.nicell, d.ncell, d.N,
                                  nrhs);
               done = true;
             }
           }
           if (!done)
-            hipLaunchKernelGGL((k_project_int<T, G3, 2>), dim3((unsigned)((ntl + 1) / 2)), dim3(128),
+            hipLaunchKernelGGL((k_project_int<T, G3>), dim3((unsigned)((ntl + 3) / 4)), dim3(256),
                                (size_t)64 * 96 * sizeof(V), st, u, sigma, (const V*)d.PshT, d.cw, d.slot_map,
                                d.icells, d.nicell, d.ncell, d.N, nrhs);
         }
         if (d.nbcell > 0)
-          hipLaunchKernelGGL((k_project_band<T, G3>), dim3(d.nbcell, (nrhs + 63) / 64), dim3(256), 0, st, u, sigma,
+          hipLaunchKernelGGL((k_project_band<T, G3>), dim3(d.nbcell, (nrhs + 15) / 16), dim3(384), 0, st, u, sigma,
                              (const V*)d.Pbd, d.cw, d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
                              d.N, d.ncell, nrhs);
       } else if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
@@ -3179,9 +3214,9 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_rows<float, -1, 256>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
-  set((const void*)k_project_int<float, true, 8>);
-  set((const void*)k_project_int<double, false, 2>);
-  set((const void*)k_project_int<float, true, 2>);
+  set((const void*)k_project_int_walk<float, true>);
+  set((const void*)k_project_int<double, false>);
+  set((const void*)k_project_int<float, true>);
   set((const void*)k_fft_cols_conv<double, 256>);
   set((const void*)k_fft_cols_conv<float, 256>);
   set((const void*)k_fft_cols_conv<double, 512>);
