@@ -381,7 +381,9 @@ ls_status ls_scattered_field(ls_op* op, const ls_targets* tg, const void* u_tot,
  * the right-hand sides of its next solve (up to max_batch); solves of
  * different scatterers run concurrently.  A batched solve advances every
  * right-hand side independently and freezes converged ones, so a request's
- * result is bitwise the same alone and in any mix.  The n2 callback is called
+ * result is bitwise the same alone and in any mix of fewer than 64
+ * right-hand sides (larger batches project onto the equivalent sources with
+ * other kernels, equal to rounding).  The n2 callback is called
  * from a worker thread when its operator is built.
  * --------------------------------------------------------------------------- */
 typedef struct ls_server ls_server;

@@ -390,8 +390,64 @@ __global__ void __launch_bounds__(512) k_project_int_walk(const typename C2<T>::
   }
 }
 
-// a1 on the matrix cores, boundary-patch nodes of a cell (their projection
-// columns Pbd differ node by node): Sigma^T [rhs x 96] += Phi^T [rhs x nb]
+// a1, boundary-patch nodes of a cell (their projection columns Pbd differ
+// node by node): sigma[r][c] += sum_b Pbd_b phi_b for RB right-hand sides
+// per workgroup, added to the interior part k_project_int wrote (cells with
+// interior nodes) or started from zero.  Thread (t, g): source t, the nodes
+// b = g mod 2; the odd half is added to the even one through LDS.  The sums
+// of one output run in the same order for every RB, so results do not
+// depend on the batch.
+template <typename T, int RB>
+__global__ void __launch_bounds__(192) k_project_band(const typename C2<T>::t* __restrict__ u,
+                                                      typename C2<T>::t* __restrict__ sigma,
+                                                      const typename C2<T>::t* __restrict__ Pbd,
+                                                      const T* __restrict__ cw, const int32_t* __restrict__ bcells,
+                                                      const int32_t* __restrict__ cell_start,
+                                                      const int32_t* __restrict__ cell_nint,
+                                                      const int32_t* __restrict__ cell_nb,
+                                                      const int32_t* __restrict__ cell_boff, int64_t N, int ncell,
+                                                      int nrhs) {
+  using V = typename C2<T>::t;
+  constexpr int U = 96;
+  extern __shared__ unsigned char smem_raw[];
+  const int c = bcells[blockIdx.x], r0 = blockIdx.y * RB, tid = threadIdx.x;
+  const int nb = cell_nb[c];
+  V* phi = reinterpret_cast<V*>(smem_raw);   // [nb][RB]
+  V* red = phi + (size_t)nb * RB;            // [RB][U] odd half's sums
+  const int64_t b0 = cell_start[c] + cell_nint[c];
+  for (int i = tid; i < nb * RB; i += blockDim.x) {
+    const int bb = i % nb, q = i / nb, r = r0 + q;    // consecutive threads: consecutive nodes
+    const int64_t j = b0 + bb;
+    phi[bb * RB + q] = r < nrhs ? cscale(u[(int64_t)r * N + j], cw[j]) : czero<V>();
+  }
+  __syncthreads();
+  const int t = tid % U, g = tid / U;
+  const bool has_int = cell_nint[c] > 0;
+  V acc[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q)
+    acc[q] = (g == 0 && has_int && r0 + q < nrhs) ? sigma[((int64_t)(r0 + q) * ncell + c) * U + t] : czero<V>();
+  const V* prow = Pbd + (int64_t)cell_boff[c] * U + t;
+  for (int bb = g; bb < nb; bb += 2) {
+    const V p = prow[(int64_t)bb * U];
+    const V* ph = phi + bb * RB;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = cfma(p, ph[q], acc[q]);
+  }
+  if (g == 1) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) red[q * U + t] = acc[q];
+  }
+  __syncthreads();
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (r0 + q < nrhs) sigma[((int64_t)(r0 + q) * ncell + c) * U + t] = cadd(acc[q], red[q * U + t]);
+  }
+}
+
+// a1 on the matrix cores for large batches, boundary-patch nodes of a cell
+// (their projection columns Pbd differ node by node): Sigma^T [rhs x 96] += Phi^T [rhs x nb]
 // Pbd^T [nb x 96] for the cell's nb nodes, added to the interior part
 // k_project_int wrote (cells with interior nodes) or started from zero.
 // One workgroup per (cell, 16 right-hand sides), wave w on sources
@@ -399,7 +455,7 @@ __global__ void __launch_bounds__(512) k_project_int_walk(const typename C2<T>::
 // 4 kk + lane / 16; B operand: 16 consecutive sources of Pbd).  Each
 // right-hand side's sums run in one fixed order whatever the batch.
 template <typename T, bool G3>
-__global__ void __launch_bounds__(384) k_project_band(const typename C2<T>::t* __restrict__ u,
+__global__ void __launch_bounds__(384) k_project_band_mfma(const typename C2<T>::t* __restrict__ u,
                                                       typename C2<T>::t* __restrict__ sigma,
                                                       const typename C2<T>::t* __restrict__ Pbd,
                                                       const T* __restrict__ cw, const int32_t* __restrict__ bcells,
@@ -2905,10 +2961,28 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                                (size_t)64 * 96 * sizeof(V), st, u, sigma, (const V*)d.PshT, d.cw, d.slot_map,
                                d.icells, d.nicell, d.ncell, d.N, nrhs);
         }
-        if (d.nbcell > 0)
-          hipLaunchKernelGGL((k_project_band<T, G3>), dim3(d.nbcell, (nrhs + 15) / 16), dim3(384), 0, st, u, sigma,
-                             (const V*)d.Pbd, d.cw, d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff,
-                             d.N, d.ncell, nrhs);
+        // boundary-patch nodes: batches of 64 or more right-hand sides on the
+        // matrix cores; fewer on the vector units (beside the interior
+        // contraction of the concurrent apply, the matrix-core kernel slowed
+        // it more than it saved)
+        if (d.nbcell > 0 && nrhs >= 64) {
+          hipLaunchKernelGGL((k_project_band_mfma<T, G3>), dim3(d.nbcell, (nrhs + 15) / 16), dim3(384), 0, st, u,
+                             sigma, (const V*)d.Pbd, d.cw, d.bcells, d.cell_start, d.cell_nint, d.cell_nb,
+                             d.cell_boff, d.N, d.ncell, nrhs);
+        } else if (d.nbcell > 0) {
+          const int RBB = nrhs >= 16 ? 16 : nrhs >= 4 ? 4 : 1;
+          const size_t shp = ((size_t)d.max_nb * RBB + (size_t)RBB * 96) * sizeof(V);
+          const dim3 gb(d.nbcell, (nrhs + RBB - 1) / RBB);
+          if (RBB == 16)
+            hipLaunchKernelGGL((k_project_band<T, 16>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
+                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
+          else if (RBB == 4)
+            hipLaunchKernelGGL((k_project_band<T, 4>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
+                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
+          else
+            hipLaunchKernelGGL((k_project_band<T, 1>), gb, dim3(192), shp, st, u, sigma, (const V*)d.Pbd, d.cw,
+                               d.bcells, d.cell_start, d.cell_nint, d.cell_nb, d.cell_boff, d.N, d.ncell, nrhs);
+        }
       } else if (d.q == 12 && d.S == 64 && d.PshT && nrhs >= RB && shb <= 64 * 1024) {
         hipLaunchKernelGGL((k_project_rb<T, RB>), dim3(d.ncell, (nrhs + RB - 1) / RB), dim3(192), shb, st, u, sigma,
                            (const V*)d.PshT, (const V*)d.Pbd, d.cw, d.slot_map, d.cell_start, d.cell_nint, d.cell_nb,
@@ -3217,6 +3291,12 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_project_int_walk<float, true>);
   set((const void*)k_project_int<double, false>);
   set((const void*)k_project_int<float, true>);
+  set((const void*)k_project_band<double, 16>);
+  set((const void*)k_project_band<double, 4>);
+  set((const void*)k_project_band<double, 1>);
+  set((const void*)k_project_band<float, 16>);
+  set((const void*)k_project_band<float, 4>);
+  set((const void*)k_project_band<float, 1>);
   set((const void*)k_fft_cols_conv<double, 256>);
   set((const void*)k_fft_cols_conv<float, 256>);
   set((const void*)k_fft_cols_conv<double, 512>);

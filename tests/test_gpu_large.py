@@ -223,6 +223,46 @@ def test_multi_rhs_batch_matches_single_and_oracle():
     assert (torch.linalg.norm(x1 - X[2]) / torch.linalg.norm(x1)).item() < 1e-6
 
 
+def test_large_batch_projection_matches_oracle():
+    """64 right-hand sides in single precision on the kappa = 16 pi star take
+    the batch projection kernels (the interior part as a walking kernel, the
+    boundary-patch nodes on the matrix cores): sampled rows of every sixth
+    right-hand side against the oracle, and every right-hand side against its
+    own single apply (smaller launches use other kernels, so to rounding)."""
+    import torch
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd import binding
+    cfg = config("star_k16pi")
+    op = _op(cfg)
+    xy, key = op.points()
+    R = 64
+    dirs = [2 * np.pi * r / R for r in range(R)]
+    U = torch.tensor(np.stack([plane_wave(cfg, xy, a) for a in dirs]), dtype=torch.complex64, device="cuda")
+    saved = op.get_schedule(binding.LS_C64)
+    try:
+        op.set_schedule(binding.LS_C64, csr_variant=2)     # rows as for one right-hand side
+        V = torch.empty_like(U)
+        op.apply(U, V)
+        V1 = torch.empty_like(U)
+        for k in range(R):
+            op.apply(U[k].contiguous(), V1[k])
+        torch.cuda.synchronize()
+    finally:
+        op.set_schedule(binding.LS_C64, **saved)
+    dif = (torch.linalg.norm(V - V1, dim=1) / torch.linalg.norm(V1, dim=1)).max().item()
+    orc = Setup2D(cfg, n2_function(cfg))
+    p = match_keys(orc.pts["key"], key)
+    rows = _sampled_rows(orc, 8)
+    A = orc.A_rows(rows)
+    err = 0.0
+    for k in range(0, R, 6):
+        v_or = A @ plane_wave(cfg, orc.pts["x"], dirs[k])
+        v = V[k].cpu().numpy().astype(complex)[p][rows]
+        err = max(err, np.abs(v - v_or).max() / np.abs(v_or).max())
+    print(f"64 right-hand sides: vs single applies {dif:.2e}, vs oracle rows {err:.2e}", flush=True)
+    assert dif < F32_TOL and err < F32_TOL
+
+
 def test_edge_cases_tiny_grid_zero_input_and_errors():
     import torch
     from oracle.op2d import Setup2D
