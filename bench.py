@@ -53,14 +53,14 @@ def stage_bytes(st, N, n_int, s, s_w, csr_variant=0):
         "interp": ncell * F * s + nb * F * s_w + S * F * s_w + 2 * N * s,
         "near_shared": S * Wn * Wn * s_w + n_int * (s + r) + 2 * n_int * s,
         "near_csr": (st["csr_nnz"] * (s_w + 2) + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s
-                     if csr_variant not in (2, 3) else
+                     if csr_variant not in (2, 3, 4) else
                      st["csr_nnz"] * s_w + st["csr_runs"] * 8 + st["csr_rows"] * (8 + 4 + 4 + 2 * s) + N * s),
     }
 
 
 # single-precision kernel of each one-kernel stage (the FFT stages run several)
-STAGE_KERNEL = {"project": "k_project2<float>", "fill": "k_fill<float>", "spectral": "k_spectral<float>",
-                "interp": "k_interp_mfma<float,16>", "near_shared": "k_near_shared_mfma_db<1>",
+STAGE_KERNEL = {"project": "k_project_int<float,true>", "fill": "k_fill<float>", "spectral": "k_spectral<float>",
+                "interp": "k_interp_mfma<float,16>", "near_shared": "k_near_shared_mfma_db<1,false>",
                 "near_csr": "k_near_csr4"}
 
 
@@ -564,11 +564,14 @@ def main():
     achieved = byts[dom] / (p32[dom] * 1e-3) / 1e9
     kname = STAGE_KERNEL.get(dom, dom)
     if tune and dom == "near_csr":
-        kname = {0: "k_near_csr4", 1: "k_near_csr<float,float2,unsigned short>", 2: "k_near_csr4r", 3: "k_near_csr4r"}[
-            tune["fp32"]["csr_variant"]]
+        # (3 and 4, the dense tiles, fall back to the run-length rows for one
+        # right-hand side)
+        kname = {0: "k_near_csr4", 1: "k_near_csr<float,float2,unsigned short>", 2: "k_near_csr4r", 3: "k_near_csr4r",
+                 4: "k_near_csr4r"}[tune["fp32"]["csr_variant"]]
     if tune and dom == "near_shared":
         nv = tune["fp32"]["near_variant"]
-        kname = "k_near_shared_mfma<float,2>" if nv == 1 else f"k_near_shared_mfma_db<{ {0: 1, 2: 2, 3: 4}[nv] }>"
+        kname = "k_near_shared_mfma<float,2>" if nv == 1 else "k_near_shared_mfma_db<" + {
+            0: "1,false", 2: "2,false", 3: "4,false", 4: "4,true"}[nv] + ">"
     roof = {"kernel": kname, "stage": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": counter_traffic(kname),
             "algorithmic_bytes": int(byts[dom]), "avg_ms": round(p32[dom], 4)}
