@@ -242,7 +242,9 @@ typedef struct {
   double fft_ms;        /* best time of the transform stages with the chosen tile */
   double near_ms;       /* best time of the interior contraction stage */
   double csr_ms;        /* best time of the boundary-patch rows stage */
-  double apply_ms;      /* one apply with all choices in place */
+  double apply_ms;      /* one apply with all choices in place (the near field concurrent
+                           with the far field; the last tuning stage times whole applies so
+                           and may revise the transform threads, tile and interior variant) */
 } ls_tune_result;
 
 /* Set the kernel schedule for later applies in precision prec (fields

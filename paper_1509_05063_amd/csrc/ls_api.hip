@@ -1155,6 +1155,69 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   ls_status s = measure(0, 7, &t);
   if (s) return s;
   res->apply_ms = t;
+  // With the near field forked onto the side stream the stages share the
+  // chip, and a schedule that is faster alone can be slower beside the others
+  // (512-thread row transforms: faster alone, 0.714 against 0.681 ms per
+  // concurrent apply with 256).  Coordinate descent over the transform
+  // threads and tile and the interior contraction variant, timed on whole
+  // concurrent applies.
+  if (d.side) {
+    // best of 3 runs of 6 back-to-back applies (as a solve issues them),
+    // per apply
+    auto conc = [&](double* best_t) -> ls_status {
+      constexpr int K = 6;
+      *best_t = 1e30;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(hipEventRecord(ev[0], st));
+        for (int k = 0; k < K; ++k) {
+          hipError_t e = lsx::launch_apply<T>(d, u, v, nrhs, ws, st);
+          if (e != hipSuccess) return fail(LS_EDEVICE, std::string("apply launch: ") + hipGetErrorString(e));
+        }
+        HIPCHK(hipEventRecord(ev[8], st));
+        HIPCHK(hipEventSynchronize(ev[8]));
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[8]);
+        *best_t = std::min(*best_t, (double)ms / K);
+      }
+      return LS_OK;
+    };
+    double cur;
+    s = conc(&cur);
+    if (s) return s;
+    log("concurrent apply (staged choices)", 0, 0, cur);
+    // try one field at a time; keep a change only if the whole apply is faster
+    auto trial = [&](int* field, int value, const char* what) -> ls_status {
+      const int keep = *field;
+      if (value == keep) return LS_OK;
+      *field = value;
+      double t2;
+      ls_status s2 = conc(&t2);
+      if (s2) return s2;
+      log(what, value, 0, t2);
+      if (t2 < cur) cur = t2;
+      else *field = keep;
+      return LS_OK;
+    };
+    for (int nth : {256, 512, 1024})
+      if ((s = trial(&d.rows_nth, nth, "concurrent: fft row threads"))) return s;
+    if (d.fft_variant == 1)
+      for (int cn : {256, 512})
+        if ((s = trial(&d.cols_nth, cn, "concurrent: fft column threads"))) return s;
+    {
+      const int tmax = (int)((150 * 1024 - d.Pa * sizeof(T) * 2) /
+                             (2 * (size_t)d.Pa * sizeof(T) * 2 * (d.fft_variant + 1)));
+      const int t0 = d.tc;
+      for (int tc : {t0 / 2, t0 * 2})
+        if (tc >= 1 && tc <= tmax && (s = trial(&d.tc, tc, "concurrent: fft column tile"))) return s;
+    }
+    for (int var = 0; var < nnear; ++var)
+      if ((s = trial(&d.near_variant, var, "concurrent: near variant"))) return s;
+    res->fft_col_tile = d.tc;
+    res->fft_row_threads = d.rows_nth;
+    res->fft_col_threads = d.cols_nth;
+    res->near_variant = d.near_variant;
+    res->apply_ms = cur;
+  }
   return LS_OK;
 }
 }  // namespace
