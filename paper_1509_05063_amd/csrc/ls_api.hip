@@ -695,6 +695,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     const size_t nr = h.rows.size();
     std::vector<int32_t> rptr(nr + 1, 0), rcs, rpre;
     bool fits = true;
+    int rmax = 0;
     for (size_t r = 0; r < nr && fits; ++r) {
       const int64_t b0 = h.rowptr[r], len = h.rowptr[r + 1] - b0;
       for (int64_t k = 0; k < len; ++k)
@@ -707,10 +708,12 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
         rpre.push_back((int32_t)len);
       }
       rptr[r + 1] = (int32_t)rcs.size();
+      rmax = std::max(rmax, rptr[r + 1] - rptr[r]);
       if (rptr[r + 1] - rptr[r] > 256) fits = false;
     }
     if (fits && !rcs.empty()) {
       op->stats[12] = (int64_t)rcs.size();
+      a.run_max = rmax;
       UP(upload_i(op, rptr, &a.run_ptr));
       UP(upload_i(op, rcs, &a.run_cs));
       UP(upload_i(op, rpre, &a.run_pre));
@@ -871,6 +874,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   b.run_ptr = a.run_ptr;
   b.run_cs = a.run_cs;
   b.run_pre = a.run_pre;
+  b.run_max = a.run_max;
   // twiddles exp(-2 pi i k / n), computed in double
   for (int which = 0; which < 2; ++which) {
     int n = which == 0 ? h.Pa : h.Pb;

@@ -2025,8 +2025,9 @@ __global__ void __launch_bounds__(256) k_near_csr4(const float2* __restrict__ u,
 // columns cs[r], cs[r]+1, ...  One wavefront per row stages the row's run
 // table in LDS; each lane finds the run of its four consecutive entries by
 // bisection.  Weights as in k_near_csr4 (rows padded to four entries; the
-// padding sits in a final run at column 0 with zero weights).
-constexpr int CSR_MAX_RUNS = 256;
+// padding sits in a final run at column 0 with zero weights).  The tables
+// take dynamic LDS, 4 (2 rmax + 1) words per workgroup for rows of at most
+// rmax runs (the operator's largest).
 __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u, float2* __restrict__ v,
                                                     const int64_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ rows,
@@ -2034,17 +2035,17 @@ __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u
                                                     const int32_t* __restrict__ run_cs,
                                                     const int32_t* __restrict__ run_pre,
                                                     const float2* __restrict__ vals, int nrows, int64_t N, int nrhs,
-                                                    float k2) {
+                                                    float k2, int rmax) {
   constexpr int RB = 4;
-  __shared__ int cs_s[4][CSR_MAX_RUNS], pre_s[4][CSR_MAX_RUNS + 1];
+  extern __shared__ int tables[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = blockIdx.x * 4 + wv;
   if (row >= nrows) return;
   const int64_t b = rowptr[row], e = rowptr[row + 1];
   const int len = (int)(e - b);
   const int r0 = run_ptr[row], nr = run_ptr[row + 1] - r0;
-  int* cs = cs_s[wv];
-  int* pre = pre_s[wv];
+  int* cs = tables + wv * (2 * rmax + 1);
+  int* pre = cs + rmax;
   for (int i = lane; i < nr; i += 64) {
     cs[i] = run_cs[r0 + i];
     pre[i] = run_pre[r0 + i];
@@ -3138,8 +3139,9 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                                (float2*)vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
                                d.bt_ntiles, d.N, nrhs, (float)k2);
         } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
-          hipLaunchKernelGGL(k_near_csr4r, g, b, 0, ns, (const float2*)u, (float2*)vt, d.rowptr, d.rows, d.run_ptr,
-                             d.run_cs, d.run_pre, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
+          hipLaunchKernelGGL(k_near_csr4r, g, b, (size_t)4 * (2 * d.run_max + 1) * sizeof(int), ns, (const float2*)u,
+                             (float2*)vt, d.rowptr, d.rows, d.run_ptr, d.run_cs, d.run_pre, (const float2*)d.vals,
+                             d.nrows, d.N, nrhs, (float)k2, d.run_max);
         else if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
           hipLaunchKernelGGL(k_near_csr4, g, b, 0, ns, (const float2*)u, (float2*)vt, d.rowptr, d.rows, d.colbase,
                              d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);

@@ -51,8 +51,10 @@ struct DevView {
   const int64_t* rowptr = nullptr;
   // the same columns as runs of consecutive indices: run r of row i is
   // run_ptr[i] + r, covering the row's entries from run_pre on at columns
-  // run_cs, run_cs + 1, ... (null when some row has more than 256 runs)
+  // run_cs, run_cs + 1, ... (null when some row has more than 256 runs);
+  // run_max: the largest number of runs of a row
   const int32_t *run_ptr = nullptr, *run_cs = nullptr, *run_pre = nullptr;
+  int run_max = 0;
   // Single precision only: the same rows as dense tiles of 16 rows of one
   // cell and kind (boundary-patch or interior targets).  Tile t: target rows
   // bt_rows[16 t ..] (-1 = padding), K = bt_info[2 t] (multiple of 4)
