@@ -1747,26 +1747,32 @@ __global__ void __launch_bounds__(256) k_near_shared(const typename C2<T>::t* __
 // is then a dense contraction: a workgroup takes 16*NT cells, wave w the
 // slots 16w..16w+15, K runs over the window row by row (W row and psi rows
 // staged in LDS), complex products as four real MFMA 16x16x4 updates.
-template <typename T>
+// The psi lattice of RB right-hand sides per thread (the node of a lattice
+// point is looked up once for all of them).
+template <typename T, int RB>
 __global__ void k_psi_grid(const typename C2<T>::t* __restrict__ u, typename C2<T>::t* __restrict__ grid,
                            const T* __restrict__ dw, const int32_t* __restrict__ cell_map,
-                           const int32_t* __restrict__ slot_map, int L, int ch, int S, int Gw, int64_t N) {
+                           const int32_t* __restrict__ slot_map, int L, int ch, int S, int Gw, int64_t N,
+                           int nrhs) {
   using V = typename C2<T>::t;
   const int64_t gsz = (int64_t)Gw * Gw;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= gsz) return;
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB;
   const int gy = (int)(idx / Gw), gx = (int)(idx % Gw);
   const int cx = gx / ch - 2, cy = gy / ch - 2;
-  V val = czero<V>();
+  int j = -1;
   if (cx >= 0 && cy >= 0 && cx < L && cy < L) {
-    int c = cell_map[cy * L + cx];
-    if (c >= 0) {
-      int j = slot_map[(int64_t)c * S + (gy % ch) * ch + (gx % ch)];
-      if (j >= 0) val = cscale(u[(int64_t)r * N + j], dw[j]);
-    }
+    const int c = cell_map[cy * L + cx];
+    if (c >= 0) j = slot_map[(int64_t)c * S + (gy % ch) * ch + (gx % ch)];
   }
-  grid[(int64_t)r * gsz + idx] = val;
+  const T w = j >= 0 ? dw[j] : (T)0;
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int r = r0 + q;
+    if (r >= nrhs) break;
+    grid[(int64_t)r * gsz + idx] = j >= 0 ? cscale(u[(int64_t)r * N + j], w) : czero<V>();
+  }
 }
 
 
@@ -3077,8 +3083,12 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       const int Gw = (d.L + 4) * 8;
       V* grid = lat + (size_t)nrhs * 4 * plane;
       const int64_t gsz = (int64_t)Gw * Gw;
-      hipLaunchKernelGGL(k_psi_grid<T>, dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, ns, u, grid, d.dw,
-                         d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N);
+      if (nrhs >= 8)
+        hipLaunchKernelGGL((k_psi_grid<T, 8>), dim3((unsigned)((gsz + 255) / 256), (nrhs + 7) / 8), dim3(256), 0, ns,
+                           u, grid, d.dw, d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N, nrhs);
+      else
+        hipLaunchKernelGGL((k_psi_grid<T, 1>), dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, ns, u, grid,
+                           d.dw, d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N, nrhs);
       if (std::is_same<T, float>::value && d.near_variant != 1) {
         const int CT = d.near_variant == 2 ? 2 : d.near_variant >= 3 ? 4 : 1;
         const dim3 gr((d.nicell + 16 * CT - 1) / (16 * CT), nrhs), bl(256 * CT);
