@@ -447,9 +447,10 @@ __global__ void __launch_bounds__(192) k_project_band(const typename C2<T>::t* _
 }
 
 // a1 on the matrix cores for large batches, boundary-patch nodes of a cell
-// (their projection columns Pbd differ node by node): Sigma^T [rhs x 96] += Phi^T [rhs x nb]
-// Pbd^T [nb x 96] for the cell's nb nodes, added to the interior part
-// k_project_int wrote (cells with interior nodes) or started from zero.
+// (their projection columns Pbd differ node by node):
+// Sigma^T [rhs x 96] += Phi^T [rhs x nb] Pbd^T [nb x 96] for the cell's nb
+// nodes, added to the interior part k_project_int wrote (cells with
+// interior nodes) or started from zero.
 // One workgroup per (cell, 16 right-hand sides), wave w on sources
 // 16 w .. 16 w + 15 (MFMA A operand: right-hand side lane % 16, nodes
 // 4 kk + lane / 16; B operand: 16 consecutive sources of Pbd).  Each
