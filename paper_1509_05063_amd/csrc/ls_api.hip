@@ -1110,6 +1110,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->fft_col_tile = best_tc;
   res->fft_variant = best_fv;
   res->fft_row_threads = best_nth;
+  res->fft_rows_inplace = d.rows_ip;
   res->fft_col_threads = d.cols_nth;
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
@@ -1204,6 +1205,9 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
     };
     for (int nth : {256, 512, 1024})
       if ((s = trial(&d.rows_nth, nth, "concurrent: fft row threads"))) return s;
+    if (d.pb.n <= lsx::kRowIpMax)
+      for (int ip : {1, 0})
+        if ((s = trial(&d.rows_ip, ip, "concurrent: one-buffer row transforms"))) return s;
     if (d.fft_variant == 1)
       for (int cn : {256, 512})
         if ((s = trial(&d.cols_nth, cn, "concurrent: fft column threads"))) return s;
@@ -1219,6 +1223,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
     res->fft_col_tile = d.tc;
     res->fft_row_threads = d.rows_nth;
     res->fft_col_threads = d.cols_nth;
+    res->fft_rows_inplace = d.rows_ip;
     res->near_variant = d.near_variant;
     res->apply_ms = cur;
   }
@@ -1279,7 +1284,10 @@ ls_status set_schedule_view(const ls_op* op, lsx::DevView<T>& d, const ls_tune_r
   if (r->csr_variant < 0 || r->csr_variant > (f32 ? 4 : 0)) return fail(LS_EINVAL, "csr_variant out of range");
   if (r->csr_variant == 2 && !d.run_ptr) return fail(LS_EINVAL, "csr_variant 2: the op keeps no run-length columns");
   if (r->csr_variant >= 3 && d.bt_ntiles == 0) return fail(LS_EINVAL, "csr_variant 3 / 4: the op keeps no dense tiles");
+  if (r->fft_rows_inplace != 0 && r->fft_rows_inplace != 1) return fail(LS_EINVAL, "fft_rows_inplace must be 0 or 1");
+  if (r->fft_rows_inplace && d.pb.n > lsx::kRowIpMax) return fail(LS_EINVAL, "fft_rows_inplace: rows longer than 4096");
   (void)op;
+  d.rows_ip = r->fft_rows_inplace;
   d.fft_variant = fv;
   d.tc = r->fft_col_tile;
   d.rows_nth = r->fft_row_threads;
@@ -1297,6 +1305,7 @@ void get_schedule_view(const lsx::DevView<T>& d, ls_tune_result* r) {
   r->fft_variant = d.fft_variant;
   r->fft_row_threads = d.rows_nth;
   r->fft_col_threads = d.cols_nth;
+  r->fft_rows_inplace = d.rows_ip;
 }
 }  // namespace
 }  // extern "C++"

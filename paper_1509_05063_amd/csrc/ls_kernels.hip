@@ -808,6 +808,91 @@ __device__ void stockham_lds(V* buf0, V* buf1, const V* __restrict__ tw, int n, 
   *result = src;
 }
 
+// One Stockham pass in place (one LDS buffer): every butterfly's inputs
+// (twiddled) are read into registers, a barrier, then the outputs are
+// written.  MB: butterflies per thread, at least n / (R nthr).
+template <typename V, int DIR, int R, int MB>
+__device__ __forceinline__ void stockham_pass_ip(V* buf, const V* __restrict__ tw, int n, int Ns, int tid,
+                                                 int nthr) {
+  const int nb = n / R;
+  const int twstep = n / (Ns * R);
+  const FastDiv fn(Ns);
+  V v[MB][R];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int j = tid + b * nthr;
+    if (j < nb) {
+      const int jq = fn.div(j), jm = j - jq * Ns;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        V x = buf[j + m * nb];
+        if (m > 0 && jm > 0) {
+          V t = tw[jm * m * twstep];
+          if (DIR < 0) t.y = -t.y;
+          x = cmul(x, t);
+        }
+        v[b][m] = x;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int j = tid + b * nthr;
+    if (j < nb) {
+      const int jq = fn.div(j), jm = j - jq * Ns;
+      dft_r<V, DIR, R>(v[b]);
+      const int o = jq * Ns * R + jm;
+#pragma unroll
+      for (int m = 0; m < R; ++m) buf[o + m * Ns] = v[b][m];
+    }
+  }
+  __syncthreads();
+}
+
+// All passes in place for a row of n <= NMAX points with NTH threads.
+template <typename V, int DIR, int NTH, int NMAX>
+__device__ void stockham_lds_ip(V* buf, const V* __restrict__ tw, int n, const int8_t* radix, int npass, int tid) {
+  int Ns = 1;
+  for (int p = 0; p < npass; ++p) {
+    const int R = radix[p];
+#define LS_IP(RR) stockham_pass_ip<V, DIR, RR, (NMAX / RR + NTH - 1) / NTH>(buf, tw, n, Ns, tid, NTH)
+    switch (R) {
+      case 2: LS_IP(2); break;
+      case 3: LS_IP(3); break;
+      case 4: LS_IP(4); break;
+      case 5: LS_IP(5); break;
+      case 6: LS_IP(6); break;
+      case 8: LS_IP(8); break;
+      case 9: LS_IP(9); break;
+      case 10: LS_IP(10); break;
+      case 12: LS_IP(12); break;
+      case 15: LS_IP(15); break;
+      default: LS_IP(16); break;
+    }
+#undef LS_IP
+    Ns *= R;
+  }
+}
+
+// Row transforms with one LDS buffer (half the LDS of k_fft_rows, two
+// barriers per pass); rows of at most NMAX points.
+template <typename T, int DIR, int NTH>
+__global__ void __launch_bounds__(NTH) k_fft_rows_ip(typename C2<T>::t* data, const typename C2<T>::t* __restrict__ tw,
+                                                     FftPlan plan, int64_t line_stride, int nload, int nstore,
+                                                     int64_t batch_stride) {
+  using V = typename C2<T>::t;
+  extern __shared__ unsigned char smem_raw[];
+  V* b0 = reinterpret_cast<V*>(smem_raw);
+  V* x = data + blockIdx.y * batch_stride + (int64_t)blockIdx.x * line_stride;
+  const int nl = min(nload, plan.n);
+  stage_lds<8>(b0, nl, [&](int i) { return x[i]; }, [](int i) { return i; });
+  zero_lds(b0 + nl, plan.n - nl, [](int i) { return i; });
+  __syncthreads();
+  stockham_lds_ip<V, DIR, NTH, kRowIpMax>(b0, tw, plan.n, plan.radix, plan.npass, threadIdx.x);
+  for (int i = threadIdx.x; i < nstore; i += NTH) x[i] = b0[i];
+}
+
 // transforms along the contiguous axis: one line per workgroup
 // (entries past nload are zero padding: not read; entries past nstore are
 // not needed downstream: not written)
@@ -3017,10 +3102,17 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     {
       size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
       // rows a >= na are zero padding: their transforms stay zero
-      auto rows_f = d.rows_nth == 1024 ? k_fft_rows<T, 1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, 1, 512>
-                                                                                     : k_fft_rows<T, 1, 256>;
-      hipLaunchKernelGGL(rows_f, dim3(d.na, nbatch), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
-                         (int64_t)d.Pb, d.nb, d.Pb, plane, (int64_t)0);
+      if (d.rows_ip) {
+        auto rows_f = d.rows_nth == 1024 ? k_fft_rows_ip<T, 1, 1024> : d.rows_nth == 512 ? k_fft_rows_ip<T, 1, 512>
+                                                                                           : k_fft_rows_ip<T, 1, 256>;
+        hipLaunchKernelGGL(rows_f, dim3(d.na, nbatch), dim3(d.rows_nth), sh / 2, st, lat, (const V*)d.twb, d.pb,
+                           (int64_t)d.Pb, d.nb, d.Pb, plane);
+      } else {
+        auto rows_f = d.rows_nth == 1024 ? k_fft_rows<T, 1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, 1, 512>
+                                                                                       : k_fft_rows<T, 1, 256>;
+        hipLaunchKernelGGL(rows_f, dim3(d.na, nbatch), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
+                           (int64_t)d.Pb, d.nb, d.Pb, plane, (int64_t)0);
+      }
       int TC = TCP;
       if (d.fft_variant == 1) {
         // fused column transforms + spectral product + inverse column transforms
@@ -3048,10 +3140,17 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                            lat,
                            (const V*)d.twa, d.pa, d.Pb, TC, 2 * plane, d.Pa, d.na, (int64_t)0);
       size_t sh = 2 * (size_t)d.pb.n * sizeof(V);
-      auto rows_i = d.rows_nth == 1024 ? k_fft_rows<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, -1, 512>
-                                                                                      : k_fft_rows<T, -1, 256>;
-      hipLaunchKernelGGL(rows_i, dim3(d.na, nrhs * 2), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
-                         (int64_t)d.Pb, d.Pb, d.nb, 2 * plane, (int64_t)0);
+      if (d.rows_ip) {
+        auto rows_i = d.rows_nth == 1024 ? k_fft_rows_ip<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows_ip<T, -1, 512>
+                                                                                            : k_fft_rows_ip<T, -1, 256>;
+        hipLaunchKernelGGL(rows_i, dim3(d.na, nrhs * 2), dim3(d.rows_nth), sh / 2, st, lat, (const V*)d.twb, d.pb,
+                           (int64_t)d.Pb, d.Pb, d.nb, 2 * plane);
+      } else {
+        auto rows_i = d.rows_nth == 1024 ? k_fft_rows<T, -1, 1024> : d.rows_nth == 512 ? k_fft_rows<T, -1, 512>
+                                                                                        : k_fft_rows<T, -1, 256>;
+        hipLaunchKernelGGL(rows_i, dim3(d.na, nrhs * 2), dim3(d.rows_nth), sh, st, lat, (const V*)d.twb, d.pb,
+                           (int64_t)d.Pb, d.Pb, d.nb, 2 * plane, (int64_t)0);
+      }
     }
     mark(5);
     if (lattice_only) return;   // the caller evaluates the field itself
@@ -3299,6 +3398,18 @@ hipError_t set_fft_lds_limits(size_t bytes) {
   set((const void*)k_fft_cols<double, -1>);
   set((const void*)k_fft_rows<float, 1, 256>);
   set((const void*)k_fft_rows<float, -1, 256>);
+  set((const void*)k_fft_rows_ip<float, 1, 256>);
+  set((const void*)k_fft_rows_ip<float, -1, 256>);
+  set((const void*)k_fft_rows_ip<float, 1, 512>);
+  set((const void*)k_fft_rows_ip<float, -1, 512>);
+  set((const void*)k_fft_rows_ip<float, 1, 1024>);
+  set((const void*)k_fft_rows_ip<float, -1, 1024>);
+  set((const void*)k_fft_rows_ip<double, 1, 256>);
+  set((const void*)k_fft_rows_ip<double, -1, 256>);
+  set((const void*)k_fft_rows_ip<double, 1, 512>);
+  set((const void*)k_fft_rows_ip<double, -1, 512>);
+  set((const void*)k_fft_rows_ip<double, 1, 1024>);
+  set((const void*)k_fft_rows_ip<double, -1, 1024>);
   set((const void*)k_fft_cols<float, 1>);
   set((const void*)k_fft_cols<float, -1>);
   set((const void*)k_project_int_walk<float, true>);

@@ -13,6 +13,9 @@ struct FftPlan {
 };
 
 // Everything one apply needs, for one precision T (double or float).
+// longest row the one-buffer row transform takes
+constexpr int kRowIpMax = 4096;
+
 template <typename T>
 struct DevView {
   int64_t N = 0;
@@ -27,6 +30,9 @@ struct DevView {
   // the matrix cores (right-hand-side-major input; used when nrhs is a
   // multiple of 16, else as 2)
   int near_variant = 0, csr_variant = 0;
+  // nonzero: row transforms with one LDS buffer (rows of at most kRowIpMax
+  // points)
+  int rows_ip = 0;
   // fft_variant 0 = separate column transforms and spectral product, 1 =
   // fused per column tile
   int fft_variant = 0;
