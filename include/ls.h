@@ -247,6 +247,8 @@ typedef struct {
                            and may revise the transform threads, tile and interior variant) */
   int fft_rows_inplace; /* 1: row transforms with one LDS buffer (rows of at most 4096
                            points; half the LDS, two barriers per pass) */
+  int near_rows_first;  /* 1: in the concurrent apply the boundary-patch rows run before the
+                           interior contraction on the side stream (0: after it) */
 } ls_tune_result;
 
 /* Set the kernel schedule for later applies in precision prec (fields
@@ -258,7 +260,7 @@ typedef struct {
  * (single precision; 2 needs the run-length columns, 3 and 4 the dense
  * tiles, and fall back to 2 when nrhs is not a multiple of 16; double
  * precision accepts 0), fft_variant 0 / 1, fft_rows_inplace 0 / 1 (1 for rows of at
- * most 4096 points), fft_row_threads 256 / 512 / 1024,
+ * most 4096 points), near_rows_first 0 / 1, fft_row_threads 256 / 512 / 1024,
  * fft_col_threads 256 / 512.  LS_EINVAL leaves the schedule unchanged.  Not
  * to be called while applies or solves on op are in flight. */
 ls_status ls_set_schedule(ls_op* op, ls_prec prec, const ls_tune_result* sched);

@@ -74,7 +74,7 @@ class TuneResult(C.Structure):
     _fields_ = [("fft_col_tile", C.c_int), ("near_variant", C.c_int), ("csr_variant", C.c_int),
                 ("fft_variant", C.c_int), ("fft_row_threads", C.c_int), ("fft_col_threads", C.c_int),
                 ("fft_ms", C.c_double), ("near_ms", C.c_double), ("csr_ms", C.c_double), ("apply_ms", C.c_double),
-                ("fft_rows_inplace", C.c_int)]
+                ("fft_rows_inplace", C.c_int), ("near_rows_first", C.c_int)]
 
 
 N2FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double),
@@ -489,7 +489,7 @@ class Operator:
         return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
     SCHEDULE_FIELDS = ("fft_col_tile", "near_variant", "csr_variant", "fft_variant", "fft_row_threads",
-                       "fft_col_threads", "fft_rows_inplace")
+                       "fft_col_threads", "fft_rows_inplace", "near_rows_first")
 
     def get_schedule(self, prec=LS_C64):
         r = TuneResult()

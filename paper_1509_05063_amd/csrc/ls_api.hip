@@ -1111,6 +1111,7 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
   res->fft_variant = best_fv;
   res->fft_row_threads = best_nth;
   res->fft_rows_inplace = d.rows_ip;
+  res->near_rows_first = d.rows_first;
   res->fft_col_threads = d.cols_nth;
   res->fft_ms = best;
   // interior contraction variant (stage 6) and near-field rows variant (stage 7)
@@ -1220,10 +1221,13 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
     }
     for (int var = 0; var < nnear; ++var)
       if ((s = trial(&d.near_variant, var, "concurrent: near variant"))) return s;
+    for (int rf : {1, 0})
+      if ((s = trial(&d.rows_first, rf, "concurrent: rows before the interior contraction"))) return s;
     res->fft_col_tile = d.tc;
     res->fft_row_threads = d.rows_nth;
     res->fft_col_threads = d.cols_nth;
     res->fft_rows_inplace = d.rows_ip;
+    res->near_rows_first = d.rows_first;
     res->near_variant = d.near_variant;
     res->apply_ms = cur;
   }
@@ -1286,8 +1290,10 @@ ls_status set_schedule_view(const ls_op* op, lsx::DevView<T>& d, const ls_tune_r
   if (r->csr_variant >= 3 && d.bt_ntiles == 0) return fail(LS_EINVAL, "csr_variant 3 / 4: the op keeps no dense tiles");
   if (r->fft_rows_inplace != 0 && r->fft_rows_inplace != 1) return fail(LS_EINVAL, "fft_rows_inplace must be 0 or 1");
   if (r->fft_rows_inplace && d.pb.n > lsx::kRowIpMax) return fail(LS_EINVAL, "fft_rows_inplace: rows longer than 4096");
+  if (r->near_rows_first != 0 && r->near_rows_first != 1) return fail(LS_EINVAL, "near_rows_first must be 0 or 1");
   (void)op;
   d.rows_ip = r->fft_rows_inplace;
+  d.rows_first = r->near_rows_first;
   d.fft_variant = fv;
   d.tc = r->fft_col_tile;
   d.rows_nth = r->fft_row_threads;
@@ -1306,6 +1312,7 @@ void get_schedule_view(const lsx::DevView<T>& d, ls_tune_result* r) {
   r->fft_row_threads = d.rows_nth;
   r->fft_col_threads = d.cols_nth;
   r->fft_rows_inplace = d.rows_ip;
+  r->near_rows_first = d.rows_first;
 }
 }  // namespace
 }  // extern "C++"

@@ -3285,8 +3285,13 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     hipError_t e = hipEventRecord(d.ev_fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(d.side, d.ev_fork, 0);
     if (e != hipSuccess) return e;
-    near_shared(d.side, vn);
-    near_rows(d.side, vn);
+    if (d.rows_first) {
+      near_rows(d.side, vn);
+      near_shared(d.side, vn);
+    } else {
+      near_shared(d.side, vn);
+      near_rows(d.side, vn);
+    }
     if ((e = hipEventRecord(d.ev_join, d.side)) != hipSuccess) return e;
   }
   far_field();

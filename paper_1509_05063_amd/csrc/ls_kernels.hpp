@@ -33,6 +33,9 @@ struct DevView {
   // nonzero: row transforms with one LDS buffer (rows of at most kRowIpMax
   // points)
   int rows_ip = 0;
+  // concurrent apply: nonzero runs the boundary-patch rows before the
+  // interior contraction on the side stream
+  int rows_first = 0;
   // fft_variant 0 = separate column transforms and spectral product, 1 =
   // fused per column tile
   int fft_variant = 0;

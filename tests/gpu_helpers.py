@@ -17,6 +17,7 @@ def schedule_cases(prec, tile_max):
             cases.append((f"fft{fv}-tile{tc}", dict(fft_variant=fv, fft_col_tile=tc)))
     cases += [(f"rows{n}", dict(fft_row_threads=n)) for n in (256, 512, 1024)]
     cases += [(f"rows{n}-inplace", dict(fft_row_threads=n, fft_rows_inplace=1)) for n in (256, 1024)]
+    cases.append(("rows-first", dict(near_rows_first=1)))
     cases += [(f"cols{n}", dict(fft_variant=1, fft_col_threads=n, fft_col_tile=min(4, tile_max))) for n in (256, 512)]
     if prec == binding.LS_C64:
         cases.append(("star-tuned", dict(csr_variant=2, near_variant=3, fft_variant=1, fft_col_tile=min(4, tile_max),

@@ -281,7 +281,7 @@ def test_schedule_setter_rejects_out_of_range(disc):
     from paper_1509_05063_amd import binding
     cfg, op, orc, A, p, xy, key = disc
     saved = op.get_schedule(binding.LS_C64)
-    for bad in (dict(csr_variant=5), dict(near_variant=5), dict(near_variant=-1), dict(fft_variant=2), dict(fft_row_threads=128), dict(fft_rows_inplace=2),
+    for bad in (dict(csr_variant=5), dict(near_variant=5), dict(near_variant=-1), dict(fft_variant=2), dict(fft_row_threads=128), dict(fft_rows_inplace=2), dict(near_rows_first=2),
                 dict(fft_col_threads=1024), dict(fft_col_tile=0), dict(fft_col_tile=100000)):
         with pytest.raises(binding.LSError):
             op.set_schedule(binding.LS_C64, **bad)
