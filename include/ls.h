@@ -106,10 +106,10 @@ typedef struct {
  *   n_fb         Dirichlet fit order: Fourier–Bessel modes |n| <= n_fb
  *   coll_factor  collocation points = coll_factor * 4q per source set
  *   skip_tiles   (storage, not the discretisation) nonzero: do not keep the
- *                single-precision near-field rows a second time as dense
- *                16-row tiles; batched applies then use the row kernels.
- *                Saves the tiles' memory (about 1.3x the single-precision
- *                row weights) and their set-up time. */
+ *                near-field rows a second time as dense 16-row tiles (in
+ *                single and double precision); batched applies then use the
+ *                row kernels.  Saves the tiles' memory (about 1.3x the row
+ *                weights of each precision) and their set-up time. */
 typedef struct {
   int Q, P;
   double chi_c0, r_int, r1, r2;
@@ -251,18 +251,19 @@ typedef struct {
                            interior contraction on the side stream (0: after it) */
 } ls_tune_result;
 
-/* Set the kernel schedule for later applies in precision prec (fields
- * fft_col_tile ... fft_col_threads of *sched; the timing fields are
- * ignored), e.g. to force one variant.  The schedule changes which kernels
- * run, not the discrete operator.  Ranges: fft_col_tile 1 ... the LDS limit
- * (LS_EINVAL beyond it), near_variant 0-4 (single precision; double
- * precision has one interior kernel and accepts 0), csr_variant 0-4
- * (single precision; 2 needs the run-length columns, 3 and 4 the dense
- * tiles, and fall back to 2 when nrhs is not a multiple of 16; double
- * precision accepts 0), fft_variant 0 / 1, fft_rows_inplace 0 / 1 (1 for rows of at
- * most 4096 points), near_rows_first 0 / 1, fft_row_threads 256 / 512 / 1024,
- * fft_col_threads 256 / 512.  LS_EINVAL leaves the schedule unchanged.  Not
- * to be called while applies or solves on op are in flight. */
+/* Set the kernel schedule for later applies in precision prec (the fields
+ * fft_col_tile ... fft_col_threads, fft_rows_inplace and near_rows_first of
+ * *sched; the timing fields are ignored), e.g. to force one variant.  The
+ * schedule changes which kernels run, not the discrete operator.  Ranges:
+ * fft_col_tile 1 ... the LDS limit (LS_EINVAL beyond it), near_variant 0-4
+ * (single precision; double precision has one interior kernel and accepts
+ * 0), csr_variant 0-4 (single precision; 2 needs the run-length columns, 3
+ * and 4 the dense tiles, and fall back to 2 when nrhs is not a multiple of
+ * 16; double precision accepts 0 and 3, its dense tiles), fft_variant 0 / 1,
+ * fft_rows_inplace 0 / 1 (1 for rows of at most 4096 points),
+ * near_rows_first 0 / 1, fft_row_threads 256 / 512 / 1024, fft_col_threads
+ * 256 / 512.  LS_EINVAL leaves the schedule unchanged.  Not to be called
+ * while applies or solves on op are in flight. */
 ls_status ls_set_schedule(ls_op* op, ls_prec prec, const ls_tune_result* sched);
 
 /* The current schedule of precision prec (timing fields zero). */

@@ -36,6 +36,7 @@ ls_status fail(ls_status s, const std::string& msg) {
   } while (0)
 
 struct Fp32c { float x, y; };
+struct Fp64c { double x, y; };
 }  // namespace
 
 struct ls_host_op {
@@ -722,6 +723,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   // adjacent far-field subtraction folded into the stored row weights (both
   // precisions); the single-precision weights then come back for the tiles
   std::vector<Fp32c> vals32(p->skip_tiles ? 0 : (size_t)prow[nrow]);
+  std::vector<Fp64c> vals64(p->skip_tiles ? 0 : (size_t)prow[nrow]);
   {
     std::vector<int64_t> olen(nrow);
     for (size_t r = 0; r < nrow; ++r) olen[r] = h.rowptr[r + 1] - h.rowptr[r];
@@ -760,6 +762,8 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     ok = ok && (vals32.empty() ||
                 hipMemcpy(vals32.data(), b.vals, 8 * vals32.size(), hipMemcpyDeviceToHost) == hipSuccess);
+    ok = ok && (vals64.empty() ||
+                hipMemcpy(vals64.data(), a.vals, 16 * vals64.size(), hipMemcpyDeviceToHost) == hipSuccess);
     dev_free(op->alloc, d_olen, b_olen);
     dev_free(op->alloc, d_cell, b_pt);
     dev_free(op->alloc, d_idx, b_pt);
@@ -779,6 +783,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     std::vector<int32_t> bt_rows, bt_info, bt_cols, adjcols, extra;
     std::vector<int64_t> bt_woff;
     std::vector<Fp32c> bt_w;
+    std::vector<Fp64c> bt_w64;   // the same tiles in double precision
     int64_t n_extra = 0;
     std::vector<int32_t> pos((size_t)h.ncell, -1);   // column of an adjacent cell's first point
     const size_t nr = h.rows.size();
@@ -822,6 +827,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
         for (int k = K; k < Kp; ++k) bt_cols.push_back(bt_cols[coff]);
         const int64_t woff = (int64_t)bt_w.size();
         bt_w.resize(bt_w.size() + (size_t)Kp * 16, Fp32c{0.f, 0.f});
+        bt_w64.resize(bt_w.size(), Fp64c{0.0, 0.0});
         bt_woff.push_back(woff);
         bt_info.push_back(Kp);
         bt_info.push_back(coff);
@@ -834,10 +840,12 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
             const int32_t j = h.cols[k];
             const int kk = in_adj(j) ? pos[cell_of[(size_t)j]] + (j - first(cell_of[(size_t)j]))
                                      : Ka + (int)(std::lower_bound(extra.begin(), extra.end(), j) - extra.begin());
-            Fp32c& w = bt_w[(size_t)woff + (size_t)(kk / 4) * 64 + (kk % 4) * 16 + q];
-            const Fp32c& src = vals32[(size_t)(prow[rr] + (k - h.rowptr[rr]))];
-            w.x += src.x;
-            w.y += src.y;
+            const size_t at = (size_t)woff + (size_t)(kk / 4) * 64 + (kk % 4) * 16 + q;
+            const size_t from = (size_t)(prow[rr] + (k - h.rowptr[rr]));
+            bt_w[at].x += vals32[from].x;
+            bt_w[at].y += vals32[from].y;
+            bt_w64[at].x += vals64[from].x;
+            bt_w64[at].y += vals64[from].y;
           }
         }
       }
@@ -853,6 +861,14 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
       UP(upload_i(op, bt_cols, &b.bt_cols));
       UP(upload_i(op, bt_woff, &b.bt_woff));
       b.bt_ntiles = (int)bt_woff.size();
+      void* wd64 = nullptr;
+      UP(upload(op, bt_w64.data(), bt_w64.size(), &wd64));
+      a.bt_w = wd64;
+      a.bt_rows = b.bt_rows;
+      a.bt_info = b.bt_info;
+      a.bt_cols = b.bt_cols;
+      a.bt_woff = b.bt_woff;
+      a.bt_ntiles = b.bt_ntiles;
       op->stats[13] = (int64_t)bt_w.size();
       op->stats[14] = n_extra;
     }
@@ -1142,6 +1158,8 @@ ls_status autotune_view(ls_op* op, lsx::DevView<T>& d, int nrhs, const void* u, 
       csr_cands.push_back(3);
       csr_cands.push_back(4);
     }
+  } else if (d.bt_ntiles > 0 && nrhs % 16 == 0) {
+    csr_cands.push_back(3);
   }
   for (int var : csr_cands) {
     d.csr_variant = var;
@@ -1285,7 +1303,8 @@ ls_status set_schedule_view(const ls_op* op, lsx::DevView<T>& d, const ls_tune_r
   if (r->fft_col_threads != 256 && r->fft_col_threads != 512)
     return fail(LS_EINVAL, "fft_col_threads must be 256 or 512");
   if (r->near_variant < 0 || r->near_variant > (f32 ? 4 : 0)) return fail(LS_EINVAL, "near_variant out of range");
-  if (r->csr_variant < 0 || r->csr_variant > (f32 ? 4 : 0)) return fail(LS_EINVAL, "csr_variant out of range");
+  if (r->csr_variant < 0 || r->csr_variant > 4 || (!f32 && r->csr_variant != 0 && r->csr_variant != 3))
+    return fail(LS_EINVAL, "csr_variant out of range");
   if (r->csr_variant == 2 && !d.run_ptr) return fail(LS_EINVAL, "csr_variant 2: the op keeps no run-length columns");
   if (r->csr_variant >= 3 && d.bt_ntiles == 0) return fail(LS_EINVAL, "csr_variant 3 / 4: the op keeps no dense tiles");
   if (r->fft_rows_inplace != 0 && r->fft_rows_inplace != 1) return fail(LS_EINVAL, "fft_rows_inplace must be 0 or 1");

@@ -2280,16 +2280,16 @@ hipError_t launch_fold_rows(const DevView<double>& a, const DevView<float>& b, c
 
 // Right-hand-side-major copy for the batched row kernel: ut[i * R + r] = u[r * N + i]
 // (32 x 32 tiles through LDS, both sides coalesced).
-__global__ void __launch_bounds__(256) k_rhs_major(const float2* __restrict__ u, float2* __restrict__ ut, int64_t N,
-                                                   int R) {
-  __shared__ float2 tile[32][33];
+template <typename V>
+__global__ void __launch_bounds__(256) k_rhs_major(const V* __restrict__ u, V* __restrict__ ut, int64_t N, int R) {
+  __shared__ V tile[32][33];
   const int64_t i0 = (int64_t)blockIdx.x * 32;
   const int r0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
   for (int k = ty; k < 32; k += 8) {
     const int r = r0 + k;
     const int64_t i = i0 + tx;
-    tile[k][tx] = (r < R && i < N) ? u[(int64_t)r * N + i] : make_float2(0.f, 0.f);
+    tile[k][tx] = (r < R && i < N) ? u[(int64_t)r * N + i] : czero<V>();
   }
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
@@ -2299,8 +2299,8 @@ __global__ void __launch_bounds__(256) k_rhs_major(const float2* __restrict__ u,
   }
 }
 
-// a4 on the matrix cores, dense tiles of 16 rows (single precision, R a
-// multiple of 16 right-hand sides, input right-hand-side-major).  One
+// a4 on the matrix cores, dense tiles of 16 rows (single or double
+// precision, R a multiple of 16 right-hand sides, input right-hand-side-major).  One
 // wavefront per (16-row tile, 16 NT right-hand sides) computes the tile's
 // product as V^T = U^T W^T: MFMA A operand = 16 right-hand sides x 4 columns
 // of the input (row = lane % 16, column k = lane / 16: 16 consecutive words
@@ -2310,16 +2310,18 @@ __global__ void __launch_bounds__(256) k_rhs_major(const float2* __restrict__ u,
 // target lane % 16): the 16 lanes of a group add into 16 targets of one
 // right-hand side.  Rows of different tiles are distinct, so the adds do not
 // race.
-template <int NT, bool G3 = false>
-__global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut, float2* __restrict__ v,
+template <typename T, int NT, bool G3 = false>
+__global__ void __launch_bounds__(256) k_near_blk(const typename C2<T>::t* __restrict__ ut,
+                                                  typename C2<T>::t* __restrict__ v,
                                                   const int32_t* __restrict__ bt_rows,
                                                   const int32_t* __restrict__ bt_info,
                                                   const int64_t* __restrict__ bt_woff,
                                                   const int32_t* __restrict__ bt_cols,
-                                                  const float2* __restrict__ bt_w, int ntiles, int64_t N, int R,
-                                                  float k2) {
-  using M = Mfma<float>;
-  typedef M::v4 v4;
+                                                  const typename C2<T>::t* __restrict__ bt_w, int ntiles, int64_t N,
+                                                  int R, T k2) {
+  using V = typename C2<T>::t;
+  using M = Mfma<T>;
+  typedef typename M::v4 v4;
   const int lane = threadIdx.x & 63;
   const int nch = (R + 16 * NT - 1) / (16 * NT);
   const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -2328,44 +2330,44 @@ __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut,
   const int n0 = (int)(gw % nch) * 16 * NT;
   const int ntv = min(NT, (R - n0) / 16);
   const int K = bt_info[2 * t];
-  const float2* __restrict__ W = bt_w + bt_woff[t] + lane;
+  const V* __restrict__ W = bt_w + bt_woff[t] + lane;
   const int32_t* __restrict__ cl = bt_cols + bt_info[2 * t + 1];
-  const float2* __restrict__ ub = ut + n0 + (lane & 15);
+  const V* __restrict__ ub = ut + n0 + (lane & 15);
   v4 re[NT], im[NT], r3[G3 ? NT : 1];
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
-    re[g] = v4{0.f, 0.f, 0.f, 0.f};
-    im[g] = v4{0.f, 0.f, 0.f, 0.f};
-    if (G3) r3[g] = v4{0.f, 0.f, 0.f, 0.f};
+    re[g] = v4{0, 0, 0, 0};
+    im[g] = v4{0, 0, 0, 0};
+    if (G3) r3[g] = v4{0, 0, 0, 0};
   }
   // the tile's columns 64 at a time, one per lane; step s (4 columns) takes
   // its column from lane 4 (s % 16) + lane / 16.  Operands of step s + 1 are
   // loaded before the products of step s.
   const int nsteps = K / 4;
   int colreg = cl[min(lane, K - 1)];
-  float2 wn = W[0], an[NT];
+  V wn = W[0], an[NT];
   {
-    const float2* __restrict__ uc = ub + (int64_t)__shfl(colreg, lane >> 4, 64) * R;
+    const V* __restrict__ uc = ub + (int64_t)__shfl(colreg, lane >> 4, 64) * R;
 #pragma unroll
-    for (int g = 0; g < NT; ++g) an[g] = g < ntv ? uc[16 * g] : make_float2(0.f, 0.f);
+    for (int g = 0; g < NT; ++g) an[g] = g < ntv ? uc[16 * g] : czero<V>();
   }
   for (int s = 0; s < nsteps; ++s) {
-    const float2 w = wn;
-    float2 a[NT];
+    const V w = wn;
+    V a[NT];
 #pragma unroll
     for (int g = 0; g < NT; ++g) a[g] = an[g];
     const int s1 = s + 1;
     if (s1 < nsteps) {
       if ((s1 & 15) == 0) colreg = cl[min(4 * s1 + lane, K - 1)];
       wn = W[(int64_t)s1 * 64];
-      const float2* __restrict__ uc = ub + (int64_t)__shfl(colreg, 4 * (s1 & 15) + (lane >> 4), 64) * R;
+      const V* __restrict__ uc = ub + (int64_t)__shfl(colreg, 4 * (s1 & 15) + (lane >> 4), 64) * R;
 #pragma unroll
-      for (int g = 0; g < NT; ++g) an[g] = g < ntv ? uc[16 * g] : make_float2(0.f, 0.f);
+      for (int g = 0; g < NT; ++g) an[g] = g < ntv ? uc[16 * g] : czero<V>();
     }
     if (G3) {
       // three real products (Gauss): p1 = (Ur + Ui) Wr, p2 = Ui (Wr + Wi),
       // p3 = Ur (Wi - Wr); real part p1 - p2, imaginary part p1 + p3
-      const float ws = w.x + w.y, wd = w.y - w.x;
+      const T ws = w.x + w.y, wd = w.y - w.x;
 #pragma unroll
       for (int g = 0; g < NT; ++g) {
         re[g] = M::op(a[g].x + a[g].y, w.x, re[g]);
@@ -2387,7 +2389,7 @@ __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut,
     for (int g = 0; g < NT; ++g)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float p1 = re[g][r];
+        const T p1 = re[g][r];
         re[g][r] = p1 - im[g][r];
         im[g][r] = p1 + r3[g][r];
       }
@@ -2399,9 +2401,11 @@ __global__ void __launch_bounds__(256) k_near_blk(const float2* __restrict__ ut,
     if (g >= ntv) break;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      float2* p = v + (int64_t)(n0 + 16 * g + M::row(lane, r)) * N + j;
-      const float2 o = *p;
-      *p = cadd(o, cscale(make_float2(re[g][r], im[g][r]), k2));
+      V* p = v + (int64_t)(n0 + 16 * g + M::row(lane, r)) * N + j;
+      V x;
+      x.x = re[g][r];
+      x.y = im[g][r];
+      *p = cadd(*p, cscale(x, k2));
     }
   }
 }
@@ -3222,7 +3226,11 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   auto near_rows = [&](hipStream_t ns, V* vt) {
     if (d.nrows > 0) {
       const dim3 g((d.nrows + 3) / 4), b(256);
-      if (d.csr_f64) {
+      // dense tiles (either precision): right-hand-side-major input copied
+      // into the lattice region (free after the interpolation; large
+      // enough, checked here)
+      const bool blk = d.bt_ntiles > 0 && d.csr_variant >= 3 && nrhs % 16 == 0 && (int64_t)4 * plane >= d.N;
+      if (d.csr_f64 && !blk) {
         if (d.coloff)
           hipLaunchKernelGGL((k_near_csr<T, double2, uint16_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
                              d.coloff, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
@@ -3230,24 +3238,20 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
           hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
                              d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
       } else {
-        // dense tiles: right-hand-side-major input copied into the lattice
-        // region (free after the interpolation; large enough, checked here)
-        const bool blk = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant >= 3 && nrhs % 16 == 0 &&
-                         (int64_t)4 * plane >= d.N;
         if (blk) {
-          float2* ut = (float2*)lat;
-          hipLaunchKernelGGL(k_rhs_major, dim3((unsigned)((d.N + 31) / 32), (nrhs + 31) / 32), dim3(256), 0, ns,
-                             (const float2*)u, ut, d.N, nrhs);
+          V* ut = lat;
+          hipLaunchKernelGGL(k_rhs_major<V>, dim3((unsigned)((d.N + 31) / 32), (nrhs + 31) / 32), dim3(256), 0, ns,
+                             u, ut, d.N, nrhs);
           constexpr int NT = 4;
           const int64_t waves = (int64_t)d.bt_ntiles * ((nrhs + 16 * NT - 1) / (16 * NT));
-          if (d.csr_variant == 4)
-            hipLaunchKernelGGL((k_near_blk<NT, true>), dim3((unsigned)((waves + 3) / 4)), b, 0, ns,
-                               (const float2*)ut, (float2*)vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols,
-                               (const float2*)d.bt_w, d.bt_ntiles, d.N, nrhs, (float)k2);
+          if (std::is_same<T, float>::value && d.csr_variant == 4)
+            hipLaunchKernelGGL((k_near_blk<T, NT, true>), dim3((unsigned)((waves + 3) / 4)), b, 0, ns,
+                               (const V*)ut, vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const V*)d.bt_w,
+                               d.bt_ntiles, d.N, nrhs, k2);
           else
-            hipLaunchKernelGGL(k_near_blk<NT>, dim3((unsigned)((waves + 3) / 4)), b, 0, ns, (const float2*)ut,
-                               (float2*)vt, d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const float2*)d.bt_w,
-                               d.bt_ntiles, d.N, nrhs, (float)k2);
+            hipLaunchKernelGGL((k_near_blk<T, NT>), dim3((unsigned)((waves + 3) / 4)), b, 0, ns, (const V*)ut, vt,
+                               d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const V*)d.bt_w, d.bt_ntiles, d.N,
+                               nrhs, k2);
         } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
           hipLaunchKernelGGL(k_near_csr4r, g, b, (size_t)4 * (2 * d.run_max + 1) * sizeof(int), ns, (const float2*)u,
                              (float2*)vt, d.rowptr, d.rows, d.run_ptr, d.run_cs, d.run_pre, (const float2*)d.vals,
@@ -3273,7 +3277,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   // rows more than it shortens the side stream.)  The dense-tile form
   // borrows the lattice region and stays on the caller's stream after the
   // far field.
-  const bool blk_rows = d.bt_ntiles > 0 && std::is_same<T, float>::value && d.csr_variant >= 3 && nrhs % 16 == 0;
+  const bool blk_rows = d.bt_ntiles > 0 && d.csr_variant >= 3 && nrhs % 16 == 0;
   const bool fork = d.side && !ev && !blk_rows;
   const int64_t nv = d.N * nrhs;
   const unsigned nvb = (unsigned)((nv + 255) / 256);
