@@ -132,33 +132,35 @@ def test_benchmark_schedules_match_oracle_rows(star32, star32_rows):
             op.set_schedule(prec, **saved)
 
 
-@pytest.mark.parametrize("variant", [3, 4])
-def test_benchmark_size_dense_tiles_match_oracle_rows(star32, star32_rows, variant):
+@pytest.mark.parametrize("double,variant", [(False, 3), (False, 4), (True, 3)])
+def test_benchmark_size_dense_tiles_match_oracle_rows(star32, star32_rows, double, variant):
     """The dense-tile row kernel (16 right-hand sides, csr_variant 3; 4: three
-    real products per complex product) at the benchmark size against the
-    oracle's rows (each right-hand side a phase-shifted copy of the random
-    density)."""
+    real products per complex product; in single and double precision) at
+    the benchmark size against the oracle's rows (each right-hand side a
+    phase-shifted copy of the random density)."""
     import torch
     from paper_1509_05063_amd import binding
     cfg, op, orc, p = star32
     rows, names, U, V_or = star32_rows
+    prec, dt, tol = (binding.LS_C128, torch.complex128, 1e-8) if double else (binding.LS_C64, torch.complex64, F32_TOL)
     ph = np.exp(2j * np.pi * np.arange(16) / 16)
     X = np.empty((16, op.N), complex)
     X[:, p] = ph[:, None] * U[:, 0][None, :]
-    saved = op.get_schedule(binding.LS_C64)
+    saved = op.get_schedule(prec)
     try:
-        op.set_schedule(binding.LS_C64, csr_variant=variant)
-        Xd = torch.tensor(X, dtype=torch.complex64, device="cuda")
+        op.set_schedule(prec, csr_variant=variant)
+        Xd = torch.tensor(X, dtype=dt, device="cuda")
         Vd = torch.empty_like(Xd)
         op.apply(Xd, Vd)
         torch.cuda.synchronize()
     finally:
-        op.set_schedule(binding.LS_C64, **saved)
+        op.set_schedule(prec, **saved)
     V = Vd.cpu().numpy().astype(complex)[:, p][:, rows]
     ref = ph[:, None] * V_or[:, 0][None, :]
     err = (np.abs(V - ref) / np.abs(ref).max()).max()
-    print(f"star_k32pi dense tiles (variant {variant}), 16 right-hand sides: max rel err {err:.3e}", flush=True)
-    assert err < F32_TOL
+    print(f"star_k32pi dense tiles ({'double' if double else 'single'} precision, variant {variant}), "
+          f"16 right-hand sides: max rel err {err:.3e}", flush=True)
+    assert err < tol
 
 
 def test_benchmark_size_solve_modes_agree(star32):
