@@ -19,14 +19,19 @@ Test infrastructure only (see oracle/__init__.py).
   the t2 integral uses the multi-split composite Newton–Cotes rule
   (eq:-VolInt-Adj-Sing-MultiSplit) anchored at t2^x.
 * Off-grid values of the patch densities come from tensor Lagrange
-  interpolation with P nodes per axis (reading of the "Fourier refined
-  polynomial interpolation": the polynomial part only).
+  interpolation with P nodes per axis.  With cfg["fft_refine"] = r > 1 the
+  boundary rule uses the Fourier refined polynomial interpolation of Sec. 3.1
+  along the periodic t1 axis of the single band: each t2 line of the density
+  is first refined r-fold by trigonometric interpolation (zero-padded
+  spectrum), and the P-point Lagrange stencils then sit on the refined grid
+  (spacing 1/r).  The t2 axis (the interface end is not periodic) and the
+  interior polar rule keep plain Lagrange stencils (reading).
 """
 import numpy as np
 from scipy import special
 
 from .quad import (centered_base, chi, gauss_legendre01, lagrange_weights,
-                   newton_cotes_closed)
+                   newton_cotes_closed, trig_interp_weights)
 
 
 def green2d(kappa, r):
@@ -217,12 +222,18 @@ def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None, patch=0):
     On a non-periodic patch the t1 rule's nodes beyond the patch ends are
     dropped (the partition of unity makes the density vanish there) and the
     t1 interpolation stencils are shifted one-sided at the ends, like the t2
-    stencils at the interface."""
+    stencils at the interface.  With cfg["fft_refine"] = r > 1 (single
+    periodic band only) the t1 stencils sit on the r-fold refined grid; a
+    refined node between grid nodes carries the trigonometric interpolant of
+    its t2 line, which spreads its weight over the whole line."""
     from .geom2d import band_map
     b = cfg["band"]
     N1, N2 = b["N1"], b["N2"]
     P = cfg["P"]
     periodic = b.get("patches", 1) == 1
+    rf = int(cfg.get("fft_refine", 1))
+    if rf > 1 and not periodic:
+        raise ValueError("fft_refine needs the single periodic band")
     if t1rule is None:
         t1rule = varrho_rule(cfg)
     d1, w1 = t1rule
@@ -242,10 +253,11 @@ def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None, patch=0):
     # a node that rounds onto the target itself has zero measure: drop it
     Gr = np.where(r > 0.0, green2d(kappa, np.where(r > 0.0, r, 1.0)), 0.0)
     Wq = (w2[:, None] / N2) * (w1[None, :] / N1) * Gr                    # (nl, n1)
-    bv = centered_base(V, P)
+    # t1 stencils in units of the (refined) grid spacing 1/rf
+    bv = centered_base(rf * V, P)
     if not periodic:
         bv = np.clip(bv, 0, N1 - P + 1)
-    Lv = lagrange_weights(V, bv, P)                                        # (n1,P)
+    Lv = lagrange_weights(rf * V, bv, P)                                   # (n1,P)
     bu = np.clip(centered_base(lines, P), 0, N2 - P + 1)
     Lu = lagrange_weights(lines, bu, P)                                    # (nl,P)
     # tangential scatter: R[l, v] = sum_k Wq[l,k] Lv[k,a] at v = bv[k]+a
@@ -262,6 +274,13 @@ def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None, patch=0):
     for bb in range(P):
         Su[bu - lo_u + bb, np.arange(lines.size)] += Lu[:, bb]
     win = Su @ Rv                                                          # (nu, nv)
+    if rf > 1:
+        # refined node (v0 + s/rf) of line u: the trigonometric interpolant
+        # of the line's N1 grid values; s = 0 is the grid node itself
+        vr = np.arange(nv) + lo_v
+        T = trig_interp_weights(vr / rf, N1)                               # (nv, N1)
+        win = win @ T                                                      # (nu, N1)
+        lo_v = 0
     iu, iv = np.nonzero(win)
     vv = np.mod(iv + lo_v, N1) if periodic else iv + lo_v
     j = band_idx[patch][vv, iu + lo_u]

@@ -107,3 +107,42 @@ def chi(s, c0):
     smooth in between: chi(s) = 1 - smooth_step((s - c0)/(1 - c0))."""
     s = np.abs(np.asarray(s, dtype=np.float64))
     return 1.0 - smooth_step((s - c0) / (1.0 - c0))
+
+
+def trig_interp_direct(x, N):
+    """Weights of N periodic samples f(0), ..., f(N-1) (unit spacing) for the
+    value at x of their trigonometric interpolant, from the definition: the
+    discrete Fourier coefficients c_k = (1/N) sum_v f(v) e^{-2 pi i k v / N}
+    summed back as sum_k c_k e^{2 pi i k x / N} over |k| < N/2, plus for even
+    N the Nyquist coefficient split evenly between k = +-N/2, i.e.
+    c_{N/2} cos(pi x).  This is the interpolant that zero-padding the
+    spectrum produces (the FFT refinement of Sec. 3.1).  O(N) per weight:
+    small N only.  Returns (len(x), N) real weights."""
+    x = np.asarray(x, dtype=np.float64)
+    v = np.arange(N)
+    y = x[:, None] - v[None, :]
+    K = (N - 1) // 2                               # |k| <= K strictly below N/2
+    W = np.ones_like(y)
+    for k in range(1, K + 1):
+        W += 2.0 * np.cos(2.0 * np.pi * k * y / N)
+    if N % 2 == 0:
+        W += np.cos(np.pi * y)
+    return W / N
+
+
+def trig_interp_weights(x, N):
+    """The same weights in closed form (the geometric sums of
+    trig_interp_direct done analytically): D(y) = sin(pi y) / (N tan(pi y/N))
+    for even N, sin(pi y) / (N sin(pi y / N)) for odd N, and 1 where y is a
+    multiple of N.  Returns (len(x), N)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = x[:, None] - np.arange(N)[None, :]
+    yr = y - N * np.round(y / N)                   # same value, |yr| <= N/2
+    on = np.abs(yr) < 1e-14
+    node = np.abs(yr - np.round(yr)) < 1e-14       # at a sample: 1 or exactly 0
+    ys = np.where(node, 0.5, yr)
+    den = N * (np.tan(np.pi * ys / N) if N % 2 == 0 else np.sin(np.pi * ys / N))
+    # numerator and denominator both from the reduced y: their ratio is the
+    # same as for y (both change sign together for odd N)
+    W = np.sin(np.pi * ys) / den
+    return np.where(on, 1.0, np.where(node, 0.0, W))
