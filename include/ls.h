@@ -109,7 +109,18 @@ typedef struct {
  *                near-field rows a second time as dense 16-row tiles (in
  *                single and double precision); batched applies then use the
  *                row kernels.  Saves the tiles' memory (about 1.3x the row
- *                weights of each precision) and their set-up time. */
+ *                weights of each precision) and their set-up time.
+ *   fft_refine   0 or 1: the boundary rule's off-grid values come from
+ *                P-point Lagrange stencils on the grid.  r in 2..8: the
+ *                Fourier refined polynomial interpolation of Sec. 3.1 along
+ *                t1 (single periodic band only, N1 <= 4096 with prime
+ *                factors 2, 3, 5): every apply refines each t2 line of the
+ *                boundary-patch density r-fold by FFT (zero-padded
+ *                spectrum) and the t1 stencils read the refined lines.  The
+ *                rows then also hold (r - 1) (N2 + 1) N1 refined columns past
+ *                the N unknowns, the dense tiles are not built, and the
+ *                workspace grows by (r (N2 + 1) N1 + N) elements per
+ *                right-hand side. */
 typedef struct {
   int Q, P;
   double chi_c0, r_int, r1, r2;
@@ -117,6 +128,7 @@ typedef struct {
   int band_M, band_n_in, band_n_out;
   int cell_h, q, n_fb, coll_factor;
   int skip_tiles;
+  int fft_refine;
 } ls_params;
 
 /* Refractive index callback: writes n^2 at n points (x, y interleaved);

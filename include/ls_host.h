@@ -34,7 +34,11 @@ ls_status ls_host_stats(const ls_host_op* h, int64_t* out, int nout);
  * quadrature (1 - eta) G c, the cut-off tails -eta G c of non-adjacent
  * sources and the singular rules.  count receives the number of entries;
  * at most cap are written (cols[cap], vals[2 cap] interleaved complex).
- * Entries with the same column may repeat (shared window and CSR parts). */
+ * Entries with the same column may repeat (shared window and CSR parts).
+ * With Fourier refinement (ls_params.fft_refine = r > 1) columns N and
+ * beyond are refined band values: column N + ((s - 1) (N2 + 1) + u) N1 + v
+ * holds the trigonometric interpolant of line u of the boundary-patch
+ * density (m omega J) u at t1 = v + s / r. */
 ls_status ls_host_near_row(const ls_host_op* h, int64_t i, int64_t cap, int32_t* cols, double* vals,
                            int64_t* count);
 

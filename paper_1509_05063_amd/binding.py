@@ -31,7 +31,8 @@ class Params(C.Structure):
                 ("r1", C.c_double), ("r2", C.c_double), ("polar_n_in", C.c_int), ("polar_grade", C.c_int),
                 ("polar_n_out", C.c_int), ("polar_n_theta", C.c_int), ("band_M", C.c_int),
                 ("band_n_in", C.c_int), ("band_n_out", C.c_int), ("cell_h", C.c_int), ("q", C.c_int),
-                ("n_fb", C.c_int), ("coll_factor", C.c_int), ("skip_tiles", C.c_int)]
+                ("n_fb", C.c_int), ("coll_factor", C.c_int), ("skip_tiles", C.c_int),
+                ("fft_refine", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -181,7 +182,8 @@ def params_from(cfg):
     return Params(int(cfg["Q"]), int(cfg["P"]), float(cfg["chi_c0"]), float(cfg["r_int"]), float(cfg["r1"]),
                   float(cfg["r2"]), int(pl["n_in"]), int(pl["grade"]), int(pl["n_out"]), int(pl["n_theta"]),
                   int(br["M"]), int(br["n_in"]), int(br["n_out"]), int(cfg["cell_h"]), int(cfg["q"]),
-                  int(cfg["n_fb"]), int(cfg["coll_factor"]), int(cfg.get("skip_tiles", 0)))
+                  int(cfg["n_fb"]), int(cfg["coll_factor"]), int(cfg.get("skip_tiles", 0)),
+                  int(cfg.get("fft_refine", 1)))
 
 
 def _n2_callback(n2_fn):

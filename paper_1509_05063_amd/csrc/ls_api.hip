@@ -238,9 +238,11 @@ size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
   const auto& d = op->d64;
   size_t Gw = (size_t)(d.L + 4) * d.ch;
   // projections, lattices, interior grid, near-field buffer of the
-  // concurrent near field
+  // concurrent near field, and with Fourier refinement the rows' input x
+  // and the band lines
+  const size_t rfe = d.rf > 1 ? (size_t)nrhs * ((size_t)d.ldx + (size_t)d.rf_lines * d.rf_n1) : 0;
   return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb + (size_t)nrhs * Gw * Gw +
-              (size_t)nrhs * op->N) + 256;
+              (size_t)nrhs * op->N + rfe) + 256;
 }
 
 }  // namespace
@@ -690,6 +692,37 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     }
   }
   UP(upload_i(op, prow, &a.rowptr));
+  if (h.rf > 1) {
+    // Fourier refinement of the band's t1 lines: line maps, phase ramps of
+    // the shifts s / rf (with the inverse transform's 1 / N1; the Nyquist
+    // term, even N1, split between +-N1/2: cos(pi s / rf)), twiddles
+    const int n1 = h.g.N1, nlines = h.g.N2 + 1, rf = h.rf;
+    a.rf = b.rf = rf;
+    a.rf_n1 = b.rf_n1 = n1;
+    a.rf_lines = b.rf_lines = nlines;
+    a.ldx = b.ldx = h.N + (int64_t)(rf - 1) * nlines * n1;
+    a.rf_plan = b.rf_plan = make_plan(n1);
+    std::vector<cd> ph((size_t)(rf - 1) * n1), tw(n1);
+    for (int s = 1; s < rf; ++s)
+      for (int k = 0; k < n1; ++k) {
+        cd z;
+        if (n1 % 2 == 0 && 2 * k == n1) {
+          z = cd(std::cos(M_PI * s / rf), 0.0);
+        } else {
+          const int f = 2 * k < n1 ? k : k - n1;
+          z = std::polar(1.0, 2.0 * M_PI * (double)f * s / ((double)rf * n1));
+        }
+        ph[(size_t)(s - 1) * n1 + k] = z / (double)n1;
+      }
+    for (int k = 0; k < n1; ++k) tw[k] = std::polar(1.0, -2.0 * M_PI * (double)k / n1);
+    UP(upload_c(op, ph, &a.rf_ph, &b.rf_ph));
+    UP(upload_c(op, tw, &a.rf_tw, &b.rf_tw));
+    UP(upload_i(op, h.rf_idx, &a.rf_idx));
+    b.rf_idx = a.rf_idx;
+    std::vector<float> df(h.rf_dens.begin(), h.rf_dens.end());
+    UP(upload_i(op, h.rf_dens, &a.rf_dens));
+    UP(upload_i(op, df, &b.rf_dens));
+  }
   {
     // the same columns as runs of consecutive indices (padding: a final run
     // at column 0); not used when some row needs more than 256 runs
@@ -722,11 +755,20 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   }
   // adjacent far-field subtraction folded into the stored row weights (both
   // precisions); the single-precision weights then come back for the tiles
-  std::vector<Fp32c> vals32(p->skip_tiles ? 0 : (size_t)prow[nrow]);
-  std::vector<Fp64c> vals64(p->skip_tiles ? 0 : (size_t)prow[nrow]);
+  // (no tiles with Fourier refinement: their columns would include the
+  // refined values)
+  const bool tiles = !p->skip_tiles && h.rf == 1;
+  std::vector<Fp32c> vals32(tiles ? (size_t)prow[nrow] : 0);
+  std::vector<Fp64c> vals64(tiles ? (size_t)prow[nrow] : 0);
   {
+    // entries the fold visits: those at unknowns (a row's refined columns,
+    // at N and beyond, come last in its sorted columns)
     std::vector<int64_t> olen(nrow);
-    for (size_t r = 0; r < nrow; ++r) olen[r] = h.rowptr[r + 1] - h.rowptr[r];
+    for (size_t r = 0; r < nrow; ++r) {
+      int64_t k = h.rowptr[r];
+      while (k < h.rowptr[r + 1] && h.cols[k] < h.N) ++k;
+      olen[r] = k - h.rowptr[r];
+    }
     std::vector<int32_t> pt_cell((size_t)h.N, -1), pt_idx((size_t)h.N, 0);
     for (int c = 0; c < h.ncell; ++c) {
       for (int a2 = 0; a2 < h.S; ++a2) {
@@ -769,7 +811,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     dev_free(op->alloc, d_idx, b_pt);
     if (!ok) return cleanup(fail(LS_EDEVICE, "near-field fold failed"));
   }
-  if (!p->skip_tiles) {
+  if (tiles) {
     // Single precision, batched use: the rows as dense tiles of 16 rows of
     // one cell and kind.  A tile's columns are the points of the 3 x 3
     // adjacent cells that all its rows couple to (every point for

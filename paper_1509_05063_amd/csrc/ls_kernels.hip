@@ -2053,6 +2053,9 @@ __global__ void __launch_bounds__(256 * CT) k_near_shared_mfma_db(const float2* 
   }
 }
 
+// (Row kernels: input right-hand side r at u + r ldu, ldu = N, or the
+// length of x = [u ; refined band values] with Fourier refinement; output
+// right-hand side r at v + r N.)
 // Single-precision rows touching the boundary patch with 16-bit column
 // offsets, rows stored padded to a multiple of four entries (zero weights,
 // offset 0): each lane takes four consecutive entries per step (one 32-byte
@@ -2064,7 +2067,7 @@ __global__ void __launch_bounds__(256) k_near_csr4(const float2* __restrict__ u,
                                                    const int32_t* __restrict__ colbase,
                                                    const uint16_t* __restrict__ coloff,
                                                    const float2* __restrict__ vals, int nrows, int64_t N, int nrhs,
-                                                   float k2) {
+                                                   float k2, int64_t ldu) {
   constexpr int RB = 4;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
@@ -2085,7 +2088,7 @@ __global__ void __launch_bounds__(256) k_near_csr4(const float2* __restrict__ u,
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
         if (q < nr) {
-          const float2* uq = ub + (int64_t)(r0 + q) * N;
+          const float2* uq = ub + (int64_t)(r0 + q) * ldu;
           acc[q] = cfma(make_float2(wa.x, wa.y), uq[c0], acc[q]);
           acc[q] = cfma(make_float2(wa.z, wa.w), uq[c1], acc[q]);
           acc[q] = cfma(make_float2(wb.x, wb.y), uq[c2], acc[q]);
@@ -2127,7 +2130,7 @@ __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u
                                                     const int32_t* __restrict__ run_cs,
                                                     const int32_t* __restrict__ run_pre,
                                                     const float2* __restrict__ vals, int nrows, int64_t N, int nrhs,
-                                                    float k2, int rmax) {
+                                                    float k2, int rmax, int64_t ldu) {
   constexpr int RB = 4;
   extern __shared__ int tables[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -2172,7 +2175,7 @@ __global__ void __launch_bounds__(256) k_near_csr4r(const float2* __restrict__ u
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
         if (q < nrr) {
-          const float2* uq = u + (int64_t)(r00 + q) * N;
+          const float2* uq = u + (int64_t)(r00 + q) * ldu;
           acc[q] = cfma(make_float2(wa.x, wa.y), uq[c[0]], acc[q]);
           acc[q] = cfma(make_float2(wa.z, wa.w), uq[c[1]], acc[q]);
           acc[q] = cfma(make_float2(wb.x, wb.y), uq[c[2]], acc[q]);
@@ -2420,7 +2423,7 @@ __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __res
                                                   const int32_t* __restrict__ rows,
                                                   const int32_t* __restrict__ colbase,
                                                   const CT* __restrict__ coloff, const VT* __restrict__ vals,
-                                                  int nrows, int64_t N, int nrhs, T k2) {
+                                                  int nrows, int64_t N, int nrhs, T k2, int64_t ldu) {
   using V = typename C2<T>::t;
   constexpr int RB = 4;
   const int lane = threadIdx.x & 63;
@@ -2450,7 +2453,7 @@ __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __res
         ww.y = (T)w[z].y;
 #pragma unroll
         for (int q = 0; q < RB; ++q)
-          if (q < nr) acc[q] = cfma(ww, ub[(int64_t)(r0 + q) * N + c[z]], acc[q]);
+          if (q < nr) acc[q] = cfma(ww, ub[(int64_t)(r0 + q) * ldu + c[z]], acc[q]);
       }
     }
     for (; k < e; k += 64) {
@@ -2461,7 +2464,7 @@ __global__ void __launch_bounds__(256) k_near_csr(const typename C2<T>::t* __res
       ww.y = (T)w.y;
 #pragma unroll
       for (int q = 0; q < RB; ++q)
-        if (q < nr) acc[q] = cfma(ww, ub[(int64_t)(r0 + q) * N + c], acc[q]);
+        if (q < nr) acc[q] = cfma(ww, ub[(int64_t)(r0 + q) * ldu + c], acc[q]);
     }
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
@@ -3013,6 +3016,52 @@ __global__ void k_add_c(V* __restrict__ v, const V* __restrict__ x, int64_t n) {
   if (i < n) v[i] = cadd(v[i], x[i]);
 }
 
+// Fourier refinement of the boundary patch's t1 lines (Sec. 3.1), first
+// step: copies each right-hand side's u into the head of its block of x (ldx
+// entries) and forms the density on the band grid, phi[line][v] = dens u[idx]
+// (zero where the grid node is not an unknown).  Grid: (max(N, nl) / 256,
+// nrhs).
+template <typename T>
+__global__ void __launch_bounds__(256) k_refine_gather(const typename C2<T>::t* __restrict__ u,
+                                                       typename C2<T>::t* __restrict__ x,
+                                                       typename C2<T>::t* __restrict__ phi,
+                                                       const int32_t* __restrict__ idx, const T* __restrict__ dens,
+                                                       int64_t N, int64_t ldx, int nl) {
+  using V = typename C2<T>::t;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y;
+  const V* ur = u + (int64_t)r * N;
+  if (i < N) x[(int64_t)r * ldx + i] = ur[i];
+  if (i < nl) {
+    const int j = idx[i];
+    V p = czero<V>();
+    if (j >= 0) {
+      const V a = ur[j];
+      const T c = dens[i];
+      p.x = c * a.x;
+      p.y = c * a.y;
+    }
+    phi[(int64_t)r * nl + i] = p;
+  }
+}
+
+// Second step, after the forward line transforms: each line's spectrum
+// times the phase ramp of the shift s / rf (ph[(s - 1) n1 + k], carrying the
+// inverse transform's 1 / n1 and the Nyquist term split between +-n1/2) into
+// the block of x for s; the inverse line transforms then leave the values at
+// t1 = v + s / rf there.  Grid: (nl / 256, nrhs, rf - 1).
+template <typename T>
+__global__ void __launch_bounds__(256) k_refine_phase(const typename C2<T>::t* __restrict__ spec,
+                                                      typename C2<T>::t* __restrict__ xt,
+                                                      const typename C2<T>::t* __restrict__ ph, int n1, int nl,
+                                                      int64_t ldx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nl) return;
+  const int r = blockIdx.y, s1 = blockIdx.z;
+  const int k = i % n1;
+  xt[(int64_t)r * ldx + (int64_t)s1 * nl + i] = cmul(spec[(int64_t)r * nl + i], ph[(int64_t)s1 * n1 + k]);
+}
+
 template <typename T>
 hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs, void* ws_, hipStream_t st,
                         hipEvent_t* ev, bool lattice_only) {
@@ -3026,6 +3075,9 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   V* lat = sigma + (size_t)nrhs * d.ncell * d.U;
   const int64_t plane = (int64_t)d.Pa * d.Pb;
   const T k2 = (T)(d.kappa * d.kappa);
+  // near-field buffer of the concurrent apply (then the refinement's x and
+  // line buffers)
+  V* vn = lat + (size_t)nrhs * 4 * plane + (size_t)nrhs * ((size_t)(d.L + 4) * d.ch) * ((size_t)(d.L + 4) * d.ch);
   mark(0);
   // far field: a0 - a3 + a5 on the caller's stream (writes v)
   auto far_field = [&]() {
@@ -3222,6 +3274,21 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                          d.nicell, d.N, k2);
     }
   };
+  // Fourier refinement of the band's t1 lines for the rows (Sec. 3.1):
+  // x = [u ; values at t1 = v + s / rf, s = 1 .. rf - 1] per right-hand side
+  auto refine_band = [&](hipStream_t ns, V* x, V* phi) {
+    const int n1 = d.rf_n1, nl = d.rf_lines * n1;
+    const int64_t nmax = std::max<int64_t>(d.N, nl);
+    hipLaunchKernelGGL(k_refine_gather<T>, dim3((unsigned)((nmax + 255) / 256), nrhs), dim3(256), 0, ns, u, x, phi,
+                       d.rf_idx, d.rf_dens, d.N, d.ldx, nl);
+    const size_t sh = (size_t)n1 * sizeof(V);
+    hipLaunchKernelGGL((k_fft_rows_ip<T, 1, 256>), dim3(d.rf_lines, nrhs), dim3(256), sh, ns, phi, (const V*)d.rf_tw,
+                       d.rf_plan, (int64_t)n1, n1, n1, (int64_t)nl);
+    hipLaunchKernelGGL(k_refine_phase<T>, dim3((unsigned)((nl + 255) / 256), nrhs, d.rf - 1), dim3(256), 0, ns,
+                       (const V*)phi, x + d.N, (const V*)d.rf_ph, n1, nl, d.ldx);
+    hipLaunchKernelGGL((k_fft_rows_ip<T, -1, 256>), dim3(d.rf_lines * (d.rf - 1), nrhs), dim3(256), sh, ns, x + d.N,
+                       (const V*)d.rf_tw, d.rf_plan, (int64_t)n1, n1, n1, d.ldx);
+  };
   // a4 rows of the boundary patch, into vt on stream ns
   auto near_rows = [&](hipStream_t ns, V* vt) {
     if (d.nrows > 0) {
@@ -3230,13 +3297,23 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       // into the lattice region (free after the interpolation; large
       // enough, checked here)
       const bool blk = d.bt_ntiles > 0 && d.csr_variant >= 3 && nrhs % 16 == 0 && (int64_t)4 * plane >= d.N;
+      // with Fourier refinement the rows read x = [u ; refined band lines]
+      const V* ux = u;
+      int64_t ldu = d.N;
+      if (d.rf > 1) {
+        V* x = vn + (size_t)nrhs * d.N;
+        V* phi = x + (size_t)nrhs * d.ldx;
+        refine_band(ns, x, phi);
+        ux = x;
+        ldu = d.ldx;
+      }
       if (d.csr_f64 && !blk) {
         if (d.coloff)
-          hipLaunchKernelGGL((k_near_csr<T, double2, uint16_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
-                             d.coloff, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
+          hipLaunchKernelGGL((k_near_csr<T, double2, uint16_t>), g, b, 0, ns, ux, vt, d.rowptr, d.rows, d.colbase,
+                             d.coloff, (const double2*)d.vals, d.nrows, d.N, nrhs, k2, ldu);
         else
-          hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
-                             d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2);
+          hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), g, b, 0, ns, ux, vt, d.rowptr, d.rows, d.colbase,
+                             d.cols32, (const double2*)d.vals, d.nrows, d.N, nrhs, k2, ldu);
       } else {
         if (blk) {
           V* ut = lat;
@@ -3253,18 +3330,18 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
                                d.bt_rows, d.bt_info, d.bt_woff, d.bt_cols, (const V*)d.bt_w, d.bt_ntiles, d.N,
                                nrhs, k2);
         } else if (d.run_ptr && std::is_same<T, float>::value && d.csr_variant >= 2)
-          hipLaunchKernelGGL(k_near_csr4r, g, b, (size_t)4 * (2 * d.run_max + 1) * sizeof(int), ns, (const float2*)u,
+          hipLaunchKernelGGL(k_near_csr4r, g, b, (size_t)4 * (2 * d.run_max + 1) * sizeof(int), ns, (const float2*)ux,
                              (float2*)vt, d.rowptr, d.rows, d.run_ptr, d.run_cs, d.run_pre, (const float2*)d.vals,
-                             d.nrows, d.N, nrhs, (float)k2, d.run_max);
+                             d.nrows, d.N, nrhs, (float)k2, d.run_max, ldu);
         else if (d.coloff && std::is_same<T, float>::value && d.csr_variant == 0)
-          hipLaunchKernelGGL(k_near_csr4, g, b, 0, ns, (const float2*)u, (float2*)vt, d.rowptr, d.rows, d.colbase,
-                             d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2);
+          hipLaunchKernelGGL(k_near_csr4, g, b, 0, ns, (const float2*)ux, (float2*)vt, d.rowptr, d.rows, d.colbase,
+                             d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, (float)k2, ldu);
         else if (d.coloff)
-          hipLaunchKernelGGL((k_near_csr<T, float2, uint16_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
-                             d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+          hipLaunchKernelGGL((k_near_csr<T, float2, uint16_t>), g, b, 0, ns, ux, vt, d.rowptr, d.rows, d.colbase,
+                             d.coloff, (const float2*)d.vals, d.nrows, d.N, nrhs, k2, ldu);
         else
-          hipLaunchKernelGGL((k_near_csr<T, float2, int32_t>), g, b, 0, ns, u, vt, d.rowptr, d.rows, d.colbase,
-                             d.cols32, (const float2*)d.vals, d.nrows, d.N, nrhs, k2);
+          hipLaunchKernelGGL((k_near_csr<T, float2, int32_t>), g, b, 0, ns, ux, vt, d.rowptr, d.rows, d.colbase,
+                             d.cols32, (const float2*)d.vals, d.nrows, d.N, nrhs, k2, ldu);
       }
     }
   };
@@ -3281,7 +3358,6 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   const bool fork = d.side && !ev && !blk_rows;
   const int64_t nv = d.N * nrhs;
   const unsigned nvb = (unsigned)((nv + 255) / 256);
-  V* vn = lat + (size_t)nrhs * 4 * plane + (size_t)nrhs * ((size_t)(d.L + 4) * d.ch) * ((size_t)(d.L + 4) * d.ch);
   if (fork) {
     // cleared before the fork: on the side stream the clear would queue
     // behind the projection's workgroups and delay the whole near field

@@ -83,6 +83,19 @@ struct DevView {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   FftPlan pa{}, pb{};
+  // Fourier refinement of the band's t1 lines (rf = 1: none): rf_lines
+  // lines of rf_n1 points, op index and density weight of each grid node at
+  // rf_idx / rf_dens [line][v]; rf_ph [(rf - 1)][rf_n1] the phase ramps of
+  // the shifts s / rf divided by rf_n1 (complex T), rf_tw the line
+  // transform's twiddles.  The rows then read x = [u ; refined values], ldx
+  // entries per right-hand side (the refined value at t1 = v + s / rf of
+  // line l at N + ((s - 1) rf_lines + l) rf_n1 + v).
+  int rf = 1, rf_n1 = 0, rf_lines = 0;
+  int64_t ldx = 0;
+  const int32_t* rf_idx = nullptr;
+  const T* rf_dens = nullptr;
+  const void *rf_ph = nullptr, *rf_tw = nullptr;
+  FftPlan rf_plan{};
 };
 
 // lattice_only: stop after the inverse transforms (workspace holds the

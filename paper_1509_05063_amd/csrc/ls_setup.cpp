@@ -289,6 +289,19 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     err = "several boundary patches need 0 < overlap < pi / n_patches"; return LS_EINVAL;
   }
   if (NP > 64) { err = "at most 64 boundary patches"; return LS_EINVAL; }
+  // Fourier refinement of the band's t1 lines (Sec. 3.1): line transforms of
+  // N1 points with radices 2, 3, 5 in one workgroup's LDS
+  const int rf = p.fft_refine > 1 ? p.fft_refine : 1;
+  if (rf > 1) {
+    int rest = g.N1;
+    for (int f : {2, 3, 5})
+      while (rest % f == 0) rest /= f;
+    if (NP > 1) { err = "fft_refine needs the single periodic band"; return LS_EINVAL; }
+    if (rf > 8 || g.N1 > 4096 || rest != 1) {
+      err = "fft_refine: r <= 8, N1 <= 4096 with prime factors 2, 3, 5"; return LS_EINVAL;
+    }
+  }
+  op.rf = rf;
   Geo G{g.shape_a, g.shape_k, g.s_in, g.s_a, g.s_b, g.N1, g.N2, NP, NP > 1 ? g.overlap : 0.0};
   const int N1 = g.N1, N2 = g.N2;
   const bool periodic = NP == 1;
@@ -453,6 +466,18 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     if (i1 < -imax || i1 > imax || i2 < -imax || i2 > imax) return -1;
     return lat[(i1 + imax) * lside + (i2 + imax)];
   };
+  if (rf > 1) {
+    // the band's t2 lines for the refinement: op index and density weight
+    // of grid node (v, u) at [u][v]
+    op.rf_idx.assign((size_t)(N2 + 1) * N1, -1);
+    op.rf_dens.assign((size_t)(N2 + 1) * N1, 0.0);
+    for (int64_t u = 0; u <= N2; ++u)
+      for (int64_t v = 0; v < N1; ++v) {
+        const int32_t j = bg(0, v, u);
+        op.rf_idx[(size_t)u * N1 + v] = j;
+        if (j >= 0) op.rf_dens[(size_t)u * N1 + v] = dens[j];
+      }
+  }
 
   // ------------------------------------------------------ singular rules
   std::vector<double> prho, pw;
@@ -464,14 +489,19 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   // boundary singular row at (vt, ut) for target point xt -> (op index, coeff)
   // On a non-periodic patch the t1 rule's nodes beyond the patch ends are
   // dropped (the partition of unity makes the density vanish there) and the
-  // t1 stencils are shifted one-sided at the ends.
+  // t1 stencils are shifted one-sided at the ends.  With Fourier refinement
+  // (rf > 1, periodic band) the t1 stencils sit on the rf-fold refined grid:
+  // refined node rf v0 + s is grid node v0 for s = 0 (an unknown, weight
+  // times its density factor) and otherwise refined column
+  // N + ((s - 1) (N2 + 1) + u) N1 + v0, whose value the apply computes from
+  // the line's density by FFT.
   auto band_sing = [&](const double* xt, double vt, double ut, int pp, std::vector<std::pair<int32_t, cd>>& out) {
     std::vector<double> lines, w2;
     multisplit(ut, N2, p.Q, p.r2, p.chi_c0, nc, lines, w2);
     if (lines.empty()) return;
     const int P = p.P;
     const int nk = (int)d1.size();
-    int64_t vlo = centered_base(vt - p.r1, P) - 1, vhi = centered_base(vt + p.r1, P) + P + 1;
+    int64_t vlo = centered_base(rf * (vt - p.r1), P) - 1, vhi = centered_base(rf * (vt + p.r1), P) + P + 1;
     if (!periodic) {
       vlo = std::max<int64_t>(vlo, 0);
       vhi = std::min<int64_t>(vhi, N1);
@@ -489,9 +519,9 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
         use[k] = 0;
         continue;
       }
-      bv[k] = centered_base(V, P);
+      bv[k] = centered_base(rf * V, P);
       if (!periodic) bv[k] = std::min<int64_t>(std::max<int64_t>(bv[k], 0), N1 - P + 1);
-      lagrange(V, bv[k], P, &Lv[(size_t)k * P]);
+      lagrange(rf * V, bv[k], P, &Lv[(size_t)k * P]);
     }
     double Lu[32];
     for (size_t l = 0; l < lines.size(); ++l) {
@@ -518,6 +548,16 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
       for (int v = 0; v < nvw; ++v) {
         cd c = win[(size_t)u * nvw + v];
         if (c == 0.0) continue;
+        if (rf > 1) {
+          const int64_t nr = (int64_t)rf * N1, vr = ((vlo + v) % nr + nr) % nr, v0 = vr / rf, s = vr % rf;
+          if (s > 0) {
+            out.emplace_back((int32_t)(N + ((s - 1) * (N2 + 1) + ulo + u) * N1 + v0), c);
+            continue;
+          }
+          const int32_t j = bg(pp, v0, ulo + u);
+          if (j >= 0) out.emplace_back(j, c * dens[j]);
+          continue;
+        }
         int64_t vv = periodic ? ((vlo + v) % N1 + N1) % N1 : vlo + v;
         int32_t j = bg(pp, vv, ulo + u);
         if (j >= 0) out.emplace_back(j, c * dens[j]);

@@ -63,6 +63,13 @@ struct HostOp {
   std::vector<int64_t> rowptr;  // CSR over `rows`
   std::vector<int32_t> rows, cols;
   std::vector<cd> vals;
+  // Fourier refinement of the band's t1 lines (rf = 1: none).  Columns
+  // N + ((s - 1) (N2 + 1) + u) N1 + v of the rows are refined values at
+  // t1 = v + s / rf on line u; rf_idx / rf_dens: [N2 + 1][N1] op index
+  // (-1: none) and density weight of grid node (v, u)
+  int rf = 1;
+  std::vector<int32_t> rf_idx;
+  std::vector<double> rf_dens;
 };
 
 // Returns LS_OK or an error code with a message in err.

@@ -115,6 +115,85 @@ def _check_rows(setup, which):
         assert err < 1e-11, (which, i, err)
 
 
+def _zero_pad_refine(N1, r):
+    """Refinement of a periodic line of N1 samples to N1 r points by numpy's
+    FFT with a zero-padded spectrum (the Nyquist bin of even N1 split evenly
+    between +-N1/2): returns the (r N1, N1) matrix whose row r v + s gives
+    the value at v + s / r."""
+    X = np.fft.fft(np.eye(N1), axis=0)
+    Y = np.zeros((r * N1, N1), complex)
+    h = (N1 + 1) // 2                         # frequencies 0 .. h-1 and -(h-1) .. -1
+    Y[:h] = X[:h]
+    Y[r * N1 - (N1 - h):] = X[h:]
+    if N1 % 2 == 0:
+        Y[N1 // 2] = X[N1 // 2] / 2
+        Y[r * N1 - N1 // 2] = X[N1 // 2] / 2
+    return np.fft.ifft(Y, axis=0) * r
+
+
+@pytest.mark.parametrize("r", [2, 3])
+def test_refined_rows_complete_oracle_rows(r):
+    """Fourier refinement along the band's t1 lines: a library row's
+    refined columns (values at t1 = v + s / r of line u of the density
+    (m omega J) u) expanded over the line's unknowns with an independent
+    zero-padded FFT refinement, plus its other columns and the plain far
+    sum, give the oracle's row (boundary-patch targets and interior targets
+    inside the patch)."""
+    cfg = scaled(config("disc_k2pi"), fft_refine=r)
+    n2 = n2_function(cfg)
+    host, orc = binding.HostOperator(cfg, n2), Setup2D(cfg, n2)
+    xy, key = host.points()
+    N = host.N
+    N1, N2 = cfg["band"]["N1"], cfg["band"]["N2"]
+    p = match_keys(orc.pts["key"], key)
+    inv = np.empty_like(p)
+    inv[p] = np.arange(p.size)
+    dens = np.zeros(N)
+    dens[p] = orc.pts["dens"]
+    grid = -np.ones((N1, N2 + 1), np.int64)
+    b = key[:, 0] == 1
+    grid[key[b, 1], key[b, 2]] = np.nonzero(b)[0]
+    R = _zero_pad_refine(N1, r)
+    cells = _cells(cfg, key, xy)
+    s_ = np.hypot(xy[:, 0], xy[:, 1])
+    rng = np.random.default_rng(11)
+    picks = list(rng.choice(np.where(key[:, 0] == 1)[0], 4, replace=False))
+    picks += list(rng.choice(np.where((key[:, 0] == 0) & (s_ > 0.82))[0], 3, replace=False))
+    n_ext = 0
+    for i in picks:
+        cols, vals = host.near_row(i)
+        assert cols.max() < N + (r - 1) * (N2 + 1) * N1
+        lib_row = np.zeros(N, complex)
+        own = cols < N
+        np.add.at(lib_row, cols[own], vals[own])
+        for c, w in zip(cols[~own], vals[~own]):
+            t = int(c) - N
+            s, rem = divmod(t, (N2 + 1) * N1)
+            u, v0 = divmod(rem, N1)
+            j = grid[:, u]
+            lib_row[j] += w * R[r * v0 + s + 1] * dens[j]
+        n_ext += int((~own).sum())
+        orow = np.zeros(N, complex)
+        orow[p] = orc.K_row(inv[i])
+        adj = np.all(np.abs(cells - cells[i]) <= 1, axis=1)
+        d = np.hypot(*(xy - xy[i]).T)
+        cw = np.zeros(N)
+        cw[p] = orc.pts["c"]
+        far = np.where(adj | (d == 0), 0.0, 0.25j * special.hankel1(0, cfg["kappa"] * np.where(d > 0, d, 1)) * cw)
+        err = np.abs(lib_row + far - orow).max() / np.abs(orow).max()
+        assert err < 1e-11, (i, err)
+    assert n_ext > 0
+
+
+def test_fft_refine_parameter_checks():
+    for over, msg in [({"band": {"patches": 2, "overlap": 0.3, "N1": 40}}, "single periodic band"),
+                      ({"band": {"N1": 56}}, "prime factors")]:
+        cfg = scaled(config("disc_k2pi"), fft_refine=2, **over)
+        with pytest.raises(binding.LSError) as e:
+            binding.HostOperator(cfg, n2_function(cfg))
+        assert msg in str(e.value)
+
+
 @pytest.mark.parametrize("over,msg", [
     ({"kappa": 40.0}, "resonate"),                    # kappa H >= pi sqrt(2)
     ({"band": {"N2": 18}}, "multiple of Q-1"),
