@@ -376,6 +376,60 @@ def fft256_run(reps):
             "grid": "256^3 complex float, in place, one transform (forward and inverse averaged)"}
 
 
+def refined_run(cfg, n2, f, x_ref, r, ortho, autotune):
+    """The same workload with Fourier refined interpolation along the band's
+    t1 lines (fft_refine = r): set-up, tuned applies, per-stage times of the
+    single-precision apply (the refinement runs inside the rows stage) and
+    the timed solve form; its solution against the unrefined FP64 reference
+    (the change the refinement makes to the discretisation)."""
+    import torch
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import scaled
+    c = scaled(cfg, fft_refine=r)
+    t0 = time.time()
+    op = binding.Operator(c, n2)
+    setup_s = time.time() - t0
+    st = op.stats()
+    out = {"fft_refine": r, "setup_s": round(setup_s, 1), "resident_gb": op.resident_bytes() / 1e9,
+           "csr_nnz": int(st["csr_nnz"])}
+    try:
+        if autotune:
+            out["autotune"] = {"fp32": op.autotune(1, binding.LS_C64), "fp64": op.autotune(1, binding.LS_C128)}
+        for name, dt in [("fp64", torch.complex128), ("fp32", torch.complex64)]:
+            u = f.to(dt)
+            v = torch.empty_like(u)
+            op.apply(u, v)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(20):
+                op.apply(u, v)
+            torch.cuda.synchronize()
+            out[f"matvecs_per_s_{name}"] = 20 / (time.perf_counter() - t1)
+        u = f.to(torch.complex64)
+        v = torch.empty_like(u)
+        acc = None
+        for _ in range(10):
+            p = op.apply_profile(u, v)
+            acc = p if acc is None else {k: acc[k] + p[k] for k in p}
+        out["stage_ms_fp32"] = {k: acc[k] / 10 for k in acc}
+        g = c["gmres"]
+        x = torch.empty_like(f)
+        ts = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            info = op.solve(f, x, tol=1e-7, restart=g["restart"], max_iter=3000, mode=binding.LS_SOLVE_FP32_REFINE,
+                            inner_tol=1e-4, max_outer=30, ortho=ortho)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        out["solves_per_s"] = 1.0 / min(ts)
+        out["iterations"] = info["iterations"]
+        out["converged"] = info["converged"]
+        out["diff_vs_unrefined_fp64_ref"] = (torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref)).item()
+    finally:
+        op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,6 +450,11 @@ def main():
     ap.add_argument("--ortho", choices=["cgs1", "cgs2"], default="cgs1",
                     help="Gram-Schmidt passes per Arnoldi step of the single-precision inner solves")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel schedules")
+    ap.add_argument("--fft-refine", type=int, default=1,
+                    help="profiling runs: build the main operator with this Fourier refinement factor")
+    ap.add_argument("--refine", type=int, default=2,
+                    help="refinement factor of the Fourier refined interpolation measured on the same workload "
+                         "(0 skips it)")
     ap.add_argument("--multi-rhs", type=int, default=256,
                     help="right-hand sides of the batched measurement on the kappa = 16 pi star (0 skips it)")
     ap.add_argument("--profile-solve", action="store_true",
@@ -437,6 +496,13 @@ def main():
     from paper_1509_05063_amd.inputs import config, n2_function, plane_wave
 
     cfg = config(args.config)
+    if args.fft_refine > 1:
+        if not (args.profile_applies or args.profile_solve):
+            print("--fft-refine is for the profiling runs; the full run measures the refined operator itself "
+                  "(--refine)", file=sys.stderr)
+            sys.exit(2)
+        from paper_1509_05063_amd.inputs import scaled
+        cfg = scaled(cfg, fft_refine=args.fft_refine)
     n2 = n2_function(cfg)
     log(f"create {args.config}")
     t0 = time.time()
@@ -594,6 +660,11 @@ def main():
                 "frac": round(fft_gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(fft_b), "avg_ms": round(fft_ms, 4),
                 "note": "2-D face lattices (2 sets x 2 kinds x Pa x Pb complex float) fit in the 256 MB MALL"}
 
+    refined = None
+    if args.refine > 1:
+        refined = refined_run(cfg, n2, f, x_ref, args.refine, ortho, not args.no_autotune)
+        log(f"refined {refined}")
+
     fft3d = None
     if args.fft3d_reps:
         fft3d = conv3d_run(args.fft3d_reps)
@@ -670,6 +741,7 @@ def main():
         "roofline_fft256": fft256,
         "autotune": tune,
         "multi_rhs": multi,
+        "fft_refined": refined,
         "serving": serving,
         "cpu_baseline": cpu,
     }
