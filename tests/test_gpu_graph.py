@@ -70,3 +70,39 @@ def test_graph_solve_small_operator_timing():
     print(f"N={op.N} iterations {st['iterations']}: eager {times[False] * 1e3:.1f} ms, "
           f"graph {times[True] * 1e3:.1f} ms", flush=True)
     op.close()
+
+
+def test_graph_solve_refined_operator_equals_eager():
+    """The Fourier refined operator (its line refinement runs inside every
+    apply): graph-replayed solves equal the eager solve bitwise, on every
+    replay, with eager work in between; the allocation-free apply equals
+    the workspace apply bitwise."""
+    import torch
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import scaled
+    cfg = scaled(config("disc_k2pi"), fft_refine=2)
+    op = binding.Operator(cfg, n2_function(cfg))
+    xy, _ = op.points()
+    F = torch.tensor(np.stack([plane_wave(cfg, xy, 0.5 * k) for k in range(2)]), dtype=torch.complex128,
+                     device="cuda")
+    kw = dict(tol=1e-10, restart=40, max_iter=3000, mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-5)
+    x_eager = torch.empty_like(F)
+    s_eager = op.solve(F, x_eager, graph=False, **kw)
+    assert s_eager["converged"] == 2
+    for rep in range(3):
+        x_graph = torch.empty_like(F)
+        s_graph = op.solve(F, x_graph, graph=True, **kw)
+        torch.cuda.synchronize()
+        assert s_graph["iterations"] == s_eager["iterations"], (s_graph, s_eager)
+        assert torch.equal(x_graph, x_eager), f"replay {rep}"
+        x_again = torch.empty_like(F)
+        op.solve(F, x_again, graph=False, **kw)
+        assert torch.equal(x_again, x_eager)
+    for dt in (torch.complex64, torch.complex128):
+        u = F.to(dt)
+        v1, v2 = torch.empty_like(u), torch.empty_like(u)
+        op.apply(u, v1)
+        op.apply_noalloc(u, v2)
+        torch.cuda.synchronize()
+        assert torch.equal(v1, v2), dt
+    op.close()
