@@ -24,8 +24,12 @@ Test infrastructure only (see oracle/__init__.py).
   along the periodic t1 axis of the single band: each t2 line of the density
   is first refined r-fold by trigonometric interpolation (zero-padded
   spectrum), and the P-point Lagrange stencils then sit on the refined grid
-  (spacing 1/r).  The t2 axis (the interface end is not periodic) and the
-  interior polar rule keep plain Lagrange stencils (reading).
+  (spacing 1/r).  The t2 axis (the interface end is not periodic) keeps
+  plain Lagrange stencils (reading).  With cfg["fft_refine_interior"] set as
+  well, the interior polar rule's stencils sit on the r-fold refined lattice:
+  the refined values are the two-dimensional trigonometric interpolant of
+  the interior density (m omega u, compactly supported inside the lattice)
+  with the period M of interior_refine_period in both axes.
 """
 import numpy as np
 from scipy import special
@@ -153,20 +157,46 @@ def multisplit_rule(ux, N2, Q, r2, c0):
 # singular (eta) parts as sparse rows
 # ----------------------------------------------------------------------------
 
-def interior_stencil(frac1, frac2, rule, cfg, kappa):
+def interior_refine_period(pts, cfg):
+    """Period (lattice points per axis) of the interior refinement: the
+    side of the box of the cells of side cell_h h that hold every node
+    (interior nodes by their lattice index, boundary-patch nodes by their
+    position), plus two cells on each side, rounded up to the next integer
+    whose only prime factors are 2, 3 and 5 (reading: the paper names no
+    period; the density vanishes well inside this box)."""
+    ch = cfg["cell_h"]
+    H = ch * cfg["h"]
+    key, x = pts["key"], pts["x"]
+    interior = key[:, 0] == 0
+    c = np.where(interior[:, None], np.floor_divide(key[:, 1:], ch), np.floor(x / H).astype(np.int64))
+    L = int(c.max() - c.min() + 1)
+    M = (L + 4) * ch
+    while True:
+        r = M
+        for f in (2, 3, 5):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            return M
+        M += 1
+
+
+def interior_stencil(frac1, frac2, rule, cfg, kappa, rf=1):
     """Polar rule around a target at (base + frac) h, base integer:
     returns lattice offsets (d1, d2) relative to base and complex weights such
     that K_sing = sum w * (m omega u)[base + d].  Quadrature nodes
     y = x + rho (cos th, sin th), th = 2 pi b / n_theta (trapezoid); values at
-    y from the P x P Lagrange stencil around y."""
+    y from the P x P Lagrange stencil around y.  rf > 1: the stencils sit on
+    the rf-fold refined lattice and the offsets are in refined units
+    (refined node rf (base + d) + s is lattice node base + d for s = 0)."""
     rho, wr = rule
     h = cfg["h"]
     P = cfg["P"]
     nth = cfg["polar"]["n_theta"]
     th = 2.0 * np.pi * np.arange(nth) / nth
     wrad = wr * rho * green2d(kappa, rho) * (2.0 * np.pi / nth)
-    p1 = (frac1 + np.multiply.outer(rho, np.cos(th)) / h).ravel()
-    p2 = (frac2 + np.multiply.outer(rho, np.sin(th)) / h).ravel()
+    p1 = (rf * (frac1 + np.multiply.outer(rho, np.cos(th)) / h)).ravel()
+    p2 = (rf * (frac2 + np.multiply.outer(rho, np.sin(th)) / h)).ravel()
     Wq = np.repeat(wrad, nth)
     b1 = centered_base(p1, P)
     b2 = centered_base(p2, P)
@@ -189,9 +219,13 @@ def interior_sing_row(xt, pts, lat_idx, cfg, kappa, rule=None, cache=None):
     (point indices, weights) such that K_sing = sum_j wt_j * (m omega)_j u_j.
     Lattice nodes that are not unknowns carry zero density and are dropped.
     On-lattice targets all share one stencil (the patch is Cartesian and G
-    depends on x - y only); it is computed once and shifted."""
+    depends on x - y only); it is computed once and shifted.  With interior
+    Fourier refinement a refined node between lattice nodes carries the
+    two-dimensional trigonometric interpolant (period M) of the lattice
+    density, which spreads its weight over the whole lattice."""
     if rule is None:
         rule = polar_radial_rule(cfg)
+    rf = int(cfg.get("fft_refine", 1)) if cfg.get("fft_refine_interior", 0) else 1
     h = cfg["h"]
     g = xt / h
     gi = np.round(g)
@@ -200,20 +234,46 @@ def interior_sing_row(xt, pts, lat_idx, cfg, kappa, rule=None, cache=None):
         if cache is not None and "onlattice" in cache:
             d1, d2, w = cache["onlattice"]
         else:
-            d1, d2, w = interior_stencil(0.0, 0.0, rule, cfg, kappa)
+            d1, d2, w = interior_stencil(0.0, 0.0, rule, cfg, kappa, rf)
             if cache is not None:
                 cache["onlattice"] = (d1, d2, w)
     else:
         base = np.floor(g).astype(np.int64)
-        d1, d2, w = interior_stencil(g[0] - base[0], g[1] - base[1], rule, cfg, kappa)
+        d1, d2, w = interior_stencil(g[0] - base[0], g[1] - base[1], rule, cfg, kappa, rf)
     imax = pts["imax"]
     n = 2 * imax + 1
+    if rf > 1:
+        s1, s2 = np.mod(d1, rf), np.mod(d2, rf)
+        on = (s1 == 0) & (s2 == 0)
+        # refined node positions in lattice index units, off the lattice
+        X1 = base[0] + d1[~on] / rf
+        X2 = base[1] + d2[~on] / rf
+        wo = w[~on]
+        d1, d2, w = d1[on] // rf, d2[on] // rf, w[on]
     I1 = base[0] + d1 + imax
     I2 = base[1] + d2 + imax
     ok = (I1 >= 0) & (I1 < n) & (I2 >= 0) & (I2 < n)
     j = lat_idx[I1[ok], I2[ok]]
     sel = j >= 0
-    return j[sel], w[ok][sel]
+    jj, ww = j[sel], w[ok][sel]
+    if rf == 1 or wo.size == 0:
+        return jj, ww
+    # sum_n wo_n D(X1_n - i1) D(X2_n - i2) over lattice (i1, i2), grouped by
+    # the distinct X1 (sample k of the period box is lattice index k - imax)
+    M = cache["period"] if cache is not None and "period" in cache else interior_refine_period(pts, cfg)
+    if cache is not None:
+        cache["period"] = M
+    ux, inv = np.unique(np.round(X1 * rf).astype(np.int64), return_inverse=True)
+    D2 = trig_interp_weights(X2 + imax, M)[:, :n] * wo[:, None]            # (n_off, n)
+    G2 = np.zeros((ux.size, n), complex)
+    np.add.at(G2, inv, D2)
+    D1 = trig_interp_weights(ux / rf + imax, M)[:, :n]                     # (n_ux, n)
+    R = D1.T @ G2                                                          # (n, n) over (I1, I2)
+    J = lat_idx
+    m = J >= 0
+    jj = np.concatenate([jj, J[m]])
+    ww = np.concatenate([ww, R[m]])
+    return jj, ww
 
 
 def band_sing_row(xt, vt, ut, pts, band_idx, cfg, kappa, t1rule=None, patch=0):

@@ -451,6 +451,54 @@ def test_fft_refined_band_interpolation_gains_the_lagrange_order():
     assert np.all(_band_rule_interp_errors(0) < 1e-13)
 
 
+def _interior_rule_interp_errors(k, refine=(1, 2, 4)):
+    """Relative error of the interior polar rule applied to the lattice
+    samples of a smooth compactly supported density (a bump of radius 0.7
+    times exp(i k x1)) against the same polar nodes and weights applied to
+    the density itself, for each refinement factor of the interior
+    refinement, at an on-lattice and an off-lattice target of the disc."""
+    from oracle.geom2d import lattice_index
+    from oracle.near2d import interior_sing_row
+    cfg = config("disc_k2pi")
+    pts = discretize(cfg, n2_function(cfg))
+    lat = lattice_index(pts)
+    h, kappa = cfg["h"], cfg["kappa"]
+
+    def f(x):
+        r = np.hypot(x[:, 0], x[:, 1]) / 0.7
+        return np.where(r < 1, np.exp(1.0 - 1.0 / np.maximum(1 - r * r, 1e-300)), 0.0) * np.exp(1j * k * x[:, 0])
+
+    rho, wr = polar_radial_rule(cfg)
+    nth = cfg["polar"]["n_theta"]
+    th = 2 * np.pi * np.arange(nth) / nth
+    W = np.repeat(wr * rho * green2d(kappa, rho) * (2 * np.pi / nth), nth)
+    out = []
+    for xt in (np.array([3 * h, 2 * h]), np.array([0.1234, -0.0456])):
+        y = xt + np.stack([np.multiply.outer(rho, np.cos(th)).ravel(), np.multiply.outer(rho, np.sin(th)).ravel()], 1)
+        exact = (W * f(y)).sum()
+        errs = []
+        for rf in refine:
+            c = scaled(cfg, fft_refine=rf, fft_refine_interior=1)
+            j, w = interior_sing_row(xt, pts, lat, c, kappa, cache={})
+            errs.append(abs((w * f(pts["x"][j])).sum() - exact) / abs(exact))
+        out.append(errs)
+    return np.array(out)
+
+
+def test_fft_refined_interior_interpolation():
+    """Interior refinement (two-dimensional trigonometric interpolation of
+    the lattice density, then P-point Lagrange stencils on the refined
+    lattice): on a density with 30 / (2 pi) waves per unit the polar rule's
+    interpolation error (3.4e-4 to 3.8e-4 unrefined) falls by 2^7.4 to
+    2^7.7 at r = 2 and further at r = 4 (down to the density's own spectral
+    tail on this lattice, about 3e-7)."""
+    e = _interior_rule_interp_errors(30.0)
+    assert np.all((e[:, 0] > 1e-4) & (e[:, 0] < 1e-3)), e
+    rate = np.log2(e[:, 0] / e[:, 1])
+    assert np.all(rate > 6.5) and np.all(rate < 9.5), (e, rate)
+    assert np.all(e[:, 2] < e[:, 1]), e
+
+
 def test_fft_refine_rejects_several_patches():
     from oracle.geom2d import band_index
     from oracle.near2d import band_sing_row
