@@ -120,7 +120,16 @@ typedef struct {
  *                rows then also hold (r - 1) (N2 + 1) N1 refined columns past
  *                the N unknowns, the dense tiles are not built, and the
  *                workspace grows by (r (N2 + 1) N1 + N) elements per
- *                right-hand side. */
+ *                right-hand side.
+ *   fft_refine_interior  nonzero (with fft_refine = r >= 2, cell_h = 8):
+ *                the interior polar rule's stencils read the r-fold refined
+ *                lattice as well: every apply transforms the interior
+ *                density on the M x M box of the cells plus two cells per
+ *                side (M rounded up to prime factors 2, 3, 5, at most 4096),
+ *                forms the r^2 - 1 shifted lattices (phase ramps, inverse
+ *                transforms) and runs the interior contraction once per
+ *                shift; the rows and the workspace grow by (r^2 - 1) M^2
+ *                elements (plus M^2 for the spectra) per right-hand side. */
 typedef struct {
   int Q, P;
   double chi_c0, r_int, r1, r2;
@@ -129,6 +138,7 @@ typedef struct {
   int cell_h, q, n_fb, coll_factor;
   int skip_tiles;
   int fft_refine;
+  int fft_refine_interior;
 } ls_params;
 
 /* Refractive index callback: writes n^2 at n points (x, y interleaved);

@@ -38,7 +38,11 @@ ls_status ls_host_stats(const ls_host_op* h, int64_t* out, int nout);
  * With Fourier refinement (ls_params.fft_refine = r > 1) columns N and
  * beyond are refined band values: column N + ((s - 1) (N2 + 1) + u) N1 + v
  * holds the trigonometric interpolant of line u of the boundary-patch
- * density (m omega J) u at t1 = v + s / r. */
+ * density (m omega J) u at t1 = v + s / r.  With fft_refine_interior also,
+ * column N + (r - 1)(N2 + 1) N1 + ((s - 1) M + gy) M + gx (s = s2 r + s1 > 0)
+ * holds the two-dimensional trigonometric interpolant (period M) of the
+ * interior density (m omega) u at lattice index (gx + s1 / r, gy + s2 / r)
+ * + (c_lo - 2) cell_h, c_lo the smallest cell index of the nodes. */
 ls_status ls_host_near_row(const ls_host_op* h, int64_t i, int64_t cap, int32_t* cols, double* vals,
                            int64_t* count);
 

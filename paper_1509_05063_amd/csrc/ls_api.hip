@@ -236,13 +236,14 @@ void release(ls_op* op) {
 size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
   size_t c = prec == LS_C128 ? 16 : 8;
   const auto& d = op->d64;
-  size_t Gw = (size_t)(d.L + 4) * d.ch;
+  size_t Gw = (size_t)d.gw;
   // projections, lattices, interior grid, near-field buffer of the
   // concurrent near field, and with Fourier refinement the rows' input x
   // and the band lines
   const size_t rfe = d.rf > 1 ? (size_t)nrhs * ((size_t)d.ldx + (size_t)d.rf_lines * d.rf_n1) : 0;
+  const size_t rfie = d.rfi > 1 ? (size_t)nrhs * Gw * Gw : 0;   // spectra of the psi grids
   return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb + (size_t)nrhs * Gw * Gw +
-              (size_t)nrhs * op->N + rfe) + 256;
+              (size_t)nrhs * op->N + rfe + rfie) + 256;
 }
 
 }  // namespace
@@ -450,6 +451,16 @@ ls_status ls_host_near_row(const ls_host_op* h, int64_t i, int64_t cap, int32_t*
         cd w = o.Wsh[(size_t)slot * Wn * Wn + (size_t)wy * Wn + wx] * o.dw[j];
         if (w != 0.0) ent.emplace_back(j, w);
       }
+    // interior refinement: the windows of the shifted psi grids, on the
+    // refined-grid columns (grid position cell * cell_h + window offset)
+    for (int s = 1; s < o.rfi * o.rfi; ++s)
+      for (int wy = 0; wy < Wn; ++wy)
+        for (int wx = 0; wx < Wn; ++wx) {
+          const cd w = o.Wsh[((size_t)s * o.S + slot) * Wn * Wn + (size_t)wy * Wn + wx];
+          if (w == 0.0) continue;
+          const int64_t gx = (int64_t)cx * ch + wx, gy = (int64_t)cy * ch + wy;
+          ent.emplace_back((int32_t)(o.N + o.rf_ioff + ((int64_t)(s - 1) * o.M + gy) * o.M + gx), w);
+        }
   }
   auto it = std::lower_bound(o.rows.begin(), o.rows.end(), (int32_t)i);
   if (it != o.rows.end() && *it == i) {
@@ -544,6 +555,9 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   a.Pa = b.Pa = h.Pa;
   a.Pb = b.Pb = h.Pb;
   a.ch = b.ch = h.p.cell_h;
+  // psi grid side: the cells plus two on each side, or the interior
+  // refinement's period
+  a.gw = b.gw = h.rfi > 1 ? h.M : (h.L + 4) * h.p.cell_h;
   a.tc = tc;
   b.tc = tc32;
   a.kappa = b.kappa = kappa;
@@ -625,7 +639,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     // shared window with the adjacent far-field subtraction of each
     // precision folded in
     std::vector<cd> w64(h.Wsh), w32(h.Wsh);
-    for (size_t i = 0; i < w64.size(); ++i) {
+    for (size_t i = 0; i < h.Wadj.size(); ++i) {     // (the window of shift 0)
       w64[i] += h.Wadj[i];
       w32[i] += h.Wadj32[i];
     }
@@ -700,7 +714,8 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     a.rf = b.rf = rf;
     a.rf_n1 = b.rf_n1 = n1;
     a.rf_lines = b.rf_lines = nlines;
-    a.ldx = b.ldx = h.N + (int64_t)(rf - 1) * nlines * n1;
+    a.ldx = b.ldx = h.N + (int64_t)(rf - 1) * nlines * n1 + (int64_t)(h.rfi * h.rfi - 1) * h.M * h.M;
+    a.rf_ioff = b.rf_ioff = h.rf_ioff;
     a.rf_plan = b.rf_plan = make_plan(n1);
     std::vector<cd> ph((size_t)(rf - 1) * n1), tw(n1);
     for (int s = 1; s < rf; ++s)
@@ -722,6 +737,24 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     std::vector<float> df(h.rf_dens.begin(), h.rf_dens.end());
     UP(upload_i(op, h.rf_dens, &a.rf_dens));
     UP(upload_i(op, df, &b.rf_dens));
+    if (h.rfi > 1) {
+      // interior: phase ramps [s][k] of the shifts s / rf on the M-point axis
+      // (1 / M included, Nyquist split as above), twiddles
+      const int M = h.M;
+      a.rfi = b.rfi = rf;
+      a.rf_iplan = b.rf_iplan = make_plan(M);
+      std::vector<cd> iph((size_t)rf * M), itw(M);
+      for (int s = 0; s < rf; ++s)
+        for (int k = 0; k < M; ++k) {
+          cd z;
+          if (M % 2 == 0 && 2 * k == M) z = cd(std::cos(M_PI * s / rf), 0.0);
+          else z = std::polar(1.0, 2.0 * M_PI * (double)(2 * k < M ? k : k - M) * s / ((double)rf * M));
+          iph[(size_t)s * M + k] = z / (double)M;
+        }
+      for (int k = 0; k < M; ++k) itw[k] = std::polar(1.0, -2.0 * M_PI * (double)k / M);
+      UP(upload_c(op, iph, &a.rf_iph, &b.rf_iph));
+      UP(upload_c(op, itw, &a.rf_itw, &b.rf_itw));
+    }
   }
   {
     // the same columns as runs of consecutive indices (padding: a final run

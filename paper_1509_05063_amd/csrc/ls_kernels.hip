@@ -1869,7 +1869,7 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::
                                                           const int32_t* __restrict__ icells,
                                                           const int32_t* __restrict__ cell_xy,
                                                           const int32_t* __restrict__ slot_map, int Gw,
-                                                          int nicell, int64_t N, T k2) {
+                                                          int nicell, int64_t N, T k2, int64_t gstride) {
   using V = typename C2<T>::t;
   using M = Mfma<T>;
   using v4 = typename M::v4;
@@ -1880,7 +1880,7 @@ __global__ void __launch_bounds__(256) k_near_shared_mfma(const typename C2<T>::
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int r = blockIdx.y;
   const int cb = blockIdx.x * NC;
-  const V* g = grid + (int64_t)r * Gw * Gw;
+  const V* g = grid + (int64_t)r * gstride;
   for (int c = tid; c < NC; c += blockDim.x) {
     int cid = cb + c < nicell ? icells[cb + c] : -1;
     cx0[c] = cid >= 0 ? cell_xy[2 * cid] * CH : -1;
@@ -1951,7 +1951,7 @@ __global__ void __launch_bounds__(256 * CT) k_near_shared_mfma_db(const float2* 
                                                                   const int32_t* __restrict__ icells,
                                                                   const int32_t* __restrict__ cell_xy,
                                                                   const int32_t* __restrict__ slot_map, int Gw,
-                                                                  int nicell, int64_t N, float k2) {
+                                                                  int nicell, int64_t N, float k2, int64_t gstride) {
   using M = Mfma<float>;
   using v4 = M::v4;
   constexpr int CH = 8, S = 64, WN = 40, KP = WN + 1, NC = 16 * CT, NTH = 256 * CT;
@@ -1963,7 +1963,7 @@ __global__ void __launch_bounds__(256 * CT) k_near_shared_mfma_db(const float2* 
   const int st = wave & 3, ct = wave >> 2;     // slot tile, cell tile
   const int r = blockIdx.y;
   const int cb = blockIdx.x * NC;
-  const float2* g = grid + (int64_t)r * Gw * Gw;
+  const float2* g = grid + (int64_t)r * gstride;   // (grid stride Gw, gstride per right-hand side)
   if (tid < NC) {
     const int cid = cb + tid < nicell ? icells[cb + tid] : -1;
     cx0[tid] = cid >= 0 ? cell_xy[2 * cid] * CH : -1;
@@ -3062,6 +3062,26 @@ __global__ void __launch_bounds__(256) k_refine_phase(const typename C2<T>::t* _
   xt[(int64_t)r * ldx + (int64_t)s1 * nl + i] = cmul(spec[(int64_t)r * nl + i], ph[(int64_t)s1 * n1 + k]);
 }
 
+// Interior refinement, after the forward 2-D transforms of the psi grids
+// (M x M, row gy, column gx): the spectrum times the phase ramps of the shift
+// (s1, s2) / rf, s = s2 rf + s1 = blockIdx.z + 1 (ph[s][k]: ramp along one
+// axis, 1 / M included), into the refined grid of shift s in x (blocks of M^2
+// from xt, ldx per right-hand side).  Grid: (M^2 / 256, nrhs, rf^2 - 1).
+template <typename T>
+__global__ void __launch_bounds__(256) k_refine_phase2(const typename C2<T>::t* __restrict__ spec,
+                                                       typename C2<T>::t* __restrict__ xt,
+                                                       const typename C2<T>::t* __restrict__ ph, int M, int rf,
+                                                       int64_t ldx) {
+  const int64_t M2 = (int64_t)M * M;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M2) return;
+  const int r = blockIdx.y, s = blockIdx.z + 1;
+  const int ky = (int)(i / M), kx = (int)(i - (int64_t)ky * M);
+  const int s1 = s % rf, s2 = s / rf;
+  xt[(int64_t)r * ldx + (int64_t)blockIdx.z * M2 + i] =
+      cmul(cmul(spec[(int64_t)r * M2 + i], ph[(int64_t)s1 * M + kx]), ph[(int64_t)s2 * M + ky]);
+}
+
 template <typename T>
 hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs, void* ws_, hipStream_t st,
                         hipEvent_t* ev, bool lattice_only) {
@@ -3077,7 +3097,7 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   const T k2 = (T)(d.kappa * d.kappa);
   // near-field buffer of the concurrent apply (then the refinement's x and
   // line buffers)
-  V* vn = lat + (size_t)nrhs * 4 * plane + (size_t)nrhs * ((size_t)(d.L + 4) * d.ch) * ((size_t)(d.L + 4) * d.ch);
+  V* vn = lat + (size_t)nrhs * 4 * plane + (size_t)nrhs * (size_t)d.gw * d.gw;
   mark(0);
   // far field: a0 - a3 + a5 on the caller's stream (writes v)
   auto far_field = [&]() {
@@ -3233,47 +3253,6 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     far_field();
     return hipGetLastError();
   }
-  // a4 between interior nodes, into vt on stream ns
-  auto near_shared = [&](hipStream_t ns, V* vt) {
-    if (d.ch == 8) {
-      const int Gw = (d.L + 4) * 8;
-      V* grid = lat + (size_t)nrhs * 4 * plane;
-      const int64_t gsz = (int64_t)Gw * Gw;
-      if (nrhs >= 8)
-        hipLaunchKernelGGL((k_psi_grid<T, 8>), dim3((unsigned)((gsz + 255) / 256), (nrhs + 7) / 8), dim3(256), 0, ns,
-                           u, grid, d.dw, d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N, nrhs);
-      else
-        hipLaunchKernelGGL((k_psi_grid<T, 1>), dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, ns, u, grid,
-                           d.dw, d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N, nrhs);
-      if (std::is_same<T, float>::value && d.near_variant != 1) {
-        const int CT = d.near_variant == 2 ? 2 : d.near_variant >= 3 ? 4 : 1;
-        const dim3 gr((d.nicell + 16 * CT - 1) / (16 * CT), nrhs), bl(256 * CT);
-        if (d.near_variant == 4)
-          hipLaunchKernelGGL((k_near_shared_mfma_db<4, true>), gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
-                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
-        else if (CT == 1)
-          hipLaunchKernelGGL(k_near_shared_mfma_db<1>, gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
-                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
-        else if (CT == 2)
-          hipLaunchKernelGGL(k_near_shared_mfma_db<2>, gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
-                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
-        else
-          hipLaunchKernelGGL(k_near_shared_mfma_db<4>, gr, bl, 0, ns, (const float2*)grid, (float2*)vt,
-                             (const float2*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2);
-      } else {
-        constexpr int NT = 2;
-        hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs), dim3(256),
-                           0, ns, (const V*)grid, vt, (const V*)d.Wsh, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell,
-                           d.N, k2);
-      }
-    } else {
-      constexpr int CT = 16, KC = 32;
-      size_t sh = (size_t)(d.S * KC + KC * CT) * sizeof(V) + 25 * CT * sizeof(int);
-      hipLaunchKernelGGL((k_near_shared<T, CT, KC>), dim3((d.nicell + CT - 1) / CT, nrhs), dim3(256), sh, ns, u, vt,
-                         (const V*)d.Wsh, d.dw, d.icells, d.cell_xy, d.cell_map, d.slot_map, d.L, d.ch, d.S,
-                         d.nicell, d.N, k2);
-    }
-  };
   // Fourier refinement of the band's t1 lines for the rows (Sec. 3.1):
   // x = [u ; values at t1 = v + s / rf, s = 1 .. rf - 1] per right-hand side
   auto refine_band = [&](hipStream_t ns, V* x, V* phi) {
@@ -3291,6 +3270,99 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
     hipLaunchKernelGGL((k_fft_rows_ip<T, -1, 256>), dim3(d.rf_lines * (d.rf - 1), nrhs), dim3(256), sh, ns, x + d.N,
                        (const V*)d.rf_tw, d.rf_plan, (int64_t)n1, n1, n1, d.ldx);
   };
+  // workspace of the refinements: x = [u ; refined band values ; refined psi
+  // grids] (ldx per right-hand side), the band lines, the psi grids' spectra
+  V* const rf_x = vn + (size_t)nrhs * d.N;
+  V* const rf_phi = rf_x + (size_t)nrhs * d.ldx;
+  V* const rf_spec = rf_phi + (size_t)nrhs * d.rf_lines * d.rf_n1;
+  // the interior psi grids (after the face lattices)
+  V* const grid = lat + (size_t)nrhs * 4 * plane;
+  // Fourier refinement of the interior lattice (Sec. 3.1): the psi grids'
+  // 2-D transforms (M x M, M = gw), times the phase ramps of each shift
+  // (s1, s2) / rf, inverse transforms into the refined grids in x
+  auto refine_interior = [&](hipStream_t ns) {
+    const int M = d.gw;
+    const int64_t M2 = (int64_t)M * M;
+    const bool dbl = sizeof(T) == 8;
+    const int TC = dbl ? 2 : 4;
+    const int nsh = d.rfi * d.rfi - 1;
+    V* xt = rf_x + d.N + d.rf_ioff;
+    (void)launch_fft_lines(dbl, 1, grid, rf_spec, d.rf_itw, d.rf_iplan, M, M, M2, 0, M, M2, 0, nrhs, 1, M, M, ns);
+    (void)launch_fft_strided(dbl, 1, rf_spec, d.rf_itw, d.rf_iplan, M, TC, M2, nrhs, M, M, 0, 1, ns);
+    hipLaunchKernelGGL(k_refine_phase2<T>, dim3((unsigned)((M2 + 255) / 256), nrhs, nsh), dim3(256), 0, ns,
+                       (const V*)rf_spec, xt, (const V*)d.rf_iph, M, d.rfi, d.ldx);
+    (void)launch_fft_strided(dbl, -1, xt, d.rf_itw, d.rf_iplan, M, TC, d.ldx, nrhs, M, M, M2, nsh, ns);
+    (void)launch_fft_lines(dbl, -1, xt, xt, d.rf_itw, d.rf_iplan, M, M, d.ldx, M2, M, d.ldx, M2, nrhs, nsh, M, M,
+                           ns);
+  };
+  // a4 between interior nodes, into vt on stream ns
+  auto psi_grid = [&](hipStream_t ns) {
+    const int Gw = d.gw;
+    const int64_t gsz = (int64_t)Gw * Gw;
+    if (nrhs >= 8)
+      hipLaunchKernelGGL((k_psi_grid<T, 8>), dim3((unsigned)((gsz + 255) / 256), (nrhs + 7) / 8), dim3(256), 0, ns, u,
+                         grid, d.dw, d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N, nrhs);
+    else
+      hipLaunchKernelGGL((k_psi_grid<T, 1>), dim3((unsigned)((gsz + 255) / 256), nrhs), dim3(256), 0, ns, u, grid,
+                         d.dw, d.cell_map, d.slot_map, d.L, 8, d.S, Gw, d.N, nrhs);
+  };
+  // the refinements the near field reads (band lines, interior psi grids),
+  // issued once per apply ahead of the first near-field kernel that needs them
+  bool prepped = false;
+  auto prep = [&](hipStream_t ns) {
+    if (prepped) return;
+    prepped = true;
+    if (d.rf > 1) refine_band(ns, rf_x, rf_phi);
+    if (d.rfi > 1) {
+      psi_grid(ns);
+      refine_interior(ns);
+    }
+  };
+  auto near_shared = [&](hipStream_t ns, V* vt) {
+    if (d.ch == 8) {
+      const int Gw = d.gw;
+      if (d.rfi > 1) prep(ns);
+      else psi_grid(ns);
+      // one contraction per shift of the refined lattice (shift 0: the psi
+      // grid itself)
+      for (int s = 0; s < d.rfi * d.rfi; ++s) {
+        const V* gs = s == 0 ? grid : rf_x + d.N + d.rf_ioff + (size_t)(s - 1) * Gw * Gw;
+        const int64_t gstride = s == 0 ? (int64_t)Gw * Gw : d.ldx;
+        const V* Ws = (const V*)d.Wsh + (size_t)s * d.S * (5 * 8) * (5 * 8);
+        if (std::is_same<T, float>::value && d.near_variant != 1) {
+          const int CT = d.near_variant == 2 ? 2 : d.near_variant >= 3 ? 4 : 1;
+          const dim3 gr((d.nicell + 16 * CT - 1) / (16 * CT), nrhs), bl(256 * CT);
+          if (d.near_variant == 4)
+            hipLaunchKernelGGL((k_near_shared_mfma_db<4, true>), gr, bl, 0, ns, (const float2*)gs, (float2*)vt,
+                               (const float2*)Ws, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2,
+                               gstride);
+          else if (CT == 1)
+            hipLaunchKernelGGL(k_near_shared_mfma_db<1>, gr, bl, 0, ns, (const float2*)gs, (float2*)vt,
+                               (const float2*)Ws, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2,
+                               gstride);
+          else if (CT == 2)
+            hipLaunchKernelGGL(k_near_shared_mfma_db<2>, gr, bl, 0, ns, (const float2*)gs, (float2*)vt,
+                               (const float2*)Ws, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2,
+                               gstride);
+          else
+            hipLaunchKernelGGL(k_near_shared_mfma_db<4>, gr, bl, 0, ns, (const float2*)gs, (float2*)vt,
+                               (const float2*)Ws, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell, d.N, (float)k2,
+                               gstride);
+        } else {
+          constexpr int NT = 2;
+          hipLaunchKernelGGL((k_near_shared_mfma<T, NT>), dim3((d.nicell + 16 * NT - 1) / (16 * NT), nrhs),
+                             dim3(256), 0, ns, (const V*)gs, vt, Ws, d.icells, d.cell_xy, d.slot_map, Gw, d.nicell,
+                             d.N, k2, gstride);
+        }
+      }
+    } else {
+      constexpr int CT = 16, KC = 32;
+      size_t sh = (size_t)(d.S * KC + KC * CT) * sizeof(V) + 25 * CT * sizeof(int);
+      hipLaunchKernelGGL((k_near_shared<T, CT, KC>), dim3((d.nicell + CT - 1) / CT, nrhs), dim3(256), sh, ns, u, vt,
+                         (const V*)d.Wsh, d.dw, d.icells, d.cell_xy, d.cell_map, d.slot_map, d.L, d.ch, d.S,
+                         d.nicell, d.N, k2);
+    }
+  };
   // a4 rows of the boundary patch, into vt on stream ns
   auto near_rows = [&](hipStream_t ns, V* vt) {
     if (d.nrows > 0) {
@@ -3303,10 +3375,8 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       const V* ux = u;
       int64_t ldu = d.N;
       if (d.rf > 1) {
-        V* x = vn + (size_t)nrhs * d.N;
-        V* phi = x + (size_t)nrhs * d.ldx;
-        refine_band(ns, x, phi);
-        ux = x;
+        prep(ns);
+        ux = rf_x;
         ldu = d.ldx;
       }
       if (d.csr_f64 && !blk) {

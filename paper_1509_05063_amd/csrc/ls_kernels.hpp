@@ -92,6 +92,15 @@ struct DevView {
   // line l at N + ((s - 1) rf_lines + l) rf_n1 + v).
   int rf = 1, rf_n1 = 0, rf_lines = 0;
   int64_t ldx = 0;
+  // psi grid side (the lattice box of the cells plus two cells per side, or
+  // with interior refinement its period M, prime factors 2, 3, 5); interior
+  // refinement (rfi = rf, else 1): the refined psi grid of shift s = s2 rf +
+  // s1 > 0 at x + N + rf_ioff + (s - 1) gw^2 (stride gw), window s at Wsh +
+  // s S Wn^2; rf_iph [rf][gw] the phase ramps / gw, rf_itw the twiddles
+  int gw = 0, rfi = 1;
+  int64_t rf_ioff = 0;
+  const void *rf_iph = nullptr, *rf_itw = nullptr;
+  FftPlan rf_iplan{};
   const int32_t* rf_idx = nullptr;
   const T* rf_dens = nullptr;
   const void *rf_ph = nullptr, *rf_tw = nullptr;

@@ -202,10 +202,12 @@ struct Stencil {
   }
 };
 
+// rf > 1: the Lagrange stencils sit on the rf-fold refined lattice and the
+// offsets are in refined units
 Stencil interior_stencil(double f1, double f2, const std::vector<double>& rho,
-                         const std::vector<double>& wr, const ls_params& p, double h, double kappa) {
+                         const std::vector<double>& wr, const ls_params& p, double h, double kappa, int rf = 1) {
   Stencil st;
-  st.R = (int)std::ceil(p.r_int / h) + p.P + 2;
+  st.R = rf * (int)std::ceil(p.r_int / h) + p.P + 2 + (rf > 1 ? rf : 0);
   int side = 2 * st.R + 1;
   st.w.assign((size_t)side * side, 0.0);
   int nth = p.polar_n_theta;
@@ -215,8 +217,8 @@ Stencil interior_stencil(double f1, double f2, const std::vector<double>& rho,
     cd wk = wr[k] * rho[k] * green2d(kappa, rho[k]) * (2.0 * M_PI / nth);
     for (int b = 0; b < nth; ++b) {
       double th = 2.0 * M_PI * b / nth;
-      double p1 = f1 + (rho[k] * std::cos(th)) / h;
-      double p2 = f2 + (rho[k] * std::sin(th)) / h;
+      double p1 = rf * (f1 + (rho[k] * std::cos(th)) / h);
+      double p2 = rf * (f2 + (rho[k] * std::sin(th)) / h);
       int64_t b1 = centered_base(p1, P), b2 = centered_base(p2, P);
       lagrange(p1, b1, P, L1);
       lagrange(p2, b2, P, L2);
@@ -302,6 +304,10 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     }
   }
   op.rf = rf;
+  if (p.fft_refine_interior) {
+    if (rf < 2) { err = "fft_refine_interior needs fft_refine >= 2"; return LS_EINVAL; }
+    if (p.cell_h != 8) { err = "fft_refine_interior needs cell_h = 8"; return LS_EINVAL; }
+  }
   Geo G{g.shape_a, g.shape_k, g.s_in, g.s_a, g.s_b, g.N1, g.N2, NP, NP > 1 ? g.overlap : 0.0};
   const int N1 = g.N1, N2 = g.N2;
   const bool periodic = NP == 1;
@@ -371,6 +377,20 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   op.S = ch * ch;
   op.L = L;
   op.c_lo = lo;
+  if (p.fft_refine_interior) {
+    // period of the interior refinement: the lattice box of the cells plus
+    // two cells on each side, rounded up to prime factors 2, 3, 5
+    int M = (L + 4) * ch;
+    for (;; ++M) {
+      int rest = M;
+      for (int f : {2, 3, 5})
+        while (rest % f == 0) rest /= f;
+      if (rest == 1) break;
+    }
+    if (M > 4096) { err = "fft_refine_interior: lattice period above 4096"; return LS_EINVAL; }
+    op.rfi = rf;
+    op.M = M;
+  }
   std::vector<int64_t> lin(N);
   for (int64_t i = 0; i < N; ++i) lin[i] = (ncy[i] - lo) * L + (ncx[i] - lo);
   std::vector<int64_t> order(N);
@@ -466,6 +486,8 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     if (i1 < -imax || i1 > imax || i2 < -imax || i2 > imax) return -1;
     return lat[(i1 + imax) * lside + (i2 + imax)];
   };
+  // refined band values past the N unknowns, then the refined psi grids
+  op.rf_ioff = rf > 1 ? (int64_t)(rf - 1) * (N2 + 1) * N1 : 0;
   if (rf > 1) {
     // the band's t2 lines for the refinement: op index and density weight
     // of grid node (v, u) at [u][v]
@@ -484,7 +506,8 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   polar_rule(p, prho, pw);
   std::vector<double> d1, w1;
   varrho_rule(p, d1, w1);
-  Stencil Ton = interior_stencil(0.0, 0.0, prho, pw, p, h, kappa);
+  const int rfi = op.rfi;
+  Stencil Ton = interior_stencil(0.0, 0.0, prho, pw, p, h, kappa, rfi);
 
   // boundary singular row at (vt, ut) for target point xt -> (op index, coeff)
   // On a non-periodic patch the t1 rule's nodes beyond the patch ends are
@@ -565,9 +588,12 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
   };
 
   // -------------------------------------------------- shared near window
+  // With interior refinement one window per refined shift s = s2 rf + s1
+  // (the values at lattice node + (s1, s2) / rf); the plain terms sit in
+  // the window of s = 0.
   const int Wn = 5 * ch;
   op.Wn = Wn;
-  op.Wsh.assign((size_t)S * Wn * Wn, 0.0);
+  op.Wsh.assign((size_t)rfi * rfi * S * Wn * Wn, 0.0);
 #pragma omp parallel for schedule(dynamic)
   for (int a = 0; a < S; ++a) {
     int ax = a % ch, ay = a / ch;
@@ -576,7 +602,7 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
         int dx = wx - 2 * ch - ax, dy = wy - 2 * ch - ay;
         int ocx = wx / ch - 2, ocy = wy / ch - 2;
         bool adj = std::abs(ocx) <= 1 && std::abs(ocy) <= 1;
-        cd val = Ton.at(dx, dy);
+        cd val = Ton.at(rfi * dx, rfi * dy);
         if (dx != 0 || dy != 0) {
           double d = std::hypot((double)dx * h, (double)dy * h);
           double eta = chi(d / p.r_int, p.chi_c0);
@@ -584,6 +610,9 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
           if (f != 0.0) val += h * h * f * green2d(kappa, d);
         }
         op.Wsh[(size_t)a * Wn * Wn + (size_t)wy * Wn + wx] = val;
+        for (int s = 1; s < rfi * rfi; ++s)
+          op.Wsh[((size_t)s * S + a) * Wn * Wn + (size_t)wy * Wn + wx] =
+              Ton.at(rfi * dx + s % rfi, rfi * dy + s / rfi);
       }
   }
 
@@ -702,12 +731,28 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
       // interior polar rule centred off the lattice
       double g1 = xi[0] / h, g2 = xi[1] / h;
       int64_t b1 = (int64_t)std::floor(g1), b2 = (int64_t)std::floor(g2);
-      Stencil st = interior_stencil(g1 - b1, g2 - b2, prho, pw, p, h, kappa);
+      Stencil st = interior_stencil(g1 - b1, g2 - b2, prho, pw, p, h, kappa, rfi);
       int side = 2 * st.R + 1;
       for (int o1 = 0; o1 < side; ++o1)
         for (int o2 = 0; o2 < side; ++o2) {
           cd c = st.w[(size_t)o1 * side + o2];
           if (c == 0.0) continue;
+          if (rfi > 1) {
+            // refined offset -> lattice node and shift; a shifted value is
+            // read from the refined psi grid of its shift
+            const int64_t r1 = o1 - st.R, r2 = o2 - st.R;
+            const int64_t d1 = floordiv(r1, rfi), d2 = floordiv(r2, rfi);
+            const int64_t s = (r2 - rfi * d2) * rfi + (r1 - rfi * d1);
+            if (s > 0) {
+              const int64_t gx = b1 + d1 - (op.c_lo - 2) * ch, gy = b2 + d2 - (op.c_lo - 2) * ch;
+              if (gx < 0 || gy < 0 || gx >= op.M || gy >= op.M) continue;   // outside the box: zero density
+              ent.emplace_back((int32_t)(N + op.rf_ioff + ((s - 1) * op.M + gy) * op.M + gx), c);
+              continue;
+            }
+            const int32_t j = lat_at(b1 + d1, b2 + d2);
+            if (j >= 0) ent.emplace_back(j, c * dens[j]);
+            continue;
+          }
           int32_t j = lat_at(b1 + o1 - st.R, b2 + o2 - st.R);
           if (j >= 0) ent.emplace_back(j, c * dens[j]);
         }

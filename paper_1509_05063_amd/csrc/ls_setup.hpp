@@ -70,6 +70,12 @@ struct HostOp {
   int rf = 1;
   std::vector<int32_t> rf_idx;
   std::vector<double> rf_dens;
+  // Fourier refinement of the interior lattice as well (rfi = rf, else 1):
+  // psi grids of side M (the period); the refined grid of shift s = s2 rf +
+  // s1 > 0 at columns N + rf_ioff + ((s - 1) M + gy) M + gx, lattice node
+  // (gx, gy) + (c_lo - 2) cell_h; Wsh holds rfi^2 windows
+  int rfi = 1, M = 0;
+  int64_t rf_ioff = 0;
 };
 
 // Returns LS_OK or an error code with a message in err.

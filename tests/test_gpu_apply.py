@@ -580,3 +580,67 @@ def test_fft_refined_interpolation_matches_oracle(r):
     print(f"refine {r} solve: {st} vs LU {e:.2e}", flush=True)
     assert st["converged"] == 1 and e < 1e-8, e
     op.close()
+
+
+def test_fft_refined_interior_matches_oracle():
+    """Fourier refinement of the interior lattice as well (fft_refine = 2,
+    fft_refine_interior = 1): the device transforms the interior psi grids
+    every apply, forms the three shifted grids and contracts one window per
+    shift.  Both precisions against the oracle's rows (every boundary-patch
+    row and 600 interior rows) under each interior-contraction and row
+    kernel schedule; a batch of three equals three single applies; the
+    refined solve satisfies the oracle's rows."""
+    import torch
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import scaled
+    cfg = scaled(config("disc_k2pi"), fft_refine=2, fft_refine_interior=1)
+    n2 = n2_function(cfg)
+    op = binding.Operator(cfg, n2)
+    orc = Setup2D(cfg, n2)
+    xy, key = op.points()
+    p = match_keys(orc.pts["key"], key)
+    rng = np.random.default_rng(3)
+    n_int = orc.pts["n_int"]
+    rows = np.concatenate([np.sort(rng.choice(n_int, 600, replace=False)), np.arange(n_int, orc.N)])
+    A = orc.A_rows(rows)
+    x_or = random_density(orc.pts["key"], seed=33)
+    y_or = A @ x_or
+    cases = {binding.LS_C128: (torch.complex128, 1e-8, [{}]),
+             binding.LS_C64: (torch.complex64, F32_TOL,
+                              [dict(near_variant=v) for v in range(5)] + [dict(csr_variant=v) for v in (0, 1, 2)])}
+    for prec, (dt, tol, scheds) in cases.items():
+        saved = op.get_schedule(prec)
+        u = torch.tensor(_to_lib(x_or, p, op.N), dtype=dt, device="cuda")
+        try:
+            for sch in scheds:
+                op.set_schedule(prec, **dict(saved, **sch))
+                v = torch.empty_like(u)
+                op.apply(u, v)
+                torch.cuda.synchronize()
+                y = v.cpu().numpy().astype(complex)[p][rows]
+                err = np.linalg.norm(y - y_or) / np.linalg.norm(y_or)
+                emax = np.abs(y - y_or).max() / np.abs(y_or).max()
+                print(f"refined interior {dt} {sch}: rel2 {err:.2e} relmax {emax:.2e}", flush=True)
+                assert err < tol and emax < 10 * tol, (sch, err, emax)
+            U = torch.stack([torch.tensor(_to_lib(random_density(orc.pts["key"], seed=50 + s), p, op.N), dtype=dt)
+                             for s in range(3)]).cuda()
+            V = torch.empty_like(U)
+            op.apply(U, V)
+            for k in range(3):
+                vk = torch.empty_like(U[k])
+                op.apply(U[k].contiguous(), vk)
+                torch.cuda.synchronize()
+                d = (torch.linalg.norm(V[k] - vk) / torch.linalg.norm(vk)).item()
+                assert d < (1e-13 if dt == torch.complex128 else 1e-6), (k, d)
+        finally:
+            op.set_schedule(prec, **saved)
+    f_or = plane_wave(cfg, orc.pts["x"], 0.3)
+    f = torch.tensor(_to_lib(f_or, p, op.N), dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(f)
+    st = op.solve(f, x, tol=1e-10, restart=100, max_iter=2000, mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-5)
+    xo = x.cpu().numpy()[p]
+    res = np.linalg.norm(A @ xo - f_or[rows]) / np.linalg.norm(f_or[rows])
+    print(f"refined interior solve: {st} oracle-row residual {res:.2e}", flush=True)
+    assert st["converged"] == 1 and res < 1e-8, res
+    op.close()

@@ -132,25 +132,28 @@ def test_benchmark_schedules_match_oracle_rows(star32, star32_rows):
             op.set_schedule(prec, **saved)
 
 
-def test_benchmark_size_fft_refined_rows(star32):
+@pytest.mark.parametrize("interior", [False, True])
+def test_benchmark_size_fft_refined_rows(star32, interior):
     """Fourier refined interpolation (fft_refine = 2) at the benchmark size:
     4096-point line transforms of the band's 33 t2 lines in both
     precisions, the rows' 32-bit columns reaching the refined values past
-    the N unknowns.  Oracle rows of every class (its refined boundary rule)
-    against both precisions' applies; the apply times are printed beside
-    the unrefined operator's."""
+    the N unknowns; with the interior refinement also the 2-D transforms of
+    the interior psi grids (1350 x 1350) and one interior contraction per
+    shift.  Oracle rows of every class (its refined rules) against both
+    precisions' applies; the apply times are printed beside the unrefined
+    operator's."""
     import copy
     import time
     import torch
     cfg0, op0, orc0, p = star32
-    cfg = scaled(cfg0, fft_refine=2)
+    cfg = scaled(cfg0, fft_refine=2, fft_refine_interior=int(interior))
     t0 = time.perf_counter()
     op = _op(cfg)
     t_setup = time.perf_counter() - t0
     orc = copy.copy(orc0)           # same nodes; its rows follow the refined rule
     orc.cfg = cfg
     orc._cache = {}
-    rows, names = classified_rows(orc, per_class=20, seed=7)
+    rows, names = classified_rows(orc, per_class=10 if interior else 20, seed=7)
     U = random_density(orc.pts["key"], seed=5)[:, None]
     V_or = oracle_rows_times(orc, rows, U)[:, 0]
     u = np.empty(op.N, complex)
@@ -170,8 +173,9 @@ def test_benchmark_size_fft_refined_rows(star32):
         v = vd.cpu().numpy().astype(complex)[p][rows]
         err = np.abs(v - V_or) / np.abs(V_or).max()
         for cl in np.unique(names):
-            print(f"refined star_k32pi {dt} {cl}: max rel err {err[names == cl].max():.3e}", flush=True)
-        print(f"refined star_k32pi {dt}: apply {times[1]:.3f} ms (unrefined {times[0]:.3f} ms), "
+            print(f"refined star_k32pi (interior {interior}) {dt} {cl}: max rel err {err[names == cl].max():.3e}",
+                  flush=True)
+        print(f"refined star_k32pi (interior {interior}) {dt}: apply {times[1]:.3f} ms (unrefined {times[0]:.3f} ms), "
               f"set-up {t_setup:.1f} s, resident {op.resident_bytes() / 1e9:.2f} GB", flush=True)
         assert err.max() < tol
     op.close()

@@ -185,10 +185,79 @@ def test_refined_rows_complete_oracle_rows(r):
     assert n_ext > 0
 
 
+def test_refined_interior_rows_complete_oracle_rows():
+    """Fourier refinement of the interior lattice as well (fft_refine = 2,
+    fft_refine_interior): a library row's refined-grid columns (the shifted
+    psi grids) expanded over the interior unknowns with an independent
+    zero-padded FFT refinement along each axis (period M: the cell box plus
+    two cells per side, rounded up to factors 2, 3, 5), its refined band
+    columns likewise, plus its other columns and the plain far sum, give the
+    oracle's row, for interior, boundary-patch and in-patch interior targets."""
+    from oracle.near2d import interior_refine_period
+    r = 2
+    cfg = scaled(config("disc_k2pi"), fft_refine=r, fft_refine_interior=1)
+    n2 = n2_function(cfg)
+    host, orc = binding.HostOperator(cfg, n2), Setup2D(cfg, n2)
+    xy, key = host.points()
+    N = host.N
+    N1, N2, ch = cfg["band"]["N1"], cfg["band"]["N2"], cfg["cell_h"]
+    H = ch * cfg["h"]
+    p = match_keys(orc.pts["key"], key)
+    inv = np.empty_like(p)
+    inv[p] = np.arange(p.size)
+    dens = np.zeros(N)
+    dens[p] = orc.pts["dens"]
+    grid = -np.ones((N1, N2 + 1), np.int64)
+    b = key[:, 0] == 1
+    grid[key[b, 1], key[b, 2]] = np.nonzero(b)[0]
+    it = np.nonzero(key[:, 0] == 0)[0]
+    cells = np.where(key[:, :1] == 0, np.floor_divide(key[:, 1:], ch), np.floor(xy / H).astype(np.int64))
+    lo = cells.min()
+    M = interior_refine_period(orc.pts, cfg)
+    gxi, gyi = key[it, 1] - (lo - 2) * ch, key[it, 2] - (lo - 2) * ch     # grid positions of the interior nodes
+    Rb, Ri = _zero_pad_refine(N1, r), _zero_pad_refine(M, r)
+    ext_b = (r - 1) * (N2 + 1) * N1
+    rng = np.random.default_rng(17)
+    s_ = np.hypot(xy[:, 0], xy[:, 1])
+    picks = list(rng.choice(np.where((key[:, 0] == 0) & (s_ < 0.5))[0], 2, replace=False))
+    picks += list(rng.choice(np.where(key[:, 0] == 1)[0], 2, replace=False))
+    picks += list(rng.choice(np.where((key[:, 0] == 0) & (s_ > 0.82))[0], 2, replace=False))
+    n_int_ext = 0
+    for i in picks:
+        cols, vals = host.near_row(i)
+        lib_row = np.zeros(N, complex)
+        own = cols < N
+        np.add.at(lib_row, cols[own], vals[own])
+        for c, w in zip(cols[~own], vals[~own]):
+            t = int(c) - N
+            if t < ext_b:
+                s, rem = divmod(t, (N2 + 1) * N1)
+                u, v0 = divmod(rem, N1)
+                j = grid[:, u]
+                lib_row[j] += w * Rb[r * v0 + s + 1] * dens[j]
+            else:
+                s, rem = divmod(t - ext_b, M * M)
+                gy, gx = divmod(rem, M)
+                s1, s2 = (s + 1) % r, (s + 1) // r
+                lib_row[it] += w * Ri[r * gx + s1, gxi] * Ri[r * gy + s2, gyi] * dens[it]
+                n_int_ext += 1
+        orow = np.zeros(N, complex)
+        orow[p] = orc.K_row(inv[i])
+        adj = np.all(np.abs(cells - cells[i]) <= 1, axis=1)
+        d = np.hypot(*(xy - xy[i]).T)
+        cw = np.zeros(N)
+        cw[p] = orc.pts["c"]
+        far = np.where(adj | (d == 0), 0.0, 0.25j * special.hankel1(0, cfg["kappa"] * np.where(d > 0, d, 1)) * cw)
+        err = np.abs(lib_row + far - orow).max() / np.abs(orow).max()
+        assert err < 1e-11, (i, err)
+    assert n_int_ext > 0
+
+
 def test_fft_refine_parameter_checks():
     for over, msg in [({"band": {"patches": 2, "overlap": 0.3, "N1": 40}}, "single periodic band"),
-                      ({"band": {"N1": 56}}, "prime factors")]:
-        cfg = scaled(config("disc_k2pi"), fft_refine=2, **over)
+                      ({"band": {"N1": 56}}, "prime factors"),
+                      ({"fft_refine": 1, "fft_refine_interior": 1}, "needs fft_refine >= 2")]:
+        cfg = scaled(config("disc_k2pi"), **dict({"fft_refine": 2}, **over))
         with pytest.raises(binding.LSError) as e:
             binding.HostOperator(cfg, n2_function(cfg))
         assert msg in str(e.value)
