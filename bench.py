@@ -376,21 +376,23 @@ def fft256_run(reps):
             "grid": "256^3 complex float, in place, one transform (forward and inverse averaged)"}
 
 
-def refined_run(cfg, n2, f, x_ref, r, ortho, autotune):
+def refined_run(cfg, n2, f, x_ref, r, ortho, autotune, interior=False):
     """The same workload with Fourier refined interpolation along the band's
-    t1 lines (fft_refine = r): set-up, tuned applies, per-stage times of the
-    single-precision apply (the refinement runs inside the rows stage) and
-    the timed solve form; its solution against the unrefined FP64 reference
-    (the change the refinement makes to the discretisation)."""
+    t1 lines (fft_refine = r), and with interior=True of the interior lattice
+    too: set-up, tuned applies, per-stage times of the single-precision apply
+    (the band refinement runs inside the rows stage, the interior one inside
+    the interior contraction's) and the timed solve form; its solution
+    against the unrefined FP64 reference (the change the refinement makes to
+    the discretisation)."""
     import torch
     from paper_1509_05063_amd import binding
     from paper_1509_05063_amd.inputs import scaled
-    c = scaled(cfg, fft_refine=r)
+    c = scaled(cfg, fft_refine=r, fft_refine_interior=int(interior))
     t0 = time.time()
     op = binding.Operator(c, n2)
     setup_s = time.time() - t0
     st = op.stats()
-    out = {"fft_refine": r, "setup_s": round(setup_s, 1), "resident_gb": op.resident_bytes() / 1e9,
+    out = {"fft_refine": r, "interior": interior, "setup_s": round(setup_s, 1), "resident_gb": op.resident_bytes() / 1e9,
            "csr_nnz": int(st["csr_nnz"])}
     try:
         if autotune:
@@ -452,6 +454,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel schedules")
     ap.add_argument("--fft-refine", type=int, default=1,
                     help="profiling runs: build the main operator with this Fourier refinement factor")
+    ap.add_argument("--fft-refine-interior", action="store_true",
+                    help="profiling runs: refine the interior lattice as well")
     ap.add_argument("--refine", type=int, default=2,
                     help="refinement factor of the Fourier refined interpolation measured on the same workload "
                          "(0 skips it)")
@@ -502,7 +506,7 @@ def main():
                   "(--refine)", file=sys.stderr)
             sys.exit(2)
         from paper_1509_05063_amd.inputs import scaled
-        cfg = scaled(cfg, fft_refine=args.fft_refine)
+        cfg = scaled(cfg, fft_refine=args.fft_refine, fft_refine_interior=int(args.fft_refine_interior))
     n2 = n2_function(cfg)
     log(f"create {args.config}")
     t0 = time.time()
@@ -660,10 +664,12 @@ def main():
                 "frac": round(fft_gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(fft_b), "avg_ms": round(fft_ms, 4),
                 "note": "2-D face lattices (2 sets x 2 kinds x Pa x Pb complex float) fit in the 256 MB MALL"}
 
-    refined = None
+    refined = refined_int = None
     if args.refine > 1:
         refined = refined_run(cfg, n2, f, x_ref, args.refine, ortho, not args.no_autotune)
         log(f"refined {refined}")
+        refined_int = refined_run(cfg, n2, f, x_ref, args.refine, ortho, not args.no_autotune, interior=True)
+        log(f"refined with the interior {refined_int}")
 
     fft3d = None
     if args.fft3d_reps:
@@ -742,6 +748,7 @@ def main():
         "autotune": tune,
         "multi_rhs": multi,
         "fft_refined": refined,
+        "fft_refined_interior": refined_int,
         "serving": serving,
         "cpu_baseline": cpu,
     }
