@@ -499,6 +499,44 @@ def test_fft_refined_interior_interpolation():
     assert np.all(e[:, 2] < e[:, 1]), e
 
 
+def test_offgrid_shortcut_weights_interpolate_smooth_data():
+    """The off-grid shortcut's interpolation weights over the band grid nodes
+    (the remark after eq:-VolInt-Adj-Sing-MultiSplit) reproduce a smooth
+    function of the patch coordinates at random off-grid points: a
+    quadratic in t2 times a 2-wave exponential in t1 to 3e-9 unrefined, and
+    a 12-wave one gaining about 2^8 per doubling of the t1 refinement."""
+    from oracle.op2d import shortcut_weights
+    cfg = config("disc_k2pi")
+    N1, N2 = cfg["band"]["N1"], cfg["band"]["N2"]
+    rng = np.random.default_rng(0)
+    pts = rng.uniform([0, 0], [N1, N2], (6, 2))
+
+    def err(m, rf):
+        def g(v, u):
+            return np.exp(2j * np.pi * m * v / N1) * (1 + 0.2 * u - 0.01 * u * u)
+        c = scaled(cfg, fft_refine=rf)
+        out = []
+        for vt, ut in pts:
+            w = shortcut_weights(vt, ut, c)
+            out.append(abs(sum(ww * g(v, u) for (v, u), ww in w.items()) - g(vt, ut)))
+        return max(out)
+
+    assert err(2, 1) < 5e-9
+    e = [err(12, rf) for rf in (1, 2, 4)]
+    assert 1e-3 < e[0] < 1e-2, e
+    assert e[1] < e[0] / 100 and e[2] < e[1] / 100, e
+
+
+def test_offgrid_shortcut_at_a_grid_node_is_the_direct_rule():
+    """At patch coordinates that fall on a grid node the shortcut's weights
+    are that node alone, so the shortcut returns the boundary rule there."""
+    from oracle.op2d import shortcut_weights
+    for rf in (1, 2):
+        w = shortcut_weights(17.0, 5.0, scaled(config("disc_k2pi"), fft_refine=rf))
+        big = {k: v for k, v in w.items() if abs(v) > 1e-13}
+        assert list(big) == [(17, 5)] and abs(big[(17, 5)] - 1) < 1e-13, big
+
+
 def test_fft_refine_rejects_several_patches():
     from oracle.geom2d import band_index
     from oracle.near2d import band_sing_row
