@@ -106,6 +106,25 @@ class Setup2D:
         return acc
 
 
+    def K_row(self, i):
+        return self.plain_row(i) + self.sing_row(i)
+
+    def K_rows(self, rows):
+        return np.stack([self.K_row(int(i)) for i in rows])
+
+    def dense_K(self):
+        return self.K_rows(range(self.N))
+
+    # ----------------------------------------------------------- operators
+    def A_rows(self, rows):
+        K = self.K_rows(rows)
+        A = (self.kappa ** 2) * K
+        A[np.arange(len(rows)), np.asarray(rows)] += 1.0
+        return A
+
+    def dense_A(self):
+        return self.A_rows(np.arange(self.N))
+
 def shortcut_weights(vt, ut, cfg):
     """Interpolation weights of the off-grid shortcut: {(v, u): weight} over
     the band grid nodes for the value at patch coordinates (vt, ut) (grid
@@ -132,22 +151,3 @@ def shortcut_weights(vt, ut, cfg):
         for v in np.nonzero(Wv)[0]:
             out[(int(v), bu + a)] = out.get((int(v), bu + a), 0.0) + Lu[a] * Wv[v]
     return out
-
-    def K_row(self, i):
-        return self.plain_row(i) + self.sing_row(i)
-
-    def K_rows(self, rows):
-        return np.stack([self.K_row(int(i)) for i in rows])
-
-    def dense_K(self):
-        return self.K_rows(range(self.N))
-
-    # ----------------------------------------------------------- operators
-    def A_rows(self, rows):
-        K = self.K_rows(rows)
-        A = (self.kappa ** 2) * K
-        A[np.arange(len(rows)), np.asarray(rows)] += 1.0
-        return A
-
-    def dense_A(self):
-        return self.A_rows(np.arange(self.N))
