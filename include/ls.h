@@ -129,7 +129,16 @@ typedef struct {
  *                forms the r^2 - 1 shifted lattices (phase ramps, inverse
  *                transforms) and runs the interior contraction once per
  *                shift; the rows and the workspace grow by (r^2 - 1) M^2
- *                elements (plus M^2 for the spectra) per right-hand side. */
+ *                elements (plus M^2 for the spectra) per right-hand side.
+ *   offgrid_shortcut  nonzero (single periodic band): the paper's shortcut
+ *                for interior lattice nodes inside the boundary patch (the
+ *                remark after eq:-VolInt-Adj-Sing-MultiSplit): the boundary
+ *                rule is evaluated at the patch's grid nodes (their values
+ *                s kept in the apply's workspace, refined along t1 like the
+ *                densities when fft_refine > 1) and interpolated to those
+ *                nodes by P x P stencils instead of being evaluated there;
+ *                every apply runs those rules first.  Workspace: rf (N2 + 1)
+ *                N1 more elements per right-hand side; no dense tiles. */
 typedef struct {
   int Q, P;
   double chi_c0, r_int, r1, r2;
@@ -139,6 +148,7 @@ typedef struct {
   int skip_tiles;
   int fft_refine;
   int fft_refine_interior;
+  int offgrid_shortcut;
 } ls_params;
 
 /* Refractive index callback: writes n^2 at n points (x, y interleaved);

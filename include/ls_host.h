@@ -42,7 +42,12 @@ ls_status ls_host_stats(const ls_host_op* h, int64_t* out, int nout);
  * column N + (r - 1)(N2 + 1) N1 + ((s - 1) M + gy) M + gx (s = s2 r + s1 > 0)
  * holds the two-dimensional trigonometric interpolant (period M) of the
  * interior density (m omega) u at lattice index (gx + s1 / r, gy + s2 / r)
- * + (c_lo - 2) cell_h, c_lo the smallest cell index of the nodes. */
+ * + (c_lo - 2) cell_h, c_lo the smallest cell index of the nodes.  With
+ * offgrid_shortcut, rows i = N .. N + n_s - 1 are the boundary rule at the
+ * patch's grid nodes in line order (t2 line u, then t1 index v), whose
+ * values the other rows read at column N + s_off + u N1 + v, s_off the
+ * columns of the refinements before them; the refined s lines follow as
+ * the densities' do. */
 ls_status ls_host_near_row(const ls_host_op* h, int64_t i, int64_t cap, int32_t* cols, double* vals,
                            int64_t* count);
 

@@ -32,7 +32,8 @@ class Params(C.Structure):
                 ("polar_n_out", C.c_int), ("polar_n_theta", C.c_int), ("band_M", C.c_int),
                 ("band_n_in", C.c_int), ("band_n_out", C.c_int), ("cell_h", C.c_int), ("q", C.c_int),
                 ("n_fb", C.c_int), ("coll_factor", C.c_int), ("skip_tiles", C.c_int),
-                ("fft_refine", C.c_int), ("fft_refine_interior", C.c_int)]
+                ("fft_refine", C.c_int), ("fft_refine_interior", C.c_int),
+                ("offgrid_shortcut", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -183,7 +184,8 @@ def params_from(cfg):
                   float(cfg["r2"]), int(pl["n_in"]), int(pl["grade"]), int(pl["n_out"]), int(pl["n_theta"]),
                   int(br["M"]), int(br["n_in"]), int(br["n_out"]), int(cfg["cell_h"]), int(cfg["q"]),
                   int(cfg["n_fb"]), int(cfg["coll_factor"]), int(cfg.get("skip_tiles", 0)),
-                  int(cfg.get("fft_refine", 1)), int(cfg.get("fft_refine_interior", 0)))
+                  int(cfg.get("fft_refine", 1)), int(cfg.get("fft_refine_interior", 0)),
+                  int(cfg.get("offgrid_shortcut", 0)))
 
 
 def _n2_callback(n2_fn):

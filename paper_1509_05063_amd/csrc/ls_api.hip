@@ -240,7 +240,7 @@ size_t ws_bytes(const ls_op* op, int nrhs, ls_prec prec) {
   // projections, lattices, interior grid, near-field buffer of the
   // concurrent near field, and with Fourier refinement the rows' input x
   // and the band lines
-  const size_t rfe = d.rf > 1 ? (size_t)nrhs * ((size_t)d.ldx + (size_t)d.rf_lines * d.rf_n1) : 0;
+  const size_t rfe = d.ldx > d.N ? (size_t)nrhs * ((size_t)d.ldx + (size_t)d.rf_lines * d.rf_n1) : 0;
   const size_t rfie = d.rfi > 1 ? (size_t)nrhs * Gw * Gw : 0;   // spectra of the psi grids
   return c * ((size_t)nrhs * d.ncell * d.U + (size_t)nrhs * 4 * d.Pa * d.Pb + (size_t)nrhs * Gw * Gw +
               (size_t)nrhs * op->N + rfe + rfie) + 256;
@@ -430,8 +430,23 @@ ls_status ls_host_near_row(const ls_host_op* h, int64_t i, int64_t cap, int32_t*
                            int64_t* count) {
   if (!h || !count) return fail(LS_EINVAL, "null argument");
   const auto& o = h->h;
-  if (i < 0 || i >= o.N) return fail(LS_EINVAL, "row out of range");
+  const int64_t nsr = (int64_t)o.sr_rows.size();
+  if (i < 0 || i >= o.N + nsr) return fail(LS_EINVAL, "row out of range");
   std::vector<std::pair<int32_t, cd>> ent;
+  if (i >= o.N) {
+    // off-grid shortcut: the boundary rule of grid node i - N (its s column
+    // is sr_rows[i - N])
+    const int64_t r = i - o.N;
+    for (int64_t k = o.sr_rowptr[r]; k < o.sr_rowptr[r + 1]; ++k) ent.emplace_back(o.sr_cols[k], o.sr_vals[k]);
+    *count = (int64_t)ent.size();
+    if (cols && vals)
+      for (int64_t k = 0; k < (int64_t)ent.size() && k < cap; ++k) {
+        cols[k] = ent[k].first;
+        vals[2 * k] = ent[k].second.real();
+        vals[2 * k + 1] = ent[k].second.imag();
+      }
+    return LS_OK;
+  }
   if (o.key[3 * i] == 0) {
     // shared window part: interior sources in the 5x5 cells around i's cell
     int c = -1, slot = -1;
@@ -706,6 +721,31 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     }
   }
   UP(upload_i(op, prow, &a.rowptr));
+  if (!h.sr_rows.empty()) {
+    // off-grid shortcut: the boundary rule at the patch's grid nodes as rows
+    // writing s into x (32-bit column offsets from each row's first column)
+    const int n1 = h.g.N1, nlines = h.g.N2 + 1;
+    a.rf_n1 = b.rf_n1 = n1;
+    a.rf_lines = b.rf_lines = nlines;
+    if (h.rf == 1) a.ldx = b.ldx = h.N + h.sc_off + (int64_t)nlines * n1;
+    a.nsr = b.nsr = (int)h.sr_rows.size();
+    a.sc_off = b.sc_off = h.sc_off;
+    const size_t ns = h.sr_rows.size();
+    std::vector<int32_t> cb(ns), c32(h.sr_cols.size());
+    for (size_t r = 0; r < ns; ++r) {
+      cb[r] = h.sr_cols[h.sr_rowptr[r]];     // sorted: the smallest column
+      for (int64_t k = h.sr_rowptr[r]; k < h.sr_rowptr[r + 1]; ++k) c32[k] = h.sr_cols[k] - cb[r];
+    }
+    UP(upload_i(op, h.sr_rowptr, &a.sr_rowptr));
+    UP(upload_i(op, h.sr_rows, &a.sr_rows));
+    UP(upload_i(op, cb, &a.sr_colbase));
+    UP(upload_i(op, c32, &a.sr_cols32));
+    UP(upload_c(op, h.sr_vals, &a.sr_vals, &b.sr_vals));
+    b.sr_rowptr = a.sr_rowptr;
+    b.sr_rows = a.sr_rows;
+    b.sr_colbase = a.sr_colbase;
+    b.sr_cols32 = a.sr_cols32;
+  }
   if (h.rf > 1) {
     // Fourier refinement of the band's t1 lines: line maps, phase ramps of
     // the shifts s / rf (with the inverse transform's 1 / N1; the Nyquist
@@ -714,7 +754,8 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
     a.rf = b.rf = rf;
     a.rf_n1 = b.rf_n1 = n1;
     a.rf_lines = b.rf_lines = nlines;
-    a.ldx = b.ldx = h.N + (int64_t)(rf - 1) * nlines * n1 + (int64_t)(h.rfi * h.rfi - 1) * h.M * h.M;
+    a.ldx = b.ldx = h.N + (int64_t)(rf - 1) * nlines * n1 + (int64_t)(h.rfi * h.rfi - 1) * h.M * h.M +
+                    (h.sr_rows.empty() ? 0 : (int64_t)rf * nlines * n1);
     a.rf_ioff = b.rf_ioff = h.rf_ioff;
     a.rf_plan = b.rf_plan = make_plan(n1);
     std::vector<cd> ph((size_t)(rf - 1) * n1), tw(n1);
@@ -790,7 +831,7 @@ ls_status ls_create(const ls_geometry* g, ls_n2_fn n2, void* ctx, double kappa, 
   // precisions); the single-precision weights then come back for the tiles
   // (no tiles with Fourier refinement: their columns would include the
   // refined values)
-  const bool tiles = !p->skip_tiles && h.rf == 1;
+  const bool tiles = !p->skip_tiles && h.rf == 1 && h.sr_rows.empty();
   std::vector<Fp32c> vals32(tiles ? (size_t)prow[nrow] : 0);
   std::vector<Fp64c> vals64(tiles ? (size_t)prow[nrow] : 0);
   {

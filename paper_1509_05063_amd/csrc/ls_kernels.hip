@@ -3016,6 +3016,20 @@ __global__ void k_add_c(V* __restrict__ v, const V* __restrict__ x, int64_t n) {
   if (i < n) v[i] = cadd(v[i], x[i]);
 }
 
+// Strided copies and clears, one block of n per right-hand side (grid: (n /
+// 256, nrhs)).
+template <typename V>
+__global__ void __launch_bounds__(256) k_copy_strided(const V* __restrict__ src, int64_t ss, V* __restrict__ dst,
+                                                      int64_t ds, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[(int64_t)blockIdx.y * ds + i] = src[(int64_t)blockIdx.y * ss + i];
+}
+template <typename V>
+__global__ void __launch_bounds__(256) k_zero_strided(V* __restrict__ x, int64_t ds, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[(int64_t)blockIdx.y * ds + i] = czero<V>();
+}
+
 // Fourier refinement of the boundary patch's t1 lines (Sec. 3.1), first
 // step: copies each right-hand side's u into the head of its block of x (ldx
 // entries) and forms the density on the band grid, phi[line][v] = dens u[idx]
@@ -3312,7 +3326,13 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
   auto prep = [&](hipStream_t ns) {
     if (prepped) return;
     prepped = true;
-    if (d.rf > 1) refine_band(ns, rf_x, rf_phi);
+    if (d.rf > 1) {
+      refine_band(ns, rf_x, rf_phi);
+    } else if (d.ldx > d.N) {
+      // x without band refinement (off-grid shortcut only): u into its head
+      hipLaunchKernelGGL(k_copy_strided<V>, dim3((unsigned)((d.N + 255) / 256), nrhs), dim3(256), 0, ns, u, d.N,
+                         rf_x, d.ldx, d.N);
+    }
     if (d.rfi > 1) {
       psi_grid(ns);
       refine_interior(ns);
@@ -3374,10 +3394,38 @@ hipError_t launch_apply(const DevView<T>& d, const void* u_, void* v_, int nrhs,
       // with Fourier refinement the rows read x = [u ; refined band lines]
       const V* ux = u;
       int64_t ldu = d.N;
-      if (d.rf > 1) {
+      if (d.ldx > d.N) {
         prep(ns);
         ux = rf_x;
         ldu = d.ldx;
+      }
+      if (d.nsr > 0) {
+        // off-grid shortcut: the boundary rule at the patch's grid nodes
+        // into s (in x), then s refined along t1 like the densities
+        const int nl = d.rf_lines * d.rf_n1;
+        V* sreg = rf_x + d.N + d.sc_off;
+        hipLaunchKernelGGL(k_zero_strided<V>, dim3((unsigned)((nl + 255) / 256), nrhs), dim3(256), 0, ns, sreg, d.ldx,
+                           (int64_t)nl);
+        if (std::is_same<T, double>::value)
+          hipLaunchKernelGGL((k_near_csr<T, double2, int32_t>), dim3((d.nsr + 3) / 4), b, 0, ns, (const V*)rf_x, rf_x,
+                             d.sr_rowptr, d.sr_rows, d.sr_colbase, d.sr_cols32, (const double2*)d.sr_vals, d.nsr,
+                             d.ldx, nrhs, (T)1, d.ldx);
+        else
+          hipLaunchKernelGGL((k_near_csr<T, float2, int32_t>), dim3((d.nsr + 3) / 4), b, 0, ns, (const V*)rf_x, rf_x,
+                             d.sr_rowptr, d.sr_rows, d.sr_colbase, d.sr_cols32, (const float2*)d.sr_vals, d.nsr,
+                             d.ldx, nrhs, (T)1, d.ldx);
+        if (d.rf > 1) {
+          const int n1 = d.rf_n1;
+          const size_t sh = (size_t)n1 * sizeof(V);
+          hipLaunchKernelGGL(k_copy_strided<V>, dim3((unsigned)((nl + 255) / 256), nrhs), dim3(256), 0, ns,
+                             (const V*)sreg, d.ldx, rf_phi, (int64_t)nl, (int64_t)nl);
+          hipLaunchKernelGGL((k_fft_rows_ip<T, 1, 256>), dim3(d.rf_lines, nrhs), dim3(256), sh, ns, rf_phi,
+                             (const V*)d.rf_tw, d.rf_plan, (int64_t)n1, n1, n1, (int64_t)nl);
+          hipLaunchKernelGGL(k_refine_phase<T>, dim3((unsigned)((nl + 255) / 256), nrhs, d.rf - 1), dim3(256), 0, ns,
+                             (const V*)rf_phi, sreg + nl, (const V*)d.rf_ph, n1, nl, d.ldx);
+          hipLaunchKernelGGL((k_fft_rows_ip<T, -1, 256>), dim3(d.rf_lines * (d.rf - 1), nrhs), dim3(256), sh, ns,
+                             sreg + nl, (const V*)d.rf_tw, d.rf_plan, (int64_t)n1, n1, n1, d.ldx);
+        }
       }
       if (d.csr_f64 && !blk) {
         if (d.coloff)

@@ -99,6 +99,15 @@ struct DevView {
   // s S Wn^2; rf_iph [rf][gw] the phase ramps / gw, rf_itw the twiddles
   int gw = 0, rfi = 1;
   int64_t rf_ioff = 0;
+  // off-grid shortcut (nsr > 0): nsr rows of the boundary rule at the
+  // patch's grid nodes (output column sr_rows in x, CSR with 32-bit column
+  // offsets from sr_colbase, weights complex T); their values s at x + N +
+  // sc_off + u N1 + v, the refined s lines after them
+  int nsr = 0;
+  int64_t sc_off = 0;
+  const int64_t* sr_rowptr = nullptr;
+  const int32_t *sr_rows = nullptr, *sr_colbase = nullptr, *sr_cols32 = nullptr;
+  const void* sr_vals = nullptr;
   const void *rf_iph = nullptr, *rf_itw = nullptr;
   FftPlan rf_iplan{};
   const int32_t* rf_idx = nullptr;

@@ -304,6 +304,7 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     }
   }
   op.rf = rf;
+  if (p.offgrid_shortcut && NP > 1) { err = "offgrid_shortcut needs the single periodic band"; return LS_EINVAL; }
   if (p.fft_refine_interior) {
     if (rf < 2) { err = "fft_refine_interior needs fft_refine >= 2"; return LS_EINVAL; }
     if (p.cell_h != 8) { err = "fft_refine_interior needs cell_h = 8"; return LS_EINVAL; }
@@ -643,6 +644,10 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
     if (periodic) dv = std::min(dv, N1 - dv);
     return chi(dv / p.r1, p.chi_c0) * chi(std::fabs(us - ut) / p.r2, p.chi_c0);
   };
+  // off-grid shortcut: boundary rule values s at the patch's grid nodes in
+  // x at N + sc_off + u N1 + v (then the refined s lines, as the densities')
+  const bool sc = p.offgrid_shortcut != 0;
+  op.sc_off = op.rf_ioff + (int64_t)(op.rfi * op.rfi - 1) * op.M * op.M;
   std::vector<std::vector<std::pair<int32_t, cd>>> rowdata(N);
   std::vector<char> has_row(N, 0);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -725,6 +730,31 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
           double d = std::hypot(op.xy[2 * j] - xi[0], op.xy[2 * j + 1] - xi[1]);
           ent.emplace_back(j, -eta * green2d(kappa, d) * op.cw[j]);
         }
+      if (sc) {
+        // off-grid shortcut: a grid node of the patch reads its own boundary
+        // rule value s from x; an interior lattice node inside the patch
+        // interpolates the node values (t2 Lagrange, t1 Lagrange on the
+        // refined lines)
+        if (tb) {
+          ent.emplace_back((int32_t)(N + op.sc_off + (int64_t)op.key[3 * i + 2] * N1 + op.key[3 * i + 1]), cd(1.0, 0.0));
+        } else {
+          const int P = p.P;
+          double Lu[32], Lv[32];
+          const int64_t bu = std::min<int64_t>(std::max<int64_t>(centered_base(tu[i], P), 0), N2 - P + 1);
+          lagrange(tu[i], bu, P, Lu);
+          const int64_t bv = centered_base(rf * tvi, P);
+          lagrange(rf * tvi, bv, P, Lv);
+          const int64_t nr = (int64_t)rf * N1;
+          for (int a = 0; a < P; ++a)
+            for (int c = 0; c < P; ++c) {
+              const int64_t vr = ((bv + c) % nr + nr) % nr, v0 = vr / rf, s = vr % rf, u = bu + a;
+              const int64_t col = s == 0 ? N + op.sc_off + u * N1 + v0
+                                         : N + op.sc_off + (int64_t)(N2 + 1) * N1 + ((s - 1) * (N2 + 1) + u) * N1 + v0;
+              ent.emplace_back((int32_t)col, cd(Lu[a] * Lv[c], 0.0));
+            }
+        }
+        continue;
+      }
       band_sing(xi, tvi, tu[i], pp, ent);
     }
     if (tb) {
@@ -785,6 +815,40 @@ ls_status build_host_op(const ls_geometry* gp, ls_n2_fn n2fn, void* ctx, double 
       for (auto& e : rowdata[i]) { op.cols[o] = e.first; op.vals[o] = e.second; ++o; }
       std::vector<std::pair<int32_t, cd>>().swap(rowdata[i]);
       ++r;
+    }
+  }
+  if (sc) {
+    // the boundary rule at every grid node of the patch, as rows whose
+    // output is the node's s entry in x
+    const int64_t nl = (int64_t)(N2 + 1) * N1;
+    std::vector<std::vector<std::pair<int32_t, cd>>> srow(nl);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t g = 0; g < nl; ++g) {
+      const int64_t u = g / N1, v = g % N1;
+      const int32_t j = bg(0, v, u);
+      if (j < 0) continue;
+      std::vector<std::pair<int32_t, cd>> ent;
+      band_sing(&op.xy[2 * j], (double)v, (double)u, 0, ent);
+      std::sort(ent.begin(), ent.end(), [](const std::pair<int32_t, cd>& a, const std::pair<int32_t, cd>& b) {
+        return a.first < b.first;
+      });
+      for (auto& e : ent) {
+        if (!srow[g].empty() && srow[g].back().first == e.first) srow[g].back().second += e.second;
+        else srow[g].push_back(e);
+      }
+    }
+    op.sr_rowptr.assign(1, 0);
+    op.sr_rows.clear();
+    op.sr_cols.clear();
+    op.sr_vals.clear();
+    for (int64_t g = 0; g < nl; ++g) {
+      if (srow[g].empty()) continue;
+      op.sr_rows.push_back((int32_t)(N + op.sc_off + g));
+      for (auto& e : srow[g]) {
+        op.sr_cols.push_back(e.first);
+        op.sr_vals.push_back(e.second);
+      }
+      op.sr_rowptr.push_back((int64_t)op.sr_cols.size());
     }
   }
 

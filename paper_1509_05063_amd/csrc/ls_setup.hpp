@@ -76,6 +76,14 @@ struct HostOp {
   // (gx, gy) + (c_lo - 2) cell_h; Wsh holds rfi^2 windows
   int rfi = 1, M = 0;
   int64_t rf_ioff = 0;
+  // off-grid shortcut: the boundary rule's value s at grid node (v, u) of
+  // the patch at column N + sc_off + u N1 + v (the refined s lines follow,
+  // (rf - 1) (N2 + 1) N1 values laid out as the densities'); sr_*: those
+  // rules as rows (output column in sr_rows, CSR over sr_rowptr)
+  int64_t sc_off = 0;
+  std::vector<int64_t> sr_rowptr;
+  std::vector<int32_t> sr_rows, sr_cols;
+  std::vector<cd> sr_vals;
 };
 
 // Returns LS_OK or an error code with a message in err.

@@ -644,3 +644,62 @@ def test_fft_refined_interior_matches_oracle():
     print(f"refined interior solve: {st} oracle-row residual {res:.2e}", flush=True)
     assert st["converged"] == 1 and res < 1e-8, res
     op.close()
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_offgrid_shortcut_matches_oracle(r):
+    """The paper's off-grid shortcut (offgrid_shortcut; with r = 2 its s lines
+    refined along t1): every apply first evaluates the boundary rule at the
+    patch's grid nodes into the workspace, then the rows read those values.
+    Both precisions against the oracle on every row of the disc, under each
+    row-kernel schedule; a batch of three equals three single applies; the
+    solve matches the oracle's dense LU solution."""
+    import torch
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import scaled
+    cfg = scaled(config("disc_k2pi"), fft_refine=r, offgrid_shortcut=1)
+    n2 = n2_function(cfg)
+    op = binding.Operator(cfg, n2)
+    orc = Setup2D(cfg, n2)
+    xy, key = op.points()
+    p = match_keys(orc.pts["key"], key)
+    A = orc.dense_A()
+    x_or = random_density(orc.pts["key"], seed=35)
+    y_or = A @ x_or
+    for prec, dt, tol, variants in ((binding.LS_C128, torch.complex128, 1e-8, (0,)),
+                                    (binding.LS_C64, torch.complex64, F32_TOL, (0, 1, 2))):
+        saved = op.get_schedule(prec)
+        u = torch.tensor(_to_lib(x_or, p, op.N), dtype=dt, device="cuda")
+        try:
+            for cv in variants:
+                op.set_schedule(prec, **dict(saved, csr_variant=cv))
+                v = torch.empty_like(u)
+                op.apply(u, v)
+                torch.cuda.synchronize()
+                y = v.cpu().numpy().astype(complex)[p]
+                err = np.linalg.norm(y - y_or) / np.linalg.norm(y_or)
+                emax = np.abs(y - y_or).max() / np.abs(y_or).max()
+                print(f"shortcut r={r} {dt} csr {cv}: rel2 {err:.2e} relmax {emax:.2e}", flush=True)
+                assert err < tol and emax < 10 * tol, (cv, err, emax)
+            U = torch.stack([torch.tensor(_to_lib(random_density(orc.pts["key"], seed=60 + s), p, op.N), dtype=dt)
+                             for s in range(3)]).cuda()
+            V = torch.empty_like(U)
+            op.apply(U, V)
+            for k in range(3):
+                vk = torch.empty_like(U[k])
+                op.apply(U[k].contiguous(), vk)
+                torch.cuda.synchronize()
+                d = (torch.linalg.norm(V[k] - vk) / torch.linalg.norm(vk)).item()
+                assert d < (1e-13 if dt == torch.complex128 else 1e-6), (k, d)
+        finally:
+            op.set_schedule(prec, **saved)
+    f_or = plane_wave(cfg, orc.pts["x"], 0.3)
+    u_or = np.linalg.solve(A, f_or)
+    f = torch.tensor(_to_lib(f_or, p, op.N), dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(f)
+    st = op.solve(f, x, tol=1e-10, restart=100, max_iter=2000, mode=binding.LS_SOLVE_FP32_REFINE, inner_tol=1e-5)
+    e = np.linalg.norm(x.cpu().numpy()[p] - u_or) / np.linalg.norm(u_or)
+    print(f"shortcut r={r} solve: {st} vs LU {e:.2e}", flush=True)
+    assert st["converged"] == 1 and e < 1e-8, e
+    op.close()

@@ -132,8 +132,8 @@ def test_benchmark_schedules_match_oracle_rows(star32, star32_rows):
             op.set_schedule(prec, **saved)
 
 
-@pytest.mark.parametrize("interior", [False, True])
-def test_benchmark_size_fft_refined_rows(star32, interior):
+@pytest.mark.parametrize("interior,shortcut", [(False, False), (True, False), (False, True)])
+def test_benchmark_size_fft_refined_rows(star32, interior, shortcut):
     """Fourier refined interpolation (fft_refine = 2) at the benchmark size:
     4096-point line transforms of the band's 33 t2 lines in both
     precisions, the rows' 32-bit columns reaching the refined values past
@@ -141,12 +141,16 @@ def test_benchmark_size_fft_refined_rows(star32, interior):
     the interior psi grids (1350 x 1350) and one interior contraction per
     shift.  Oracle rows of every class (its refined rules) against both
     precisions' applies; the apply times are printed beside the unrefined
-    operator's."""
+    operator's.  With the off-grid shortcut (unrefined): the boundary rule at
+    the 135,168 grid nodes first, then the rows reading those values."""
     import copy
     import time
     import torch
     cfg0, op0, orc0, p = star32
-    cfg = scaled(cfg0, fft_refine=2, fft_refine_interior=int(interior))
+    # (the off-grid shortcut unrefined here: the oracle's refined shortcut
+    # spreads over whole 4096-point lines of node rules)
+    cfg = scaled(cfg0, fft_refine=1 if shortcut else 2, fft_refine_interior=int(interior),
+                 offgrid_shortcut=int(shortcut))
     t0 = time.perf_counter()
     op = _op(cfg)
     t_setup = time.perf_counter() - t0
@@ -173,9 +177,9 @@ def test_benchmark_size_fft_refined_rows(star32, interior):
         v = vd.cpu().numpy().astype(complex)[p][rows]
         err = np.abs(v - V_or) / np.abs(V_or).max()
         for cl in np.unique(names):
-            print(f"refined star_k32pi (interior {interior}) {dt} {cl}: max rel err {err[names == cl].max():.3e}",
-                  flush=True)
-        print(f"refined star_k32pi (interior {interior}) {dt}: apply {times[1]:.3f} ms (unrefined {times[0]:.3f} ms), "
+            print(f"refined star_k32pi (interior {interior}, shortcut {shortcut}) {dt} {cl}: max rel err "
+                  f"{err[names == cl].max():.3e}", flush=True)
+        print(f"refined star_k32pi (interior {interior}, shortcut {shortcut}) {dt}: apply {times[1]:.3f} ms (unrefined {times[0]:.3f} ms), "
               f"set-up {t_setup:.1f} s, resident {op.resident_bytes() / 1e9:.2f} GB", flush=True)
         assert err.max() < tol
     op.close()

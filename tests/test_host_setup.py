@@ -253,6 +253,79 @@ def test_refined_interior_rows_complete_oracle_rows():
     assert n_int_ext > 0
 
 
+@pytest.mark.parametrize("r", [1, 2])
+def test_offgrid_shortcut_rows_complete_oracle_rows(r):
+    """The paper's off-grid shortcut (offgrid_shortcut, with and without the
+    t1 refinement): a library row's s columns (the boundary rule at the
+    patch's grid nodes, read back through ls_host_near_row's rows N ..) and
+    refined s columns (expanded with an independent zero-padded FFT
+    refinement of the s lines), plus its other columns and the plain far
+    sum, give the oracle's row, for grid-node and in-patch interior targets."""
+    cfg = scaled(config("disc_k2pi"), fft_refine=r, offgrid_shortcut=1)
+    n2 = n2_function(cfg)
+    host, orc = binding.HostOperator(cfg, n2), Setup2D(cfg, n2)
+    xy, key = host.points()
+    N = host.N
+    N1, N2 = cfg["band"]["N1"], cfg["band"]["N2"]
+    nl = (N2 + 1) * N1
+    p = match_keys(orc.pts["key"], key)
+    inv = np.empty_like(p)
+    inv[p] = np.arange(p.size)
+    dens = np.zeros(N)
+    dens[p] = orc.pts["dens"]
+    grid = -np.ones((N1, N2 + 1), np.int64)
+    b = key[:, 0] == 1
+    grid[key[b, 1], key[b, 2]] = np.nonzero(b)[0]
+    assert np.all(grid >= 0)
+    R = _zero_pad_refine(N1, r) if r > 1 else None
+    ext_b = (r - 1) * nl                       # refined band densities, then s, then refined s
+    node_rows = {}
+
+    def expand(cols, vals, out, scale=1.0):
+        for c, w in zip(cols, vals):
+            c = int(c)
+            if c < N:
+                out[c] += scale * w
+                continue
+            t = c - N
+            if t < ext_b:                       # refined band density
+                s, rem = divmod(t, nl)
+                u, v0 = divmod(rem, N1)
+                j = grid[:, u]
+                out[j] += scale * w * R[r * v0 + s + 1] * dens[j]
+            elif t < ext_b + nl:                # s at grid node g
+                g = t - ext_b
+                if g not in node_rows:
+                    node_rows[g] = host.near_row(N + g)
+                expand(*node_rows[g], out, scale * w)
+            else:                               # refined s line
+                s, rem = divmod(t - ext_b - nl, nl)
+                u, v0 = divmod(rem, N1)
+                for v in range(N1):
+                    g = u * N1 + v
+                    if g not in node_rows:
+                        node_rows[g] = host.near_row(N + g)
+                    expand(*node_rows[g], out, scale * w * R[r * v0 + s + 1, v])
+
+    cells = _cells(cfg, key, xy)
+    s_ = np.hypot(xy[:, 0], xy[:, 1])
+    rng = np.random.default_rng(23)
+    picks = list(rng.choice(np.where((key[:, 0] == 0) & (s_ > 0.82))[0], 3, replace=False))
+    picks += list(rng.choice(np.where(key[:, 0] == 1)[0], 2, replace=False))
+    for i in picks:
+        lib_row = np.zeros(N, complex)
+        expand(*host.near_row(i), lib_row)
+        orow = np.zeros(N, complex)
+        orow[p] = orc.K_row(inv[i])
+        adj = np.all(np.abs(cells - cells[i]) <= 1, axis=1)
+        d = np.hypot(*(xy - xy[i]).T)
+        cw = np.zeros(N)
+        cw[p] = orc.pts["c"]
+        far = np.where(adj | (d == 0), 0.0, 0.25j * special.hankel1(0, cfg["kappa"] * np.where(d > 0, d, 1)) * cw)
+        err = np.abs(lib_row + far - orow).max() / np.abs(orow).max()
+        assert err < 1e-11, (i, err)
+
+
 def test_fft_refine_parameter_checks():
     for over, msg in [({"band": {"patches": 2, "overlap": 0.3, "N1": 40}}, "single periodic band"),
                       ({"band": {"N1": 56}}, "prime factors"),
