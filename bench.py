@@ -376,23 +376,26 @@ def fft256_run(reps):
             "grid": "256^3 complex float, in place, one transform (forward and inverse averaged)"}
 
 
-def refined_run(cfg, n2, f, x_ref, r, ortho, autotune, interior=False):
+def refined_run(cfg, n2, f, x_ref, r, ortho, autotune, interior=False, shortcut=False):
     """The same workload with Fourier refined interpolation along the band's
     t1 lines (fft_refine = r), and with interior=True of the interior lattice
     too: set-up, tuned applies, per-stage times of the single-precision apply
     (the band refinement runs inside the rows stage, the interior one inside
-    the interior contraction's) and the timed solve form; its solution
+    the interior contraction's) and the timed solve form; with shortcut=True
+    the interior lattice nodes inside the boundary patch interpolate the
+    boundary rule's values at the patch's grid nodes (computed first in the
+    rows stage) instead of evaluating it.  Its solution
     against the unrefined FP64 reference (the change the refinement makes to
     the discretisation)."""
     import torch
     from paper_1509_05063_amd import binding
     from paper_1509_05063_amd.inputs import scaled
-    c = scaled(cfg, fft_refine=r, fft_refine_interior=int(interior))
+    c = scaled(cfg, fft_refine=r, fft_refine_interior=int(interior), offgrid_shortcut=int(shortcut))
     t0 = time.time()
     op = binding.Operator(c, n2)
     setup_s = time.time() - t0
     st = op.stats()
-    out = {"fft_refine": r, "interior": interior, "setup_s": round(setup_s, 1), "resident_gb": op.resident_bytes() / 1e9,
+    out = {"fft_refine": r, "interior": interior, "offgrid_shortcut": shortcut, "setup_s": round(setup_s, 1), "resident_gb": op.resident_bytes() / 1e9,
            "csr_nnz": int(st["csr_nnz"])}
     try:
         if autotune:
@@ -456,6 +459,8 @@ def main():
                     help="profiling runs: build the main operator with this Fourier refinement factor")
     ap.add_argument("--fft-refine-interior", action="store_true",
                     help="profiling runs: refine the interior lattice as well")
+    ap.add_argument("--offgrid-shortcut", action="store_true",
+                    help="profiling runs: the off-grid shortcut for the boundary patch's interior lattice nodes")
     ap.add_argument("--refine", type=int, default=2,
                     help="refinement factor of the Fourier refined interpolation measured on the same workload "
                          "(0 skips it)")
@@ -506,7 +511,8 @@ def main():
                   "(--refine)", file=sys.stderr)
             sys.exit(2)
         from paper_1509_05063_amd.inputs import scaled
-        cfg = scaled(cfg, fft_refine=args.fft_refine, fft_refine_interior=int(args.fft_refine_interior))
+        cfg = scaled(cfg, fft_refine=args.fft_refine, fft_refine_interior=int(args.fft_refine_interior),
+                     offgrid_shortcut=int(args.offgrid_shortcut))
     n2 = n2_function(cfg)
     log(f"create {args.config}")
     t0 = time.time()
@@ -664,12 +670,14 @@ def main():
                 "frac": round(fft_gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(fft_b), "avg_ms": round(fft_ms, 4),
                 "note": "2-D face lattices (2 sets x 2 kinds x Pa x Pb complex float) fit in the 256 MB MALL"}
 
-    refined = refined_int = None
+    refined = refined_int = refined_sc = None
     if args.refine > 1:
         refined = refined_run(cfg, n2, f, x_ref, args.refine, ortho, not args.no_autotune)
         log(f"refined {refined}")
         refined_int = refined_run(cfg, n2, f, x_ref, args.refine, ortho, not args.no_autotune, interior=True)
         log(f"refined with the interior {refined_int}")
+        refined_sc = refined_run(cfg, n2, f, x_ref, args.refine, ortho, not args.no_autotune, shortcut=True)
+        log(f"refined with the off-grid shortcut {refined_sc}")
 
     fft3d = None
     if args.fft3d_reps:
@@ -749,6 +757,7 @@ def main():
         "multi_rhs": multi,
         "fft_refined": refined,
         "fft_refined_interior": refined_int,
+        "fft_refined_shortcut": refined_sc,
         "serving": serving,
         "cpu_baseline": cpu,
     }
