@@ -650,7 +650,7 @@ def main():
             0: "1,false", 2: "2,false", 3: "4,false", 4: "4,true"}[nv] + ">"
     alg = byts[dom]
     if dom == "near_csr":
-        # the survey's per-unit figure for stored near-field rows: a weight
+        # per-unit bytes of stored near-field rows (the roofline figure): a weight
         # (8 B, complex float) and a 4-byte column index per stored entry;
         # the run-length kernel moves fewer bytes (kernel_bytes: weights,
         # one 8-byte entry per column run, row data, the input vector)
