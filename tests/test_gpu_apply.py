@@ -703,3 +703,37 @@ def test_offgrid_shortcut_matches_oracle(r):
     print(f"shortcut r={r} solve: {st} vs LU {e:.2e}", flush=True)
     assert st["converged"] == 1 and e < 1e-8, e
     op.close()
+
+
+def test_fft_refined_odd_line_length_matches_oracle():
+    """Fourier refinement on band lines of odd length (N1 = 75 = 3 x 5^2:
+    no Nyquist term, mixed-radix line transforms) with r = 3, the interior
+    refined as well (eight shifted grids): both precisions against the
+    oracle on 300 boundary-patch and 300 interior rows of the disc."""
+    import torch
+    from oracle.op2d import Setup2D
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import scaled
+    cfg = scaled(config("disc_k2pi"), band={"N1": 75}, fft_refine=3, fft_refine_interior=1)
+    n2 = n2_function(cfg)
+    op = binding.Operator(cfg, n2)
+    orc = Setup2D(cfg, n2)
+    xy, key = op.points()
+    p = match_keys(orc.pts["key"], key)
+    n_int = orc.pts["n_int"]
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([np.sort(rng.choice(n_int, 300, replace=False)),
+                           n_int + np.sort(rng.choice(orc.N - n_int, 300, replace=False))])
+    A = orc.A_rows(rows)
+    x_or = random_density(orc.pts["key"], seed=37)
+    y_or = A @ x_or
+    for dt, tol in ((torch.complex128, 1e-8), (torch.complex64, F32_TOL)):
+        u = torch.tensor(_to_lib(x_or, p, op.N), dtype=dt, device="cuda")
+        v = torch.empty_like(u)
+        op.apply(u, v)
+        torch.cuda.synchronize()
+        y = v.cpu().numpy().astype(complex)[p][rows]
+        err = np.linalg.norm(y - y_or) / np.linalg.norm(y_or)
+        print(f"odd N1 refine 3 {dt}: rel2 {err:.2e}", flush=True)
+        assert err < tol, (dt, err)
+    op.close()

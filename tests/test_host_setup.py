@@ -131,20 +131,20 @@ def _zero_pad_refine(N1, r):
     return np.fft.ifft(Y, axis=0) * r
 
 
-@pytest.mark.parametrize("r", [2, 3])
-def test_refined_rows_complete_oracle_rows(r):
+@pytest.mark.parametrize("r,N1", [(2, 64), (3, 64), (3, 75)])
+def test_refined_rows_complete_oracle_rows(r, N1):
     """Fourier refinement along the band's t1 lines: a library row's
     refined columns (values at t1 = v + s / r of line u of the density
     (m omega J) u) expanded over the line's unknowns with an independent
     zero-padded FFT refinement, plus its other columns and the plain far
     sum, give the oracle's row (boundary-patch targets and interior targets
     inside the patch)."""
-    cfg = scaled(config("disc_k2pi"), fft_refine=r)
+    cfg = scaled(config("disc_k2pi"), fft_refine=r, band={"N1": N1})
     n2 = n2_function(cfg)
     host, orc = binding.HostOperator(cfg, n2), Setup2D(cfg, n2)
     xy, key = host.points()
     N = host.N
-    N1, N2 = cfg["band"]["N1"], cfg["band"]["N2"]
+    N2 = cfg["band"]["N2"]
     p = match_keys(orc.pts["key"], key)
     inv = np.empty_like(p)
     inv[p] = np.arange(p.size)
