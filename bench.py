@@ -168,6 +168,30 @@ def cpu_disc_oracle():
             "solves_per_s_incl_rows": round(1 / (t_build + t_lu), 4)}
 
 
+def multi_rhs_profile(nrhs, reps):
+    """Profiling run: the kappa = 16 pi star's batched single-precision apply
+    (tuned for nrhs right-hand sides), reps staged applies."""
+    import torch
+    from paper_1509_05063_amd import binding
+    from paper_1509_05063_amd.inputs import config, n2_function, plane_wave
+    cfg = config("star_k16pi")
+    op = binding.Operator(cfg, n2_function(cfg))
+    try:
+        tune = op.autotune(nrhs, binding.LS_C64)
+        xy, _ = op.points()
+        F = torch.tensor(np.stack([plane_wave(cfg, xy, 2 * math.pi * r / nrhs) for r in range(nrhs)]),
+                         dtype=torch.complex64, device="cuda")
+        V = torch.empty_like(F)
+        acc = None
+        for _ in range(reps):
+            p = op.apply_profile(F, V)
+            acc = p if acc is None else {k: acc[k] + p[k] for k in p}
+        torch.cuda.synchronize()
+        return {"schedule": tune, "stage_ms": {k: v / reps for k, v in acc.items()}}
+    finally:
+        op.close()
+
+
 def multi_rhs_run(nrhs, ortho, autotune):
     """Batched solves on the kappa = 16 pi star: nrhs equispaced incident
     directions as the right-hand sides of one solve (FP64 reference, then the
@@ -473,6 +497,9 @@ def main():
                          "device copy (the calibration kernel for HBM byte counters)")
     ap.add_argument("--fft3d-reps", type=int, default=20,
                     help="applies of the 3-D face-lattice convolution in its measurement (0 skips it)")
+    ap.add_argument("--profile-multi", type=int, default=0,
+                    help="profiling run: only this many batched single-precision applies on the kappa = 16 pi star "
+                         "(--multi-rhs right-hand sides)")
     ap.add_argument("--profile-fft3d", type=int, default=0,
                     help="profiling run: only this many 3-D face-lattice convolutions")
     ap.add_argument("--fft256-reps", type=int, default=20,
@@ -492,6 +519,9 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)          # the calibration kernel for HBM byte counters
         torch.cuda.synchronize()
+        return
+    if args.profile_multi:
+        log(f"profile multi {multi_rhs_profile(args.multi_rhs, args.profile_multi)}")
         return
     if args.profile_fft256:
         log(f"profile fft256 {fft256_run(args.profile_fft256)}")
